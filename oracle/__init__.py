@@ -1,0 +1,289 @@
+"""Plain FP64 CPU oracle: TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product (``paper_1002_3094_amd``)
+never imports it, and the two share no code: the only common dependency is the
+seeded input generator module ``synth``.
+
+The numerical work is in ``oracle.c`` (built into ``liboracle.so`` by
+``oracle/build.py``); this module marshals numpy arrays and holds the Laguerre
+series driver, written as a plain loop over harmonics with the direct sum of
+the paper's eq. (35).
+
+Parity notes: every function is pinned by ``tests/test_oracle_*.py`` against
+the mathematics (dense assembly, closed forms, library routines, brute force).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+Z_DIRICHLET = 0
+Z_NEUMANN = 1
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    i, d = ctypes.c_int, ctypes.c_double
+    sig = {
+        "orc_num_threads": ([], i),
+        "orc_face_kappa": ([i, i, _dp, _dp, _dp], None),
+        "orc_coeffs": ([i, i, d, d, i, _dp, _dp, _dp, _dp, _dp, _dp], None),
+        "orc_apply": ([i, i, _dp, _dp, _dp, _dp, _dp], None),
+        "orc_rhs": ([i, i, d, _dp, _dp], None),
+        "orc_dot": ([i, i, _dp, _dp], d),
+        "orc_fft": ([i, _dp, _dp], None),
+        "orc_ztrans_fwd": ([i, i, _dp, _dp], None),
+        "orc_ztrans_inv": ([i, i, _dp, _dp], None),
+        "orc_mode_eig": ([i, d, i, _dp], None),
+        "orc_thomas": ([i, _dp, _dp, _dp, _dp, _dp], None),
+        "orc_precond": ([i, i, d, d, i, d, d, _dp, _dp], None),
+        "orc_pcg": ([i, i, d, d, i, _dp, _dp, _dp, d, d, _dp, _dp, d, i, _ip, _dp], i),
+        "orc_laguerre_coeffs": ([i, d, i, d, _dp, _dp], None),
+        "orc_laguerre_functions": ([i, d, i, _dp, _dp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def num_threads() -> int:
+    return _load().orc_num_threads()
+
+
+# --------------------------------------------------------------------------
+# Operator of the scheme, §2.1 eqs. (4)-(6)
+# --------------------------------------------------------------------------
+@dataclass
+class Operator:
+    nr: int
+    nz: int
+    lr: float
+    lz: float
+    bc_z: int
+    cr: np.ndarray      # [nr][nz]   r-face conductances (outer face doubled)
+    cz: np.ndarray      # [nr][nz+1] z-face conductances
+    w: np.ndarray       # [nr][nz]   r q
+    kbar: float         # preconditioner constants, §4.2 eq. (37)
+    qbar: float
+
+    @property
+    def hr(self):
+        return self.lr / self.nr
+
+    @property
+    def hz(self):
+        return self.lz / self.nz
+
+    @property
+    def r(self):
+        return (np.arange(self.nr) + 0.5) * self.hr
+
+
+def face_kappa(kappa: np.ndarray):
+    nr, nz = kappa.shape
+    kc = _c(kappa)
+    kr = np.empty((nr, nz))
+    kz = np.empty((nr, nz + 1))
+    _load().orc_face_kappa(nr, nz, _p(kc), _p(kr), _p(kz))
+    return kr, kz
+
+
+def operator_from_faces(kr, kz, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, qbar=None) -> Operator:
+    kr, kz, q = _c(kr), _c(kz), _c(q)
+    nr, nz = q.shape
+    assert kr.shape == (nr, nz) and kz.shape == (nr, nz + 1)
+    cr = np.empty((nr, nz))
+    cz = np.empty((nr, nz + 1))
+    w = np.empty((nr, nz))
+    _load().orc_coeffs(nr, nz, float(lr), float(lz), int(bc_z), _p(kr), _p(kz), _p(q), _p(cr), _p(cz), _p(w))
+    if kbar is None:
+        kbar = float(kr.mean())
+    if qbar is None:
+        qbar = float(q.mean())
+    return Operator(nr, nz, float(lr), float(lz), int(bc_z), cr, cz, w, float(kbar), float(qbar))
+
+
+def operator_from_cells(kappa, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, qbar=None) -> Operator:
+    """Operator from cell-centre kappa and q.  Preconditioner constants default
+    to the arithmetic means of the cell values (the paper's footnote to
+    eq. (37) uses the mid-range (min+max)/2; CG is invariant to scaling B, so
+    this choice only changes iteration counts)."""
+    kappa = _c(kappa)
+    kr, kz = face_kappa(kappa)
+    if kbar is None:
+        kbar = float(kappa.mean())
+    if qbar is None:
+        qbar = float(np.asarray(q).mean())
+    return operator_from_faces(kr, kz, q, lr, lz, bc_z, kbar, qbar)
+
+
+def apply(op: Operator, x) -> np.ndarray:
+    x = _c(x)
+    y = np.empty_like(x)
+    _load().orc_apply(op.nr, op.nz, _p(op.cr), _p(op.cz), _p(op.w), _p(x), _p(y))
+    return y
+
+
+def rhs(op: Operator, f) -> np.ndarray:
+    """phi = r f, eq. (6)."""
+    f = _c(f)
+    b = np.empty_like(f)
+    _load().orc_rhs(op.nr, op.nz, op.lr, _p(f), _p(b))
+    return b
+
+
+def dot(a, b) -> float:
+    a, b = _c(a), _c(b)
+    if a.ndim == 1:
+        a = a[None, :]
+        b = b[None, :]
+    return _load().orc_dot(a.shape[0], a.shape[1], _p(a), _p(b))
+
+
+# --------------------------------------------------------------------------
+# Transforms, §4.2 eq. (38)
+# --------------------------------------------------------------------------
+def fft(x) -> np.ndarray:
+    x = np.asarray(x, dtype=np.complex128)
+    re, im = _c(x.real), _c(x.imag)
+    _load().orc_fft(len(x), _p(re), _p(im))
+    return re + 1j * im
+
+
+def ztrans_fwd(x, bc_z=Z_DIRICHLET) -> np.ndarray:
+    """Row-wise orthonormal forward z-transform of a [.., nz] array."""
+    x = _c(x)
+    flat = x.reshape(-1, x.shape[-1])
+    out = np.empty_like(flat)
+    lib = _load()
+    for i in range(flat.shape[0]):
+        lib.orc_ztrans_fwd(flat.shape[1], int(bc_z), _p(_c(flat[i])), out[i:].ctypes.data_as(_dp))
+    return out.reshape(x.shape)
+
+
+def ztrans_inv(X, bc_z=Z_DIRICHLET) -> np.ndarray:
+    X = _c(X)
+    flat = X.reshape(-1, X.shape[-1])
+    out = np.empty_like(flat)
+    lib = _load()
+    for i in range(flat.shape[0]):
+        lib.orc_ztrans_inv(flat.shape[1], int(bc_z), _p(_c(flat[i])), out[i:].ctypes.data_as(_dp))
+    return out.reshape(X.shape)
+
+
+def mode_eig(nz, lz=1.0, bc_z=Z_DIRICHLET) -> np.ndarray:
+    mu = np.empty(nz)
+    _load().orc_mode_eig(nz, float(lz), int(bc_z), _p(mu))
+    return mu
+
+
+def thomas(a, b, c, f) -> np.ndarray:
+    a, b, c, f = _c(a), _c(b), _c(c), _c(f)
+    x = np.empty_like(f)
+    _load().orc_thomas(len(f), _p(a), _p(b), _p(c), _p(f), _p(x))
+    return x
+
+
+def precond(op: Operator, r) -> np.ndarray:
+    """B^{-1} r, §4.2 eqs. (36)-(39)."""
+    r = _c(r)
+    z = np.empty_like(r)
+    _load().orc_precond(op.nr, op.nz, op.lr, op.lz, op.bc_z, op.kbar, op.qbar, _p(r), _p(z))
+    return z
+
+
+def pcg(op: Operator, b, x0=None, rtol=1e-13, maxit=500):
+    """PCG (§2.2, eq. (8) with CG parameters).  Returns (x, status, iters, relres)."""
+    b = _c(b)
+    x = np.zeros_like(b) if x0 is None else _c(x0).copy()
+    it = ctypes.c_int(0)
+    rel = ctypes.c_double(0.0)
+    st = _load().orc_pcg(op.nr, op.nz, op.lr, op.lz, op.bc_z, _p(op.cr), _p(op.cz), _p(op.w),
+                         op.kbar, op.qbar, _p(b), _p(x), float(rtol), int(maxit),
+                         ctypes.byref(it), ctypes.byref(rel))
+    return x, int(st), int(it.value), float(rel.value)
+
+
+def solve_reference(op: Operator, b, x0=None, rtol=1e-13, maxit=500):
+    """Reference solution for parity: PCG run to rtol (default 1e-13) or to
+    maxit, whichever comes first."""
+    x, st, it, rel = pcg(op, b, x0, rtol, maxit)
+    return x
+
+
+# --------------------------------------------------------------------------
+# Laguerre series, §4.1 eqs. (34)-(35) with alpha = 0
+# --------------------------------------------------------------------------
+def laguerre_coeffs(n: int, eta: float, ft, t_max: float) -> np.ndarray:
+    ft = _c(ft)
+    g = np.empty(n)
+    _load().orc_laguerre_coeffs(int(n), float(eta), len(ft), float(t_max), _p(ft), _p(g))
+    return g
+
+
+def laguerre_functions(n: int, eta: float, t) -> np.ndarray:
+    t = _c(t)
+    out = np.empty((n, len(t)))
+    _load().orc_laguerre_functions(int(n), float(eta), len(t), _p(t), _p(out))
+    return out
+
+
+def point_delta_rhs(op: Operator, src_i: int, src_k: int) -> np.ndarray:
+    """r-weighted discrete delta: b = 1/(h_r h_z) in the source cell, so that
+    sum(b) h_r h_z = 1 (the 1/(2 pi) of the 3-D delta is a dropped scale)."""
+    b = np.zeros((op.nr, op.nz))
+    b[src_i, src_k] = 1.0 / (op.hr * op.hz)
+    return b
+
+
+def laguerre_chain(op: Operator, kappa, g, eta: float, src_i: int, src_k: int,
+                   n_harm: int, rtol=1e-13, maxit=500, guess="prev"):
+    """Harmonics u_0..u_{n_harm-1} of eq. (35) with alpha = 0 and rho^2 read as
+    c^2 = kappa:
+        A u_m = r f_m,  f_m = g_m delta_h - (eta^2 / c^2) * sum_{k<m} (m-k) u_k.
+    The sum is evaluated directly over the stored harmonics."""
+    us = []
+    r = op.r[:, None]
+    coef = eta * eta / np.asarray(kappa)
+    delta = point_delta_rhs(op, src_i, src_k)
+    stats = []
+    for m in range(n_harm):
+        s = np.zeros((op.nr, op.nz))
+        for k in range(m):
+            s += (m - k) * us[k]
+        b = g[m] * delta - r * coef * s
+        x0 = us[-1] if (guess == "prev" and us) else None
+        x, st, it, rel = pcg(op, b, x0, rtol, maxit)
+        us.append(x)
+        stats.append((st, it, rel))
+    return us, stats
