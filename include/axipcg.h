@@ -1,0 +1,170 @@
+/*
+ * axipcg — preconditioned conjugate gradients for the axisymmetric
+ * variable-coefficient elliptic operator, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: A.V. Terekhov, "High performance parallel algorithm for solving
+ * elliptic equations with non-separable variables" (arXiv:1002.3094).
+ * Section and equation numbers below are the paper's.
+ *
+ * Problem (§2.1 eq. (2)):
+ *     (1/r) d/dr (r kappa du/dr) + d/dz (kappa du/dz) - q u = -f
+ * on [0, lr] x [0, lz], with r kappa du/dr = 0 on the axis, u = 0 at r = lr,
+ * and either u = 0 (Dirichlet) or du/dz = 0 (Neumann, the paper's choice) at
+ * z = 0 and z = lz.  kappa > 0, q >= 0 (eq. (3)).
+ *
+ * Discretisation (eqs. (4)-(6), cell-centred reading): nr x nz cells,
+ * h_r = lr/nr, h_z = lz/nz, r_i = (i+1/2) h_r.  The discrete operator A is the
+ * r-weighted finite-volume scheme, symmetric positive definite (eq. (7)); the
+ * discrete right-hand side is b = r f.  Boundary faces with u = 0 use the
+ * half-cell flux (doubled face conductance).
+ *
+ * Preconditioner (§4.2 eqs. (36)-(39)): B = A with kappa = kbar and q = qbar
+ * everywhere, inverted by separation of variables: an orthonormal sine
+ * (Dirichlet) or cosine (Neumann) transform along z, one tridiagonal solve in r
+ * per z-mode, the inverse transform.
+ *
+ * Conventions for every entry point:
+ *  - Grid arrays are [nr][nz] row-major, z contiguous, 0-based, IEEE double
+ *    unless stated.  "device" pointers are HIP device memory of the calling
+ *    process' current device (e.g. torch tensors); "host" pointers are host
+ *    memory.  The caller owns every array it passes; the library never keeps
+ *    a caller pointer after the call returns.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *    stream-ordered: device outputs are valid once the stream reaches the
+ *    call's position; entry points that return host values synchronise the
+ *    stream before returning.
+ *  - An operator handle owns its device buffers and workspace.  It must not be
+ *    used from two streams (or two host threads) at the same time.
+ *  - Arguments are validated before any device work; on failure the call
+ *    returns AXIPCG_EINVAL (or another negative code), writes no output, and
+ *    axipcg_last_error() describes the problem.  C++ exceptions never cross
+ *    this interface.
+ */
+#ifndef AXIPCG_H
+#define AXIPCG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct axipcg_op *axipcg_op_t;
+
+/* Status codes.  AXIPCG_ENOTCONV is positive: the call completed and its
+ * outputs hold the last iterate. */
+enum {
+    AXIPCG_OK = 0,
+    AXIPCG_ENOTCONV = 1,
+    AXIPCG_EINVAL = -1,
+    AXIPCG_ENOMEM = -2,
+    AXIPCG_EDEVICE = -3,
+    AXIPCG_EBREAKDOWN = -4
+};
+
+enum { AXIPCG_Z_DIRICHLET = 0, AXIPCG_Z_NEUMANN = 1 };
+
+/* Arithmetic of the preconditioner.  The outer PCG vectors, dot products,
+ * residual recurrence and stop test are FP64 in both cases. */
+enum { AXIPCG_PREC_FP64 = 0, AXIPCG_PREC_FP32 = 1 };
+
+/* pcg_solve flags */
+enum {
+    AXIPCG_FLAG_TRUE_RESIDUAL = 1u,  /* also compute ||b - A x|| / ||b|| at exit */
+    AXIPCG_FLAG_POLAK_RIBIERE = 2u   /* beta = r.(z - z_old) / rho_old (flexible CG) */
+};
+
+typedef struct {
+    int iters;          /* PCG iterations performed */
+    int status;         /* AXIPCG_OK, AXIPCG_ENOTCONV or AXIPCG_EBREAKDOWN */
+    double relres_rec;  /* ||r_k|| / ||b|| from the recurrence */
+    double relres_true; /* ||b - A x|| / ||b|| if requested, else -1 */
+} axipcg_stats;
+
+/* ---- operator setup (§2.1 eqs. (4)-(6); §4.2 eqs. (36)-(37)) ---------------
+ * Build the operator from cell-centre kappa and q (host arrays [nr][nz]).
+ * Face values of kappa are the mean of the two adjacent cells (the boundary
+ * face takes its cell's value).  kbar <= 0 selects the mean of kappa, qbar < 0
+ * the mean of q (the paper's footnote to eq. (37) uses the mid-range; PCG is
+ * invariant to scaling B, so this only changes iteration counts).
+ * Limits: 2 <= nr <= 4096; nz a power of two with 2 <= nz <= 4096; lr, lz > 0;
+ * kappa > 0 and q >= 0, all finite.  Allocates ~ (10 * 8) bytes per cell of
+ * device memory.  *out receives the handle. */
+int axipcg_op_create(int nr, int nz, double lr, double lz, int bc_z,
+                     const double *kappa, const double *q,
+                     double kbar, double qbar, void *stream, axipcg_op_t *out);
+
+/* Same, with kappa given directly at the faces (host arrays):
+ * kappa_r [nr][nz] at (rho_{i+1/2}, z_k), i = nr-1 being the face r = lr;
+ * kappa_z [nr][nz+1] at (r_i, k h_z), k = 0 and k = nz the faces z = 0, lz.
+ * kbar must be > 0 and qbar >= 0 (no default). */
+int axipcg_op_create_faces(int nr, int nz, double lr, double lz, int bc_z,
+                           const double *kappa_r, const double *kappa_z, const double *q,
+                           double kbar, double qbar, void *stream, axipcg_op_t *out);
+
+/* Release the handle and its device memory (NULL-safe).  Synchronises the
+ * stream the handle was created on. */
+void axipcg_op_destroy(axipcg_op_t op);
+
+/* Sizes and preconditioner constants of a handle (any pointer may be NULL). */
+int axipcg_op_info(axipcg_op_t op, int *nr, int *nz, double *kbar, double *qbar);
+
+/* ---- operator application (§2.1 eq. (4)) ---------------------------------
+ * y = A x; x, y device [nr][nz]; x and y must not overlap. */
+int axipcg_apply_A(axipcg_op_t op, const double *x, double *y, void *stream);
+
+/* b = r f (eq. (6)); f, b device [nr][nz]; may alias. */
+int axipcg_rhs_from_f(axipcg_op_t op, const double *f, double *b, void *stream);
+
+/* ---- preconditioner (§4.2 eqs. (36)-(39)) --------------------------------
+ * z = B^{-1} r; r, z device [nr][nz] (must not overlap).  prec selects the
+ * arithmetic of the transforms and r-solves (AXIPCG_PREC_FP32 reads r as
+ * double, computes in float, writes z as double). */
+int axipcg_precond_apply(axipcg_op_t op, const double *r, double *z, int prec, void *stream);
+
+/* out_host[0] = ||b - A x||_2, out_host[1] = ||b||_2 (host double[2]).
+ * b, x device.  Synchronises the stream. */
+int axipcg_residual_norm(axipcg_op_t op, const double *b, const double *x,
+                         double *out_host, void *stream);
+
+/* ---- PCG (§2.2 eq. (8) with conjugate-gradient parameters) -----------------
+ * Solve A x = b.  x (device) holds the initial guess on entry and the last
+ * iterate on return; b device.  Stops when ||r_k|| / ||b|| <= rtol, r_k the
+ * recursively updated residual (§4.3 stop test), or after maxit iterations.
+ * st (host, may be NULL) receives the statistics.  Returns AXIPCG_OK,
+ * AXIPCG_ENOTCONV (maxit reached) or AXIPCG_EBREAKDOWN (p.Ap <= 0 or a
+ * non-finite scalar; x holds the last iterate).  b = 0 gives x = 0.
+ * Synchronises the stream (the iteration count is decided on the device and
+ * read back in chunks).  rtol > 0, 1 <= maxit <= 100000. */
+int axipcg_pcg_solve(axipcg_op_t op, const double *b, double *x, double rtol, int maxit,
+                     int prec, unsigned flags, axipcg_stats *st, void *stream);
+
+/* ---- Laguerre series (§4.1 eqs. (34)-(35), alpha = 0) ----------------------
+ * g_m = int_0^{t_max} f(t) l_m(t) dt, l_m(t) = sqrt(eta) e^{-eta t/2} L_m(eta t),
+ * for m < n, from nt >= 3 uniform samples f_host[j] = f(j t_max/(nt-1)) (host).
+ * The integral is the trapezoid rule (exact to machine precision for pulses
+ * that vanish smoothly at both ends).  g_host: host double[n]. */
+int axipcg_laguerre_coeffs(int n, double eta, int nt, double t_max,
+                           const double *f_host, double *g_host, void *stream);
+
+/* Right-hand side of harmonic m (eq. (35)):
+ *     b = r * (g_m delta_h - c * sum_{k<m} (m-k) u_k)
+ * kept as two running sums (device [nr][nz], caller-owned, zero before m = 0):
+ *     S1 += u_prev (skipped when u_prev is NULL, i.e. m = 0);  S2 += S1;
+ *     b = r g_m delta_h - r c S2.
+ * delta_h is the discrete point source at cell (src_i, src_k): r delta_h =
+ * 1/(h_r h_z) there and 0 elsewhere.  c is `coef` (device [nr][nz], e.g.
+ * eta^2/c^2) or, when coef is NULL, 4 q: the paper's damping and history
+ * coefficients are h^2/(4 rho^2) and h^2/rho^2.  u_prev may not alias S1, S2
+ * or b. */
+int axipcg_laguerre_rhs(axipcg_op_t op, double g_m, int src_i, int src_k,
+                        const double *coef, const double *u_prev,
+                        double *S1, double *S2, double *b, void *stream);
+
+/* ---- errors ---------------------------------------------------------------- */
+const char *axipcg_strerror(int code);
+/* Message of the last failing call on this host thread ("" if none). */
+const char *axipcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AXIPCG_H */

@@ -1,0 +1,221 @@
+"""Thin ctypes binding of the axipcg C-ABI (``include/axipcg.h``).
+
+Argument marshalling only: every numerical step runs in the HIP library
+``libaxipcg.so`` built for gfx950.  Device arrays are torch tensors
+(float64, contiguous, on the current HIP device); host arrays are numpy
+arrays.  The stream defaults to torch's current stream.  Loading fails loudly
+when the library has not been built: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaxipcg.so")
+
+OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN = 0, 1, -1, -2, -3, -4
+Z_DIRICHLET, Z_NEUMANN = 0, 1
+PREC_FP64, PREC_FP32 = 0, 1
+FLAG_TRUE_RESIDUAL, FLAG_POLAK_RIBIERE = 1, 2
+
+_lib = None
+
+
+class AxipcgError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("status", ctypes.c_int),
+                ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_i, _d, _u = ctypes.c_int, ctypes.c_double, ctypes.c_uint
+
+SIGNATURES = {
+    "axipcg_op_create": ([_i, _i, _d, _d, _i, _dp, _dp, _d, _d, _vp, ctypes.POINTER(_vp)], _i),
+    "axipcg_op_create_faces": ([_i, _i, _d, _d, _i, _dp, _dp, _dp, _d, _d, _vp, ctypes.POINTER(_vp)], _i),
+    "axipcg_op_destroy": ([_vp], None),
+    "axipcg_op_info": ([_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), _dp, _dp], _i),
+    "axipcg_apply_A": ([_vp, _vp, _vp, _vp], _i),
+    "axipcg_rhs_from_f": ([_vp, _vp, _vp, _vp], _i),
+    "axipcg_precond_apply": ([_vp, _vp, _vp, _i, _vp], _i),
+    "axipcg_residual_norm": ([_vp, _vp, _vp, _dp, _vp], _i),
+    "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
+    "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
+    "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "axipcg_strerror": ([_i], ctypes.c_char_p),
+    "axipcg_last_error": ([], ctypes.c_char_p),
+}
+
+
+def lib():
+    """Load libaxipcg.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1002_3094_amd/build.py")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = h
+    return _lib
+
+
+def _check(code: int, where: str, allow=(OK,)):
+    if code in allow:
+        return code
+    msg = lib().axipcg_last_error().decode() or lib().axipcg_strerror(code).decode()
+    raise AxipcgError(code, where, msg)
+
+
+def _host(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _hp(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _dev(t, name="array"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device torch tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    return _vp(t.data_ptr())
+
+
+def _opt_dev(t, name):
+    return None if t is None else _dev(t, name)
+
+
+def _stream(stream):
+    if stream is not None:
+        return _vp(stream if isinstance(stream, int) else stream.cuda_stream)
+    import torch
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+class Op:
+    """Owning wrapper of an axipcg_op_t handle."""
+
+    def __init__(self, handle: int):
+        self.handle = _vp(handle)
+        n_r, n_z, kb, qb = _i(), _i(), _d(), _d()
+        _check(lib().axipcg_op_info(self.handle, ctypes.byref(n_r), ctypes.byref(n_z),
+                                    ctypes.byref(kb), ctypes.byref(qb)), "op_info")
+        self.nr, self.nz, self.kbar, self.qbar = n_r.value, n_z.value, kb.value, qb.value
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().axipcg_op_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def op_create(kappa, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=-1.0, qbar=-1.0, stream=None) -> Op:
+    kappa, q = _host(kappa), _host(q)
+    if kappa.ndim != 2 or q.shape != kappa.shape:
+        raise ValueError("kappa and q must be [nr][nz] arrays of the same shape")
+    nr, nz = kappa.shape
+    out = _vp()
+    _check(lib().axipcg_op_create(nr, nz, lr, lz, bc_z, _hp(kappa), _hp(q), kbar, qbar,
+                                  _stream(stream), ctypes.byref(out)), "op_create")
+    return Op(out.value)
+
+
+def op_create_faces(kappa_r, kappa_z, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=1.0, qbar=0.0,
+                    stream=None) -> Op:
+    kappa_r, kappa_z, q = _host(kappa_r), _host(kappa_z), _host(q)
+    nr, nz = q.shape
+    if kappa_r.shape != (nr, nz) or kappa_z.shape != (nr, nz + 1):
+        raise ValueError("kappa_r must be [nr][nz] and kappa_z [nr][nz+1]")
+    out = _vp()
+    _check(lib().axipcg_op_create_faces(nr, nz, lr, lz, bc_z, _hp(kappa_r), _hp(kappa_z), _hp(q),
+                                        kbar, qbar, _stream(stream), ctypes.byref(out)),
+           "op_create_faces")
+    return Op(out.value)
+
+
+def op_destroy(op: Op):
+    op.close()
+
+
+def apply_A(op: Op, x, y, stream=None):
+    _check(lib().axipcg_apply_A(op.handle, _dev(x, "x"), _dev(y, "y"), _stream(stream)), "apply_A")
+
+
+def rhs_from_f(op: Op, f, b, stream=None):
+    _check(lib().axipcg_rhs_from_f(op.handle, _dev(f, "f"), _dev(b, "b"), _stream(stream)), "rhs_from_f")
+
+
+def precond_apply(op: Op, r, z, prec=PREC_FP32, stream=None):
+    _check(lib().axipcg_precond_apply(op.handle, _dev(r, "r"), _dev(z, "z"), prec, _stream(stream)),
+           "precond_apply")
+
+
+def residual_norm(op: Op, b, x, stream=None):
+    out = np.zeros(2)
+    _check(lib().axipcg_residual_norm(op.handle, _dev(b, "b"), _dev(x, "x"), _hp(out), _stream(stream)),
+           "residual_norm")
+    return float(out[0]), float(out[1])
+
+
+def pcg_solve(op: Op, b, x, rtol=1e-10, maxit=1000, prec=PREC_FP32, flags=0, stream=None,
+              allow_notconv=True) -> dict:
+    st = Stats()
+    code = lib().axipcg_pcg_solve(op.handle, _dev(b, "b"), _dev(x, "x"), rtol, maxit, prec, flags,
+                                  ctypes.byref(st), _stream(stream))
+    _check(code, "pcg_solve", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    d = st.as_dict()
+    d["code"] = code
+    return d
+
+
+def laguerre_coeffs(n: int, eta: float, f_samples, t_max: float, stream=None) -> np.ndarray:
+    f = _host(f_samples)
+    g = np.zeros(n)
+    _check(lib().axipcg_laguerre_coeffs(n, eta, f.size, t_max, _hp(f), _hp(g), _stream(stream)),
+           "laguerre_coeffs")
+    return g
+
+
+def laguerre_rhs(op: Op, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=None, coef=None,
+                 stream=None):
+    _check(lib().axipcg_laguerre_rhs(op.handle, g_m, src_i, src_k, _opt_dev(coef, "coef"),
+                                     _opt_dev(u_prev, "u_prev"), _dev(S1, "S1"), _dev(S2, "S2"),
+                                     _dev(b, "b"), _stream(stream)), "laguerre_rhs")
+
+
+def strerror(code: int) -> str:
+    return lib().axipcg_strerror(code).decode()
+
+
+def last_error() -> str:
+    return lib().axipcg_last_error().decode()

@@ -1,0 +1,424 @@
+// Preconditioner B^{-1} of §4.2 (eqs. (36)-(39)) on gfx950: batched z-transforms
+// in LDS and a partitioned r-tridiagonal solver with an in-wavefront reduced
+// system.
+#include "fft.h"
+#include "kernels.h"
+
+namespace axipcg {
+
+namespace {
+
+constexpr int DIR = AXIPCG_Z_DIRICHLET;
+
+// ---------------------------------------------------------------------------
+// Forward transform: one workgroup per r-row.
+// ---------------------------------------------------------------------------
+template <typename T, int BC, bool FUSED>
+__global__ void __launch_bounds__(256)
+k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
+       const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
+       double *__restrict__ partials, unsigned *ticket,
+       T *__restrict__ spec, const typename vec2_of<T>::type *__restrict__ tw,
+       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+{
+    if (FUSED && st->done) return;
+    extern __shared__ char smem_raw[];
+    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *b = a + N;
+    __shared__ double red[8];
+
+    const int i = xcd_swizzle(blockIdx.x, nr);
+    const size_t row = (size_t)i * N;
+    double rr = 0.0;
+    const double alpha = FUSED ? st->alpha : 0.0;
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        double rv;
+        if (FUSED) {
+            const size_t c = row + k;
+            x[c] += alpha * p[c];
+            rv = r[c] - alpha * q[c];
+            r[c] = rv;
+            rr += rv * rv;
+        } else {
+            rv = rin[row + k];
+        }
+        T v = (T)rv;
+        int n;
+        if ((k & 1) == 0) {
+            n = k >> 1;
+        } else {
+            n = N - 1 - (k >> 1);
+            if (BC == DIR) v = -v;
+        }
+        a[n] = {v, (T)0};
+    }
+    __syncthreads();
+    const cx<T> *V = fft_stockham<T>(a, b, N, tw);
+    const T nrm = (T)sqrt(2.0 / N);
+    const T half = (T)0.70710678118654752440;
+    for (int j = threadIdx.x; j < N; j += blockDim.x) {
+        const int m = (BC == DIR) ? N - 1 - j : j;
+        const cx<T> w = ld_tw<T>(pt, m);
+        const T Y = V[m].x * w.x - V[m].y * w.y;
+        const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
+        spec[row + j] = nrm * (edge ? half : (T)1) * Y;
+    }
+    if (FUSED) {
+        const double s = block_sum(rr, red);
+        if (publish_partial(s, partials + SLOT_RR * MAX_PARTIALS, ticket + SLOT_RR * 16, gridDim.x, blockIdx.x)) {
+            const double tot = sum_partials(partials + SLOT_RR * MAX_PARTIALS, gridDim.x, red);
+            if (threadIdx.x == 0) {
+                st->rr = tot;
+                st->iters += 1;
+                if (!(tot == tot) || tot > 1e300) st->done = 2;
+                else if (tot <= st->tol2) st->done = 1;
+                else if (st->iters >= st->maxit) st->done = 3;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inverse transform: one workgroup per r-row, FP64 output.
+// ---------------------------------------------------------------------------
+template <typename T, int BC, int MODE>
+__global__ void __launch_bounds__(256)
+k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
+       PcgState *st, double *__restrict__ partials, unsigned *ticket,
+       const typename vec2_of<T>::type *__restrict__ tw,
+       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+{
+    if (MODE != 0 && st->done) return;
+    extern __shared__ char smem_raw[];
+    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
+    cx<T> *b = a + N;
+    __shared__ double red[8];
+
+    const int i = xcd_swizzle(blockIdx.x, nr);
+    const size_t row = (size_t)i * N;
+    const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
+    const T sq2 = (T)1.41421356237309504880;
+    auto Yval = [&](int m) -> T {
+        // unnormalised DCT-II coefficient Y_m of y
+        const int j = (BC == DIR) ? N - 1 - m : m;
+        const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
+        return spec[row + j] * isc * (edge ? sq2 : (T)1);
+    };
+    for (int m = threadIdx.x; m < N; m += blockDim.x) {
+        const T ym = Yval(m);
+        const T yn = (m == 0) ? (T)0 : Yval(N - m);
+        const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
+        // V = conj(w) (ym - i yn); store conj(V) = w (ym + i yn)
+        a[m] = {w.x * ym - w.y * yn, w.x * yn + w.y * ym};
+    }
+    __syncthreads();
+    const cx<T> *res = fft_stockham<T>(a, b, N, tw);
+    const T invN = (T)1 / (T)N;
+    double rz = 0.0, rzo = 0.0;
+    const bool pr = (MODE == 1) && (st->flags & AXIPCG_FLAG_POLAK_RIBIERE);
+    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+        const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
+        T v = res[n].x * invN;
+        if (BC == DIR && (k & 1)) v = -v;
+        const double zv = (double)v;
+        const size_t c = row + k;
+        if (MODE != 0) {
+            const double rv = r[c];
+            if (pr) rzo += rv * zout[c];
+            rz += rv * zv;
+        }
+        zout[c] = zv;
+    }
+    if (MODE != 0) {
+        const double s = block_sum(rz, red);
+        double so = 0.0;
+        if (pr) so = block_sum(rzo, red);
+        if (pr && threadIdx.x == 0)
+            __hip_atomic_store(reinterpret_cast<unsigned long long *>(partials + SLOT_RZOLD * MAX_PARTIALS + blockIdx.x),
+                               (unsigned long long)__double_as_longlong(so), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (publish_partial(s, partials + SLOT_RZ * MAX_PARTIALS, ticket + SLOT_RZ * 16, gridDim.x, blockIdx.x)) {
+            const double tot = sum_partials(partials + SLOT_RZ * MAX_PARTIALS, gridDim.x, red);
+            double toto = 0.0;
+            if (pr) toto = sum_partials(partials + SLOT_RZOLD * MAX_PARTIALS, gridDim.x, red);
+            if (threadIdx.x == 0) {
+                if (MODE == 2) {
+                    st->rho = tot;
+                    st->beta = 0.0;
+                } else {
+                    const double num = pr ? (tot - toto) : tot;
+                    st->beta = num / st->rho;
+                    st->rho = tot;
+                }
+                if (!(tot == tot)) st->done = 2;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Partitioned r-tridiagonal solve (one system per z-mode l):
+//     -cb[i-1] y[i-1] + (db[i] + r_i lam_l) y[i] - cb[i] y[i+1] = f[i].
+// A workgroup loads the [nr][M] tile of M consecutive modes into LDS; wave w
+// solves mode l0 + w.  Lane s owns rows [lo_s, hi_s): its interior rows
+// lo_s..hi_s-2 are eliminated locally against three right-hand sides (data and
+// the two couplings to the neighbouring interface rows), which reduces the
+// line to a tridiagonal system in the interface rows hi_s - 1, one per lane;
+// that system is solved across the wavefront by parallel cyclic reduction
+// with cross-lane shuffles, after which each lane back-substitutes.  This is
+// the divide-and-conquer idea of §3 (split a tridiagonal system into
+// independent subsystems by first computing values at the partition
+// boundaries) mapped onto the lanes of one wavefront.
+// ---------------------------------------------------------------------------
+template <typename T, int LMAX>
+__global__ void __launch_bounds__(256)
+k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ db,
+          const T *__restrict__ rw, const T *__restrict__ lam, const PcgState *gate,
+          int nr, int nz, int M, int S, int pitch, int Lp)
+{
+    if (gate && gate->done) return;
+    extern __shared__ char smem_raw[];
+    T *tile = reinterpret_cast<T *>(smem_raw);
+    const int ngroups = nz / M;
+    const int l0 = xcd_swizzle(blockIdx.x, ngroups) * M;
+    auto prow = [&](int row) { return row + row / Lp; };
+
+    for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
+        const int row = e / M, m = e - row * M;
+        tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
+    }
+    __syncthreads();
+
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (w < M) {
+        T *col = tile + w * pitch;
+        const T lm = lam[l0 + w];
+        const bool active = lane < S;
+        const int lo = active ? (int)(((long)lane * nr) / S) : 0;
+        const int hi = active ? (int)(((long)(lane + 1) * nr) / S) : 0;
+        const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
+
+        T cp[LMAX], gp[LMAX], vp[LMAX];
+        T cprev = 0, gprev = 0, vprev = 0, inv = 1;
+#pragma unroll
+        for (int t = 0; t < LMAX; ++t) {
+            if (t < n) {
+                const int i = lo + t;
+                const T d = db[i] + rw[i] * lm;
+                const T sub = (t > 0) ? -cb[i - 1] : (T)0;
+                inv = (T)1 / (d - sub * cprev);
+                cprev = -cb[i] * inv;
+                gprev = (col[prow(i)] - sub * gprev) * inv;
+                const T vr = (t == 0 && i > 0) ? cb[i - 1] : (T)0;
+                vprev = (vr - sub * vprev) * inv;
+                cp[t] = cprev;
+                gp[t] = gprev;
+                vp[t] = vprev;
+            }
+        }
+        const int R = hi - 1;                        // interface row of this lane
+        const T cbR1 = active ? cb[R - 1] : (T)0;    // coupling interface <- last interior
+        const T wl = cbR1 * inv;                     // w' of the last interior row
+        T gl = active ? gprev : (T)0, vl = active ? vprev : (T)0;
+        // back-substitute to obtain the first interior values of g, v, w
+        T g = gl, v = vl, ww = wl;
+#pragma unroll
+        for (int t = LMAX - 2; t >= 0; --t) {
+            if (t < n - 1) {
+                g = gp[t] - cp[t] * g;
+                v = vp[t] - cp[t] * v;
+                ww = -cp[t] * ww;
+            }
+        }
+        if (!active) { g = 0; v = 0; ww = 0; }
+        // neighbour (lane + 1) first values
+        const T gfn = __shfl_down(g, 1, 64);
+        const T vfn = __shfl_down(v, 1, 64);
+        const T wfn = __shfl_down(ww, 1, 64);
+        const bool has_right = active && (lane + 1 < S);
+        const T cbR = has_right ? cb[R] : (T)0;
+        T ra = 0, rb = 1, rc = 0, re = 0;
+        if (active) {
+            ra = -cbR1 * vl;
+            rb = db[R] + rw[R] * lm - cbR1 * wl - (has_right ? cbR * vfn : (T)0);
+            rc = has_right ? -cbR * wfn : (T)0;
+            re = col[prow(R)] + cbR1 * gl + (has_right ? cbR * gfn : (T)0);
+        }
+        // parallel cyclic reduction over the S interface unknowns
+        for (int k = 1; k < S; k <<= 1) {
+            const T am = __shfl_up(ra, k, 64), bm = __shfl_up(rb, k, 64);
+            const T cm = __shfl_up(rc, k, 64), em = __shfl_up(re, k, 64);
+            const T ap = __shfl_down(ra, k, 64), bp = __shfl_down(rb, k, 64);
+            const T cq = __shfl_down(rc, k, 64), ep = __shfl_down(re, k, 64);
+            const bool hm = lane >= k, hp = lane + k < S;
+            const T al = hm ? -ra / bm : (T)0;
+            const T ga = hp ? -rc / bp : (T)0;
+            const T na = hm ? al * am : (T)0;
+            const T nc = hp ? ga * cq : (T)0;
+            const T nb = rb + (hm ? al * cm : (T)0) + (hp ? ga * ap : (T)0);
+            const T ne = re + (hm ? al * em : (T)0) + (hp ? ga * ep : (T)0);
+            if (active) { ra = na; rb = nb; rc = nc; re = ne; }
+        }
+        const T xs = active ? re / rb : (T)0;
+        T xm = __shfl_up(xs, 1, 64);
+        if (lane == 0) xm = 0;
+        // interior values: forward-eliminated rhs y' = g' + v' x_{s-1} (+ w' x_s
+        // on the last interior row), then the backward sweep
+        if (active) {
+            T y = gp[0];  // placeholder, overwritten below
+#pragma unroll
+            for (int t = LMAX - 1; t >= 0; --t) {
+                if (t < n) {
+                    T yp = gp[t] + vp[t] * xm;
+                    if (t == n - 1) y = yp + wl * xs;
+                    else y = yp - cp[t] * y;
+                    col[prow(lo + t)] = y;
+                }
+            }
+            col[prow(R)] = xs;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
+        const int row = e / M, m = e - row * M;
+        spec[(size_t)row * nz + l0 + m] = tile[m * pitch + prow(row)];
+    }
+}
+
+template <typename T>
+struct Tables {
+    const typename vec2_of<T>::type *tw, *pt;
+    const T *cb, *db, *rw, *lam;
+};
+template <typename T> Tables<T> tables(const Operator &op);
+template <> Tables<float> tables<float>(const Operator &op)
+{
+    return {op.tw32, op.pt32, op.cb32, op.db32, op.rw32, op.lam32};
+}
+template <> Tables<double> tables<double>(const Operator &op)
+{
+    return {op.tw64, op.pt64, op.cb64, op.db64, op.rw64, op.lam64};
+}
+
+template <typename T, int BC>
+void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
+{
+    const int N = op.nz;
+    const auto tb = tables<T>(op);
+    const size_t shm = 2 * (size_t)N * sizeof(cx<T>);
+    const int thr = fft_threads(N);
+    if (a.fused)
+        hipLaunchKernelGGL((k_zfwd<T, BC, true>), dim3(op.nr), dim3(thr), shm, s, nullptr, a.x, a.r, a.p, a.q,
+                           a.state, op.partials, op.tickets, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
+    else
+        hipLaunchKernelGGL((k_zfwd<T, BC, false>), dim3(op.nr), dim3(thr), shm, s, a.rin, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, op.partials, op.tickets, (T *)op.spec, tb.tw, tb.pt,
+                           op.nr, N);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T, int BC>
+void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
+{
+    const int N = op.nz;
+    const auto tb = tables<T>(op);
+    const size_t shm = 2 * (size_t)N * sizeof(cx<T>);
+    const int thr = fft_threads(N);
+    switch (a.mode) {
+    case 0:
+        hipLaunchKernelGGL((k_zinv<T, BC, 0>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           nullptr, nullptr, op.partials, op.tickets, tb.tw, tb.pt, op.nr, N);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_zinv<T, BC, 1>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           a.r, a.state, op.partials, op.tickets, tb.tw, tb.pt, op.nr, N);
+        break;
+    default:
+        hipLaunchKernelGGL((k_zinv<T, BC, 2>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           a.r, a.state, op.partials, op.tickets, tb.tw, tb.pt, op.nr, N);
+        break;
+    }
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+struct TriGeom {
+    int M, S, L, Lp, pitch;
+    size_t shm;
+};
+
+template <typename T>
+TriGeom tri_geom(int nr, int nz)
+{
+    TriGeom g;
+    g.S = nr / 2 < 64 ? nr / 2 : 64;
+    g.L = (nr + g.S - 1) / g.S;
+    g.Lp = nr / g.S;
+    g.pitch = nr + nr / g.Lp + 1;
+    g.M = 4;
+    while (g.M > 1 && ((size_t)g.M * g.pitch * sizeof(T) > 65536 || nz % g.M != 0)) g.M >>= 1;
+    g.shm = (size_t)g.M * g.pitch * sizeof(T);
+    return g;
+}
+
+template <typename T>
+void tridiag_t(const Operator &op, const PcgState *gate, hipStream_t s)
+{
+    const TriGeom g = tri_geom<T>(op.nr, op.nz);
+    const auto tb = tables<T>(op);
+    const dim3 grid(op.nz / g.M), block(64 * g.M);
+    T *spec = (T *)op.spec;
+#define AXI_TRI(LM)                                                                                    \
+    hipLaunchKernelGGL((k_tridiag<T, LM>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam, gate, \
+                       op.nr, op.nz, g.M, g.S, g.pitch, g.Lp)
+    if (g.L <= 4) AXI_TRI(4);
+    else if (g.L <= 8) AXI_TRI(8);
+    else if (g.L <= 16) AXI_TRI(16);
+    else if (g.L <= 32) AXI_TRI(32);
+    else if (g.L <= 64) AXI_TRI(64);
+    else throw Error{AXIPCG_EINVAL, "nr too large for the r-solver"};
+#undef AXI_TRI
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace
+
+void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
+{
+    if (prec == AXIPCG_PREC_FP32) {
+        if (op.bc_z == DIR) zfwd_t<float, DIR>(op, a, s);
+        else zfwd_t<float, AXIPCG_Z_NEUMANN>(op, a, s);
+    } else {
+        if (op.bc_z == DIR) zfwd_t<double, DIR>(op, a, s);
+        else zfwd_t<double, AXIPCG_Z_NEUMANN>(op, a, s);
+    }
+}
+
+void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
+{
+    if (prec == AXIPCG_PREC_FP32) {
+        if (op.bc_z == DIR) zinv_t<float, DIR>(op, a, s);
+        else zinv_t<float, AXIPCG_Z_NEUMANN>(op, a, s);
+    } else {
+        if (op.bc_z == DIR) zinv_t<double, DIR>(op, a, s);
+        else zinv_t<double, AXIPCG_Z_NEUMANN>(op, a, s);
+    }
+}
+
+void launch_tridiag(const Operator &op, int prec, const PcgState *gate, hipStream_t s)
+{
+    if (prec == AXIPCG_PREC_FP32) tridiag_t<float>(op, gate, s);
+    else tridiag_t<double>(op, gate, s);
+}
+
+void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s)
+{
+    ZfwdArgs fa;
+    fa.rin = r;
+    launch_zfwd(op, prec, fa, s);
+    launch_tridiag(op, prec, nullptr, s);
+    ZinvArgs ia;
+    ia.zout = z;
+    launch_zinv(op, prec, ia, s);
+}
+
+}  // namespace axipcg

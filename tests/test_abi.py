@@ -1,0 +1,99 @@
+"""C-ABI checks that need no GPU: the library loads, exports every entry point
+declared in include/axipcg.h, and rejects invalid arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    hdr = open(os.path.join(ROOT, "include", "axipcg.h")).read()
+    hdr = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    return sorted(set(re.findall(r"\b(axipcg_[A-Za-z_0-9]+)\s*\(", hdr)))
+
+
+@pytest.fixture(scope="module")
+def ax():
+    from paper_1002_3094_amd import axipcg
+    axipcg.lib()
+    return axipcg
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for expected in ("axipcg_op_create", "axipcg_precond_apply", "axipcg_pcg_solve", "axipcg_apply_A",
+                     "axipcg_laguerre_rhs", "axipcg_laguerre_coeffs", "axipcg_residual_norm"):
+        assert expected in names
+
+
+def test_every_declared_symbol_is_exported(ax):
+    h = ctypes.CDLL(ax.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(h, n)]
+    assert not missing, missing
+    # and the binding covers them with the same names
+    assert set(_declared()) <= set(ax.SIGNATURES)
+
+
+def test_binding_never_imports_the_oracle():
+    import paper_1002_3094_amd.axipcg as b
+    src = open(b.__file__).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+
+
+def test_strerror(ax):
+    assert ax.strerror(ax.EINVAL) == "invalid argument"
+    assert ax.strerror(ax.ENOTCONV) == "not converged within maxit"
+    assert ax.strerror(12345) == "unknown status"
+
+
+@pytest.mark.parametrize("case", ["nz_not_pow2", "kappa_nonpositive", "q_negative", "nan", "nr_small", "bc"])
+def test_op_create_validates_before_device_work(ax, case):
+    nr, nz, bc = 8, 8, 0
+    kappa = np.ones((nr, nz))
+    q = np.zeros((nr, nz))
+    if case == "nz_not_pow2":
+        nz = 12
+        kappa = np.ones((nr, nz))
+        q = np.zeros((nr, nz))
+    elif case == "kappa_nonpositive":
+        kappa[3, 3] = 0.0
+    elif case == "q_negative":
+        q[1, 2] = -1e-3
+    elif case == "nan":
+        kappa[0, 0] = np.nan
+    elif case == "nr_small":
+        nr = 1
+        kappa = np.ones((nr, nz))
+        q = np.zeros((nr, nz))
+    elif case == "bc":
+        bc = 7
+    out = ctypes.c_void_p()
+    lib = ax.lib()
+    code = lib.axipcg_op_create(nr, nz, 1.0, 1.0, bc, kappa.ctypes.data_as(ax._dp), q.ctypes.data_as(ax._dp),
+                                -1.0, -1.0, None, ctypes.byref(out))
+    assert code == ax.EINVAL
+    assert out.value is None
+    assert ax.last_error() != ""
+
+
+def test_null_handles_rejected(ax):
+    lib = ax.lib()
+    assert lib.axipcg_apply_A(None, None, None, None) == ax.EINVAL
+    assert lib.axipcg_pcg_solve(None, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
+    assert lib.axipcg_precond_apply(None, None, None, 1, None) == ax.EINVAL
+    lib.axipcg_op_destroy(None)  # NULL-safe
+
+
+def test_laguerre_coeffs_validates(ax):
+    lib = ax.lib()
+    f = np.zeros(2)
+    g = np.zeros(4)
+    assert lib.axipcg_laguerre_coeffs(4, 10.0, 2, 0.2, f.ctypes.data_as(ax._dp), g.ctypes.data_as(ax._dp),
+                                      None) == ax.EINVAL
+    assert lib.axipcg_laguerre_coeffs(0, 10.0, 8, 0.2, f.ctypes.data_as(ax._dp), g.ctypes.data_as(ax._dp),
+                                      None) == ax.EINVAL
