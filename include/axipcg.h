@@ -159,6 +159,23 @@ int axipcg_laguerre_rhs(axipcg_op_t op, double g_m, int src_i, int src_k,
                         const double *coef, const double *u_prev,
                         double *S1, double *S2, double *b, void *stream);
 
+/* ---- per-kernel timing (tracing aid) ----------------------------------------
+ * Select one kernel class of the PCG iteration; pcg_solve then brackets each
+ * launch of that class that does work (iterations before the stop test
+ * fired) with a pair of HIP events on the caller's stream and adds the
+ * elapsed times once the solve has synchronised.  AXIPCG_KERNEL_NONE turns
+ * the timing off (the default).  profile_read returns the accumulated time
+ * and launch count (host pointers, may be NULL) and clears them if reset. */
+enum {
+    AXIPCG_KERNEL_NONE = -1,
+    AXIPCG_KERNEL_SPMV = 0,    /* p update, q = A p, p.q           */
+    AXIPCG_KERNEL_ZFWD = 1,    /* x, r update, ||r||^2, transform  */
+    AXIPCG_KERNEL_TRIDIAG = 2, /* r-solves, one per z-mode         */
+    AXIPCG_KERNEL_ZINV = 3     /* inverse transform, r.z           */
+};
+int axipcg_profile_select(axipcg_op_t op, int kernel);
+int axipcg_profile_read(axipcg_op_t op, double *total_ms, long long *launches, int reset);
+
 /* ---- errors ---------------------------------------------------------------- */
 const char *axipcg_strerror(int code);
 /* Message of the last failing call on this host thread ("" if none). */

@@ -20,6 +20,7 @@ OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 Z_DIRICHLET, Z_NEUMANN = 0, 1
 PREC_FP64, PREC_FP32 = 0, 1
 FLAG_TRUE_RESIDUAL, FLAG_POLAK_RIBIERE = 1, 2
+KERNEL_NONE, KERNEL_SPMV, KERNEL_ZFWD, KERNEL_TRIDIAG, KERNEL_ZINV = -1, 0, 1, 2, 3
 
 _lib = None
 
@@ -54,6 +55,8 @@ SIGNATURES = {
     "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "axipcg_profile_select": ([_vp, _i], _i),
+    "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
     "axipcg_last_error": ([], ctypes.c_char_p),
 }
@@ -211,6 +214,17 @@ def laguerre_rhs(op: Op, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=N
     _check(lib().axipcg_laguerre_rhs(op.handle, g_m, src_i, src_k, _opt_dev(coef, "coef"),
                                      _opt_dev(u_prev, "u_prev"), _dev(S1, "S1"), _dev(S2, "S2"),
                                      _dev(b, "b"), _stream(stream)), "laguerre_rhs")
+
+
+def profile_select(op: Op, kernel: int):
+    _check(lib().axipcg_profile_select(op.handle, kernel), "profile_select")
+
+
+def profile_read(op: Op, reset: bool = False):
+    ms = ctypes.c_double()
+    n = ctypes.c_longlong()
+    _check(lib().axipcg_profile_read(op.handle, ctypes.byref(ms), ctypes.byref(n), int(reset)), "profile_read")
+    return ms.value, n.value
 
 
 def strerror(code: int) -> str:

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "axipcg.h"
 
@@ -97,6 +98,14 @@ struct Operator {
     double *dscal = nullptr;         // 16 device scalars (residual norms)
     PcgState *state_host = nullptr;  // pinned mirror
     double *scratch_host = nullptr;  // pinned host scalars
+
+    // per-kernel timing (axipcg_profile_*)
+    int prof_kernel = -1;
+    std::vector<hipEvent_t> prof_events;  // pairs (start, stop)
+    std::vector<int> prof_iter;           // iteration of each pair
+    size_t prof_used = 0;
+    double prof_ms = 0.0;
+    long long prof_count = 0;
 };
 
 // Run an ABI body: translate exceptions into status codes and keep the

@@ -123,15 +123,43 @@ struct SolveCtx {
     hipStream_t s;
 };
 
-void launch_iteration(const SolveCtx &c, int parity)
+// Event pair around one launch of the profiled kernel class.
+struct ProfScope {
+    Operator &op;
+    hipStream_t s;
+    bool on;
+    size_t slot = 0;
+    ProfScope(Operator &o, hipStream_t st, int kernel, int iter) : op(o), s(st), on(o.prof_kernel == kernel)
+    {
+        if (!on) return;
+        slot = op.prof_used++;
+        while (op.prof_events.size() < 2 * op.prof_used) {
+            hipEvent_t e;
+            AXI_CHECK_HIP(hipEventCreate(&e));
+            op.prof_events.push_back(e);
+        }
+        if (op.prof_iter.size() < op.prof_used) op.prof_iter.resize(op.prof_used);
+        op.prof_iter[slot] = iter;
+        AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot], s));
+    }
+    ~ProfScope() noexcept(false)
+    {
+        if (on) AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot + 1], s));
+    }
+};
+
+void launch_iteration(const SolveCtx &c, int parity, int iter)
 {
     Operator &op = *c.op;
     const size_t n = (size_t)op.nr * op.nz;
     double *pold = parity ? op.p1 : op.p0;
     double *pnew = parity ? op.p0 : op.p1;
-    hipLaunchKernelGGL(k_pcg_spmv, dim3(pointwise_blocks(n)), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D,
-                       op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, op.tickets);
-    AXI_CHECK_HIP(hipGetLastError());
+    {
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_SPMV, iter);
+        hipLaunchKernelGGL(k_pcg_spmv, dim3(pointwise_blocks(n)), dim3(256), 0, c.s, op.z, pold, pnew, op.q,
+                           op.D, op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, op.tickets);
+        AXI_CHECK_HIP(hipGetLastError());
+    }
     ZfwdArgs fa;
     fa.fused = true;
     fa.x = c.x;
@@ -139,14 +167,41 @@ void launch_iteration(const SolveCtx &c, int parity)
     fa.p = pnew;
     fa.q = op.q;
     fa.state = op.state;
-    launch_zfwd(op, c.prec, fa, c.s);
-    launch_tridiag(op, c.prec, op.state, c.s);
+    {
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_ZFWD, iter);
+        launch_zfwd(op, c.prec, fa, c.s);
+    }
+    {
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_TRIDIAG, iter);
+        launch_tridiag(op, c.prec, op.state, c.s);
+    }
     ZinvArgs ia;
     ia.zout = op.z;
     ia.r = op.r;
     ia.state = op.state;
     ia.mode = 1;
-    launch_zinv(op, c.prec, ia, c.s);
+    {
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_ZINV, iter);
+        launch_zinv(op, c.prec, ia, c.s);
+    }
+}
+
+// Add the timed launches that did work: the SpMV and forward kernels of
+// iterations 0..iters-1, the r-solve and inverse of iterations 0..iters-2
+// (the stop test fires inside the forward kernel).
+void collect_profile(Operator &op, int iters)
+{
+    for (size_t k = 0; k < op.prof_used; ++k) {
+        const int it = op.prof_iter[k];
+        const int limit = (op.prof_kernel == AXIPCG_KERNEL_SPMV || op.prof_kernel == AXIPCG_KERNEL_ZFWD)
+                              ? iters : iters - 1;
+        if (it >= limit) continue;
+        float ms = 0.f;
+        AXI_CHECK_HIP(hipEventElapsedTime(&ms, op.prof_events[2 * k], op.prof_events[2 * k + 1]));
+        op.prof_ms += ms;
+        op.prof_count += 1;
+    }
+    op.prof_used = 0;
 }
 
 int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit, int prec, unsigned flags,
@@ -176,11 +231,12 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     // iterations, in chunks; the first chunk is sized from the previous solve
     int launched = 0;
     int parity = 0;
+    op.prof_used = 0;
     int chunk = op.last_iters > 2 ? op.last_iters - 1 : 4;
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
         for (int it = 0; it < chunk; ++it) {
-            launch_iteration(c, parity);
+            launch_iteration(c, parity, launched + it);
             parity ^= 1;
         }
         launched += chunk;
@@ -191,6 +247,7 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     }
     const PcgState h = *op.state_host;
     op.last_iters = h.iters;
+    if (op.prof_kernel >= 0) collect_profile(op, h.iters);
     int status;
     if (h.done == 1 || h.done == 4) status = AXIPCG_OK;
     else if (h.done == 2) status = AXIPCG_EBREAKDOWN;
@@ -219,6 +276,33 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
 }  // namespace axipcg
 
 using namespace axipcg;
+
+extern "C" int axipcg_profile_select(axipcg_op_t h, int kernel)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        AXI_REQUIRE(kernel >= AXIPCG_KERNEL_NONE && kernel <= AXIPCG_KERNEL_ZINV, "unknown kernel class");
+        op->prof_kernel = kernel;
+        op->prof_used = 0;
+        return AXIPCG_OK;
+    });
+}
+
+extern "C" int axipcg_profile_read(axipcg_op_t h, double *total_ms, long long *launches, int reset)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        if (total_ms) *total_ms = op->prof_ms;
+        if (launches) *launches = op->prof_count;
+        if (reset) {
+            op->prof_ms = 0.0;
+            op->prof_count = 0;
+        }
+        return AXIPCG_OK;
+    });
+}
 
 extern "C" int axipcg_pcg_solve(axipcg_op_t h, const double *b, double *x, double rtol, int maxit, int prec,
                                 unsigned flags, axipcg_stats *st, void *stream)

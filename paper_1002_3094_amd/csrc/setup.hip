@@ -183,6 +183,7 @@ void free_op(Operator *op)
                     op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->tickets, op->state, op->dscal};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (hipEvent_t e : op->prof_events) (void)hipEventDestroy(e);
     if (op->state_host) (void)hipHostFree(op->state_host);
     if (op->scratch_host) (void)hipHostFree(op->scratch_host);
     delete op;

@@ -1,0 +1,86 @@
+"""Parity at the benchmark's sizes, in the launch configuration bench.py times.
+
+* single solve on the 1024^2 layered medium with the spatial Ricker source,
+  FP64 and FP32 preconditioner, error <= 1e-8 vs the oracle;
+* Laguerre source coefficients g_m (device trapezoid rule vs the oracle's
+  Simpson rule on the same samples) to 1e-10 relative;
+* the Laguerre series itself: the GPU chain (running-sum right-hand sides,
+  previous-harmonic guess, FP32 preconditioner, rtol 1e-10) against the
+  oracle's chain (direct history sum, FP64, rtol 1e-13) from the same seeded
+  inputs, every harmonic within 1e-8 relative L2.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev, host, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1002_3094_amd import axipcg
+    axipcg.lib()
+    return axipcg
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_layered_1024_single_solve(ax, orc, prec):
+    log(f"layered 1024^2 single solve prec={prec}")
+    p = synth.problem_layered(1024, 1024, seed=0)
+    oop = orc.operator_from_cells(p.kappa, p.q)
+    bo = orc.rhs(oop, p.f)
+    xr = orc.solve_reference(oop, bo, rtol=1e-13)
+    with ax.op_create(p.kappa, p.q) as op:
+        b = dev(np.zeros((1024, 1024)))
+        ax.rhs_from_f(op, dev(p.f), b)
+        x = dev(np.zeros((1024, 1024)))
+        st = ax.pcg_solve(op, b, x, 1e-10, 500, prec, ax.FLAG_TRUE_RESIDUAL)
+        xg = host(x)
+    err = rel(xg, xr)
+    log(f"  iters={st['iters']} relres_true={st['relres_true']:.2e} err={err:.2e}")
+    assert st["code"] == ax.OK and err <= 1e-8
+
+
+@pytest.mark.parametrize("n,eta", [(400, 10.0), (64, 300.0)])
+def test_laguerre_coeffs_match_oracle(ax, orc, n, eta):
+    log(f"laguerre coeffs n={n} eta={eta}")
+    t, ft = synth.ricker_pulse_samples()
+    gg = ax.laguerre_coeffs(n, eta, ft, t[-1])
+    go = orc.laguerre_coeffs(n, eta, ft, t[-1])
+    assert np.abs(gg - go).max() <= 1e-10 * np.abs(go).max()
+
+
+def _gpu_chain(ax, inp, n_harm, prec=1):
+    nr, nz = inp["kappa"].shape
+    g = ax.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
+    out, stats = [], []
+    with ax.op_create(inp["kappa"], inp["q"]) as op:
+        S1 = dev(np.zeros((nr, nz)))
+        S2 = dev(np.zeros((nr, nz)))
+        b = dev(np.zeros((nr, nz)))
+        u = dev(np.zeros((nr, nz)))
+        for m in range(n_harm):
+            ax.laguerre_rhs(op, float(g[m]), inp["src_i"], inp["src_k"], S1, S2, b, u_prev=(u if m else None))
+            st = ax.pcg_solve(op, b, u, 1e-10, 1000, prec)
+            assert st["code"] == ax.OK
+            out.append(host(u).copy())
+            stats.append(st["iters"])
+    return out, stats
+
+
+@pytest.mark.parametrize("nr,nz,n_harm", [(64, 64, 12), (1024, 1024, 3), (2048, 2048, 2)])
+def test_laguerre_chain_matches_oracle(ax, orc, nr, nz, n_harm):
+    log(f"laguerre chain {nr}x{nz} harmonics={n_harm}")
+    inp = synth.laguerre_series_inputs(nr, nz, seed=0)
+    ug, its = _gpu_chain(ax, inp, n_harm)
+    oop = orc.operator_from_cells(inp["kappa"], inp["q"])
+    go = orc.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
+    uo, ost = orc.laguerre_chain(oop, inp["kappa"], go, inp["eta"], inp["src_i"], inp["src_k"], n_harm,
+                                 rtol=1e-13 if nr < 2048 else 1e-12)
+    errs = [rel(a, b) for a, b in zip(ug, uo)]
+    log(f"  iters={its} errs={[f'{e:.1e}' for e in errs]}")
+    assert max(errs) <= 1e-8
