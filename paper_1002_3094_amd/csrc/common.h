@@ -39,27 +39,31 @@ void clear_last_error();
     } while (0)
 
 // ---------------------------------------------------------------------------
-// Device-side PCG scalars.  One instance per operator, written only by the
-// "last block" of the kernel that completes a reduction.
+// Device-side PCG scalars.  No kernel both reads and writes a field: every
+// field is written by workgroup 0 of one kernel and read by later kernels
+// (kernel boundaries order the accesses).  The scalars of a reduction are
+// recomputed by every workgroup of the consuming kernel from the producer's
+// per-workgroup partial sums, in a fixed order, so all workgroups agree.
 // ---------------------------------------------------------------------------
 struct PcgState {
-    double rho;      // r . z of the current iterate
-    double alpha;    // rho / (p . Ap)
-    double beta;     // rho_new / rho_old
-    double rr;       // ||r||^2
-    double bb;       // ||b||^2
-    double tol2;     // rtol^2 ||b||^2
-    double rz_old;   // r_new . z_old (Polak-Ribiere)
-    double pad0;
-    int done;        // 0 running, 1 converged, 2 breakdown
-    int iters;       // completed iterations
+    double rho[2];   // r.z of iteration k at slot k & 1 (SpMV kernel)
+    double rr;       // ||r||^2 after the last update (r-solve kernel)
+    double bb;       // ||b||^2 (start)
+    double tol2;     // rtol^2 ||b||^2 (start)
+    double pad[3];
+    int done;        // 0 running, 1 converged, 2 breakdown, 3 maxit, 4 b = 0
+    int iters;       // completed iterations (r-solve kernel)
+    int cur;         // iteration being processed (forward kernel)
     int maxit;
     int flags;
+    int pad2[3];
 };
 
 // Reduction slots: each fused kernel owns one ticket counter and one
 // partial-sum array in the operator's workspace.
 enum Slot { SLOT_PQ = 0, SLOT_RR = 1, SLOT_RZ = 2, SLOT_MISC = 3, SLOT_RZOLD = 4, NUM_SLOTS = 5 };
+// PCG kernel status codes stored in PcgState::done
+enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_BZERO = 4 };
 
 constexpr int MAX_PARTIALS = 16384;
 
@@ -92,8 +96,7 @@ struct Operator {
     // PCG workspace (device)
     double *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     void *spec = nullptr;          // spectral buffer, nr*nz doubles (used as float or double)
-    double *partials = nullptr;    // [NUM_SLOTS][MAX_PARTIALS]
-    unsigned *tickets = nullptr;   // [NUM_SLOTS] (64-byte strided)
+    double *partials = nullptr;    // [NUM_SLOTS][MAX_PARTIALS] per-workgroup partial sums
     PcgState *state = nullptr;
     double *dscal = nullptr;         // 16 device scalars (residual norms)
     PcgState *state_host = nullptr;  // pinned mirror
@@ -157,39 +160,19 @@ __device__ inline double block_sum(double v, double *sm)
     return s;
 }
 
-__device__ inline double load_agent(const double *p)
-{
-    unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double(static_cast<long long>(u));
-}
-
-// Publish this block's partial sum; returns true in every thread of the block
-// that finishes last.  That block then sees every partial through
-// load_agent().  The ticket is reset by the last block.
-__device__ inline bool publish_partial(double blocksum, double *partials, unsigned *ticket,
-                                       unsigned nblocks, int bid)
-{
-    __shared__ int am_last;
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(reinterpret_cast<unsigned long long *>(partials + bid),
-                           static_cast<unsigned long long>(__double_as_longlong(blocksum)),
-                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        am_last = (t == nblocks - 1);
-        if (am_last) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    return am_last != 0;
-}
-
-// Sum of partials[0..n) in a fixed order (strided per thread, then the block
-// tree); valid in thread 0.
-__device__ inline double sum_partials(const double *partials, unsigned n, double *sm)
+// Sum of parts[0..n) in a fixed order (strided per thread, then the block
+// tree), returned in every thread.  `sm` needs blockDim.x / 64 + 1 doubles.
+__device__ inline double block_total(const double *__restrict__ parts, int n, double *sm)
 {
     double s = 0.0;
-    for (unsigned i = threadIdx.x; i < n; i += blockDim.x) s += load_agent(partials + i);
-    return block_sum(s, sm);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += parts[i];
+    s = block_sum(s, sm);
+    const int nw = (blockDim.x + 63) >> 6;
+    if (threadIdx.x == 0) sm[nw] = s;
+    __syncthreads();
+    s = sm[nw];
+    __syncthreads();
+    return s;
 }
 
 // Map a block index to a logical tile so that each XCD (blocks are dealt to

@@ -7,30 +7,44 @@ namespace axipcg {
 
 // Forward z-transform of every r-row (§4.2 eq. (38)).
 //  plain: spec = S rin
-//  fused PCG step (iteration after SpMV): x += alpha p, r -= alpha q,
-//    ||r||^2 reduced into state->rr (iteration counter and stop test updated
-//    by the last block), then spec = S r.
+//  fused PCG step (after the SpMV kernel): alpha = rho / p.q from the SpMV
+//    partials (p.q <= 0 marks a breakdown), x += alpha p, r -= alpha q,
+//    one ||r||^2 partial per workgroup, then spec = S r.
 struct ZfwdArgs {
     const double *rin = nullptr;           // plain mode input
     double *x = nullptr, *r = nullptr;     // fused mode
     const double *p = nullptr, *q = nullptr;
     PcgState *state = nullptr;             // fused: gate + scalars
+    int n_pq = 0;                          // fused: number of p.q partials
     bool fused = false;
 };
 void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s);
 
 // One r-tridiagonal solve per z-mode, in place on op.spec (§4.2 eq. (39)).
-void launch_tridiag(const Operator &op, int prec, const PcgState *gate, hipStream_t s);
+//  mode 0: plain;
+//  mode 1: PCG step: ||r||^2 from the forward kernel's partials -> stop test
+//          (workgroup 0 records it), then solve unless stopped;
+//  mode 2: PCG start: ||r||^2 and ||b||^2 from the start kernel's partials ->
+//          state initialised, start test, then solve unless stopped.
+struct TriGate {
+    int mode = 0;
+    PcgState *state = nullptr;
+    int n_rr = 0;          // partials of ||r||^2 (and of ||b||^2 in mode 2)
+    double rtol2 = 0.0;    // mode 2
+    int maxit = 0, flags = 0;
+};
+void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t s);
 
 // Inverse z-transform of every row: zout = S^T spec.
-//  mode 0: plain;  mode 1: PCG step, rho' = r.z reduced, beta and rho
-//  updated by the last block (Polak-Ribiere if state->flags asks);
-//  mode 2: PCG start, rho = r.z, beta = 0.
+//  mode 0: plain;  modes 1 (PCG step) and 2 (PCG start): skipped once the
+//  stop test has fired, one r.z partial per workgroup (and r.z_old for the
+//  Polak-Ribiere form), reduced by the next SpMV kernel.
 struct ZinvArgs {
     double *zout = nullptr;
     const double *r = nullptr;
     PcgState *state = nullptr;
     int mode = 0;
+    bool pr = false;   // also reduce r.z_old (Polak-Ribiere)
 };
 void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s);
 

@@ -1,12 +1,15 @@
 // PCG (§2.2 eq. (8) with conjugate-gradient parameters) on gfx950.
 //
-// One iteration is four stream-ordered launches; every scalar lives in device
-// memory (PcgState) and is produced by the last workgroup of the kernel that
-// completes its reduction, so the host never waits inside an iteration:
-//   1. p = z + beta p_old (ping-pong), q = A p, p.q  -> alpha = rho / p.q
-//   2. x += alpha p, r -= alpha q, ||r||^2 -> stop test; forward z-transform of r
-//   3. r-tridiagonal solves of the preconditioner
-//   4. inverse z-transform -> z, r.z -> beta, rho
+// One iteration k is four stream-ordered launches.  Each kernel writes one
+// partial sum per workgroup; the next kernel's workgroups each sum those
+// partials in the same fixed order and take the same decision, so the host
+// never waits inside an iteration and no atomics are needed:
+//   1. SpMV:    rho_k = sum(r.z partials), beta = rho_k / rho_{k-1};
+//               p = z + beta p_old (ping-pong buffers), q = A p, p.q partials
+//   2. forward: alpha = rho_k / p.q; x += alpha p, r -= alpha q, ||r||^2
+//               partials; z-transform of r
+//   3. r-solve: ||r||^2 -> stop test (sets `done`); r-tridiagonal solves
+//   4. inverse: inverse z-transform -> z, r.z partials
 // After the stop test fires, the remaining launches of the chunk return at
 // once.  The host reads the state back once per chunk of iterations.
 #include <cmath>
@@ -15,111 +18,127 @@
 
 namespace axipcg {
 
-void apply_impl(const Operator &op, const double *x, double *y, hipStream_t s);
 void resid_impl(const Operator &op, const double *b, const double *x, double *out_dev, hipStream_t s);
 
 namespace {
 
-// p_new = z + beta p_old; q = A p_new; reduce p_new . q.
+inline unsigned row_blocks(int nr) { return (unsigned)(nr < MAX_PARTIALS ? nr : MAX_PARTIALS); }
+
+// 5-point stencil of the r-weighted scheme at (i, k) applied to the field
+// returned by `val(offset)`.
+template <typename F>
+__device__ inline double stencil(const double *__restrict__ D, const double *__restrict__ CR,
+                                 const double *__restrict__ CZ, size_t e, int i, int k, int nr, int nz, F val)
+{
+    double v = D[e] * val(0);
+    if (i + 1 < nr) v -= CR[e] * val((long)nz);
+    if (i > 0) v -= CR[e - nz] * val(-(long)nz);
+    if (k + 1 < nz) v -= CZ[e] * val(1);
+    if (k > 0) v -= CZ[e - 1] * val(-1);
+    return v;
+}
+
+// rho_k, beta; p_new = z + beta p_old; q = A p_new; p_new . q partials.
+// A z and A p_old are formed first (no scalar needed), so the loads overlap
+// the reduction of the r.z partials; q = A z + beta A p_old is the same
+// product up to rounding (no recurrence: both terms are recomputed from the
+// stored vectors every iteration).
+constexpr int SPMV_PPT = 8;   // points per thread per row (nz <= 2048, 256 threads)
+
+template <bool PR>
 __global__ void __launch_bounds__(256)
 k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double *__restrict__ pnew,
            double *__restrict__ q, const double *__restrict__ D, const double *__restrict__ CR,
-           const double *__restrict__ CZ, int nr, int nz, PcgState *st, double *partials, unsigned *tickets)
+           const double *__restrict__ CZ, int nr, int nz, PcgState *st, double *__restrict__ partials, int n_rz)
 {
     if (st->done) return;
     __shared__ double red[8];
-    const double beta = st->beta;
-    const size_t n = (size_t)nr * nz;
+    const int k_it = st->iters;
     double acc = 0.0;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
-        const double pc = z[e] + beta * pold[e];
-        double v = D[e] * pc;
-        if (i + 1 < nr) v -= CR[e] * (z[e + nz] + beta * pold[e + nz]);
-        if (i > 0) v -= CR[e - nz] * (z[e - nz] + beta * pold[e - nz]);
-        if (k + 1 < nz) v -= CZ[e] * (z[e + 1] + beta * pold[e + 1]);
-        if (k > 0) v -= CZ[e - 1] * (z[e - 1] + beta * pold[e - 1]);
-        pnew[e] = pc;
-        q[e] = v;
-        acc += pc * v;
-    }
-    const double s = block_sum(acc, red);
-    if (publish_partial(s, partials + SLOT_PQ * MAX_PARTIALS, tickets + SLOT_PQ * 16, gridDim.x, blockIdx.x)) {
-        const double pq = sum_partials(partials + SLOT_PQ * MAX_PARTIALS, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            if (!(pq > 0.0) || !(pq < 1e308)) st->done = 2;
-            else st->alpha = st->rho / pq;
+    double beta = 0.0;
+    bool have_beta = false;
+    for (int b = blockIdx.x; b < nr; b += gridDim.x) {
+        const int i = xcd_swizzle(b, nr);
+        double az[SPMV_PPT], ap[SPMV_PPT], zc[SPMV_PPT], pc[SPMV_PPT];
+#pragma unroll
+        for (int j = 0; j < SPMV_PPT; ++j) {
+            const int k = threadIdx.x + j * 256;
+            if (k < nz) {
+                const size_t e = (size_t)i * nz + k;
+                zc[j] = z[e];
+                pc[j] = pold[e];
+                az[j] = stencil(D, CR, CZ, e, i, k, nr, nz, [&](long o) { return z[e + o]; });
+                ap[j] = stencil(D, CR, CZ, e, i, k, nr, nz, [&](long o) { return pold[e + o]; });
+            }
+        }
+        if (!have_beta) {   // scalars once per workgroup, after the first row's loads
+            const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
+            if (k_it > 0) {
+                double num = rho;
+                if (PR) num -= block_total(partials + SLOT_RZOLD * MAX_PARTIALS, n_rz, red);
+                beta = num / st->rho[(k_it - 1) & 1];
+            }
+            if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k_it & 1] = rho;
+            have_beta = true;
+        }
+#pragma unroll
+        for (int j = 0; j < SPMV_PPT; ++j) {
+            const int k = threadIdx.x + j * 256;
+            if (k < nz) {
+                const size_t e = (size_t)i * nz + k;
+                const double p_new = (k_it > 0) ? zc[j] + beta * pc[j] : zc[j];
+                const double q_new = (k_it > 0) ? az[j] + beta * ap[j] : az[j];
+                pnew[e] = p_new;
+                q[e] = q_new;
+                acc += p_new * q_new;
+            }
         }
     }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[SLOT_PQ * MAX_PARTIALS + blockIdx.x] = s;
 }
 
-// r = b - A x; ||r||^2 and ||b||^2; initial state.
+// r = b - A x; ||r||^2 and ||b||^2 partials.
 __global__ void __launch_bounds__(256)
 k_pcg_init(const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ r,
            const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
-           int nz, PcgState *st, double *partials, unsigned *tickets, double rtol2, int maxit, int flags)
+           int nz, double *__restrict__ partials)
 {
     __shared__ double red[8];
-    const size_t n = (size_t)nr * nz;
     double s_r = 0.0, s_b = 0.0;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
-        double v = D[e] * x[e];
-        if (i + 1 < nr) v -= CR[e] * x[e + nz];
-        if (i > 0) v -= CR[e - nz] * x[e - nz];
-        if (k + 1 < nz) v -= CZ[e] * x[e + 1];
-        if (k > 0) v -= CZ[e - 1] * x[e - 1];
-        const double bv = b[e];
-        const double d = bv - v;
-        r[e] = d;
-        s_r += d * d;
-        s_b += bv * bv;
+    for (int blk = blockIdx.x; blk < nr; blk += gridDim.x) {
+        const int i = xcd_swizzle(blk, nr);
+        for (int k = threadIdx.x; k < nz; k += blockDim.x) {
+            const size_t e = (size_t)i * nz + k;
+            const double v = stencil(D, CR, CZ, e, i, k, nr, nz, [&](long o) { return x[e + o]; });
+            const double bv = b[e];
+            const double d = bv - v;
+            r[e] = d;
+            s_r += d * d;
+            s_b += bv * bv;
+        }
     }
     const double tb = block_sum(s_b, red);
-    if (threadIdx.x == 0)
-        __hip_atomic_store(reinterpret_cast<unsigned long long *>(partials + SLOT_MISC * MAX_PARTIALS + blockIdx.x),
-                           (unsigned long long)__double_as_longlong(tb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double tr = block_sum(s_r, red);
-    if (publish_partial(tr, partials + SLOT_RR * MAX_PARTIALS, tickets + SLOT_RR * 16, gridDim.x, blockIdx.x)) {
-        const double rr = sum_partials(partials + SLOT_RR * MAX_PARTIALS, gridDim.x, red);
-        const double bb = sum_partials(partials + SLOT_MISC * MAX_PARTIALS, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            st->rr = rr;
-            st->bb = bb;
-            st->tol2 = rtol2 * bb;
-            st->iters = 0;
-            st->maxit = maxit;
-            st->flags = flags;
-            st->alpha = 0.0;
-            st->beta = 0.0;
-            st->rho = 0.0;
-            if (bb == 0.0) st->done = 4;               // b = 0: x = 0 is the answer
-            else if (!(rr == rr)) st->done = 2;
-            else st->done = (rr <= st->tol2) ? 1 : 0;
-        }
+    if (threadIdx.x == 0) {
+        partials[SLOT_MISC * MAX_PARTIALS + blockIdx.x] = tb;
+        partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = tr;
     }
 }
 
-// x = 0 when b = 0 (state->done == 4).
+// x = 0 when b = 0.
 __global__ void k_zero_if_b_zero(double *__restrict__ x, size_t n, const PcgState *st)
 {
-    if (st->done != 4) return;
+    if (st->done != ST_BZERO) return;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
         x[e] = 0.0;
 }
 
-__global__ void k_copy_gated(const double *__restrict__ a, double *__restrict__ b, size_t n, const PcgState *st)
-{
-    if (st->done) return;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-        b[e] = a[e];
-}
-
 struct SolveCtx {
     Operator *op;
-    const double *b;
     double *x;
     int prec;
+    bool pr;
     hipStream_t s;
 };
 
@@ -151,13 +170,17 @@ struct ProfScope {
 void launch_iteration(const SolveCtx &c, int parity, int iter)
 {
     Operator &op = *c.op;
-    const size_t n = (size_t)op.nr * op.nz;
     double *pold = parity ? op.p1 : op.p0;
     double *pnew = parity ? op.p0 : op.p1;
+    const unsigned gs = row_blocks(op.nr);
     {
         ProfScope ps(op, c.s, AXIPCG_KERNEL_SPMV, iter);
-        hipLaunchKernelGGL(k_pcg_spmv, dim3(pointwise_blocks(n)), dim3(256), 0, c.s, op.z, pold, pnew, op.q,
-                           op.D, op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, op.tickets);
+        if (c.pr)
+            hipLaunchKernelGGL(k_pcg_spmv<true>, dim3(gs), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D, op.CR,
+                               op.CZ, op.nr, op.nz, op.state, op.partials, op.nr);
+        else
+            hipLaunchKernelGGL(k_pcg_spmv<false>, dim3(gs), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D,
+                               op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, op.nr);
         AXI_CHECK_HIP(hipGetLastError());
     }
     ZfwdArgs fa;
@@ -167,19 +190,25 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
     fa.p = pnew;
     fa.q = op.q;
     fa.state = op.state;
+    fa.n_pq = (int)gs;
     {
         ProfScope ps(op, c.s, AXIPCG_KERNEL_ZFWD, iter);
         launch_zfwd(op, c.prec, fa, c.s);
     }
     {
         ProfScope ps(op, c.s, AXIPCG_KERNEL_TRIDIAG, iter);
-        launch_tridiag(op, c.prec, op.state, c.s);
+        TriGate g;
+        g.mode = 1;
+        g.state = op.state;
+        g.n_rr = op.nr;
+        launch_tridiag(op, c.prec, g, c.s);
     }
     ZinvArgs ia;
     ia.zout = op.z;
     ia.r = op.r;
     ia.state = op.state;
     ia.mode = 1;
+    ia.pr = c.pr;
     {
         ProfScope ps(op, c.s, AXIPCG_KERNEL_ZINV, iter);
         launch_zinv(op, c.prec, ia, c.s);
@@ -188,7 +217,7 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
 
 // Add the timed launches that did work: the SpMV and forward kernels of
 // iterations 0..iters-1, the r-solve and inverse of iterations 0..iters-2
-// (the stop test fires inside the forward kernel).
+// (the last r-solve launch only runs the stop test).
 void collect_profile(Operator &op, int iters)
 {
     for (size_t k = 0; k < op.prof_used; ++k) {
@@ -208,30 +237,36 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
                axipcg_stats *st, hipStream_t s)
 {
     const size_t n = (size_t)op.nr * op.nz;
-    SolveCtx c{&op, b, x, prec, s};
-    // start: r = b - A x, z = B^{-1} r, rho = r.z, p_0 = z
-    hipLaunchKernelGGL(k_pcg_init, dim3(pointwise_blocks(n)), dim3(256), 0, s, b, x, op.r, op.D, op.CR, op.CZ,
-                       op.nr, op.nz, op.state, op.partials, op.tickets, rtol * rtol, maxit, (int)flags);
-    AXI_CHECK_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_zero_if_b_zero, dim3(pointwise_blocks(n)), dim3(256), 0, s, x, n, op.state);
+    SolveCtx c{&op, x, prec, (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0, s};
+    op.prof_used = 0;
+    // start: r = b - A x; z = B^{-1} r (the r-solve launch runs the start test)
+    const unsigned gi = row_blocks(op.nr);
+    hipLaunchKernelGGL(k_pcg_init, dim3(gi), dim3(256), 0, s, b, x, op.r, op.D, op.CR, op.CZ, op.nr, op.nz,
+                       op.partials);
     AXI_CHECK_HIP(hipGetLastError());
     ZfwdArgs fa;
     fa.rin = op.r;
     launch_zfwd(op, prec, fa, s);
-    launch_tridiag(op, prec, op.state, s);
+    TriGate g;
+    g.mode = 2;
+    g.state = op.state;
+    g.n_rr = (int)gi;
+    g.rtol2 = rtol * rtol;
+    g.maxit = maxit;
+    g.flags = (int)flags;
+    launch_tridiag(op, prec, g, s);
+    hipLaunchKernelGGL(k_zero_if_b_zero, dim3(pointwise_blocks(n)), dim3(256), 0, s, x, n, op.state);
+    AXI_CHECK_HIP(hipGetLastError());
     ZinvArgs ia;
     ia.zout = op.z;
     ia.r = op.r;
     ia.state = op.state;
     ia.mode = 2;
     launch_zinv(op, prec, ia, s);
-    hipLaunchKernelGGL(k_copy_gated, dim3(pointwise_blocks(n)), dim3(256), 0, s, op.z, op.p0, n, op.state);
-    AXI_CHECK_HIP(hipGetLastError());
 
     // iterations, in chunks; the first chunk is sized from the previous solve
     int launched = 0;
     int parity = 0;
-    op.prof_used = 0;
     int chunk = op.last_iters > 2 ? op.last_iters - 1 : 4;
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
@@ -242,15 +277,15 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
         launched += chunk;
         AXI_CHECK_HIP(hipMemcpyAsync(op.state_host, op.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
         AXI_CHECK_HIP(hipStreamSynchronize(s));
-        if (op.state_host->done || launched >= maxit) break;
+        if (op.state_host->done != ST_RUN || launched >= maxit) break;
         chunk = 2;
     }
     const PcgState h = *op.state_host;
     op.last_iters = h.iters;
     if (op.prof_kernel >= 0) collect_profile(op, h.iters);
     int status;
-    if (h.done == 1 || h.done == 4) status = AXIPCG_OK;
-    else if (h.done == 2) status = AXIPCG_EBREAKDOWN;
+    if (h.done == ST_CONV || h.done == ST_BZERO) status = AXIPCG_OK;
+    else if (h.done == ST_BREAK) status = AXIPCG_EBREAKDOWN;
     else status = AXIPCG_ENOTCONV;
     if (st) {
         st->iters = h.iters;

@@ -10,37 +10,85 @@ namespace {
 
 constexpr int DIR = AXIPCG_Z_DIRICHLET;
 
+template <typename T> __device__ inline T fast_rcp(T x);
+template <> __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double fast_rcp<double>(double x) { return 1.0 / x; }
+
+// Copy the length-N twiddle table into LDS (when it fits) so that the FFT
+// passes read it without a trip to L2.
+template <typename T>
+__device__ inline const typename vec2_of<T>::type *stage_twiddles(const typename vec2_of<T>::type *tw,
+                                                                  typename vec2_of<T>::type *lds, int N)
+{
+    for (int k = threadIdx.x; k < N; k += blockDim.x) lds[k] = tw[k];
+    return lds;
+}
+
 // ---------------------------------------------------------------------------
 // Forward transform: one workgroup per r-row.
 // ---------------------------------------------------------------------------
-template <typename T, int BC, bool FUSED>
+template <typename T, int BC, bool FUSED, bool TWLDS>
 __global__ void __launch_bounds__(256)
 k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
        const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
-       double *__restrict__ partials, unsigned *ticket,
+       double *__restrict__ partials, int n_pq,
        T *__restrict__ spec, const typename vec2_of<T>::type *__restrict__ tw,
        const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
 {
-    if (FUSED && st->done) return;
+    using V2 = typename vec2_of<T>::type;
     extern __shared__ char smem_raw[];
     cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *b = a + N;
+    V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
 
+    if (FUSED && st->done) return;
     const int i = xcd_swizzle(blockIdx.x, nr);
     const size_t row = (size_t)i * N;
+    // issue the row loads before the p.q reduction so the latencies overlap
+    constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
+    double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int k = threadIdx.x + j * blockDim.x;
+        if (k < N) {
+            if (FUSED) {
+                xv[j] = x[row + k];
+                rv0[j] = r[row + k];
+                pv[j] = p[row + k];
+                qv[j] = q[row + k];
+            } else {
+                rv0[j] = rin[row + k];
+            }
+        }
+    }
+    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
+    double alpha = 0.0;
+    if (FUSED) {
+        const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
+        const int k_it = st->iters;
+        if (!(pq > 0.0) || !(pq < 1e308)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) st->done = ST_BREAK;
+            return;
+        }
+        alpha = st->rho[k_it & 1] / pq;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = k_it;
+    }
+
     double rr = 0.0;
-    const double alpha = FUSED ? st->alpha : 0.0;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int k = threadIdx.x + j * blockDim.x;
+        if (k >= N) continue;
         double rv;
         if (FUSED) {
             const size_t c = row + k;
-            x[c] += alpha * p[c];
-            rv = r[c] - alpha * q[c];
+            x[c] = xv[j] + alpha * pv[j];
+            rv = rv0[j] - alpha * qv[j];
             r[c] = rv;
             rr += rv * rv;
         } else {
-            rv = rin[row + k];
+            rv = rv0[j];
         }
         T v = (T)rv;
         int n;
@@ -53,46 +101,40 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
         a[n] = {v, (T)0};
     }
     __syncthreads();
-    const cx<T> *V = fft_stockham<T>(a, b, N, tw);
+    const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
     const T nrm = (T)sqrt(2.0 / N);
     const T half = (T)0.70710678118654752440;
     for (int j = threadIdx.x; j < N; j += blockDim.x) {
         const int m = (BC == DIR) ? N - 1 - j : j;
         const cx<T> w = ld_tw<T>(pt, m);
-        const T Y = V[m].x * w.x - V[m].y * w.y;
+        const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
         const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
         spec[row + j] = nrm * (edge ? half : (T)1) * Y;
     }
     if (FUSED) {
         const double s = block_sum(rr, red);
-        if (publish_partial(s, partials + SLOT_RR * MAX_PARTIALS, ticket + SLOT_RR * 16, gridDim.x, blockIdx.x)) {
-            const double tot = sum_partials(partials + SLOT_RR * MAX_PARTIALS, gridDim.x, red);
-            if (threadIdx.x == 0) {
-                st->rr = tot;
-                st->iters += 1;
-                if (!(tot == tot) || tot > 1e300) st->done = 2;
-                else if (tot <= st->tol2) st->done = 1;
-                else if (st->iters >= st->maxit) st->done = 3;
-            }
-        }
+        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Inverse transform: one workgroup per r-row, FP64 output.
 // ---------------------------------------------------------------------------
-template <typename T, int BC, int MODE>
+template <typename T, int BC, int MODE, bool TWLDS>
 __global__ void __launch_bounds__(256)
 k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
-       PcgState *st, double *__restrict__ partials, unsigned *ticket,
+       const PcgState *st, double *__restrict__ partials, bool pr,
        const typename vec2_of<T>::type *__restrict__ tw,
        const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
 {
+    using V2 = typename vec2_of<T>::type;
     if (MODE != 0 && st->done) return;
     extern __shared__ char smem_raw[];
     cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *b = a + N;
+    V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
+    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
 
     const int i = xcd_swizzle(blockIdx.x, nr);
     const size_t row = (size_t)i * N;
@@ -112,10 +154,9 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
         a[m] = {w.x * ym - w.y * yn, w.x * yn + w.y * ym};
     }
     __syncthreads();
-    const cx<T> *res = fft_stockham<T>(a, b, N, tw);
+    const cx<T> *res = fft_stockham<T>(a, b, N, twp);
     const T invN = (T)1 / (T)N;
     double rz = 0.0, rzo = 0.0;
-    const bool pr = (MODE == 1) && (st->flags & AXIPCG_FLAG_POLAK_RIBIERE);
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
         T v = res[n].x * invN;
@@ -131,27 +172,10 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
     }
     if (MODE != 0) {
         const double s = block_sum(rz, red);
-        double so = 0.0;
-        if (pr) so = block_sum(rzo, red);
-        if (pr && threadIdx.x == 0)
-            __hip_atomic_store(reinterpret_cast<unsigned long long *>(partials + SLOT_RZOLD * MAX_PARTIALS + blockIdx.x),
-                               (unsigned long long)__double_as_longlong(so), __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-        if (publish_partial(s, partials + SLOT_RZ * MAX_PARTIALS, ticket + SLOT_RZ * 16, gridDim.x, blockIdx.x)) {
-            const double tot = sum_partials(partials + SLOT_RZ * MAX_PARTIALS, gridDim.x, red);
-            double toto = 0.0;
-            if (pr) toto = sum_partials(partials + SLOT_RZOLD * MAX_PARTIALS, gridDim.x, red);
-            if (threadIdx.x == 0) {
-                if (MODE == 2) {
-                    st->rho = tot;
-                    st->beta = 0.0;
-                } else {
-                    const double num = pr ? (tot - toto) : tot;
-                    st->beta = num / st->rho;
-                    st->rho = tot;
-                }
-                if (!(tot == tot)) st->done = 2;
-            }
+        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + blockIdx.x] = s;
+        if (pr) {
+            const double so = block_sum(rzo, red);
+            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + blockIdx.x] = so;
         }
     }
 }
@@ -169,24 +193,87 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
 // the divide-and-conquer idea of §3 (split a tridiagonal system into
 // independent subsystems by first computing values at the partition
 // boundaries) mapped onto the lanes of one wavefront.
+//
+// In PCG mode the kernel first runs the stop test on ||r||^2 (partials of the
+// preceding kernel), recorded by workgroup 0; every workgroup reaches the
+// same decision.
 // ---------------------------------------------------------------------------
-template <typename T, int LMAX>
-__global__ void __launch_bounds__(256)
-k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ db,
-          const T *__restrict__ rw, const T *__restrict__ lam, const PcgState *gate,
-          int nr, int nz, int M, int S, int pitch, int Lp)
+// Gate of the r-solve launch in PCG mode: returns the stop status (ST_RUN to
+// go on).  Workgroup 0 records it.
+__device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ partials, const TriGate &g, double *red)
 {
-    if (gate && gate->done) return;
+    if (g.mode == 1) {
+        const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
+        const int k_it = st->cur;
+        int status = ST_RUN;
+        if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
+        else if (rr <= st->tol2) status = ST_CONV;
+        else if (k_it + 1 >= st->maxit) status = ST_MAXIT;
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->rr = rr;
+            st->iters = k_it + 1;
+            st->done = status;
+        }
+        return status;
+    }
+    const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
+    const double bb = block_total(partials + SLOT_MISC * MAX_PARTIALS, g.n_rr, red);
+    const double tol2 = g.rtol2 * bb;
+    int status = ST_RUN;
+    if (bb == 0.0) status = ST_BZERO;
+    else if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
+    else if (rr <= tol2) status = ST_CONV;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rr = rr;
+        st->bb = bb;
+        st->tol2 = tol2;
+        st->iters = 0;
+        st->cur = 0;
+        st->maxit = g.maxit;
+        st->flags = g.flags;
+        st->done = status;
+    }
+    return status;
+}
+
+// UNI: every active lane owns exactly LMAX rows (nr = S * LMAX), so the
+// per-row loops carry no guards.
+template <typename T, int LMAX, bool UNI>
+__global__ void __launch_bounds__(256)
+k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
+          const T *__restrict__ rw_g, const T *__restrict__ lam, PcgState *st,
+          const double *__restrict__ partials, TriGate g, int nr, int nz, int M, int S, int pitch, int Lp)
+{
+    __shared__ double red[8];
+    if (g.mode == 1 && st->done) return;
     extern __shared__ char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
+    T *cb = tile + M * pitch;          // r-line coefficients staged in LDS
+    T *db = cb + nr;
+    T *rw = db + nr;
     const int ngroups = nz / M;
     const int l0 = xcd_swizzle(blockIdx.x, ngroups) * M;
     auto prow = [&](int row) { return row + row / Lp; };
 
-    for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
-        const int row = e / M, m = e - row * M;
-        tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
+    if (M * sizeof(T) == 16) {
+        // one 16-byte load per row
+        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
+            const T *tv = reinterpret_cast<const T *>(&v);
+            for (int m = 0; m < M; ++m) tile[m * pitch + prow(row)] = tv[m];
+        }
+    } else {
+        for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
+            const int row = e / M, m = e - row * M;
+            tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
+        }
     }
+    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
+        cb[i] = cb_g[i];
+        db[i] = db_g[i];
+        rw[i] = rw_g[i];
+    }
+    if (g.mode != 0 && tridiag_gate(st, partials, g, red) != ST_RUN) return;
     __syncthreads();
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -194,22 +281,33 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ 
         T *col = tile + w * pitch;
         const T lm = lam[l0 + w];
         const bool active = lane < S;
-        const int lo = active ? (int)(((long)lane * nr) / S) : 0;
-        const int hi = active ? (int)(((long)(lane + 1) * nr) / S) : 0;
+        const int lo = active ? (UNI ? lane * LMAX : (int)(((long)lane * nr) / S)) : 0;
+        const int hi = active ? (UNI ? lo + LMAX : (int)(((long)(lane + 1) * nr) / S)) : 0;
         const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
+        auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
 
+        // prefetch the lane's data, diagonal and couplings from LDS
+        T fv[LMAX], dv[LMAX], cv[LMAX];
+#pragma unroll
+        for (int t = 0; t < LMAX; ++t) {
+            if (in_seg(t)) {
+                const int i = lo + t;
+                fv[t] = col[prow(i)];
+                dv[t] = db[i] + rw[i] * lm;
+                cv[t] = cb[i];
+            }
+        }
+        const T cbm = (active && lo > 0) ? cb[lo - 1] : (T)0;
         T cp[LMAX], gp[LMAX], vp[LMAX];
         T cprev = 0, gprev = 0, vprev = 0, inv = 1;
 #pragma unroll
         for (int t = 0; t < LMAX; ++t) {
-            if (t < n) {
-                const int i = lo + t;
-                const T d = db[i] + rw[i] * lm;
-                const T sub = (t > 0) ? -cb[i - 1] : (T)0;
-                inv = (T)1 / (d - sub * cprev);
-                cprev = -cb[i] * inv;
-                gprev = (col[prow(i)] - sub * gprev) * inv;
-                const T vr = (t == 0 && i > 0) ? cb[i - 1] : (T)0;
+            if (in_seg(t)) {
+                const T sub = (t > 0) ? -cv[t - 1] : (T)0;
+                inv = fast_rcp<T>(dv[t] - sub * cprev);
+                cprev = -cv[t] * inv;
+                gprev = (fv[t] - sub * gprev) * inv;
+                const T vr = (t == 0) ? cbm : (T)0;
                 vprev = (vr - sub * vprev) * inv;
                 cp[t] = cprev;
                 gp[t] = gprev;
@@ -221,18 +319,18 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ 
         const T wl = cbR1 * inv;                     // w' of the last interior row
         T gl = active ? gprev : (T)0, vl = active ? vprev : (T)0;
         // back-substitute to obtain the first interior values of g, v, w
-        T g = gl, v = vl, ww = wl;
+        T gq = gl, v = vl, ww = wl;
 #pragma unroll
         for (int t = LMAX - 2; t >= 0; --t) {
-            if (t < n - 1) {
-                g = gp[t] - cp[t] * g;
+            if (UNI ? (t < LMAX - 2 + 0 && active) : (t < n - 1)) {
+                gq = gp[t] - cp[t] * gq;
                 v = vp[t] - cp[t] * v;
                 ww = -cp[t] * ww;
             }
         }
-        if (!active) { g = 0; v = 0; ww = 0; }
+        if (!active) { gq = 0; v = 0; ww = 0; }
         // neighbour (lane + 1) first values
-        const T gfn = __shfl_down(g, 1, 64);
+        const T gfn = __shfl_down(gq, 1, 64);
         const T vfn = __shfl_down(v, 1, 64);
         const T wfn = __shfl_down(ww, 1, 64);
         const bool has_right = active && (lane + 1 < S);
@@ -251,8 +349,8 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ 
             const T ap = __shfl_down(ra, k, 64), bp = __shfl_down(rb, k, 64);
             const T cq = __shfl_down(rc, k, 64), ep = __shfl_down(re, k, 64);
             const bool hm = lane >= k, hp = lane + k < S;
-            const T al = hm ? -ra / bm : (T)0;
-            const T ga = hp ? -rc / bp : (T)0;
+            const T al = hm ? -ra * fast_rcp<T>(bm) : (T)0;
+            const T ga = hp ? -rc * fast_rcp<T>(bp) : (T)0;
             const T na = hm ? al * am : (T)0;
             const T nc = hp ? ga * cq : (T)0;
             const T nb = rb + (hm ? al * cm : (T)0) + (hp ? ga * ap : (T)0);
@@ -265,11 +363,11 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ 
         // interior values: forward-eliminated rhs y' = g' + v' x_{s-1} (+ w' x_s
         // on the last interior row), then the backward sweep
         if (active) {
-            T y = gp[0];  // placeholder, overwritten below
+            T y = 0;
 #pragma unroll
             for (int t = LMAX - 1; t >= 0; --t) {
-                if (t < n) {
-                    T yp = gp[t] + vp[t] * xm;
+                if (in_seg(t)) {
+                    const T yp = gp[t] + vp[t] * xm;
                     if (t == n - 1) y = yp + wl * xs;
                     else y = yp - cp[t] * y;
                     col[prow(lo + t)] = y;
@@ -279,9 +377,18 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb, const T *__restrict__ 
         }
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
-        const int row = e / M, m = e - row * M;
-        spec[(size_t)row * nz + l0 + m] = tile[m * pitch + prow(row)];
+    if (M * sizeof(T) == 16) {
+        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
+            uint4 v;
+            T *tv = reinterpret_cast<T *>(&v);
+            for (int m = 0; m < M; ++m) tv[m] = tile[m * pitch + prow(row)];
+            *reinterpret_cast<uint4 *>(spec + (size_t)row * nz + l0) = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
+            const int row = e / M, m = e - row * M;
+            spec[(size_t)row * nz + l0 + m] = tile[m * pitch + prow(row)];
+        }
     }
 }
 
@@ -300,45 +407,65 @@ template <> Tables<double> tables<double>(const Operator &op)
     return {op.tw64, op.pt64, op.cb64, op.db64, op.rw64, op.lam64};
 }
 
-template <typename T, int BC>
-void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
+// LDS of a transform workgroup: two data buffers, plus the twiddle table when
+// the total stays within 64 KiB.
+template <typename T>
+bool twiddles_in_lds(int N) { return 3 * (size_t)N * sizeof(cx<T>) <= 65536; }
+template <typename T>
+size_t transform_lds(int N) { return (twiddles_in_lds<T>(N) ? 3 : 2) * (size_t)N * sizeof(cx<T>); }
+
+template <typename T, int BC, bool TWL>
+void zfwd_tt(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
     const int N = op.nz;
     const auto tb = tables<T>(op);
-    const size_t shm = 2 * (size_t)N * sizeof(cx<T>);
+    const size_t shm = transform_lds<T>(N);
     const int thr = fft_threads(N);
     if (a.fused)
-        hipLaunchKernelGGL((k_zfwd<T, BC, true>), dim3(op.nr), dim3(thr), shm, s, nullptr, a.x, a.r, a.p, a.q,
-                           a.state, op.partials, op.tickets, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
+        hipLaunchKernelGGL((k_zfwd<T, BC, true, TWL>), dim3(op.nr), dim3(thr), shm, s, nullptr, a.x, a.r, a.p, a.q,
+                           a.state, op.partials, a.n_pq, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
     else
-        hipLaunchKernelGGL((k_zfwd<T, BC, false>), dim3(op.nr), dim3(thr), shm, s, a.rin, nullptr, nullptr,
-                           nullptr, nullptr, nullptr, op.partials, op.tickets, (T *)op.spec, tb.tw, tb.pt,
-                           op.nr, N);
+        hipLaunchKernelGGL((k_zfwd<T, BC, false, TWL>), dim3(op.nr), dim3(thr), shm, s, a.rin, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, op.partials, 0, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T, int BC>
+void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
+{
+    if (twiddles_in_lds<T>(op.nz)) zfwd_tt<T, BC, true>(op, a, s);
+    else zfwd_tt<T, BC, false>(op, a, s);
+}
+
+template <typename T, int BC, bool TWL>
+void zinv_tt(const Operator &op, const ZinvArgs &a, hipStream_t s)
+{
+    const int N = op.nz;
+    const auto tb = tables<T>(op);
+    const size_t shm = transform_lds<T>(N);
+    const int thr = fft_threads(N);
+    switch (a.mode) {
+    case 0:
+        hipLaunchKernelGGL((k_zinv<T, BC, 0, TWL>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           nullptr, nullptr, op.partials, false, tb.tw, tb.pt, op.nr, N);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_zinv<T, BC, 1, TWL>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           a.r, a.state, op.partials, a.pr, tb.tw, tb.pt, op.nr, N);
+        break;
+    default:
+        hipLaunchKernelGGL((k_zinv<T, BC, 2, TWL>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           a.r, a.state, op.partials, false, tb.tw, tb.pt, op.nr, N);
+        break;
+    }
     AXI_CHECK_HIP(hipGetLastError());
 }
 
 template <typename T, int BC>
 void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
 {
-    const int N = op.nz;
-    const auto tb = tables<T>(op);
-    const size_t shm = 2 * (size_t)N * sizeof(cx<T>);
-    const int thr = fft_threads(N);
-    switch (a.mode) {
-    case 0:
-        hipLaunchKernelGGL((k_zinv<T, BC, 0>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
-                           nullptr, nullptr, op.partials, op.tickets, tb.tw, tb.pt, op.nr, N);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_zinv<T, BC, 1>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
-                           a.r, a.state, op.partials, op.tickets, tb.tw, tb.pt, op.nr, N);
-        break;
-    default:
-        hipLaunchKernelGGL((k_zinv<T, BC, 2>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
-                           a.r, a.state, op.partials, op.tickets, tb.tw, tb.pt, op.nr, N);
-        break;
-    }
-    AXI_CHECK_HIP(hipGetLastError());
+    if (twiddles_in_lds<T>(op.nz)) zinv_tt<T, BC, true>(op, a, s);
+    else zinv_tt<T, BC, false>(op, a, s);
 }
 
 struct TriGeom {
@@ -354,27 +481,34 @@ TriGeom tri_geom(int nr, int nz)
     g.L = (nr + g.S - 1) / g.S;
     g.Lp = nr / g.S;
     g.pitch = nr + nr / g.Lp + 1;
-    g.M = 4;
-    while (g.M > 1 && ((size_t)g.M * g.pitch * sizeof(T) > 65536 || nz % g.M != 0)) g.M >>= 1;
-    g.shm = (size_t)g.M * g.pitch * sizeof(T);
+    g.M = 16 / (int)sizeof(T);   // one 16-byte vector of modes per row
+    auto lds = [&](int M) { return ((size_t)M * g.pitch + 3 * (size_t)nr) * sizeof(T); };
+    while (g.M > 1 && (lds(g.M) > 65536 || nz % g.M != 0)) g.M >>= 1;
+    g.shm = lds(g.M);
     return g;
 }
 
 template <typename T>
-void tridiag_t(const Operator &op, const PcgState *gate, hipStream_t s)
+void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
 {
     const TriGeom g = tri_geom<T>(op.nr, op.nz);
     const auto tb = tables<T>(op);
     const dim3 grid(op.nz / g.M), block(64 * g.M);
     T *spec = (T *)op.spec;
-#define AXI_TRI(LM)                                                                                    \
-    hipLaunchKernelGGL((k_tridiag<T, LM>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam, gate, \
-                       op.nr, op.nz, g.M, g.S, g.pitch, g.Lp)
-    if (g.L <= 4) AXI_TRI(4);
-    else if (g.L <= 8) AXI_TRI(8);
-    else if (g.L <= 16) AXI_TRI(16);
-    else if (g.L <= 32) AXI_TRI(32);
-    else if (g.L <= 64) AXI_TRI(64);
+#define AXI_TRI(LM, U)                                                                                   \
+    hipLaunchKernelGGL((k_tridiag<T, LM, U>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam,  \
+                       gate.state, op.partials, gate, op.nr, op.nz, g.M, g.S, g.pitch, g.Lp)
+    const bool uni = (op.nr % g.S) == 0;
+    if (uni && g.L == 2) AXI_TRI(2, true);
+    else if (uni && g.L == 4) AXI_TRI(4, true);
+    else if (uni && g.L == 8) AXI_TRI(8, true);
+    else if (uni && g.L == 16) AXI_TRI(16, true);
+    else if (uni && g.L == 32) AXI_TRI(32, true);
+    else if (g.L <= 4) AXI_TRI(4, false);
+    else if (g.L <= 8) AXI_TRI(8, false);
+    else if (g.L <= 16) AXI_TRI(16, false);
+    else if (g.L <= 32) AXI_TRI(32, false);
+    else if (g.L <= 64) AXI_TRI(64, false);
     else throw Error{AXIPCG_EINVAL, "nr too large for the r-solver"};
 #undef AXI_TRI
     AXI_CHECK_HIP(hipGetLastError());
@@ -404,10 +538,10 @@ void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
     }
 }
 
-void launch_tridiag(const Operator &op, int prec, const PcgState *gate, hipStream_t s)
+void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t s)
 {
-    if (prec == AXIPCG_PREC_FP32) tridiag_t<float>(op, gate, s);
-    else tridiag_t<double>(op, gate, s);
+    if (prec == AXIPCG_PREC_FP32) tridiag_t<float>(op, g, s);
+    else tridiag_t<double>(op, g, s);
 }
 
 void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s)
@@ -415,7 +549,7 @@ void precond_apply_impl(const Operator &op, const double *r, double *z, int prec
     ZfwdArgs fa;
     fa.rin = r;
     launch_zfwd(op, prec, fa, s);
-    launch_tridiag(op, prec, nullptr, s);
+    launch_tridiag(op, prec, TriGate{}, s);
     ZinvArgs ia;
     ia.zout = z;
     launch_zinv(op, prec, ia, s);

@@ -131,11 +131,10 @@ __global__ void k_rhs(const double *__restrict__ f, double *__restrict__ b, cons
         b[e] = rw[e / nz] * f[e];
 }
 
-// Partial sums of ||b - A x||^2 and ||b||^2; the last block writes both.
+// Partial sums of ||b - A x||^2 and ||b||^2, one pair per workgroup.
 __global__ void __launch_bounds__(256)
 k_resid(const double *__restrict__ b, const double *__restrict__ x, const double *__restrict__ D,
-        const double *__restrict__ CR, const double *__restrict__ CZ, int nr, int nz,
-        double *partials, unsigned *tickets, double *out)
+        const double *__restrict__ CR, const double *__restrict__ CZ, int nr, int nz, double *partials)
 {
     __shared__ double red[8];
     const size_t n = (size_t)nr * nz;
@@ -152,17 +151,22 @@ k_resid(const double *__restrict__ b, const double *__restrict__ x, const double
         s_b += b[e] * b[e];
     }
     const double tb = block_sum(s_b, red);
-    if (threadIdx.x == 0)
-        __hip_atomic_store(reinterpret_cast<unsigned long long *>(partials + SLOT_MISC * MAX_PARTIALS + blockIdx.x),
-                           (unsigned long long)__double_as_longlong(tb), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const double tr = block_sum(s_r, red);
-    if (publish_partial(tr, partials + SLOT_PQ * MAX_PARTIALS, tickets + SLOT_PQ * 16, gridDim.x, blockIdx.x)) {
-        const double rt = sum_partials(partials + SLOT_PQ * MAX_PARTIALS, gridDim.x, red);
-        const double bt = sum_partials(partials + SLOT_MISC * MAX_PARTIALS, gridDim.x, red);
-        if (threadIdx.x == 0) {
-            out[0] = rt;
-            out[1] = bt;
-        }
+    if (threadIdx.x == 0) {
+        partials[SLOT_PQ * MAX_PARTIALS + blockIdx.x] = tr;
+        partials[SLOT_MISC * MAX_PARTIALS + blockIdx.x] = tb;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_resid_finish(const double *__restrict__ partials, int n, double *out)
+{
+    __shared__ double red[8];
+    const double rt = block_total(partials + SLOT_PQ * MAX_PARTIALS, n, red);
+    const double bt = block_total(partials + SLOT_MISC * MAX_PARTIALS, n, red);
+    if (threadIdx.x == 0) {
+        out[0] = rt;
+        out[1] = bt;
     }
 }
 
@@ -180,7 +184,7 @@ void free_op(Operator *op)
     if (!op) return;
     void *ptrs[] = {op->D, op->CR, op->CZ, op->W, op->cb64, op->db64, op->rw64, op->lam64, op->cb32,
                     op->db32, op->rw32, op->lam32, op->tw64, op->pt64, op->tw32, op->pt32, op->r,
-                    op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->tickets, op->state, op->dscal};
+                    op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->state, op->dscal};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : op->prof_events) (void)hipEventDestroy(e);
@@ -237,12 +241,13 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         dmalloc(&op->r, n); dmalloc(&op->z, n); dmalloc(&op->p0, n); dmalloc(&op->p1, n); dmalloc(&op->q, n);
         dmalloc((double **)&op->spec, n);
         dmalloc(&op->partials, (size_t)NUM_SLOTS * MAX_PARTIALS);
-        dmalloc(&op->tickets, (size_t)NUM_SLOTS * 16);
         dmalloc(&op->state, 1);
         dmalloc(&op->dscal, 16);
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->state_host, sizeof(PcgState), hipHostMallocDefault));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->scratch_host, 4 * sizeof(double), hipHostMallocDefault));
-        AXI_CHECK_HIP(hipMemsetAsync(op->tickets, 0, sizeof(unsigned) * NUM_SLOTS * 16, s));
+        AXI_CHECK_HIP(hipMemsetAsync(op->partials, 0, sizeof(double) * NUM_SLOTS * MAX_PARTIALS, s));
+        AXI_CHECK_HIP(hipMemsetAsync(op->p0, 0, sizeof(double) * n, s));
+        AXI_CHECK_HIP(hipMemsetAsync(op->p1, 0, sizeof(double) * n, s));
         AXI_CHECK_HIP(hipMemsetAsync(op->state, 0, sizeof(PcgState), s));
 
         // temporaries: kappa at faces and q on the device
@@ -307,8 +312,10 @@ void apply_impl(const Operator &op, const double *x, double *y, hipStream_t s)
 void resid_impl(const Operator &op, const double *b, const double *x, double *out_dev, hipStream_t s)
 {
     const size_t n = (size_t)op.nr * op.nz;
-    hipLaunchKernelGGL(k_resid, dim3(pointwise_blocks(n)), dim3(256), 0, s, b, x, op.D, op.CR, op.CZ, op.nr, op.nz,
-                       op.partials, op.tickets, out_dev);
+    const unsigned nb = pointwise_blocks(n);
+    hipLaunchKernelGGL(k_resid, dim3(nb), dim3(256), 0, s, b, x, op.D, op.CR, op.CZ, op.nr, op.nz, op.partials);
+    AXI_CHECK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_resid_finish, dim3(1), dim3(256), 0, s, op.partials, (int)nb, out_dev);
     AXI_CHECK_HIP(hipGetLastError());
 }
 
