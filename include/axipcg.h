@@ -137,6 +137,18 @@ int axipcg_residual_norm(axipcg_op_t op, const double *b, const double *x,
 int axipcg_pcg_solve(axipcg_op_t op, const double *b, double *x, double rtol, int maxit,
                      int prec, unsigned flags, axipcg_stats *st, void *stream);
 
+/* ---- batched PCG over independent problems (§2.2 eq. (8) for each) ---------
+ * Solve A_p x_p = b_p for p < n at once; ops[p] are distinct handles (each
+ * problem uses its handle's workspace), b[p] and x[p] device pointers of that
+ * handle's size (host arrays of n pointers).  Every PCG phase is one launch
+ * over the whole batch, so the launch count per iteration does not grow with
+ * n; each problem stops on its own test.  st (host, may be NULL) receives n
+ * statistics.  Returns the worst status (AXIPCG_EBREAKDOWN, then
+ * AXIPCG_ENOTCONV, else AXIPCG_OK).  Members need nr <= 1024 and nz >= 4; all
+ * handles must live on the current device.  Synchronises the stream. */
+int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *const *b, double *const *x,
+                       double rtol, int maxit, int prec, unsigned flags, axipcg_stats *st, void *stream);
+
 /* ---- Laguerre series (§4.1 eqs. (34)-(35), alpha = 0) ----------------------
  * g_m = int_0^{t_max} f(t) l_m(t) dt, l_m(t) = sqrt(eta) e^{-eta t/2} L_m(eta t),
  * for m < n, from nt >= 3 uniform samples f_host[j] = f(j t_max/(nt-1)) (host).

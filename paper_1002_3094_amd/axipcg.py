@@ -53,6 +53,8 @@ SIGNATURES = {
     "axipcg_precond_apply": ([_vp, _vp, _vp, _i, _vp], _i),
     "axipcg_residual_norm": ([_vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
+    "axipcg_batch_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _d, _i, _i, _u,
+                            ctypes.POINTER(Stats), _vp], _i),
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_profile_select": ([_vp, _i], _i),
@@ -199,6 +201,20 @@ def pcg_solve(op: Op, b, x, rtol=1e-10, maxit=1000, prec=PREC_FP32, flags=0, str
     d = st.as_dict()
     d["code"] = code
     return d
+
+
+def batch_solve(ops, bs, xs, rtol=1e-10, maxit=1000, prec=PREC_FP32, flags=0, stream=None,
+                allow_notconv=True):
+    n = len(ops)
+    if not (len(bs) == len(xs) == n):
+        raise ValueError("ops, bs and xs must have the same length")
+    h = (_vp * n)(*[o.handle.value for o in ops])
+    bp = (_vp * n)(*[_dev(t, "b").value for t in bs])
+    xp = (_vp * n)(*[_dev(t, "x").value for t in xs])
+    st = (Stats * n)()
+    code = lib().axipcg_batch_solve(n, h, bp, xp, rtol, maxit, prec, flags, st, _stream(stream))
+    _check(code, "batch_solve", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    return code, [s.as_dict() for s in st]
 
 
 def laguerre_coeffs(n: int, eta: float, f_samples, t_max: float, stream=None) -> np.ndarray:

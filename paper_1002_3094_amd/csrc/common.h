@@ -111,6 +111,40 @@ struct Operator {
     long long prof_count = 0;
 };
 
+// One problem of a batched solve, as the batched kernels see it.  Workgroup g
+// of a row-indexed launch belongs to the problem whose [row_start, row_start +
+// nr) range holds g; of the r-solve launch, [tri_start, tri_start + nz / M).
+struct ProbDesc {
+    int nr, nz, bc_z;
+    int row_start, tri_start;
+    int tri_S, tri_L, tri_Lp, tri_pitch;
+    const double *b;
+    double *x;
+    const double *D, *CR, *CZ;
+    double *r, *z, *p0, *p1, *q;
+    void *spec;
+    double *partials;
+    PcgState *state;
+    const float *cb32, *db32, *rw32, *lam32;
+    const double *cb64, *db64, *rw64, *lam64;
+    const float2 *tw32, *pt32;
+    const double2 *tw64, *pt64;
+};
+
+// Index of the problem owning global workgroup g (binary search on the
+// starts; `tri` selects the r-solve ranges).
+__device__ inline int find_problem(const ProbDesc *d, int n, int g, bool tri)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int st = tri ? d[mid].tri_start : d[mid].row_start;
+        if (st <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Run an ABI body: translate exceptions into status codes and keep the
 // message for axipcg_last_error().
 template <typename F>

@@ -20,6 +20,9 @@ struct ZfwdArgs {
 };
 void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s);
 
+// Workgroups (= partial sums) of the transform launches for this operator.
+int transform_blocks(const Operator &op, int prec);
+
 // One r-tridiagonal solve per z-mode, in place on op.spec (§4.2 eq. (39)).
 //  mode 0: plain;
 //  mode 1: PCG step: ||r||^2 from the forward kernel's partials -> stop test
@@ -50,6 +53,18 @@ void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 
 // z = B^{-1} r with three launches (forward, r-solves, inverse).
 void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s);
+
+// ---- batched solve: one launch per PCG phase covers every problem ----------
+void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm);
+void launch_b_init(const ProbDesc *d, int n, int rows, hipStream_t s);
+void launch_b_zero(const ProbDesc *d, int n, int rows, hipStream_t s);
+void launch_b_spmv(const ProbDesc *d, int n, int rows, bool pr, int parity, hipStream_t s);
+void launch_b_zfwd(const ProbDesc *d, int n, int rows, int prec, bool fused, int parity, int nz_max, hipStream_t s);
+void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriGate &g, int M, size_t shm,
+                      hipStream_t s);
+void launch_b_zinv(const ProbDesc *d, int n, int rows, int prec, int mode, bool pr, int nz_max, hipStream_t s);
+void launch_b_gather(const ProbDesc *d, int n, PcgState *out, hipStream_t s);
+void resid_impl(const Operator &op, const double *b, const double *x, double *out_dev, hipStream_t s);
 
 // Flattened grid geometry for pointwise kernels.
 inline unsigned pointwise_blocks(size_t n, int threads = 256)

@@ -46,18 +46,18 @@ __device__ inline double stencil(const double *__restrict__ D, const double *__r
 constexpr int SPMV_PPT = 8;   // points per thread per row (nz <= 2048, 256 threads)
 
 template <bool PR>
-__global__ void __launch_bounds__(256)
-k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double *__restrict__ pnew,
-           double *__restrict__ q, const double *__restrict__ D, const double *__restrict__ CR,
-           const double *__restrict__ CZ, int nr, int nz, PcgState *st, double *__restrict__ partials, int n_rz)
+__device__ __forceinline__ void spmv_body(const double *__restrict__ z, const double *__restrict__ pold,
+                                          double *__restrict__ pnew, double *__restrict__ q,
+                                          const double *__restrict__ D, const double *__restrict__ CR,
+                                          const double *__restrict__ CZ, int nr, int nz, PcgState *st,
+                                          double *__restrict__ partials, int n_rz, int vb, int vnb)
 {
-    if (st->done) return;
     __shared__ double red[8];
-    const int k_it = st->iters;
     double acc = 0.0;
     double beta = 0.0;
     bool have_beta = false;
-    for (int b = blockIdx.x; b < nr; b += gridDim.x) {
+    int k_it = 0;
+    for (int b = vb; b < nr; b += vnb) {
         const int i = xcd_swizzle(b, nr);
         double az[SPMV_PPT], ap[SPMV_PPT], zc[SPMV_PPT], pc[SPMV_PPT];
 #pragma unroll
@@ -72,13 +72,15 @@ k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double
             }
         }
         if (!have_beta) {   // scalars once per workgroup, after the first row's loads
+            if (st->done) return;
+            k_it = st->iters;
             const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
             if (k_it > 0) {
                 double num = rho;
                 if (PR) num -= block_total(partials + SLOT_RZOLD * MAX_PARTIALS, n_rz, red);
                 beta = num / st->rho[(k_it - 1) & 1];
             }
-            if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k_it & 1] = rho;
+            if (vb == 0 && threadIdx.x == 0) st->rho[k_it & 1] = rho;
             have_beta = true;
         }
 #pragma unroll
@@ -95,18 +97,27 @@ k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double
         }
     }
     const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[SLOT_PQ * MAX_PARTIALS + blockIdx.x] = s;
+    if (threadIdx.x == 0) partials[SLOT_PQ * MAX_PARTIALS + vb] = s;
+}
+
+template <bool PR>
+__global__ void __launch_bounds__(256)
+k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double *__restrict__ pnew,
+           double *__restrict__ q, const double *__restrict__ D, const double *__restrict__ CR,
+           const double *__restrict__ CZ, int nr, int nz, PcgState *st, double *__restrict__ partials, int n_rz)
+{
+    spmv_body<PR>(z, pold, pnew, q, D, CR, CZ, nr, nz, st, partials, n_rz, blockIdx.x, gridDim.x);
 }
 
 // r = b - A x; ||r||^2 and ||b||^2 partials.
-__global__ void __launch_bounds__(256)
-k_pcg_init(const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ r,
-           const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
-           int nz, double *__restrict__ partials)
+__device__ __forceinline__ void init_body(const double *__restrict__ b, const double *__restrict__ x,
+                                          double *__restrict__ r, const double *__restrict__ D,
+                                          const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
+                                          int nz, double *__restrict__ partials, int vb, int vnb)
 {
     __shared__ double red[8];
     double s_r = 0.0, s_b = 0.0;
-    for (int blk = blockIdx.x; blk < nr; blk += gridDim.x) {
+    for (int blk = vb; blk < nr; blk += vnb) {
         const int i = xcd_swizzle(blk, nr);
         for (int k = threadIdx.x; k < nz; k += blockDim.x) {
             const size_t e = (size_t)i * nz + k;
@@ -121,9 +132,51 @@ k_pcg_init(const double *__restrict__ b, const double *__restrict__ x, double *_
     const double tb = block_sum(s_b, red);
     const double tr = block_sum(s_r, red);
     if (threadIdx.x == 0) {
-        partials[SLOT_MISC * MAX_PARTIALS + blockIdx.x] = tb;
-        partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = tr;
+        partials[SLOT_MISC * MAX_PARTIALS + vb] = tb;
+        partials[SLOT_RR * MAX_PARTIALS + vb] = tr;
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_pcg_init(const double *__restrict__ b, const double *__restrict__ x, double *__restrict__ r,
+           const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
+           int nz, double *__restrict__ partials)
+{
+    init_body(b, x, r, D, CR, CZ, nr, nz, partials, blockIdx.x, gridDim.x);
+}
+
+// ---- batched launches: one launch covers every problem of a batch --------
+template <bool PR>
+__global__ void __launch_bounds__(256) k_b_spmv(const ProbDesc *__restrict__ d, int n, int parity)
+{
+    const int p = find_problem(d, n, blockIdx.x, false);
+    const ProbDesc &P = d[p];
+    const double *pold = parity ? P.p1 : P.p0;
+    double *pnew = parity ? P.p0 : P.p1;
+    spmv_body<PR>(P.z, pold, pnew, P.q, P.D, P.CR, P.CZ, P.nr, P.nz, P.state, P.partials, P.nr,
+                  blockIdx.x - P.row_start, P.nr);
+}
+
+__global__ void __launch_bounds__(256) k_b_init(const ProbDesc *__restrict__ d, int n)
+{
+    const int p = find_problem(d, n, blockIdx.x, false);
+    const ProbDesc &P = d[p];
+    init_body(P.b, P.x, P.r, P.D, P.CR, P.CZ, P.nr, P.nz, P.partials, blockIdx.x - P.row_start, P.nr);
+}
+
+__global__ void __launch_bounds__(256) k_b_zero_if_b_zero(const ProbDesc *__restrict__ d, int n)
+{
+    const int p = find_problem(d, n, blockIdx.x, false);
+    const ProbDesc &P = d[p];
+    if (P.state->done != ST_BZERO) return;
+    const int i = blockIdx.x - P.row_start;
+    for (int k = threadIdx.x; k < P.nz; k += blockDim.x) P.x[(size_t)i * P.nz + k] = 0.0;
+}
+
+// Copy every problem's state into one array (one read-back per chunk).
+__global__ void k_b_gather(const ProbDesc *__restrict__ d, int n, PcgState *out)
+{
+    for (int p = threadIdx.x; p < n; p += blockDim.x) out[p] = *d[p].state;
 }
 
 // x = 0 when b = 0.
@@ -140,6 +193,7 @@ struct SolveCtx {
     int prec;
     bool pr;
     hipStream_t s;
+    int n_tr;   // workgroups (partials) of the transform kernels
 };
 
 // Event pair around one launch of the profiled kernel class.
@@ -177,10 +231,10 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
         ProfScope ps(op, c.s, AXIPCG_KERNEL_SPMV, iter);
         if (c.pr)
             hipLaunchKernelGGL(k_pcg_spmv<true>, dim3(gs), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D, op.CR,
-                               op.CZ, op.nr, op.nz, op.state, op.partials, op.nr);
+                               op.CZ, op.nr, op.nz, op.state, op.partials, c.n_tr);
         else
             hipLaunchKernelGGL(k_pcg_spmv<false>, dim3(gs), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D,
-                               op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, op.nr);
+                               op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, c.n_tr);
         AXI_CHECK_HIP(hipGetLastError());
     }
     ZfwdArgs fa;
@@ -200,7 +254,7 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
         TriGate g;
         g.mode = 1;
         g.state = op.state;
-        g.n_rr = op.nr;
+        g.n_rr = c.n_tr;
         launch_tridiag(op, c.prec, g, c.s);
     }
     ZinvArgs ia;
@@ -237,7 +291,7 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
                axipcg_stats *st, hipStream_t s)
 {
     const size_t n = (size_t)op.nr * op.nz;
-    SolveCtx c{&op, x, prec, (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0, s};
+    SolveCtx c{&op, x, prec, (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0, s, transform_blocks(op, prec)};
     op.prof_used = 0;
     // start: r = b - A x; z = B^{-1} r (the r-solve launch runs the start test)
     const unsigned gi = row_blocks(op.nr);
@@ -307,6 +361,31 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
 }
 
 }  // namespace
+
+void launch_b_spmv(const ProbDesc *d, int n, int rows, bool pr, int parity, hipStream_t s)
+{
+    if (pr) hipLaunchKernelGGL(k_b_spmv<true>, dim3(rows), dim3(256), 0, s, d, n, parity);
+    else hipLaunchKernelGGL(k_b_spmv<false>, dim3(rows), dim3(256), 0, s, d, n, parity);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_b_init(const ProbDesc *d, int n, int rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_init, dim3(rows), dim3(256), 0, s, d, n);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_b_zero(const ProbDesc *d, int n, int rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_zero_if_b_zero, dim3(rows), dim3(256), 0, s, d, n);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_b_gather(const ProbDesc *d, int n, PcgState *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_gather, dim3(1), dim3(256), 0, s, d, n, out);
+    AXI_CHECK_HIP(hipGetLastError());
+}
 
 }  // namespace axipcg
 

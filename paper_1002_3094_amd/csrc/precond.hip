@@ -28,12 +28,13 @@ __device__ inline const typename vec2_of<T>::type *stage_twiddles(const typename
 // Forward transform: one workgroup per r-row.
 // ---------------------------------------------------------------------------
 template <typename T, int BC, bool FUSED, bool TWLDS>
-__global__ void __launch_bounds__(256)
-k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
-       const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
-       double *__restrict__ partials, int n_pq,
-       T *__restrict__ spec, const typename vec2_of<T>::type *__restrict__ tw,
-       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+__device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double *__restrict__ x,
+                                          double *__restrict__ r, const double *__restrict__ p,
+                                          const double *__restrict__ q, PcgState *st,
+                                          double *__restrict__ partials, int n_pq, T *__restrict__ spec,
+                                          const typename vec2_of<T>::type *__restrict__ tw,
+                                          const typename vec2_of<T>::type *__restrict__ pt, int nr, int N,
+                                          int vb)
 {
     using V2 = typename vec2_of<T>::type;
     extern __shared__ char smem_raw[];
@@ -43,7 +44,7 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
     __shared__ double red[8];
 
     if (FUSED && st->done) return;
-    const int i = xcd_swizzle(blockIdx.x, nr);
+    const int i = xcd_swizzle(vb, nr);
     const size_t row = (size_t)i * N;
     // issue the row loads before the p.q reduction so the latencies overlap
     constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
@@ -68,11 +69,11 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
         const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
         const int k_it = st->iters;
         if (!(pq > 0.0) || !(pq < 1e308)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) st->done = ST_BREAK;
+            if (vb == 0 && threadIdx.x == 0) st->done = ST_BREAK;
             return;
         }
         alpha = st->rho[k_it & 1] / pq;
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = k_it;
+        if (vb == 0 && threadIdx.x == 0) st->cur = k_it;
     }
 
     double rr = 0.0;
@@ -113,19 +114,30 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
     }
     if (FUSED) {
         const double s = block_sum(rr, red);
-        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
+        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + vb] = s;
     }
+}
+
+template <typename T, int BC, bool FUSED, bool TWLDS>
+__global__ void __launch_bounds__(256)
+k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
+       const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
+       double *__restrict__ partials, int n_pq,
+       T *__restrict__ spec, const typename vec2_of<T>::type *__restrict__ tw,
+       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+{
+    zfwd_body<T, BC, FUSED, TWLDS>(rin, x, r, p, q, st, partials, n_pq, spec, tw, pt, nr, N, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Inverse transform: one workgroup per r-row, FP64 output.
 // ---------------------------------------------------------------------------
 template <typename T, int BC, int MODE, bool TWLDS>
-__global__ void __launch_bounds__(256)
-k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
-       const PcgState *st, double *__restrict__ partials, bool pr,
-       const typename vec2_of<T>::type *__restrict__ tw,
-       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+__device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__restrict__ zout,
+                                          const double *__restrict__ r, const PcgState *st,
+                                          double *__restrict__ partials, bool pr,
+                                          const typename vec2_of<T>::type *__restrict__ tw,
+                                          const typename vec2_of<T>::type *__restrict__ pt, int nr, int N, int vb)
 {
     using V2 = typename vec2_of<T>::type;
     if (MODE != 0 && st->done) return;
@@ -136,7 +148,7 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
     __shared__ double red[8];
     const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
 
-    const int i = xcd_swizzle(blockIdx.x, nr);
+    const int i = xcd_swizzle(vb, nr);
     const size_t row = (size_t)i * N;
     const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
     const T sq2 = (T)1.41421356237309504880;
@@ -172,12 +184,22 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
     }
     if (MODE != 0) {
         const double s = block_sum(rz, red);
-        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + blockIdx.x] = s;
+        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + vb] = s;
         if (pr) {
             const double so = block_sum(rzo, red);
-            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + blockIdx.x] = so;
+            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + vb] = so;
         }
     }
+}
+
+template <typename T, int BC, int MODE, bool TWLDS>
+__global__ void __launch_bounds__(256)
+k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
+       const PcgState *st, double *__restrict__ partials, bool pr,
+       const typename vec2_of<T>::type *__restrict__ tw,
+       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+{
+    zinv_body<T, BC, MODE, TWLDS>(spec, zout, r, st, partials, pr, tw, pt, nr, N, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -200,16 +222,18 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
 // ---------------------------------------------------------------------------
 // Gate of the r-solve launch in PCG mode: returns the stop status (ST_RUN to
 // go on).  Workgroup 0 records it.
-__device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ partials, const TriGate &g, double *red)
+__device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ partials, const TriGate &g, double *red,
+                                   int vb)
 {
     if (g.mode == 1) {
+        if (st->done) return st->done;   // stopped earlier: leave the state alone
         const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
         const int k_it = st->cur;
         int status = ST_RUN;
         if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
         else if (rr <= st->tol2) status = ST_CONV;
         else if (k_it + 1 >= st->maxit) status = ST_MAXIT;
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (vb == 0 && threadIdx.x == 0) {
             st->rr = rr;
             st->iters = k_it + 1;
             st->done = status;
@@ -223,7 +247,7 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
     if (bb == 0.0) status = ST_BZERO;
     else if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
     else if (rr <= tol2) status = ST_CONV;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (vb == 0 && threadIdx.x == 0) {
         st->rr = rr;
         st->bb = bb;
         st->tol2 = tol2;
@@ -239,20 +263,20 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
 // UNI: every active lane owns exactly LMAX rows (nr = S * LMAX), so the
 // per-row loops carry no guards.
 template <typename T, int LMAX, bool UNI>
-__global__ void __launch_bounds__(256)
-k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
-          const T *__restrict__ rw_g, const T *__restrict__ lam, PcgState *st,
-          const double *__restrict__ partials, TriGate g, int nr, int nz, int M, int S, int pitch, int Lp)
+__device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__restrict__ cb_g,
+                                             const T *__restrict__ db_g, const T *__restrict__ rw_g,
+                                             const T *__restrict__ lam, PcgState *st,
+                                             const double *__restrict__ partials, const TriGate &g, int nr,
+                                             int nz, int M, int S, int pitch, int Lp, int vb)
 {
     __shared__ double red[8];
-    if (g.mode == 1 && st->done) return;
     extern __shared__ char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
     T *cb = tile + M * pitch;          // r-line coefficients staged in LDS
     T *db = cb + nr;
     T *rw = db + nr;
     const int ngroups = nz / M;
-    const int l0 = xcd_swizzle(blockIdx.x, ngroups) * M;
+    const int l0 = xcd_swizzle(vb, ngroups) * M;
     auto prow = [&](int row) { return row + row / Lp; };
 
     if (M * sizeof(T) == 16) {
@@ -273,7 +297,7 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict_
         db[i] = db_g[i];
         rw[i] = rw_g[i];
     }
-    if (g.mode != 0 && tridiag_gate(st, partials, g, red) != ST_RUN) return;
+    if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb) != ST_RUN) return;
     __syncthreads();
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -390,6 +414,86 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict_
             spec[(size_t)row * nz + l0 + m] = tile[m * pitch + prow(row)];
         }
     }
+}
+
+template <typename T, int LMAX, bool UNI>
+__global__ void __launch_bounds__(256)
+k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
+          const T *__restrict__ rw_g, const T *__restrict__ lam, PcgState *st,
+          const double *__restrict__ partials, TriGate g, int nr, int nz, int M, int S, int pitch, int Lp)
+{
+    tridiag_body<T, LMAX, UNI>(spec, cb_g, db_g, rw_g, lam, st, partials, g, nr, nz, M, S, pitch, Lp, blockIdx.x);
+}
+
+// ---- batched launches ----------------------------------------------------
+template <typename T> __device__ inline const T *pd_cb(const ProbDesc &P);
+template <> __device__ inline const float *pd_cb<float>(const ProbDesc &P) { return P.cb32; }
+template <> __device__ inline const double *pd_cb<double>(const ProbDesc &P) { return P.cb64; }
+template <typename T> __device__ inline const T *pd_db(const ProbDesc &P);
+template <> __device__ inline const float *pd_db<float>(const ProbDesc &P) { return P.db32; }
+template <> __device__ inline const double *pd_db<double>(const ProbDesc &P) { return P.db64; }
+template <typename T> __device__ inline const T *pd_rw(const ProbDesc &P);
+template <> __device__ inline const float *pd_rw<float>(const ProbDesc &P) { return P.rw32; }
+template <> __device__ inline const double *pd_rw<double>(const ProbDesc &P) { return P.rw64; }
+template <typename T> __device__ inline const T *pd_lam(const ProbDesc &P);
+template <> __device__ inline const float *pd_lam<float>(const ProbDesc &P) { return P.lam32; }
+template <> __device__ inline const double *pd_lam<double>(const ProbDesc &P) { return P.lam64; }
+template <typename T> __device__ inline const typename vec2_of<T>::type *pd_tw(const ProbDesc &P);
+template <> __device__ inline const float2 *pd_tw<float>(const ProbDesc &P) { return P.tw32; }
+template <> __device__ inline const double2 *pd_tw<double>(const ProbDesc &P) { return P.tw64; }
+template <typename T> __device__ inline const typename vec2_of<T>::type *pd_pt(const ProbDesc &P);
+template <> __device__ inline const float2 *pd_pt<float>(const ProbDesc &P) { return P.pt32; }
+template <> __device__ inline const double2 *pd_pt<double>(const ProbDesc &P) { return P.pt64; }
+
+template <typename T, bool FUSED, bool TWLDS>
+__global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, int n, int parity)
+{
+    const int p = find_problem(d, n, blockIdx.x, false);
+    const ProbDesc &P = d[p];
+    const double *pnew = parity ? P.p0 : P.p1;   // written by this iteration's SpMV
+    const int vb = blockIdx.x - P.row_start;
+    if (P.bc_z == DIR)
+        zfwd_body<T, DIR, FUSED, TWLDS>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr, (T *)P.spec,
+                                        pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
+    else
+        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr,
+                                                     (T *)P.spec, pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
+}
+
+template <typename T, int MODE, bool TWLDS>
+__global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, int n, bool pr)
+{
+    const int p = find_problem(d, n, blockIdx.x, false);
+    const ProbDesc &P = d[p];
+    const int vb = blockIdx.x - P.row_start;
+    if (P.bc_z == DIR)
+        zinv_body<T, DIR, MODE, TWLDS>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
+                                       pd_pt<T>(P), P.nr, P.nz, vb);
+    else
+        zinv_body<T, AXIPCG_Z_NEUMANN, MODE, TWLDS>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
+                                                    pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_b_tridiag(const ProbDesc *__restrict__ d, int n, TriGate g, int M)
+{
+    const int p = find_problem(d, n, blockIdx.x, true);
+    const ProbDesc &P = d[p];
+    const int vb = blockIdx.x - P.tri_start;
+    g.state = P.state;
+    g.n_rr = P.nr;
+    const bool uni = (P.nr % P.tri_S) == 0;
+#define AXI_BTRI(LM, U)                                                                                       \
+    tridiag_body<T, LM, U>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,           \
+                           P.partials, g, P.nr, P.nz, M, P.tri_S, P.tri_pitch, P.tri_Lp, vb)
+    if (uni && P.tri_L == 2) AXI_BTRI(2, true);
+    else if (uni && P.tri_L == 4) AXI_BTRI(4, true);
+    else if (uni && P.tri_L == 8) AXI_BTRI(8, true);
+    else if (uni && P.tri_L == 16) AXI_BTRI(16, true);
+    else if (P.tri_L <= 4) AXI_BTRI(4, false);
+    else if (P.tri_L <= 8) AXI_BTRI(8, false);
+    else AXI_BTRI(16, false);
+#undef AXI_BTRI
 }
 
 template <typename T>
@@ -515,6 +619,67 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
 }
 
 }  // namespace
+
+int transform_blocks(const Operator &op, int prec) { return op.nr; }
+
+// ---- batched launchers -------------------------------------------------------
+void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm)
+{
+    *S = nr / 2 < 64 ? nr / 2 : 64;
+    *L = (nr + *S - 1) / *S;
+    *Lp = nr / *S;
+    *pitch = nr + nr / *Lp + 1;
+    const size_t el = (prec == AXIPCG_PREC_FP32) ? sizeof(float) : sizeof(double);
+    *shm = ((size_t)M * *pitch + 3 * (size_t)nr) * el;
+}
+
+template <typename T>
+void b_zfwd_t(const ProbDesc *d, int n, int rows, bool fused, int parity, int nz_max, hipStream_t s)
+{
+    const size_t shm = transform_lds<T>(nz_max);
+    if (twiddles_in_lds<T>(nz_max)) {
+        if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, true>), dim3(rows), dim3(256), shm, s, d, n, parity);
+        else hipLaunchKernelGGL((k_b_zfwd<T, false, true>), dim3(rows), dim3(256), shm, s, d, n, parity);
+    } else {
+        if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, false>), dim3(rows), dim3(256), shm, s, d, n, parity);
+        else hipLaunchKernelGGL((k_b_zfwd<T, false, false>), dim3(rows), dim3(256), shm, s, d, n, parity);
+    }
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T>
+void b_zinv_t(const ProbDesc *d, int n, int rows, int mode, bool pr, int nz_max, hipStream_t s)
+{
+    const size_t shm = transform_lds<T>(nz_max);
+    const bool twl = twiddles_in_lds<T>(nz_max);
+#define AXI_BZI(MD, TW) hipLaunchKernelGGL((k_b_zinv<T, MD, TW>), dim3(rows), dim3(256), shm, s, d, n, pr)
+    if (mode == 1) { if (twl) AXI_BZI(1, true); else AXI_BZI(1, false); }
+    else { if (twl) AXI_BZI(2, true); else AXI_BZI(2, false); }
+#undef AXI_BZI
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_b_zfwd(const ProbDesc *d, int n, int rows, int prec, bool fused, int parity, int nz_max, hipStream_t s)
+{
+    if (prec == AXIPCG_PREC_FP32) b_zfwd_t<float>(d, n, rows, fused, parity, nz_max, s);
+    else b_zfwd_t<double>(d, n, rows, fused, parity, nz_max, s);
+}
+
+void launch_b_zinv(const ProbDesc *d, int n, int rows, int prec, int mode, bool pr, int nz_max, hipStream_t s)
+{
+    if (prec == AXIPCG_PREC_FP32) b_zinv_t<float>(d, n, rows, mode, pr, nz_max, s);
+    else b_zinv_t<double>(d, n, rows, mode, pr, nz_max, s);
+}
+
+void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriGate &g, int M, size_t shm,
+                      hipStream_t s)
+{
+    if (prec == AXIPCG_PREC_FP32)
+        hipLaunchKernelGGL(k_b_tridiag<float>, dim3(blocks), dim3(64 * M), shm, s, d, n, g, M);
+    else
+        hipLaunchKernelGGL(k_b_tridiag<double>, dim3(blocks), dim3(64 * M), shm, s, d, n, g, M);
+    AXI_CHECK_HIP(hipGetLastError());
+}
 
 void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
 {
