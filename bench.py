@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--roofline-kernel", choices=list(KERNEL_IDS), default="spmv")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem uneven batch")
     return ap.parse_args()
 
 
@@ -102,6 +103,48 @@ def cpu_baseline(inp, prec_rtol, budget_s, n_max=16):
     return {"value": done / el, "unit": "harmonics/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"first {done} harmonics of the same {inp['nr']}x{inp['nz']} chain, FP64 oracle "
                       f"(4N-embedding FFT transforms, Thomas r-solves, PCG to 1e-10), {el:.1f} s"}
+
+
+def batch_measure(ax, torch, prec, reps=3):
+    """64 independent uneven problems (N_r, N_z ~ U{256,512,1024}, seeds
+    1000+p): one batched solve versus the same problems solved one by one."""
+    import synth
+    probs = [synth.problem_batch_member(p) for p in range(64)]
+    ops, bs, xs = [], [], []
+    for pr in probs:
+        op = ax.op_create(pr.kappa, pr.q)
+        b = torch.empty((pr.nr, pr.nz), dtype=torch.float64, device="cuda")
+        ax.rhs_from_f(op, torch.from_numpy(pr.f).cuda(), b)
+        ops.append(op)
+        bs.append(b)
+        xs.append(torch.zeros_like(b))
+    ax.batch_solve(ops, bs, xs, 1e-10, 1000, prec)      # warm-up
+    times, iters = [], []
+    for _ in range(reps):
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        code, st = ax.batch_solve(ops, bs, xs, 1e-10, 1000, prec)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters = [s["iters"] for s in st]
+        assert code == ax.OK
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for op, b, x in zip(ops, bs, xs):
+        ax.pcg_solve(op, b, x, 1e-10, 1000, prec)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    pts = sum(p.nr * p.nz for p in probs)
+    for op in ops:
+        op.close()
+    t_b = min(times)
+    return {"workload": "batch_64_uneven_256-1024", "points": pts, "solves_per_s": round(64 / t_b, 1),
+            "ms_per_batch": round(t_b * 1e3, 3), "sequential_solves_per_s": round(64 / t_seq, 1),
+            "iters_min_max": [min(iters), max(iters)]}
 
 
 def main():
@@ -225,6 +268,8 @@ def main():
         "us_per_iteration": round(elapsed_s * 1e6 / max(1, sum(timed_iters)), 2),
         "setup_s": round(t_setup, 3),
     }
+    if not a.no_batch:
+        out["batch"] = batch_measure(ax, torch, prec)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(inp, rtol, a.cpu_seconds)
     op.close()
