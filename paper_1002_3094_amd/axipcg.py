@@ -57,6 +57,15 @@ SIGNATURES = {
                             ctypes.POINTER(Stats), _vp], _i),
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "axipcg_nn_num_params": ([], _i),
+    "axipcg_nn_create": ([_i, _i, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_vp)], _i),
+    "axipcg_nn_destroy": ([_vp], None),
+    "axipcg_nn_get_params": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], _i),
+    "axipcg_nn_set_params": ([_vp, ctypes.POINTER(ctypes.c_float)], _i),
+    "axipcg_nn_forward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "axipcg_nn_backward": ([_vp, _vp, _vp, _dp, _vp], _i),
+    "axipcg_nn_adam": ([_vp, _d, _d, _d, _d, _vp], _i),
+    "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_profile_select": ([_vp, _i], _i),
     "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
@@ -230,6 +239,91 @@ def laguerre_rhs(op: Op, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=N
     _check(lib().axipcg_laguerre_rhs(op.handle, g_m, src_i, src_k, _opt_dev(coef, "coef"),
                                      _opt_dev(u_prev, "u_prev"), _dev(S1, "S1"), _dev(S2, "S2"),
                                      _dev(b, "b"), _stream(stream)), "laguerre_rhs")
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def nn_num_params() -> int:
+    return int(lib().axipcg_nn_num_params())
+
+
+class Net:
+    """Owning wrapper of an axipcg_nn_t handle (learned initial guess)."""
+
+    def __init__(self, handle: int, nr: int, nz: int):
+        self.handle = _vp(handle)
+        self.nr, self.nz = nr, nz
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().axipcg_nn_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def nn_create(nr: int, nz: int, params) -> Net:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != nn_num_params():
+        raise ValueError(f"expected {nn_num_params()} parameters, got {p.size}")
+    out = _vp()
+    _check(lib().axipcg_nn_create(nr, nz, _fp(p), ctypes.byref(out)), "nn_create")
+    return Net(out.value, nr, nz)
+
+
+def nn_destroy(net: Net):
+    net.close()
+
+
+def nn_get_params(net: Net):
+    """Return (params, grads) as host float32 arrays."""
+    p = np.zeros(nn_num_params(), dtype=np.float32)
+    g = np.zeros(nn_num_params(), dtype=np.float32)
+    _check(lib().axipcg_nn_get_params(net.handle, _fp(p), _fp(g)), "nn_get_params")
+    return p, g
+
+
+def nn_set_params(net: Net, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    if p.size != nn_num_params():
+        raise ValueError(f"expected {nn_num_params()} parameters, got {p.size}")
+    _check(lib().axipcg_nn_set_params(net.handle, _fp(p)), "nn_set_params")
+
+
+def nn_forward(net: Net, u1, u2, b, kappa, guess, stream=None):
+    _check(lib().axipcg_nn_forward(net.handle, _dev(u1, "u1"), _dev(u2, "u2"), _dev(b, "b"),
+                                   _dev(kappa, "kappa"), _dev(guess, "guess"), _stream(stream)), "nn_forward")
+
+
+def nn_backward(net: Net, u1, u_target, stream=None, want_loss=True):
+    loss = np.zeros(1)
+    _check(lib().axipcg_nn_backward(net.handle, _dev(u1, "u1"), _dev(u_target, "u_target"),
+                                    _hp(loss) if want_loss else None, _stream(stream)), "nn_backward")
+    return float(loss[0]) if want_loss else None
+
+
+def nn_adam(net: Net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().axipcg_nn_adam(net.handle, lr, beta1, beta2, eps, _stream(stream)), "nn_adam")
+
+
+def nn_guess(op: Op, net: Net, b, u1, u2, kappa, guess_scratch, x, stream=None, want_resid=True):
+    res = np.zeros(2)
+    _check(lib().axipcg_nn_guess(op.handle, net.handle, _dev(b, "b"), _dev(u1, "u1"), _dev(u2, "u2"),
+                                 _dev(kappa, "kappa"), _dev(guess_scratch, "guess_scratch"), _dev(x, "x"),
+                                 _hp(res) if want_resid else None, _stream(stream)), "nn_guess")
+    return (float(res[0]), float(res[1])) if want_resid else None
 
 
 def profile_select(op: Op, kernel: int):

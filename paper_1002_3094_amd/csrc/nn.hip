@@ -1,0 +1,695 @@
+// Learned initial guess for the Laguerre series (an extension beyond the
+// paper; PCG of §2.2 stays the judge of the answer).
+//
+// A 6-layer 3x3 convolutional network, 32 channels wide, maps four input
+// channels of harmonic m -- u_{m-1}/s, u_{m-2}/s, b_m/s_b and (kappa-2.5)/1.5,
+// s = RMS(u_{m-1}), s_b = RMS(b_m) -- to a correction c, and the guess is
+// u_{m-1} + s c (a zero network returns the previous-harmonic guess).  ReLU
+// after every layer but the last, zero "same" padding.  Weights and
+// activations are BF16, products are accumulated in FP32 by MFMA
+// (v_mfma_f32_16x16x16_bf16); training keeps FP32 master weights with Adam.
+//
+// Every convolution is an implicit GEMM over 16-pixel tiles of one grid row:
+// M = pixels, N = output channels, K = 9 taps x input channels.  A wave holds
+// all of its layer's B fragments in registers and sweeps tiles.  The data
+// gradient is the same kernel with flipped, transposed weights and the ReLU
+// mask of the layer below fused into its epilogue.  The weight gradient is a
+// GEMM over pixels (M = output channels, N = input channels, K = pixels) fed
+// from channel-major tiles staged in LDS, with per-workgroup partials summed
+// in a fixed order.
+#include <cmath>
+#include <vector>
+
+#include "kernels.h"
+
+namespace axipcg {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16;
+
+constexpr int NL = 6;
+constexpr int NPARAM = 38465;
+__host__ __device__ constexpr int cin_of(int l) { return l == 0 ? 4 : 32; }
+__host__ __device__ constexpr int cout_of(int l) { return l == NL - 1 ? 1 : 32; }
+__host__ __device__ constexpr int cinp_of(int l) { return l == 0 ? 16 : 32; }     // padded for MFMA K
+__host__ __device__ constexpr int coutp_of(int l) { return l == NL - 1 ? 16 : 32; }
+// offset of layer l's parameters: W[t][ci][co] (9 cin cout values) then b[co]
+__host__ __device__ constexpr int param_off(int l)
+{
+    int o = 0;
+    for (int j = 0; j < l; ++j) o += 9 * cin_of(j) * cout_of(j) + cout_of(j);
+    return o;
+}
+static_assert(param_off(NL) == NPARAM, "parameter count");
+
+__host__ __device__ inline bf16 to_bf16(float f)
+{
+    unsigned u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (bf16)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+    return (bf16)(u >> 16);
+}
+__device__ inline float from_bf16(bf16 h) { return __uint_as_float((unsigned)h << 16); }
+
+struct Net {
+    int nr = 0, nz = 0, device = 0;
+    float *params = nullptr, *grads = nullptr, *m1 = nullptr, *m2 = nullptr;
+    long long adam_t = 0;
+    bf16 *wf_fwd[NL] = {}, *wf_bwd[NL] = {};
+    float *bias_p[NL] = {};
+    bf16 *act[NL] = {};          // act[0]: packed input (16 ch); act[l]: output of layer l-1 (32 ch)
+    float *out = nullptr;        // last layer (1 channel, FP32)
+    bf16 *dpre[2] = {};          // gradient w.r.t. a layer's pre-activation (<= 32 ch)
+    float *wpart = nullptr;      // weight-gradient partials [WG_BLOCKS][9*32*32 + 32]
+    double *scal = nullptr;      // [0] s, [1] s_b, [2] loss, [3] residual of guess, [4] residual of u1
+    double *red = nullptr;       // [3][MAX_PARTIALS] partial sums
+    double *res_host = nullptr;  // pinned
+};
+
+constexpr int WG_BLOCKS = 512;
+constexpr int WG_SEG = 64;   // pixels per staged segment of the weight gradient
+
+// ---- input normalisation -----------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_nn_norms(const double *__restrict__ u1, const double *__restrict__ b, size_t n, double *red)
+{
+    __shared__ double sm[8];
+    double s1 = 0.0, s2 = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        s1 += u1[e] * u1[e];
+        s2 += b[e] * b[e];
+    }
+    const double t1 = block_sum(s1, sm);
+    const double t2 = block_sum(s2, sm);
+    if (threadIdx.x == 0) {
+        red[blockIdx.x] = t1;
+        red[MAX_PARTIALS + blockIdx.x] = t2;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_nn_norms_fin(const double *red, int nb, size_t n, double *scal)
+{
+    __shared__ double sm[8];
+    const double t1 = block_total(red, nb, sm);
+    const double t2 = block_total(red + MAX_PARTIALS, nb, sm);
+    if (threadIdx.x == 0) {
+        const double s = sqrt(t1 / (double)n), sb = sqrt(t2 / (double)n);
+        scal[0] = s > 0 ? s : 1.0;
+        scal[1] = sb > 0 ? sb : 1.0;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_nn_pack(const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ b,
+          const double *__restrict__ kap, bf16 *__restrict__ act0, size_t n, const double *scal)
+{
+    const double is = 1.0 / scal[0], ib = 1.0 / scal[1];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        alignas(16) bf16 v[16] = {};
+        v[0] = to_bf16((float)(u1[e] * is));
+        v[1] = to_bf16((float)(u2[e] * is));
+        v[2] = to_bf16((float)(b[e] * ib));
+        v[3] = to_bf16((float)((kap[e] - 2.5) / 1.5));
+        uint4 *dst = reinterpret_cast<uint4 *>(act0 + e * 16);
+        dst[0] = *reinterpret_cast<const uint4 *>(&v[0]);
+        dst[1] = *reinterpret_cast<const uint4 *>(&v[8]);
+    }
+}
+
+// ---- 3x3 convolution (forward, or data gradient with flipped weights) --------
+// in: [pixels][CINP] bf16; out: [pixels][COUTP] bf16 (or FP32 channel 0 when
+// LAST); wf: B fragments [9][CINP/16][COUTP/16][64 lanes]; mask: [pixels][COUTP]
+// bf16 (MASK: zero where mask <= 0).
+template <int CINP, int COUTP, bool RELU, bool MASK, bool LAST>
+__global__ void __launch_bounds__(256)
+k_conv3(const bf16 *__restrict__ in, void *__restrict__ outp, const bf16x4 *__restrict__ wf,
+        const float *__restrict__ bias, const bf16 *__restrict__ mask, int nr, int nz, int ntiles)
+{
+    constexpr int KB = CINP / 16, NB = COUTP / 16;
+    const int lane = threadIdx.x & 63;
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    bf16x4 w[9][KB][NB];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) w[t][kb][nb] = wf[((t * KB + kb) * NB + nb) * 64 + lane];
+    const int m = lane & 15, kq = lane >> 4;
+    float bl[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) bl[nb] = bias ? bias[nb * 16 + m] : 0.f;
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int p0 = tile * 16;
+        const int i = p0 / nz, k0 = p0 - i * nz;
+        f32x4 acc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{bl[nb], bl[nb], bl[nb], bl[nb]};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ii = i + t / 3 - 1, kk = k0 + m + t % 3 - 1;
+            const bool ok = ii >= 0 && ii < nr && kk >= 0 && kk < nz;
+            const bf16 *src = in + (size_t)(ok ? ii * nz + kk : 0) * CINP + kq * 4;
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                const bf16x4 a = ok ? *reinterpret_cast<const bf16x4 *>(src + kb * 16) : bf16x4{0, 0, 0, 0};
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[t][kb][nb], acc[nb], 0, 0, 0);
+            }
+        }
+        // D layout: lane holds pixel 4 kq + j, channel 16 nb + m
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const size_t pix = (size_t)p0 + 4 * kq + j;
+                const int ch = nb * 16 + m;
+                float v = acc[nb][j];
+                if (LAST) {
+                    if (nb == 0 && m == 0) static_cast<float *>(outp)[pix] = v;
+                } else {
+                    if (RELU) v = v > 0.f ? v : 0.f;
+                    if (MASK && !(from_bf16(mask[pix * COUTP + ch]) > 0.f)) v = 0.f;
+                    static_cast<bf16 *>(outp)[pix * COUTP + ch] = to_bf16(v);
+                }
+            }
+    }
+}
+
+// ---- loss: d = out - (u_target - u1)/s; gradient seed 2 d / P (channel 0) --
+__global__ void __launch_bounds__(256)
+k_nn_dout(const float *__restrict__ out, const double *__restrict__ ut, const double *__restrict__ u1,
+          bf16 *__restrict__ dpre, size_t n, const double *scal, double *red)
+{
+    __shared__ double sm[8];
+    const double is = 1.0 / scal[0];
+    const double g = 2.0 / (double)n;
+    double acc = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const double d = (double)out[e] - (ut[e] - u1[e]) * is;
+        acc += d * d;
+        alignas(16) bf16 v[16] = {};
+        v[0] = to_bf16((float)(g * d));
+        uint4 *dst = reinterpret_cast<uint4 *>(dpre + e * 16);
+        dst[0] = *reinterpret_cast<const uint4 *>(&v[0]);
+        dst[1] = *reinterpret_cast<const uint4 *>(&v[8]);
+    }
+    const double s = block_sum(acc, sm);
+    if (threadIdx.x == 0) red[2 * MAX_PARTIALS + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(256) k_nn_loss_fin(const double *red, int nb, size_t n, double *scal)
+{
+    __shared__ double sm[8];
+    const double t = block_total(red + 2 * MAX_PARTIALS, nb, sm);
+    if (threadIdx.x == 0) scal[2] = t / (double)n;
+}
+
+// ---- weight gradient ------------------------------------------------------------
+// dW[t][ci][co] = sum_p act[p + off_t][ci] dpre[p][co];  db[co] = sum_p dpre[p][co].
+// Workgroup partials wpart[block][t][co][ci] (padded channels) then db[co].
+template <int CINP, int COUTP>
+__global__ void __launch_bounds__(256)
+k_wgrad(const bf16 *__restrict__ act, const bf16 *__restrict__ dpre, float *__restrict__ wpart, int nr, int nz)
+{
+    constexpr int NBO = COUTP / 16, NBI = CINP / 16, NT = 9 * NBO * NBI;
+    constexpr int TPW = (NT + 3) / 4;   // tiles per wave
+    constexpr int XW = WG_SEG + 2;
+    __shared__ bf16 yt[COUTP][WG_SEG];
+    __shared__ bf16 xt[3][CINP][XW];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.f;
+    const int segs_per_row = nz / WG_SEG;
+    const int nseg = nr * segs_per_row;
+    for (int sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
+        const int i = sg / segs_per_row, k0 = (sg - i * segs_per_row) * WG_SEG;
+        __syncthreads();
+        for (int e = threadIdx.x; e < WG_SEG * COUTP; e += blockDim.x) {
+            const int q = e / COUTP, co = e - q * COUTP;
+            yt[co][q] = dpre[((size_t)i * nz + k0 + q) * COUTP + co];
+        }
+        for (int e = threadIdx.x; e < 3 * XW * CINP; e += blockDim.x) {
+            const int r = e / (XW * CINP), rem = e - r * XW * CINP;
+            const int q = rem / CINP, ci = rem - q * CINP;
+            const int ii = i + r - 1, kk = k0 + q - 1;
+            bf16 v = 0;
+            if (ii >= 0 && ii < nr && kk >= 0 && kk < nz) v = act[((size_t)ii * nz + kk) * CINP + ci];
+            xt[r][ci][q] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < COUTP)
+            for (int q = 0; q < WG_SEG; ++q) dbias += from_bf16(yt[threadIdx.x][q]);
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int tl = wv * TPW + u;
+            if (tl >= NT) continue;
+            const int t = tl / (NBO * NBI), rem = tl - t * NBO * NBI;
+            const int ob = rem / NBI, ib = rem - ob * NBI;
+            const int di = t / 3, dk = t % 3;   // staged row r = di, column offset q + dk
+#pragma unroll
+            for (int ks = 0; ks < WG_SEG / 16; ++ks) {
+                const int q = ks * 16 + 4 * kq;
+                bf16x4 a, b;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    a[j] = (short)yt[ob * 16 + m][q + j];
+                    b[j] = (short)xt[di][ib * 16 + m][q + j + dk];
+                }
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[u], 0, 0, 0);
+            }
+        }
+    }
+    // D[co][ci]: lane holds co = 16 ob + 4 kq + j, ci = 16 ib + m
+    float *wp = wpart + (size_t)blockIdx.x * (9 * 32 * 32 + 32);
+#pragma unroll
+    for (int u = 0; u < TPW; ++u) {
+        const int tl = wv * TPW + u;
+        if (tl >= NT) continue;
+        const int t = tl / (NBO * NBI), rem = tl - t * NBO * NBI;
+        const int ob = rem / NBI, ib = rem - ob * NBI;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = ob * 16 + 4 * kq + j, ci = ib * 16 + m;
+            wp[(t * COUTP + co) * CINP + ci] = acc[u][j];
+        }
+    }
+    if (threadIdx.x < COUTP) wp[9 * 32 * 32 + threadIdx.x] = dbias;
+}
+
+// grads (master layout) = sum of the partials over workgroups, in order.
+template <int CINP, int COUTP>
+__global__ void __launch_bounds__(256)
+k_wgrad_reduce(const float *__restrict__ wpart, int nblk, float *__restrict__ grads, int cin, int cout)
+{
+    const int nw = 9 * cin * cout;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nw + cout; e += gridDim.x * blockDim.x) {
+        int src;
+        if (e < nw) {
+            const int t = e / (cin * cout), rem = e - t * cin * cout;
+            const int ci = rem / cout, co = rem - ci * cout;
+            src = (t * COUTP + co) * CINP + ci;
+        } else {
+            src = 9 * 32 * 32 + (e - nw);
+        }
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += wpart[(size_t)b * (9 * 32 * 32 + 32) + src];
+        grads[e] = (float)s;
+    }
+}
+
+// ---- Adam on the FP32 master weights ---------------------------------------------
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m1,
+                       float *__restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const float gv = g[e];
+        const float a = b1 * m1[e] + (1.f - b1) * gv;
+        const float v = b2 * m2[e] + (1.f - b2) * gv * gv;
+        m1[e] = a;
+        m2[e] = v;
+        p[e] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+    }
+}
+
+// ---- master weights -> BF16 MFMA fragments ----------------------------------------
+// forward fragment (t, kb, nb, lane, item): W[t][ci = 16 kb + 4 (lane/16) + item][co = 16 nb + lane%16]
+// data-gradient fragment: W'[t][co][ci] = W[8 - t][ci][co], K = co, N = ci
+template <int L>
+__global__ void k_pack_weights(const float *__restrict__ params, bf16 *__restrict__ wf, bf16 *__restrict__ wb,
+                               float *__restrict__ bias_p)
+{
+    constexpr int CI = cin_of(L), CO = cout_of(L), CIP = cinp_of(L), COP = coutp_of(L);
+    const float *W = params + param_off(L);
+    const float *bias = W + 9 * CI * CO;
+    const int nf = 9 * CIP * COP;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
+        const int item = e & 3, lane = (e >> 2) & 63, frag = e >> 8;
+        // forward
+        {
+            const int NBk = COP / 16, KBk = CIP / 16;
+            const int nb = frag % NBk, kb = (frag / NBk) % KBk, t = frag / (NBk * KBk);
+            const int ci = 16 * kb + 4 * (lane >> 4) + item, co = 16 * nb + (lane & 15);
+            const float v = (ci < CI && co < CO) ? W[(t * CI + ci) * CO + co] : 0.f;
+            wf[e] = to_bf16(v);
+        }
+        // data gradient (input channels COP, output channels CIP)
+        if (wb) {
+            const int NBk = CIP / 16, KBk = COP / 16;
+            const int nb = frag % NBk, kb = (frag / NBk) % KBk, t = frag / (NBk * KBk);
+            const int co = 16 * kb + 4 * (lane >> 4) + item, ci = 16 * nb + (lane & 15);
+            const float v = (ci < CI && co < CO) ? W[((8 - t) * CI + ci) * CO + co] : 0.f;
+            wb[e] = to_bf16(v);
+        }
+    }
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < COP; c += gridDim.x * blockDim.x)
+        bias_p[c] = c < CO ? bias[c] : 0.f;
+}
+
+// guess = u1 + s * out
+__global__ void __launch_bounds__(256)
+k_nn_unpack(const double *__restrict__ u1, const float *__restrict__ out, double *__restrict__ g, size_t n,
+            const double *scal)
+{
+    const double s = scal[0];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        g[e] = u1[e] + s * (double)out[e];
+}
+
+// ||b - A g||^2 and ||b - A u1||^2 partials
+__global__ void __launch_bounds__(256)
+k_nn_resid2(const double *__restrict__ b, const double *__restrict__ g, const double *__restrict__ u1,
+            const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
+            int nz, double *red)
+{
+    __shared__ double sm[8];
+    const size_t n = (size_t)nr * nz;
+    double s1 = 0.0, s2 = 0.0;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
+        double v1 = D[e] * g[e], v2 = D[e] * u1[e];
+        if (i + 1 < nr) { v1 -= CR[e] * g[e + nz]; v2 -= CR[e] * u1[e + nz]; }
+        if (i > 0) { v1 -= CR[e - nz] * g[e - nz]; v2 -= CR[e - nz] * u1[e - nz]; }
+        if (k + 1 < nz) { v1 -= CZ[e] * g[e + 1]; v2 -= CZ[e] * u1[e + 1]; }
+        if (k > 0) { v1 -= CZ[e - 1] * g[e - 1]; v2 -= CZ[e - 1] * u1[e - 1]; }
+        const double d1 = b[e] - v1, d2 = b[e] - v2;
+        s1 += d1 * d1;
+        s2 += d2 * d2;
+    }
+    const double t1 = block_sum(s1, sm);
+    const double t2 = block_sum(s2, sm);
+    if (threadIdx.x == 0) {
+        red[blockIdx.x] = t1;
+        red[MAX_PARTIALS + blockIdx.x] = t2;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_nn_resid_fin(const double *red, int nb, double *scal)
+{
+    __shared__ double sm[8];
+    const double r1 = block_total(red, nb, sm);
+    const double r2 = block_total(red + MAX_PARTIALS, nb, sm);
+    if (threadIdx.x == 0) {
+        scal[3] = r1;
+        scal[4] = r2;
+    }
+}
+
+// x = guess if its residual is finite and smaller than that of u1, else u1
+__global__ void __launch_bounds__(256)
+k_nn_select(const double *__restrict__ g, const double *u1, double *x, size_t n, const double *scal)
+{
+    const double r1 = scal[3], r2 = scal[4];
+    const bool use = (r1 == r1) && r1 < r2;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+        x[e] = use ? g[e] : u1[e];
+}
+
+// ---- host helpers -------------------------------------------------------------------
+template <typename P>
+void nalloc(P **p, size_t count)
+{
+    void *v = nullptr;
+    hipError_t e = hipMalloc(&v, count * sizeof(P));
+    if (e != hipSuccess) throw Error{AXIPCG_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    *p = static_cast<P *>(v);
+}
+
+void free_net(Net *n)
+{
+    if (!n) return;
+    std::vector<void *> ptrs = {n->params, n->grads, n->m1, n->m2, n->out, n->dpre[0], n->dpre[1], n->wpart,
+                                n->scal, n->red};
+    for (int l = 0; l < NL; ++l) {
+        ptrs.push_back(n->wf_fwd[l]);
+        ptrs.push_back(n->wf_bwd[l]);
+        ptrs.push_back(n->bias_p[l]);
+        ptrs.push_back(n->act[l]);
+    }
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (n->res_host) (void)hipHostFree(n->res_host);
+    delete n;
+}
+
+unsigned pw_blocks(size_t n) { return pointwise_blocks(n); }
+
+void pack_all(Net &n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_weights<0>, dim3(16), dim3(256), 0, s, n.params, n.wf_fwd[0], nullptr, n.bias_p[0]);
+    hipLaunchKernelGGL(k_pack_weights<1>, dim3(64), dim3(256), 0, s, n.params, n.wf_fwd[1], n.wf_bwd[1], n.bias_p[1]);
+    hipLaunchKernelGGL(k_pack_weights<2>, dim3(64), dim3(256), 0, s, n.params, n.wf_fwd[2], n.wf_bwd[2], n.bias_p[2]);
+    hipLaunchKernelGGL(k_pack_weights<3>, dim3(64), dim3(256), 0, s, n.params, n.wf_fwd[3], n.wf_bwd[3], n.bias_p[3]);
+    hipLaunchKernelGGL(k_pack_weights<4>, dim3(64), dim3(256), 0, s, n.params, n.wf_fwd[4], n.wf_bwd[4], n.bias_p[4]);
+    hipLaunchKernelGGL(k_pack_weights<5>, dim3(32), dim3(256), 0, s, n.params, n.wf_fwd[5], n.wf_bwd[5], n.bias_p[5]);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+unsigned conv_blocks(int ntiles)
+{
+    // one tile per wave per sweep step; 4 waves per workgroup
+    int b = (ntiles + 3) / 4;
+    if (b > 2048) b = 2048;
+    return (unsigned)b;
+}
+
+void forward_impl(Net &n, const double *u1, const double *u2, const double *b, const double *kap, hipStream_t s)
+{
+    const size_t np = (size_t)n.nr * n.nz;
+    const unsigned pb = pw_blocks(np);
+    hipLaunchKernelGGL(k_nn_norms, dim3(pb), dim3(256), 0, s, u1, b, np, n.red);
+    hipLaunchKernelGGL(k_nn_norms_fin, dim3(1), dim3(256), 0, s, n.red, (int)pb, np, n.scal);
+    hipLaunchKernelGGL(k_nn_pack, dim3(pb), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.scal);
+    const int ntiles = (int)(np / 16);
+    const dim3 cg(conv_blocks(ntiles)), cb(256);
+    hipLaunchKernelGGL((k_conv3<16, 32, true, false, false>), cg, cb, 0, s, n.act[0], (void *)n.act[1],
+                       (const bf16x4 *)n.wf_fwd[0], n.bias_p[0], nullptr, n.nr, n.nz, ntiles);
+    for (int l = 1; l < NL - 1; ++l)
+        hipLaunchKernelGGL((k_conv3<32, 32, true, false, false>), cg, cb, 0, s, n.act[l], (void *)n.act[l + 1],
+                           (const bf16x4 *)n.wf_fwd[l], n.bias_p[l], nullptr, n.nr, n.nz, ntiles);
+    hipLaunchKernelGGL((k_conv3<32, 16, false, false, true>), cg, cb, 0, s, n.act[NL - 1], (void *)n.out,
+                       (const bf16x4 *)n.wf_fwd[NL - 1], n.bias_p[NL - 1], nullptr, n.nr, n.nz, ntiles);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void backward_impl(Net &n, const double *ut, const double *u1, hipStream_t s)
+{
+    const size_t np = (size_t)n.nr * n.nz;
+    const unsigned pb = pw_blocks(np);
+    hipLaunchKernelGGL(k_nn_dout, dim3(pb), dim3(256), 0, s, n.out, ut, u1, n.dpre[0], np, n.scal, n.red);
+    hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(256), 0, s, n.red, (int)pb, np, n.scal);
+    const int ntiles = (int)(np / 16);
+    const dim3 cg(conv_blocks(ntiles)), cb(256);
+    const int nseg = (int)(np / WG_SEG);
+    const int wgb = nseg < WG_BLOCKS ? nseg : WG_BLOCKS;
+    int cur = 0;
+    for (int l = NL - 1; l >= 0; --l) {
+        float *g = n.grads + param_off(l);
+        const int rb = (9 * cin_of(l) * cout_of(l) + cout_of(l) + 255) / 256;
+        // weight gradient of layer l from act[l] and dpre[cur]
+        if (l == 0) {
+            hipLaunchKernelGGL((k_wgrad<16, 32>), dim3(wgb), dim3(256), 0, s, n.act[0], n.dpre[cur], n.wpart, n.nr, n.nz);
+            hipLaunchKernelGGL((k_wgrad_reduce<16, 32>), dim3(rb), dim3(256), 0, s, n.wpart, wgb, g, cin_of(l), cout_of(l));
+        } else if (l == NL - 1) {
+            hipLaunchKernelGGL((k_wgrad<32, 16>), dim3(wgb), dim3(256), 0, s, n.act[l], n.dpre[cur], n.wpart, n.nr, n.nz);
+            hipLaunchKernelGGL((k_wgrad_reduce<32, 16>), dim3(rb), dim3(256), 0, s, n.wpart, wgb, g, cin_of(l), cout_of(l));
+        } else {
+            hipLaunchKernelGGL((k_wgrad<32, 32>), dim3(wgb), dim3(256), 0, s, n.act[l], n.dpre[cur], n.wpart, n.nr, n.nz);
+            hipLaunchKernelGGL((k_wgrad_reduce<32, 32>), dim3(rb), dim3(256), 0, s, n.wpart, wgb, g, cin_of(l), cout_of(l));
+        }
+        // data gradient into layer l-1's pre-activation (masked by its ReLU output act[l])
+        if (l >= 1) {
+            if (l == NL - 1)
+                hipLaunchKernelGGL((k_conv3<16, 32, false, true, false>), cg, cb, 0, s, n.dpre[cur], (void *)n.dpre[1 - cur],
+                                   (const bf16x4 *)n.wf_bwd[l], nullptr, n.act[l], n.nr, n.nz, ntiles);
+            else
+                hipLaunchKernelGGL((k_conv3<32, 32, false, true, false>), cg, cb, 0, s, n.dpre[cur], (void *)n.dpre[1 - cur],
+                                   (const bf16x4 *)n.wf_bwd[l], nullptr, n.act[l], n.nr, n.nz, ntiles);
+            cur = 1 - cur;
+        }
+    }
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+Net *create_impl_nn(int nr, int nz, const float *params)
+{
+    Net *n = new (std::nothrow) Net();
+    if (!n) throw Error{AXIPCG_ENOMEM, "host allocation failed"};
+    try {
+        n->nr = nr;
+        n->nz = nz;
+        AXI_CHECK_HIP(hipGetDevice(&n->device));
+        const size_t np = (size_t)nr * nz;
+        nalloc(&n->params, NPARAM);
+        nalloc(&n->grads, NPARAM);
+        nalloc(&n->m1, NPARAM);
+        nalloc(&n->m2, NPARAM);
+        for (int l = 0; l < NL; ++l) {
+            nalloc(&n->wf_fwd[l], (size_t)9 * cinp_of(l) * coutp_of(l));
+            if (l >= 1) nalloc(&n->wf_bwd[l], (size_t)9 * cinp_of(l) * coutp_of(l));
+            nalloc(&n->bias_p[l], (size_t)coutp_of(l));
+            nalloc(&n->act[l], np * (size_t)cinp_of(l));
+        }
+        nalloc(&n->out, np);
+        nalloc(&n->dpre[0], np * 32);
+        nalloc(&n->dpre[1], np * 32);
+        nalloc(&n->wpart, (size_t)WG_BLOCKS * (9 * 32 * 32 + 32));
+        nalloc(&n->scal, 8);
+        nalloc(&n->red, 3 * (size_t)MAX_PARTIALS);
+        AXI_CHECK_HIP(hipHostMalloc((void **)&n->res_host, 8 * sizeof(double), hipHostMallocDefault));
+        AXI_CHECK_HIP(hipMemcpy(n->params, params, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
+        AXI_CHECK_HIP(hipMemset(n->grads, 0, sizeof(float) * NPARAM));
+        AXI_CHECK_HIP(hipMemset(n->m1, 0, sizeof(float) * NPARAM));
+        AXI_CHECK_HIP(hipMemset(n->m2, 0, sizeof(float) * NPARAM));
+        pack_all(*n, nullptr);
+        AXI_CHECK_HIP(hipDeviceSynchronize());
+    } catch (...) {
+        free_net(n);
+        throw;
+    }
+    return n;
+}
+
+}  // namespace
+}  // namespace axipcg
+
+using namespace axipcg;
+
+extern "C" {
+
+int axipcg_nn_num_params(void) { return NPARAM; }
+
+int axipcg_nn_create(int nr, int nz, const float *params, axipcg_nn_t *out)
+{
+    return guarded([&] {
+        AXI_REQUIRE(out && params, "NULL argument");
+        AXI_REQUIRE(nr >= 1 && nr <= 8192, "nr must be in [1, 8192]");
+        AXI_REQUIRE(nz >= 64 && nz <= 8192 && nz % 64 == 0, "nz must be a multiple of 64 in [64, 8192]");
+        for (int e = 0; e < NPARAM; ++e) AXI_REQUIRE(std::isfinite(params[e]), "non-finite parameter");
+        *out = reinterpret_cast<axipcg_nn_t>(create_impl_nn(nr, nz, params));
+        return AXIPCG_OK;
+    });
+}
+
+void axipcg_nn_destroy(axipcg_nn_t h)
+{
+    Net *n = reinterpret_cast<Net *>(h);
+    if (!n) return;
+    (void)hipDeviceSynchronize();
+    free_net(n);
+}
+
+int axipcg_nn_get_params(axipcg_nn_t h, float *params, float *grads)
+{
+    return guarded([&] {
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(n != nullptr, "NULL network");
+        AXI_CHECK_HIP(hipDeviceSynchronize());
+        if (params) AXI_CHECK_HIP(hipMemcpy(params, n->params, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+        if (grads) AXI_CHECK_HIP(hipMemcpy(grads, n->grads, sizeof(float) * NPARAM, hipMemcpyDeviceToHost));
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_set_params(axipcg_nn_t h, const float *params)
+{
+    return guarded([&] {
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(n && params, "NULL argument");
+        for (int e = 0; e < NPARAM; ++e) AXI_REQUIRE(std::isfinite(params[e]), "non-finite parameter");
+        AXI_CHECK_HIP(hipDeviceSynchronize());
+        AXI_CHECK_HIP(hipMemcpy(n->params, params, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
+        pack_all(*n, nullptr);
+        AXI_CHECK_HIP(hipDeviceSynchronize());
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_forward(axipcg_nn_t h, const double *u1, const double *u2, const double *b, const double *kappa,
+                      double *guess, void *stream)
+{
+    return guarded([&] {
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(n && u1 && u2 && b && kappa && guess, "NULL argument");
+        hipStream_t s = (hipStream_t)stream;
+        forward_impl(*n, u1, u2, b, kappa, s);
+        const size_t np = (size_t)n->nr * n->nz;
+        hipLaunchKernelGGL(k_nn_unpack, dim3(pw_blocks(np)), dim3(256), 0, s, u1, n->out, guess, np, n->scal);
+        AXI_CHECK_HIP(hipGetLastError());
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_backward(axipcg_nn_t h, const double *u1, const double *u_target, double *loss_host, void *stream)
+{
+    return guarded([&] {
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(n && u1 && u_target, "NULL argument");
+        hipStream_t s = (hipStream_t)stream;
+        backward_impl(*n, u_target, u1, s);
+        if (loss_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            *loss_host = n->res_host[0];
+        }
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_adam(axipcg_nn_t h, double lr, double beta1, double beta2, double eps, void *stream)
+{
+    return guarded([&] {
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(n != nullptr, "NULL network");
+        AXI_REQUIRE(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0, "bad Adam constants");
+        hipStream_t s = (hipStream_t)stream;
+        n->adam_t += 1;
+        const float c1 = (float)(1.0 - std::pow(beta1, (double)n->adam_t));
+        const float c2 = (float)(1.0 - std::pow(beta2, (double)n->adam_t));
+        hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, n->params, n->grads, n->m1, n->m2,
+                           NPARAM, (float)lr, (float)beta1, (float)beta2, (float)eps, c1, c2);
+        AXI_CHECK_HIP(hipGetLastError());
+        pack_all(*n, s);
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const double *u1, const double *u2,
+                    const double *kappa, double *guess_scratch, double *x, double *resid_host, void *stream)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(hop);
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(op && n && b && u1 && u2 && kappa && guess_scratch && x, "NULL argument");
+        AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
+        AXI_REQUIRE(guess_scratch != x && guess_scratch != u1 && guess_scratch != b && guess_scratch != kappa,
+                    "guess_scratch aliases another argument");
+        hipStream_t s = (hipStream_t)stream;
+        forward_impl(*n, u1, u2, b, kappa, s);
+        const size_t np = (size_t)n->nr * n->nz;
+        const unsigned pb = pw_blocks(np);
+        hipLaunchKernelGGL(k_nn_unpack, dim3(pb), dim3(256), 0, s, u1, n->out, guess_scratch, np, n->scal);
+        hipLaunchKernelGGL(k_nn_resid2, dim3(pb), dim3(256), 0, s, b, guess_scratch, u1, op->D, op->CR, op->CZ,
+                           op->nr, op->nz, n->red);
+        hipLaunchKernelGGL(k_nn_resid_fin, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal);
+        hipLaunchKernelGGL(k_nn_select, dim3(pb), dim3(256), 0, s, guess_scratch, u1, x, np, n->scal);
+        AXI_CHECK_HIP(hipGetLastError());
+        if (resid_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            resid_host[0] = std::sqrt(n->res_host[0]);
+            resid_host[1] = std::sqrt(n->res_host[1]);
+        }
+        return AXIPCG_OK;
+    });
+}
+
+}  // extern "C"

@@ -185,3 +185,26 @@ def laguerre_series_inputs(nr: int, nz: int, seed: int = 0, eta: float = 10.0, z
     t, ft = ricker_pulse_samples()
     return dict(nr=nr, nz=nz, lr=1.0, lz=1.0, kappa=kappa, q=q, src_i=0, src_k=k0,
                 eta=eta, t=t, ft=ft, seed=seed)
+
+
+def nn_example(nr: int, nz: int, seed: int = 0):
+    """Smooth random fields shaped like the learned guess's inputs.
+
+    u1, u2, ut play u_{m-1}, u_{m-2} and the solved u_m (correlated, O(1)
+    amplitude), b a right-hand side with a localised bump and kappa a medium
+    in [1, 4].  Plain random data: no step of the method is computed here.
+    """
+    rng = np.random.default_rng(seed)
+
+    def smooth(scale):
+        g = ndimage.gaussian_filter(rng.standard_normal((nr, nz)), sigma=max(1.0, min(nr, nz) / 8), mode="wrap")
+        return scale * _unit_std(g)
+
+    base = smooth(1.0)
+    u1 = base + 0.3 * smooth(1.0)
+    u2 = base + 0.3 * smooth(1.0)
+    ut = base + 0.3 * smooth(1.0)
+    b = smooth(0.2)
+    b[nr // 3, nz // 2] += 5.0
+    kappa = 2.5 + 1.5 * np.tanh(smooth(1.0))
+    return {"u1": u1, "u2": u2, "ut": ut, "b": b, "kappa": kappa}

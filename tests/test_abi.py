@@ -97,3 +97,23 @@ def test_laguerre_coeffs_validates(ax):
                                       None) == ax.EINVAL
     assert lib.axipcg_laguerre_coeffs(0, 10.0, 8, 0.2, f.ctypes.data_as(ax._dp), g.ctypes.data_as(ax._dp),
                                       None) == ax.EINVAL
+
+
+def test_nn_entry_points_validate_before_device_work(ax):
+    lib = ax.lib()
+    n = lib.axipcg_nn_num_params()
+    assert n == 38465
+    p = np.zeros(n, dtype=np.float32)
+    out = ctypes.c_void_p()
+    for nr, nz in ((0, 64), (8, 65), (8, 32), (9000, 64), (8, 8256)):
+        assert lib.axipcg_nn_create(nr, nz, ax._fp(p), ctypes.byref(out)) == ax.EINVAL
+        assert out.value is None
+    p[100] = np.inf
+    assert lib.axipcg_nn_create(8, 64, ax._fp(p), ctypes.byref(out)) == ax.EINVAL
+    assert "non-finite" in ax.last_error()
+    assert lib.axipcg_nn_create(8, 64, None, ctypes.byref(out)) == ax.EINVAL
+    assert lib.axipcg_nn_forward(None, None, None, None, None, None, None) == ax.EINVAL
+    assert lib.axipcg_nn_backward(None, None, None, None, None) == ax.EINVAL
+    assert lib.axipcg_nn_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == ax.EINVAL
+    assert lib.axipcg_nn_guess(None, None, None, None, None, None, None, None, None, None) == ax.EINVAL
+    lib.axipcg_nn_destroy(None)  # NULL-safe
