@@ -178,13 +178,14 @@ int axipcg_laguerre_rhs(axipcg_op_t op, double g_m, int src_i, int src_k,
  * (device [nr][nz] doubles): u1 = u_{m-1}, u2 = u_{m-2}, b = right-hand side
  * of harmonic m, kappa per cell.  With s = RMS(u1) and s_b = RMS(b) (1 where
  * zero) the channels are u1/s, u2/s, b/s_b, (kappa - 2.5)/1.5, and the guess
- * is u1 + s * out, so a network whose last layer is zero reproduces u1.
- * Parameters (host float[axipcg_nn_num_params()]): for each layer l = 0..5,
- * W_l[t][ci][co] (t = 3 (di+1) + (dk+1) over the 3x3 window in (r, z),
- * ci < cin_l, co < cout_l; cin = 4,32,32,32,32,32, cout = 32,...,32,1) then
- * bias_l[co].  The handle owns device copies and Adam moments; sizes: nr in
- * [1, 8192], nz a multiple of 64 in [64, 8192].  Calls on one handle must
- * not overlap. */
+ * is 2 u1 - u2 + s * out (a network whose last layer is zero returns the
+ * linear extrapolation).  Parameters (host float[axipcg_nn_num_params()]):
+ * for each layer l = 0..5, W_l[t][ci][co] (t = 3 (di+1) + (dk+1) over the
+ * 3x3 window in (r, z), ci < cin_l, co < cout_l; cin = 4,32,32,32,32,32,
+ * cout = 32,...,32,1) then bias_l[co].  The handle owns device copies, the
+ * activations of the last forward and the Adam moments; sizes: nr in
+ * [1, 8192], nz a multiple of 64 in [64, 8192].  Calls on one handle must not
+ * overlap. */
 typedef struct axipcg_nn *axipcg_nn_t;
 int axipcg_nn_num_params(void);
 int axipcg_nn_create(int nr, int nz, const float *params, axipcg_nn_t *out);
@@ -194,26 +195,30 @@ void axipcg_nn_destroy(axipcg_nn_t nn);
 int axipcg_nn_get_params(axipcg_nn_t nn, float *params, float *grads);
 /* Replace the parameters (finite values only); Adam moments are kept. */
 int axipcg_nn_set_params(axipcg_nn_t nn, const float *params);
-/* guess = u1 + s * net(u1, u2, b, kappa) (device [nr][nz]; guess may not
- * alias an input).  Keeps the activations for nn_backward. */
+/* guess = 2 u1 - u2 + s * net(u1, u2, b, kappa), unguarded (device
+ * [nr][nz]; guess may alias u1 or u2, not b or kappa). */
 int axipcg_nn_forward(axipcg_nn_t nn, const double *u1, const double *u2, const double *b,
                       const double *kappa, double *guess, void *stream);
-/* Loss of the last forward, L = mean((out - (u_target - u1)/s)^2), and the
- * gradient of L w.r.t. every parameter (kept on the device; nn_get_params
- * reads it).  u1 must be the forward's u1.  loss_host (may be NULL)
- * receives L and then the call synchronises the stream. */
-int axipcg_nn_backward(axipcg_nn_t nn, const double *u1, const double *u_target, double *loss_host,
-                       void *stream);
+/* Training loss of the last forward (or nn_guess) against the solved
+ * harmonic u_target: with e = 2 u1 - u2 + s * out - u_target,
+ *     L = e^T A e / (s^2 nr nz)   (the energy norm of the guess error),
+ * A the operator of op (same sizes), and its gradient w.r.t. every parameter
+ * (kept on the device; nn_get_params reads it).  u1 and u2 must be the
+ * forward's.  loss_host (may be NULL) receives L and then the call
+ * synchronises the stream. */
+int axipcg_nn_backward(axipcg_op_t op, axipcg_nn_t nn, const double *u1, const double *u2,
+                       const double *u_target, double *loss_host, void *stream);
 /* One Adam step with the last gradients (bias-corrected moments, step count
  * kept by the handle). */
 int axipcg_nn_adam(axipcg_nn_t nn, double lr, double beta1, double beta2, double eps, void *stream);
-/* Guarded guess for PCG: computes the network guess into guess_scratch, then
- * writes to x whichever of it and u1 has the smaller ||b - A x|| (u1 when the
- * guess is not finite).  guess_scratch may not alias u1, b, kappa or x; x may
- * alias u1 or u2.  resid_host (may be NULL; host double[2]) receives the two
- * residual norms (guess, u1), and then the call synchronises the stream. */
+/* Guarded guess for PCG: runs the network, then writes to x the candidate
+ * among u1, 2 u1 - u2 and the network guess with the smallest residual
+ * |b - A x| (a later candidate must be strictly smaller; a NaN never wins).
+ * x may alias u1 or u2, not b or kappa.  resid_host (host double[3]: network,
+ * extrapolation, u1) and choice_host (0 u1, 1 extrapolation, 2 network) may
+ * be NULL; when either is given the call synchronises the stream. */
 int axipcg_nn_guess(axipcg_op_t op, axipcg_nn_t nn, const double *b, const double *u1, const double *u2,
-                    const double *kappa, double *guess_scratch, double *x, double *resid_host, void *stream);
+                    const double *kappa, double *x, double *resid_host, int *choice_host, void *stream);
 
 /* ---- per-kernel timing (tracing aid) ----------------------------------------
  * Select one kernel class of the PCG iteration; pcg_solve then brackets each

@@ -12,8 +12,13 @@ header rather than by the paper:
   u_{m-1}/s, u_{m-2}/s, b_m/s_b, (kappa - 2.5)/1.5;
 * six 3x3 convolutions with zero "same" padding, 4 -> 32 -> ... -> 32 -> 1
   channels, ReLU after every layer but the last;
-* guess = u_{m-1} + s * out;
-* loss L = mean((out - (u_target - u_{m-1})/s)^2), Adam on the parameters.
+* guess = 2 u_{m-1} - u_{m-2} + s * out (the network corrects the linear
+  extrapolation in m);
+* loss: the energy norm of the guess error, L = e^T A e / (s^2 P) with
+  e = guess - u_target, A the scheme's matrix and P the number of cells;
+  Adam on the parameters;
+* guard: of u_{m-1}, the extrapolation and the guess, the one with the
+  smallest residual |b - A x|, a later candidate only when strictly smaller.
 
 Parameters are a flat float32 vector: per layer W[t][ci][co] with
 t = 3 (di + 1) + (dk + 1) for the neighbour (i + di, k + dk), then bias[co].
@@ -58,7 +63,7 @@ def unpack(params):
 
 
 def init_params(seed: int, last_zero: bool = True) -> np.ndarray:
-    """He-normal weights, zero biases; a zero last layer makes the guess u_{m-1}."""
+    """He-normal weights, zero biases; a zero last layer makes the guess the extrapolation."""
     rng = np.random.default_rng(seed)
     p = np.zeros(N_PARAMS, dtype=np.float32)
     for l in range(N_LAYERS):
@@ -133,19 +138,24 @@ def forward(params, u1, u2, b, kappa, bf16=True):
             acts.append(rnd(np.maximum(y, 0.0)))
         else:
             out = y[..., 0]
-    guess = np.asarray(u1, dtype=np.float64) + s * out
-    return guess, {"acts": acts, "out": out, "s": s, "bf16": bf16}
+    u1, u2 = np.asarray(u1, dtype=np.float64), np.asarray(u2, dtype=np.float64)
+    guess = 2.0 * u1 - u2 + s * out
+    return guess, {"acts": acts, "out": out, "s": s, "bf16": bf16, "guess": guess}
 
 
-def backward(params, cache, u1, u_target):
-    """Loss and its gradient w.r.t. the flat parameter vector (FP64)."""
+def backward(params, cache, apply_A, u_target):
+    """Energy-norm loss and its gradient w.r.t. the flat parameter vector.
+
+    ``apply_A`` maps a [nr][nz] array to A times it (A symmetric), so that
+    dL/d(out) = 2 s A e / (s^2 P)."""
     rnd = bf16_round if cache["bf16"] else _ident
     layers = unpack(params)
-    acts, out, s = cache["acts"], cache["out"], cache["s"]
-    d = out - (np.asarray(u_target, dtype=np.float64) - np.asarray(u1, dtype=np.float64)) / s
-    P = d.size
-    loss = float(np.mean(d * d))
-    g = rnd(2.0 * d / P)[..., None]          # dL/d(out), channel axis last
+    acts, s = cache["acts"], cache["s"]
+    e = cache["guess"] - np.asarray(u_target, dtype=np.float64)
+    y = apply_A(e)
+    P = e.size
+    loss = float(np.sum(e * y)) / (s * s * P)
+    g = rnd(2.0 * y / (s * P))[..., None]    # dL/d(out), channel axis last
     grads = np.zeros(N_PARAMS)
     for l in range(N_LAYERS - 1, -1, -1):
         W = rnd(layers[l][0])
@@ -164,6 +174,20 @@ def backward(params, cache, u1, u_target):
                 dx += shift(g, -di, -dk) @ W[t].T
             g = rnd(dx * (x > 0))
     return loss, grads
+
+
+def guard(b, u1, u2, guess, apply_A):
+    """Residual norms of (guess, extrapolation, u1) and the pick: 0 u1,
+    1 extrapolation, 2 guess; a later candidate must be strictly smaller."""
+    u1, u2 = np.asarray(u1, dtype=np.float64), np.asarray(u2, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    cands = [u1, 2.0 * u1 - u2, np.asarray(guess, dtype=np.float64)]
+    res = [float(np.sqrt(np.sum((b - apply_A(x)) ** 2))) for x in cands]
+    pick, best = 0, res[0]
+    for j in (1, 2):
+        if res[j] < best:
+            pick, best = j, res[j]
+    return (res[2], res[1], res[0]), pick
 
 
 def adam(params, grads, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -63,9 +63,9 @@ SIGNATURES = {
     "axipcg_nn_get_params": ([_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)], _i),
     "axipcg_nn_set_params": ([_vp, ctypes.POINTER(ctypes.c_float)], _i),
     "axipcg_nn_forward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i),
-    "axipcg_nn_backward": ([_vp, _vp, _vp, _dp, _vp], _i),
+    "axipcg_nn_backward": ([_vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_nn_adam": ([_vp, _d, _d, _d, _d, _vp], _i),
-    "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
+    "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_profile_select": ([_vp, _i], _i),
     "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
@@ -307,10 +307,11 @@ def nn_forward(net: Net, u1, u2, b, kappa, guess, stream=None):
                                    _dev(kappa, "kappa"), _dev(guess, "guess"), _stream(stream)), "nn_forward")
 
 
-def nn_backward(net: Net, u1, u_target, stream=None, want_loss=True):
+def nn_backward(op: Op, net: Net, u1, u2, u_target, stream=None, want_loss=True):
     loss = np.zeros(1)
-    _check(lib().axipcg_nn_backward(net.handle, _dev(u1, "u1"), _dev(u_target, "u_target"),
-                                    _hp(loss) if want_loss else None, _stream(stream)), "nn_backward")
+    _check(lib().axipcg_nn_backward(op.handle, net.handle, _dev(u1, "u1"), _dev(u2, "u2"),
+                                    _dev(u_target, "u_target"), _hp(loss) if want_loss else None,
+                                    _stream(stream)), "nn_backward")
     return float(loss[0]) if want_loss else None
 
 
@@ -318,12 +319,18 @@ def nn_adam(net: Net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
     _check(lib().axipcg_nn_adam(net.handle, lr, beta1, beta2, eps, _stream(stream)), "nn_adam")
 
 
-def nn_guess(op: Op, net: Net, b, u1, u2, kappa, guess_scratch, x, stream=None, want_resid=True):
-    res = np.zeros(2)
+GUESS_PREV, GUESS_EXTRAP, GUESS_NN = 0, 1, 2
+
+
+def nn_guess(op: Op, net: Net, b, u1, u2, kappa, x, stream=None, want_info=True):
+    """Guarded guess into x; returns (residual norms [network, extrapolation,
+    previous], choice) when want_info (which synchronises), else None."""
+    phi = np.zeros(3)
+    choice = _i()
     _check(lib().axipcg_nn_guess(op.handle, net.handle, _dev(b, "b"), _dev(u1, "u1"), _dev(u2, "u2"),
-                                 _dev(kappa, "kappa"), _dev(guess_scratch, "guess_scratch"), _dev(x, "x"),
-                                 _hp(res) if want_resid else None, _stream(stream)), "nn_guess")
-    return (float(res[0]), float(res[1])) if want_resid else None
+                                 _dev(kappa, "kappa"), _dev(x, "x"), _hp(phi) if want_info else None,
+                                 ctypes.byref(choice) if want_info else None, _stream(stream)), "nn_guess")
+    return (phi, choice.value) if want_info else None
 
 
 def profile_select(op: Op, kernel: int):

@@ -4,10 +4,21 @@
 // A 6-layer 3x3 convolutional network, 32 channels wide, maps four input
 // channels of harmonic m -- u_{m-1}/s, u_{m-2}/s, b_m/s_b and (kappa-2.5)/1.5,
 // s = RMS(u_{m-1}), s_b = RMS(b_m) -- to a correction c, and the guess is
-// u_{m-1} + s c (a zero network returns the previous-harmonic guess).  ReLU
-// after every layer but the last, zero "same" padding.  Weights and
-// activations are BF16, products are accumulated in FP32 by MFMA
-// (v_mfma_f32_16x16x16_bf16); training keeps FP32 master weights with Adam.
+// 2 u_{m-1} - u_{m-2} + s c: the network corrects the linear extrapolation
+// in m, which is formed in FP64 outside it, so the network's own rounding
+// noise scales with the correction only.  ReLU after every layer but the
+// last, zero "same" padding.  Weights and activations are BF16, products are
+// accumulated in FP32 by MFMA (v_mfma_f32_16x16x16_bf16); training keeps FP32
+// master weights with Adam.
+//
+// Training minimises the energy norm of the guess error, (g - u)^T A (g - u),
+// the norm of CG's error bound; unlike an L2 loss it weighs the grid-scale
+// roughness a pointwise network produces, and unlike a residual loss (A^2
+// weighting) its gradients stay dominated by the learnable smooth part.  The
+// guard picks, among u_{m-1}, the extrapolation and the network guess, the
+// one with the smallest residual |b - A x|: PCG's stop test measures that
+// norm, and with a spectrally equivalent preconditioner the iterations a
+// start needs follow it.
 //
 // Every convolution is an implicit GEMM over 16-pixel tiles of one grid row:
 // M = pixels, N = output channels, K = 9 taps x input channels.  A wave holds
@@ -181,33 +192,50 @@ k_conv3(const bf16 *__restrict__ in, void *__restrict__ outp, const bf16x4 *__re
     }
 }
 
-// ---- loss: d = out - (u_target - u1)/s; gradient seed 2 d / P (channel 0) --
+// ---- loss: energy norm of the guess error ----------------------------------------
+// e = 2 u1 - u2 + s out - u_target, y = A e (A symmetric), L = e.y / (s^2 P);
+// dL/dout = 2 y / (s P), written as the BF16 gradient seed (channel 0 of 16).
+__device__ inline double guess_err(const float *out, const double *u1, const double *u2, const double *ut,
+                                   double s, size_t q)
+{
+    return 2.0 * u1[q] - u2[q] + s * (double)out[q] - ut[q];
+}
+
 __global__ void __launch_bounds__(256)
-k_nn_dout(const float *__restrict__ out, const double *__restrict__ ut, const double *__restrict__ u1,
-          bf16 *__restrict__ dpre, size_t n, const double *scal, double *red)
+k_nn_energy_seed(const float *__restrict__ out, const double *__restrict__ u1, const double *__restrict__ u2,
+                 const double *__restrict__ ut, const double *__restrict__ D, const double *__restrict__ CR,
+                 const double *__restrict__ CZ, int nr, int nz, bf16 *__restrict__ dpre, const double *scal,
+                 double *red)
 {
     __shared__ double sm[8];
-    const double is = 1.0 / scal[0];
-    const double g = 2.0 / (double)n;
+    const size_t n = (size_t)nr * nz;
+    const double s = scal[0];
+    const double g = 2.0 / (s * (double)n);
     double acc = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const double d = (double)out[e] - (ut[e] - u1[e]) * is;
-        acc += d * d;
+        const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
+        const double ee = guess_err(out, u1, u2, ut, s, e);
+        double y = D[e] * ee;
+        if (i + 1 < nr) y -= CR[e] * guess_err(out, u1, u2, ut, s, e + nz);
+        if (i > 0) y -= CR[e - nz] * guess_err(out, u1, u2, ut, s, e - nz);
+        if (k + 1 < nz) y -= CZ[e] * guess_err(out, u1, u2, ut, s, e + 1);
+        if (k > 0) y -= CZ[e - 1] * guess_err(out, u1, u2, ut, s, e - 1);
+        acc += ee * y;
         alignas(16) bf16 v[16] = {};
-        v[0] = to_bf16((float)(g * d));
+        v[0] = to_bf16((float)(g * y));
         uint4 *dst = reinterpret_cast<uint4 *>(dpre + e * 16);
         dst[0] = *reinterpret_cast<const uint4 *>(&v[0]);
         dst[1] = *reinterpret_cast<const uint4 *>(&v[8]);
     }
-    const double s = block_sum(acc, sm);
-    if (threadIdx.x == 0) red[2 * MAX_PARTIALS + blockIdx.x] = s;
+    const double t = block_sum(acc, sm);
+    if (threadIdx.x == 0) red[2 * MAX_PARTIALS + blockIdx.x] = t;
 }
 
 __global__ void __launch_bounds__(256) k_nn_loss_fin(const double *red, int nb, size_t n, double *scal)
 {
     __shared__ double sm[8];
     const double t = block_total(red + 2 * MAX_PARTIALS, nb, sm);
-    if (threadIdx.x == 0) scal[2] = t / (double)n;
+    if (threadIdx.x == 0) scal[2] = t / (scal[0] * scal[0] * (double)n);
 }
 
 // ---- weight gradient ------------------------------------------------------------
@@ -354,63 +382,96 @@ __global__ void k_pack_weights(const float *__restrict__ params, bf16 *__restric
         bias_p[c] = c < CO ? bias[c] : 0.f;
 }
 
-// guess = u1 + s * out
+// guess = 2 u1 - u2 + s * out
 __global__ void __launch_bounds__(256)
-k_nn_unpack(const double *__restrict__ u1, const float *__restrict__ out, double *__restrict__ g, size_t n,
+k_nn_unpack(const double *u1, const double *u2, const float *__restrict__ out, double *g, size_t n,
             const double *scal)
 {
     const double s = scal[0];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-        g[e] = u1[e] + s * (double)out[e];
+        g[e] = 2.0 * u1[e] - u2[e] + s * (double)out[e];
 }
 
-// ||b - A g||^2 and ||b - A u1||^2 partials
+// Guard: partial sums of |b - A x|^2 for the three candidates x_p = u1,
+// x_e = 2 u1 - u2 and x_n = x_e + s out (PCG's stop test measures this norm,
+// and a spectrally equivalent preconditioner reduces it at a roughly uniform
+// rate, so the smallest start needs the fewest iterations).
 __global__ void __launch_bounds__(256)
-k_nn_resid2(const double *__restrict__ b, const double *__restrict__ g, const double *__restrict__ u1,
-            const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
-            int nz, double *red)
+k_nn_res3(const double *__restrict__ b, const double *__restrict__ u1, const double *__restrict__ u2,
+          const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
+          const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
 {
     __shared__ double sm[8];
     const size_t n = (size_t)nr * nz;
-    double s1 = 0.0, s2 = 0.0;
+    const double s = scal[0];
+    double fp = 0.0, fe = 0.0, fn = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
-        double v1 = D[e] * g[e], v2 = D[e] * u1[e];
-        if (i + 1 < nr) { v1 -= CR[e] * g[e + nz]; v2 -= CR[e] * u1[e + nz]; }
-        if (i > 0) { v1 -= CR[e - nz] * g[e - nz]; v2 -= CR[e - nz] * u1[e - nz]; }
-        if (k + 1 < nz) { v1 -= CZ[e] * g[e + 1]; v2 -= CZ[e] * u1[e + 1]; }
-        if (k > 0) { v1 -= CZ[e - 1] * g[e - 1]; v2 -= CZ[e - 1] * u1[e - 1]; }
-        const double d1 = b[e] - v1, d2 = b[e] - v2;
-        s1 += d1 * d1;
-        s2 += d2 * d2;
+        double a1 = D[e] * u1[e], a2 = D[e] * u2[e], ao = D[e] * (double)out[e];
+        if (i + 1 < nr) {
+            const double c = CR[e];
+            a1 -= c * u1[e + nz]; a2 -= c * u2[e + nz]; ao -= c * (double)out[e + nz];
+        }
+        if (i > 0) {
+            const double c = CR[e - nz];
+            a1 -= c * u1[e - nz]; a2 -= c * u2[e - nz]; ao -= c * (double)out[e - nz];
+        }
+        if (k + 1 < nz) {
+            const double c = CZ[e];
+            a1 -= c * u1[e + 1]; a2 -= c * u2[e + 1]; ao -= c * (double)out[e + 1];
+        }
+        if (k > 0) {
+            const double c = CZ[e - 1];
+            a1 -= c * u1[e - 1]; a2 -= c * u2[e - 1]; ao -= c * (double)out[e - 1];
+        }
+        const double rp = b[e] - a1;
+        const double re = b[e] - (2.0 * a1 - a2);
+        const double rn = re - s * ao;
+        fp += rp * rp;
+        fe += re * re;
+        fn += rn * rn;
     }
-    const double t1 = block_sum(s1, sm);
-    const double t2 = block_sum(s2, sm);
+    const double tp = block_sum(fp, sm);
+    const double te = block_sum(fe, sm);
+    const double tn = block_sum(fn, sm);
     if (threadIdx.x == 0) {
-        red[blockIdx.x] = t1;
-        red[MAX_PARTIALS + blockIdx.x] = t2;
+        red[blockIdx.x] = tn;
+        red[MAX_PARTIALS + blockIdx.x] = te;
+        red[2 * MAX_PARTIALS + blockIdx.x] = tp;
     }
 }
 
-__global__ void __launch_bounds__(256) k_nn_resid_fin(const double *red, int nb, double *scal)
+// scal[3..5] = residual norms of (network, extrapolation, previous); scal[6]
+// = choice (0 previous, 1 extrapolation, 2 network): a candidate replaces a
+// simpler one only when its residual is strictly smaller (a NaN never does).
+__global__ void __launch_bounds__(256) k_nn_res_fin(const double *red, int nb, double *scal)
 {
     __shared__ double sm[8];
-    const double r1 = block_total(red, nb, sm);
-    const double r2 = block_total(red + MAX_PARTIALS, nb, sm);
+    const double fn = sqrt(block_total(red, nb, sm));
+    const double fe = sqrt(block_total(red + MAX_PARTIALS, nb, sm));
+    const double fp = sqrt(block_total(red + 2 * MAX_PARTIALS, nb, sm));
     if (threadIdx.x == 0) {
-        scal[3] = r1;
-        scal[4] = r2;
+        int c = 0;
+        double best = fp;
+        if (fe < best) { c = 1; best = fe; }
+        if (fn < best) c = 2;
+        scal[3] = fn;
+        scal[4] = fe;
+        scal[5] = fp;
+        scal[6] = (double)c;
     }
 }
 
-// x = guess if its residual is finite and smaller than that of u1, else u1
 __global__ void __launch_bounds__(256)
-k_nn_select(const double *__restrict__ g, const double *u1, double *x, size_t n, const double *scal)
+k_nn_select(const double *u1, const double *u2, const float *__restrict__ out, double *x, size_t n,
+            const double *scal)
 {
-    const double r1 = scal[3], r2 = scal[4];
-    const bool use = (r1 == r1) && r1 < r2;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-        x[e] = use ? g[e] : u1[e];
+    const int c = (int)scal[6];
+    const double s = scal[0];
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const double p = u1[e], q = u2[e];
+        x[e] = c == 0 ? p : (c == 1 ? 2.0 * p - q : 2.0 * p - q + s * (double)out[e]);
+    }
 }
 
 // ---- host helpers -------------------------------------------------------------------
@@ -480,11 +541,12 @@ void forward_impl(Net &n, const double *u1, const double *u2, const double *b, c
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-void backward_impl(Net &n, const double *ut, const double *u1, hipStream_t s)
+void backward_impl(Net &n, const Operator &op, const double *u1, const double *u2, const double *ut, hipStream_t s)
 {
     const size_t np = (size_t)n.nr * n.nz;
     const unsigned pb = pw_blocks(np);
-    hipLaunchKernelGGL(k_nn_dout, dim3(pb), dim3(256), 0, s, n.out, ut, u1, n.dpre[0], np, n.scal, n.red);
+    hipLaunchKernelGGL(k_nn_energy_seed, dim3(pb), dim3(256), 0, s, n.out, u1, u2, ut, op.D, op.CR, op.CZ, n.nr,
+                       n.nz, n.dpre[0], n.scal, n.red);
     hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(256), 0, s, n.red, (int)pb, np, n.scal);
     const int ntiles = (int)(np / 16);
     const dim3 cg(conv_blocks(ntiles)), cb(256);
@@ -622,19 +684,22 @@ int axipcg_nn_forward(axipcg_nn_t h, const double *u1, const double *u2, const d
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
         const size_t np = (size_t)n->nr * n->nz;
-        hipLaunchKernelGGL(k_nn_unpack, dim3(pw_blocks(np)), dim3(256), 0, s, u1, n->out, guess, np, n->scal);
+        hipLaunchKernelGGL(k_nn_unpack, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, n->out, guess, np, n->scal);
         AXI_CHECK_HIP(hipGetLastError());
         return AXIPCG_OK;
     });
 }
 
-int axipcg_nn_backward(axipcg_nn_t h, const double *u1, const double *u_target, double *loss_host, void *stream)
+int axipcg_nn_backward(axipcg_op_t hop, axipcg_nn_t h, const double *u1, const double *u2, const double *u_target,
+                       double *loss_host, void *stream)
 {
     return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(hop);
         Net *n = reinterpret_cast<Net *>(h);
-        AXI_REQUIRE(n && u1 && u_target, "NULL argument");
+        AXI_REQUIRE(op && n && u1 && u2 && u_target, "NULL argument");
+        AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
         hipStream_t s = (hipStream_t)stream;
-        backward_impl(*n, u_target, u1, s);
+        backward_impl(*n, *op, u1, u2, u_target, s);
         if (loss_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
@@ -663,30 +728,29 @@ int axipcg_nn_adam(axipcg_nn_t h, double lr, double beta1, double beta2, double 
 }
 
 int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const double *u1, const double *u2,
-                    const double *kappa, double *guess_scratch, double *x, double *resid_host, void *stream)
+                    const double *kappa, double *x, double *resid_host, int *choice_host, void *stream)
 {
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(hop);
         Net *n = reinterpret_cast<Net *>(h);
-        AXI_REQUIRE(op && n && b && u1 && u2 && kappa && guess_scratch && x, "NULL argument");
+        AXI_REQUIRE(op && n && b && u1 && u2 && kappa && x, "NULL argument");
         AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
-        AXI_REQUIRE(guess_scratch != x && guess_scratch != u1 && guess_scratch != b && guess_scratch != kappa,
-                    "guess_scratch aliases another argument");
+        AXI_REQUIRE(x != b && x != kappa, "x aliases b or kappa");
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
         const size_t np = (size_t)n->nr * n->nz;
         const unsigned pb = pw_blocks(np);
-        hipLaunchKernelGGL(k_nn_unpack, dim3(pb), dim3(256), 0, s, u1, n->out, guess_scratch, np, n->scal);
-        hipLaunchKernelGGL(k_nn_resid2, dim3(pb), dim3(256), 0, s, b, guess_scratch, u1, op->D, op->CR, op->CZ,
-                           op->nr, op->nz, n->red);
-        hipLaunchKernelGGL(k_nn_resid_fin, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal);
-        hipLaunchKernelGGL(k_nn_select, dim3(pb), dim3(256), 0, s, guess_scratch, u1, x, np, n->scal);
+        hipLaunchKernelGGL(k_nn_res3, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ, op->nr,
+                           op->nz, n->scal, n->red);
+        hipLaunchKernelGGL(k_nn_res_fin, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal);
+        hipLaunchKernelGGL(k_nn_select, dim3(pb), dim3(256), 0, s, u1, u2, n->out, x, np, n->scal);
         AXI_CHECK_HIP(hipGetLastError());
-        if (resid_host) {
-            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (resid_host || choice_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
-            resid_host[0] = std::sqrt(n->res_host[0]);
-            resid_host[1] = std::sqrt(n->res_host[1]);
+            if (resid_host)
+                for (int j = 0; j < 3; ++j) resid_host[j] = n->res_host[j];
+            if (choice_host) *choice_host = (int)n->res_host[3];
         }
         return AXIPCG_OK;
     });

@@ -1,0 +1,138 @@
+"""Laguerre series driver (§4.1, eqs. (34)-(35), alpha = 0).
+
+Harmonics are solved in order m = 0, 1, ...: the right-hand side of m needs
+the sum of all earlier solutions, kept on the device as two running sums
+(``axipcg_laguerre_rhs``), and each PCG run (§2.2) starts from a guess:
+
+* ``"zero"``  -- x0 = 0, as in the paper's experiments;
+* ``"prev"``  -- x0 = u_{m-1};
+* ``"nn"``    -- the learned guess with its guard (``axipcg_nn_guess``: the
+  one of u_{m-1}, 2 u_{m-1} - u_{m-2} and the network's correction of the
+  latter with the smallest residual), optionally trained online: after harmonic m is
+  solved, one backward pass against u_m and one Adam step.
+
+Every numerical step runs in the HIP library; this module only sequences the
+calls and owns the device buffers.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+
+from . import axipcg as ax
+
+
+@dataclass
+class SeriesStats:
+    iters: list = field(default_factory=list)
+    status: list = field(default_factory=list)
+    choice: list = field(default_factory=list)      # guard's pick (nn mode): 0 prev, 1 extrap, 2 network
+    resid: list = field(default_factory=list)       # guard's |b - A x| of (network, extrap, prev) (nn mode)
+    loss: list = field(default_factory=list)        # training loss per harmonic (when training)
+    gpu_ms: float = 0.0
+
+
+class LaguerreSeries:
+    """Device state of one series: running sums, right-hand side, the last two
+    solutions and the current one.  ``kappa`` (host [nr][nz]) feeds the
+    learned guess."""
+
+    def __init__(self, op: "ax.Op", g, src_i: int, src_k: int, kappa=None, coef=None):
+        import torch
+        self.torch = torch
+        self.op, self.g = op, [float(v) for v in g]
+        self.src_i, self.src_k = int(src_i), int(src_k)
+        shape = (op.nr, op.nz)
+        z = lambda: torch.zeros(shape, dtype=torch.float64, device="cuda")  # noqa: E731
+        self.S1, self.S2, self.b = z(), z(), z()
+        self.u1, self.u2, self.u = z(), z(), z()
+        self.coef = coef
+        self.kappa = None if kappa is None else torch.as_tensor(kappa, dtype=torch.float64).cuda().contiguous()
+        self.m = 0
+
+    def reset(self):
+        for t in (self.S1, self.S2, self.b, self.u1, self.u2, self.u):
+            t.zero_()
+        self.m = 0
+
+    def step(self, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats,
+             net=None, lr: float | None = None, want_info: bool = False):
+        """Solve harmonic self.m; afterwards self.u1 holds u_m."""
+        m = self.m
+        ax.laguerre_rhs(self.op, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
+                        u_prev=(self.u1 if m > 0 else None), coef=self.coef)
+        if guess == "zero":
+            self.u.zero_()
+        elif guess == "prev":
+            self.u.copy_(self.u1)
+        elif guess == "nn":
+            if net is None or self.kappa is None:
+                raise ValueError("nn guess needs a network and kappa")
+            r = ax.nn_guess(self.op, net, self.b, self.u1, self.u2, self.kappa, self.u, want_info=want_info)
+            if r is not None:
+                stats.resid.append(r[0])
+                stats.choice.append(r[1])
+        else:
+            raise ValueError(f"unknown guess {guess!r}")
+        st = ax.pcg_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
+        stats.iters.append(st["iters"])
+        stats.status.append(st["code"])
+        if guess == "nn" and lr is not None:
+            stats.loss.append(ax.nn_backward(self.op, net, self.u1, self.u2, self.u, want_loss=want_info))
+            ax.nn_adam(net, lr=lr)
+        # rotate: u2 <- u1 <- u
+        self.u2, self.u1, self.u = self.u1, self.u, self.u2
+        self.m += 1
+
+    def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000, net=None,
+            lr: float | None = None, want_info: bool = False) -> SeriesStats:
+        """Solve the next n harmonics, timed with events on the current stream."""
+        torch = self.torch
+        stats = SeriesStats()
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            self.step(guess, prec, rtol, maxit, stats, net=net, lr=lr, want_info=want_info)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        stats.gpu_ms = e0.elapsed_time(e1)
+        return stats
+
+
+def train_online(net, problems, n_harm: int, prec: int, lr: float = 1e-3, rtol: float = 1e-10,
+                 maxit: int = 1000):
+    """Train the learned guess on the series of each problem in turn.
+
+    ``problems`` yields (op, g, src_i, src_k, kappa).  Returns (seconds,
+    per-problem mean iterations, last losses)."""
+    t0 = time.perf_counter()
+    iters, losses = [], []
+    for op, g, si, sk, kappa in problems:
+        s = LaguerreSeries(op, g, si, sk, kappa=kappa)
+        st = s.run(n_harm, "nn", prec, rtol=rtol, maxit=maxit, net=net, lr=lr, want_info=True)
+        iters.append(sum(st.iters) / len(st.iters))
+        losses.append(st.loss[-1] if st.loss else None)
+    return time.perf_counter() - t0, iters, losses
+
+
+# layer shapes of the learned guess (cin, cout) and its flat parameter layout:
+# per layer W[t][ci][co] then bias[co]
+NN_LAYERS = ((4, 32), (32, 32), (32, 32), (32, 32), (32, 32), (32, 1))
+
+
+def nn_init_params(seed: int, last_zero: bool = True):
+    """He-normal weights and zero biases (float32); with a zero last layer the
+    network starts as the previous-harmonic guess."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    parts = []
+    for l, (ci, co) in enumerate(NN_LAYERS):
+        w = rng.standard_normal(9 * ci * co) * np.sqrt(2.0 / (9 * ci))
+        if l == len(NN_LAYERS) - 1 and last_zero:
+            w[:] = 0.0
+        parts += [w, np.zeros(co)]
+    p = np.concatenate(parts).astype(np.float32)
+    assert p.size == ax.nn_num_params()
+    return p

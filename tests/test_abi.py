@@ -113,7 +113,7 @@ def test_nn_entry_points_validate_before_device_work(ax):
     assert "non-finite" in ax.last_error()
     assert lib.axipcg_nn_create(8, 64, None, ctypes.byref(out)) == ax.EINVAL
     assert lib.axipcg_nn_forward(None, None, None, None, None, None, None) == ax.EINVAL
-    assert lib.axipcg_nn_backward(None, None, None, None, None) == ax.EINVAL
+    assert lib.axipcg_nn_backward(None, None, None, None, None, None, None) == ax.EINVAL
     assert lib.axipcg_nn_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == ax.EINVAL
     assert lib.axipcg_nn_guess(None, None, None, None, None, None, None, None, None, None) == ax.EINVAL
     lib.axipcg_nn_destroy(None)  # NULL-safe

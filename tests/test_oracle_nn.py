@@ -1,19 +1,37 @@
 """Pins of the learned-guess oracle (oracle/nn.py) against things other than itself.
 
 * bfloat16 rounding against torch's own float32 -> bfloat16 conversion;
-* the FP64 network against torch.nn.functional.conv2d, and its gradients
+* the FP64 network against torch.nn.functional.conv2d, and the gradients of
+  its energy-norm loss (matrix from the independent assembly in _assembly.py)
   against torch autograd and against central finite differences;
 * Adam against torch.optim.Adam;
-* special cases: a zero last layer returns u_{m-1} exactly; the rounded
+* the guard's pick against the error seen through A from a direct solve;
+* special cases: a zero last layer returns the extrapolation exactly; the rounded
   network stays within bfloat16's error of the FP64 one; every stored
   activation is a bfloat16 value.
 """
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 import torch
 
 from oracle import nn as onn
 from synth import nn_example
+from tests._assembly import assemble
+
+
+def _matrix(ex):
+    """Scheme matrix for the example's kappa (independent assembly), q = 1."""
+    kappa = ex["kappa"]
+    nr, nz = kappa.shape
+    kr = np.empty_like(kappa)
+    kr[:-1] = 0.5 * (kappa[:-1] + kappa[1:])
+    kr[-1] = kappa[-1]
+    kz = np.empty((nr, nz + 1))
+    kz[:, 1:-1] = 0.5 * (kappa[:, :-1] + kappa[:, 1:])
+    kz[:, 0], kz[:, -1] = kappa[:, 0], kappa[:, -1]
+    A = assemble(kr, kz, np.ones_like(kappa))
+    return A, (lambda e: (A @ e.ravel()).reshape(e.shape))
 
 
 def _torch_net(params):
@@ -69,19 +87,22 @@ def test_forward_fp64_matches_torch_conv2d():
     ws = _torch_net(params)
     out = _torch_forward(ws, x).detach().numpy()
     np.testing.assert_allclose(cache["out"], out, rtol=1e-12, atol=1e-12 * np.abs(out).max())
-    np.testing.assert_allclose(guess, ex["u1"] + s * out, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(guess, 2 * ex["u1"] - ex["u2"] + s * out, rtol=1e-12, atol=1e-14)
 
 
 def test_backward_fp64_matches_torch_autograd():
     ex = nn_example(10, 16, seed=6)
+    A, apply_A = _matrix(ex)
     params = onn.init_params(8, last_zero=False)
     _, cache = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
-    loss, grads = onn.backward(params, cache, ex["u1"], ex["ut"])
+    loss, grads = onn.backward(params, cache, apply_A, ex["ut"])
     x, s = onn.inputs(ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
     ws = _torch_net(params)
     out = _torch_forward(ws, x)
-    target = torch.tensor((ex["ut"] - ex["u1"]) / s)
-    tl = torch.mean((out - target) ** 2)
+    guess = torch.tensor(2 * ex["u1"] - ex["u2"]) + s * out
+    e = (guess - torch.tensor(ex["ut"])).reshape(-1)
+    tA = torch.tensor(A.toarray())
+    tl = (e @ (tA @ e)) / (s * s * e.numel())
     tl.backward()
     assert loss == pytest.approx(tl.item(), rel=1e-12)
     ref = _flat_grads(ws)
@@ -90,13 +111,14 @@ def test_backward_fp64_matches_torch_autograd():
 
 def test_backward_fp64_finite_differences():
     ex = nn_example(8, 12, seed=9)
+    _, apply_A = _matrix(ex)
     params = onn.init_params(10, last_zero=False).astype(np.float64)
     _, cache = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
-    _, grads = onn.backward(params, cache, ex["u1"], ex["ut"])
+    _, grads = onn.backward(params, cache, apply_A, ex["ut"])
 
     def loss_at(p):
         _, c = onn.forward(p, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
-        return onn.backward(p, c, ex["u1"], ex["ut"])[0]
+        return onn.backward(p, c, apply_A, ex["ut"])[0]
 
     rng = np.random.default_rng(0)
     idx = list(rng.choice(onn.N_PARAMS, 24, replace=False))
@@ -107,15 +129,35 @@ def test_backward_fp64_finite_differences():
         pp[e] += h
         pm[e] -= h
         fd = (loss_at(pp) - loss_at(pm)) / (2 * h)
-        assert fd == pytest.approx(grads[e], rel=1e-5, abs=1e-9), e
+        assert fd == pytest.approx(grads[e], rel=1e-5, abs=1e-9 * np.abs(grads).max()), e
 
 
-def test_zero_last_layer_returns_previous_harmonic():
+def test_guard_picks_smallest_residual():
+    ex = nn_example(12, 16, seed=17)
+    A, apply_A = _matrix(ex)
+    ustar = spla.spsolve(A.tocsc(), ex["b"].ravel()).reshape(ex["b"].shape)
+    rng = np.random.default_rng(4)
+    for trial in range(6):
+        u1 = ustar + rng.standard_normal(ustar.shape) * 10.0 ** rng.uniform(-3, 0)
+        u2 = ustar + rng.standard_normal(ustar.shape) * 10.0 ** rng.uniform(-3, 0)
+        guess = ustar + rng.standard_normal(ustar.shape) * 10.0 ** rng.uniform(-3, 0)
+        res, pick = onn.guard(ex["b"], u1, u2, guess, apply_A)
+        # A (x - u*) = A x - b: the residual is the error seen through A
+        cands = [u1, 2 * u1 - u2, guess]
+        ref = [np.linalg.norm(A @ (x - ustar).ravel()) for x in cands]
+        assert pick == int(np.argmin(ref))
+        np.testing.assert_allclose((res[2], res[1], res[0]), ref, rtol=1e-8)
+    # ties keep the simpler candidate
+    res, pick = onn.guard(ex["b"], ustar, ustar, ustar, apply_A)
+    assert pick == 0
+
+
+def test_zero_last_layer_returns_extrapolation():
     ex = nn_example(9, 14, seed=11)
     params = onn.init_params(12, last_zero=True)
     for bf in (False, True):
         guess, _ = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=bf)
-        np.testing.assert_array_equal(guess, ex["u1"])
+        np.testing.assert_array_equal(guess, 2 * ex["u1"] - ex["u2"])
 
 
 def test_rounded_network_close_to_fp64_and_on_bf16_grid():
@@ -128,8 +170,16 @@ def test_rounded_network_close_to_fp64_and_on_bf16_grid():
     assert 1e-5 < rel < 5e-2
     for a in c16["acts"]:
         np.testing.assert_array_equal(onn.bf16_round(a), a)
-    l64, gr64 = onn.backward(params, c64, ex["u1"], ex["ut"])
-    l16, gr16 = onn.backward(params, c16, ex["u1"], ex["ut"])
+    # The energy loss weighs the output's grid-scale rounding noise by A, so the
+    # gradients agree to bfloat16 accuracy when the correction is small next to
+    # the extrapolation error (the regime the guess works in).
+    params[onn.OFFSETS[5]:onn.OFFSETS[5] + 9 * 32] *= 0.01
+    _, c64 = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
+    _, c16 = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=True)
+    _, apply_A = _matrix(ex)
+    l64, gr64 = onn.backward(params, c64, apply_A, ex["ut"])
+    l16, gr16 = onn.backward(params, c16, apply_A, ex["ut"])
+    assert l16 == pytest.approx(l64, rel=1e-3)
     assert np.linalg.norm(gr16 - gr64) / np.linalg.norm(gr64) < 5e-2
 
 
