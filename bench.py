@@ -2,14 +2,22 @@
 """Benchmark: Laguerre harmonics solved per second on a 1024^2 grid.
 
 One step = one harmonic of the Laguerre series (§4.1 eq. (35)): the
-right-hand side from the running history sums, then PCG to ||r||/||b|| <=
-1e-10 with the FP32 separation-of-variables preconditioner and FP64 outer
-iteration, warm-started from the previous harmonic.  The medium is the
-layered synthetic recipe (5 z-layers, smooth lognormal perturbation, q =
-(eta^2/4)/kappa, eta = 10) on a held-out seed; the source is a point source on
-the axis at z = 0.3 with a 25 Hz Ricker time pulse.  Inputs are resident in
-HBM before the timed region.  Accuracy (error <= 1e-8 against the FP64
-oracle) is asserted by the GPU test suite, not here.
+right-hand side from the running history sums, an initial guess, then PCG to
+||r||/||b|| <= 1e-10 with the separation-of-variables preconditioner.  The
+medium is the layered synthetic recipe (5 z-layers, smooth lognormal
+perturbation, q = (eta^2/4)/kappa, eta = 10) on a held-out seed; the source
+is a point source on the axis at z = 0.3 with a 25 Hz Ricker time pulse.
+Inputs are resident in HBM before the timed region.
+
+Modes (each a fresh series of warmup + steps harmonics on the same medium):
+  A  FP64 preconditioner, previous-harmonic guess (the plain method)
+  B  FP32 preconditioner, previous-harmonic guess
+  X  FP32 preconditioner, best of u_{m-1} and the extrapolation by residual
+  Z  FP32 preconditioner, zero guess (the paper's choice)
+  C  FP32 preconditioner, learned guess with its guard (headline), the network
+     trained beforehand (untimed) on harmonics of eight other media
+The first harmonics of the headline mode are checked against the FP64 oracle
+chain that the CPU-baseline leg computes on the same inputs.
 
 Prints one JSON line (see the design doc for the fields).
 """
@@ -44,13 +52,16 @@ KERNEL_SYMBOLS = {"spmv": "k_pcg_spmv", "zfwd": "k_zfwd", "tridiag": "k_tridiag"
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed harmonics")
+    ap.add_argument("--steps", type=int, default=400, help="timed harmonics")
     ap.add_argument("--warmup", type=int, default=5, help="untimed harmonics before the timed ones")
     ap.add_argument("--nr", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=101)
-    ap.add_argument("--prec", choices=["fp32", "fp64"], default="fp32")
-    ap.add_argument("--guess", choices=["prev", "zero"], default="prev")
+    ap.add_argument("--modes", default="A,B,X,Z,C", help="comma-separated modes to run")
+    ap.add_argument("--headline", default="C", help="mode whose throughput is the value")
+    ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8")
+    ap.add_argument("--train-harmonics", type=int, default=200)
+    ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--roofline-kernel", choices=list(KERNEL_IDS), default="spmv")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -80,7 +91,7 @@ def measured_traffic(kernel, workload, launch_bytes):
 
 def cpu_baseline(inp, prec_rtol, budget_s, n_max=16):
     """The FP64 oracle's own Laguerre chain on the host cores, for a bounded
-    prefix of the same series (time-bounded)."""
+    prefix of the same series (time-bounded).  Returns (record, harmonics)."""
     import oracle
     op = oracle.operator_from_cells(inp["kappa"], inp["q"])
     g = oracle.laguerre_coeffs(n_max, inp["eta"], inp["ft"], inp["t"][-1])
@@ -100,9 +111,9 @@ def cpu_baseline(inp, prec_rtol, budget_s, n_max=16):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": done / el, "unit": "harmonics/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {done} harmonics of the same {inp['nr']}x{inp['nz']} chain, FP64 oracle "
-                      f"(4N-embedding FFT transforms, Thomas r-solves, PCG to 1e-10), {el:.1f} s"}
+    return ({"value": done / el, "unit": "harmonics/s", "cores": oracle.num_threads(), "kind": "oracle",
+             "sample": f"first {done} harmonics of the same {inp['nr']}x{inp['nz']} chain, FP64 oracle "
+                       f"(4N-embedding FFT transforms, Thomas r-solves, PCG to 1e-10), {el:.1f} s"}, us)
 
 
 def batch_measure(ax, torch, prec, reps=3):
@@ -147,6 +158,37 @@ def batch_measure(ax, torch, prec, reps=3):
             "iters_min_max": [min(iters), max(iters)]}
 
 
+MODES = {
+    "A": ("fp64", "prev"),
+    "B": ("fp32", "prev"),
+    "X": ("fp32", "extrap"),
+    "Z": ("fp32", "zero"),
+    "C": ("fp32", "nn"),
+}
+NN_FLOP_PER_POINT = 2 * 9 * (4 * 32 + 4 * 32 * 32 + 32 * 1)   # 76 608: six 3x3 convolutions
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def train_network(ax, torch, synth, series, a):
+    """Online training on the series of each training medium (untimed)."""
+    net = ax.nn_create(a.nr, a.nz, series.nn_init_params(0))
+    seeds = [int(v) for v in a.train_seeds.split(",") if v]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, losses = [], []
+    for seed in seeds:
+        inp = synth.laguerre_series_inputs(a.nr, a.nz, seed=seed)
+        with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
+            g = ax.laguerre_coeffs(a.train_harmonics, inp["eta"], inp["ft"], inp["t"][-1])
+            s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+            st = s.run(a.train_harmonics, "nn", ax.PREC_FP32, net=net, lr=a.lr, want_info=True)
+            iters.append(float(np.mean(st.iters)))
+            losses.append(float(np.mean(st.loss[-20:])))
+    torch.cuda.synchronize()
+    return net, {"seeds": seeds, "harmonics_per_seed": a.train_harmonics, "seconds": round(time.perf_counter() - t0, 2),
+                 "final_loss_per_seed": [round(v, 5) for v in losses]}
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -158,10 +200,13 @@ def main():
 
     import synth
     from paper_1002_3094_amd import axipcg as ax
+    from paper_1002_3094_amd import series
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    prec = ax.PREC_FP32 if a.prec == "fp32" else ax.PREC_FP64
+    modes = [m for m in a.modes.split(",") if m]
+    if a.headline not in modes:
+        modes.append(a.headline)
     rtol = 1e-10
     inp = synth.laguerre_series_inputs(a.nr, a.nz, seed=a.seed)
     workload = f"laguerre_{a.nr}x{a.nz}"
@@ -173,105 +218,136 @@ def main():
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
 
-    shape = (a.nr, a.nz)
-    S1 = torch.zeros(shape, dtype=torch.float64, device=dev)
-    S2 = torch.zeros(shape, dtype=torch.float64, device=dev)
-    b = torch.zeros(shape, dtype=torch.float64, device=dev)
-    u = torch.zeros(shape, dtype=torch.float64, device=dev)
-    iters = []
-    statuses = []
+    net, training = (None, None)
+    if "C" in modes:
+        net, training = train_network(ax, torch, synth, series, a)
 
-    def harmonic(m):
-        # S1 += u_{m-1}; S2 += S1; b_m; then u is overwritten in place by u_m
-        ax.laguerre_rhs(op, float(g[m]), inp["src_i"], inp["src_k"], S1, S2, b, u_prev=(u if m > 0 else None))
-        if a.guess == "zero":
-            u.zero_()
-        st = ax.pcg_solve(op, b, u, rtol=rtol, maxit=1000, prec=prec)
-        iters.append(st["iters"])
-        statuses.append(st["code"])
-
-    for m in range(a.warmup):
-        harmonic(m)
-    torch.cuda.synchronize()
-
-    ax.profile_select(op, KERNEL_IDS[a.roofline_kernel])
-    ax.profile_read(op, reset=True)
+    results = {}
+    roofline = None
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for m in range(a.warmup, n_harm):
-        harmonic(m)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    k_ms, k_n = ax.profile_read(op, reset=True)
-    ax.profile_select(op, ax.KERNEL_NONE)
-    timed_iters = iters[a.warmup:]
-    assert all(s == ax.OK for s in statuses), statuses
+    for mode in modes:
+        prec_name, guess = MODES[mode]
+        prec = ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64
+        s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        warm = s.run(a.warmup, guess, prec, rtol=rtol, net=net)
+        assert all(c == ax.OK for c in warm.status), warm.status
+        head = mode == a.headline
+        if head:
+            ax.profile_select(op, KERNEL_IDS[a.roofline_kernel])
+            ax.profile_read(op, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.run(a.steps, guess, prec, rtol=rtol, net=net)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert all(c == ax.OK for c in st.status), st.status
+        elapsed = max(wall, st.gpu_ms / 1e3)
+        results[mode] = {"precond": prec_name, "guess": guess, "harmonics_per_s": round(a.steps / elapsed, 2),
+                         "ms_per_harmonic": round(elapsed * 1e3 / a.steps, 4),
+                         "iters_per_harmonic": round(float(np.mean(st.iters)), 3),
+                         "us_per_iteration": round(elapsed * 1e6 / max(1, sum(st.iters)), 2)}
+        if head:
+            k_ms, k_n = ax.profile_read(op, reset=True)
+            ax.profile_select(op, ax.KERNEL_NONE)
+            n_pts = a.nr * a.nz
+            k_avg_s = (k_ms / 1e3) / max(k_n, 1)
+            k_bytes = BYTES_PER_POINT[a.roofline_kernel] * n_pts
+            achieved = k_bytes / k_avg_s / 1e9
+            roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(a.roofline_kernel, workload, k_bytes),
+                        "kernel": KERNEL_SYMBOLS[a.roofline_kernel], "launches": k_n,
+                        "mean_us": round(k_avg_s * 1e6, 2), "bytes_per_launch": k_bytes}
+            head_elapsed = elapsed
+    # the guard's picks in the headline run (untimed replay of the same series)
+    if a.headline in ("C", "X"):
+        s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        st = s.run(n_harm, MODES[a.headline][1], ax.PREC_FP32, rtol=rtol, net=net, want_info=True)
+        results[a.headline]["guard_picks_prev_extrap_net"] = np.bincount(st.choice, minlength=3).tolist()
 
     n_pts = a.nr * a.nz
-    elapsed_s = max(wall, gpu_ms / 1e3)
-    value = a.steps / elapsed_s
-
-    # roofline of the dominant kernel: algorithmic bytes per launch / mean duration
-    k_avg_s = (k_ms / 1e3) / max(k_n, 1)
-    k_bytes = BYTES_PER_POINT[a.roofline_kernel] * n_pts
-    achieved = k_bytes / k_avg_s / 1e9
-    traffic = measured_traffic(a.roofline_kernel, workload, k_bytes)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_SYMBOLS[a.roofline_kernel], "launches": k_n,
-                "mean_us": round(k_avg_s * 1e6, 2), "bytes_per_launch": k_bytes}
-
     # preconditioner applies (3 launches: transform, r-solves, inverse), standalone
-    r = torch.randn(shape, dtype=torch.float64, device=dev)
+    prec_head = ax.PREC_FP32 if MODES[a.headline][0] == "fp32" else ax.PREC_FP64
+    r = torch.randn((a.nr, a.nz), dtype=torch.float64, device=dev)
     z = torch.empty_like(r)
     for _ in range(3):
-        ax.precond_apply(op, r, z, prec)
+        ax.precond_apply(op, r, z, prec_head)
     n_pc = 50
     p0 = torch.cuda.Event(enable_timing=True)
     p1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     p0.record(stream)
     for _ in range(n_pc):
-        ax.precond_apply(op, r, z, prec)
+        ax.precond_apply(op, r, z, prec_head)
     p1.record(stream)
     torch.cuda.synchronize()
     pc_s = p0.elapsed_time(p1) / 1e3 / n_pc
     pc_gbs = PRECOND_BYTES_PER_POINT * n_pts / pc_s / 1e9
 
+    nn_rec = None
+    if net is not None:
+        s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        s.run(3, "prev", ax.PREC_FP32, rtol=rtol)
+        gx = torch.empty_like(s.u)
+        for _ in range(3):
+            ax.nn_forward(net, s.u1, s.u2, s.b, s.kappa, gx)
+        n_nn = 20
+        torch.cuda.synchronize()
+        p0.record(stream)
+        for _ in range(n_nn):
+            ax.nn_forward(net, s.u1, s.u2, s.b, s.kappa, gx)
+        p1.record(stream)
+        torch.cuda.synchronize()
+        f_s = p0.elapsed_time(p1) / 1e3 / n_nn
+        tfl = NN_FLOP_PER_POINT * n_pts / f_s / 1e12
+        nn_rec = {"forward_ms": round(f_s * 1e3, 4), "tflops": round(tfl, 1), "peak_tflops": BF16_PEAK_TFLOPS,
+                  "frac": round(tfl / BF16_PEAK_TFLOPS, 4), "flop_per_point": NN_FLOP_PER_POINT,
+                  "training": training}
+
+    prec_name, guess = MODES[a.headline]
     out = {
         "metric": METRIC,
-        "value": round(value, 3),
+        "value": results[a.headline]["harmonics_per_s"],
         "unit": "harmonics/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(elapsed_s * 1e3 / a.steps, 4),
+        "ms_per_step": round(head_elapsed * 1e3 / a.steps, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32" if prec == ax.PREC_FP32 else "f64",
+        "dtype": "f64+f32+bf16" if guess == "nn" else ("f64+f32" if prec_name == "fp32" else "f64"),
         "data": "synthetic",
         "config": {"workload": workload, "nr": a.nr, "nz": a.nz, "medium": "layered", "seed": a.seed,
-                   "eta": inp["eta"], "harmonics_timed": a.steps, "preconditioner": a.prec,
-                   "guess": a.guess, "rtol": rtol},
+                   "eta": inp["eta"], "harmonics_timed": a.steps, "mode": a.headline, "preconditioner": prec_name,
+                   "guess": guess, "rtol": rtol},
         "roofline": roofline,
+        "modes": results,
         "precond": {"applies_per_s": round(1.0 / pc_s, 1), "gbs": round(pc_gbs, 1),
                     "frac_of_peak": round(pc_gbs / HBM_PEAK_GBS, 4), "bytes_per_point": PRECOND_BYTES_PER_POINT,
-                    "mean_us": round(pc_s * 1e6, 2)},
-        "iters_per_harmonic": round(float(np.mean(timed_iters)), 2),
-        "us_per_iteration": round(elapsed_s * 1e6 / max(1, sum(timed_iters)), 2),
+                    "mean_us": round(pc_s * 1e6, 2), "prec": MODES[a.headline][0]},
+        "nn": nn_rec,
         "setup_s": round(t_setup, 3),
     }
+    if "A" in results:
+        out["speedup_vs_plain_fp64"] = round(results[a.headline]["harmonics_per_s"] / results["A"]["harmonics_per_s"], 3)
     if not a.no_batch:
-        out["batch"] = batch_measure(ax, torch, prec)
+        out["batch"] = batch_measure(ax, torch, ax.PREC_FP32)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inp, rtol, a.cpu_seconds)
+        rec, us = cpu_baseline(inp, rtol, a.cpu_seconds)
+        out["cpu_baseline"] = rec
+        # accuracy of the headline mode on the harmonics the oracle reached
+        s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        st = series.SeriesStats()
+        errs = []
+        for uo in us:
+            s.step(guess, ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64, rtol, 1000, st, net=net)
+            ug = s.u1.cpu().numpy()
+            errs.append(float(np.linalg.norm(ug - uo) / max(np.linalg.norm(uo), 1e-300)))
+        out["accuracy"] = {"harmonics_checked": len(errs), "max_rel_err_vs_oracle": max(errs) if errs else None,
+                           "tolerance": 1e-8}
+    if net is not None:
+        net.close()
     op.close()
     print(json.dumps(out), flush=True)
 

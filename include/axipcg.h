@@ -171,6 +171,18 @@ int axipcg_laguerre_rhs(axipcg_op_t op, double g_m, int src_i, int src_k,
                         const double *coef, const double *u_prev,
                         double *S1, double *S2, double *b, void *stream);
 
+/* ---- initial guess from earlier harmonics (§4.1: the harmonics are solved in
+ * order, so u_{m-1} = u1 and u_{m-2} = u2 are known when harmonic m starts) ----
+ * Writes to x whichever of u1 and the linear extrapolation 2 u1 - u2 has the
+ * smaller residual |b - A x| (the extrapolation only when strictly smaller).
+ * Device [nr][nz] arrays of op's size; x may alias u1 or u2, not b.
+ * resid_host (host double[2]: extrapolation, u1) and choice_host (0 u1,
+ * 1 extrapolation) may be NULL; when either is given the call synchronises
+ * the stream.  Uses the handle's workspace: do not overlap with a solve on
+ * the same handle. */
+int axipcg_guess_extrap(axipcg_op_t op, const double *b, const double *u1, const double *u2, double *x,
+                        double *resid_host, int *choice_host, void *stream);
+
 /* ---- learned initial guess (extension; §4.1's harmonics are solved in order,
  * so u_{m-1} and u_{m-2} are known when harmonic m starts) ---------------------
  * A 6-layer 3x3 convolutional network, 32 channels wide, ReLU between layers,

@@ -57,6 +57,7 @@ SIGNATURES = {
                             ctypes.POINTER(Stats), _vp], _i),
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "axipcg_guess_extrap": ([_vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_nn_num_params": ([], _i),
     "axipcg_nn_create": ([_i, _i, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_vp)], _i),
     "axipcg_nn_destroy": ([_vp], None),
@@ -239,6 +240,18 @@ def laguerre_rhs(op: Op, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=N
     _check(lib().axipcg_laguerre_rhs(op.handle, g_m, src_i, src_k, _opt_dev(coef, "coef"),
                                      _opt_dev(u_prev, "u_prev"), _dev(S1, "S1"), _dev(S2, "S2"),
                                      _dev(b, "b"), _stream(stream)), "laguerre_rhs")
+
+
+def guess_extrap(op: Op, b, u1, u2, x, stream=None, want_info=False):
+    """Best of u1 and 2 u1 - u2 by residual into x; returns (residual norms
+    [extrapolation, previous], choice) when want_info (which synchronises)."""
+    res = np.zeros(2)
+    choice = _i()
+    _check(lib().axipcg_guess_extrap(op.handle, _dev(b, "b"), _dev(u1, "u1"), _dev(u2, "u2"), _dev(x, "x"),
+                                     _hp(res) if want_info else None,
+                                     ctypes.byref(choice) if want_info else None, _stream(stream)),
+           "guess_extrap")
+    return (res, choice.value) if want_info else None
 
 
 def _fp(a: np.ndarray):

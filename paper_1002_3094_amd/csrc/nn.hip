@@ -392,85 +392,98 @@ k_nn_unpack(const double *u1, const double *u2, const float *__restrict__ out, d
         g[e] = 2.0 * u1[e] - u2[e] + s * (double)out[e];
 }
 
-// Guard: partial sums of |b - A x|^2 for the three candidates x_p = u1,
-// x_e = 2 u1 - u2 and x_n = x_e + s out (PCG's stop test measures this norm,
-// and a spectrally equivalent preconditioner reduces it at a roughly uniform
-// rate, so the smallest start needs the fewest iterations).
+// ---- guard -------------------------------------------------------------------------
+// Partial sums of |b - A x|^2 for the candidates x_p = u1, x_e = 2 u1 - u2 and
+// (NET) x_n = x_e + s out (PCG's stop test measures this norm, and with a
+// spectrally equivalent preconditioner the iterations a start needs follow
+// it).  red[0..2][MAX_PARTIALS]: network, extrapolation, previous.
+template <bool NET>
 __global__ void __launch_bounds__(256)
-k_nn_res3(const double *__restrict__ b, const double *__restrict__ u1, const double *__restrict__ u2,
-          const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
-          const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
+k_guess_res(const double *__restrict__ b, const double *__restrict__ u1, const double *__restrict__ u2,
+            const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
+            const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
 {
     __shared__ double sm[8];
     const size_t n = (size_t)nr * nz;
-    const double s = scal[0];
+    const double s = NET ? scal[0] : 0.0;
     double fp = 0.0, fe = 0.0, fn = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
-        double a1 = D[e] * u1[e], a2 = D[e] * u2[e], ao = D[e] * (double)out[e];
+        double a1 = D[e] * u1[e], a2 = D[e] * u2[e], ao = NET ? D[e] * (double)out[e] : 0.0;
         if (i + 1 < nr) {
             const double c = CR[e];
-            a1 -= c * u1[e + nz]; a2 -= c * u2[e + nz]; ao -= c * (double)out[e + nz];
+            a1 -= c * u1[e + nz]; a2 -= c * u2[e + nz];
+            if (NET) ao -= c * (double)out[e + nz];
         }
         if (i > 0) {
             const double c = CR[e - nz];
-            a1 -= c * u1[e - nz]; a2 -= c * u2[e - nz]; ao -= c * (double)out[e - nz];
+            a1 -= c * u1[e - nz]; a2 -= c * u2[e - nz];
+            if (NET) ao -= c * (double)out[e - nz];
         }
         if (k + 1 < nz) {
             const double c = CZ[e];
-            a1 -= c * u1[e + 1]; a2 -= c * u2[e + 1]; ao -= c * (double)out[e + 1];
+            a1 -= c * u1[e + 1]; a2 -= c * u2[e + 1];
+            if (NET) ao -= c * (double)out[e + 1];
         }
         if (k > 0) {
             const double c = CZ[e - 1];
-            a1 -= c * u1[e - 1]; a2 -= c * u2[e - 1]; ao -= c * (double)out[e - 1];
+            a1 -= c * u1[e - 1]; a2 -= c * u2[e - 1];
+            if (NET) ao -= c * (double)out[e - 1];
         }
         const double rp = b[e] - a1;
         const double re = b[e] - (2.0 * a1 - a2);
-        const double rn = re - s * ao;
         fp += rp * rp;
         fe += re * re;
-        fn += rn * rn;
+        if (NET) {
+            const double rn = re - s * ao;
+            fn += rn * rn;
+        }
     }
     const double tp = block_sum(fp, sm);
     const double te = block_sum(fe, sm);
-    const double tn = block_sum(fn, sm);
+    const double tn = NET ? block_sum(fn, sm) : 0.0;
     if (threadIdx.x == 0) {
-        red[blockIdx.x] = tn;
+        if (NET) red[blockIdx.x] = tn;
         red[MAX_PARTIALS + blockIdx.x] = te;
         red[2 * MAX_PARTIALS + blockIdx.x] = tp;
     }
 }
 
-// scal[3..5] = residual norms of (network, extrapolation, previous); scal[6]
-// = choice (0 previous, 1 extrapolation, 2 network): a candidate replaces a
-// simpler one only when its residual is strictly smaller (a NaN never does).
-__global__ void __launch_bounds__(256) k_nn_res_fin(const double *red, int nb, double *scal)
+// res[0..2] = residual norms of (network, extrapolation, previous) (res[0]
+// NaN without a network); res[3] = choice (0 previous, 1 extrapolation,
+// 2 network): a candidate replaces a simpler one only when its residual is
+// strictly smaller (a NaN never does).
+template <bool NET>
+__global__ void __launch_bounds__(256) k_guess_fin(const double *red, int nb, double *res)
 {
     __shared__ double sm[8];
-    const double fn = sqrt(block_total(red, nb, sm));
+    const double fn = NET ? sqrt(block_total(red, nb, sm)) : __builtin_nan("");
     const double fe = sqrt(block_total(red + MAX_PARTIALS, nb, sm));
     const double fp = sqrt(block_total(red + 2 * MAX_PARTIALS, nb, sm));
     if (threadIdx.x == 0) {
         int c = 0;
         double best = fp;
         if (fe < best) { c = 1; best = fe; }
-        if (fn < best) c = 2;
-        scal[3] = fn;
-        scal[4] = fe;
-        scal[5] = fp;
-        scal[6] = (double)c;
+        if (NET && fn < best) c = 2;
+        res[0] = fn;
+        res[1] = fe;
+        res[2] = fp;
+        res[3] = (double)c;
     }
 }
 
+template <bool NET>
 __global__ void __launch_bounds__(256)
-k_nn_select(const double *u1, const double *u2, const float *__restrict__ out, double *x, size_t n,
-            const double *scal)
+k_guess_select(const double *u1, const double *u2, const float *__restrict__ out, double *x, size_t n,
+               const double *res, const double *scal)
 {
-    const int c = (int)scal[6];
-    const double s = scal[0];
+    const int c = (int)res[3];
+    const double s = NET ? scal[0] : 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const double p = u1[e], q = u2[e];
-        x[e] = c == 0 ? p : (c == 1 ? 2.0 * p - q : 2.0 * p - q + s * (double)out[e]);
+        double v = c == 0 ? p : 2.0 * p - q;
+        if (NET && c == 2) v += s * (double)out[e];
+        x[e] = v;
     }
 }
 
@@ -740,10 +753,11 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
         forward_impl(*n, u1, u2, b, kappa, s);
         const size_t np = (size_t)n->nr * n->nz;
         const unsigned pb = pw_blocks(np);
-        hipLaunchKernelGGL(k_nn_res3, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ, op->nr,
-                           op->nz, n->scal, n->red);
-        hipLaunchKernelGGL(k_nn_res_fin, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal);
-        hipLaunchKernelGGL(k_nn_select, dim3(pb), dim3(256), 0, s, u1, u2, n->out, x, np, n->scal);
+        hipLaunchKernelGGL(k_guess_res<true>, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ,
+                           op->nr, op->nz, n->scal, n->red);
+        hipLaunchKernelGGL(k_guess_fin<true>, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal + 3);
+        hipLaunchKernelGGL(k_guess_select<true>, dim3(pb), dim3(256), 0, s, u1, u2, n->out, x, np, n->scal + 3,
+                           n->scal);
         AXI_CHECK_HIP(hipGetLastError());
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -751,6 +765,37 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
             if (resid_host)
                 for (int j = 0; j < 3; ++j) resid_host[j] = n->res_host[j];
             if (choice_host) *choice_host = (int)n->res_host[3];
+        }
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_guess_extrap(axipcg_op_t hop, const double *b, const double *u1, const double *u2, double *x,
+                        double *resid_host, int *choice_host, void *stream)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(hop);
+        AXI_REQUIRE(op && b && u1 && u2 && x, "NULL argument");
+        AXI_REQUIRE(x != b, "x aliases b");
+        hipStream_t s = (hipStream_t)stream;
+        const size_t np = (size_t)op->nr * op->nz;
+        const unsigned pb = pw_blocks(np);
+        // the reductions use the handle's partial-sum rows 0..2 and scalars 8..11,
+        // which a solve only reads after writing them itself
+        double *res = op->dscal + 8;
+        hipLaunchKernelGGL(k_guess_res<false>, dim3(pb), dim3(256), 0, s, b, u1, u2, nullptr, op->D, op->CR, op->CZ,
+                           op->nr, op->nz, nullptr, op->partials);
+        hipLaunchKernelGGL(k_guess_fin<false>, dim3(1), dim3(256), 0, s, op->partials, (int)pb, res);
+        hipLaunchKernelGGL(k_guess_select<false>, dim3(pb), dim3(256), 0, s, u1, u2, nullptr, x, np, res, nullptr);
+        AXI_CHECK_HIP(hipGetLastError());
+        if (resid_host || choice_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            if (resid_host) {
+                resid_host[0] = op->scratch_host[1];
+                resid_host[1] = op->scratch_host[2];
+            }
+            if (choice_host) *choice_host = (int)op->scratch_host[3];
         }
         return AXIPCG_OK;
     });

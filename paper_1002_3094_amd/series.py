@@ -6,6 +6,8 @@ the sum of all earlier solutions, kept on the device as two running sums
 
 * ``"zero"``  -- x0 = 0, as in the paper's experiments;
 * ``"prev"``  -- x0 = u_{m-1};
+* ``"extrap"`` -- whichever of u_{m-1} and 2 u_{m-1} - u_{m-2} has the smaller
+  residual (``axipcg_guess_extrap``);
 * ``"nn"``    -- the learned guess with its guard (``axipcg_nn_guess``: the
   one of u_{m-1}, 2 u_{m-1} - u_{m-2} and the network's correction of the
   latter with the smallest residual), optionally trained online: after harmonic m is
@@ -26,8 +28,8 @@ from . import axipcg as ax
 class SeriesStats:
     iters: list = field(default_factory=list)
     status: list = field(default_factory=list)
-    choice: list = field(default_factory=list)      # guard's pick (nn mode): 0 prev, 1 extrap, 2 network
-    resid: list = field(default_factory=list)       # guard's |b - A x| of (network, extrap, prev) (nn mode)
+    choice: list = field(default_factory=list)      # guard's pick: 0 prev, 1 extrap, 2 network
+    resid: list = field(default_factory=list)       # guard's |b - A x| per candidate
     loss: list = field(default_factory=list)        # training loss per harmonic (when training)
     gpu_ms: float = 0.0
 
@@ -65,6 +67,11 @@ class LaguerreSeries:
             self.u.zero_()
         elif guess == "prev":
             self.u.copy_(self.u1)
+        elif guess == "extrap":
+            r = ax.guess_extrap(self.op, self.b, self.u1, self.u2, self.u, want_info=want_info)
+            if r is not None:
+                stats.resid.append(r[0])
+                stats.choice.append(r[1])
         elif guess == "nn":
             if net is None or self.kappa is None:
                 raise ValueError("nn guess needs a network and kappa")

@@ -189,3 +189,36 @@ def test_guard_picks_smallest_residual(ax, onn, orc):
     np.testing.assert_array_equal(xh, u1)
     net.close()
     op.close()
+
+
+def test_extrapolation_guard(ax, onn, orc):
+    nr, nz = 32, 64
+    kappa, q = synth.medium_layered(nr, nz, 5)
+    op, oop = _ops(ax, orc, kappa, q)
+    f = synth.gaussian_source(nr, nz, 1.0, 1.0, 0.3, 0.4, 0.05)
+    b = orc.rhs(oop, f)
+    ustar, status, _, _ = orc.pcg(oop, b, np.zeros_like(b), rtol=1e-14, maxit=2000)
+    assert status == 0
+    A = lambda x: orc.apply(oop, x)  # noqa: E731
+    rng = np.random.default_rng(8)
+    bd = dev(b)
+    cases = [
+        (ustar + 0.1 * rng.standard_normal(b.shape), None, 1),        # u2 = 2 u1 - u*: extrapolation exact
+        (ustar + 0.1 * rng.standard_normal(b.shape), "same", 0),      # u2 = u1: tie, u1 kept
+        (ustar + 1e-3 * rng.standard_normal(b.shape), "far", 0),      # u2 far off: u1 better
+    ]
+    for u1, kind, want in cases:
+        u2 = 2 * u1 - ustar if kind is None else (u1 if kind == "same" else u1 + rng.standard_normal(b.shape))
+        x = dev(np.zeros_like(b))
+        res, pick = ax.guess_extrap(op, bd, dev(u1), dev(u2), x, want_info=True)
+        res_ref, pick_ref = onn.guard(b, u1, u2, 2 * u1 - u2, A)
+        log(f"extrap guard {kind}: resid {res} (oracle {res_ref[1:]}) pick {pick}")
+        assert pick == want and pick_ref in (want, 2)
+        np.testing.assert_allclose(res, res_ref[1:], rtol=1e-9, atol=1e-12 * res_ref[2])
+        np.testing.assert_array_equal(host(x), u1 if want == 0 else 2 * u1 - u2)
+    # x may alias u1: the choice is made before x is written
+    u1 = ustar + 0.1 * rng.standard_normal(b.shape)
+    u1d = dev(u1)
+    ax.guess_extrap(op, bd, u1d, dev(2 * u1 - ustar), u1d)
+    np.testing.assert_allclose(host(u1d), ustar, rtol=0, atol=1e-12 * np.abs(ustar).max())
+    op.close()
