@@ -80,7 +80,7 @@ struct Net {
     double *res_host = nullptr;  // pinned
 };
 
-constexpr int WG_BLOCKS = 512;
+constexpr int WG_BLOCKS = 1024;
 constexpr int WG_SEG = 64;   // pixels per staged segment of the weight gradient
 
 // ---- input normalisation -----------------------------------------------------
@@ -119,76 +119,223 @@ k_nn_pack(const double *__restrict__ u1, const double *__restrict__ u2, const do
 {
     const double is = 1.0 / scal[0], ib = 1.0 / scal[1];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        alignas(16) bf16 v[16] = {};
-        v[0] = to_bf16((float)(u1[e] * is));
-        v[1] = to_bf16((float)(u2[e] * is));
-        v[2] = to_bf16((float)(b[e] * ib));
-        v[3] = to_bf16((float)((kap[e] - 2.5) / 1.5));
-        uint4 *dst = reinterpret_cast<uint4 *>(act0 + e * 16);
-        dst[0] = *reinterpret_cast<const uint4 *>(&v[0]);
-        dst[1] = *reinterpret_cast<const uint4 *>(&v[8]);
+        bf16x4 v;
+        v[0] = (short)to_bf16((float)(u1[e] * is));
+        v[1] = (short)to_bf16((float)(u2[e] * is));
+        v[2] = (short)to_bf16((float)(b[e] * ib));
+        v[3] = (short)to_bf16((float)((kap[e] - 2.5) / 1.5));
+        *reinterpret_cast<bf16x4 *>(act0 + e * 4) = v;
     }
 }
 
 // ---- 3x3 convolution (forward, or data gradient with flipped weights) --------
-// in: [pixels][CINP] bf16; out: [pixels][COUTP] bf16 (or FP32 channel 0 when
-// LAST); wf: B fragments [9][CINP/16][COUTP/16][64 lanes]; mask: [pixels][COUTP]
-// bf16 (MASK: zero where mask <= 0).
+// Activations are [pixels][C] BF16 with C = 16 or 32 (natural channel order).
+// A 32-input-channel convolution uses v_mfma_f32_16x16x32_bf16 (one K-block
+// per tap: lane (m, kq) holds channels 8 kq .. 8 kq + 7 of pixel m, one
+// 16-byte load); a 16-channel input uses v_mfma_f32_16x16x16_bf16 (channels
+// 4 kq .. 4 kq + 3).
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mbf16x8 __attribute__((ext_vector_type(8)));
+
+template <int CINP>
+struct FragT;
+template <>
+struct FragT<32> { typedef bf16x8 type; };
+template <>
+struct FragT<16> { typedef bf16x4 type; };
+
+__device__ inline f32x4 mfma(const bf16x8 &a, const bf16x8 &b, const f32x4 &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(mbf16x8, a), __builtin_bit_cast(mbf16x8, b),
+                                                   c, 0, 0, 0);
+}
+__device__ inline f32x4 mfma(const bf16x4 &a, const bf16x4 &b, const f32x4 &c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// A-operand fragments of input row `row` for the z-offsets dk = -1, 0, +1 of
+// the 16-pixel strip starting at column k0 (lane m holds pixel k0 + m).  Out
+// of the grid the fragment is zero (the load itself stays in bounds).
+template <int CINP>
+__device__ inline void load_row(typename FragT<CINP>::type (&f)[3], const bf16 *__restrict__ in, int row, int nr,
+                                int nz, int k0, int m, int kq)
+{
+    typedef typename FragT<CINP>::type Frag;
+    constexpr int LANE_OFF = CINP / 4;
+    const bool row_ok = row >= 0 && row < nr;
+    const int rr = row_ok ? row : 0;
+#pragma unroll
+    for (int dk = 0; dk < 3; ++dk) {
+        const int col = k0 + m + dk - 1;
+        const bool ok = row_ok && col >= 0 && col < nz;
+        const int cc = ok ? col : 0;
+        const Frag v = *reinterpret_cast<const Frag *>(in + ((size_t)rr * nz + cc) * CINP + kq * LANE_OFF);
+        f[dk] = ok ? v : Frag{};
+    }
+}
+
+template <int CINP, int NB>
+__device__ inline void conv_taps(f32x4 (&acc)[NB], const typename FragT<CINP>::type (&r)[3],
+                                 const typename FragT<CINP>::type (&w)[9][NB], int di)
+{
+#pragma unroll
+    for (int dk = 0; dk < 3; ++dk)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = mfma(r[dk], w[di * 3 + dk][nb], acc[nb]);
+}
+
+// Epilogue of a hidden layer for one 16-pixel tile: bias is already in acc
+// (D layout: lane (m, kq) holds pixels 4 kq + j of channels 16 nb + m);
+// ReLU, BF16, transpose through the wave's own LDS slice, then coalesced
+// 16-byte stores ([pixels][32]), with the ReLU mask of the layer below
+// applied when MASK.  Only this wave touches the slice and a wave's LDS
+// operations complete in issue order, so a compiler fence orders the write,
+// the read and the next tile's write.
+template <bool RELU, bool MASK>
+__device__ inline void store_hidden(const f32x4 (&acc)[2], bf16 *ep, bf16 *__restrict__ out,
+                                    const bf16 *__restrict__ mask, size_t pix0, int lane)
+{
+    const int m = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            float v = acc[nb][j];
+            if (RELU) v = v > 0.f ? v : 0.f;
+            ep[(4 * kq + j) * 32 + nb * 16 + m] = to_bf16(v);
+        }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int lp = lane >> 2, q = lane & 3;
+    bf16x8 v = *reinterpret_cast<const bf16x8 *>(&ep[lp * 32 + q * 8]);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const size_t g = (pix0 + lp) * 32 + q * 8;
+    if (MASK) {
+        const bf16x8 mk = *reinterpret_cast<const bf16x8 *>(mask + g);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (!(mk[e] > 0)) v[e] = 0;   // a BF16 value is positive iff its bits are, as int16
+    }
+    *reinterpret_cast<bf16x8 *>(out + g) = v;
+}
+
+// Input layer (4 channels) as im2col: K = tap * 4 + channel over the nine
+// taps, padded to three K-blocks of 16; lane (m, kq) of K-block kb loads the
+// four channels of pixel m at tap 4 kb + kq (zero past tap 8 or outside the
+// grid).  Six v_mfma_f32_16x16x16_bf16 per 16-pixel tile instead of 18 with
+// the channels padded to 16.  wf: [3 kb][2 nb][64 lanes] fragments.
+__global__ void __launch_bounds__(256)
+k_conv_in(const bf16 *__restrict__ in, bf16 *__restrict__ out, const bf16x4 *__restrict__ wf,
+          const float *__restrict__ bias, int nr, int nz, int rows_per_band)
+{
+    __shared__ bf16 ep[4][16 * 32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int groups = nz >> 6;
+    const int band = blockIdx.x / groups, grp = blockIdx.x - band * groups;
+    const int k0 = (grp * 4 + wv) * 16;
+    const int i0 = band * rows_per_band;
+    const int i1 = min(nr, i0 + rows_per_band);
+    bf16x4 w[3][2];
+#pragma unroll
+    for (int kb = 0; kb < 3; ++kb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) w[kb][nb] = wf[(kb * 2 + nb) * 64 + lane];
+    const float b0 = bias[m], b1 = bias[16 + m];
+    // fragment of K-block kb for output row i (row i + 1's are loaded while row i computes)
+    auto load = [&](bf16x4 (&a)[3], int i) {
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) {
+            const int t = 4 * kb + kq;
+            const int ii = i + t / 3 - 1, kk = k0 + m + t % 3 - 1;
+            const bool ok = t < 9 && ii >= 0 && ii < nr && kk >= 0 && kk < nz;
+            const bf16x4 v = *reinterpret_cast<const bf16x4 *>(in + (ok ? (size_t)ii * nz + kk : 0) * 4);
+            a[kb] = ok ? v : bf16x4{0, 0, 0, 0};
+        }
+    };
+    bf16x4 cur[3], nxt[3];
+    load(cur, i0);
+    for (int i = i0; i < i1; ++i) {
+        if (i + 1 < i1) load(nxt, i + 1);
+        f32x4 acc[2] = {f32x4{b0, b0, b0, b0}, f32x4{b1, b1, b1, b1}};
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) {
+            acc[0] = mfma(cur[kb], w[kb][0], acc[0]);
+            acc[1] = mfma(cur[kb], w[kb][1], acc[1]);
+        }
+        store_hidden<true, false>(acc, ep[wv], out, nullptr, (size_t)i * nz + k0, lane);
+#pragma unroll
+        for (int kb = 0; kb < 3; ++kb) cur[kb] = nxt[kb];
+    }
+}
+
+// One workgroup = 4 waves on 4 adjacent 16-pixel strips of one band of rows.
+// Each wave streams down its strip keeping input rows i-1, i, i+1 (and the
+// prefetched i+2) in registers, so every input row is read once per strip.
+// in: [pixels][CINP]; out: [pixels][32] BF16 or, LAST, FP32 channel 0; wf: B
+// fragments [9][COUTP/16][64 lanes]; MASK zeroes outputs where mask (same
+// layout as out) is not positive.
 template <int CINP, int COUTP, bool RELU, bool MASK, bool LAST>
 __global__ void __launch_bounds__(256)
-k_conv3(const bf16 *__restrict__ in, void *__restrict__ outp, const bf16x4 *__restrict__ wf,
-        const float *__restrict__ bias, const bf16 *__restrict__ mask, int nr, int nz, int ntiles)
+k_conv3(const bf16 *__restrict__ in, void *__restrict__ outp, const typename FragT<CINP>::type *__restrict__ wf,
+        const float *__restrict__ bias, const bf16 *__restrict__ mask, int nr, int nz, int rows_per_band)
 {
-    constexpr int KB = CINP / 16, NB = COUTP / 16;
-    const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    bf16x4 w[9][KB][NB];
+    typedef typename FragT<CINP>::type Frag;
+    constexpr int NB = COUTP / 16;
+    static_assert(LAST || COUTP == 32, "hidden outputs have 32 channels");
+    __shared__ bf16 ep[4][16 * 32];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, kq = lane >> 4;
+    const int groups = nz >> 6;
+    const int band = blockIdx.x / groups, grp = blockIdx.x - band * groups;
+    const int k0 = (grp * 4 + wv) * 16;
+    const int i0 = band * rows_per_band;
+    const int i1 = min(nr, i0 + rows_per_band);
+
+    Frag w[9][NB];
 #pragma unroll
     for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-            for (int nb = 0; nb < NB; ++nb) w[t][kb][nb] = wf[((t * KB + kb) * NB + nb) * 64 + lane];
-    const int m = lane & 15, kq = lane >> 4;
+        for (int nb = 0; nb < NB; ++nb) w[t][nb] = wf[(t * NB + nb) * 64 + lane];
     float bl[NB];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) bl[nb] = bias ? bias[nb * 16 + m] : 0.f;
-    for (int tile = wave; tile < ntiles; tile += nwaves) {
-        const int p0 = tile * 16;
-        const int i = p0 / nz, k0 = p0 - i * nz;
+
+    auto row_out = [&](int i, const Frag(&ra)[3], const Frag(&rb)[3], const Frag(&rc)[3]) {
         f32x4 acc[NB];
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[nb] = f32x4{bl[nb], bl[nb], bl[nb], bl[nb]};
+        conv_taps<CINP, NB>(acc, ra, w, 0);
+        conv_taps<CINP, NB>(acc, rb, w, 1);
+        conv_taps<CINP, NB>(acc, rc, w, 2);
+        const size_t pix0 = (size_t)i * nz + k0;
+        if constexpr (LAST) {
+            // D layout: lane holds pixels 4 kq + j of channel 16 nb + m
+            if (m == 0) {
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int ii = i + t / 3 - 1, kk = k0 + m + t % 3 - 1;
-            const bool ok = ii >= 0 && ii < nr && kk >= 0 && kk < nz;
-            const bf16 *src = in + (size_t)(ok ? ii * nz + kk : 0) * CINP + kq * 4;
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                const bf16x4 a = ok ? *reinterpret_cast<const bf16x4 *>(src + kb * 16) : bf16x4{0, 0, 0, 0};
-#pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    acc[nb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, w[t][kb][nb], acc[nb], 0, 0, 0);
+                for (int j = 0; j < 4; ++j) static_cast<float *>(outp)[pix0 + 4 * kq + j] = acc[0][j];
             }
+        } else {
+            store_hidden<RELU, MASK>(acc, ep[wv], static_cast<bf16 *>(outp), mask, pix0, lane);
         }
-        // D layout: lane holds pixel 4 kq + j, channel 16 nb + m
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const size_t pix = (size_t)p0 + 4 * kq + j;
-                const int ch = nb * 16 + m;
-                float v = acc[nb][j];
-                if (LAST) {
-                    if (nb == 0 && m == 0) static_cast<float *>(outp)[pix] = v;
-                } else {
-                    if (RELU) v = v > 0.f ? v : 0.f;
-                    if (MASK && !(from_bf16(mask[pix * COUTP + ch]) > 0.f)) v = 0.f;
-                    static_cast<bf16 *>(outp)[pix * COUTP + ch] = to_bf16(v);
-                }
-            }
+    };
+
+    Frag S0[3], S1[3], S2[3], S3[3];
+    load_row<CINP>(S0, in, i0 - 1, nr, nz, k0, m, kq);
+    load_row<CINP>(S1, in, i0, nr, nz, k0, m, kq);
+    load_row<CINP>(S2, in, i0 + 1, nr, nz, k0, m, kq);
+    for (int i = i0; i < i1; i += 4) {
+        load_row<CINP>(S3, in, i + 2, nr, nz, k0, m, kq);
+        row_out(i, S0, S1, S2);
+        if (i + 1 >= i1) break;
+        load_row<CINP>(S0, in, i + 3, nr, nz, k0, m, kq);
+        row_out(i + 1, S1, S2, S3);
+        if (i + 2 >= i1) break;
+        load_row<CINP>(S1, in, i + 4, nr, nz, k0, m, kq);
+        row_out(i + 2, S2, S3, S0);
+        if (i + 3 >= i1) break;
+        load_row<CINP>(S2, in, i + 5, nr, nz, k0, m, kq);
+        row_out(i + 3, S3, S0, S1);
     }
 }
 
@@ -239,19 +386,31 @@ __global__ void __launch_bounds__(256) k_nn_loss_fin(const double *red, int nb, 
 }
 
 // ---- weight gradient ------------------------------------------------------------
-// dW[t][ci][co] = sum_p act[p + off_t][ci] dpre[p][co];  db[co] = sum_p dpre[p][co].
-// Workgroup partials wpart[block][t][co][ci] (padded channels) then db[co].
-template <int CINP, int COUTP>
+// dW[t][ci][co] = sum_p x[p + off_t][ci] g[p][co] and db[co] = sum_p g[p][co],
+// a GEMM over pixels per tap (M = co, N = ci, K = pixels) with
+// v_mfma_f32_16x16x32_bf16.  A workgroup stages one 64-pixel segment of a
+// row at a time in LDS, channel-major so that a lane's eight consecutive
+// pixels are one aligned 16-byte read: g of the row, and x of rows i-1..i+1
+// in three copies shifted by the z-offset of the tap.  Each wave owns one
+// (co-block, ci-block) pair and a share of the taps; per-workgroup partials
+// [block][t][co][ci] (+ bias) are summed in a fixed order afterwards.  x has
+// CMEM channels in memory (4 for the input layer), padded to CINP in LDS.
+constexpr int WG_PITCH = WG_SEG + 8;   // LDS row pitch (elements): staggers banks, keeps 16-byte alignment
+
+template <int CINP, int COUTP, int CMEM>
 __global__ void __launch_bounds__(256)
 k_wgrad(const bf16 *__restrict__ act, const bf16 *__restrict__ dpre, float *__restrict__ wpart, int nr, int nz)
 {
-    constexpr int NBO = COUTP / 16, NBI = CINP / 16, NT = 9 * NBO * NBI;
-    constexpr int TPW = (NT + 3) / 4;   // tiles per wave
-    constexpr int XW = WG_SEG + 2;
-    __shared__ bf16 yt[COUTP][WG_SEG];
-    __shared__ bf16 xt[3][CINP][XW];
+    constexpr int NBO = COUTP / 16, NBI = CINP / 16, NPAIR = NBO * NBI;
+    constexpr int PARTS = 4 / NPAIR;                 // waves sharing a pair split the taps
+    constexpr int TPW = (9 + PARTS - 1) / PARTS;     // taps per wave
+    __shared__ __attribute__((aligned(16))) bf16 xs[3][3][CINP][WG_PITCH];
+    __shared__ __attribute__((aligned(16))) bf16 gs[COUTP][WG_PITCH];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
+    const int pair = wv % NPAIR, part = wv / NPAIR;
+    const int ob = pair / NBI, ib = pair - ob * NBI;
+    const int t0 = part * TPW;
     f32x4 acc[TPW];
 #pragma unroll
     for (int u = 0; u < TPW; ++u) acc[u] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -261,38 +420,54 @@ k_wgrad(const bf16 *__restrict__ act, const bf16 *__restrict__ dpre, float *__re
     for (int sg = blockIdx.x; sg < nseg; sg += gridDim.x) {
         const int i = sg / segs_per_row, k0 = (sg - i * segs_per_row) * WG_SEG;
         __syncthreads();
-        for (int e = threadIdx.x; e < WG_SEG * COUTP; e += blockDim.x) {
-            const int q = e / COUTP, co = e - q * COUTP;
-            yt[co][q] = dpre[((size_t)i * nz + k0 + q) * COUTP + co];
+        // g of row i: task (co, octet), eight 2-byte loads (lanes on consecutive co coalesce)
+        for (int e = threadIdx.x; e < COUTP * 8; e += blockDim.x) {
+            const int co = e % COUTP, o = e / COUTP;
+            bf16x8 v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = (short)dpre[((size_t)i * nz + k0 + 8 * o + j) * COUTP + co];
+            *reinterpret_cast<bf16x8 *>(&gs[co][8 * o]) = v;
         }
-        for (int e = threadIdx.x; e < 3 * XW * CINP; e += blockDim.x) {
-            const int r = e / (XW * CINP), rem = e - r * XW * CINP;
-            const int q = rem / CINP, ci = rem - q * CINP;
-            const int ii = i + r - 1, kk = k0 + q - 1;
-            bf16 v = 0;
-            if (ii >= 0 && ii < nr && kk >= 0 && kk < nz) v = act[((size_t)ii * nz + kk) * CINP + ci];
-            xt[r][ci][q] = v;
+        // x of rows i-1..i+1: task (ci, octet, row) loads ten pixels and
+        // writes the three z-shifted octets
+        for (int e = threadIdx.x; e < 3 * 8 * CINP; e += blockDim.x) {
+            const int ci = e % CINP, o = (e / CINP) % 8, r = e / (8 * CINP);
+            const int ii = i + r - 1;
+            short v[10];
+#pragma unroll
+            for (int j = 0; j < 10; ++j) {
+                const int kk = k0 + 8 * o + j - 1;
+                const bool ok = ci < CMEM && ii >= 0 && ii < nr && kk >= 0 && kk < nz;
+                v[j] = ok ? (short)act[((size_t)ii * nz + kk) * CMEM + ci] : (short)0;
+            }
+#pragma unroll
+            for (int dk = 0; dk < 3; ++dk) {
+                bf16x8 w;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) w[j] = v[j + dk];
+                *reinterpret_cast<bf16x8 *>(&xs[r][dk][ci][8 * o]) = w;
+            }
         }
         __syncthreads();
-        if (threadIdx.x < COUTP)
-            for (int q = 0; q < WG_SEG; ++q) dbias += from_bf16(yt[threadIdx.x][q]);
+        if (threadIdx.x < COUTP) {
 #pragma unroll
-        for (int u = 0; u < TPW; ++u) {
-            const int tl = wv * TPW + u;
-            if (tl >= NT) continue;
-            const int t = tl / (NBO * NBI), rem = tl - t * NBO * NBI;
-            const int ob = rem / NBI, ib = rem - ob * NBI;
-            const int di = t / 3, dk = t % 3;   // staged row r = di, column offset q + dk
+            for (int o = 0; o < 8; ++o) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(&gs[threadIdx.x][8 * o]);
 #pragma unroll
-            for (int ks = 0; ks < WG_SEG / 16; ++ks) {
-                const int q = ks * 16 + 4 * kq;
-                bf16x4 a, b;
+                for (int j = 0; j < 8; ++j) dbias += from_bf16((bf16)v[j]);
+            }
+        }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    a[j] = (short)yt[ob * 16 + m][q + j];
-                    b[j] = (short)xt[di][ib * 16 + m][q + j + dk];
+        for (int ks = 0; ks < WG_SEG / 32; ++ks) {
+            const int q = ks * 32 + kq * 8;
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&gs[ob * 16 + m][q]);
+#pragma unroll
+            for (int u = 0; u < TPW; ++u) {
+                const int t = t0 + u;
+                if (t < 9) {
+                    const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&xs[t / 3][t % 3][ib * 16 + m][q]);
+                    acc[u] = mfma(a, b, acc[u]);
                 }
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[u], 0, 0, 0);
             }
         }
     }
@@ -300,37 +475,46 @@ k_wgrad(const bf16 *__restrict__ act, const bf16 *__restrict__ dpre, float *__re
     float *wp = wpart + (size_t)blockIdx.x * (9 * 32 * 32 + 32);
 #pragma unroll
     for (int u = 0; u < TPW; ++u) {
-        const int tl = wv * TPW + u;
-        if (tl >= NT) continue;
-        const int t = tl / (NBO * NBI), rem = tl - t * NBO * NBI;
-        const int ob = rem / NBI, ib = rem - ob * NBI;
+        const int t = t0 + u;
+        if (t < 9) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int co = ob * 16 + 4 * kq + j, ci = ib * 16 + m;
-            wp[(t * COUTP + co) * CINP + ci] = acc[u][j];
+            for (int j = 0; j < 4; ++j) {
+                const int co = ob * 16 + 4 * kq + j, ci = ib * 16 + m;
+                wp[(t * COUTP + co) * CINP + ci] = acc[u][j];
+            }
         }
     }
     if (threadIdx.x < COUTP) wp[9 * 32 * 32 + threadIdx.x] = dbias;
 }
 
-// grads (master layout) = sum of the partials over workgroups, in order.
+// grads (master layout) = sum of the partials over workgroups in a fixed
+// order: 32 parameters per workgroup, eight threads per parameter striding
+// over the partials, then the eight sums in order.
 template <int CINP, int COUTP>
 __global__ void __launch_bounds__(256)
 k_wgrad_reduce(const float *__restrict__ wpart, int nblk, float *__restrict__ grads, int cin, int cout)
 {
+    __shared__ double sm[8][32];
     const int nw = 9 * cin * cout;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nw + cout; e += gridDim.x * blockDim.x) {
-        int src;
-        if (e < nw) {
-            const int t = e / (cin * cout), rem = e - t * cin * cout;
-            const int ci = rem / cout, co = rem - ci * cout;
-            src = (t * COUTP + co) * CINP + ci;
-        } else {
-            src = 9 * 32 * 32 + (e - nw);
-        }
-        double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += wpart[(size_t)b * (9 * 32 * 32 + 32) + src];
-        grads[e] = (float)s;
+    const int pl = threadIdx.x & 31, part = threadIdx.x >> 5;
+    const int e = blockIdx.x * 32 + pl;
+    int src = -1;
+    if (e < nw) {
+        const int t = e / (cin * cout), rem = e - t * cin * cout;
+        const int ci = rem / cout, co = rem - ci * cout;
+        src = (t * COUTP + co) * CINP + ci;
+    } else if (e < nw + cout) {
+        src = 9 * 32 * 32 + (e - nw);
+    }
+    double acc = 0.0;
+    if (src >= 0)
+        for (int b = part; b < nblk; b += 8) acc += wpart[(size_t)b * (9 * 32 * 32 + 32) + src];
+    sm[part][pl] = acc;
+    __syncthreads();
+    if (part == 0 && src >= 0) {
+        double t = 0.0;
+        for (int j = 0; j < 8; ++j) t += sm[j][pl];
+        grads[e] = (float)t;
     }
 }
 
@@ -349,8 +533,11 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 // ---- master weights -> BF16 MFMA fragments ----------------------------------------
-// forward fragment (t, kb, nb, lane, item): W[t][ci = 16 kb + 4 (lane/16) + item][co = 16 nb + lane%16]
-// data-gradient fragment: W'[t][co][ci] = W[8 - t][ci][co], K = co, N = ci
+// Fragment (t, nb, lane, item) of a convolution with C input channels
+// (K = C per tap; 8 items per lane when C = 32, 4 when C = 16):
+//   B[k = (C/4) (lane/16) + item][n = 16 nb + lane%16].
+// Forward: k = ci, n = co of W[t]; data gradient (flipped, transposed):
+// k = co, n = ci of W[8 - t].
 template <int L>
 __global__ void k_pack_weights(const float *__restrict__ params, bf16 *__restrict__ wf, bf16 *__restrict__ wb,
                                float *__restrict__ bias_p)
@@ -358,24 +545,35 @@ __global__ void k_pack_weights(const float *__restrict__ params, bf16 *__restric
     constexpr int CI = cin_of(L), CO = cout_of(L), CIP = cinp_of(L), COP = coutp_of(L);
     const float *W = params + param_off(L);
     const float *bias = W + 9 * CI * CO;
+    if constexpr (L == 0) {
+        // input layer, im2col: fragment (kb, nb, lane, item) holds
+        // W[t = 4 kb + lane/16][ci = item][co = 16 nb + lane%16] (0 past tap 8)
+        for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < 3 * 2 * 64 * 4; e += gridDim.x * blockDim.x) {
+            const int item = e & 3, lane = (e >> 2) & 63, frag = e >> 8;
+            const int nb = frag & 1, kb = frag >> 1;
+            const int t = 4 * kb + (lane >> 4), co = 16 * nb + (lane & 15);
+            wf[e] = to_bf16(t < 9 ? W[(t * CI + item) * CO + co] : 0.f);
+        }
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < COP; c += gridDim.x * blockDim.x) bias_p[c] = bias[c];
+        return;
+    }
     const int nf = 9 * CIP * COP;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
-        const int item = e & 3, lane = (e >> 2) & 63, frag = e >> 8;
-        // forward
+        // forward: K = CIP, N = COP
         {
-            const int NBk = COP / 16, KBk = CIP / 16;
-            const int nb = frag % NBk, kb = (frag / NBk) % KBk, t = frag / (NBk * KBk);
-            const int ci = 16 * kb + 4 * (lane >> 4) + item, co = 16 * nb + (lane & 15);
-            const float v = (ci < CI && co < CO) ? W[(t * CI + ci) * CO + co] : 0.f;
-            wf[e] = to_bf16(v);
+            constexpr int IT = CIP / 4;
+            const int item = e % IT, lane = (e / IT) % 64, frag = e / (IT * 64);
+            const int nb = frag % (COP / 16), t = frag / (COP / 16);
+            const int ci = IT * (lane >> 4) + item, co = 16 * nb + (lane & 15);
+            wf[e] = to_bf16((ci < CI && co < CO) ? W[(t * CI + ci) * CO + co] : 0.f);
         }
-        // data gradient (input channels COP, output channels CIP)
+        // data gradient: K = COP (its input channels), N = CIP
         if (wb) {
-            const int NBk = CIP / 16, KBk = COP / 16;
-            const int nb = frag % NBk, kb = (frag / NBk) % KBk, t = frag / (NBk * KBk);
-            const int co = 16 * kb + 4 * (lane >> 4) + item, ci = 16 * nb + (lane & 15);
-            const float v = (ci < CI && co < CO) ? W[((8 - t) * CI + ci) * CO + co] : 0.f;
-            wb[e] = to_bf16(v);
+            constexpr int IT = COP / 4;
+            const int item = e % IT, lane = (e / IT) % 64, frag = e / (IT * 64);
+            const int nb = frag % (CIP / 16), t = frag / (CIP / 16);
+            const int co = IT * (lane >> 4) + item, ci = 16 * nb + (lane & 15);
+            wb[e] = to_bf16((ci < CI && co < CO) ? W[((8 - t) * CI + ci) * CO + co] : 0.f);
         }
     }
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < COP; c += gridDim.x * blockDim.x)
@@ -515,6 +713,12 @@ void free_net(Net *n)
 }
 
 unsigned pw_blocks(size_t n) { return pointwise_blocks(n); }
+// grid of a reduction kernel: at most 1024 partial sums for its one-block finish
+unsigned red_blocks(size_t n)
+{
+    const unsigned b = pointwise_blocks(n);
+    return b < 1024 ? b : 1024;
+}
 
 void pack_all(Net &n, hipStream_t s)
 {
@@ -527,67 +731,77 @@ void pack_all(Net &n, hipStream_t s)
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-unsigned conv_blocks(int ntiles)
+// Rows per band of a convolution launch: about `waves` waves over the nz/16
+// strips (2048 = one round at two waves per SIMD on 1024 SIMDs for the
+// register-heavy 32-channel kernels), at least 4 rows so the halo rows stay a
+// small overhead.
+int conv_rows(int nr, int nz, long waves = 2048)
 {
-    // one tile per wave per sweep step; 4 waves per workgroup
-    int b = (ntiles + 3) / 4;
-    if (b > 2048) b = 2048;
-    return (unsigned)b;
+    const long strips = nz / 16;
+    long r = ((long)nr * strips + waves - 1) / waves;
+    if (r < 4) r = 4;
+    return (int)r;
+}
+
+unsigned conv_blocks(int nr, int nz, int rows)
+{
+    return (unsigned)(((nr + rows - 1) / rows) * (nz / 64));
 }
 
 void forward_impl(Net &n, const double *u1, const double *u2, const double *b, const double *kap, hipStream_t s)
 {
     const size_t np = (size_t)n.nr * n.nz;
-    const unsigned pb = pw_blocks(np);
-    hipLaunchKernelGGL(k_nn_norms, dim3(pb), dim3(256), 0, s, u1, b, np, n.red);
-    hipLaunchKernelGGL(k_nn_norms_fin, dim3(1), dim3(256), 0, s, n.red, (int)pb, np, n.scal);
-    hipLaunchKernelGGL(k_nn_pack, dim3(pb), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.scal);
-    const int ntiles = (int)(np / 16);
-    const dim3 cg(conv_blocks(ntiles)), cb(256);
-    hipLaunchKernelGGL((k_conv3<16, 32, true, false, false>), cg, cb, 0, s, n.act[0], (void *)n.act[1],
-                       (const bf16x4 *)n.wf_fwd[0], n.bias_p[0], nullptr, n.nr, n.nz, ntiles);
+    const unsigned rb = red_blocks(np);
+    hipLaunchKernelGGL(k_nn_norms, dim3(rb), dim3(256), 0, s, u1, b, np, n.red);
+    hipLaunchKernelGGL(k_nn_norms_fin, dim3(1), dim3(256), 0, s, n.red, (int)rb, np, n.scal);
+    hipLaunchKernelGGL(k_nn_pack, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.scal);
+    const int rows = conv_rows(n.nr, n.nz);
+    const dim3 cg(conv_blocks(n.nr, n.nz, rows)), cb(256);
+    const int rows_in = conv_rows(n.nr, n.nz, 8192);
+    hipLaunchKernelGGL(k_conv_in, dim3(conv_blocks(n.nr, n.nz, rows_in)), cb, 0, s, n.act[0], n.act[1],
+                       (const bf16x4 *)n.wf_fwd[0], n.bias_p[0], n.nr, n.nz, rows_in);
     for (int l = 1; l < NL - 1; ++l)
         hipLaunchKernelGGL((k_conv3<32, 32, true, false, false>), cg, cb, 0, s, n.act[l], (void *)n.act[l + 1],
-                           (const bf16x4 *)n.wf_fwd[l], n.bias_p[l], nullptr, n.nr, n.nz, ntiles);
+                           (const bf16x8 *)n.wf_fwd[l], n.bias_p[l], nullptr, n.nr, n.nz, rows);
     hipLaunchKernelGGL((k_conv3<32, 16, false, false, true>), cg, cb, 0, s, n.act[NL - 1], (void *)n.out,
-                       (const bf16x4 *)n.wf_fwd[NL - 1], n.bias_p[NL - 1], nullptr, n.nr, n.nz, ntiles);
+                       (const bf16x8 *)n.wf_fwd[NL - 1], n.bias_p[NL - 1], nullptr, n.nr, n.nz, rows);
     AXI_CHECK_HIP(hipGetLastError());
 }
 
 void backward_impl(Net &n, const Operator &op, const double *u1, const double *u2, const double *ut, hipStream_t s)
 {
     const size_t np = (size_t)n.nr * n.nz;
-    const unsigned pb = pw_blocks(np);
+    const unsigned pb = red_blocks(np);
     hipLaunchKernelGGL(k_nn_energy_seed, dim3(pb), dim3(256), 0, s, n.out, u1, u2, ut, op.D, op.CR, op.CZ, n.nr,
                        n.nz, n.dpre[0], n.scal, n.red);
     hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(256), 0, s, n.red, (int)pb, np, n.scal);
-    const int ntiles = (int)(np / 16);
-    const dim3 cg(conv_blocks(ntiles)), cb(256);
+    const int rows = conv_rows(n.nr, n.nz);
+    const dim3 cg(conv_blocks(n.nr, n.nz, rows)), cb(256);
     const int nseg = (int)(np / WG_SEG);
     const int wgb = nseg < WG_BLOCKS ? nseg : WG_BLOCKS;
     int cur = 0;
     for (int l = NL - 1; l >= 0; --l) {
         float *g = n.grads + param_off(l);
-        const int rb = (9 * cin_of(l) * cout_of(l) + cout_of(l) + 255) / 256;
+        const int rb = (9 * cin_of(l) * cout_of(l) + cout_of(l) + 31) / 32;
         // weight gradient of layer l from act[l] and dpre[cur]
         if (l == 0) {
-            hipLaunchKernelGGL((k_wgrad<16, 32>), dim3(wgb), dim3(256), 0, s, n.act[0], n.dpre[cur], n.wpart, n.nr, n.nz);
+            hipLaunchKernelGGL((k_wgrad<16, 32, 4>), dim3(wgb), dim3(256), 0, s, n.act[0], n.dpre[cur], n.wpart, n.nr, n.nz);
             hipLaunchKernelGGL((k_wgrad_reduce<16, 32>), dim3(rb), dim3(256), 0, s, n.wpart, wgb, g, cin_of(l), cout_of(l));
         } else if (l == NL - 1) {
-            hipLaunchKernelGGL((k_wgrad<32, 16>), dim3(wgb), dim3(256), 0, s, n.act[l], n.dpre[cur], n.wpart, n.nr, n.nz);
+            hipLaunchKernelGGL((k_wgrad<32, 16, 32>), dim3(wgb), dim3(256), 0, s, n.act[l], n.dpre[cur], n.wpart, n.nr, n.nz);
             hipLaunchKernelGGL((k_wgrad_reduce<32, 16>), dim3(rb), dim3(256), 0, s, n.wpart, wgb, g, cin_of(l), cout_of(l));
         } else {
-            hipLaunchKernelGGL((k_wgrad<32, 32>), dim3(wgb), dim3(256), 0, s, n.act[l], n.dpre[cur], n.wpart, n.nr, n.nz);
+            hipLaunchKernelGGL((k_wgrad<32, 32, 32>), dim3(wgb), dim3(256), 0, s, n.act[l], n.dpre[cur], n.wpart, n.nr, n.nz);
             hipLaunchKernelGGL((k_wgrad_reduce<32, 32>), dim3(rb), dim3(256), 0, s, n.wpart, wgb, g, cin_of(l), cout_of(l));
         }
         // data gradient into layer l-1's pre-activation (masked by its ReLU output act[l])
         if (l >= 1) {
             if (l == NL - 1)
                 hipLaunchKernelGGL((k_conv3<16, 32, false, true, false>), cg, cb, 0, s, n.dpre[cur], (void *)n.dpre[1 - cur],
-                                   (const bf16x4 *)n.wf_bwd[l], nullptr, n.act[l], n.nr, n.nz, ntiles);
+                                   (const bf16x4 *)n.wf_bwd[l], nullptr, n.act[l], n.nr, n.nz, rows);
             else
                 hipLaunchKernelGGL((k_conv3<32, 32, false, true, false>), cg, cb, 0, s, n.dpre[cur], (void *)n.dpre[1 - cur],
-                                   (const bf16x4 *)n.wf_bwd[l], nullptr, n.act[l], n.nr, n.nz, ntiles);
+                                   (const bf16x8 *)n.wf_bwd[l], nullptr, n.act[l], n.nr, n.nz, rows);
             cur = 1 - cur;
         }
     }
@@ -611,7 +825,7 @@ Net *create_impl_nn(int nr, int nz, const float *params)
             nalloc(&n->wf_fwd[l], (size_t)9 * cinp_of(l) * coutp_of(l));
             if (l >= 1) nalloc(&n->wf_bwd[l], (size_t)9 * cinp_of(l) * coutp_of(l));
             nalloc(&n->bias_p[l], (size_t)coutp_of(l));
-            nalloc(&n->act[l], np * (size_t)cinp_of(l));
+            nalloc(&n->act[l], np * (size_t)(l == 0 ? cin_of(0) : cinp_of(l)));
         }
         nalloc(&n->out, np);
         nalloc(&n->dpre[0], np * 32);
@@ -752,12 +966,12 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
         const size_t np = (size_t)n->nr * n->nz;
-        const unsigned pb = pw_blocks(np);
+        const unsigned pb = red_blocks(np);
         hipLaunchKernelGGL(k_guess_res<true>, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ,
                            op->nr, op->nz, n->scal, n->red);
         hipLaunchKernelGGL(k_guess_fin<true>, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal + 3);
-        hipLaunchKernelGGL(k_guess_select<true>, dim3(pb), dim3(256), 0, s, u1, u2, n->out, x, np, n->scal + 3,
-                           n->scal);
+        hipLaunchKernelGGL(k_guess_select<true>, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, n->out, x, np,
+                           n->scal + 3, n->scal);
         AXI_CHECK_HIP(hipGetLastError());
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -779,14 +993,15 @@ int axipcg_guess_extrap(axipcg_op_t hop, const double *b, const double *u1, cons
         AXI_REQUIRE(x != b, "x aliases b");
         hipStream_t s = (hipStream_t)stream;
         const size_t np = (size_t)op->nr * op->nz;
-        const unsigned pb = pw_blocks(np);
+        const unsigned pb = red_blocks(np);
         // the reductions use the handle's partial-sum rows 0..2 and scalars 8..11,
         // which a solve only reads after writing them itself
         double *res = op->dscal + 8;
         hipLaunchKernelGGL(k_guess_res<false>, dim3(pb), dim3(256), 0, s, b, u1, u2, nullptr, op->D, op->CR, op->CZ,
                            op->nr, op->nz, nullptr, op->partials);
         hipLaunchKernelGGL(k_guess_fin<false>, dim3(1), dim3(256), 0, s, op->partials, (int)pb, res);
-        hipLaunchKernelGGL(k_guess_select<false>, dim3(pb), dim3(256), 0, s, u1, u2, nullptr, x, np, res, nullptr);
+        hipLaunchKernelGGL(k_guess_select<false>, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, nullptr, x, np, res,
+                           nullptr);
         AXI_CHECK_HIP(hipGetLastError());
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
