@@ -233,12 +233,14 @@ int axipcg_nn_guess(axipcg_op_t op, axipcg_nn_t nn, const double *b, const doubl
                     const double *kappa, double *x, double *resid_host, int *choice_host, void *stream);
 
 /* ---- per-kernel timing (tracing aid) ----------------------------------------
- * Select one kernel class of the PCG iteration; pcg_solve then brackets each
- * launch of that class that does work (iterations before the stop test
- * fired) with a pair of HIP events on the caller's stream and adds the
- * elapsed times once the solve has synchronised.  AXIPCG_KERNEL_NONE turns
- * the timing off (the default).  profile_read returns the accumulated time
- * and launch count (host pointers, may be NULL) and clears them if reset. */
+ * Select one kernel class of the PCG iteration; pcg_solve then brackets one
+ * launch in `every` (>= 1) of that class with a pair of HIP events on the
+ * caller's stream -- sampling keeps the events' own cost out of a timed loop
+ * -- and, once the solve has synchronised, adds the elapsed times of the
+ * bracketed launches that did work (iterations before the stop test fired).
+ * AXIPCG_KERNEL_NONE turns the timing off (the default).  profile_read
+ * returns the accumulated time and launch count (host pointers, may be NULL)
+ * and clears them if reset. */
 enum {
     AXIPCG_KERNEL_NONE = -1,
     AXIPCG_KERNEL_SPMV = 0,    /* p update, q = A p, p.q           */
@@ -246,7 +248,7 @@ enum {
     AXIPCG_KERNEL_TRIDIAG = 2, /* r-solves, one per z-mode         */
     AXIPCG_KERNEL_ZINV = 3     /* inverse transform, r.z           */
 };
-int axipcg_profile_select(axipcg_op_t op, int kernel);
+int axipcg_profile_select(axipcg_op_t op, int kernel, int every);
 int axipcg_profile_read(axipcg_op_t op, double *total_ms, long long *launches, int reset);
 
 /* ---- errors ---------------------------------------------------------------- */

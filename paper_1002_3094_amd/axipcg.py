@@ -67,7 +67,7 @@ SIGNATURES = {
     "axipcg_nn_backward": ([_vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_nn_adam": ([_vp, _d, _d, _d, _d, _vp], _i),
     "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
-    "axipcg_profile_select": ([_vp, _i], _i),
+    "axipcg_profile_select": ([_vp, _i, _i], _i),
     "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
     "axipcg_last_error": ([], ctypes.c_char_p),
@@ -346,8 +346,8 @@ def nn_guess(op: Op, net: Net, b, u1, u2, kappa, x, stream=None, want_info=True)
     return (phi, choice.value) if want_info else None
 
 
-def profile_select(op: Op, kernel: int):
-    _check(lib().axipcg_profile_select(op.handle, kernel), "profile_select")
+def profile_select(op: Op, kernel: int, every: int = 1):
+    _check(lib().axipcg_profile_select(op.handle, kernel, every), "profile_select")
 
 
 def profile_read(op: Op, reset: bool = False):

@@ -104,6 +104,8 @@ struct Operator {
 
     // per-kernel timing (axipcg_profile_*)
     int prof_kernel = -1;
+    int prof_every = 1;                   // time one launch in `every` of the class
+    long long prof_seen = 0;              // launches of the class since select
     std::vector<hipEvent_t> prof_events;  // pairs (start, stop)
     std::vector<int> prof_iter;           // iteration of each pair
     size_t prof_used = 0;

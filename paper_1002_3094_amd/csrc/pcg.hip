@@ -42,8 +42,39 @@ __device__ inline double stencil(const double *__restrict__ D, const double *__r
 // A z and A p_old are formed first (no scalar needed), so the loads overlap
 // the reduction of the r.z partials; q = A z + beta A p_old is the same
 // product up to rounding (no recurrence: both terms are recomputed from the
-// stored vectors every iteration).
-constexpr int SPMV_PPT = 8;   // points per thread per row (nz <= 2048, 256 threads)
+// stored vectors every iteration).  A thread handles pairs of adjacent points
+// (16-byte loads and stores; the z-neighbours k-1 and k+2 are 8-byte loads
+// that hit the lines its wave already fetched).
+constexpr int SPMV_PAIRS = 4;   // pairs per thread per row (nz <= 2048, 256 threads)
+
+struct Pair { double a, b; };
+
+__device__ inline Pair ld2(const double *p) { const double2 v = *reinterpret_cast<const double2 *>(p); return {v.x, v.y}; }
+
+// (A v) at the pair (e, e+1) of row i, columns k, k+1 (k even, k + 1 < nz)
+__device__ inline Pair stencil2(const double *__restrict__ v, const double *__restrict__ D,
+                                const double *__restrict__ CR, const double *__restrict__ CZ, size_t e, int i, int k,
+                                int nr, int nz, const Pair &c)
+{
+    const Pair d = ld2(D + e), cz = ld2(CZ + e);
+    Pair y{d.a * c.a, d.b * c.b};
+    if (i + 1 < nr) {
+        const Pair cr = ld2(CR + e), vn = ld2(v + e + nz);
+        y.a -= cr.a * vn.a;
+        y.b -= cr.b * vn.b;
+    }
+    if (i > 0) {
+        const Pair cr = ld2(CR + e - nz), vn = ld2(v + e - nz);
+        y.a -= cr.a * vn.a;
+        y.b -= cr.b * vn.b;
+    }
+    // z-couplings: (k, k+1) inside the pair, k-1 and k+2 outside
+    y.a -= cz.a * c.b;
+    y.b -= cz.a * c.a;
+    if (k + 2 < nz) y.b -= cz.b * v[e + 2];
+    if (k > 0) y.a -= CZ[e - 1] * v[e - 1];
+    return y;
+}
 
 template <bool PR>
 __device__ __forceinline__ void spmv_body(const double *__restrict__ z, const double *__restrict__ pold,
@@ -59,16 +90,16 @@ __device__ __forceinline__ void spmv_body(const double *__restrict__ z, const do
     int k_it = 0;
     for (int b = vb; b < nr; b += vnb) {
         const int i = xcd_swizzle(b, nr);
-        double az[SPMV_PPT], ap[SPMV_PPT], zc[SPMV_PPT], pc[SPMV_PPT];
+        Pair az[SPMV_PAIRS], ap[SPMV_PAIRS], zc[SPMV_PAIRS], pc[SPMV_PAIRS];
 #pragma unroll
-        for (int j = 0; j < SPMV_PPT; ++j) {
-            const int k = threadIdx.x + j * 256;
+        for (int j = 0; j < SPMV_PAIRS; ++j) {
+            const int k = 2 * (threadIdx.x + j * 256);
             if (k < nz) {
                 const size_t e = (size_t)i * nz + k;
-                zc[j] = z[e];
-                pc[j] = pold[e];
-                az[j] = stencil(D, CR, CZ, e, i, k, nr, nz, [&](long o) { return z[e + o]; });
-                ap[j] = stencil(D, CR, CZ, e, i, k, nr, nz, [&](long o) { return pold[e + o]; });
+                zc[j] = ld2(z + e);
+                pc[j] = ld2(pold + e);
+                az[j] = stencil2(z, D, CR, CZ, e, i, k, nr, nz, zc[j]);
+                ap[j] = stencil2(pold, D, CR, CZ, e, i, k, nr, nz, pc[j]);
             }
         }
         if (!have_beta) {   // scalars once per workgroup, after the first row's loads
@@ -84,15 +115,19 @@ __device__ __forceinline__ void spmv_body(const double *__restrict__ z, const do
             have_beta = true;
         }
 #pragma unroll
-        for (int j = 0; j < SPMV_PPT; ++j) {
-            const int k = threadIdx.x + j * 256;
+        for (int j = 0; j < SPMV_PAIRS; ++j) {
+            const int k = 2 * (threadIdx.x + j * 256);
             if (k < nz) {
                 const size_t e = (size_t)i * nz + k;
-                const double p_new = (k_it > 0) ? zc[j] + beta * pc[j] : zc[j];
-                const double q_new = (k_it > 0) ? az[j] + beta * ap[j] : az[j];
-                pnew[e] = p_new;
-                q[e] = q_new;
-                acc += p_new * q_new;
+                double2 pn, qn;
+                pn.x = (k_it > 0) ? zc[j].a + beta * pc[j].a : zc[j].a;
+                pn.y = (k_it > 0) ? zc[j].b + beta * pc[j].b : zc[j].b;
+                qn.x = (k_it > 0) ? az[j].a + beta * ap[j].a : az[j].a;
+                qn.y = (k_it > 0) ? az[j].b + beta * ap[j].b : az[j].b;
+                *reinterpret_cast<double2 *>(pnew + e) = pn;
+                *reinterpret_cast<double2 *>(q + e) = qn;
+                acc += pn.x * qn.x;
+                acc += pn.y * qn.y;
             }
         }
     }
@@ -202,7 +237,8 @@ struct ProfScope {
     hipStream_t s;
     bool on;
     size_t slot = 0;
-    ProfScope(Operator &o, hipStream_t st, int kernel, int iter) : op(o), s(st), on(o.prof_kernel == kernel)
+    ProfScope(Operator &o, hipStream_t st, int kernel, int iter)
+        : op(o), s(st), on(o.prof_kernel == kernel && (o.prof_seen++ % o.prof_every) == 0)
     {
         if (!on) return;
         slot = op.prof_used++;
@@ -318,10 +354,12 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     ia.mode = 2;
     launch_zinv(op, prec, ia, s);
 
-    // iterations, in chunks; the first chunk is sized from the previous solve
+    // iterations, in chunks: the first one covers the previous solve's count
+    // plus one, so a series of similar solves reads the state back once each
+    // (the launches past the stop test return at once)
     int launched = 0;
     int parity = 0;
-    int chunk = op.last_iters > 2 ? op.last_iters - 1 : 4;
+    int chunk = op.last_iters > 0 ? op.last_iters + 1 : 4;
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
         for (int it = 0; it < chunk; ++it) {
@@ -391,13 +429,16 @@ void launch_b_gather(const ProbDesc *d, int n, PcgState *out, hipStream_t s)
 
 using namespace axipcg;
 
-extern "C" int axipcg_profile_select(axipcg_op_t h, int kernel)
+extern "C" int axipcg_profile_select(axipcg_op_t h, int kernel, int every)
 {
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(h);
         AXI_REQUIRE(op != nullptr, "op is NULL");
         AXI_REQUIRE(kernel >= AXIPCG_KERNEL_NONE && kernel <= AXIPCG_KERNEL_ZINV, "unknown kernel class");
+        AXI_REQUIRE(every >= 1, "every must be >= 1");
         op->prof_kernel = kernel;
+        op->prof_every = every;
+        op->prof_seen = 0;
         op->prof_used = 0;
         return AXIPCG_OK;
     });
