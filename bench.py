@@ -67,6 +67,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem uneven batch")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy a 64 MiB tensor five times (the known-size kernel that scales the "
+                         "FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
+    ap.add_argument("--ingest-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter CSVs of two rocprofv3 --pmc runs of this script (with "
+                         "--copy-calibration) into profiles/traffic_<kernel>_<workload>.json and exit")
     return ap.parse_args()
 
 
@@ -88,6 +94,53 @@ def measured_traffic(kernel, workload, launch_bytes):
     if d.get("source_sha") != source_sha():
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+COPY_BYTES = 64 << 20
+
+
+def ingest_traffic(a, fetch_csv, write_csv):
+    """HBM (data-fabric) bytes per launch of the roofline kernel from two
+    rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+    scaled by what the same counter reads for the calibration copy of
+    COPY_BYTES.  Launches past the stop test (which return at once) are left
+    out: only dispatches above a tenth of the kernel's largest count are
+    averaged."""
+    import csv
+
+    def per_kernel(path):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            out.setdefault(name, []).append(float(r["Counter_Value"]))
+        return out
+
+    def copy_kib(d):
+        # the calibration copies are the largest copy dispatches of the run
+        vals = [v for n, vs in d.items() if "copybuffer" in n.lower() for v in vs]
+        big = [v for v in vals if v > 0.95 * max(vals)]
+        return sum(big) / len(big)
+
+    def kernel_kib(d, symbol):
+        vals = [v for n, vs in d.items() if symbol in n for v in vs]
+        big = [v for v in vals if v > 0.1 * max(vals)]
+        return sum(big) / len(big), len(big)
+
+    f, w = per_kernel(fetch_csv), per_kernel(write_csv)
+    fscale = COPY_BYTES / (copy_kib(f) * 1024)
+    wscale = COPY_BYTES / (copy_kib(w) * 1024)
+    sym = KERNEL_SYMBOLS[a.roofline_kernel]
+    fk, nf = kernel_kib(f, sym)
+    wk, nw = kernel_kib(w, sym)
+    rec = {"kernel": sym, "workload": f"laguerre_{a.nr}x{a.nz}", "source_sha": source_sha(),
+           "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+           "fetch_bytes_per_launch": round(fk * 1024 * fscale), "write_bytes_per_launch": round(wk * 1024 * wscale),
+           "dispatches": [nf, nw]}
+    rec["hbm_bytes_per_launch"] = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    rec["algorithmic_bytes_per_launch"] = BYTES_PER_POINT[a.roofline_kernel] * a.nr * a.nz
+    path = os.path.join(ROOT, "profiles", f"traffic_{a.roofline_kernel}_{rec['workload']}.json")
+    json.dump(rec, open(path, "w"), indent=1)
+    print(json.dumps(rec))
 
 
 def cpu_baseline(inp, prec_rtol, budget_s, n_max=16):
@@ -192,6 +245,9 @@ def train_network(ax, torch, synth, series, a):
 
 def main():
     a = parse()
+    if a.ingest_traffic:
+        ingest_traffic(a, *a.ingest_traffic)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU r-strip "
               "decomposition is a design in DESIGN.md, not part of this build.", file=sys.stderr)
@@ -205,6 +261,12 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if a.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     modes = [m for m in a.modes.split(",") if m]
     if a.headline not in modes:
         modes.append(a.headline)
