@@ -25,9 +25,11 @@ __device__ inline const typename vec2_of<T>::type *stage_twiddles(const typename
 }
 
 // ---------------------------------------------------------------------------
-// Forward transform: one workgroup per r-row.
+// Forward transform: one workgroup per ROWS consecutive r-rows.  With two
+// rows the second row's loads are issued before the first row's FFT, so the
+// memory traffic of one row overlaps the LDS work of the other.
 // ---------------------------------------------------------------------------
-template <typename T, int BC, bool FUSED, bool TWLDS>
+template <typename T, int BC, bool FUSED, bool TWLDS, int ROWS>
 __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double *__restrict__ x,
                                           double *__restrict__ r, const double *__restrict__ p,
                                           const double *__restrict__ q, PcgState *st,
@@ -44,25 +46,28 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     __shared__ double red[8];
 
     if (FUSED && st->done) return;
-    const int i = xcd_swizzle(vb, nr);
-    const size_t row = (size_t)i * N;
-    // issue the row loads before the p.q reduction so the latencies overlap
+    const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
     double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
+    auto load = [&](int i) {
+        const size_t row = (size_t)i * N;
 #pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-        const int k = threadIdx.x + j * blockDim.x;
-        if (k < N) {
-            if (FUSED) {
-                xv[j] = x[row + k];
-                rv0[j] = r[row + k];
-                pv[j] = p[row + k];
-                qv[j] = q[row + k];
-            } else {
-                rv0[j] = rin[row + k];
+        for (int j = 0; j < KPT; ++j) {
+            const int k = threadIdx.x + j * blockDim.x;
+            if (k < N) {
+                if (FUSED) {
+                    xv[j] = x[row + k];
+                    rv0[j] = r[row + k];
+                    pv[j] = p[row + k];
+                    qv[j] = q[row + k];
+                } else {
+                    rv0[j] = rin[row + k];
+                }
             }
         }
-    }
+    };
+    // issue the first row's loads before the p.q reduction so the latencies overlap
+    load(i0);
     const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
     double alpha = 0.0;
     if (FUSED) {
@@ -77,40 +82,46 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     }
 
     double rr = 0.0;
-#pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-        const int k = threadIdx.x + j * blockDim.x;
-        if (k >= N) continue;
-        double rv;
-        if (FUSED) {
-            const size_t c = row + k;
-            x[c] = xv[j] + alpha * pv[j];
-            rv = rv0[j] - alpha * qv[j];
-            r[c] = rv;
-            rr += rv * rv;
-        } else {
-            rv = rv0[j];
-        }
-        T v = (T)rv;
-        int n;
-        if ((k & 1) == 0) {
-            n = k >> 1;
-        } else {
-            n = N - 1 - (k >> 1);
-            if (BC == DIR) v = -v;
-        }
-        a[n] = {v, (T)0};
-    }
-    __syncthreads();
-    const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
     const T nrm = (T)sqrt(2.0 / N);
     const T half = (T)0.70710678118654752440;
-    for (int j = threadIdx.x; j < N; j += blockDim.x) {
-        const int m = (BC == DIR) ? N - 1 - j : j;
-        const cx<T> w = ld_tw<T>(pt, m);
-        const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
-        const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
-        spec[row + j] = nrm * (edge ? half : (T)1) * Y;
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+        const size_t row = (size_t)(i0 + s) * N;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int k = threadIdx.x + j * blockDim.x;
+            if (k >= N) continue;
+            double rv;
+            if (FUSED) {
+                const size_t c = row + k;
+                x[c] = xv[j] + alpha * pv[j];
+                rv = rv0[j] - alpha * qv[j];
+                r[c] = rv;
+                rr += rv * rv;
+            } else {
+                rv = rv0[j];
+            }
+            T v = (T)rv;
+            int n;
+            if ((k & 1) == 0) {
+                n = k >> 1;
+            } else {
+                n = N - 1 - (k >> 1);
+                if (BC == DIR) v = -v;
+            }
+            a[n] = {v, (T)0};
+        }
+        if (s + 1 < ROWS) load(i0 + s + 1);
+        __syncthreads();
+        const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
+        for (int j = threadIdx.x; j < N; j += blockDim.x) {
+            const int m = (BC == DIR) ? N - 1 - j : j;
+            const cx<T> w = ld_tw<T>(pt, m);
+            const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
+            const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
+            spec[row + j] = nrm * (edge ? half : (T)1) * Y;
+        }
+        if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
     }
     if (FUSED) {
         const double s = block_sum(rr, red);
@@ -118,7 +129,7 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     }
 }
 
-template <typename T, int BC, bool FUSED, bool TWLDS>
+template <typename T, int BC, bool FUSED, bool TWLDS, int ROWS>
 __global__ void __launch_bounds__(256)
 k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
        const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
@@ -126,13 +137,14 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
        T *__restrict__ spec, const typename vec2_of<T>::type *__restrict__ tw,
        const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
 {
-    zfwd_body<T, BC, FUSED, TWLDS>(rin, x, r, p, q, st, partials, n_pq, spec, tw, pt, nr, N, blockIdx.x);
+    zfwd_body<T, BC, FUSED, TWLDS, ROWS>(rin, x, r, p, q, st, partials, n_pq, spec, tw, pt, nr, N, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
-// Inverse transform: one workgroup per r-row, FP64 output.
+// Inverse transform: one workgroup per ROWS consecutive r-rows, FP64 output;
+// the next row's spectral values are loaded during the current row's FFT.
 // ---------------------------------------------------------------------------
-template <typename T, int BC, int MODE, bool TWLDS>
+template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
 __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__restrict__ zout,
                                           const double *__restrict__ r, const PcgState *st,
                                           double *__restrict__ partials, bool pr,
@@ -148,39 +160,74 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
     __shared__ double red[8];
     const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
 
-    const int i = xcd_swizzle(vb, nr);
-    const size_t row = (size_t)i * N;
+    const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
     const T sq2 = (T)1.41421356237309504880;
-    auto Yval = [&](int m) -> T {
+    constexpr int KPT = 8;   // N <= 2048, >= 256 threads for N >= 1024
+    T ymv[KPT], ynv[KPT];
+    auto Yval = [&](size_t row, int m) -> T {
         // unnormalised DCT-II coefficient Y_m of y
         const int j = (BC == DIR) ? N - 1 - m : m;
         const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
         return spec[row + j] * isc * (edge ? sq2 : (T)1);
     };
-    for (int m = threadIdx.x; m < N; m += blockDim.x) {
-        const T ym = Yval(m);
-        const T yn = (m == 0) ? (T)0 : Yval(N - m);
-        const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
-        // V = conj(w) (ym - i yn); store conj(V) = w (ym + i yn)
-        a[m] = {w.x * ym - w.y * yn, w.x * yn + w.y * ym};
-    }
-    __syncthreads();
-    const cx<T> *res = fft_stockham<T>(a, b, N, twp);
+    auto load = [&](int i) {
+        const size_t row = (size_t)i * N;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int m = threadIdx.x + j * blockDim.x;
+            if (m < N) {
+                ymv[j] = Yval(row, m);
+                ynv[j] = (m == 0) ? (T)0 : Yval(row, N - m);
+            }
+        }
+    };
+    load(i0);
     const T invN = (T)1 / (T)N;
     double rz = 0.0, rzo = 0.0;
-    for (int k = threadIdx.x; k < N; k += blockDim.x) {
-        const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
-        T v = res[n].x * invN;
-        if (BC == DIR && (k & 1)) v = -v;
-        const double zv = (double)v;
-        const size_t c = row + k;
-        if (MODE != 0) {
-            const double rv = r[c];
-            if (pr) rzo += rv * zout[c];
-            rz += rv * zv;
+#pragma unroll
+    for (int s = 0; s < ROWS; ++s) {
+        const size_t row = (size_t)(i0 + s) * N;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int m = threadIdx.x + j * blockDim.x;
+            if (m < N) {
+                const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
+                // V = conj(w) (ym - i yn); store conj(V) = w (ym + i yn)
+                a[m] = {w.x * ymv[j] - w.y * ynv[j], w.x * ynv[j] + w.y * ymv[j]};
+            }
         }
-        zout[c] = zv;
+        // r (and the old z) of this row, and the next row's spectral values,
+        // are in flight during the FFT
+        double rv[KPT], zo[KPT];
+        if (MODE != 0) {
+#pragma unroll
+            for (int j = 0; j < KPT; ++j) {
+                const int k = threadIdx.x + j * blockDim.x;
+                if (k < N) {
+                    rv[j] = r[row + k];
+                    if (pr) zo[j] = zout[row + k];
+                }
+            }
+        }
+        if (s + 1 < ROWS) load(i0 + s + 1);
+        __syncthreads();
+        const cx<T> *res = fft_stockham<T>(a, b, N, twp);
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int k = threadIdx.x + j * blockDim.x;
+            if (k >= N) continue;
+            const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
+            T v = res[n].x * invN;
+            if (BC == DIR && (k & 1)) v = -v;
+            const double zv = (double)v;
+            if (MODE != 0) {
+                if (pr) rzo += rv[j] * zo[j];
+                rz += rv[j] * zv;
+            }
+            zout[row + k] = zv;
+        }
+        if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
     }
     if (MODE != 0) {
         const double s = block_sum(rz, red);
@@ -192,14 +239,14 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
     }
 }
 
-template <typename T, int BC, int MODE, bool TWLDS>
+template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
 __global__ void __launch_bounds__(256)
 k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
        const PcgState *st, double *__restrict__ partials, bool pr,
        const typename vec2_of<T>::type *__restrict__ tw,
        const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
 {
-    zinv_body<T, BC, MODE, TWLDS>(spec, zout, r, st, partials, pr, tw, pt, nr, N, blockIdx.x);
+    zinv_body<T, BC, MODE, TWLDS, ROWS>(spec, zout, r, st, partials, pr, tw, pt, nr, N, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -272,9 +319,12 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     __shared__ double red[8];
     extern __shared__ char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
-    T *cb = tile + M * pitch;          // r-line coefficients staged in LDS
-    T *db = cb + nr;
-    T *rw = db + nr;
+    // r-line coefficients: each lane reads its own contiguous rows from global
+    // memory (L2-resident, a few KB); staged in LDS they would be read at a
+    // stride of a segment, one bank for the whole wave
+    const T *__restrict__ cb = cb_g;
+    const T *__restrict__ db = db_g;
+    const T *__restrict__ rw = rw_g;
     const int ngroups = nz / M;
     const int l0 = xcd_swizzle(vb, ngroups) * M;
     auto prow = [&](int row) { return row + row / Lp; };
@@ -292,11 +342,6 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
             tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
         }
     }
-    for (int i = threadIdx.x; i < nr; i += blockDim.x) {
-        cb[i] = cb_g[i];
-        db[i] = db_g[i];
-        rw[i] = rw_g[i];
-    }
     if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb) != ST_RUN) return;
     __syncthreads();
 
@@ -310,15 +355,37 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
         const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
         auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
 
-        // prefetch the lane's data, diagonal and couplings from LDS
+        // prefetch the lane's data (LDS), diagonal and couplings (global)
         T fv[LMAX], dv[LMAX], cv[LMAX];
+        constexpr int VW = 16 / (int)sizeof(T);
+        if constexpr (UNI && LMAX % VW == 0) {
+            // all LMAX rows, the interface row included, as 16-byte vectors
+            typedef T V __attribute__((ext_vector_type(VW)));
+            if (active) {
 #pragma unroll
-        for (int t = 0; t < LMAX; ++t) {
-            if (in_seg(t)) {
-                const int i = lo + t;
-                fv[t] = col[prow(i)];
-                dv[t] = db[i] + rw[i] * lm;
-                cv[t] = cb[i];
+                for (int j = 0; j < LMAX / VW; ++j) {
+                    const V c4 = *reinterpret_cast<const V *>(cb + lo + j * VW);
+                    const V d4 = *reinterpret_cast<const V *>(db + lo + j * VW);
+                    const V r4 = *reinterpret_cast<const V *>(rw + lo + j * VW);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        cv[j * VW + e] = c4[e];
+                        dv[j * VW + e] = d4[e] + r4[e] * lm;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t)
+                if (in_seg(t)) fv[t] = col[prow(lo + t)];
+        } else {
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t) {
+                if (in_seg(t)) {
+                    const int i = lo + t;
+                    fv[t] = col[prow(i)];
+                    dv[t] = db[i] + rw[i] * lm;
+                    cv[t] = cb[i];
+                }
             }
         }
         const T cbm = (active && lo > 0) ? cb[lo - 1] : (T)0;
@@ -453,10 +520,10 @@ __global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, 
     const double *pnew = parity ? P.p0 : P.p1;   // written by this iteration's SpMV
     const int vb = blockIdx.x - P.row_start;
     if (P.bc_z == DIR)
-        zfwd_body<T, DIR, FUSED, TWLDS>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr, (T *)P.spec,
+        zfwd_body<T, DIR, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr, (T *)P.spec,
                                         pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
     else
-        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr,
+        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr,
                                                      (T *)P.spec, pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
 }
 
@@ -467,10 +534,10 @@ __global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, 
     const ProbDesc &P = d[p];
     const int vb = blockIdx.x - P.row_start;
     if (P.bc_z == DIR)
-        zinv_body<T, DIR, MODE, TWLDS>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
+        zinv_body<T, DIR, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
                                        pd_pt<T>(P), P.nr, P.nz, vb);
     else
-        zinv_body<T, AXIPCG_Z_NEUMANN, MODE, TWLDS>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
+        zinv_body<T, AXIPCG_Z_NEUMANN, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
                                                     pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
 }
 
@@ -518,18 +585,29 @@ bool twiddles_in_lds(int N) { return 3 * (size_t)N * sizeof(cx<T>) <= 65536; }
 template <typename T>
 size_t transform_lds(int N) { return (twiddles_in_lds<T>(N) ? 3 : 2) * (size_t)N * sizeof(cx<T>); }
 
-template <typename T, int BC, bool TWL>
-void zfwd_tt(const Operator &op, const ZfwdArgs &a, hipStream_t s)
+// Rows per transform workgroup: two (pipelined) for the FP64 transforms when
+// that still leaves at least 256 workgroups, else one.  (Measured at 1024^2:
+// two rows take the FP64 forward transform from 28 to 25 us but slow the FP32
+// ones, whose FFT is too short to hide a second row's loads behind while the
+// grid loses half its workgroups.)
+inline int transform_rows(int nr, int prec)
+{
+    return (prec == AXIPCG_PREC_FP64 && nr % 2 == 0 && nr >= 512) ? 2 : 1;
+}
+
+template <typename T, int BC, bool TWL, int ROWS>
+void zfwd_ttr(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
     const int N = op.nz;
     const auto tb = tables<T>(op);
     const size_t shm = transform_lds<T>(N);
     const int thr = fft_threads(N);
+    const dim3 grid(op.nr / ROWS);
     if (a.fused)
-        hipLaunchKernelGGL((k_zfwd<T, BC, true, TWL>), dim3(op.nr), dim3(thr), shm, s, nullptr, a.x, a.r, a.p, a.q,
+        hipLaunchKernelGGL((k_zfwd<T, BC, true, TWL, ROWS>), grid, dim3(thr), shm, s, nullptr, a.x, a.r, a.p, a.q,
                            a.state, op.partials, a.n_pq, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
     else
-        hipLaunchKernelGGL((k_zfwd<T, BC, false, TWL>), dim3(op.nr), dim3(thr), shm, s, a.rin, nullptr, nullptr,
+        hipLaunchKernelGGL((k_zfwd<T, BC, false, TWL, ROWS>), grid, dim3(thr), shm, s, a.rin, nullptr, nullptr,
                            nullptr, nullptr, nullptr, op.partials, 0, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
     AXI_CHECK_HIP(hipGetLastError());
 }
@@ -537,28 +615,35 @@ void zfwd_tt(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 template <typename T, int BC>
 void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
-    if (twiddles_in_lds<T>(op.nz)) zfwd_tt<T, BC, true>(op, a, s);
-    else zfwd_tt<T, BC, false>(op, a, s);
+    const bool twl = twiddles_in_lds<T>(op.nz);
+    if (transform_rows(op.nr, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
+        if (twl) zfwd_ttr<T, BC, true, 2>(op, a, s);
+        else zfwd_ttr<T, BC, false, 2>(op, a, s);
+    } else {
+        if (twl) zfwd_ttr<T, BC, true, 1>(op, a, s);
+        else zfwd_ttr<T, BC, false, 1>(op, a, s);
+    }
 }
 
-template <typename T, int BC, bool TWL>
-void zinv_tt(const Operator &op, const ZinvArgs &a, hipStream_t s)
+template <typename T, int BC, bool TWL, int ROWS>
+void zinv_ttr(const Operator &op, const ZinvArgs &a, hipStream_t s)
 {
     const int N = op.nz;
     const auto tb = tables<T>(op);
     const size_t shm = transform_lds<T>(N);
     const int thr = fft_threads(N);
+    const dim3 grid(op.nr / ROWS);
     switch (a.mode) {
     case 0:
-        hipLaunchKernelGGL((k_zinv<T, BC, 0, TWL>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+        hipLaunchKernelGGL((k_zinv<T, BC, 0, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
                            nullptr, nullptr, op.partials, false, tb.tw, tb.pt, op.nr, N);
         break;
     case 1:
-        hipLaunchKernelGGL((k_zinv<T, BC, 1, TWL>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+        hipLaunchKernelGGL((k_zinv<T, BC, 1, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
                            a.r, a.state, op.partials, a.pr, tb.tw, tb.pt, op.nr, N);
         break;
     default:
-        hipLaunchKernelGGL((k_zinv<T, BC, 2, TWL>), dim3(op.nr), dim3(thr), shm, s, (const T *)op.spec, a.zout,
+        hipLaunchKernelGGL((k_zinv<T, BC, 2, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
                            a.r, a.state, op.partials, false, tb.tw, tb.pt, op.nr, N);
         break;
     }
@@ -568,8 +653,14 @@ void zinv_tt(const Operator &op, const ZinvArgs &a, hipStream_t s)
 template <typename T, int BC>
 void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
 {
-    if (twiddles_in_lds<T>(op.nz)) zinv_tt<T, BC, true>(op, a, s);
-    else zinv_tt<T, BC, false>(op, a, s);
+    const bool twl = twiddles_in_lds<T>(op.nz);
+    if (transform_rows(op.nr, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
+        if (twl) zinv_ttr<T, BC, true, 2>(op, a, s);
+        else zinv_ttr<T, BC, false, 2>(op, a, s);
+    } else {
+        if (twl) zinv_ttr<T, BC, true, 1>(op, a, s);
+        else zinv_ttr<T, BC, false, 1>(op, a, s);
+    }
 }
 
 struct TriGeom {
@@ -586,7 +677,7 @@ TriGeom tri_geom(int nr, int nz)
     g.Lp = nr / g.S;
     g.pitch = nr + nr / g.Lp + 1;
     g.M = 16 / (int)sizeof(T);   // one 16-byte vector of modes per row
-    auto lds = [&](int M) { return ((size_t)M * g.pitch + 3 * (size_t)nr) * sizeof(T); };
+    auto lds = [&](int M) { return (size_t)M * g.pitch * sizeof(T); };
     while (g.M > 1 && (lds(g.M) > 65536 || nz % g.M != 0)) g.M >>= 1;
     g.shm = lds(g.M);
     return g;
@@ -620,7 +711,7 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
 
 }  // namespace
 
-int transform_blocks(const Operator &op, int prec) { return op.nr; }
+int transform_blocks(const Operator &op, int prec) { return op.nr / transform_rows(op.nr, prec); }
 
 // ---- batched launchers -------------------------------------------------------
 void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm)
@@ -630,7 +721,7 @@ void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch
     *Lp = nr / *S;
     *pitch = nr + nr / *Lp + 1;
     const size_t el = (prec == AXIPCG_PREC_FP32) ? sizeof(float) : sizeof(double);
-    *shm = ((size_t)M * *pitch + 3 * (size_t)nr) * el;
+    *shm = (size_t)M * *pitch * el;
 }
 
 template <typename T>
