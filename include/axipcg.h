@@ -120,6 +120,20 @@ int axipcg_rhs_from_f(axipcg_op_t op, const double *f, double *b, void *stream);
  * double, computes in float, writes z as double). */
 int axipcg_precond_apply(axipcg_op_t op, const double *r, double *z, int prec, void *stream);
 
+/* ---- single-pass preconditioner (opt-in) --------------------------------
+ * precond_apply can run as one cooperative launch instead of three: G
+ * workgroups (a power of two <= the CU count, dividing nr and nz) own strips
+ * of R = nr / G in {2, 4, 8, 16} rows, transform and eliminate them in LDS,
+ * and exchange only two reduced equations per strip and mode (the partition
+ * idea of §3 across workgroups), with two grid barriers.  Both forms compute
+ * the same B^{-1} r up to rounding.  On MI355X at 1024^2 the single pass is
+ * slower (one workgroup per CU hides less latency than four), so it is off
+ * unless set_fused enables it for the handle; fused_info reports whether it
+ * is used for `prec`, its strip count and (synchronising the device) whether
+ * a grid barrier ever gave up (host pointers, may be NULL). */
+int axipcg_op_set_fused(axipcg_op_t op, int enable);
+int axipcg_op_fused_info(axipcg_op_t op, int prec, int *active, int *strips, int *barrier_errors);
+
 /* out_host[0] = ||b - A x||_2, out_host[1] = ||b||_2 (host double[2]).
  * b, x device.  Synchronises the stream. */
 int axipcg_residual_norm(axipcg_op_t op, const double *b, const double *x,

@@ -52,6 +52,8 @@ SIGNATURES = {
     "axipcg_rhs_from_f": ([_vp, _vp, _vp, _vp], _i),
     "axipcg_precond_apply": ([_vp, _vp, _vp, _i, _vp], _i),
     "axipcg_residual_norm": ([_vp, _vp, _vp, _dp, _vp], _i),
+    "axipcg_op_set_fused": ([_vp, _i], _i),
+    "axipcg_op_fused_info": ([_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_batch_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _d, _i, _i, _u,
                             ctypes.POINTER(Stats), _vp], _i),
@@ -193,6 +195,18 @@ def rhs_from_f(op: Op, f, b, stream=None):
 def precond_apply(op: Op, r, z, prec=PREC_FP32, stream=None):
     _check(lib().axipcg_precond_apply(op.handle, _dev(r, "r"), _dev(z, "z"), prec, _stream(stream)),
            "precond_apply")
+
+
+def op_set_fused(op: Op, enable: bool):
+    _check(lib().axipcg_op_set_fused(op.handle, int(bool(enable))), "op_set_fused")
+
+
+def op_fused_info(op: Op, prec=PREC_FP32, want_errors=False):
+    """(active, strips, barrier_errors or None); want_errors synchronises the device."""
+    act, strips, errs = _i(), _i(), _i()
+    _check(lib().axipcg_op_fused_info(op.handle, prec, ctypes.byref(act), ctypes.byref(strips),
+                                      ctypes.byref(errs) if want_errors else None), "op_fused_info")
+    return bool(act.value), strips.value, (errs.value if want_errors else None)
 
 
 def residual_norm(op: Op, b, x, stream=None):

@@ -67,6 +67,14 @@ enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_BZERO = 4 };
 
 constexpr int MAX_PARTIALS = 16384;
 
+// Launch plan of the single-pass preconditioner for one precision.
+struct PfPlan {
+    int state = 0;   // 0 not planned, 1 usable, -1 not usable (three launches)
+    int G = 0, R = 0, L2 = 0, RP = 1;
+    size_t shm = 0;
+    void *fn = nullptr;
+};
+
 struct Operator {
     int nr = 0, nz = 0, bc_z = 0;
     double lr = 0, lz = 0, hr = 0, hz = 0;
@@ -101,6 +109,14 @@ struct Operator {
     double *dscal = nullptr;         // 16 device scalars (residual norms)
     PcgState *state_host = nullptr;  // pinned mirror
     double *scratch_host = nullptr;  // pinned host scalars
+
+    // single-pass preconditioner (pfused.hip): plan per precision [FP64, FP32]
+    PfPlan pf[2];
+    bool fused_enabled = false;      // axipcg_op_set_fused (opt-in)
+    void *pf_work = nullptr;         // reduced equations and unknowns
+    size_t pf_work_bytes = 0;
+    unsigned *pf_bar = nullptr;      // grid barrier words: generation, then one flag per workgroup
+    int *pf_err = nullptr;           // set when a grid barrier gave up
 
     // per-kernel timing (axipcg_profile_*)
     int prof_kernel = -1;

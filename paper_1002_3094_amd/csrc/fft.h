@@ -41,16 +41,29 @@ __device__ inline cx<T> ld_tw(const typename vec2_of<T>::type *tw, int k)
 // Returns the buffer holding the result.  All threads of the block take part;
 // the block must be synchronised on entry.
 template <typename T>
+__device__ cx<T> *fft_stockham_part(cx<T> *a, cx<T> *b, int N, const typename vec2_of<T>::type *__restrict__ tw,
+                                    int tid, int nthr);
+
+template <typename T>
 __device__ cx<T> *fft_stockham(cx<T> *a, cx<T> *b, int N,
                                const typename vec2_of<T>::type *__restrict__ tw)
 {
+    return fft_stockham_part<T>(a, b, N, tw, threadIdx.x, blockDim.x);
+}
+
+// The same FFT run by `nthr` threads of the block (local index `tid`); the
+// block's other threads may run other FFTs of the same length alongside, as
+// every pass ends with a block-wide barrier.
+template <typename T>
+__device__ cx<T> *fft_stockham_part(cx<T> *a, cx<T> *b, int N, const typename vec2_of<T>::type *__restrict__ tw,
+                                    int tid, int nthr)
+{
     cx<T> *src = a, *dst = b;
     int Ns = 1;
-    const int nthr = blockDim.x;
     while ((Ns << 2) <= N) {
         const int Q = N >> 2;
         const int stride = N / (Ns << 2);
-        for (int j = threadIdx.x; j < Q; j += nthr) {
+        for (int j = tid; j < Q; j += nthr) {
             const int jm = j & (Ns - 1);
             cx<T> v0 = src[j], v1 = src[j + Q], v2 = src[j + 2 * Q], v3 = src[j + 3 * Q];
             if (Ns > 1) {
@@ -75,7 +88,7 @@ __device__ cx<T> *fft_stockham(cx<T> *a, cx<T> *b, int N,
     if (Ns < N) {  // one radix-2 pass (odd log2 N)
         const int Q = N >> 1;
         const int stride = N / (Ns << 1);
-        for (int j = threadIdx.x; j < Q; j += nthr) {
+        for (int j = tid; j < Q; j += nthr) {
             const int jm = j & (Ns - 1);
             cx<T> v0 = src[j], v1 = src[j + Q];
             if (Ns > 1) v1 = cmul(v1, ld_tw<T>(tw, jm * stride));

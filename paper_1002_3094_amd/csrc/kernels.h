@@ -54,6 +54,11 @@ void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 // z = B^{-1} r with three launches (forward, r-solves, inverse).
 void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s);
 
+// The same in one cooperative launch (pfused.hip), when pfused_plan accepts
+// the operator's geometry for this precision.
+bool pfused_plan(Operator &op, int prec);
+void pfused_apply(const Operator &op, const double *r, double *z, int prec, hipStream_t s);
+
 // ---- batched solve: one launch per PCG phase covers every problem ----------
 void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm);
 void launch_b_init(const ProbDesc *d, int n, int rows, hipStream_t s);

@@ -184,7 +184,8 @@ void free_op(Operator *op)
     if (!op) return;
     void *ptrs[] = {op->D, op->CR, op->CZ, op->W, op->cb64, op->db64, op->rw64, op->lam64, op->cb32,
                     op->db32, op->rw32, op->lam32, op->tw64, op->pt64, op->tw32, op->pt32, op->r,
-                    op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->state, op->dscal};
+                    op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->state, op->dscal,
+                    op->pf_work, op->pf_bar, op->pf_err};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : op->prof_events) (void)hipEventDestroy(e);
@@ -243,6 +244,10 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         dmalloc(&op->partials, (size_t)NUM_SLOTS * MAX_PARTIALS);
         dmalloc(&op->state, 1);
         dmalloc(&op->dscal, 16);
+        AXI_CHECK_HIP(hipMalloc((void **)&op->pf_bar, (1 + 256) * sizeof(unsigned)));
+        AXI_CHECK_HIP(hipMalloc((void **)&op->pf_err, sizeof(int)));
+        AXI_CHECK_HIP(hipMemsetAsync(op->pf_bar, 0, (1 + 256) * sizeof(unsigned), s));
+        AXI_CHECK_HIP(hipMemsetAsync(op->pf_err, 0, sizeof(int), s));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->state_host, sizeof(PcgState), hipHostMallocDefault));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->scratch_host, 4 * sizeof(double), hipHostMallocDefault));
         AXI_CHECK_HIP(hipMemsetAsync(op->partials, 0, sizeof(double) * NUM_SLOTS * MAX_PARTIALS, s));
@@ -399,11 +404,41 @@ int axipcg_rhs_from_f(axipcg_op_t h, const double *f, double *b, void *stream)
 int axipcg_precond_apply(axipcg_op_t h, const double *r, double *z, int prec, void *stream)
 {
     return guarded([&] {
-        const Operator *op = reinterpret_cast<const Operator *>(h);
+        Operator *op = reinterpret_cast<Operator *>(h);
         AXI_REQUIRE(op && r && z, "NULL argument");
         AXI_REQUIRE(r != z, "r and z must not alias");
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
-        precond_apply_impl(*op, r, z, prec, (hipStream_t)stream);
+        if (op->fused_enabled && pfused_plan(*op, prec)) pfused_apply(*op, r, z, prec, (hipStream_t)stream);
+        else precond_apply_impl(*op, r, z, prec, (hipStream_t)stream);
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_op_set_fused(axipcg_op_t h, int enable)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        op->fused_enabled = enable != 0;
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_op_fused_info(axipcg_op_t h, int prec, int *active, int *strips, int *barrier_errors)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
+        const bool ok = op->fused_enabled && pfused_plan(*op, prec);
+        if (active) *active = ok ? 1 : 0;
+        if (strips) *strips = ok ? op->pf[prec == AXIPCG_PREC_FP32 ? 1 : 0].G : 0;
+        if (barrier_errors) {
+            int e = 0;
+            AXI_CHECK_HIP(hipDeviceSynchronize());
+            AXI_CHECK_HIP(hipMemcpy(&e, op->pf_err, sizeof(int), hipMemcpyDeviceToHost));
+            *barrier_errors = e;
+        }
         return AXIPCG_OK;
     });
 }
