@@ -287,3 +287,65 @@ def laguerre_chain(op: Operator, kappa, g, eta: float, src_i: int, src_k: int,
         us.append(x)
         stats.append((st, it, rel))
     return us, stats
+
+
+def energy_bounds(op: Operator):
+    """Energy-equivalence constants of eq. (7) for B = the same scheme with
+    kbar, qbar in place of kappa, q (§4.2 eqs. (36)-(37)): both quadratic forms
+    are sums over faces of conductance * (difference)^2 plus sums over cells of
+    w * u^2, so gamma1 / gamma2 are the smallest / largest ratio of matching
+    terms (faces and cells where B's term is non-zero)."""
+    B = operator_from_cells(np.full((op.nr, op.nz), op.kbar), np.full((op.nr, op.nz), op.qbar),
+                            op.lr, op.lz, op.bc_z, op.kbar, op.qbar)
+    ratios = []
+    for a, b in ((op.cr, B.cr), (op.cz, B.cz), (op.w, B.w)):
+        m = b > 0
+        if m.any():
+            ratios.append(a[m] / b[m])
+    allr = np.concatenate([x.ravel() for x in ratios])
+    return float(allr.min()), float(allr.max())
+
+
+def cheb_alpha(m: int, rho2: float) -> float:
+    """alpha_m of the Chebyshev parameters of eq. (8): alpha_1 = 1,
+    alpha_2 = 2 / (2 - rho0^2), alpha_{k+1} = 4 / (4 - rho0^2 alpha_k)."""
+    if m == 1:
+        return 1.0
+    a = 2.0 / (2.0 - rho2)
+    for _ in range(2, m):
+        a = 4.0 / (4.0 - rho2 * a)
+    return a
+
+
+def cheb(op: Operator, b, x0=None, gamma1=None, gamma2=None, rtol=1e-13, maxit=500, iters=None):
+    """The two-step iteration of §2.2 eq. (8),
+        B (ybar - y_k) / tau + A y_k = f,   y_{k+1} = alpha_{k+1} ybar + (1 - alpha_{k+1}) y_{k-1},
+    with the Chebyshev parameters for the bounds gamma1, gamma2 of eq. (7):
+    tau = 2 / (gamma1 + gamma2), rho0 = (1 - xi) / (1 + xi), xi = gamma1 / gamma2
+    (alpha_1 = 1, so y_{-1} does not enter).  Stops when ||f - A y_k|| / ||f||
+    <= rtol, or after exactly `iters` steps when given.  Returns
+    (y, status, iterations, relres) with status 0 converged, 1 maxit."""
+    if gamma1 is None or gamma2 is None:
+        gamma1, gamma2 = energy_bounds(op)
+    f = _c(b)
+    y = np.zeros_like(f) if x0 is None else _c(x0).copy()
+    y_prev = y.copy()
+    tau = 2.0 / (gamma1 + gamma2)
+    xi = gamma1 / gamma2
+    rho2 = ((1.0 - xi) / (1.0 + xi)) ** 2
+    fn = np.linalg.norm(f)
+    if fn == 0.0:
+        return np.zeros_like(f), 0, 0, 0.0
+    k = 0
+    limit = maxit if iters is None else iters
+    while True:
+        res = f - apply(op, y)
+        rel = np.linalg.norm(res) / fn
+        if (iters is None and rel <= rtol) or k >= limit:
+            break
+        ybar = y + tau * precond(op, res)
+        a = cheb_alpha(k + 1, rho2)
+        y, y_prev = a * ybar + (1.0 - a) * y_prev, y
+        k += 1
+    status = 0 if rel <= rtol else 1
+    return y, status, k, rel
