@@ -14,6 +14,8 @@ Modes (each a fresh series of warmup + steps harmonics on the same medium):
   B  FP32 preconditioner, previous-harmonic guess
   X  FP32 preconditioner, best of u_{m-1} and the extrapolation by residual
   Z  FP32 preconditioner, zero guess (the paper's choice)
+  Y  FP32 preconditioner, extrapolation guard, Chebyshev iteration of eq. (8)
+     (the operator's own bounds; no dot products)
   C  FP32 preconditioner, learned guess with its guard (headline), the network
      trained beforehand (untimed) on harmonics of eight other media
 The first harmonics of the headline mode are checked against the FP64 oracle
@@ -58,7 +60,7 @@ def parse():
     ap.add_argument("--nr", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=101)
-    ap.add_argument("--modes", default="A,B,X,Z,C", help="comma-separated modes to run")
+    ap.add_argument("--modes", default="A,B,X,Z,Y,C", help="comma-separated modes to run")
     ap.add_argument("--headline", default="C", help="mode whose throughput is the value")
     ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--train-harmonics", type=int, default=200)
@@ -212,12 +214,13 @@ def batch_measure(ax, torch, prec, reps=3):
             "iters_min_max": [min(iters), max(iters)]}
 
 
-MODES = {
-    "A": ("fp64", "prev"),
-    "B": ("fp32", "prev"),
-    "X": ("fp32", "extrap"),
-    "Z": ("fp32", "zero"),
-    "C": ("fp32", "nn"),
+MODES = {   # (preconditioner, guess, solver)
+    "A": ("fp64", "prev", "pcg"),
+    "B": ("fp32", "prev", "pcg"),
+    "X": ("fp32", "extrap", "pcg"),
+    "Z": ("fp32", "zero", "pcg"),
+    "Y": ("fp32", "extrap", "cheb"),
+    "C": ("fp32", "nn", "pcg"),
 }
 NN_FLOP_PER_POINT = 2 * 9 * (4 * 32 + 4 * 32 * 32 + 32 * 1)   # 76 608: six 3x3 convolutions
 BF16_PEAK_TFLOPS = 2500.0
@@ -289,10 +292,10 @@ def main():
     roofline = None
     stream = torch.cuda.current_stream()
     for mode in modes:
-        prec_name, guess = MODES[mode]
+        prec_name, guess, solver = MODES[mode]
         prec = ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64
         s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
-        warm = s.run(a.warmup, guess, prec, rtol=rtol, net=net)
+        warm = s.run(a.warmup, guess, prec, rtol=rtol, net=net, solver=solver)
         assert all(c == ax.OK for c in warm.status), warm.status
         head = mode == a.headline
         if head:
@@ -300,12 +303,13 @@ def main():
             ax.profile_read(op, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st = s.run(a.steps, guess, prec, rtol=rtol, net=net)
+        st = s.run(a.steps, guess, prec, rtol=rtol, net=net, solver=solver)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         assert all(c == ax.OK for c in st.status), st.status
         elapsed = max(wall, st.gpu_ms / 1e3)
-        results[mode] = {"precond": prec_name, "guess": guess, "harmonics_per_s": round(a.steps / elapsed, 2),
+        results[mode] = {"precond": prec_name, "guess": guess, "solver": solver,
+                         "harmonics_per_s": round(a.steps / elapsed, 2),
                          "ms_per_harmonic": round(elapsed * 1e3 / a.steps, 4),
                          "iters_per_harmonic": round(float(np.mean(st.iters)), 3),
                          "us_per_iteration": round(elapsed * 1e6 / max(1, sum(st.iters)), 2)}
@@ -325,7 +329,8 @@ def main():
     # the guard's picks in the headline run (untimed replay of the same series)
     if a.headline in ("C", "X"):
         s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
-        st = s.run(n_harm, MODES[a.headline][1], ax.PREC_FP32, rtol=rtol, net=net, want_info=True)
+        st = s.run(n_harm, MODES[a.headline][1], ax.PREC_FP32, rtol=rtol, net=net, want_info=True,
+                   solver=MODES[a.headline][2])
         results[a.headline]["guard_picks_prev_extrap_net"] = np.bincount(st.choice, minlength=3).tolist()
 
     n_pts = a.nr * a.nz
@@ -367,7 +372,7 @@ def main():
                   "frac": round(tfl / BF16_PEAK_TFLOPS, 4), "flop_per_point": NN_FLOP_PER_POINT,
                   "training": training}
 
-    prec_name, guess = MODES[a.headline]
+    prec_name, guess, solver = MODES[a.headline]
     out = {
         "metric": METRIC,
         "value": results[a.headline]["harmonics_per_s"],
@@ -404,7 +409,8 @@ def main():
         st = series.SeriesStats()
         errs = []
         for uo in us:
-            s.step(guess, ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64, rtol, 1000, st, net=net)
+            s.step(guess, ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64, rtol, 1000, st, net=net,
+                   solver=solver)
             ug = s.u1.cpu().numpy()
             errs.append(float(np.linalg.norm(ug - uo) / max(np.linalg.norm(uo), 1e-300)))
         out["accuracy"] = {"harmonics_checked": len(errs), "max_rel_err_vs_oracle": max(errs) if errs else None,

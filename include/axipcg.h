@@ -151,6 +151,25 @@ int axipcg_residual_norm(axipcg_op_t op, const double *b, const double *x,
 int axipcg_pcg_solve(axipcg_op_t op, const double *b, double *x, double rtol, int maxit,
                      int prec, unsigned flags, axipcg_stats *st, void *stream);
 
+/* ---- Chebyshev iteration (§2.2 eq. (8) with Chebyshev parameters) ---------
+ * The two-step scheme of eq. (8) with tau = 2 / (gamma1 + gamma2) and
+ * alpha_1 = 1, alpha_2 = 2 / (2 - rho0^2), alpha_{k+1} = 4 / (4 - rho0^2
+ * alpha_k), rho0 = (1 - xi) / (1 + xi), xi = gamma1 / gamma2, where
+ * gamma1 <= (Au,u)/(Bu,u) <= gamma2 (eq. (7)).  Run in increment form
+ * (d_k = (alpha_{k+1} - 1) d_{k-1} + alpha_{k+1} tau B^{-1} r_k,
+ * x += d_k, r -= A d_k): no dot products except ||r||^2 for the stop test
+ * ||r_k|| / ||b|| <= rtol.  gamma1 = gamma2 = 0 takes the operator's own
+ * bounds (op_bounds); bounds that do not contain the spectrum may diverge
+ * (reported as AXIPCG_ENOTCONV or AXIPCG_EBREAKDOWN).  x: initial guess in,
+ * solution out (device).  Synchronises the stream; uses the handle's PCG
+ * workspace. */
+int axipcg_cheb_solve(axipcg_op_t op, const double *b, double *x, double gamma1, double gamma2,
+                      double rtol, int maxit, int prec, axipcg_stats *st, void *stream);
+/* The operator's energy-equivalence bounds of eq. (7) for its B: the extreme
+ * ratios kappa_face / kbar over faces with non-zero conductance and q / qbar
+ * over cells (when qbar > 0).  gamma1 is 0 when some q is 0 and qbar > 0. */
+int axipcg_op_bounds(axipcg_op_t op, double *gamma1, double *gamma2);
+
 /* ---- batched PCG over independent problems (§2.2 eq. (8) for each) ---------
  * Solve A_p x_p = b_p for p < n at once; ops[p] are distinct handles (each
  * problem uses its handle's workspace), b[p] and x[p] device pointers of that

@@ -53,6 +53,8 @@ SIGNATURES = {
     "axipcg_precond_apply": ([_vp, _vp, _vp, _i, _vp], _i),
     "axipcg_residual_norm": ([_vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_op_set_fused": ([_vp, _i], _i),
+    "axipcg_op_bounds": ([_vp, _dp, _dp], _i),
+    "axipcg_cheb_solve": ([_vp, _vp, _vp, _d, _d, _d, _i, _i, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_op_fused_info": ([_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_batch_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _d, _i, _i, _u,
@@ -222,6 +224,23 @@ def pcg_solve(op: Op, b, x, rtol=1e-10, maxit=1000, prec=PREC_FP32, flags=0, str
     code = lib().axipcg_pcg_solve(op.handle, _dev(b, "b"), _dev(x, "x"), rtol, maxit, prec, flags,
                                   ctypes.byref(st), _stream(stream))
     _check(code, "pcg_solve", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    d = st.as_dict()
+    d["code"] = code
+    return d
+
+
+def op_bounds(op: Op):
+    g1, g2 = _d(), _d()
+    _check(lib().axipcg_op_bounds(op.handle, ctypes.byref(g1), ctypes.byref(g2)), "op_bounds")
+    return g1.value, g2.value
+
+
+def cheb_solve(op: Op, b, x, gamma1=0.0, gamma2=0.0, rtol=1e-10, maxit=1000, prec=PREC_FP32, stream=None,
+               allow_notconv=True) -> dict:
+    st = Stats()
+    code = lib().axipcg_cheb_solve(op.handle, _dev(b, "b"), _dev(x, "x"), gamma1, gamma2, rtol, maxit, prec,
+                                   ctypes.byref(st), _stream(stream))
+    _check(code, "cheb_solve", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
     d = st.as_dict()
     d["code"] = code
     return d

@@ -6,7 +6,7 @@
 namespace axipcg {
 
 // Forward z-transform of every r-row (§4.2 eq. (38)).
-//  plain: spec = S rin
+//  plain: spec = S rin (with `state` set: skipped once the stop test has fired)
 //  fused PCG step (after the SpMV kernel): alpha = rho / p.q from the SpMV
 //    partials (p.q <= 0 marks a breakdown), x += alpha p, r -= alpha q,
 //    one ||r||^2 partial per workgroup, then spec = S r.
@@ -42,12 +42,18 @@ void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t 
 //  mode 0: plain;  modes 1 (PCG step) and 2 (PCG start): skipped once the
 //  stop test has fired, one r.z partial per workgroup (and r.z_old for the
 //  Polak-Ribiere form), reduced by the next SpMV kernel.
+//  modes 3 (Chebyshev step) and 4 (Chebyshev start): z is not stored; it
+//  forms the increment of eq. (8) in Chebyshev form instead,
+//  d = (alpha_m - 1) d + alpha_m tau z with m = iterations done + 1
+//  (mode 4: d = tau z), skipped once the stop test has fired.
 struct ZinvArgs {
     double *zout = nullptr;
     const double *r = nullptr;
     PcgState *state = nullptr;
     int mode = 0;
     bool pr = false;   // also reduce r.z_old (Polak-Ribiere)
+    double *d = nullptr;           // modes 3, 4
+    double tau = 0.0, rho2 = 0.0;  // modes 3, 4: Chebyshev parameters
 };
 void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s);
 

@@ -144,6 +144,43 @@ k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double
     spmv_body<PR>(z, pold, pnew, q, D, CR, CZ, nr, nz, st, partials, n_rz, blockIdx.x, gridDim.x);
 }
 
+// Chebyshev step of eq. (8) in increment form: x += d, r -= A d, ||r||^2
+// partials (one per workgroup, for the stop test of the r-solve launch);
+// workgroup 0 records the iteration being processed.
+__global__ void __launch_bounds__(256)
+k_cheb_update(const double *__restrict__ d, double *__restrict__ x, double *__restrict__ r,
+              const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
+              int nz, PcgState *st, double *__restrict__ partials)
+{
+    __shared__ double red[8];
+    if (st->done) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = st->iters;
+    double acc = 0.0;
+    for (int b = blockIdx.x; b < nr; b += gridDim.x) {
+        const int i = xcd_swizzle(b, nr);
+#pragma unroll
+        for (int j = 0; j < SPMV_PAIRS; ++j) {
+            const int k = 2 * (threadIdx.x + j * 256);
+            if (k < nz) {
+                const size_t e = (size_t)i * nz + k;
+                const Pair dc = ld2(d + e);
+                const Pair ad = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc);
+                const Pair xc = ld2(x + e), rc = ld2(r + e);
+                double2 xn, rn;
+                xn.x = xc.a + dc.a;
+                xn.y = xc.b + dc.b;
+                rn.x = rc.a - ad.a;
+                rn.y = rc.b - ad.b;
+                *reinterpret_cast<double2 *>(x + e) = xn;
+                *reinterpret_cast<double2 *>(r + e) = rn;
+                acc += rn.x * rn.x + rn.y * rn.y;
+            }
+        }
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
+}
+
 // r = b - A x; ||r||^2 and ||b||^2 partials.
 __device__ __forceinline__ void init_body(const double *__restrict__ b, const double *__restrict__ x,
                                           double *__restrict__ r, const double *__restrict__ D,
@@ -398,6 +435,85 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     return status;
 }
 
+// Chebyshev form of eq. (8): start r = b - A x, z = B^{-1} r (start test),
+// d = tau z; then per iteration x += d, r -= A d (||r||^2), forward
+// transform, r-solves (stop test), inverse transform forming the next d.  No
+// dot products beyond ||r||^2 for the stop test.
+int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, double gamma2, double rtol, int maxit,
+                    int prec, axipcg_stats *st, hipStream_t s)
+{
+    const size_t n = (size_t)op.nr * op.nz;
+    const double tau = 2.0 / (gamma1 + gamma2);
+    const double xi = gamma1 / gamma2;
+    const double rho2 = ((1.0 - xi) / (1.0 + xi)) * ((1.0 - xi) / (1.0 + xi));
+    double *d = op.p0;   // the increment lives in the first search-direction buffer
+    const unsigned gi = row_blocks(op.nr);
+    hipLaunchKernelGGL(k_pcg_init, dim3(gi), dim3(256), 0, s, b, x, op.r, op.D, op.CR, op.CZ, op.nr, op.nz,
+                       op.partials);
+    AXI_CHECK_HIP(hipGetLastError());
+    ZfwdArgs fa;
+    fa.rin = op.r;
+    launch_zfwd(op, prec, fa, s);
+    TriGate g;
+    g.mode = 2;
+    g.state = op.state;
+    g.n_rr = (int)gi;
+    g.rtol2 = rtol * rtol;
+    g.maxit = maxit;
+    g.flags = 0;
+    launch_tridiag(op, prec, g, s);
+    hipLaunchKernelGGL(k_zero_if_b_zero, dim3(pointwise_blocks(n)), dim3(256), 0, s, x, n, op.state);
+    AXI_CHECK_HIP(hipGetLastError());
+    ZinvArgs ia;
+    ia.state = op.state;
+    ia.mode = 4;
+    ia.d = d;
+    ia.tau = tau;
+    ia.rho2 = rho2;
+    launch_zinv(op, prec, ia, s);
+
+    ZfwdArgs ga;
+    ga.rin = op.r;
+    ga.state = op.state;
+    TriGate g1;
+    g1.mode = 1;
+    g1.state = op.state;
+    g1.n_rr = (int)gi;
+    ZinvArgs ib = ia;
+    ib.mode = 3;
+    int launched = 0;
+    int chunk = op.last_iters > 0 ? op.last_iters + 1 : 4;
+    for (;;) {
+        if (chunk > maxit - launched) chunk = maxit - launched;
+        for (int it = 0; it < chunk; ++it) {
+            hipLaunchKernelGGL(k_cheb_update, dim3(gi), dim3(256), 0, s, d, x, op.r, op.D, op.CR, op.CZ, op.nr, op.nz,
+                               op.state, op.partials);
+            AXI_CHECK_HIP(hipGetLastError());
+            launch_zfwd(op, prec, ga, s);
+            launch_tridiag(op, prec, g1, s);
+            launch_zinv(op, prec, ib, s);
+        }
+        launched += chunk;
+        AXI_CHECK_HIP(hipMemcpyAsync(op.state_host, op.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+        AXI_CHECK_HIP(hipStreamSynchronize(s));
+        if (op.state_host->done != ST_RUN || launched >= maxit) break;
+        chunk = 2;
+    }
+    const PcgState h = *op.state_host;
+    op.last_iters = h.iters;
+    int status;
+    if (h.done == ST_CONV || h.done == ST_BZERO) status = AXIPCG_OK;
+    else if (h.done == ST_BREAK) status = AXIPCG_EBREAKDOWN;
+    else status = AXIPCG_ENOTCONV;
+    if (st) {
+        st->iters = h.iters;
+        st->status = status;
+        st->relres_rec = (h.bb > 0) ? std::sqrt(h.rr / h.bb) : 0.0;
+        st->relres_true = -1.0;
+    }
+    return status;
+}
+
 }  // namespace
 
 void launch_b_spmv(const ProbDesc *d, int n, int rows, bool pr, int parity, hipStream_t s)
@@ -471,5 +587,26 @@ extern "C" int axipcg_pcg_solve(axipcg_op_t h, const double *b, double *x, doubl
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
         AXI_REQUIRE((flags & ~3u) == 0, "unknown flags");
         return solve_impl(*op, b, x, rtol, maxit, prec, flags, st, (hipStream_t)stream);
+    });
+}
+
+extern "C" int axipcg_cheb_solve(axipcg_op_t h, const double *b, double *x, double gamma1, double gamma2,
+                                 double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(h);
+        AXI_REQUIRE(op && b && x, "NULL argument");
+        AXI_REQUIRE(b != x, "b and x must not alias");
+        AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
+        AXI_REQUIRE(rtol > 0 && rtol < 1, "rtol must be in (0, 1)");
+        AXI_REQUIRE(maxit >= 1, "maxit must be >= 1");
+        if (gamma1 <= 0 && gamma2 <= 0) {
+            gamma1 = op->gamma1;
+            gamma2 = op->gamma2;
+        }
+        AXI_REQUIRE(std::isfinite(gamma1) && std::isfinite(gamma2) && gamma1 > 0 && gamma1 <= gamma2,
+                    "need 0 < gamma1 <= gamma2 (the operator's own bounds have gamma1 = 0 when some q is 0 "
+                    "while qbar > 0)");
+        return cheb_solve_impl(*op, b, x, gamma1, gamma2, rtol, maxit, prec, st, (hipStream_t)stream);
     });
 }

@@ -45,7 +45,7 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
 
-    if (FUSED && st->done) return;
+    if (st && st->done) return;
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
     double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
@@ -144,13 +144,26 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
 // Inverse transform: one workgroup per ROWS consecutive r-rows, FP64 output;
 // the next row's spectral values are loaded during the current row's FFT.
 // ---------------------------------------------------------------------------
+// alpha_m of eq. (8) with Chebyshev parameters: alpha_1 = 1,
+// alpha_2 = 2 / (2 - rho0^2), alpha_{k+1} = 4 / (4 - rho0^2 alpha_k).
+__device__ inline double cheb_alpha(int m, double rho2)
+{
+    if (m <= 1) return 1.0;
+    double a = 2.0 / (2.0 - rho2);
+    for (int k = 2; k < m; ++k) a = 4.0 / (4.0 - rho2 * a);
+    return a;
+}
+
 template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
 __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__restrict__ zout,
                                           const double *__restrict__ r, const PcgState *st,
                                           double *__restrict__ partials, bool pr,
                                           const typename vec2_of<T>::type *__restrict__ tw,
-                                          const typename vec2_of<T>::type *__restrict__ pt, int nr, int N, int vb)
+                                          const typename vec2_of<T>::type *__restrict__ pt, int nr, int N, int vb,
+                                          double *__restrict__ dinc = nullptr, double tau = 0.0, double rho2 = 0.0)
 {
+    constexpr bool PCGM = (MODE == 1 || MODE == 2);
+    constexpr bool CHEB = (MODE == 3 || MODE == 4);
     using V2 = typename vec2_of<T>::type;
     if (MODE != 0 && st->done) return;
     extern __shared__ char smem_raw[];
@@ -185,6 +198,12 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
     load(i0);
     const T invN = (T)1 / (T)N;
     double rz = 0.0, rzo = 0.0;
+    double c1 = 0.0, c2 = 0.0;
+    if (CHEB) {
+        const double alpha = cheb_alpha(st->iters + 1, rho2);
+        c1 = alpha - 1.0;
+        c2 = alpha * tau;
+    }
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
         const size_t row = (size_t)(i0 + s) * N;
@@ -200,7 +219,7 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
         // r (and the old z) of this row, and the next row's spectral values,
         // are in flight during the FFT
         double rv[KPT], zo[KPT];
-        if (MODE != 0) {
+        if (PCGM) {
 #pragma unroll
             for (int j = 0; j < KPT; ++j) {
                 const int k = threadIdx.x + j * blockDim.x;
@@ -221,15 +240,20 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
             T v = res[n].x * invN;
             if (BC == DIR && (k & 1)) v = -v;
             const double zv = (double)v;
-            if (MODE != 0) {
+            if (PCGM) {
                 if (pr) rzo += rv[j] * zo[j];
                 rz += rv[j] * zv;
             }
-            zout[row + k] = zv;
+            if (CHEB) {
+                if (MODE == 4) dinc[row + k] = c2 * zv;
+                else dinc[row + k] = c1 * dinc[row + k] + c2 * zv;
+            } else {
+                zout[row + k] = zv;
+            }
         }
         if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
     }
-    if (MODE != 0) {
+    if (PCGM) {
         const double s = block_sum(rz, red);
         if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + vb] = s;
         if (pr) {
@@ -244,9 +268,10 @@ __global__ void __launch_bounds__(256)
 k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
        const PcgState *st, double *__restrict__ partials, bool pr,
        const typename vec2_of<T>::type *__restrict__ tw,
-       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
+       const typename vec2_of<T>::type *__restrict__ pt, int nr, int N, double *__restrict__ dinc, double tau,
+       double rho2)
 {
-    zinv_body<T, BC, MODE, TWLDS, ROWS>(spec, zout, r, st, partials, pr, tw, pt, nr, N, blockIdx.x);
+    zinv_body<T, BC, MODE, TWLDS, ROWS>(spec, zout, r, st, partials, pr, tw, pt, nr, N, blockIdx.x, dinc, tau, rho2);
 }
 
 // ---------------------------------------------------------------------------
@@ -519,11 +544,14 @@ __global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, 
     const ProbDesc &P = d[p];
     const double *pnew = parity ? P.p0 : P.p1;   // written by this iteration's SpMV
     const int vb = blockIdx.x - P.row_start;
+    // the start-up transform runs before the r-solve launch resets the state,
+    // so only the in-loop (fused) transform may read the stop flag
+    PcgState *st = FUSED ? P.state : nullptr;
     if (P.bc_z == DIR)
-        zfwd_body<T, DIR, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr, (T *)P.spec,
+        zfwd_body<T, DIR, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec,
                                         pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
     else
-        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, P.state, P.partials, P.nr,
+        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr,
                                                      (T *)P.spec, pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
 }
 
@@ -608,7 +636,7 @@ void zfwd_ttr(const Operator &op, const ZfwdArgs &a, hipStream_t s)
                            a.state, op.partials, a.n_pq, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
     else
         hipLaunchKernelGGL((k_zfwd<T, BC, false, TWL, ROWS>), grid, dim3(thr), shm, s, a.rin, nullptr, nullptr,
-                           nullptr, nullptr, nullptr, op.partials, 0, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
+                           nullptr, nullptr, a.state, op.partials, 0, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
     AXI_CHECK_HIP(hipGetLastError());
 }
 
@@ -636,15 +664,23 @@ void zinv_ttr(const Operator &op, const ZinvArgs &a, hipStream_t s)
     switch (a.mode) {
     case 0:
         hipLaunchKernelGGL((k_zinv<T, BC, 0, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
-                           nullptr, nullptr, op.partials, false, tb.tw, tb.pt, op.nr, N);
+                           nullptr, nullptr, op.partials, false, tb.tw, tb.pt, op.nr, N, nullptr, 0.0, 0.0);
         break;
     case 1:
         hipLaunchKernelGGL((k_zinv<T, BC, 1, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
-                           a.r, a.state, op.partials, a.pr, tb.tw, tb.pt, op.nr, N);
+                           a.r, a.state, op.partials, a.pr, tb.tw, tb.pt, op.nr, N, nullptr, 0.0, 0.0);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_zinv<T, BC, 2, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
+                           a.r, a.state, op.partials, false, tb.tw, tb.pt, op.nr, N, nullptr, 0.0, 0.0);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_zinv<T, BC, 3, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, nullptr,
+                           nullptr, a.state, op.partials, false, tb.tw, tb.pt, op.nr, N, a.d, a.tau, a.rho2);
         break;
     default:
-        hipLaunchKernelGGL((k_zinv<T, BC, 2, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,
-                           a.r, a.state, op.partials, false, tb.tw, tb.pt, op.nr, N);
+        hipLaunchKernelGGL((k_zinv<T, BC, 4, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, nullptr,
+                           nullptr, a.state, op.partials, false, tb.tw, tb.pt, op.nr, N, a.d, a.tau, a.rho2);
         break;
     }
     AXI_CHECK_HIP(hipGetLastError());

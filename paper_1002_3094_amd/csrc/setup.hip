@@ -287,6 +287,37 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         const double qb = qbar >= 0 ? qbar : op->scratch_host[1] / (double)n;
         op->kbar = kb;
         op->qbar = qb;
+        // energy-equivalence bounds of eq. (7) for B (kbar, qbar): both
+        // quadratic forms are sums of face terms (conductance x squared
+        // difference) and cell terms (r q u^2), so gamma1 / gamma2 are the
+        // extreme ratios of matching terms where B's is non-zero
+        {
+            double g1 = INFINITY, g2 = 0.0;
+            auto acc = [&](double v) {
+                g1 = v < g1 ? v : g1;
+                g2 = v > g2 ? v : g2;
+            };
+            const bool dir = bc_z == AXIPCG_Z_DIRICHLET;
+            for (int i = 0; i < nr; ++i)
+                for (int k = 0; k < nz; ++k) {
+                    const size_t e = (size_t)i * nz + k;
+                    if (kappa_cells) {
+                        const double kc = kappa_cells[e];
+                        acc((i + 1 < nr ? 0.5 * (kc + kappa_cells[e + nz]) : kc) / kb);   // r-face i+1/2
+                        if (k + 1 < nz) acc(0.5 * (kc + kappa_cells[e + 1]) / kb);        // z-face k+1/2
+                        if (dir && (k == 0 || k == nz - 1)) acc(kc / kb);                 // Dirichlet z-faces
+                    } else {
+                        acc(kappa_r[e] / kb);
+                        const size_t f = (size_t)i * (nz + 1) + k;
+                        if (k > 0) acc(kappa_z[f] / kb);
+                        if (dir && k == 0) acc(kappa_z[f] / kb);
+                        if (dir && k == nz - 1) acc(kappa_z[f + 1] / kb);
+                    }
+                    if (qb > 0) acc(q[e] / qb);
+                }
+            op->gamma1 = g1;
+            op->gamma2 = g2;
+        }
         const int tb = (nr > nz ? nr : nz);
         hipLaunchKernelGGL(k_tables, dim3((tb + 255) / 256), dim3(256), 0, s, *op, kb, qb);
         AXI_CHECK_HIP(hipGetLastError());
@@ -414,6 +445,17 @@ int axipcg_precond_apply(axipcg_op_t h, const double *r, double *z, int prec, vo
     });
 }
 
+int axipcg_op_bounds(axipcg_op_t h, double *gamma1, double *gamma2)
+{
+    return guarded([&] {
+        const Operator *op = reinterpret_cast<const Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        if (gamma1) *gamma1 = op->gamma1;
+        if (gamma2) *gamma2 = op->gamma2;
+        return AXIPCG_OK;
+    });
+}
+
 int axipcg_op_set_fused(axipcg_op_t h, int enable)
 {
     return guarded([&] {
@@ -467,7 +509,7 @@ const char *axipcg_strerror(int code)
     case AXIPCG_EINVAL: return "invalid argument";
     case AXIPCG_ENOMEM: return "out of memory";
     case AXIPCG_EDEVICE: return "device error";
-    case AXIPCG_EBREAKDOWN: return "PCG breakdown";
+    case AXIPCG_EBREAKDOWN: return "iteration breakdown (non-positive or non-finite scalar)";
     default: return "unknown status";
     }
 }

@@ -58,8 +58,9 @@ class LaguerreSeries:
         self.m = 0
 
     def step(self, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats,
-             net=None, lr: float | None = None, want_info: bool = False):
-        """Solve harmonic self.m; afterwards self.u1 holds u_m."""
+             net=None, lr: float | None = None, want_info: bool = False, solver: str = "pcg"):
+        """Solve harmonic self.m (PCG, or the Chebyshev iteration of eq. (8)
+        with the operator's own bounds); afterwards self.u1 holds u_m."""
         m = self.m
         ax.laguerre_rhs(self.op, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
                         u_prev=(self.u1 if m > 0 else None), coef=self.coef)
@@ -81,7 +82,10 @@ class LaguerreSeries:
                 stats.choice.append(r[1])
         else:
             raise ValueError(f"unknown guess {guess!r}")
-        st = ax.pcg_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
+        if solver == "cheb":
+            st = ax.cheb_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
+        else:
+            st = ax.pcg_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
         stats.iters.append(st["iters"])
         stats.status.append(st["code"])
         if guess == "nn" and lr is not None:
@@ -92,7 +96,7 @@ class LaguerreSeries:
         self.m += 1
 
     def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000, net=None,
-            lr: float | None = None, want_info: bool = False) -> SeriesStats:
+            lr: float | None = None, want_info: bool = False, solver: str = "pcg") -> SeriesStats:
         """Solve the next n harmonics, timed with events on the current stream."""
         torch = self.torch
         stats = SeriesStats()
@@ -101,7 +105,7 @@ class LaguerreSeries:
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(n):
-            self.step(guess, prec, rtol, maxit, stats, net=net, lr=lr, want_info=want_info)
+            self.step(guess, prec, rtol, maxit, stats, net=net, lr=lr, want_info=want_info, solver=solver)
         e1.record(stream)
         torch.cuda.synchronize()
         stats.gpu_ms = e0.elapsed_time(e1)

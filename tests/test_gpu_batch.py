@@ -48,6 +48,16 @@ def test_small_uneven_batch_matches_oracle(ax, orc, prec):
         err = rel(host(xs[k]), refs[k])
         log(f"  member {k} {SMALL[k]} iters={st[k]['iters']} true={st[k]['relres_true']:.1e} err={err:.1e}")
         assert st[k]["status"] == ax.OK and st[k]["relres_true"] <= 1e-9 and err <= 1e-8
+    # a second solve on the same handles starts from their finished state
+    # (stop flags set by the first): it must run the full iteration again
+    first = [host(x).copy() for x in xs]
+    for x in xs:
+        x.zero_()
+    code2, st2 = ax.batch_solve(ops, bs, xs, 1e-10, 500, prec, ax.FLAG_TRUE_RESIDUAL)
+    assert code2 == ax.OK
+    for k in range(len(ops)):
+        assert st2[k]["iters"] == st[k]["iters"] and st2[k]["relres_true"] <= 1e-9
+        np.testing.assert_array_equal(host(xs[k]), first[k])
     for op in ops:
         op.close()
 
