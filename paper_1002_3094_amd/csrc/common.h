@@ -215,10 +215,21 @@ __device__ inline double block_sum(double v, double *sm)
 
 // Sum of parts[0..n) in a fixed order (strided per thread, then the block
 // tree), returned in every thread.  `sm` needs blockDim.x / 64 + 1 doubles.
+// Each thread issues its (up to eight) loads before the first add, so the
+// reads of one round are in flight together rather than one latency apiece.
 __device__ inline double block_total(const double *__restrict__ parts, int n, double *sm)
 {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += parts[i];
+    const int nt = blockDim.x;
+    for (int base = 0; base < n; base += 8 * nt) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = base + (int)threadIdx.x + j * nt;
+            v[j] = (i < n) ? parts[i] : 0.0;
+        }
+        s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
     s = block_sum(s, sm);
     const int nw = (blockDim.x + 63) >> 6;
     if (threadIdx.x == 0) sm[nw] = s;

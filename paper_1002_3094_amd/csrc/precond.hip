@@ -3,6 +3,7 @@
 // system.
 #include "fft.h"
 #include "kernels.h"
+#include "wfft.h"
 
 namespace axipcg {
 
@@ -20,7 +21,20 @@ template <typename T>
 __device__ inline const typename vec2_of<T>::type *stage_twiddles(const typename vec2_of<T>::type *tw,
                                                                   typename vec2_of<T>::type *lds, int N)
 {
-    for (int k = threadIdx.x; k < N; k += blockDim.x) lds[k] = tw[k];
+    // eight loads in flight per round (N <= 2048, >= 64 threads: at most four rounds)
+    for (int base = 0; base < N; base += 8 * (int)blockDim.x) {
+        typename vec2_of<T>::type v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = base + (int)threadIdx.x + j * (int)blockDim.x;
+            if (k < N) v[j] = tw[k];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int k = base + (int)threadIdx.x + j * (int)blockDim.x;
+            if (k < N) lds[k] = v[j];
+        }
+    }
     return lds;
 }
 
@@ -45,7 +59,6 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
 
-    if (st && st->done) return;
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
     double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
@@ -68,7 +81,20 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     };
     // issue the first row's loads before the p.q reduction so the latencies overlap
     load(i0);
+    // post-twiddles exp(-i pi m / 2N) of this thread's outputs (the same for every row)
+    T pwx[KPT], pwy[KPT];
+#pragma unroll
+    for (int j = 0; j < KPT; ++j) {
+        const int k = threadIdx.x + j * blockDim.x;
+        if (k < N) {
+            const cx<T> w = ld_tw<T>(pt, (BC == DIR) ? N - 1 - k : k);
+            pwx[j] = w.x;
+            pwy[j] = w.y;
+        }
+    }
     const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
+    // the stop flag is read once the row's loads are in flight
+    if (st && st->done) return;
     double alpha = 0.0;
     if (FUSED) {
         const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
@@ -114,10 +140,12 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
         if (s + 1 < ROWS) load(i0 + s + 1);
         __syncthreads();
         const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
-        for (int j = threadIdx.x; j < N; j += blockDim.x) {
+#pragma unroll
+        for (int q = 0; q < KPT; ++q) {
+            const int j = threadIdx.x + q * blockDim.x;
+            if (j >= N) continue;
             const int m = (BC == DIR) ? N - 1 - j : j;
-            const cx<T> w = ld_tw<T>(pt, m);
-            const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
+            const T Y = Vr[m].x * pwx[q] - Vr[m].y * pwy[q];
             const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
             spec[row + j] = nrm * (edge ? half : (T)1) * Y;
         }
@@ -165,13 +193,11 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
     constexpr bool PCGM = (MODE == 1 || MODE == 2);
     constexpr bool CHEB = (MODE == 3 || MODE == 4);
     using V2 = typename vec2_of<T>::type;
-    if (MODE != 0 && st->done) return;
     extern __shared__ char smem_raw[];
     cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *b = a + N;
     V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
-    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
 
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
@@ -196,6 +222,9 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
         }
     };
     load(i0);
+    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
+    // the stop flag is read once the row's loads are in flight
+    if (MODE != 0 && st->done) return;
     const T invN = (T)1 / (T)N;
     double rz = 0.0, rzo = 0.0;
     double c1 = 0.0, c2 = 0.0;
@@ -275,6 +304,280 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
 }
 
 // ---------------------------------------------------------------------------
+// One-wavefront-per-row transforms for N = 128 R2 (R2 = 4, 8, 16): the
+// sequence v of Makhoul's reordering, read as M = N/2 complex numbers
+// z[n] = v[2n] + i v[2n+1], is transformed with one length-M FFT (wfft.h)
+// and split into the length-N spectrum of v:
+//     V_m = (Z_m + conj Z_{M-m}) / 2 - i w_N^m (Z_m - conj Z_{M-m}) / 2,
+// V_{N-m} = conj V_m.  Each wave owns one row; the workgroup's WR waves meet
+// only for the partial sums.  Lane l loads and stores the element pairs
+// (2 l + 128 t, 2 l + 128 t + 1), t < R2, as 16-byte vectors.
+// ---------------------------------------------------------------------------
+template <typename T, int R2>
+constexpr int wave_rows() { return (sizeof(T) == 8 && R2 >= 16) ? 2 : 4; }
+
+template <typename T, int BC, bool FUSED, int R2>
+__global__ void __launch_bounds__(256)
+k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
+         const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
+         double *__restrict__ partials, int n_pq, T *__restrict__ spec,
+         const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
+         int nr)
+{
+    using G = wfft::Geo<R2>;
+    constexpr int M = G::M, N = G::N, U = G::U, WR = wave_rows<T, R2>();
+    extern __shared__ char smem_raw[];
+    __shared__ double red[8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw) + wv * G::LB;
+    T *fbuf = reinterpret_cast<T *>(buf);
+    const int row = blockIdx.x * WR + wv;
+    const bool valid = row < nr;
+    const size_t base = (size_t)(valid ? row : nr - 1) * N + 2 * lane;
+
+    // every global read first: the row (and the PCG vectors), the twiddles
+    double2 rv[R2], xv[R2], pv[R2], qv[R2];
+#pragma unroll
+    for (int t = 0; t < R2; ++t) {
+        if (FUSED) {
+            xv[t] = *reinterpret_cast<const double2 *>(x + base + 128 * t);
+            rv[t] = *reinterpret_cast<const double2 *>(r + base + 128 * t);
+            pv[t] = *reinterpret_cast<const double2 *>(p + base + 128 * t);
+            qv[t] = *reinterpret_cast<const double2 *>(q + base + 128 * t);
+        } else {
+            rv[t] = *reinterpret_cast<const double2 *>(rin + base + 128 * t);
+        }
+    }
+    wfft::Twiddles<T, R2> twd;
+    twd.load(tw, lane);
+    cx<T> wN[U][8], cP[U][8];   // w_N^m and exp(-i pi m / 2N) of this lane's outputs
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+        for (int k0 = 0; k0 < 8; ++k0) {
+            const int m = wfft::out_index<R2>(lane, j, k0) & (M - 1);
+            wN[j][k0] = ld_tw<T>(tw, m);
+            cP[j][k0] = ld_tw<T>(pt, m);
+        }
+    if (st && st->done) return;
+    double alpha = 0.0;
+    if (FUSED) {
+        const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
+        const int k_it = st->iters;
+        if (!(pq > 0.0) || !(pq < 1e308)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) st->done = ST_BREAK;
+            return;
+        }
+        alpha = st->rho[k_it & 1] / pq;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = k_it;
+    }
+
+    // r update, Makhoul reordering into the slice (even k -> v[k/2], odd k -> v[N-1-(k-1)/2])
+    double rr = 0.0;
+#pragma unroll
+    for (int t = 0; t < R2; ++t) {
+        double2 rn = rv[t];
+        if (FUSED) {
+            double2 xn;
+            xn.x = xv[t].x + alpha * pv[t].x;
+            xn.y = xv[t].y + alpha * pv[t].y;
+            rn.x = rv[t].x - alpha * qv[t].x;
+            rn.y = rv[t].y - alpha * qv[t].y;
+            if (valid) {
+                *reinterpret_cast<double2 *>(x + base + 128 * t) = xn;
+                *reinterpret_cast<double2 *>(r + base + 128 * t) = rn;
+                rr += rn.x * rn.x + rn.y * rn.y;
+            }
+        }
+        const int sv = lane + 64 * t;
+        fbuf[wfft::fslot(sv)] = (T)rn.x;
+        fbuf[wfft::fslot(N - 1 - sv)] = (BC == DIR) ? -(T)rn.y : (T)rn.y;   // sine: y_k = (-1)^k x_k
+    }
+    wfft::wave_fence();
+    cx<T> a[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) a[n2] = buf[wfft::vslot(lane + 64 * n2)];
+    cx<T> X[U][8];
+    wfft::fft<T, R2>(a, X, buf, twd, lane);
+
+    // split: the partner of Z_m is Z_{M-m}, exchanged through the slice
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if (wfft::unit_active<R2>(lane + 64 * j))
+#pragma unroll
+            for (int k0 = 0; k0 < 8; ++k0) buf[wfft::vslot(wfft::out_index<R2>(lane, j, k0))] = X[j][k0];
+    wfft::wave_fence();
+    const T nrm = (T)sqrt(2.0 / N);
+    const T half = (T)0.70710678118654752440;
+    T *srow = spec + (size_t)(valid ? row : 0) * N;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        if (!wfft::unit_active<R2>(lane + 64 * j)) continue;
+#pragma unroll
+        for (int k0 = 0; k0 < 8; ++k0) {
+            const int m = wfft::out_index<R2>(lane, j, k0);
+            const cx<T> Zm = X[j][k0];
+            T Ym, YNm;   // Y_m and Y_{N-m} (Y_M for m = 0)
+            if (m == 0) {
+                Ym = Zm.x + Zm.y;
+                YNm = (Zm.x - Zm.y) * half;
+            } else {
+                const cx<T> Zp = buf[wfft::vslot(M - m)];
+                const cx<T> sum = {Zm.x + Zp.x, Zm.y - Zp.y};        // Z_m + conj Z_{M-m}
+                const cx<T> dif = {Zm.x - Zp.x, Zm.y + Zp.y};        // Z_m - conj Z_{M-m}
+                const cx<T> wd = cmul(wN[j][k0], dif);
+                const cx<T> V = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
+                const cx<T> cv = cmul(cP[j][k0], V);
+                Ym = cv.x;
+                YNm = -cv.y;
+            }
+            const int mN = (m == 0) ? M : N - m;
+            if (valid) {
+                if (BC == DIR) {
+                    srow[N - 1 - m] = nrm * ((m == 0) ? half : (T)1) * Ym;
+                    srow[N - 1 - mN] = nrm * YNm;
+                } else {
+                    srow[m] = nrm * ((m == 0) ? half : (T)1) * Ym;
+                    srow[mN] = nrm * YNm;
+                }
+            }
+        }
+    }
+    if (FUSED) {
+        const double s = block_sum(rr, red);
+        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
+    }
+}
+
+template <typename T, int BC, int MODE, int R2>
+__global__ void __launch_bounds__(256)
+k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
+         const PcgState *st, double *__restrict__ partials, bool pr,
+         const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
+         int nr, double *__restrict__ dinc, double tau, double rho2)
+{
+    constexpr bool PCGM = (MODE == 1 || MODE == 2);
+    constexpr bool CHEB = (MODE == 3 || MODE == 4);
+    using G = wfft::Geo<R2>;
+    constexpr int M = G::M, N = G::N, U = G::U, WR = wave_rows<T, R2>();
+    extern __shared__ char smem_raw[];
+    __shared__ double red[8];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw) + wv * G::LB;
+    const T *fbuf = reinterpret_cast<const T *>(buf);
+    const int row = blockIdx.x * WR + wv;
+    const bool valid = row < nr;
+    const int rowc = valid ? row : nr - 1;
+    const size_t base = (size_t)rowc * N + 2 * lane;
+    const T *srow = spec + (size_t)rowc * N;
+
+    // spectral values Y_m, Y_{N-m}, Y_{M-m}, Y_{M+m} for m = lane + 64 n2
+    // (unnormalised DCT-II coefficients of y; Y_N = 0)
+    const T isc = (T)sqrt(0.5 * N);
+    const T sq2 = (T)1.41421356237309504880;
+    auto yidx = [&](int m) { return (BC == DIR) ? N - 1 - m : m; };
+    T y0[R2], y1[R2], y2[R2], y3[R2];
+    cx<T> cm[R2], cq[R2], wm[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        const int m = lane + 64 * n2;
+        y0[n2] = srow[yidx(m)];
+        y1[n2] = srow[yidx(m == 0 ? M : N - m)];   // (m = 0: unused)
+        y2[n2] = srow[yidx(M - m)];
+        y3[n2] = srow[yidx(M + m == N ? M : M + m)];
+        cm[n2] = ld_tw<T>(pt, m);
+        cq[n2] = ld_tw<T>(pt, M - m);
+        wm[n2] = ld_tw<T>(tw, m);
+    }
+    wfft::Twiddles<T, R2> twd;
+    twd.load(tw, lane);
+    double2 rv[R2], zo[R2], dv[R2];
+#pragma unroll
+    for (int t = 0; t < R2; ++t) {
+        if (PCGM) {
+            rv[t] = *reinterpret_cast<const double2 *>(r + base + 128 * t);
+            if (pr) zo[t] = *reinterpret_cast<const double2 *>(zout + base + 128 * t);
+        }
+        if (MODE == 3) dv[t] = *reinterpret_cast<const double2 *>(dinc + base + 128 * t);
+    }
+    if (MODE != 0 && st->done) return;
+    double c1 = 0.0, c2 = 0.0;
+    if (CHEB) {
+        const double alpha = cheb_alpha(st->iters + 1, rho2);
+        c1 = alpha - 1.0;
+        c2 = alpha * tau;
+    }
+
+    // Z'_m = E_m + i O_m with E_m = (V_m + V_{m+M}) / 2, O_m = w_N^{-m} (V_m - V_{m+M}) / 2,
+    // V_m = exp(i pi m / 2N) (Y_m - i Y_{N-m}); the FFT runs on its conjugate
+    cx<T> a[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        const int m = lane + 64 * n2;
+        const auto edge = [&](int mm) { return yidx(mm) == ((BC == DIR) ? N - 1 : 0); };
+        const T Ym = y0[n2] * isc * (edge(m) ? sq2 : (T)1);
+        const T YMm = y2[n2] * isc * (edge(M - m) ? sq2 : (T)1);
+        cx<T> Vm, Vp;   // V_m, V_{m+M}
+        if (m == 0) {
+            Vm = {Ym, (T)0};
+            Vp = {sq2 * YMm, (T)0};
+        } else {
+            const T YNm = y1[n2] * isc;
+            const T YMp = y3[n2] * isc;
+            Vm = cmul<T>({cm[n2].x, -cm[n2].y}, {Ym, -YNm});
+            const cx<T> Vq = cmul<T>({cq[n2].x, -cq[n2].y}, {YMm, -YMp});   // V_{M-m}
+            Vp = {Vq.x, -Vq.y};
+        }
+        const cx<T> E = {(T)0.5 * (Vm.x + Vp.x), (T)0.5 * (Vm.y + Vp.y)};
+        const cx<T> O = cmul<T>({wm[n2].x, -wm[n2].y}, {(T)0.5 * (Vm.x - Vp.x), (T)0.5 * (Vm.y - Vp.y)});
+        a[n2] = {E.x - O.y, -(E.y + O.x)};
+    }
+    cx<T> X[U][8];
+    wfft::fft<T, R2>(a, X, buf, twd, lane);
+
+    // z = conj(X) / M as v[2k] + i v[2k+1]; back to y through the slice
+    const T invM = (T)1 / (T)M;
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if (wfft::unit_active<R2>(lane + 64 * j))
+#pragma unroll
+            for (int k0 = 0; k0 < 8; ++k0)
+                buf[wfft::vslot(wfft::out_index<R2>(lane, j, k0))] = {X[j][k0].x * invM, -X[j][k0].y * invM};
+    wfft::wave_fence();
+    double rz = 0.0, rzo = 0.0;
+#pragma unroll
+    for (int t = 0; t < R2; ++t) {
+        const int sv = lane + 64 * t;
+        double2 zv;
+        zv.x = (double)fbuf[wfft::fslot(sv)];
+        const T yo = fbuf[wfft::fslot(N - 1 - sv)];
+        zv.y = (double)((BC == DIR) ? -yo : yo);
+        if (!valid) continue;
+        double *dst = (CHEB ? dinc : zout) + base + 128 * t;
+        if (PCGM) {
+            if (pr) rzo += rv[t].x * zo[t].x + rv[t].y * zo[t].y;
+            rz += rv[t].x * zv.x + rv[t].y * zv.y;
+        }
+        if (CHEB) {
+            double2 d;
+            d.x = (MODE == 4) ? c2 * zv.x : c1 * dv[t].x + c2 * zv.x;
+            d.y = (MODE == 4) ? c2 * zv.y : c1 * dv[t].y + c2 * zv.y;
+            *reinterpret_cast<double2 *>(dst) = d;
+        } else {
+            *reinterpret_cast<double2 *>(dst) = zv;
+        }
+    }
+    if (PCGM) {
+        const double s = block_sum(rz, red);
+        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + blockIdx.x] = s;
+        if (pr) {
+            const double so = block_sum(rzo, red);
+            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + blockIdx.x] = so;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Partitioned r-tridiagonal solve (one system per z-mode l):
 //     -cb[i-1] y[i-1] + (db[i] + r_i lam_l) y[i] - cb[i] y[i+1] = f[i].
 // A workgroup loads the [nr][M] tile of M consecutive modes into LDS; wave w
@@ -298,8 +601,9 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
                                    int vb)
 {
     if (g.mode == 1) {
-        if (st->done) return st->done;   // stopped earlier: leave the state alone
+        // partial sums first, so that their reads overlap the flag's
         const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
+        if (st->done) return st->done;   // stopped earlier: leave the state alone
         const int k_it = st->cur;
         int status = ST_RUN;
         if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
@@ -333,8 +637,9 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
 }
 
 // UNI: every active lane owns exactly LMAX rows (nr = S * LMAX), so the
-// per-row loops carry no guards.
-template <typename T, int LMAX, bool UNI>
+// per-row loops carry no guards.  V16: the tile holds M = 16 / sizeof(T)
+// modes, one 16-byte vector per row.
+template <typename T, int LMAX, bool UNI, bool V16>
 __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__restrict__ cb_g,
                                              const T *__restrict__ db_g, const T *__restrict__ rw_g,
                                              const T *__restrict__ lam, PcgState *st,
@@ -354,66 +659,117 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     const int l0 = xcd_swizzle(vb, ngroups) * M;
     auto prow = [&](int row) { return row + row / Lp; };
 
-    if (M * sizeof(T) == 16) {
-        // one 16-byte load per row
-        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
-            const T *tv = reinterpret_cast<const T *>(&v);
-            for (int m = 0; m < M; ++m) tile[m * pitch + prow(row)] = tv[m];
-        }
-    } else {
-        for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
-            const int row = e / M, m = e - row * M;
-            tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
+    // Every global read of the launch is issued before the first wait: the
+    // lane's r-line coefficients (L2), the tile of spectral values and, in
+    // PCG mode, the stop test's partial sums.
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool solver = w < M;
+    const bool active = solver && lane < S;
+    const int lo = active ? (UNI ? lane * LMAX : (int)(((long)lane * nr) / S)) : 0;
+    const int hi = active ? (UNI ? lo + LMAX : (int)(((long)(lane + 1) * nr) / S)) : 0;
+    const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
+    auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
+    // The reads below are unconditional, at indices clamped into range, so
+    // that they form one straight run of loads: the tile first (the longest
+    // trip), then the coefficients, then the partial sums of the gate.
+    auto cl = [&](int i) { return i < 0 ? 0 : (i > nr - 1 ? nr - 1 : i); };
+    constexpr int TR = 8;   // tile rows in flight per thread and round
+    constexpr int MV = 16 / (int)sizeof(T);
+    uint4 tl[TR];
+    if constexpr (V16) {
+#pragma unroll
+        for (int j = 0; j < TR; ++j) {
+            const int row = cl((int)threadIdx.x + j * (int)blockDim.x);
+            tl[j] = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
         }
     }
+    const T lm = lam[l0 + (solver ? w : 0)];
+    T fv[LMAX], dv[LMAX], cv[LMAX], rv[LMAX];
+    constexpr int VW = 16 / (int)sizeof(T);
+    if constexpr (UNI && LMAX % VW == 0) {
+        // all LMAX rows, the interface row included, as 16-byte vectors
+        // (nr = S * LMAX >= LMAX, so rows lo..lo+LMAX-1 exist for every lane)
+        typedef T V __attribute__((ext_vector_type(VW)));
+#pragma unroll
+        for (int j = 0; j < LMAX / VW; ++j) {
+            const V c4 = *reinterpret_cast<const V *>(cb + lo + j * VW);
+            const V d4 = *reinterpret_cast<const V *>(db + lo + j * VW);
+            const V r4 = *reinterpret_cast<const V *>(rw + lo + j * VW);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                cv[j * VW + e] = c4[e];
+                dv[j * VW + e] = d4[e];
+                rv[j * VW + e] = r4[e];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < LMAX; ++t) {
+            const int i = cl(lo + t);
+            dv[t] = db[i];
+            rv[t] = rw[i];
+            cv[t] = cb[i];
+        }
+    }
+    const int R = hi - 1;                        // interface row of this lane
+    const bool has_right = active && (lane + 1 < S);
+    const T cbm_ = cb[cl(lo - 1)], cbR1_ = cb[cl(R - 1)], cbR_ = cb[cl(R)];
+    const T dbR = db[cl(R)], rwR = rw[cl(R)];
+    // stop test (its partial-sum reads join the loads above)
     if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb) != ST_RUN) return;
-    __syncthreads();
 
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (w < M) {
-        T *col = tile + w * pitch;
-        const T lm = lam[l0 + w];
-        const bool active = lane < S;
-        const int lo = active ? (UNI ? lane * LMAX : (int)(((long)lane * nr) / S)) : 0;
-        const int hi = active ? (UNI ? lo + LMAX : (int)(((long)(lane + 1) * nr) / S)) : 0;
-        const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
-        auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
-
-        // prefetch the lane's data (LDS), diagonal and couplings (global)
-        T fv[LMAX], dv[LMAX], cv[LMAX];
-        constexpr int VW = 16 / (int)sizeof(T);
-        if constexpr (UNI && LMAX % VW == 0) {
-            // all LMAX rows, the interface row included, as 16-byte vectors
-            typedef T V __attribute__((ext_vector_type(VW)));
-            if (active) {
+    if constexpr (V16) {
+        for (int base = 0;; base += TR * (int)blockDim.x) {
 #pragma unroll
-                for (int j = 0; j < LMAX / VW; ++j) {
-                    const V c4 = *reinterpret_cast<const V *>(cb + lo + j * VW);
-                    const V d4 = *reinterpret_cast<const V *>(db + lo + j * VW);
-                    const V r4 = *reinterpret_cast<const V *>(rw + lo + j * VW);
+            for (int j = 0; j < TR; ++j) {
+                const int row = base + (int)threadIdx.x + j * (int)blockDim.x;
+                if (row < nr) {
+                    const T *tv = reinterpret_cast<const T *>(&tl[j]);
 #pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        cv[j * VW + e] = c4[e];
-                        dv[j * VW + e] = d4[e] + r4[e] * lm;
-                    }
+                    for (int m = 0; m < MV; ++m) tile[m * pitch + prow(row)] = tv[m];
                 }
             }
+            if (base + TR * (int)blockDim.x >= nr) break;
 #pragma unroll
-            for (int t = 0; t < LMAX; ++t)
-                if (in_seg(t)) fv[t] = col[prow(lo + t)];
-        } else {
+            for (int j = 0; j < TR; ++j) {
+                const int row = cl(base + TR * (int)blockDim.x + (int)threadIdx.x + j * (int)blockDim.x);
+                tl[j] = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
+            }
+        }
+    } else {
+        for (int base = 0; base < nr * M; base += 8 * (int)blockDim.x) {
+            T v[8];
 #pragma unroll
-            for (int t = 0; t < LMAX; ++t) {
-                if (in_seg(t)) {
-                    const int i = lo + t;
-                    fv[t] = col[prow(i)];
-                    dv[t] = db[i] + rw[i] * lm;
-                    cv[t] = cb[i];
+            for (int j = 0; j < 8; ++j) {
+                int e = base + (int)threadIdx.x + j * (int)blockDim.x;
+                e = e < nr * M ? e : nr * M - 1;
+                const int row = e / M, m = e - row * M;
+                v[j] = spec[(size_t)row * nz + l0 + m];
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int e = base + (int)threadIdx.x + j * (int)blockDim.x;
+                if (e < nr * M) {
+                    const int row = e / M, m = e - row * M;
+                    tile[m * pitch + prow(row)] = v[j];
                 }
             }
         }
-        const T cbm = (active && lo > 0) ? cb[lo - 1] : (T)0;
+    }
+
+#pragma unroll
+    for (int t = 0; t < LMAX; ++t) dv[t] += rv[t] * lm;
+    const T cbm = (active && lo > 0) ? cbm_ : (T)0;
+    const T cbR1 = active ? cbR1_ : (T)0;        // coupling interface <- last interior
+    const T cbR = has_right ? cbR_ : (T)0;
+    const T dR = active ? dbR + rwR * lm : (T)1;
+    __syncthreads();
+
+    if (solver) {
+        T *col = tile + w * pitch;
+#pragma unroll
+        for (int t = 0; t < LMAX; ++t)
+            if (in_seg(t)) fv[t] = col[prow(lo + t)];
         T cp[LMAX], gp[LMAX], vp[LMAX];
         T cprev = 0, gprev = 0, vprev = 0, inv = 1;
 #pragma unroll
@@ -430,8 +786,6 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
                 vp[t] = vprev;
             }
         }
-        const int R = hi - 1;                        // interface row of this lane
-        const T cbR1 = active ? cb[R - 1] : (T)0;    // coupling interface <- last interior
         const T wl = cbR1 * inv;                     // w' of the last interior row
         T gl = active ? gprev : (T)0, vl = active ? vprev : (T)0;
         // back-substitute to obtain the first interior values of g, v, w
@@ -449,12 +803,10 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
         const T gfn = __shfl_down(gq, 1, 64);
         const T vfn = __shfl_down(v, 1, 64);
         const T wfn = __shfl_down(ww, 1, 64);
-        const bool has_right = active && (lane + 1 < S);
-        const T cbR = has_right ? cb[R] : (T)0;
         T ra = 0, rb = 1, rc = 0, re = 0;
         if (active) {
             ra = -cbR1 * vl;
-            rb = db[R] + rw[R] * lm - cbR1 * wl - (has_right ? cbR * vfn : (T)0);
+            rb = dR - cbR1 * wl - (has_right ? cbR * vfn : (T)0);
             rc = has_right ? -cbR * wfn : (T)0;
             re = col[prow(R)] + cbR1 * gl + (has_right ? cbR * gfn : (T)0);
         }
@@ -493,11 +845,12 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
         }
     }
     __syncthreads();
-    if (M * sizeof(T) == 16) {
+    if constexpr (V16) {
         for (int row = threadIdx.x; row < nr; row += blockDim.x) {
             uint4 v;
             T *tv = reinterpret_cast<T *>(&v);
-            for (int m = 0; m < M; ++m) tv[m] = tile[m * pitch + prow(row)];
+#pragma unroll
+            for (int m = 0; m < MV; ++m) tv[m] = tile[m * pitch + prow(row)];
             *reinterpret_cast<uint4 *>(spec + (size_t)row * nz + l0) = v;
         }
     } else {
@@ -508,13 +861,14 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     }
 }
 
-template <typename T, int LMAX, bool UNI>
+template <typename T, int LMAX, bool UNI, bool V16>
 __global__ void __launch_bounds__(256)
 k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
           const T *__restrict__ rw_g, const T *__restrict__ lam, PcgState *st,
           const double *__restrict__ partials, TriGate g, int nr, int nz, int M, int S, int pitch, int Lp)
 {
-    tridiag_body<T, LMAX, UNI>(spec, cb_g, db_g, rw_g, lam, st, partials, g, nr, nz, M, S, pitch, Lp, blockIdx.x);
+    tridiag_body<T, LMAX, UNI, V16>(spec, cb_g, db_g, rw_g, lam, st, partials, g, nr, nz, M, S, pitch, Lp,
+                                    blockIdx.x);
 }
 
 // ---- batched launches ----------------------------------------------------
@@ -579,7 +933,7 @@ __global__ void __launch_bounds__(256) k_b_tridiag(const ProbDesc *__restrict__ 
     g.n_rr = P.nr;
     const bool uni = (P.nr % P.tri_S) == 0;
 #define AXI_BTRI(LM, U)                                                                                       \
-    tridiag_body<T, LM, U>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,           \
+    tridiag_body<T, LM, U, true>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,     \
                            P.partials, g, P.nr, P.nz, M, P.tri_S, P.tri_pitch, P.tri_Lp, vb)
     if (uni && P.tri_L == 2) AXI_BTRI(2, true);
     else if (uni && P.tri_L == 4) AXI_BTRI(4, true);
@@ -640,9 +994,46 @@ void zfwd_ttr(const Operator &op, const ZfwdArgs &a, hipStream_t s)
     AXI_CHECK_HIP(hipGetLastError());
 }
 
+// Rows per workgroup of the one-wave transforms for length N, 0 when N has
+// no one-wave plan (then the block-wide Stockham kernels run).
+template <typename T>
+int wave_plan_rows(int N)
+{
+    switch (N) {
+    case 512: return wave_rows<T, 4>();
+    case 1024: return wave_rows<T, 8>();
+    case 2048: return sizeof(T) == 4 ? wave_rows<T, 16>() : 0;   // FP64 at 2048 would spill
+    default: return 0;
+    }
+}
+
+template <typename T, int BC, int R2>
+void zfwd_wave(const Operator &op, const ZfwdArgs &a, hipStream_t s)
+{
+    constexpr int WR = wave_rows<T, R2>();
+    const auto tb = tables<T>(op);
+    const dim3 grid((op.nr + WR - 1) / WR), block(64 * WR);
+    const size_t shm = (size_t)WR * wfft::Geo<R2>::LB * sizeof(cx<T>);
+    if (a.fused)
+        hipLaunchKernelGGL((k_zfwd_w<T, BC, true, R2>), grid, block, shm, s, nullptr, a.x, a.r, a.p, a.q, a.state,
+                           op.partials, a.n_pq, (T *)op.spec, tb.tw, tb.pt, op.nr);
+    else
+        hipLaunchKernelGGL((k_zfwd_w<T, BC, false, R2>), grid, block, shm, s, a.rin, nullptr, nullptr, nullptr,
+                           nullptr, a.state, op.partials, 0, (T *)op.spec, tb.tw, tb.pt, op.nr);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
 template <typename T, int BC>
 void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
+    switch (op.nz) {
+    case 512: return zfwd_wave<T, BC, 4>(op, a, s);
+    case 1024: return zfwd_wave<T, BC, 8>(op, a, s);
+    case 2048:
+        if constexpr (sizeof(T) == 4) return zfwd_wave<T, BC, 16>(op, a, s);
+        break;
+    default: break;
+    }
     const bool twl = twiddles_in_lds<T>(op.nz);
     if (transform_rows(op.nr, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
         if (twl) zfwd_ttr<T, BC, true, 2>(op, a, s);
@@ -686,9 +1077,50 @@ void zinv_ttr(const Operator &op, const ZinvArgs &a, hipStream_t s)
     AXI_CHECK_HIP(hipGetLastError());
 }
 
+template <typename T, int BC, int R2>
+void zinv_wave(const Operator &op, const ZinvArgs &a, hipStream_t s)
+{
+    constexpr int WR = wave_rows<T, R2>();
+    const auto tb = tables<T>(op);
+    const dim3 grid((op.nr + WR - 1) / WR), block(64 * WR);
+    const size_t shm = (size_t)WR * wfft::Geo<R2>::LB * sizeof(cx<T>);
+    const T *spec = (const T *)op.spec;
+    switch (a.mode) {
+    case 0:
+        hipLaunchKernelGGL((k_zinv_w<T, BC, 0, R2>), grid, block, shm, s, spec, a.zout, nullptr, nullptr,
+                           op.partials, false, tb.tw, tb.pt, op.nr, nullptr, 0.0, 0.0);
+        break;
+    case 1:
+        hipLaunchKernelGGL((k_zinv_w<T, BC, 1, R2>), grid, block, shm, s, spec, a.zout, a.r, a.state, op.partials,
+                           a.pr, tb.tw, tb.pt, op.nr, nullptr, 0.0, 0.0);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_zinv_w<T, BC, 2, R2>), grid, block, shm, s, spec, a.zout, a.r, a.state, op.partials,
+                           false, tb.tw, tb.pt, op.nr, nullptr, 0.0, 0.0);
+        break;
+    case 3:
+        hipLaunchKernelGGL((k_zinv_w<T, BC, 3, R2>), grid, block, shm, s, spec, nullptr, nullptr, a.state,
+                           op.partials, false, tb.tw, tb.pt, op.nr, a.d, a.tau, a.rho2);
+        break;
+    default:
+        hipLaunchKernelGGL((k_zinv_w<T, BC, 4, R2>), grid, block, shm, s, spec, nullptr, nullptr, a.state,
+                           op.partials, false, tb.tw, tb.pt, op.nr, a.d, a.tau, a.rho2);
+        break;
+    }
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
 template <typename T, int BC>
 void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
 {
+    switch (op.nz) {
+    case 512: return zinv_wave<T, BC, 4>(op, a, s);
+    case 1024: return zinv_wave<T, BC, 8>(op, a, s);
+    case 2048:
+        if constexpr (sizeof(T) == 4) return zinv_wave<T, BC, 16>(op, a, s);
+        break;
+    default: break;
+    }
     const bool twl = twiddles_in_lds<T>(op.nz);
     if (transform_rows(op.nr, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
         if (twl) zinv_ttr<T, BC, true, 2>(op, a, s);
@@ -726,28 +1158,43 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
     const auto tb = tables<T>(op);
     const dim3 grid(op.nz / g.M), block(64 * g.M);
     T *spec = (T *)op.spec;
-#define AXI_TRI(LM, U)                                                                                   \
-    hipLaunchKernelGGL((k_tridiag<T, LM, U>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam,  \
+#define AXI_TRI(LM, U, V)                                                                                   \
+    hipLaunchKernelGGL((k_tridiag<T, LM, U, V>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam,  \
                        gate.state, op.partials, gate, op.nr, op.nz, g.M, g.S, g.pitch, g.Lp)
     const bool uni = (op.nr % g.S) == 0;
-    if (uni && g.L == 2) AXI_TRI(2, true);
-    else if (uni && g.L == 4) AXI_TRI(4, true);
-    else if (uni && g.L == 8) AXI_TRI(8, true);
-    else if (uni && g.L == 16) AXI_TRI(16, true);
-    else if (uni && g.L == 32) AXI_TRI(32, true);
-    else if (g.L <= 4) AXI_TRI(4, false);
-    else if (g.L <= 8) AXI_TRI(8, false);
-    else if (g.L <= 16) AXI_TRI(16, false);
-    else if (g.L <= 32) AXI_TRI(32, false);
-    else if (g.L <= 64) AXI_TRI(64, false);
-    else throw Error{AXIPCG_EINVAL, "nr too large for the r-solver"};
+    if (g.L > 64) throw Error{AXIPCG_EINVAL, "nr too large for the r-solver"};
+    if (g.M * sizeof(T) == 16) {
+        if (uni && g.L == 2) AXI_TRI(2, true, true);
+        else if (uni && g.L == 4) AXI_TRI(4, true, true);
+        else if (uni && g.L == 8) AXI_TRI(8, true, true);
+        else if (uni && g.L == 16) AXI_TRI(16, true, true);
+        else if (uni && g.L == 32) AXI_TRI(32, true, true);
+        else if (g.L <= 4) AXI_TRI(4, false, true);
+        else if (g.L <= 8) AXI_TRI(8, false, true);
+        else if (g.L <= 16) AXI_TRI(16, false, true);
+        else if (g.L <= 32) AXI_TRI(32, false, true);
+        else AXI_TRI(64, false, true);
+    } else {
+        // fewer modes than a 16-byte vector per row (nz = 2, or the tile of
+        // the longest lines): general element loads
+        if (g.L <= 4) AXI_TRI(4, false, false);
+        else if (g.L <= 8) AXI_TRI(8, false, false);
+        else if (g.L <= 16) AXI_TRI(16, false, false);
+        else if (g.L <= 32) AXI_TRI(32, false, false);
+        else AXI_TRI(64, false, false);
+    }
 #undef AXI_TRI
     AXI_CHECK_HIP(hipGetLastError());
 }
 
 }  // namespace
 
-int transform_blocks(const Operator &op, int prec) { return op.nr / transform_rows(op.nr, prec); }
+int transform_blocks(const Operator &op, int prec)
+{
+    const int wr = (prec == AXIPCG_PREC_FP32) ? wave_plan_rows<float>(op.nz) : wave_plan_rows<double>(op.nz);
+    if (wr > 0) return (op.nr + wr - 1) / wr;
+    return op.nr / transform_rows(op.nr, prec);
+}
 
 // ---- batched launchers -------------------------------------------------------
 void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm)

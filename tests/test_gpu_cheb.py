@@ -25,7 +25,7 @@ def ax():
     return axipcg
 
 
-CASES = [(64, 64, 0), (128, 256, 1), (96, 64, 0), (256, 256, 0)]
+CASES = [(64, 64, 0), (128, 256, 1), (96, 64, 0), (256, 256, 0), (42, 1024, 1)]
 
 
 @pytest.mark.parametrize("nr,nz,bc", CASES)

@@ -96,7 +96,10 @@ def _precond_case(ax, orc, nr, nz, bc, prec, seed=3):
 
 
 PC_SHAPES = [(64, 64, 0), (64, 64, 1), (256, 128, 0), (128, 512, 1), (100, 64, 0), (1000, 256, 0),
-             (2048, 128, 1), (4, 4, 0), (2, 2, 1), (7, 16, 0)]
+             (2048, 128, 1), (4, 4, 0), (2, 2, 1), (7, 16, 0),
+             # one-wave transforms (nz = 512, 1024, 2048), row counts that leave a
+             # workgroup partly empty
+             (130, 512, 0), (3, 512, 1), (64, 1024, 0), (37, 1024, 1), (6, 2048, 0), (33, 2048, 1)]
 
 
 @pytest.mark.parametrize("nr,nz,bc", PC_SHAPES)
@@ -118,7 +121,8 @@ def test_precond_fp32(ax, orc, nr, nz, bc):
 
 
 SOLVE_CASES = [("smooth", 64, 64, 0), ("layered", 256, 256, 0), ("layered", 128, 64, 1),
-               ("layered", 96, 256, 0), ("layered", 100, 128, 1), ("layered", 8, 4, 0)]
+               ("layered", 96, 256, 0), ("layered", 100, 128, 1), ("layered", 8, 4, 0),
+               ("layered", 66, 1024, 0), ("layered", 30, 2048, 1), ("layered", 45, 512, 1)]
 
 
 @pytest.mark.parametrize("kind,nr,nz,bc", SOLVE_CASES)
