@@ -103,13 +103,14 @@ __device__ __forceinline__ void spmv_body(const double *__restrict__ z, const do
             }
         }
         if (!have_beta) {   // scalars once per workgroup, after the first row's loads
-            // the partial sums are read before the stop flag, so that the
-            // two reads overlap (a stopped solve reads them in vain)
-            const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
-            const double rho_old = PR ? block_total(partials + SLOT_RZOLD * MAX_PARTIALS, n_rz, red) : 0.0;
             if (st->done) return;
             k_it = st->iters;
-            if (k_it > 0) beta = (rho - rho_old) / st->rho[(k_it - 1) & 1];
+            const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
+            if (k_it > 0) {
+                double num = rho;
+                if (PR) num -= block_total(partials + SLOT_RZOLD * MAX_PARTIALS, n_rz, red);
+                beta = num / st->rho[(k_it - 1) & 1];
+            }
             if (vb == 0 && threadIdx.x == 0) st->rho[k_it & 1] = rho;
             have_beta = true;
         }
@@ -152,40 +153,30 @@ k_cheb_update(const double *__restrict__ d, double *__restrict__ x, double *__re
               int nz, PcgState *st, double *__restrict__ partials)
 {
     __shared__ double red[8];
-    const int done = st->done;   // tested once the first row's loads are issued
+    if (st->done) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = st->iters;
     double acc = 0.0;
     for (int b = blockIdx.x; b < nr; b += gridDim.x) {
         const int i = xcd_swizzle(b, nr);
-        Pair dc[SPMV_PAIRS], ad[SPMV_PAIRS], xc[SPMV_PAIRS], rc[SPMV_PAIRS];
 #pragma unroll
         for (int j = 0; j < SPMV_PAIRS; ++j) {
             const int k = 2 * (threadIdx.x + j * 256);
             if (k < nz) {
                 const size_t e = (size_t)i * nz + k;
-                dc[j] = ld2(d + e);
-                ad[j] = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc[j]);
-                xc[j] = ld2(x + e);
-                rc[j] = ld2(r + e);
-            }
-        }
-        if (done) return;
-#pragma unroll
-        for (int j = 0; j < SPMV_PAIRS; ++j) {
-            const int k = 2 * (threadIdx.x + j * 256);
-            if (k < nz) {
-                const size_t e = (size_t)i * nz + k;
+                const Pair dc = ld2(d + e);
+                const Pair ad = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc);
+                const Pair xc = ld2(x + e), rc = ld2(r + e);
                 double2 xn, rn;
-                xn.x = xc[j].a + dc[j].a;
-                xn.y = xc[j].b + dc[j].b;
-                rn.x = rc[j].a - ad[j].a;
-                rn.y = rc[j].b - ad[j].b;
+                xn.x = xc.a + dc.a;
+                xn.y = xc.b + dc.b;
+                rn.x = rc.a - ad.a;
+                rn.y = rc.b - ad.b;
                 *reinterpret_cast<double2 *>(x + e) = xn;
                 *reinterpret_cast<double2 *>(r + e) = rn;
                 acc += rn.x * rn.x + rn.y * rn.y;
             }
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = st->iters;
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
 }

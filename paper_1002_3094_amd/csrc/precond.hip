@@ -59,6 +59,7 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
 
+    if (st && st->done) return;
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
     double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
@@ -81,20 +82,7 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     };
     // issue the first row's loads before the p.q reduction so the latencies overlap
     load(i0);
-    // post-twiddles exp(-i pi m / 2N) of this thread's outputs (the same for every row)
-    T pwx[KPT], pwy[KPT];
-#pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-        const int k = threadIdx.x + j * blockDim.x;
-        if (k < N) {
-            const cx<T> w = ld_tw<T>(pt, (BC == DIR) ? N - 1 - k : k);
-            pwx[j] = w.x;
-            pwy[j] = w.y;
-        }
-    }
     const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
-    // the stop flag is read once the row's loads are in flight
-    if (st && st->done) return;
     double alpha = 0.0;
     if (FUSED) {
         const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
@@ -140,12 +128,10 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
         if (s + 1 < ROWS) load(i0 + s + 1);
         __syncthreads();
         const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
-#pragma unroll
-        for (int q = 0; q < KPT; ++q) {
-            const int j = threadIdx.x + q * blockDim.x;
-            if (j >= N) continue;
+        for (int j = threadIdx.x; j < N; j += blockDim.x) {
             const int m = (BC == DIR) ? N - 1 - j : j;
-            const T Y = Vr[m].x * pwx[q] - Vr[m].y * pwy[q];
+            const cx<T> w = ld_tw<T>(pt, m);
+            const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
             const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
             spec[row + j] = nrm * (edge ? half : (T)1) * Y;
         }
@@ -193,11 +179,13 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
     constexpr bool PCGM = (MODE == 1 || MODE == 2);
     constexpr bool CHEB = (MODE == 3 || MODE == 4);
     using V2 = typename vec2_of<T>::type;
+    if (MODE != 0 && st->done) return;
     extern __shared__ char smem_raw[];
     cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *b = a + N;
     V2 *twl = reinterpret_cast<V2 *>(b + N);
     __shared__ double red[8];
+    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
 
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
@@ -222,9 +210,6 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
         }
     };
     load(i0);
-    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
-    // the stop flag is read once the row's loads are in flight
-    if (MODE != 0 && st->done) return;
     const T invN = (T)1 / (T)N;
     double rz = 0.0, rzo = 0.0;
     double c1 = 0.0, c2 = 0.0;
@@ -601,9 +586,8 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
                                    int vb)
 {
     if (g.mode == 1) {
-        // partial sums first, so that their reads overlap the flag's
-        const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
         if (st->done) return st->done;   // stopped earlier: leave the state alone
+        const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
         const int k_it = st->cur;
         int status = ST_RUN;
         if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
@@ -637,9 +621,8 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
 }
 
 // UNI: every active lane owns exactly LMAX rows (nr = S * LMAX), so the
-// per-row loops carry no guards.  V16: the tile holds M = 16 / sizeof(T)
-// modes, one 16-byte vector per row.
-template <typename T, int LMAX, bool UNI, bool V16>
+// per-row loops carry no guards.
+template <typename T, int LMAX, bool UNI>
 __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__restrict__ cb_g,
                                              const T *__restrict__ db_g, const T *__restrict__ rw_g,
                                              const T *__restrict__ lam, PcgState *st,
@@ -659,117 +642,66 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     const int l0 = xcd_swizzle(vb, ngroups) * M;
     auto prow = [&](int row) { return row + row / Lp; };
 
-    // Every global read of the launch is issued before the first wait: the
-    // lane's r-line coefficients (L2), the tile of spectral values and, in
-    // PCG mode, the stop test's partial sums.
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool solver = w < M;
-    const bool active = solver && lane < S;
-    const int lo = active ? (UNI ? lane * LMAX : (int)(((long)lane * nr) / S)) : 0;
-    const int hi = active ? (UNI ? lo + LMAX : (int)(((long)(lane + 1) * nr) / S)) : 0;
-    const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
-    auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
-    // The reads below are unconditional, at indices clamped into range, so
-    // that they form one straight run of loads: the tile first (the longest
-    // trip), then the coefficients, then the partial sums of the gate.
-    auto cl = [&](int i) { return i < 0 ? 0 : (i > nr - 1 ? nr - 1 : i); };
-    constexpr int TR = 8;   // tile rows in flight per thread and round
-    constexpr int MV = 16 / (int)sizeof(T);
-    uint4 tl[TR];
-    if constexpr (V16) {
-#pragma unroll
-        for (int j = 0; j < TR; ++j) {
-            const int row = cl((int)threadIdx.x + j * (int)blockDim.x);
-            tl[j] = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
-        }
-    }
-    const T lm = lam[l0 + (solver ? w : 0)];
-    T fv[LMAX], dv[LMAX], cv[LMAX], rv[LMAX];
-    constexpr int VW = 16 / (int)sizeof(T);
-    if constexpr (UNI && LMAX % VW == 0) {
-        // all LMAX rows, the interface row included, as 16-byte vectors
-        // (nr = S * LMAX >= LMAX, so rows lo..lo+LMAX-1 exist for every lane)
-        typedef T V __attribute__((ext_vector_type(VW)));
-#pragma unroll
-        for (int j = 0; j < LMAX / VW; ++j) {
-            const V c4 = *reinterpret_cast<const V *>(cb + lo + j * VW);
-            const V d4 = *reinterpret_cast<const V *>(db + lo + j * VW);
-            const V r4 = *reinterpret_cast<const V *>(rw + lo + j * VW);
-#pragma unroll
-            for (int e = 0; e < VW; ++e) {
-                cv[j * VW + e] = c4[e];
-                dv[j * VW + e] = d4[e];
-                rv[j * VW + e] = r4[e];
-            }
+    if (M * sizeof(T) == 16) {
+        // one 16-byte load per row
+        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
+            const T *tv = reinterpret_cast<const T *>(&v);
+            for (int m = 0; m < M; ++m) tile[m * pitch + prow(row)] = tv[m];
         }
     } else {
-#pragma unroll
-        for (int t = 0; t < LMAX; ++t) {
-            const int i = cl(lo + t);
-            dv[t] = db[i];
-            rv[t] = rw[i];
-            cv[t] = cb[i];
+        for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
+            const int row = e / M, m = e - row * M;
+            tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
         }
     }
-    const int R = hi - 1;                        // interface row of this lane
-    const bool has_right = active && (lane + 1 < S);
-    const T cbm_ = cb[cl(lo - 1)], cbR1_ = cb[cl(R - 1)], cbR_ = cb[cl(R)];
-    const T dbR = db[cl(R)], rwR = rw[cl(R)];
-    // stop test (its partial-sum reads join the loads above)
     if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb) != ST_RUN) return;
-
-    if constexpr (V16) {
-        for (int base = 0;; base += TR * (int)blockDim.x) {
-#pragma unroll
-            for (int j = 0; j < TR; ++j) {
-                const int row = base + (int)threadIdx.x + j * (int)blockDim.x;
-                if (row < nr) {
-                    const T *tv = reinterpret_cast<const T *>(&tl[j]);
-#pragma unroll
-                    for (int m = 0; m < MV; ++m) tile[m * pitch + prow(row)] = tv[m];
-                }
-            }
-            if (base + TR * (int)blockDim.x >= nr) break;
-#pragma unroll
-            for (int j = 0; j < TR; ++j) {
-                const int row = cl(base + TR * (int)blockDim.x + (int)threadIdx.x + j * (int)blockDim.x);
-                tl[j] = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
-            }
-        }
-    } else {
-        for (int base = 0; base < nr * M; base += 8 * (int)blockDim.x) {
-            T v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                int e = base + (int)threadIdx.x + j * (int)blockDim.x;
-                e = e < nr * M ? e : nr * M - 1;
-                const int row = e / M, m = e - row * M;
-                v[j] = spec[(size_t)row * nz + l0 + m];
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int e = base + (int)threadIdx.x + j * (int)blockDim.x;
-                if (e < nr * M) {
-                    const int row = e / M, m = e - row * M;
-                    tile[m * pitch + prow(row)] = v[j];
-                }
-            }
-        }
-    }
-
-#pragma unroll
-    for (int t = 0; t < LMAX; ++t) dv[t] += rv[t] * lm;
-    const T cbm = (active && lo > 0) ? cbm_ : (T)0;
-    const T cbR1 = active ? cbR1_ : (T)0;        // coupling interface <- last interior
-    const T cbR = has_right ? cbR_ : (T)0;
-    const T dR = active ? dbR + rwR * lm : (T)1;
     __syncthreads();
 
-    if (solver) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (w < M) {
         T *col = tile + w * pitch;
+        const T lm = lam[l0 + w];
+        const bool active = lane < S;
+        const int lo = active ? (UNI ? lane * LMAX : (int)(((long)lane * nr) / S)) : 0;
+        const int hi = active ? (UNI ? lo + LMAX : (int)(((long)(lane + 1) * nr) / S)) : 0;
+        const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
+        auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
+
+        // prefetch the lane's data (LDS), diagonal and couplings (global)
+        T fv[LMAX], dv[LMAX], cv[LMAX];
+        constexpr int VW = 16 / (int)sizeof(T);
+        if constexpr (UNI && LMAX % VW == 0) {
+            // all LMAX rows, the interface row included, as 16-byte vectors
+            typedef T V __attribute__((ext_vector_type(VW)));
+            if (active) {
 #pragma unroll
-        for (int t = 0; t < LMAX; ++t)
-            if (in_seg(t)) fv[t] = col[prow(lo + t)];
+                for (int j = 0; j < LMAX / VW; ++j) {
+                    const V c4 = *reinterpret_cast<const V *>(cb + lo + j * VW);
+                    const V d4 = *reinterpret_cast<const V *>(db + lo + j * VW);
+                    const V r4 = *reinterpret_cast<const V *>(rw + lo + j * VW);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e) {
+                        cv[j * VW + e] = c4[e];
+                        dv[j * VW + e] = d4[e] + r4[e] * lm;
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t)
+                if (in_seg(t)) fv[t] = col[prow(lo + t)];
+        } else {
+#pragma unroll
+            for (int t = 0; t < LMAX; ++t) {
+                if (in_seg(t)) {
+                    const int i = lo + t;
+                    fv[t] = col[prow(i)];
+                    dv[t] = db[i] + rw[i] * lm;
+                    cv[t] = cb[i];
+                }
+            }
+        }
+        const T cbm = (active && lo > 0) ? cb[lo - 1] : (T)0;
         T cp[LMAX], gp[LMAX], vp[LMAX];
         T cprev = 0, gprev = 0, vprev = 0, inv = 1;
 #pragma unroll
@@ -786,6 +718,8 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
                 vp[t] = vprev;
             }
         }
+        const int R = hi - 1;                        // interface row of this lane
+        const T cbR1 = active ? cb[R - 1] : (T)0;    // coupling interface <- last interior
         const T wl = cbR1 * inv;                     // w' of the last interior row
         T gl = active ? gprev : (T)0, vl = active ? vprev : (T)0;
         // back-substitute to obtain the first interior values of g, v, w
@@ -803,10 +737,12 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
         const T gfn = __shfl_down(gq, 1, 64);
         const T vfn = __shfl_down(v, 1, 64);
         const T wfn = __shfl_down(ww, 1, 64);
+        const bool has_right = active && (lane + 1 < S);
+        const T cbR = has_right ? cb[R] : (T)0;
         T ra = 0, rb = 1, rc = 0, re = 0;
         if (active) {
             ra = -cbR1 * vl;
-            rb = dR - cbR1 * wl - (has_right ? cbR * vfn : (T)0);
+            rb = db[R] + rw[R] * lm - cbR1 * wl - (has_right ? cbR * vfn : (T)0);
             rc = has_right ? -cbR * wfn : (T)0;
             re = col[prow(R)] + cbR1 * gl + (has_right ? cbR * gfn : (T)0);
         }
@@ -845,12 +781,11 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
         }
     }
     __syncthreads();
-    if constexpr (V16) {
+    if (M * sizeof(T) == 16) {
         for (int row = threadIdx.x; row < nr; row += blockDim.x) {
             uint4 v;
             T *tv = reinterpret_cast<T *>(&v);
-#pragma unroll
-            for (int m = 0; m < MV; ++m) tv[m] = tile[m * pitch + prow(row)];
+            for (int m = 0; m < M; ++m) tv[m] = tile[m * pitch + prow(row)];
             *reinterpret_cast<uint4 *>(spec + (size_t)row * nz + l0) = v;
         }
     } else {
@@ -861,14 +796,13 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     }
 }
 
-template <typename T, int LMAX, bool UNI, bool V16>
+template <typename T, int LMAX, bool UNI>
 __global__ void __launch_bounds__(256)
 k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
           const T *__restrict__ rw_g, const T *__restrict__ lam, PcgState *st,
           const double *__restrict__ partials, TriGate g, int nr, int nz, int M, int S, int pitch, int Lp)
 {
-    tridiag_body<T, LMAX, UNI, V16>(spec, cb_g, db_g, rw_g, lam, st, partials, g, nr, nz, M, S, pitch, Lp,
-                                    blockIdx.x);
+    tridiag_body<T, LMAX, UNI>(spec, cb_g, db_g, rw_g, lam, st, partials, g, nr, nz, M, S, pitch, Lp, blockIdx.x);
 }
 
 // ---- batched launches ----------------------------------------------------
@@ -933,7 +867,7 @@ __global__ void __launch_bounds__(256) k_b_tridiag(const ProbDesc *__restrict__ 
     g.n_rr = P.nr;
     const bool uni = (P.nr % P.tri_S) == 0;
 #define AXI_BTRI(LM, U)                                                                                       \
-    tridiag_body<T, LM, U, true>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,     \
+    tridiag_body<T, LM, U>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,           \
                            P.partials, g, P.nr, P.nz, M, P.tri_S, P.tri_pitch, P.tri_Lp, vb)
     if (uni && P.tri_L == 2) AXI_BTRI(2, true);
     else if (uni && P.tri_L == 4) AXI_BTRI(4, true);
@@ -1158,31 +1092,21 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
     const auto tb = tables<T>(op);
     const dim3 grid(op.nz / g.M), block(64 * g.M);
     T *spec = (T *)op.spec;
-#define AXI_TRI(LM, U, V)                                                                                   \
-    hipLaunchKernelGGL((k_tridiag<T, LM, U, V>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam,  \
+#define AXI_TRI(LM, U)                                                                                   \
+    hipLaunchKernelGGL((k_tridiag<T, LM, U>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam,  \
                        gate.state, op.partials, gate, op.nr, op.nz, g.M, g.S, g.pitch, g.Lp)
     const bool uni = (op.nr % g.S) == 0;
-    if (g.L > 64) throw Error{AXIPCG_EINVAL, "nr too large for the r-solver"};
-    if (g.M * sizeof(T) == 16) {
-        if (uni && g.L == 2) AXI_TRI(2, true, true);
-        else if (uni && g.L == 4) AXI_TRI(4, true, true);
-        else if (uni && g.L == 8) AXI_TRI(8, true, true);
-        else if (uni && g.L == 16) AXI_TRI(16, true, true);
-        else if (uni && g.L == 32) AXI_TRI(32, true, true);
-        else if (g.L <= 4) AXI_TRI(4, false, true);
-        else if (g.L <= 8) AXI_TRI(8, false, true);
-        else if (g.L <= 16) AXI_TRI(16, false, true);
-        else if (g.L <= 32) AXI_TRI(32, false, true);
-        else AXI_TRI(64, false, true);
-    } else {
-        // fewer modes than a 16-byte vector per row (nz = 2, or the tile of
-        // the longest lines): general element loads
-        if (g.L <= 4) AXI_TRI(4, false, false);
-        else if (g.L <= 8) AXI_TRI(8, false, false);
-        else if (g.L <= 16) AXI_TRI(16, false, false);
-        else if (g.L <= 32) AXI_TRI(32, false, false);
-        else AXI_TRI(64, false, false);
-    }
+    if (uni && g.L == 2) AXI_TRI(2, true);
+    else if (uni && g.L == 4) AXI_TRI(4, true);
+    else if (uni && g.L == 8) AXI_TRI(8, true);
+    else if (uni && g.L == 16) AXI_TRI(16, true);
+    else if (uni && g.L == 32) AXI_TRI(32, true);
+    else if (g.L <= 4) AXI_TRI(4, false);
+    else if (g.L <= 8) AXI_TRI(8, false);
+    else if (g.L <= 16) AXI_TRI(16, false);
+    else if (g.L <= 32) AXI_TRI(32, false);
+    else if (g.L <= 64) AXI_TRI(64, false);
+    else throw Error{AXIPCG_EINVAL, "nr too large for the r-solver"};
 #undef AXI_TRI
     AXI_CHECK_HIP(hipGetLastError());
 }
