@@ -265,6 +265,23 @@ int axipcg_nn_adam(axipcg_nn_t nn, double lr, double beta1, double beta2, double
 int axipcg_nn_guess(axipcg_op_t op, axipcg_nn_t nn, const double *b, const double *u1, const double *u2,
                     const double *kappa, double *x, double *resid_host, int *choice_host, void *stream);
 
+/* ---- one harmonic of a Laguerre series (§4.1 eqs. (34)-(35); §2.2 eq. (8)) --
+ * The calls a series makes for harmonic m, queued back to back so that the
+ * device never waits for the host between them: b = the right-hand side of
+ * harmonic m (laguerre_rhs, u_prev = u1 when m > 0), the initial guess into x
+ * (guess: AXIPCG_GUESS_ZERO, _PREV = u1, _EXTRAP = guess_extrap,
+ * _NN = nn_guess with nn and kappa), then the solve (solver 0: pcg_solve with
+ * flags 0; 1: cheb_solve with the operator's own bounds).  The only host wait
+ * is the solve's own state read.  Arguments, ownership and errors are those
+ * of the individual calls (nn and kappa may be NULL unless guess is _NN); x
+ * must not alias b, S1, S2, u1 or u2.  st (host, may be NULL) receives the
+ * solve's statistics; the return value is the solve's status. */
+enum { AXIPCG_GUESS_ZERO = 0, AXIPCG_GUESS_PREV = 1, AXIPCG_GUESS_EXTRAP = 2, AXIPCG_GUESS_NN = 3 };
+int axipcg_series_step(axipcg_op_t op, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k,
+                       const double *coef, double *S1, double *S2, double *b, const double *u1,
+                       const double *u2, const double *kappa, double *x, int guess, int solver,
+                       double rtol, int maxit, int prec, axipcg_stats *st, void *stream);
+
 /* ---- per-kernel timing (tracing aid) ----------------------------------------
  * Select one kernel class of the PCG iteration; pcg_solve then brackets one
  * launch in `every` (>= 1) of that class with a pair of HIP events on the

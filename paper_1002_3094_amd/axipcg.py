@@ -71,6 +71,8 @@ SIGNATURES = {
     "axipcg_nn_backward": ([_vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_nn_adam": ([_vp, _d, _d, _d, _d, _vp], _i),
     "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
+    "axipcg_series_step": ([_vp, _vp, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _i,
+                            ctypes.POINTER(Stats), _vp], _i),
     "axipcg_profile_select": ([_vp, _i, _i], _i),
     "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
@@ -377,6 +379,27 @@ def nn_guess(op: Op, net: Net, b, u1, u2, kappa, x, stream=None, want_info=True)
                                  _dev(kappa, "kappa"), _dev(x, "x"), _hp(phi) if want_info else None,
                                  ctypes.byref(choice) if want_info else None, _stream(stream)), "nn_guess")
     return (phi, choice.value) if want_info else None
+
+
+# initial-guess modes of series_step
+SERIES_GUESS = {"zero": 0, "prev": 1, "extrap": 2, "nn": 3}
+
+
+def series_step(op: Op, m: int, g_m: float, src_i: int, src_k: int, S1, S2, b, u1, u2, x, guess: str,
+                solver: str = "pcg", net=None, kappa=None, coef=None, rtol=1e-10, maxit=1000, prec=PREC_FP32,
+                stream=None, allow_notconv=True) -> dict:
+    """Harmonic m of a Laguerre series in one call: right-hand side into b,
+    initial guess into x, then the solve (PCG or Chebyshev)."""
+    st = Stats()
+    code = lib().axipcg_series_step(op.handle, net.handle if net is not None else None, m, g_m, src_i, src_k,
+                                    _opt_dev(coef, "coef"), _dev(S1, "S1"), _dev(S2, "S2"), _dev(b, "b"),
+                                    _dev(u1, "u1"), _dev(u2, "u2"), _opt_dev(kappa, "kappa"), _dev(x, "x"),
+                                    SERIES_GUESS[guess], {"pcg": 0, "cheb": 1}[solver], rtol, maxit, prec,
+                                    ctypes.byref(st), _stream(stream))
+    _check(code, "series_step", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    d = st.as_dict()
+    d["code"] = code
+    return d
 
 
 def profile_select(op: Op, kernel: int, every: int = 1):

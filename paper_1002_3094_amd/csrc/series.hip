@@ -1,0 +1,52 @@
+// One harmonic of a Laguerre series (§4.1 eqs. (34)-(35)) as one library
+// call: right-hand side, initial guess and solve are queued back to back on
+// the caller's stream, so the device does not idle while the host returns
+// between them.  Composed of the public entry points; no arithmetic here.
+#include "axipcg.h"
+#include "common.h"
+
+using namespace axipcg;
+
+extern "C" int axipcg_series_step(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k,
+                                  const double *coef, double *S1, double *S2, double *b, const double *u1,
+                                  const double *u2, const double *kappa, double *x, int guess, int solver,
+                                  double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
+{
+    int code = guarded([&] {
+        AXI_REQUIRE(hop && S1 && S2 && b && u1 && u2 && x, "NULL argument");
+        AXI_REQUIRE(m >= 0, "m must be >= 0");
+        AXI_REQUIRE(guess >= AXIPCG_GUESS_ZERO && guess <= AXIPCG_GUESS_NN, "unknown guess mode");
+        AXI_REQUIRE(solver == 0 || solver == 1, "unknown solver");
+        AXI_REQUIRE(guess != AXIPCG_GUESS_NN || (nn && kappa), "the learned guess needs nn and kappa");
+        AXI_REQUIRE(x != b && x != S1 && x != S2 && x != u1 && x != u2, "x aliases another array");
+        return AXIPCG_OK;
+    });
+    if (code != AXIPCG_OK) return code;
+    code = axipcg_laguerre_rhs(hop, g_m, src_i, src_k, coef, m > 0 ? u1 : nullptr, S1, S2, b, stream);
+    if (code != AXIPCG_OK) return code;
+    const Operator *op = reinterpret_cast<const Operator *>(hop);
+    const size_t bytes = (size_t)op->nr * op->nz * sizeof(double);
+    switch (guess) {
+    case AXIPCG_GUESS_ZERO:
+        code = guarded([&] {
+            AXI_CHECK_HIP(hipMemsetAsync(x, 0, bytes, (hipStream_t)stream));
+            return AXIPCG_OK;
+        });
+        break;
+    case AXIPCG_GUESS_PREV:
+        code = guarded([&] {
+            AXI_CHECK_HIP(hipMemcpyAsync(x, u1, bytes, hipMemcpyDeviceToDevice, (hipStream_t)stream));
+            return AXIPCG_OK;
+        });
+        break;
+    case AXIPCG_GUESS_EXTRAP:
+        code = axipcg_guess_extrap(hop, b, u1, u2, x, nullptr, nullptr, stream);
+        break;
+    default:
+        code = axipcg_nn_guess(hop, nn, b, u1, u2, kappa, x, nullptr, nullptr, stream);
+        break;
+    }
+    if (code != AXIPCG_OK) return code;
+    if (solver == 1) return axipcg_cheb_solve(hop, b, x, 0.0, 0.0, rtol, maxit, prec, st, stream);
+    return axipcg_pcg_solve(hop, b, x, rtol, maxit, prec, 0u, st, stream);
+}

@@ -62,6 +62,20 @@ class LaguerreSeries:
         """Solve harmonic self.m (PCG, or the Chebyshev iteration of eq. (8)
         with the operator's own bounds); afterwards self.u1 holds u_m."""
         m = self.m
+        if not want_info and lr is None:
+            # the whole harmonic in one library call (no host round trips
+            # between the right-hand side, the guess and the solve)
+            if guess == "nn" and (net is None or self.kappa is None):
+                raise ValueError("nn guess needs a network and kappa")
+            st = ax.series_step(self.op, m, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
+                                self.u1, self.u2, self.u, guess, solver=solver, net=net,
+                                kappa=self.kappa if guess == "nn" else None, coef=self.coef, rtol=rtol,
+                                maxit=maxit, prec=prec)
+            stats.iters.append(st["iters"])
+            stats.status.append(st["code"])
+            self.u2, self.u1, self.u = self.u1, self.u, self.u2
+            self.m += 1
+            return
         ax.laguerre_rhs(self.op, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
                         u_prev=(self.u1 if m > 0 else None), coef=self.coef)
         if guess == "zero":

@@ -1,0 +1,62 @@
+"""``axipcg_series_step`` (one call per Laguerre harmonic) against the same
+harmonic made of separate calls: identical kernels in identical order, so the
+solutions must agree bit for bit, with the same iteration counts."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev, host, log
+
+pytestmark = pytest.mark.gpu
+
+N = 128
+N_HARM = 5
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1002_3094_amd import axipcg
+    axipcg.lib()
+    return axipcg
+
+
+@pytest.mark.parametrize("guess,solver", [("zero", "pcg"), ("prev", "pcg"), ("extrap", "pcg"), ("nn", "pcg"),
+                                          ("extrap", "cheb")])
+def test_series_step_matches_separate_calls(ax, guess, solver):
+    from paper_1002_3094_amd.series import LaguerreSeries, SeriesStats, nn_init_params
+    log(f"series_step guess={guess} solver={solver}")
+    inp = synth.laguerre_series_inputs(N, N, seed=3)
+    net = ax.nn_create(N, N, nn_init_params(5, last_zero=False)) if guess == "nn" else None
+    with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
+        g = ax.laguerre_coeffs(N_HARM, inp["eta"], inp["ft"], inp["t"][-1])
+        sols, its = {}, {}
+        for path in ("separate", "one_call"):
+            s = LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+            st = SeriesStats()
+            out = []
+            for _ in range(N_HARM):
+                s.step(guess, ax.PREC_FP32, 1e-10, 1000, st, net=net, want_info=(path == "separate"), solver=solver)
+                out.append(host(s.u1).copy())
+            assert all(c == ax.OK for c in st.status)
+            sols[path], its[path] = out, st.iters
+        log(f"  iterations {its['one_call']}")
+        assert its["separate"] == its["one_call"]
+        for a, b in zip(sols["separate"], sols["one_call"]):
+            np.testing.assert_array_equal(a, b)
+    if net is not None:
+        net.close()
+
+
+def test_series_step_rejects_bad_arguments(ax):
+    inp = synth.laguerre_series_inputs(32, 32, seed=1)
+    with ax.op_create(inp["kappa"], inp["q"]) as op:
+        z = lambda: dev(np.zeros((32, 32)))  # noqa: E731
+        S1, S2, b, u1, u2, x = z(), z(), z(), z(), z(), z()
+        with pytest.raises(ax.AxipcgError):   # the learned guess without a network
+            ax.series_step(op, 0, 1.0, inp["src_i"], inp["src_k"], S1, S2, b, u1, u2, x, "nn")
+        with pytest.raises(ax.AxipcgError):   # x aliasing u1
+            ax.series_step(op, 0, 1.0, inp["src_i"], inp["src_k"], S1, S2, b, u1, u2, u1, "prev")
+        with pytest.raises(ax.AxipcgError):   # source cell out of range
+            ax.series_step(op, 0, 1.0, 99, 0, S1, S2, b, u1, u2, x, "zero")
