@@ -14,6 +14,8 @@
 // once.  The host reads the state back once per chunk of iterations.
 #include <cmath>
 
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 
 namespace axipcg {
@@ -268,14 +270,18 @@ struct SolveCtx {
     int n_tr;   // workgroups (partials) of the transform kernels
 };
 
-// Event pair around one launch of the profiled kernel class.
+// Event pair around one launch of the profiled kernel class.  With `ext`
+// the launch site hands the pair to hipExtLaunchKernelGGL, which stamps them
+// from the dispatch itself (no separate event packets around the kernel);
+// otherwise the events are recorded on the stream before and after it.
 struct ProfScope {
     Operator &op;
     hipStream_t s;
     bool on;
+    bool ext;
     size_t slot = 0;
-    ProfScope(Operator &o, hipStream_t st, int kernel, int iter)
-        : op(o), s(st), on(o.prof_kernel == kernel && (o.prof_seen++ % o.prof_every) == 0)
+    ProfScope(Operator &o, hipStream_t st, int kernel, int iter, bool ext_launch = false)
+        : op(o), s(st), on(o.prof_kernel == kernel && (o.prof_seen++ % o.prof_every) == 0), ext(ext_launch)
     {
         if (!on) return;
         slot = op.prof_used++;
@@ -286,11 +292,13 @@ struct ProfScope {
         }
         if (op.prof_iter.size() < op.prof_used) op.prof_iter.resize(op.prof_used);
         op.prof_iter[slot] = iter;
-        AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot], s));
+        if (!ext) AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot], s));
     }
+    hipEvent_t start() const { return on ? op.prof_events[2 * slot] : nullptr; }
+    hipEvent_t stop() const { return on ? op.prof_events[2 * slot + 1] : nullptr; }
     ~ProfScope() noexcept(false)
     {
-        if (on) AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot + 1], s));
+        if (on && !ext) AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot + 1], s));
     }
 };
 
@@ -301,13 +309,13 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
     double *pnew = parity ? op.p0 : op.p1;
     const unsigned gs = row_blocks(op.nr);
     {
-        ProfScope ps(op, c.s, AXIPCG_KERNEL_SPMV, iter);
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_SPMV, iter, true);
         if (c.pr)
-            hipLaunchKernelGGL(k_pcg_spmv<true>, dim3(gs), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D, op.CR,
-                               op.CZ, op.nr, op.nz, op.state, op.partials, c.n_tr);
+            hipExtLaunchKernelGGL(k_pcg_spmv<true>, dim3(gs), dim3(256), 0, c.s, ps.start(), ps.stop(), 0, op.z,
+                                  pold, pnew, op.q, op.D, op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, c.n_tr);
         else
-            hipLaunchKernelGGL(k_pcg_spmv<false>, dim3(gs), dim3(256), 0, c.s, op.z, pold, pnew, op.q, op.D,
-                               op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, c.n_tr);
+            hipExtLaunchKernelGGL(k_pcg_spmv<false>, dim3(gs), dim3(256), 0, c.s, ps.start(), ps.stop(), 0, op.z,
+                                  pold, pnew, op.q, op.D, op.CR, op.CZ, op.nr, op.nz, op.state, op.partials, c.n_tr);
         AXI_CHECK_HIP(hipGetLastError());
     }
     ZfwdArgs fa;
