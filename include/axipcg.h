@@ -204,6 +204,35 @@ int axipcg_laguerre_rhs(axipcg_op_t op, double g_m, int src_i, int src_k,
                         const double *coef, const double *u_prev,
                         double *S1, double *S2, double *b, void *stream);
 
+/* ---- Laguerre series with integer alpha >= 0 (§4.1 eqs. (34)-(35)) --------
+ * The transform of eq. (34): Q_m = int u(t) psi_m(t) dt and
+ * u(t) = sum_m Q_m phi_m(t), with psi_m(t) = sqrt(eta m!/(m+alpha)!)
+ * e^{-eta t/2} L^alpha_m(eta t) and phi_m(t) = (eta t)^alpha psi_m(t)
+ * (alpha = 0 gives the functions of axipcg_laguerre_coeffs).
+ *
+ * f_m = int_0^{t_max} f psi_m dt for m < n from nt >= 3 uniform host samples
+ * (trapezoid rule), into g_host (host double[n]); 0 <= alpha <= 64. */
+int axipcg_laguerre_coeffs_alpha(int n, int alpha, double eta, int nt, double t_max,
+                                 const double *f_host, double *g_host, void *stream);
+/* Right-hand side of harmonic m of eq. (35) with alpha:
+ *     b = r * (f_m delta_h - c * c_m * sum_{k<m} (m-k) d_k u_k),
+ *     c_m = sqrt(m!/(m+alpha)!),  d_k = sqrt((k+alpha)!/k!),
+ * through the running sums S1 += d_{m-1} u_prev, S2 += S1 (device, zero
+ * before m = 0).  u_prev is u_{m-1}: NULL exactly when m = 0.  c, delta_h,
+ * coef and aliasing rules as for axipcg_laguerre_rhs. */
+int axipcg_laguerre_rhs_alpha(axipcg_op_t op, int m, int alpha, double g_m, int src_i, int src_k,
+                              const double *coef, const double *u_prev, double *S1, double *S2,
+                              double *b, void *stream);
+/* out[j] = u[idx[j]] for j < n (receiver samples of a harmonic; u, idx, out
+ * device, idx flat indices into the op's [nr][nz] grid, 1 <= n <= 65536; an
+ * index outside the grid yields NaN). */
+int axipcg_gather(axipcg_op_t op, const double *u, const long long *idx, int n, double *out, void *stream);
+/* Time traces from harmonics (eq. (34)): traces[r][j] = sum_{m<n} Q[m][r]
+ * phi_m(t_j), t_j = j t_max/(nt-1); Q device [n][nrec], traces device
+ * [nrec][nt]. */
+int axipcg_laguerre_synth(int n, int alpha, double eta, int nrec, const double *Q, int nt, double t_max,
+                          double *traces, void *stream);
+
 /* ---- initial guess from earlier harmonics (§4.1: the harmonics are solved in
  * order, so u_{m-1} = u1 and u_{m-2} = u2 are known when harmonic m starts) ----
  * Writes to x whichever of u1 and the linear extrapolation 2 u1 - u2 has the

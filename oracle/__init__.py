@@ -58,6 +58,8 @@ def _load():
         "orc_pcg": ([i, i, d, d, i, _dp, _dp, _dp, d, d, _dp, _dp, d, i, _ip, _dp], i),
         "orc_laguerre_coeffs": ([i, d, i, d, _dp, _dp], None),
         "orc_laguerre_functions": ([i, d, i, _dp, _dp], None),
+        "orc_laguerre_psi": ([i, i, d, i, _dp, _dp], None),
+        "orc_laguerre_coeffs_a": ([i, i, d, i, d, _dp, _dp], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -256,6 +258,58 @@ def laguerre_functions(n: int, eta: float, t) -> np.ndarray:
     out = np.empty((n, len(t)))
     _load().orc_laguerre_functions(int(n), float(eta), len(t), _p(t), _p(out))
     return out
+
+
+def laguerre_psi(n: int, alpha: int, eta: float, t) -> np.ndarray:
+    """Projection kernel of the generalized transform (§4.1 eq. (34)):
+    psi_m(t) = sqrt(eta m!/(m+alpha)!) e^{-eta t/2} L^alpha_m(eta t), [n][len(t)]."""
+    t = _c(t)
+    out = np.empty((n, len(t)))
+    _load().orc_laguerre_psi(int(n), int(alpha), float(eta), len(t), _p(t), _p(out))
+    return out
+
+
+def laguerre_synthesis(n: int, alpha: int, eta: float, t) -> np.ndarray:
+    """Synthesis functions phi_m(t) = (eta t)^alpha psi_m(t) of eq. (34):
+    u(t) = sum_m Q_m phi_m(t).  [n][len(t)]."""
+    t = _c(t)
+    return laguerre_psi(n, alpha, eta, t) * (eta * t)[None, :] ** alpha
+
+
+def laguerre_coeffs_a(n: int, alpha: int, eta: float, ft, t_max: float) -> np.ndarray:
+    """f_m = int f psi_m dt (composite Simpson on uniform samples of [0, t_max])."""
+    ft = _c(ft)
+    g = np.empty(n)
+    _load().orc_laguerre_coeffs_a(int(n), int(alpha), float(eta), len(ft), float(t_max), _p(ft), _p(g))
+    return g
+
+
+def laguerre_weights(n: int, alpha: int):
+    """c_m = sqrt(m!/(m+alpha)!) and d_k = sqrt((k+alpha)!/k!) of eq. (35)."""
+    from math import lgamma, exp
+    c = np.array([exp(0.5 * (lgamma(m + 1) - lgamma(m + alpha + 1))) for m in range(n)])
+    return c, 1.0 / c
+
+
+def laguerre_chain_a(op: Operator, coef, g, alpha: int, src_i: int, src_k: int, n_harm: int,
+                     rtol=1e-13, maxit=500, guess="zero"):
+    """Harmonics of eq. (35) with general alpha:
+        A Q_m = r (g_m delta_h - coef * c_m * sum_{k<m} (m - k) d_k Q_k),
+    coef = eta^2 / rho^2 per cell; the sum is evaluated directly."""
+    us, stats = [], []
+    r = op.r[:, None]
+    c, dd = laguerre_weights(n_harm, alpha)
+    delta = point_delta_rhs(op, src_i, src_k)
+    for m in range(n_harm):
+        s = np.zeros((op.nr, op.nz))
+        for k in range(m):
+            s += (m - k) * dd[k] * us[k]
+        b = g[m] * delta - r * coef * c[m] * s
+        x0 = us[-1] if (guess == "prev" and us) else None
+        x, st, it, rel = pcg(op, b, x0, rtol, maxit)
+        us.append(x)
+        stats.append((st, it, rel))
+    return us, stats
 
 
 def point_delta_rhs(op: Operator, src_i: int, src_k: int) -> np.ndarray:

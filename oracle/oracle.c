@@ -425,3 +425,46 @@ void orc_laguerre_functions(int n, double eta, int nt, const double *t, double *
         }
     }
 }
+
+/* Generalized transform of §4.1 eq. (34) with integer alpha >= 0: the
+ * projection kernel psi_m(t) = sqrt(eta m!/(m+alpha)!) e^{-eta t/2} L^alpha_m(eta t),
+ * with L^alpha_m from its three-term recurrence
+ *   (m+1) L_{m+1} = (2m + 1 + alpha - x) L_m - (m + alpha) L_{m-1},
+ * so that Q_m = int u(t) psi_m(t) dt and u(t) = sum_m Q_m (eta t)^alpha psi_m(t).
+ * out: [n][nt]. */
+void orc_laguerre_psi(int n, int alpha, double eta, int nt, const double *t, double *out)
+{
+    for (int j = 0; j < nt; ++j) {
+        const double x = eta * t[j];
+        const double env = exp(-0.5 * x);
+        double lm1 = 0.0, l0 = 1.0;
+        for (int m = 0; m < n; ++m) {
+            const double nrm = exp(0.5 * (log(eta) + lgamma(m + 1.0) - lgamma(m + alpha + 1.0)));
+            out[(size_t)m * nt + j] = nrm * env * l0;
+            const double l1 = ((2.0 * m + 1.0 + alpha - x) * l0 - (m + alpha) * lm1) / (m + 1.0);
+            lm1 = l0;
+            l0 = l1;
+        }
+    }
+}
+
+/* f_m = int f(t) psi_m(t) dt over the uniform samples of [0, tmax] (composite
+ * Simpson; nt odd). */
+void orc_laguerre_coeffs_a(int n, int alpha, double eta, int nt, double tmax, const double *f, double *g)
+{
+    const double dt = tmax / (nt - 1);
+    double *tt = (double *)malloc(sizeof(double) * nt);
+    double *psi = (double *)malloc(sizeof(double) * (size_t)n * nt);
+    for (int j = 0; j < nt; ++j) tt[j] = j * dt;
+    orc_laguerre_psi(n, alpha, eta, nt, tt, psi);
+    for (int m = 0; m < n; ++m) {
+        double acc = 0.0;
+        for (int j = 0; j < nt; ++j) {
+            const double wgt = (j == 0 || j == nt - 1) ? 1.0 : ((j % 2) ? 4.0 : 2.0);
+            acc += wgt * f[j] * psi[(size_t)m * nt + j];
+        }
+        g[m] = acc * dt / 3.0;
+    }
+    free(psi);
+    free(tt);
+}

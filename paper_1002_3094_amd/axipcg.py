@@ -62,6 +62,10 @@ SIGNATURES = {
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_guess_extrap": ([_vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
+    "axipcg_laguerre_coeffs_alpha": ([_i, _i, _d, _i, _d, _dp, _dp, _vp], _i),
+    "axipcg_laguerre_rhs_alpha": ([_vp, _i, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
+    "axipcg_gather": ([_vp, _vp, _vp, _i, _vp, _vp], _i),
+    "axipcg_laguerre_synth": ([_i, _i, _d, _i, _vp, _i, _d, _vp, _vp], _i),
     "axipcg_nn_num_params": ([], _i),
     "axipcg_nn_create": ([_i, _i, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_vp)], _i),
     "axipcg_nn_destroy": ([_vp], None),
@@ -275,6 +279,47 @@ def laguerre_rhs(op: Op, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=N
     _check(lib().axipcg_laguerre_rhs(op.handle, g_m, src_i, src_k, _opt_dev(coef, "coef"),
                                      _opt_dev(u_prev, "u_prev"), _dev(S1, "S1"), _dev(S2, "S2"),
                                      _dev(b, "b"), _stream(stream)), "laguerre_rhs")
+
+
+def laguerre_coeffs_alpha(n: int, alpha: int, eta: float, f_samples, t_max: float, stream=None) -> np.ndarray:
+    f = _host(f_samples)
+    g = np.zeros(n)
+    _check(lib().axipcg_laguerre_coeffs_alpha(n, alpha, eta, len(f), t_max, _hp(f), _hp(g), _stream(stream)),
+           "laguerre_coeffs_alpha")
+    return g
+
+
+def laguerre_rhs_alpha(op: Op, m: int, alpha: int, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=None,
+                       coef=None, stream=None):
+    _check(lib().axipcg_laguerre_rhs_alpha(op.handle, m, alpha, g_m, src_i, src_k, _opt_dev(coef, "coef"),
+                                           _opt_dev(u_prev, "u_prev"), _dev(S1, "S1"), _dev(S2, "S2"),
+                                           _dev(b, "b"), _stream(stream)), "laguerre_rhs_alpha")
+
+
+def _dev_any(t, name, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous device tensor of {dtype}")
+    return _vp(t.data_ptr())
+
+
+def gather(op: Op, u, idx, out, stream=None):
+    """out[j] = u.flatten()[idx[j]] (idx: int64 device tensor; NaN where out of range)."""
+    import torch
+    n = idx.numel()
+    if out.numel() != n:
+        raise ValueError("out and idx must have the same length")
+    _check(lib().axipcg_gather(op.handle, _dev(u, "u"), _dev_any(idx, "idx", torch.int64), n,
+                               _dev(out, "out"), _stream(stream)), "gather")
+
+
+def laguerre_synth(alpha: int, eta: float, Q, nt: int, t_max: float, traces, stream=None):
+    """traces[r][j] = sum_m Q[m][r] phi_m(t_j) (Q [n][nrec], traces [nrec][nt], device float64)."""
+    n, nrec = Q.shape
+    if tuple(traces.shape) != (nrec, nt):
+        raise ValueError("traces must be [nrec][nt]")
+    _check(lib().axipcg_laguerre_synth(n, alpha, eta, nrec, _dev(Q, "Q"), nt, t_max, _dev(traces, "traces"),
+                                       _stream(stream)), "laguerre_synth")
 
 
 def guess_extrap(op: Op, b, u1, u2, x, stream=None, want_info=False):

@@ -126,6 +126,67 @@ class LaguerreSeries:
         return stats
 
 
+class PaperSeries:
+    """The paper's experiment (§4.3): the harmonics of eq. (35) with integer
+    alpha (alpha = 5, eta = h = 300 there), a zero or previous-harmonic
+    initial guess, the receiver samples of every harmonic, and the time
+    traces synthesised from them (eq. (34)).  ``coef`` (device or host
+    [nr][nz]) is eta^2/rho^2; ``rec_idx`` flat receiver indices."""
+
+    def __init__(self, op: "ax.Op", g, alpha: int, eta: float, src_i: int, src_k: int, coef, rec_idx):
+        import torch
+        self.torch = torch
+        self.op, self.g, self.alpha, self.eta = op, [float(v) for v in g], int(alpha), float(eta)
+        self.src_i, self.src_k = int(src_i), int(src_k)
+        shape = (op.nr, op.nz)
+        z = lambda: torch.zeros(shape, dtype=torch.float64, device="cuda")  # noqa: E731
+        self.S1, self.S2, self.b, self.u1, self.u = z(), z(), z(), z(), z()
+        self.coef = torch.as_tensor(coef, dtype=torch.float64).cuda().contiguous()
+        self.rec_idx = torch.as_tensor(rec_idx, dtype=torch.int64).cuda().contiguous()
+        self.Q = torch.zeros((len(self.g), self.rec_idx.numel()), dtype=torch.float64, device="cuda")
+        self.m = 0
+
+    def step(self, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats, solver: str = "pcg"):
+        m = self.m
+        ax.laguerre_rhs_alpha(self.op, m, self.alpha, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
+                              u_prev=(self.u1 if m > 0 else None), coef=self.coef)
+        if guess == "zero":
+            self.u.zero_()
+        elif guess == "prev":
+            self.u.copy_(self.u1)
+        else:
+            raise ValueError(f"unknown guess {guess!r}")
+        if solver == "cheb":
+            st = ax.cheb_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
+        else:
+            st = ax.pcg_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
+        stats.iters.append(st["iters"])
+        stats.status.append(st["code"])
+        ax.gather(self.op, self.u, self.rec_idx, self.Q[m])
+        self.u1, self.u = self.u, self.u1
+        self.m += 1
+
+    def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000,
+            solver: str = "pcg") -> SeriesStats:
+        torch = self.torch
+        stats = SeriesStats()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            self.step(guess, prec, rtol, maxit, stats, solver=solver)
+        e1.record()
+        torch.cuda.synchronize()
+        stats.gpu_ms = e0.elapsed_time(e1)
+        return stats
+
+    def traces(self, nt: int, t_max: float):
+        """[n_rec][nt] receiver traces u(t_j) from the harmonics solved so far."""
+        out = self.torch.empty((self.rec_idx.numel(), nt), dtype=self.torch.float64, device="cuda")
+        ax.laguerre_synth(self.alpha, self.eta, self.Q[:self.m].contiguous(), nt, t_max, out)
+        return out
+
+
 def train_online(net, problems, n_harm: int, prec: int, lr: float = 1e-3, rtol: float = 1e-10,
                  maxit: int = 1000):
     """Train the learned guess on the series of each problem in turn.

@@ -36,6 +36,9 @@ __all__ = [
     "problem_layered",
     "problem_batch_member",
     "laguerre_series_inputs",
+    "gauss_sine_pulse_samples",
+    "medium_fault",
+    "paper_series_inputs",
 ]
 
 
@@ -208,3 +211,49 @@ def nn_example(nr: int, nz: int, seed: int = 0):
     b[nr // 3, nz // 2] += 5.0
     kappa = 2.5 + 1.5 * np.tanh(smooth(1.0))
     return {"u1": u1, "u2": u2, "ut": ut, "b": b, "kappa": kappa}
+
+
+def gauss_sine_pulse_samples(nt: int = 4001, t_max: float = 0.4, f0: float = 30.0, t0: float = 0.2,
+                             gamma: float = 4.0):
+    """The source time function of the paper's experiment (§4.3 eq. (40)),
+    exp(-(2 pi f0 (t-t0))^2 / gamma^2) sin(2 pi f0 (t-t0)) with f0 = 30 Hz,
+    t0 = 0.2 s, gamma = 4, sampled uniformly on [0, t_max] (both ends)."""
+    t = np.linspace(0.0, t_max, nt)
+    a = 2.0 * math.pi * f0 * (t - t0)
+    return t, np.exp(-a * a / (gamma * gamma)) * np.sin(a)
+
+
+def medium_fault(nr: int, nz: int, lr: float = 2.0, lz: float = 2.0, seed: int = 0):
+    """Stand-in for the paper's "geological fault" model (whose figure is not
+    available): wave speed 2.0 km/s above and 3.5 km/s below an interface at
+    depth 0.6 km for r < 0.8 km and 0.9 km beyond (a vertical throw of
+    0.3 km), times a smooth 5% lognormal perturbation (Gaussian-filtered
+    N(0,1), sigma = N/32 cells, unit std), the interface smoothed over two
+    cells.  Returns V [nr][nz] (the coefficient of the operator, read as
+    kappa)."""
+    rng = np.random.default_rng(seed)
+    r = cell_centres(nr, lr)[:, None]
+    z = cell_centres(nz, lz)[None, :]
+    depth = np.where(r < 0.8, 0.6, 0.9)
+    v = np.where(z < depth, 2.0, 3.5)
+    v = ndimage.gaussian_filter(v, sigma=2.0, mode="nearest")
+    g = _unit_std(ndimage.gaussian_filter(rng.standard_normal((nr, nz)), sigma=(nr / 32.0, nz / 32.0),
+                                          mode="reflect"))
+    return np.ascontiguousarray(v * np.exp(0.05 * g))
+
+
+def paper_series_inputs(nr: int, nz: int, seed: int = 0, eta: float = 300.0, alpha: int = 5, n_rec: int = 16,
+                        lr: float = 2.0, lz: float = 2.0):
+    """Inputs of the paper's Laguerre experiment (§4.3): the fault stand-in
+    (kappa = V), density rho = 1 so that q = eta^2/4 and the history
+    coefficient is eta^2 (eq. (35)), Neumann in z (free surface, eq. (32)), the
+    point source at the origin (cell (0, 0)), the pulse of eq. (40), alpha = 5,
+    eta (the paper's h) = 300, and n_rec receivers on the surface row k = 0 at
+    r = (j + 1/2) lr / (2 n_rec) (flat indices i * nz)."""
+    kappa = medium_fault(nr, nz, lr, lz, seed)
+    q = np.full((nr, nz), eta * eta / 4.0)
+    coef = np.full((nr, nz), eta * eta)
+    t, ft = gauss_sine_pulse_samples()
+    ri = np.minimum(((np.arange(n_rec) + 0.5) * nr / (2 * n_rec)).astype(np.int64), nr - 1)
+    return dict(nr=nr, nz=nz, lr=lr, lz=lz, kappa=kappa, q=q, coef=coef, bc_z=1, src_i=0, src_k=0,
+                eta=eta, alpha=alpha, t=t, ft=ft, rec_idx=ri * nz, seed=seed)

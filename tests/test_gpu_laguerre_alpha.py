@@ -1,0 +1,93 @@
+"""The paper's Laguerre experiment (§4.3; eqs. (34)-(35) with alpha = 5,
+h = 300, Neumann in z, the pulse of eq. (40)) on the GPU against the oracle:
+coefficients, harmonics from zero guesses, receiver samples and traces."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev, host, log, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1002_3094_amd import axipcg
+    axipcg.lib()
+    return axipcg
+
+
+def test_coefficients_match_oracle(ax, orc):
+    t, ft = synth.gauss_sine_pulse_samples()
+    for alpha, eta, n in ((5, 300.0, 400), (2, 60.0, 100)):
+        gg = ax.laguerre_coeffs_alpha(n, alpha, eta, ft, t[-1])
+        go = orc.laguerre_coeffs_a(n, alpha, eta, ft, t[-1])
+        log(f"  alpha={alpha} eta={eta}: max |g| {np.abs(go).max():.3e}, err {np.abs(gg - go).max():.2e}")
+        assert np.abs(gg - go).max() <= 1e-9 * np.abs(go).max()
+    # alpha = 0 is the plain transform
+    t2, f2 = synth.ricker_pulse_samples()
+    np.testing.assert_allclose(ax.laguerre_coeffs_alpha(50, 0, 10.0, f2, t2[-1]),
+                               ax.laguerre_coeffs(50, 10.0, f2, t2[-1]), rtol=1e-12, atol=1e-15)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_paper_chain_and_traces_match_oracle(ax, orc, prec):
+    from paper_1002_3094_amd.series import PaperSeries, SeriesStats
+    nr = nz = 64
+    n_harm = 12
+    inp = synth.paper_series_inputs(nr, nz, seed=2)
+    oop = orc.operator_from_cells(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"])
+    go = orc.laguerre_coeffs_a(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+    uo, _ = orc.laguerre_chain_a(oop, inp["coef"], go, inp["alpha"], inp["src_i"], inp["src_k"], n_harm)
+    with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"]) as op:
+        g = ax.laguerre_coeffs_alpha(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+        s = PaperSeries(op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"], inp["rec_idx"])
+        st = SeriesStats()
+        errs = []
+        for m in range(n_harm):
+            s.step("zero", prec, 1e-10, 1000, st)
+            errs.append(rel(host(s.u1), uo[m]))
+        assert all(c == ax.OK for c in st.status)
+        log(f"  prec={prec}: iterations {st.iters}, max rel err {max(errs):.2e}")
+        assert max(errs) <= 1e-8
+        # receiver samples are the harmonics at the receivers, exactly
+        Qo = np.array([u.ravel()[inp["rec_idx"]] for u in uo])
+        Qg = host(s.Q)
+        assert np.abs(Qg - Qo).max() <= 1e-8 * np.abs(Qo).max()
+        # traces: the GPU synthesis of its harmonics against the oracle's
+        nt, tmax = 201, 0.6
+        tr = host(s.traces(nt, tmax))
+        tt = np.linspace(0.0, tmax, nt)
+        tro = Qo.T @ orc.laguerre_synthesis(n_harm, inp["alpha"], inp["eta"], tt)
+        assert np.abs(tr - tro).max() <= 1e-8 * np.abs(tro).max()
+
+
+def test_synthesis_matches_oracle_on_the_same_input(ax, orc):
+    import torch
+    rng = np.random.default_rng(0)
+    n, nrec, nt, tmax = 300, 21, 257, 0.8
+    Q = rng.standard_normal((n, nrec))
+    out = torch.empty((nrec, nt), dtype=torch.float64, device="cuda")
+    ax.laguerre_synth(5, 300.0, dev(Q), nt, tmax, out)
+    ref = Q.T @ orc.laguerre_synthesis(n, 5, 300.0, np.linspace(0.0, tmax, nt))
+    assert np.abs(host(out) - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+def test_gather_and_rhs_edge_cases(ax):
+    import torch
+    inp = synth.paper_series_inputs(16, 16)
+    with ax.op_create(inp["kappa"], inp["q"], bc_z=1) as op:
+        u = dev(np.arange(256, dtype=np.float64).reshape(16, 16))
+        idx = torch.tensor([0, 17, 255, -1, 256], dtype=torch.int64, device="cuda")
+        out = torch.empty(5, dtype=torch.float64, device="cuda")
+        ax.gather(op, u, idx, out)
+        o = host(out)
+        assert o[0] == 0.0 and o[1] == 17.0 and o[2] == 255.0 and np.isnan(o[3]) and np.isnan(o[4])
+        z = lambda: dev(np.zeros((16, 16)))  # noqa: E731
+        S1, S2, b = z(), z(), z()
+        with pytest.raises(ax.AxipcgError):    # u_prev must be given for m > 0
+            ax.laguerre_rhs_alpha(op, 1, 5, 1.0, 0, 0, S1, S2, b)
+        with pytest.raises(ax.AxipcgError):
+            ax.laguerre_rhs_alpha(op, 0, -1, 1.0, 0, 0, S1, S2, b)
