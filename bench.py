@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem uneven batch")
+    ap.add_argument("--no-paper", action="store_true", help="skip the paper-experiment pipeline record")
+    ap.add_argument("--paper-harmonics", type=int, default=200,
+                    help="harmonics timed in the paper-experiment record (the paper used 2000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 64 MiB tensor five times (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
@@ -171,6 +174,39 @@ def cpu_baseline(inp, prec_rtol, budget_s, n_max=16):
     return ({"value": done / el, "unit": "harmonics/s", "cores": oracle.num_threads(), "kind": "oracle",
              "sample": f"first {done} harmonics of the same {inp['nr']}x{inp['nz']} chain, FP64 oracle "
                        f"(4N-embedding FFT transforms, Thomas r-solves, PCG to 1e-10), {el:.1f} s"}, us)
+
+
+def paper_measure(ax, torch, n_harm):
+    """The paper's experiment (§4.3) at 1024^2: the fault stand-in, Neumann in
+    z, alpha = 5, h = 300, the pulse of eq. (40), FP32 preconditioner; a zero
+    initial guess (the paper's) and the previous harmonic; receiver traces
+    synthesised from the harmonics."""
+    import synth
+    from paper_1002_3094_amd import series
+    inp = synth.paper_series_inputs(1024, 1024, seed=101)
+    op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"])
+    g = ax.laguerre_coeffs_alpha(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+    rec = {"workload": "laguerre_paper_1024x1024_alpha5_h300", "harmonics": n_harm, "alpha": inp["alpha"],
+           "eta": inp["eta"], "bc_z": "neumann", "receivers": int(len(inp["rec_idx"]))}
+    for guess in ("zero", "prev"):
+        s = series.PaperSeries(op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"],
+                               inp["rec_idx"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.run(n_harm, guess, ax.PREC_FP32)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert all(c == ax.OK for c in st.status), st.status
+        rec[guess] = {"harmonics_per_s": round(n_harm / el, 2), "iters_per_harmonic": round(float(np.mean(st.iters)), 2),
+                      "us_per_iteration": round(el * 1e6 / max(1, sum(st.iters)), 2)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = s.traces(1001, 0.8)
+    torch.cuda.synchronize()
+    rec["traces_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    rec["trace_peak"] = float(tr.abs().max().item())
+    op.close()
+    return rec
 
 
 def batch_measure(ax, torch, prec, reps=3):
@@ -402,6 +438,8 @@ def main():
         out["speedup_vs_plain_fp64"] = round(results[a.headline]["harmonics_per_s"] / results["A"]["harmonics_per_s"], 3)
     if not a.no_batch:
         out["batch"] = batch_measure(ax, torch, ax.PREC_FP32)
+    if not a.no_paper:
+        out["paper_pipeline"] = paper_measure(ax, torch, a.paper_harmonics)
     if not a.no_cpu_baseline:
         rec, us = cpu_baseline(inp, rtol, a.cpu_seconds)
         out["cpu_baseline"] = rec
