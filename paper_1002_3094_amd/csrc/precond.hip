@@ -640,7 +640,9 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     const T *__restrict__ rw = rw_g;
     const int ngroups = nz / M;
     const int l0 = xcd_swizzle(vb, ngroups) * M;
-    auto prow = [&](int row) { return row + row / Lp; };
+    // padded LDS row index (one gap per Lp rows); for UNI, Lp = LMAX, a power of
+    // two, so the division is a shift
+    auto prow = [&](int row) { return UNI ? row + row / LMAX : row + row / Lp; };
 
     if (M * sizeof(T) == 16) {
         // one 16-byte load per row
