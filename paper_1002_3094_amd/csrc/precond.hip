@@ -289,7 +289,7 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
 }
 
 // ---------------------------------------------------------------------------
-// One-wavefront-per-row transforms for N = 128 R2 (R2 = 4, 8, 16): the
+// One-wavefront-per-row transforms for N = 128 R2 (R2 = 2, 4, 8, 16): the
 // sequence v of Makhoul's reordering, read as M = N/2 complex numbers
 // z[n] = v[2n] + i v[2n+1], is transformed with one length-M FFT (wfft.h)
 // and split into the length-N spectrum of v:
@@ -936,6 +936,7 @@ template <typename T>
 int wave_plan_rows(int N)
 {
     switch (N) {
+    case 256: return wave_rows<T, 2>();
     case 512: return wave_rows<T, 4>();
     case 1024: return wave_rows<T, 8>();
     case 2048: return sizeof(T) == 4 ? wave_rows<T, 16>() : 0;   // FP64 at 2048 would spill
@@ -963,6 +964,7 @@ template <typename T, int BC>
 void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
     switch (op.nz) {
+    case 256: return zfwd_wave<T, BC, 2>(op, a, s);
     case 512: return zfwd_wave<T, BC, 4>(op, a, s);
     case 1024: return zfwd_wave<T, BC, 8>(op, a, s);
     case 2048:
@@ -1050,6 +1052,7 @@ template <typename T, int BC>
 void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
 {
     switch (op.nz) {
+    case 256: return zinv_wave<T, BC, 2>(op, a, s);
     case 512: return zinv_wave<T, BC, 4>(op, a, s);
     case 1024: return zinv_wave<T, BC, 8>(op, a, s);
     case 2048:

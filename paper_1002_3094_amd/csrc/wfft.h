@@ -1,4 +1,4 @@
-// One-wavefront complex FFT of length M = 64 R2 (R2 = 4, 8, 16) for the
+// One-wavefront complex FFT of length M = 64 R2 (R2 = 2, 4, 8, 16) for the
 // z-transforms of the preconditioner (§4.2 eq. (38)).
 //
 // The index is split as n = n0 + 8 n1 + 64 n2 (n0, n1 < 8, n2 < R2) and the
