@@ -82,11 +82,17 @@ def parse():
 
 
 def source_sha():
-    """Hash of the sources the roofline kernel (the PCG SpMV) is built from."""
+    """Hash of the sources the roofline kernel (the PCG SpMV) is built from:
+    the single-problem kernels of pcg.hip (the text before its batched
+    kernels) and common.h without the batch descriptor block."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1002_3094_amd", "csrc")
-    for f in ("common.h", "pcg.hip"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+    pcg = open(os.path.join(csrc, "pcg.hip")).read()
+    h.update(pcg.split("// ---- batched launches")[0].encode())
+    com = open(os.path.join(csrc, "common.h")).read()
+    a = com.index("// One problem of a batched solve")
+    b = com.index("// Run an ABI body")
+    h.update((com[:a] + com[b:]).encode())
     return h.hexdigest()[:16]
 
 

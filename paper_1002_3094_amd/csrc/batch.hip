@@ -5,8 +5,9 @@
 // workgroups are dealt out to the problems by prefix sums of their row (or
 // mode-group) counts, each problem keeps its own device state, partial sums
 // and stop flag, and a finished problem's workgroups return at once.  The
-// number of launches per iteration is therefore four whatever the number of
-// problems, and the host reads all states back once per chunk of iterations.
+// number of launches per iteration does not grow with the number of problems
+// (four, plus one transform launch per extra transform plan present), and the
+// host reads all states back once per chunk of iterations.
 #include <cmath>
 #include <vector>
 
@@ -25,7 +26,8 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
 {
     const int M = (prec == AXIPCG_PREC_FP32) ? 4 : 2;   // modes per r-solve workgroup
     std::vector<ProbDesc> h(n);
-    int rows = 0, tri = 0, nz_max = 0;
+    std::vector<int> plan(n);
+    int rows = 0, tri = 0;
     size_t tri_shm = 0;
     for (int p = 0; p < n; ++p) {
         const Operator &op = *ops[p];
@@ -40,7 +42,9 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         rows += op.nr;
         tri += op.nz / M;
         if (shm > tri_shm) tri_shm = shm;
-        if (op.nz > nz_max) nz_max = op.nz;
+        int wr = 1;
+        plan[p] = batch_transform_plan(op.nz, prec, &wr);
+        d.n_tr = (op.nr + wr - 1) / wr;
         d.b = b[p];
         d.x = x[p];
         d.D = op.D; d.CR = op.CR; d.CZ = op.CZ;
@@ -53,9 +57,30 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         d.tw32 = op.tw32; d.pt32 = op.pt32; d.tw64 = op.tw64; d.pt64 = op.pt64;
     }
     AXI_REQUIRE(tri_shm <= 65536, "a batch member's r-solve tile exceeds the LDS budget");
+    // a second copy of the descriptors, grouped by transform plan: one
+    // transform launch per plan present
+    std::vector<ProbDesc> hp;
+    std::vector<BatchPlan> plans;
+    hp.reserve(n);
+    for (const int r2 : {0, 2, 4, 8, 16}) {
+        BatchPlan pl;
+        pl.r2 = r2;
+        pl.off = (int)hp.size();
+        for (int p = 0; p < n; ++p) {
+            if (plan[p] != r2) continue;
+            ProbDesc e = h[p];
+            e.tr_start = pl.blocks;
+            pl.blocks += e.n_tr;
+            if (e.nz > pl.nz_max) pl.nz_max = e.nz;
+            hp.push_back(e);
+            ++pl.n;
+        }
+        if (pl.n > 0) plans.push_back(pl);
+    }
+    AXI_REQUIRE((int)hp.size() == n, "unknown transform plan");
 
     DevBuf dd, ds;
-    AXI_CHECK_HIP(hipMalloc(&dd.p, sizeof(ProbDesc) * n));
+    AXI_CHECK_HIP(hipMalloc(&dd.p, 2 * sizeof(ProbDesc) * n));
     AXI_CHECK_HIP(hipMalloc(&ds.p, sizeof(PcgState) * n));
     PcgState *hs = nullptr;
     AXI_CHECK_HIP(hipHostMalloc((void **)&hs, sizeof(PcgState) * n, hipHostMallocDefault));
@@ -64,13 +89,15 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         ~HostFree() { if (p) (void)hipHostFree(p); }
     } hf{hs};
     const ProbDesc *d = static_cast<const ProbDesc *>(dd.p);
+    const ProbDesc *dp = d + n;
     PcgState *dstates = static_cast<PcgState *>(ds.p);
     AXI_CHECK_HIP(hipMemcpyAsync(dd.p, h.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, s));
+    AXI_CHECK_HIP(hipMemcpyAsync((void *)dp, hp.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, s));
 
     const bool pr = (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0;
     // start: r = b - A x, z = B^{-1} r (the r-solve launch initialises each state)
     launch_b_init(d, n, rows, s);
-    launch_b_zfwd(d, n, rows, prec, false, 0, nz_max, s);
+    for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, false, 0, s);
     TriGate g;
     g.mode = 2;
     g.rtol2 = rtol * rtol;
@@ -78,7 +105,7 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
     g.flags = (int)flags;
     launch_b_tridiag(d, n, tri, prec, g, M, tri_shm, s);
     launch_b_zero(d, n, rows, s);
-    launch_b_zinv(d, n, rows, prec, 2, false, nz_max, s);
+    for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 2, false, s);
 
     TriGate gi;
     gi.mode = 1;
@@ -87,9 +114,9 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         if (chunk > maxit - launched) chunk = maxit - launched;
         for (int it = 0; it < chunk; ++it) {
             launch_b_spmv(d, n, rows, pr, parity, s);
-            launch_b_zfwd(d, n, rows, prec, true, parity, nz_max, s);
+            for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, true, parity, s);
             launch_b_tridiag(d, n, tri, prec, gi, M, tri_shm, s);
-            launch_b_zinv(d, n, rows, prec, 1, pr, nz_max, s);
+            for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 1, pr, s);
             parity ^= 1;
         }
         launched += chunk;

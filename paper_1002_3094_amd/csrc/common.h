@@ -132,10 +132,12 @@ struct Operator {
 
 // One problem of a batched solve, as the batched kernels see it.  Workgroup g
 // of a row-indexed launch belongs to the problem whose [row_start, row_start +
-// nr) range holds g; of the r-solve launch, [tri_start, tri_start + nz / M).
+// nr) range holds g; of the r-solve launch, [tri_start, tri_start + nz / M);
+// of its transform launch, [tr_start, tr_start + n_tr).
 struct ProbDesc {
     int nr, nz, bc_z;
     int row_start, tri_start;
+    int tr_start, n_tr;
     int tri_S, tri_L, tri_Lp, tri_pitch;
     const double *b;
     double *x;
@@ -151,13 +153,15 @@ struct ProbDesc {
 };
 
 // Index of the problem owning global workgroup g (binary search on the
-// starts; `tri` selects the r-solve ranges).
-__device__ inline int find_problem(const ProbDesc *d, int n, int g, bool tri)
+// starts of the launch's ranges: rows, r-solve mode groups or transform
+// workgroups).
+enum : int { RANGE_ROWS = 0, RANGE_TRI = 1, RANGE_TR = 2 };
+__device__ inline int find_problem(const ProbDesc *d, int n, int g, int range)
 {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int st = tri ? d[mid].tri_start : d[mid].row_start;
+        const int st = range == RANGE_TRI ? d[mid].tri_start : range == RANGE_TR ? d[mid].tr_start : d[mid].row_start;
         if (st <= g) lo = mid;
         else hi = mid - 1;
     }

@@ -70,10 +70,19 @@ void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch
 void launch_b_init(const ProbDesc *d, int n, int rows, hipStream_t s);
 void launch_b_zero(const ProbDesc *d, int n, int rows, hipStream_t s);
 void launch_b_spmv(const ProbDesc *d, int n, int rows, bool pr, int parity, hipStream_t s);
-void launch_b_zfwd(const ProbDesc *d, int n, int rows, int prec, bool fused, int parity, int nz_max, hipStream_t s);
+// One batched transform launch covers the problems d[off, off + n) of an
+// array sorted by transform plan: r2 = N / 128 for the one-wave plans, 0 for
+// the block-wide kernels (one row per workgroup); `blocks` workgroups in all.
+struct BatchPlan {
+    int r2 = 0, off = 0, n = 0, blocks = 0, nz_max = 0;
+};
+// Plan of a batch member with nz points per row: returns r2 and sets the rows
+// per transform workgroup.
+int batch_transform_plan(int nz, int prec, int *rows_per_wg);
+void launch_b_zfwd(const ProbDesc *d, const BatchPlan &pl, int prec, bool fused, int parity, hipStream_t s);
 void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriGate &g, int M, size_t shm,
                       hipStream_t s);
-void launch_b_zinv(const ProbDesc *d, int n, int rows, int prec, int mode, bool pr, int nz_max, hipStream_t s);
+void launch_b_zinv(const ProbDesc *d, const BatchPlan &pl, int prec, int mode, bool pr, hipStream_t s);
 void launch_b_gather(const ProbDesc *d, int n, PcgState *out, hipStream_t s);
 void resid_impl(const Operator &op, const double *b, const double *x, double *out_dev, hipStream_t s);
 

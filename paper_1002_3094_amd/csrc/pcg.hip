@@ -223,24 +223,24 @@ k_pcg_init(const double *__restrict__ b, const double *__restrict__ x, double *_
 template <bool PR>
 __global__ void __launch_bounds__(256) k_b_spmv(const ProbDesc *__restrict__ d, int n, int parity)
 {
-    const int p = find_problem(d, n, blockIdx.x, false);
+    const int p = find_problem(d, n, blockIdx.x, RANGE_ROWS);
     const ProbDesc &P = d[p];
     const double *pold = parity ? P.p1 : P.p0;
     double *pnew = parity ? P.p0 : P.p1;
-    spmv_body<PR>(P.z, pold, pnew, P.q, P.D, P.CR, P.CZ, P.nr, P.nz, P.state, P.partials, P.nr,
+    spmv_body<PR>(P.z, pold, pnew, P.q, P.D, P.CR, P.CZ, P.nr, P.nz, P.state, P.partials, P.n_tr,
                   blockIdx.x - P.row_start, P.nr);
 }
 
 __global__ void __launch_bounds__(256) k_b_init(const ProbDesc *__restrict__ d, int n)
 {
-    const int p = find_problem(d, n, blockIdx.x, false);
+    const int p = find_problem(d, n, blockIdx.x, RANGE_ROWS);
     const ProbDesc &P = d[p];
     init_body(P.b, P.x, P.r, P.D, P.CR, P.CZ, P.nr, P.nz, P.partials, blockIdx.x - P.row_start, P.nr);
 }
 
 __global__ void __launch_bounds__(256) k_b_zero_if_b_zero(const ProbDesc *__restrict__ d, int n)
 {
-    const int p = find_problem(d, n, blockIdx.x, false);
+    const int p = find_problem(d, n, blockIdx.x, RANGE_ROWS);
     const ProbDesc &P = d[p];
     if (P.state->done != ST_BZERO) return;
     const int i = blockIdx.x - P.row_start;

@@ -302,12 +302,12 @@ template <typename T, int R2>
 constexpr int wave_rows() { return (sizeof(T) == 8 && R2 >= 16) ? 2 : 4; }
 
 template <typename T, int BC, bool FUSED, int R2>
-__global__ void __launch_bounds__(256)
-k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
-         const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
-         double *__restrict__ partials, int n_pq, T *__restrict__ spec,
-         const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
-         int nr)
+__device__ __forceinline__ void
+zfwd_w_body(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
+            const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
+            double *__restrict__ partials, int n_pq, T *__restrict__ spec,
+            const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
+            int nr, int blk)
 {
     using G = wfft::Geo<R2>;
     constexpr int M = G::M, N = G::N, U = G::U, WR = wave_rows<T, R2>();
@@ -316,7 +316,7 @@ k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restr
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw) + wv * G::LB;
     T *fbuf = reinterpret_cast<T *>(buf);
-    const int row = blockIdx.x * WR + wv;
+    const int row = blk * WR + wv;
     const bool valid = row < nr;
     const size_t base = (size_t)(valid ? row : nr - 1) * N + 2 * lane;
 
@@ -350,11 +350,11 @@ k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restr
         const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
         const int k_it = st->iters;
         if (!(pq > 0.0) || !(pq < 1e308)) {
-            if (blockIdx.x == 0 && threadIdx.x == 0) st->done = ST_BREAK;
+            if (blk == 0 && threadIdx.x == 0) st->done = ST_BREAK;
             return;
         }
         alpha = st->rho[k_it & 1] / pq;
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = k_it;
+        if (blk == 0 && threadIdx.x == 0) st->cur = k_it;
     }
 
     // r update, Makhoul reordering into the slice (even k -> v[k/2], odd k -> v[N-1-(k-1)/2])
@@ -430,16 +430,16 @@ k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restr
     }
     if (FUSED) {
         const double s = block_sum(rr, red);
-        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
+        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blk] = s;
     }
 }
 
 template <typename T, int BC, int MODE, int R2>
-__global__ void __launch_bounds__(256)
-k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
-         const PcgState *st, double *__restrict__ partials, bool pr,
-         const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
-         int nr, double *__restrict__ dinc, double tau, double rho2)
+__device__ __forceinline__ void
+zinv_w_body(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
+            const PcgState *st, double *__restrict__ partials, bool pr,
+            const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
+            int nr, double *__restrict__ dinc, double tau, double rho2, int blk)
 {
     constexpr bool PCGM = (MODE == 1 || MODE == 2);
     constexpr bool CHEB = (MODE == 3 || MODE == 4);
@@ -450,7 +450,7 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw) + wv * G::LB;
     const T *fbuf = reinterpret_cast<const T *>(buf);
-    const int row = blockIdx.x * WR + wv;
+    const int row = blk * WR + wv;
     const bool valid = row < nr;
     const int rowc = valid ? row : nr - 1;
     const size_t base = (size_t)rowc * N + 2 * lane;
@@ -554,12 +554,33 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
     }
     if (PCGM) {
         const double s = block_sum(rz, red);
-        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + blockIdx.x] = s;
+        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + blk] = s;
         if (pr) {
             const double so = block_sum(rzo, red);
-            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + blockIdx.x] = so;
+            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + blk] = so;
         }
     }
+}
+
+template <typename T, int BC, bool FUSED, int R2>
+__global__ void __launch_bounds__(256)
+k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
+         const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
+         double *__restrict__ partials, int n_pq, T *__restrict__ spec,
+         const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
+         int nr)
+{
+    zfwd_w_body<T, BC, FUSED, R2>(rin, x, r, p, q, st, partials, n_pq, spec, tw, pt, nr, blockIdx.x);
+}
+
+template <typename T, int BC, int MODE, int R2>
+__global__ void __launch_bounds__(256)
+k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
+         const PcgState *st, double *__restrict__ partials, bool pr,
+         const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
+         int nr, double *__restrict__ dinc, double tau, double rho2)
+{
+    zinv_w_body<T, BC, MODE, R2>(spec, zout, r, st, partials, pr, tw, pt, nr, dinc, tau, rho2, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -827,13 +848,15 @@ template <typename T> __device__ inline const typename vec2_of<T>::type *pd_pt(c
 template <> __device__ inline const float2 *pd_pt<float>(const ProbDesc &P) { return P.pt32; }
 template <> __device__ inline const double2 *pd_pt<double>(const ProbDesc &P) { return P.pt64; }
 
+// The batched transforms run one launch per transform plan; `d` holds the
+// problems of that plan, with tr_start counted within the launch.
 template <typename T, bool FUSED, bool TWLDS>
 __global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, int n, int parity)
 {
-    const int p = find_problem(d, n, blockIdx.x, false);
+    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
     const ProbDesc &P = d[p];
     const double *pnew = parity ? P.p0 : P.p1;   // written by this iteration's SpMV
-    const int vb = blockIdx.x - P.row_start;
+    const int vb = blockIdx.x - P.tr_start;
     // the start-up transform runs before the r-solve launch resets the state,
     // so only the in-loop (fused) transform may read the stop flag
     PcgState *st = FUSED ? P.state : nullptr;
@@ -848,9 +871,9 @@ __global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, 
 template <typename T, int MODE, bool TWLDS>
 __global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, int n, bool pr)
 {
-    const int p = find_problem(d, n, blockIdx.x, false);
+    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
     const ProbDesc &P = d[p];
-    const int vb = blockIdx.x - P.row_start;
+    const int vb = blockIdx.x - P.tr_start;
     if (P.bc_z == DIR)
         zinv_body<T, DIR, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
                                        pd_pt<T>(P), P.nr, P.nz, vb);
@@ -859,14 +882,44 @@ __global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, 
                                                     pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
 }
 
+template <typename T, bool FUSED, int R2>
+__global__ void __launch_bounds__(256) k_b_zfwd_w(const ProbDesc *__restrict__ d, int n, int parity)
+{
+    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
+    const ProbDesc &P = d[p];
+    const double *pnew = parity ? P.p0 : P.p1;
+    const int vb = blockIdx.x - P.tr_start;
+    PcgState *st = FUSED ? P.state : nullptr;   // as in k_b_zfwd
+    if (P.bc_z == DIR)
+        zfwd_w_body<T, DIR, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec, pd_tw<T>(P),
+                                       pd_pt<T>(P), P.nr, vb);
+    else
+        zfwd_w_body<T, AXIPCG_Z_NEUMANN, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec,
+                                                    pd_tw<T>(P), pd_pt<T>(P), P.nr, vb);
+}
+
+template <typename T, int MODE, int R2>
+__global__ void __launch_bounds__(256) k_b_zinv_w(const ProbDesc *__restrict__ d, int n, bool pr)
+{
+    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
+    const ProbDesc &P = d[p];
+    const int vb = blockIdx.x - P.tr_start;
+    if (P.bc_z == DIR)
+        zinv_w_body<T, DIR, MODE, R2>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
+                                      pd_pt<T>(P), P.nr, nullptr, 0.0, 0.0, vb);
+    else
+        zinv_w_body<T, AXIPCG_Z_NEUMANN, MODE, R2>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
+                                                   pd_tw<T>(P), pd_pt<T>(P), P.nr, nullptr, 0.0, 0.0, vb);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_b_tridiag(const ProbDesc *__restrict__ d, int n, TriGate g, int M)
 {
-    const int p = find_problem(d, n, blockIdx.x, true);
+    const int p = find_problem(d, n, blockIdx.x, RANGE_TRI);
     const ProbDesc &P = d[p];
     const int vb = blockIdx.x - P.tri_start;
     g.state = P.state;
-    g.n_rr = P.nr;
+    g.n_rr = g.mode == 2 ? P.nr : P.n_tr;   // start: the init partials, one per row
     const bool uni = (P.nr % P.tri_S) == 0;
 #define AXI_BTRI(LM, U)                                                                                       \
     tridiag_body<T, LM, U>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,           \
@@ -1136,42 +1189,99 @@ void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch
     *shm = (size_t)M * *pitch * el;
 }
 
-template <typename T>
-void b_zfwd_t(const ProbDesc *d, int n, int rows, bool fused, int parity, int nz_max, hipStream_t s)
+int batch_transform_plan(int nz, int prec, int *rows_per_wg)
 {
-    const size_t shm = transform_lds<T>(nz_max);
-    if (twiddles_in_lds<T>(nz_max)) {
-        if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, true>), dim3(rows), dim3(256), shm, s, d, n, parity);
-        else hipLaunchKernelGGL((k_b_zfwd<T, false, true>), dim3(rows), dim3(256), shm, s, d, n, parity);
-    } else {
-        if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, false>), dim3(rows), dim3(256), shm, s, d, n, parity);
-        else hipLaunchKernelGGL((k_b_zfwd<T, false, false>), dim3(rows), dim3(256), shm, s, d, n, parity);
+    const int wr = (prec == AXIPCG_PREC_FP32) ? wave_plan_rows<float>(nz) : wave_plan_rows<double>(nz);
+    *rows_per_wg = wr > 0 ? wr : 1;
+    return wr > 0 ? nz / 128 : 0;
+}
+
+template <typename T, int R2>
+void b_zfwd_wave(const ProbDesc *d, const BatchPlan &pl, bool fused, int parity, hipStream_t s)
+{
+    constexpr int WR = wave_rows<T, R2>();
+    const size_t shm = (size_t)WR * wfft::Geo<R2>::LB * sizeof(cx<T>);
+    if (fused)
+        hipLaunchKernelGGL((k_b_zfwd_w<T, true, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n,
+                           parity);
+    else
+        hipLaunchKernelGGL((k_b_zfwd_w<T, false, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n,
+                           parity);
+}
+
+template <typename T, int R2>
+void b_zinv_wave(const ProbDesc *d, const BatchPlan &pl, int mode, bool pr, hipStream_t s)
+{
+    constexpr int WR = wave_rows<T, R2>();
+    const size_t shm = (size_t)WR * wfft::Geo<R2>::LB * sizeof(cx<T>);
+    if (mode == 1)
+        hipLaunchKernelGGL((k_b_zinv_w<T, 1, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n, pr);
+    else
+        hipLaunchKernelGGL((k_b_zinv_w<T, 2, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n, pr);
+}
+
+template <typename T>
+void b_zfwd_t(const ProbDesc *d, const BatchPlan &pl, bool fused, int parity, hipStream_t s)
+{
+    switch (pl.r2) {
+    case 2: b_zfwd_wave<T, 2>(d, pl, fused, parity, s); break;
+    case 4: b_zfwd_wave<T, 4>(d, pl, fused, parity, s); break;
+    case 8: b_zfwd_wave<T, 8>(d, pl, fused, parity, s); break;
+    case 16:
+        if constexpr (sizeof(T) == 4) b_zfwd_wave<T, 16>(d, pl, fused, parity, s);
+        else AXI_REQUIRE(false, "no one-wave FP64 plan for N = 2048");
+        break;
+    default: {
+        const size_t shm = transform_lds<T>(pl.nz_max);
+        const dim3 grid(pl.blocks), block(256);
+        const ProbDesc *dp = d + pl.off;
+        if (twiddles_in_lds<T>(pl.nz_max)) {
+            if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, true>), grid, block, shm, s, dp, pl.n, parity);
+            else hipLaunchKernelGGL((k_b_zfwd<T, false, true>), grid, block, shm, s, dp, pl.n, parity);
+        } else {
+            if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, false>), grid, block, shm, s, dp, pl.n, parity);
+            else hipLaunchKernelGGL((k_b_zfwd<T, false, false>), grid, block, shm, s, dp, pl.n, parity);
+        }
+    }
     }
     AXI_CHECK_HIP(hipGetLastError());
 }
 
 template <typename T>
-void b_zinv_t(const ProbDesc *d, int n, int rows, int mode, bool pr, int nz_max, hipStream_t s)
+void b_zinv_t(const ProbDesc *d, const BatchPlan &pl, int mode, bool pr, hipStream_t s)
 {
-    const size_t shm = transform_lds<T>(nz_max);
-    const bool twl = twiddles_in_lds<T>(nz_max);
-#define AXI_BZI(MD, TW) hipLaunchKernelGGL((k_b_zinv<T, MD, TW>), dim3(rows), dim3(256), shm, s, d, n, pr)
-    if (mode == 1) { if (twl) AXI_BZI(1, true); else AXI_BZI(1, false); }
-    else { if (twl) AXI_BZI(2, true); else AXI_BZI(2, false); }
+    switch (pl.r2) {
+    case 2: b_zinv_wave<T, 2>(d, pl, mode, pr, s); break;
+    case 4: b_zinv_wave<T, 4>(d, pl, mode, pr, s); break;
+    case 8: b_zinv_wave<T, 8>(d, pl, mode, pr, s); break;
+    case 16:
+        if constexpr (sizeof(T) == 4) b_zinv_wave<T, 16>(d, pl, mode, pr, s);
+        else AXI_REQUIRE(false, "no one-wave FP64 plan for N = 2048");
+        break;
+    default: {
+        const size_t shm = transform_lds<T>(pl.nz_max);
+        const bool twl = twiddles_in_lds<T>(pl.nz_max);
+        const dim3 grid(pl.blocks), block(256);
+        const ProbDesc *dp = d + pl.off;
+#define AXI_BZI(MD, TW) hipLaunchKernelGGL((k_b_zinv<T, MD, TW>), grid, block, shm, s, dp, pl.n, pr)
+        if (mode == 1) { if (twl) AXI_BZI(1, true); else AXI_BZI(1, false); }
+        else { if (twl) AXI_BZI(2, true); else AXI_BZI(2, false); }
 #undef AXI_BZI
+    }
+    }
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-void launch_b_zfwd(const ProbDesc *d, int n, int rows, int prec, bool fused, int parity, int nz_max, hipStream_t s)
+void launch_b_zfwd(const ProbDesc *d, const BatchPlan &pl, int prec, bool fused, int parity, hipStream_t s)
 {
-    if (prec == AXIPCG_PREC_FP32) b_zfwd_t<float>(d, n, rows, fused, parity, nz_max, s);
-    else b_zfwd_t<double>(d, n, rows, fused, parity, nz_max, s);
+    if (prec == AXIPCG_PREC_FP32) b_zfwd_t<float>(d, pl, fused, parity, s);
+    else b_zfwd_t<double>(d, pl, fused, parity, s);
 }
 
-void launch_b_zinv(const ProbDesc *d, int n, int rows, int prec, int mode, bool pr, int nz_max, hipStream_t s)
+void launch_b_zinv(const ProbDesc *d, const BatchPlan &pl, int prec, int mode, bool pr, hipStream_t s)
 {
-    if (prec == AXIPCG_PREC_FP32) b_zinv_t<float>(d, n, rows, mode, pr, nz_max, s);
-    else b_zinv_t<double>(d, n, rows, mode, pr, nz_max, s);
+    if (prec == AXIPCG_PREC_FP32) b_zinv_t<float>(d, pl, mode, pr, s);
+    else b_zinv_t<double>(d, pl, mode, pr, s);
 }
 
 void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriGate &g, int M, size_t shm,

@@ -25,7 +25,11 @@ def _member(shape, bc, seed):
     return kappa, q, f, bc
 
 
-SMALL = [((64, 64), 0), ((128, 256), 1), ((256, 128), 0), ((96, 64), 0), ((256, 512), 1), ((32, 16), 0)]
+# z-lengths with a one-wave transform plan (256, 512, 1024, 2048 in FP32) and
+# without (16, 64, 128; 2048 in FP64), so that every transform launch of a
+# batch covers problems of one plan while the other launches mix them
+SMALL = [((64, 64), 0), ((128, 256), 1), ((256, 128), 0), ((96, 64), 0), ((256, 512), 1), ((32, 16), 0),
+         ((18, 1024), 1), ((8, 2048), 0), ((40, 256), 0)]
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -111,8 +115,8 @@ def test_uneven_batch_of_64(ax, orc):
     for p in range(64):
         xs1 = dev(np.zeros((probs[p].nr, probs[p].nz)))
         s1 = ax.pcg_solve(ops[p], bs[p], xs1, 1e-10, 1000, ax.PREC_FP32)
-        # the batched transforms use 256 threads per row for every size, so
-        # partial sums may be added in another order than in the single solve
+        # the batched r-solve sizes its segments for the batch, so partial
+        # sums may be added in another order than in the single solve
         assert abs(s1["iters"] - st[p]["iters"]) <= 1
         assert rel(host(xs[p]), host(xs1)) <= 1e-9, p
     for op in ops:
