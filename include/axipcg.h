@@ -310,6 +310,22 @@ int axipcg_series_step(axipcg_op_t op, axipcg_nn_t nn, int m, double g_m, int sr
                        const double *coef, double *S1, double *S2, double *b, const double *u1,
                        const double *u2, const double *kappa, double *x, int guess, int solver,
                        double rtol, int maxit, int prec, axipcg_stats *st, void *stream);
+/* Harmonics m0, m0 + 1, ..., m0 + count - 1 of the same series in one call,
+ * each as series_step, with no return to the caller between them.  g (host,
+ * count values): g_{m0}, g_{m0+1}, ....  u (host array of three distinct
+ * device [nr][nz] arrays): {u_{m0-1}, u_{m0-2}, work} on entry (at m0 = 0
+ * the first two only feed the initial guess: zero them); each harmonic solves
+ * into the work array and the three pointers rotate, so that on return u[0]
+ * holds u_{m0+count-1}, u[1] u_{m0+count-2} and u[2] is free.  st (host,
+ * count entries, may be NULL) receives each solve's statistics; done (host,
+ * may be NULL) the number of harmonics completed.  A harmonic that does not
+ * converge is kept and the run goes on (the return value is then
+ * AXIPCG_ENOTCONV); a breakdown or any other error stops the run at that
+ * harmonic with its code, leaving u as it was before it. */
+int axipcg_series_run(axipcg_op_t op, axipcg_nn_t nn, int m0, int count, const double *g, int src_i, int src_k,
+                      const double *coef, double *S1, double *S2, double *b, double **u, const double *kappa,
+                      int guess, int solver, double rtol, int maxit, int prec, axipcg_stats *st, int *done,
+                      void *stream);
 
 /* ---- per-kernel timing (tracing aid) ----------------------------------------
  * Select one kernel class of the PCG iteration; pcg_solve then brackets one

@@ -77,6 +77,8 @@ SIGNATURES = {
     "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_series_step": ([_vp, _vp, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _i,
                             ctypes.POINTER(Stats), _vp], _i),
+    "axipcg_series_run": ([_vp, _vp, _i, _i, _dp, _i, _i, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp), _vp, _i, _i,
+                           _d, _i, _i, ctypes.POINTER(Stats), ctypes.POINTER(_i), _vp], _i),
     "axipcg_profile_select": ([_vp, _i, _i], _i),
     "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
@@ -445,6 +447,29 @@ def series_step(op: Op, m: int, g_m: float, src_i: int, src_k: int, S1, S2, b, u
     d = st.as_dict()
     d["code"] = code
     return d
+
+
+def series_run(op: Op, m0: int, g, src_i: int, src_k: int, S1, S2, b, u: list, guess: str,
+               solver: str = "pcg", net=None, kappa=None, coef=None, rtol=1e-10, maxit=1000, prec=PREC_FP32,
+               stream=None, allow_notconv=True):
+    """Harmonics m0 .. m0 + len(g) - 1 in one call (see series_step).  u is a
+    list of three device arrays [u_{m0-1}, u_{m0-2}, work]; it is rotated in
+    place so that afterwards u[0] holds the last solution and u[1] the one
+    before.  Returns (code, per-harmonic stats dicts)."""
+    gv = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    count = int(gv.size)
+    ptrs = (_vp * 3)(*[_dev(t, "u") for t in u])
+    by_ptr = {t.data_ptr(): t for t in u}
+    st = (Stats * max(count, 1))()
+    done = _i()
+    code = lib().axipcg_series_run(op.handle, net.handle if net is not None else None, m0, count,
+                                   gv.ctypes.data_as(_dp), src_i, src_k, _opt_dev(coef, "coef"), _dev(S1, "S1"),
+                                   _dev(S2, "S2"), _dev(b, "b"), ptrs, _opt_dev(kappa, "kappa"), SERIES_GUESS[guess],
+                                   {"pcg": 0, "cheb": 1}[solver], rtol, maxit, prec, st, ctypes.byref(done),
+                                   _stream(stream))
+    u[:] = [by_ptr[ptrs[j]] for j in range(3)]
+    _check(code, "series_run", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    return code, [st[j].as_dict() for j in range(done.value)]
 
 
 def profile_select(op: Op, kernel: int, every: int = 1):

@@ -320,22 +320,28 @@ k_conv3(const bf16 *__restrict__ in, void *__restrict__ outp, const typename Fra
         }
     };
 
-    Frag S0[3], S1[3], S2[3], S3[3];
+    // a ring of five input rows: output row i needs rows i-1..i+1 while rows
+    // i+2 and i+3 are in flight
+    Frag S0[3], S1[3], S2[3], S3[3], S4[3];
     load_row<CINP>(S0, in, i0 - 1, nr, nz, k0, m, kq);
     load_row<CINP>(S1, in, i0, nr, nz, k0, m, kq);
     load_row<CINP>(S2, in, i0 + 1, nr, nz, k0, m, kq);
-    for (int i = i0; i < i1; i += 4) {
-        load_row<CINP>(S3, in, i + 2, nr, nz, k0, m, kq);
+    load_row<CINP>(S3, in, i0 + 2, nr, nz, k0, m, kq);
+    for (int i = i0; i < i1; i += 5) {
+        load_row<CINP>(S4, in, i + 3, nr, nz, k0, m, kq);
         row_out(i, S0, S1, S2);
         if (i + 1 >= i1) break;
-        load_row<CINP>(S0, in, i + 3, nr, nz, k0, m, kq);
+        load_row<CINP>(S0, in, i + 4, nr, nz, k0, m, kq);
         row_out(i + 1, S1, S2, S3);
         if (i + 2 >= i1) break;
-        load_row<CINP>(S1, in, i + 4, nr, nz, k0, m, kq);
-        row_out(i + 2, S2, S3, S0);
+        load_row<CINP>(S1, in, i + 5, nr, nz, k0, m, kq);
+        row_out(i + 2, S2, S3, S4);
         if (i + 3 >= i1) break;
-        load_row<CINP>(S2, in, i + 5, nr, nz, k0, m, kq);
-        row_out(i + 3, S3, S0, S1);
+        load_row<CINP>(S2, in, i + 6, nr, nz, k0, m, kq);
+        row_out(i + 3, S3, S4, S0);
+        if (i + 4 >= i1) break;
+        load_row<CINP>(S3, in, i + 7, nr, nz, k0, m, kq);
+        row_out(i + 4, S4, S0, S1);
     }
 }
 
@@ -601,40 +607,67 @@ k_guess_res(const double *__restrict__ b, const double *__restrict__ u1, const d
             const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
             const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
 {
+    // workgroups take whole rows, the rows of one XCD contiguous (their
+    // neighbour rows then come from that XCD's L2); each thread the element
+    // pairs (k, k + 1), k even, read as 16-byte (8-byte for out) vectors; the
+    // coefficients are read once for the three candidates
     __shared__ double sm[8];
-    const size_t n = (size_t)nr * nz;
     const double s = NET ? scal[0] : 0.0;
     double fp = 0.0, fe = 0.0, fn = 0.0;
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
-        double a1 = D[e] * u1[e], a2 = D[e] * u2[e], ao = NET ? D[e] * (double)out[e] : 0.0;
-        if (i + 1 < nr) {
-            const double c = CR[e];
-            a1 -= c * u1[e + nz]; a2 -= c * u2[e + nz];
-            if (NET) ao -= c * (double)out[e + nz];
-        }
-        if (i > 0) {
-            const double c = CR[e - nz];
-            a1 -= c * u1[e - nz]; a2 -= c * u2[e - nz];
-            if (NET) ao -= c * (double)out[e - nz];
-        }
-        if (k + 1 < nz) {
-            const double c = CZ[e];
-            a1 -= c * u1[e + 1]; a2 -= c * u2[e + 1];
-            if (NET) ao -= c * (double)out[e + 1];
-        }
-        if (k > 0) {
-            const double c = CZ[e - 1];
-            a1 -= c * u1[e - 1]; a2 -= c * u2[e - 1];
-            if (NET) ao -= c * (double)out[e - 1];
-        }
-        const double rp = b[e] - a1;
-        const double re = b[e] - (2.0 * a1 - a2);
-        fp += rp * rp;
-        fe += re * re;
-        if (NET) {
-            const double rn = re - s * ao;
-            fn += rn * rn;
+    auto ld = [](const double *p) { return *reinterpret_cast<const double2 *>(p); };
+    auto ldo = [](const float *p) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        return double2{(double)v.x, (double)v.y};
+    };
+    for (int blk = blockIdx.x; blk < nr; blk += gridDim.x) {
+        const int i = xcd_swizzle(blk, nr);
+        for (int k = 2 * threadIdx.x; k < nz; k += 512) {
+            const size_t e = (size_t)i * nz + k;
+            const double2 d = ld(D + e), cz = ld(CZ + e), bv = ld(b + e);
+            const double2 c1 = ld(u1 + e), c2 = ld(u2 + e);
+            const double2 co = NET ? ldo(out + e) : double2{0.0, 0.0};
+            double2 a1{d.x * c1.x, d.y * c1.y}, a2{d.x * c2.x, d.y * c2.y}, ao{d.x * co.x, d.y * co.y};
+            if (i + 1 < nr) {
+                const double2 c = ld(CR + e), v1 = ld(u1 + e + nz), v2 = ld(u2 + e + nz);
+                a1.x -= c.x * v1.x; a1.y -= c.y * v1.y;
+                a2.x -= c.x * v2.x; a2.y -= c.y * v2.y;
+                if (NET) {
+                    const double2 vo = ldo(out + e + nz);
+                    ao.x -= c.x * vo.x; ao.y -= c.y * vo.y;
+                }
+            }
+            if (i > 0) {
+                const double2 c = ld(CR + e - nz), v1 = ld(u1 + e - nz), v2 = ld(u2 + e - nz);
+                a1.x -= c.x * v1.x; a1.y -= c.y * v1.y;
+                a2.x -= c.x * v2.x; a2.y -= c.y * v2.y;
+                if (NET) {
+                    const double2 vo = ldo(out + e - nz);
+                    ao.x -= c.x * vo.x; ao.y -= c.y * vo.y;
+                }
+            }
+            // z-couplings: (k, k+1) inside the pair, k-1 and k+2 outside
+            a1.x -= cz.x * c1.y; a1.y -= cz.x * c1.x;
+            a2.x -= cz.x * c2.y; a2.y -= cz.x * c2.x;
+            ao.x -= cz.x * co.y; ao.y -= cz.x * co.x;
+            if (k + 2 < nz) {
+                a1.y -= cz.y * u1[e + 2];
+                a2.y -= cz.y * u2[e + 2];
+                if (NET) ao.y -= cz.y * (double)out[e + 2];
+            }
+            if (k > 0) {
+                const double c = CZ[e - 1];
+                a1.x -= c * u1[e - 1];
+                a2.x -= c * u2[e - 1];
+                if (NET) ao.x -= c * (double)out[e - 1];
+            }
+            const double rpx = bv.x - a1.x, rpy = bv.y - a1.y;
+            const double rex = bv.x - (2.0 * a1.x - a2.x), rey = bv.y - (2.0 * a1.y - a2.y);
+            fp += rpx * rpx + rpy * rpy;
+            fe += rex * rex + rey * rey;
+            if (NET) {
+                const double rnx = rex - s * ao.x, rny = rey - s * ao.y;
+                fn += rnx * rnx + rny * rny;
+            }
         }
     }
     const double tp = block_sum(fp, sm);
@@ -719,6 +752,10 @@ unsigned red_blocks(size_t n)
     const unsigned b = pointwise_blocks(n);
     return b < 1024 ? b : 1024;
 }
+
+// grid of the guard's residual kernel: whole rows per workgroup, at most 1024
+// partial sums
+unsigned guard_blocks(int nr) { return nr < 1024 ? (unsigned)nr : 1024u; }
 
 void pack_all(Net &n, hipStream_t s)
 {
@@ -966,7 +1003,7 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
         const size_t np = (size_t)n->nr * n->nz;
-        const unsigned pb = red_blocks(np);
+        const unsigned pb = guard_blocks(op->nr);
         hipLaunchKernelGGL(k_guess_res<true>, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ,
                            op->nr, op->nz, n->scal, n->red);
         hipLaunchKernelGGL(k_guess_fin<true>, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal + 3);
@@ -993,7 +1030,7 @@ int axipcg_guess_extrap(axipcg_op_t hop, const double *b, const double *u1, cons
         AXI_REQUIRE(x != b, "x aliases b");
         hipStream_t s = (hipStream_t)stream;
         const size_t np = (size_t)op->nr * op->nz;
-        const unsigned pb = red_blocks(np);
+        const unsigned pb = guard_blocks(op->nr);
         // the reductions use the handle's partial-sum rows 0..2 and scalars 8..11,
         // which a solve only reads after writing them itself
         double *res = op->dscal + 8;

@@ -1,7 +1,9 @@
 // One harmonic of a Laguerre series (§4.1 eqs. (34)-(35)) as one library
 // call: right-hand side, initial guess and solve are queued back to back on
 // the caller's stream, so the device does not idle while the host returns
-// between them.  Composed of the public entry points; no arithmetic here.
+// between them; and a run of harmonics as one call, so that the caller's own
+// per-harmonic overhead is not paid between them either.  Composed of the
+// public entry points; no arithmetic here.
 #include "axipcg.h"
 #include "common.h"
 
@@ -49,4 +51,33 @@ extern "C" int axipcg_series_step(axipcg_op_t hop, axipcg_nn_t nn, int m, double
     if (code != AXIPCG_OK) return code;
     if (solver == 1) return axipcg_cheb_solve(hop, b, x, 0.0, 0.0, rtol, maxit, prec, st, stream);
     return axipcg_pcg_solve(hop, b, x, rtol, maxit, prec, 0u, st, stream);
+}
+
+extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int count, const double *g, int src_i,
+                                 int src_k, const double *coef, double *S1, double *S2, double *b, double **u,
+                                 const double *kappa, int guess, int solver, double rtol, int maxit, int prec,
+                                 axipcg_stats *st, int *done, void *stream)
+{
+    if (done) *done = 0;
+    int code = guarded([&] {
+        AXI_REQUIRE(m0 >= 0 && count >= 0, "m0 and count must be >= 0");
+        AXI_REQUIRE(count == 0 || g != nullptr, "g is NULL");
+        AXI_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u must hold three device arrays");
+        AXI_REQUIRE(u[0] != u[1] && u[1] != u[2] && u[0] != u[2], "the three u arrays must be distinct");
+        return AXIPCG_OK;
+    });
+    if (code != AXIPCG_OK) return code;
+    int worst = AXIPCG_OK;
+    for (int j = 0; j < count; ++j) {
+        code = axipcg_series_step(hop, nn, m0 + j, g[j], src_i, src_k, coef, S1, S2, b, u[0], u[1], kappa, u[2],
+                                  guess, solver, rtol, maxit, prec, st ? st + j : nullptr, stream);
+        if (code < 0) return code;   // the failed harmonic's buffers keep their roles
+        if (code == AXIPCG_ENOTCONV) worst = AXIPCG_ENOTCONV;
+        double *w = u[1];            // u_{m-2} becomes the next work array
+        u[1] = u[0];
+        u[0] = u[2];
+        u[2] = w;
+        if (done) *done = j + 1;
+    }
+    return worst;
 }

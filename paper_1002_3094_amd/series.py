@@ -109,6 +109,27 @@ class LaguerreSeries:
         self.u2, self.u1, self.u = self.u1, self.u, self.u2
         self.m += 1
 
+    def run_harmonics(self, n: int, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats,
+                      net=None, solver: str = "pcg"):
+        """Solve the next n harmonics in one library call (series_run: no
+        return to Python between harmonics); afterwards self.u1 holds the
+        last solution."""
+        if n <= 0:
+            return
+        if self.m + n > len(self.g):
+            raise ValueError("not enough Laguerre coefficients")
+        if guess == "nn" and (net is None or self.kappa is None):
+            raise ValueError("nn guess needs a network and kappa")
+        u = [self.u1, self.u2, self.u]
+        code, sts = ax.series_run(self.op, self.m, self.g[self.m:self.m + n], self.src_i, self.src_k, self.S1,
+                                  self.S2, self.b, u, guess, solver=solver, net=net,
+                                  kappa=self.kappa if guess == "nn" else None, coef=self.coef, rtol=rtol,
+                                  maxit=maxit, prec=prec)
+        stats.iters.extend(st["iters"] for st in sts)
+        stats.status.extend(st["status"] for st in sts)
+        self.u1, self.u2, self.u = u
+        self.m += len(sts)
+
     def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000, net=None,
             lr: float | None = None, want_info: bool = False, solver: str = "pcg") -> SeriesStats:
         """Solve the next n harmonics, timed with events on the current stream."""
@@ -118,8 +139,11 @@ class LaguerreSeries:
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(n):
-            self.step(guess, prec, rtol, maxit, stats, net=net, lr=lr, want_info=want_info, solver=solver)
+        if not want_info and lr is None:
+            self.run_harmonics(n, guess, prec, rtol, maxit, stats, net=net, solver=solver)
+        else:
+            for _ in range(n):
+                self.step(guess, prec, rtol, maxit, stats, net=net, lr=lr, want_info=want_info, solver=solver)
         e1.record(stream)
         torch.cuda.synchronize()
         stats.gpu_ms = e0.elapsed_time(e1)

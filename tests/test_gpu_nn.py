@@ -132,8 +132,13 @@ def _bias_only(onn, c):
     return p
 
 
-def test_guard_picks_smallest_residual(ax, onn, orc):
-    nr, nz = 32, 64
+# several row pairs per thread (nz = 1024), an odd row count, more rows than
+# residual workgroups (1100 > 1024)
+GUARD_SHAPES = [(32, 64), (37, 1024), (1100, 64)]
+
+
+@pytest.mark.parametrize("nr,nz", GUARD_SHAPES)
+def test_guard_picks_smallest_residual(ax, onn, orc, nr, nz):
     kappa, q = synth.medium_layered(nr, nz, 3)
     op, oop = _ops(ax, orc, kappa, q)
     f = synth.gaussian_source(nr, nz, 1.0, 1.0, 0.2, 0.5, 0.05)
@@ -191,8 +196,8 @@ def test_guard_picks_smallest_residual(ax, onn, orc):
     op.close()
 
 
-def test_extrapolation_guard(ax, onn, orc):
-    nr, nz = 32, 64
+@pytest.mark.parametrize("nr,nz", GUARD_SHAPES)
+def test_extrapolation_guard(ax, onn, orc, nr, nz):
     kappa, q = synth.medium_layered(nr, nz, 5)
     op, oop = _ops(ax, orc, kappa, q)
     f = synth.gaussian_source(nr, nz, 1.0, 1.0, 0.3, 0.4, 0.05)

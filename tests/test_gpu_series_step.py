@@ -1,5 +1,6 @@
-"""``axipcg_series_step`` (one call per Laguerre harmonic) against the same
-harmonic made of separate calls: identical kernels in identical order, so the
+"""``axipcg_series_step`` (one call per Laguerre harmonic) and
+``axipcg_series_run`` (one call for several harmonics) against the same
+harmonics made of separate calls: identical kernels in identical order, so the
 solutions must agree bit for bit, with the same iteration counts."""
 import numpy as np
 import pytest
@@ -47,6 +48,58 @@ def test_series_step_matches_separate_calls(ax, guess, solver):
             np.testing.assert_array_equal(a, b)
     if net is not None:
         net.close()
+
+
+@pytest.mark.parametrize("guess,solver", [("prev", "pcg"), ("nn", "pcg"), ("extrap", "cheb")])
+def test_series_run_matches_steps(ax, guess, solver):
+    """Harmonics 0..6 as one run of 2 and one of 5 against seven single steps."""
+    from paper_1002_3094_amd.series import LaguerreSeries, SeriesStats, nn_init_params
+    log(f"series_run guess={guess} solver={solver}")
+    n_harm = 7
+    inp = synth.laguerre_series_inputs(N, N, seed=4)
+    net = ax.nn_create(N, N, nn_init_params(6, last_zero=False)) if guess == "nn" else None
+    with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
+        g = ax.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
+        s1 = LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        st1 = SeriesStats()
+        ref = []
+        for _ in range(n_harm):
+            s1.step(guess, ax.PREC_FP32, 1e-10, 1000, st1, net=net, solver=solver)
+            ref.append((host(s1.u1).copy(), host(s1.u2).copy()))
+        s2 = LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        st2 = SeriesStats()
+        s2.run_harmonics(2, guess, ax.PREC_FP32, 1e-10, 1000, st2, net=net, solver=solver)
+        np.testing.assert_array_equal(host(s2.u1), ref[1][0])
+        np.testing.assert_array_equal(host(s2.u2), ref[1][1])
+        s2.run_harmonics(5, guess, ax.PREC_FP32, 1e-10, 1000, st2, net=net, solver=solver)
+        log(f"  iterations {st2.iters}")
+        assert st2.iters == st1.iters and all(c == ax.OK for c in st2.status) and s2.m == n_harm
+        np.testing.assert_array_equal(host(s2.u1), ref[-1][0])
+        np.testing.assert_array_equal(host(s2.u2), ref[-1][1])
+        assert len({s2.u1.data_ptr(), s2.u2.data_ptr(), s2.u.data_ptr()}) == 3
+    if net is not None:
+        net.close()
+
+
+def test_series_run_edge_cases(ax):
+    inp = synth.laguerre_series_inputs(32, 32, seed=2)
+    with ax.op_create(inp["kappa"], inp["q"]) as op:
+        z = lambda: dev(np.zeros((32, 32)))  # noqa: E731
+        S1, S2, b = z(), z(), z()
+        u = [z(), z(), z()]
+        before = [t.data_ptr() for t in u]
+        code, sts = ax.series_run(op, 0, [], inp["src_i"], inp["src_k"], S1, S2, b, u, "prev")
+        assert code == ax.OK and sts == [] and [t.data_ptr() for t in u] == before
+        with pytest.raises(ax.AxipcgError):   # two roles on one array
+            ax.series_run(op, 0, [1.0], inp["src_i"], inp["src_k"], S1, S2, b, [u[0], u[0], u[2]], "prev")
+        with pytest.raises(ax.AxipcgError):   # the learned guess without a network
+            ax.series_run(op, 0, [1.0, 0.5], inp["src_i"], inp["src_k"], S1, S2, b, u, "nn")
+        assert [t.data_ptr() for t in u] == before
+        # a harmonic that stops at maxit is kept and the run goes on
+        code, sts = ax.series_run(op, 0, [1.0, 0.5, 0.25], inp["src_i"], inp["src_k"], S1, S2, b, u, "zero",
+                                  maxit=2)
+        assert code == ax.ENOTCONV and len(sts) == 3
+        assert all(st["status"] == ax.ENOTCONV and st["iters"] == 2 for st in sts)
 
 
 def test_series_step_rejects_bad_arguments(ax):
