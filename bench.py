@@ -47,6 +47,7 @@ BYTES_PER_POINT = {
     "zinv": 20,      # read spectral (f32), r; write z
 }
 PRECOND_BYTES_PER_POINT = 32  # r (8) -> spectral (4+4) -> spectral (4+4) -> z (8)
+PRECOND_BYTES_PER_POINT_FP64 = 48  # r (8) -> spectral (8+8) -> spectral (8+8) -> z (8)
 KERNEL_IDS = {"spmv": 0, "zfwd": 1, "tridiag": 2, "zinv": 3}
 PROFILE_EVERY = 8   # time one launch in 8 of the roofline kernel inside the timed loop
 KERNEL_SYMBOLS = {"spmv": "k_pcg_spmv", "zfwd": "k_zfwd", "tridiag": "k_tridiag", "zinv": "k_zinv"}
@@ -60,7 +61,7 @@ def parse():
     ap.add_argument("--nr", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=101)
-    ap.add_argument("--modes", default="A,B,X,Z,Y,C", help="comma-separated modes to run")
+    ap.add_argument("--modes", default="A,B,X,Z,Y,W,C", help="comma-separated modes to run")
     ap.add_argument("--headline", default="C", help="mode whose throughput is the value")
     ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--train-harmonics", type=int, default=200)
@@ -70,6 +71,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-problem uneven batch")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-experiment pipeline record")
+    ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 series record")
+    ap.add_argument("--large-harmonics", type=int, default=100, help="timed harmonics of the 2048^2 record")
     ap.add_argument("--paper-harmonics", type=int, default=200,
                     help="harmonics timed in the paper-experiment record (the paper used 2000)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -81,18 +84,30 @@ def parse():
     return ap.parse_args()
 
 
+def _block(text, start):
+    """The text of the declaration that begins with `start` up to its closing
+    brace at column 0 (or its first line, for one-line declarations)."""
+    a = text.index(start)
+    line_end = text.index("\n", a)
+    if text[a:line_end].rstrip().endswith(";") or text[a:line_end].rstrip().endswith("}"):
+        return text[a:line_end]
+    return text[a:text.index("\n}", a) + 2]
+
+
 def source_sha():
-    """Hash of the sources the roofline kernel (the PCG SpMV) is built from:
-    the single-problem kernels of pcg.hip (the text before its batched
-    kernels) and common.h without the batch descriptor block."""
+    """Hash of the source text the roofline kernel (the PCG SpMV) is built
+    from: its body, kernel and stencil helpers and launch size in pcg.hip, and
+    the state, slot layout and reduction helpers it uses from common.h."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1002_3094_amd", "csrc")
     pcg = open(os.path.join(csrc, "pcg.hip")).read()
-    h.update(pcg.split("// ---- batched launches")[0].encode())
+    h.update(_block(pcg, "inline unsigned row_blocks").encode())
+    h.update(pcg[pcg.index("struct Pair {"):pcg.index("// Chebyshev step of eq. (8)")].encode())
     com = open(os.path.join(csrc, "common.h")).read()
-    a = com.index("// One problem of a batched solve")
-    b = com.index("// Run an ABI body")
-    h.update((com[:a] + com[b:]).encode())
+    for start in ("struct PcgState {", "enum Slot {", "constexpr int MAX_PARTIALS",
+                  "__device__ inline double block_sum(", "__device__ inline double block_total(",
+                  "__device__ inline int xcd_swizzle("):
+        h.update(_block(com, start).encode())
     return h.hexdigest()[:16]
 
 
@@ -182,6 +197,61 @@ def cpu_baseline(inp, prec_rtol, budget_s, n_max=16):
                        f"(4N-embedding FFT transforms, Thomas r-solves, PCG to 1e-10), {el:.1f} s"}, us)
 
 
+def large_measure(ax, torch, n, n_harm, seed):
+    """The Laguerre chain of the layered medium on an n x n grid (the
+    paper-scale series): FP32 and FP64 preconditioners with the previous
+    harmonic as guess, the SpMV's HIP-event duration in the FP32 run, and
+    standalone preconditioner applies."""
+    import synth
+    from paper_1002_3094_amd import series
+    inp = synth.laguerre_series_inputs(n, n, seed=seed)
+    op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
+    g = ax.laguerre_coeffs(n_harm + 3, inp["eta"], inp["ft"], inp["t"][-1])
+    rec = {"workload": f"laguerre_{n}x{n}", "harmonics": n_harm, "guess": "prev", "rtol": 1e-10}
+    for name, prec in (("fp64", ax.PREC_FP64), ("fp32", ax.PREC_FP32)):
+        s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"])
+        s.run(3, "prev", prec)
+        if prec == ax.PREC_FP32:
+            ax.profile_select(op, KERNEL_IDS["spmv"], PROFILE_EVERY)
+            ax.profile_read(op, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = s.run(n_harm, "prev", prec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert all(c == ax.OK for c in st.status), st.status
+        rec[name] = {"harmonics_per_s": round(n_harm / el, 2), "iters_per_harmonic": round(float(np.mean(st.iters)), 3),
+                     "us_per_iteration": round(el * 1e6 / max(1, sum(st.iters)), 2)}
+        if prec == ax.PREC_FP32:
+            k_ms, k_n = ax.profile_read(op, reset=True)
+            ax.profile_select(op, ax.KERNEL_NONE)
+            k_s = (k_ms / 1e3) / max(k_n, 1)
+            gbs = BYTES_PER_POINT["spmv"] * n * n / k_s / 1e9
+            rec["spmv"] = {"mean_us": round(k_s * 1e6, 2), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                           "launches": k_n}
+    rec["speedup_fp32_vs_fp64"] = round(rec["fp32"]["harmonics_per_s"] / rec["fp64"]["harmonics_per_s"], 3)
+    r = torch.randn((n, n), dtype=torch.float64, device="cuda")
+    z = torch.empty_like(r)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    for name, prec in (("fp64", ax.PREC_FP64), ("fp32", ax.PREC_FP32)):
+        for _ in range(3):
+            ax.precond_apply(op, r, z, prec)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(50):
+            ax.precond_apply(op, r, z, prec)
+        e1.record()
+        torch.cuda.synchronize()
+        pc_s = e0.elapsed_time(e1) / 1e3 / 50
+        bpp = PRECOND_BYTES_PER_POINT if prec == ax.PREC_FP32 else PRECOND_BYTES_PER_POINT_FP64
+        gbs = bpp * n * n / pc_s / 1e9
+        rec[f"precond_{name}"] = {"applies_per_s": round(1.0 / pc_s, 1), "mean_us": round(pc_s * 1e6, 2),
+                                  "bytes_per_point": bpp, "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    op.close()
+    return rec
+
+
 def paper_measure(ax, torch, n_harm):
     """The paper's experiment (§4.3) at 1024^2: the fault stand-in, Neumann in
     z, alpha = 5, h = 300, the pulse of eq. (40), FP32 preconditioner; a zero
@@ -264,6 +334,7 @@ MODES = {   # (preconditioner, guess, solver)
     "Z": ("fp32", "zero", "pcg"),
     "Y": ("fp32", "extrap", "cheb"),
     "C": ("fp32", "nn", "pcg"),
+    "W": ("fp32", "nn", "cheb"),
 }
 NN_FLOP_PER_POINT = 2 * 9 * (4 * 32 + 4 * 32 * 32 + 32 * 1)   # 76 608: six 3x3 convolutions
 BF16_PEAK_TFLOPS = 2500.0
@@ -328,7 +399,7 @@ def main():
     t_setup = time.perf_counter() - t_setup
 
     net, training = (None, None)
-    if "C" in modes:
+    if any(MODES[m][1] == "nn" for m in modes):
         net, training = train_network(ax, torch, synth, series, a)
 
     results = {}
@@ -446,6 +517,8 @@ def main():
         out["batch"] = batch_measure(ax, torch, ax.PREC_FP32)
     if not a.no_paper:
         out["paper_pipeline"] = paper_measure(ax, torch, a.paper_harmonics)
+    if not a.no_large:
+        out["series_2048"] = large_measure(ax, torch, 2048, a.large_harmonics, a.seed)
     if not a.no_cpu_baseline:
         rec, us = cpu_baseline(inp, rtol, a.cpu_seconds)
         out["cpu_baseline"] = rec

@@ -59,6 +59,22 @@ struct PcgState {
     int pad2[3];
 };
 
+// Progress of a solve as the host sees it, in coherent pinned host memory:
+// workgroup 0 of an r-solve launch writes it when the stop test fires, and at
+// the one iteration of a chunk the host asks for, so that the host can follow
+// a solve without draining the stream.  rr and bb first, then (after a
+// system-scope fence) word = seq << 32 | iters << 8 | done.
+struct HostMirror {
+    double rr, bb;
+    unsigned long long word;
+    unsigned long long pad;
+};
+__host__ __device__ inline unsigned long long mirror_word(unsigned seq, int iters, int done)
+{
+    return ((unsigned long long)seq << 32) | ((unsigned long long)((unsigned)iters & 0xffffffu) << 8) |
+           (unsigned long long)((unsigned)done & 0xffu);
+}
+
 // Reduction slots: each fused kernel owns one ticket counter and one
 // partial-sum array in the operator's workspace.
 enum Slot { SLOT_PQ = 0, SLOT_RR = 1, SLOT_RZ = 2, SLOT_MISC = 3, SLOT_RZOLD = 4, NUM_SLOTS = 5 };
@@ -108,7 +124,10 @@ struct Operator {
     double *partials = nullptr;    // [NUM_SLOTS][MAX_PARTIALS] per-workgroup partial sums
     PcgState *state = nullptr;
     double *dscal = nullptr;         // 16 device scalars (residual norms)
-    PcgState *state_host = nullptr;  // pinned mirror
+    PcgState *state_host = nullptr;  // pinned copy of the state (read after the stream drains)
+    HostMirror *mirror_host = nullptr;   // coherent pinned progress record (host address)
+    HostMirror *mirror_dev = nullptr;    // the same, device address
+    unsigned mirror_seq = 0;             // number of the current solve
     double *scratch_host = nullptr;  // pinned host scalars
 
     // single-pass preconditioner (pfused.hip): plan per precision [FP64, FP32]

@@ -29,12 +29,17 @@ int transform_blocks(const Operator &op, int prec);
 //          (workgroup 0 records it), then solve unless stopped;
 //  mode 2: PCG start: ||r||^2 and ||b||^2 from the start kernel's partials ->
 //          state initialised, start test, then solve unless stopped.
+//  With `mirror`, workgroup 0 also publishes the outcome to the host
+//  (HostMirror) when the test stops the solve, or always when `report`.
 struct TriGate {
     int mode = 0;
     PcgState *state = nullptr;
     int n_rr = 0;          // partials of ||r||^2 (and of ||b||^2 in mode 2)
     double rtol2 = 0.0;    // mode 2
     int maxit = 0, flags = 0;
+    HostMirror *mirror = nullptr;
+    unsigned seq = 0;
+    int report = 0;
 };
 void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t s);
 
@@ -93,5 +98,15 @@ inline unsigned pointwise_blocks(size_t n, int threads = 256)
     if (b > (size_t)MAX_PARTIALS) b = MAX_PARTIALS;
     return (unsigned)b;
 }
+
+// The solve entry points behind axipcg_pcg_solve / axipcg_cheb_solve (which
+// pass sync_end = true).  With sync_end = false the call returns as soon as
+// the host has seen the stop test's outcome: launches of the last chunk may
+// still be queued, so later work on the stream is ordered after them while
+// the host has not waited for them.
+int pcg_solve_entry(axipcg_op_t h, const double *b, double *x, double rtol, int maxit, int prec, unsigned flags,
+                    axipcg_stats *st, void *stream, bool sync_end);
+int cheb_solve_entry(axipcg_op_t h, const double *b, double *x, double gamma1, double gamma2, double rtol,
+                     int maxit, int prec, axipcg_stats *st, void *stream, bool sync_end);
 
 }  // namespace axipcg

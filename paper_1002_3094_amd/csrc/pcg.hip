@@ -11,7 +11,9 @@
 //   3. r-solve: ||r||^2 -> stop test (sets `done`); r-tridiagonal solves
 //   4. inverse: inverse z-transform -> z, r.z partials
 // After the stop test fires, the remaining launches of the chunk return at
-// once.  The host reads the state back once per chunk of iterations.
+// once.  The host follows the solve through a progress record that the stop
+// test publishes to pinned host memory (HostMirror), normally once per solve.
+#include <atomic>
 #include <cmath>
 
 #include <hip/hip_ext.h>
@@ -268,6 +270,8 @@ struct SolveCtx {
     bool pr;
     hipStream_t s;
     int n_tr;   // workgroups (partials) of the transform kernels
+    unsigned seq = 0;     // solve number published through the host mirror
+    int report_it = -1;   // iteration whose stop test publishes even without a stop
 };
 
 // Event pair around one launch of the profiled kernel class.  With `ext`
@@ -336,6 +340,9 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
         g.mode = 1;
         g.state = op.state;
         g.n_rr = c.n_tr;
+        g.mirror = op.mirror_dev;
+        g.seq = c.seq;
+        g.report = iter == c.report_it;
         launch_tridiag(op, c.prec, g, c.s);
     }
     ZinvArgs ia;
@@ -361,6 +368,9 @@ void collect_profile(Operator &op, int iters)
                               ? iters : iters - 1;
         if (it >= limit) continue;
         float ms = 0.f;
+        // complete (they precede the stop test in stream order); the wait
+        // only covers the completion notice reaching the runtime
+        AXI_CHECK_HIP(hipEventSynchronize(op.prof_events[2 * k + 1]));
         AXI_CHECK_HIP(hipEventElapsedTime(&ms, op.prof_events[2 * k], op.prof_events[2 * k + 1]));
         op.prof_ms += ms;
         op.prof_count += 1;
@@ -368,11 +378,46 @@ void collect_profile(Operator &op, int iters)
     op.prof_used = 0;
 }
 
+// Wait until solve `seq` has published a stop, or (need >= 0) at least
+// `need` finished iterations, through the host mirror.  Should the stream
+// drain first (a stop that no r-solve launch publishes, such as a breakdown
+// found by the forward transform), the device state is read instead.
+PcgState wait_progress(Operator &op, hipStream_t s, unsigned seq, int need)
+{
+    const volatile unsigned long long *w = &op.mirror_host->word;
+    for (unsigned spin = 1;; ++spin) {
+        const unsigned long long v = *w;
+        if ((unsigned)(v >> 32) == seq) {
+            const int done = (int)(v & 0xffu), iters = (int)((v >> 8) & 0xffffffu);
+            if (done != ST_RUN || (need >= 0 && iters >= need)) {
+                std::atomic_thread_fence(std::memory_order_acquire);
+                PcgState h{};
+                h.done = done;
+                h.iters = iters;
+                h.rr = static_cast<const volatile double &>(op.mirror_host->rr);
+                h.bb = static_cast<const volatile double &>(op.mirror_host->bb);
+                return h;
+            }
+        }
+        if ((spin & 31u) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                AXI_CHECK_HIP(hipMemcpyAsync(op.state_host, op.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
+                AXI_CHECK_HIP(hipStreamSynchronize(s));
+                return *op.state_host;
+            }
+            if (e != hipErrorNotReady) AXI_CHECK_HIP(e);
+        }
+        __builtin_ia32_pause();
+    }
+}
+
 int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit, int prec, unsigned flags,
-               axipcg_stats *st, hipStream_t s)
+               axipcg_stats *st, hipStream_t s, bool sync_end)
 {
     const size_t n = (size_t)op.nr * op.nz;
     SolveCtx c{&op, x, prec, (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0, s, transform_blocks(op, prec)};
+    c.seq = ++op.mirror_seq;
     op.prof_used = 0;
     // start: r = b - A x; z = B^{-1} r (the r-solve launch runs the start test)
     const unsigned gi = row_blocks(op.nr);
@@ -389,6 +434,8 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     g.rtol2 = rtol * rtol;
     g.maxit = maxit;
     g.flags = (int)flags;
+    g.mirror = op.mirror_dev;
+    g.seq = c.seq;
     launch_tridiag(op, prec, g, s);
     hipLaunchKernelGGL(k_zero_if_b_zero, dim3(pointwise_blocks(n)), dim3(256), 0, s, x, n, op.state);
     AXI_CHECK_HIP(hipGetLastError());
@@ -400,24 +447,27 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     launch_zinv(op, prec, ia, s);
 
     // iterations, in chunks: the first one covers the previous solve's count
-    // plus one, so a series of similar solves reads the state back once each
-    // (the launches past the stop test return at once)
+    // plus one, so a series of similar solves needs one chunk each (the
+    // launches past the stop test return at once).  The host follows the
+    // solve through the mirror: the stop test publishes a stop at once, and
+    // the next-to-last iteration of a chunk publishes its progress, so that
+    // a further chunk is queued before the current one has drained.
     int launched = 0;
     int parity = 0;
     int chunk = op.last_iters > 0 ? op.last_iters + 1 : 4;
+    PcgState h{};
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
+        c.report_it = launched + (chunk >= 2 ? chunk - 2 : 0);
         for (int it = 0; it < chunk; ++it) {
             launch_iteration(c, parity, launched + it);
             parity ^= 1;
         }
         launched += chunk;
-        AXI_CHECK_HIP(hipMemcpyAsync(op.state_host, op.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        AXI_CHECK_HIP(hipStreamSynchronize(s));
-        if (op.state_host->done != ST_RUN || launched >= maxit) break;
+        h = wait_progress(op, s, c.seq, launched >= maxit ? -1 : c.report_it + 1);
+        if (h.done != ST_RUN || launched >= maxit) break;
         chunk = 2;
     }
-    const PcgState h = *op.state_host;
     op.last_iters = h.iters;
     if (op.prof_kernel >= 0) collect_profile(op, h.iters);
     int status;
@@ -440,6 +490,7 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
             }
         }
     }
+    if (sync_end) AXI_CHECK_HIP(hipStreamSynchronize(s));
     return status;
 }
 
@@ -448,8 +499,9 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
 // transform, r-solves (stop test), inverse transform forming the next d.  No
 // dot products beyond ||r||^2 for the stop test.
 int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, double gamma2, double rtol, int maxit,
-                    int prec, axipcg_stats *st, hipStream_t s)
+                    int prec, axipcg_stats *st, hipStream_t s, bool sync_end)
 {
+    const unsigned seq = ++op.mirror_seq;
     const size_t n = (size_t)op.nr * op.nz;
     const double tau = 2.0 / (gamma1 + gamma2);
     const double xi = gamma1 / gamma2;
@@ -469,6 +521,8 @@ int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, dou
     g.rtol2 = rtol * rtol;
     g.maxit = maxit;
     g.flags = 0;
+    g.mirror = op.mirror_dev;
+    g.seq = seq;
     launch_tridiag(op, prec, g, s);
     hipLaunchKernelGGL(k_zero_if_b_zero, dim3(pointwise_blocks(n)), dim3(256), 0, s, x, n, op.state);
     AXI_CHECK_HIP(hipGetLastError());
@@ -487,27 +541,30 @@ int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, dou
     g1.mode = 1;
     g1.state = op.state;
     g1.n_rr = (int)gi;
+    g1.mirror = op.mirror_dev;
+    g1.seq = seq;
     ZinvArgs ib = ia;
     ib.mode = 3;
     int launched = 0;
     int chunk = op.last_iters > 0 ? op.last_iters + 1 : 4;
+    PcgState h{};
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
+        const int report_it = launched + (chunk >= 2 ? chunk - 2 : 0);
         for (int it = 0; it < chunk; ++it) {
             hipLaunchKernelGGL(k_cheb_update, dim3(gi), dim3(256), 0, s, d, x, op.r, op.D, op.CR, op.CZ, op.nr, op.nz,
                                op.state, op.partials);
             AXI_CHECK_HIP(hipGetLastError());
             launch_zfwd(op, prec, ga, s);
+            g1.report = launched + it == report_it;
             launch_tridiag(op, prec, g1, s);
             launch_zinv(op, prec, ib, s);
         }
         launched += chunk;
-        AXI_CHECK_HIP(hipMemcpyAsync(op.state_host, op.state, sizeof(PcgState), hipMemcpyDeviceToHost, s));
-        AXI_CHECK_HIP(hipStreamSynchronize(s));
-        if (op.state_host->done != ST_RUN || launched >= maxit) break;
+        h = wait_progress(op, s, seq, launched >= maxit ? -1 : report_it + 1);
+        if (h.done != ST_RUN || launched >= maxit) break;
         chunk = 2;
     }
-    const PcgState h = *op.state_host;
     op.last_iters = h.iters;
     int status;
     if (h.done == ST_CONV || h.done == ST_BZERO) status = AXIPCG_OK;
@@ -519,6 +576,7 @@ int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, dou
         st->relres_rec = (h.bb > 0) ? std::sqrt(h.rr / h.bb) : 0.0;
         st->relres_true = -1.0;
     }
+    if (sync_end) AXI_CHECK_HIP(hipStreamSynchronize(s));
     return status;
 }
 
@@ -583,8 +641,9 @@ extern "C" int axipcg_profile_read(axipcg_op_t h, double *total_ms, long long *l
     });
 }
 
-extern "C" int axipcg_pcg_solve(axipcg_op_t h, const double *b, double *x, double rtol, int maxit, int prec,
-                                unsigned flags, axipcg_stats *st, void *stream)
+namespace axipcg {
+int pcg_solve_entry(axipcg_op_t h, const double *b, double *x, double rtol, int maxit, int prec, unsigned flags,
+                    axipcg_stats *st, void *stream, bool sync_end)
 {
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(h);
@@ -594,12 +653,12 @@ extern "C" int axipcg_pcg_solve(axipcg_op_t h, const double *b, double *x, doubl
         AXI_REQUIRE(maxit >= 1 && maxit <= 100000, "maxit must be in [1, 100000]");
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
         AXI_REQUIRE((flags & ~3u) == 0, "unknown flags");
-        return solve_impl(*op, b, x, rtol, maxit, prec, flags, st, (hipStream_t)stream);
+        return solve_impl(*op, b, x, rtol, maxit, prec, flags, st, (hipStream_t)stream, sync_end);
     });
 }
 
-extern "C" int axipcg_cheb_solve(axipcg_op_t h, const double *b, double *x, double gamma1, double gamma2,
-                                 double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
+int cheb_solve_entry(axipcg_op_t h, const double *b, double *x, double gamma1, double gamma2, double rtol,
+                     int maxit, int prec, axipcg_stats *st, void *stream, bool sync_end)
 {
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(h);
@@ -615,6 +674,19 @@ extern "C" int axipcg_cheb_solve(axipcg_op_t h, const double *b, double *x, doub
         AXI_REQUIRE(std::isfinite(gamma1) && std::isfinite(gamma2) && gamma1 > 0 && gamma1 <= gamma2,
                     "need 0 < gamma1 <= gamma2 (the operator's own bounds have gamma1 = 0 when some q is 0 "
                     "while qbar > 0)");
-        return cheb_solve_impl(*op, b, x, gamma1, gamma2, rtol, maxit, prec, st, (hipStream_t)stream);
+        return cheb_solve_impl(*op, b, x, gamma1, gamma2, rtol, maxit, prec, st, (hipStream_t)stream, sync_end);
     });
+}
+}  // namespace axipcg
+
+extern "C" int axipcg_pcg_solve(axipcg_op_t h, const double *b, double *x, double rtol, int maxit, int prec,
+                                unsigned flags, axipcg_stats *st, void *stream)
+{
+    return pcg_solve_entry(h, b, x, rtol, maxit, prec, flags, st, stream, true);
+}
+
+extern "C" int axipcg_cheb_solve(axipcg_op_t h, const double *b, double *x, double gamma1, double gamma2,
+                                 double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
+{
+    return cheb_solve_entry(h, b, x, gamma1, gamma2, rtol, maxit, prec, st, stream, true);
 }

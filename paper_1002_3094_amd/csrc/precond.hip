@@ -603,6 +603,15 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
 // ---------------------------------------------------------------------------
 // Gate of the r-solve launch in PCG mode: returns the stop status (ST_RUN to
 // go on).  Workgroup 0 records it.
+// Publish a solve's progress to the host (one thread).
+__device__ inline void publish(HostMirror *m, unsigned seq, double rr, double bb, int iters, int done)
+{
+    m->rr = rr;
+    m->bb = bb;
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned long long *>(&m->word) = mirror_word(seq, iters, done);
+}
+
 __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ partials, const TriGate &g, double *red,
                                    int vb)
 {
@@ -618,6 +627,7 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
             st->rr = rr;
             st->iters = k_it + 1;
             st->done = status;
+            if (g.mirror && (status != ST_RUN || g.report)) publish(g.mirror, g.seq, rr, st->bb, k_it + 1, status);
         }
         return status;
     }
@@ -637,6 +647,7 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
         st->maxit = g.maxit;
         st->flags = g.flags;
         st->done = status;
+        if (g.mirror && (status != ST_RUN || g.report)) publish(g.mirror, g.seq, rr, bb, 0, status);
     }
     return status;
 }

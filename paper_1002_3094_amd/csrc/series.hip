@@ -5,14 +5,18 @@
 // per-harmonic overhead is not paid between them either.  Composed of the
 // public entry points; no arithmetic here.
 #include "axipcg.h"
-#include "common.h"
+#include "kernels.h"
 
 using namespace axipcg;
 
-extern "C" int axipcg_series_step(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k,
-                                  const double *coef, double *S1, double *S2, double *b, const double *u1,
-                                  const double *u2, const double *kappa, double *x, int guess, int solver,
-                                  double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
+namespace {
+
+// sync_end = false: return once the host has seen the solve's outcome, with
+// the tail of its last chunk possibly still queued (see pcg_solve_entry).
+int series_step_impl(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k, const double *coef,
+                     double *S1, double *S2, double *b, const double *u1, const double *u2, const double *kappa,
+                     double *x, int guess, int solver, double rtol, int maxit, int prec, axipcg_stats *st,
+                     void *stream, bool sync_end)
 {
     int code = guarded([&] {
         AXI_REQUIRE(hop && S1 && S2 && b && u1 && u2 && x, "NULL argument");
@@ -49,8 +53,19 @@ extern "C" int axipcg_series_step(axipcg_op_t hop, axipcg_nn_t nn, int m, double
         break;
     }
     if (code != AXIPCG_OK) return code;
-    if (solver == 1) return axipcg_cheb_solve(hop, b, x, 0.0, 0.0, rtol, maxit, prec, st, stream);
-    return axipcg_pcg_solve(hop, b, x, rtol, maxit, prec, 0u, st, stream);
+    if (solver == 1) return cheb_solve_entry(hop, b, x, 0.0, 0.0, rtol, maxit, prec, st, stream, sync_end);
+    return pcg_solve_entry(hop, b, x, rtol, maxit, prec, 0u, st, stream, sync_end);
+}
+
+}  // namespace
+
+extern "C" int axipcg_series_step(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k,
+                                  const double *coef, double *S1, double *S2, double *b, const double *u1,
+                                  const double *u2, const double *kappa, double *x, int guess, int solver,
+                                  double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
+{
+    return series_step_impl(hop, nn, m, g_m, src_i, src_k, coef, S1, S2, b, u1, u2, kappa, x, guess, solver, rtol,
+                            maxit, prec, st, stream, true);
 }
 
 extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int count, const double *g, int src_i,
@@ -67,11 +82,16 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
         return AXIPCG_OK;
     });
     if (code != AXIPCG_OK) return code;
+    // between harmonics the host does not wait for the stream to drain: the
+    // next right-hand side is queued behind the tail of the previous solve
     int worst = AXIPCG_OK;
     for (int j = 0; j < count; ++j) {
-        code = axipcg_series_step(hop, nn, m0 + j, g[j], src_i, src_k, coef, S1, S2, b, u[0], u[1], kappa, u[2],
-                                  guess, solver, rtol, maxit, prec, st ? st + j : nullptr, stream);
-        if (code < 0) return code;   // the failed harmonic's buffers keep their roles
+        code = series_step_impl(hop, nn, m0 + j, g[j], src_i, src_k, coef, S1, S2, b, u[0], u[1], kappa, u[2], guess,
+                                solver, rtol, maxit, prec, st ? st + j : nullptr, stream, false);
+        if (code < 0) {              // the failed harmonic's buffers keep their roles
+            (void)hipStreamSynchronize((hipStream_t)stream);
+            return code;
+        }
         if (code == AXIPCG_ENOTCONV) worst = AXIPCG_ENOTCONV;
         double *w = u[1];            // u_{m-2} becomes the next work array
         u[1] = u[0];
@@ -79,5 +99,9 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
         u[2] = w;
         if (done) *done = j + 1;
     }
-    return worst;
+    code = guarded([&] {
+        AXI_CHECK_HIP(hipStreamSynchronize((hipStream_t)stream));
+        return AXIPCG_OK;
+    });
+    return code != AXIPCG_OK ? code : worst;
 }

@@ -191,6 +191,7 @@ void free_op(Operator *op)
     for (hipEvent_t e : op->prof_events) (void)hipEventDestroy(e);
     if (op->state_host) (void)hipHostFree(op->state_host);
     if (op->scratch_host) (void)hipHostFree(op->scratch_host);
+    if (op->mirror_host) (void)hipHostFree(op->mirror_host);
     delete op;
 }
 
@@ -250,6 +251,10 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         AXI_CHECK_HIP(hipMemsetAsync(op->pf_err, 0, sizeof(int), s));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->state_host, sizeof(PcgState), hipHostMallocDefault));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->scratch_host, 4 * sizeof(double), hipHostMallocDefault));
+        AXI_CHECK_HIP(hipHostMalloc((void **)&op->mirror_host, sizeof(HostMirror),
+                                    hipHostMallocCoherent | hipHostMallocMapped));
+        *op->mirror_host = HostMirror{};
+        AXI_CHECK_HIP(hipHostGetDevicePointer((void **)&op->mirror_dev, op->mirror_host, 0));
         AXI_CHECK_HIP(hipMemsetAsync(op->partials, 0, sizeof(double) * NUM_SLOTS * MAX_PARTIALS, s));
         AXI_CHECK_HIP(hipMemsetAsync(op->p0, 0, sizeof(double) * n, s));
         AXI_CHECK_HIP(hipMemsetAsync(op->p1, 0, sizeof(double) * n, s));

@@ -50,7 +50,7 @@ def test_series_step_matches_separate_calls(ax, guess, solver):
         net.close()
 
 
-@pytest.mark.parametrize("guess,solver", [("prev", "pcg"), ("nn", "pcg"), ("extrap", "cheb")])
+@pytest.mark.parametrize("guess,solver", [("prev", "pcg"), ("nn", "pcg"), ("extrap", "cheb"), ("nn", "cheb")])
 def test_series_run_matches_steps(ax, guess, solver):
     """Harmonics 0..6 as one run of 2 and one of 5 against seven single steps."""
     from paper_1002_3094_amd.series import LaguerreSeries, SeriesStats, nn_init_params
