@@ -446,19 +446,20 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     ia.mode = 2;
     launch_zinv(op, prec, ia, s);
 
-    // iterations, in chunks: the first one covers the previous solve's count
-    // plus one, so a series of similar solves needs one chunk each (the
-    // launches past the stop test return at once).  The host follows the
-    // solve through the mirror: the stop test publishes a stop at once, and
-    // the next-to-last iteration of a chunk publishes its progress, so that
-    // a further chunk is queued before the current one has drained.
+    // iterations, in chunks: the first one covers the previous solve's
+    // count, so a series of similar solves needs one chunk each (the launches
+    // past the stop test return at once, but still cost a few microseconds
+    // each).  The host follows the solve through the mirror: the stop test
+    // publishes a stop at once, and the last iteration of a chunk publishes
+    // its progress; only then is a further chunk queued, which leaves a short
+    // gap but never more than one iteration of no-op launches.
     int launched = 0;
     int parity = 0;
-    int chunk = op.last_iters > 0 ? op.last_iters + 1 : 4;
+    int chunk = op.last_iters > 0 ? op.last_iters : 4;
     PcgState h{};
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
-        c.report_it = launched + (chunk >= 2 ? chunk - 2 : 0);
+        c.report_it = launched + chunk - 1;
         for (int it = 0; it < chunk; ++it) {
             launch_iteration(c, parity, launched + it);
             parity ^= 1;
@@ -546,11 +547,11 @@ int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, dou
     ZinvArgs ib = ia;
     ib.mode = 3;
     int launched = 0;
-    int chunk = op.last_iters > 0 ? op.last_iters + 1 : 4;
+    int chunk = op.last_iters > 0 ? op.last_iters : 4;
     PcgState h{};
     for (;;) {
         if (chunk > maxit - launched) chunk = maxit - launched;
-        const int report_it = launched + (chunk >= 2 ? chunk - 2 : 0);
+        const int report_it = launched + chunk - 1;
         for (int it = 0; it < chunk; ++it) {
             hipLaunchKernelGGL(k_cheb_update, dim3(gi), dim3(256), 0, s, d, x, op.r, op.D, op.CR, op.CZ, op.nr, op.nz,
                                op.state, op.partials);
