@@ -79,6 +79,8 @@ SIGNATURES = {
                             ctypes.POINTER(Stats), _vp], _i),
     "axipcg_series_run": ([_vp, _vp, _i, _i, _dp, _i, _i, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp), _vp, _i, _i,
                            _d, _i, _i, ctypes.POINTER(Stats), ctypes.POINTER(_i), _vp], _i),
+    "axipcg_series_run_alpha": ([_vp, _i, _i, _i, _dp, _i, _i, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp), _vp, _i, _vp,
+                                 _i, _i, _d, _i, _i, ctypes.POINTER(Stats), ctypes.POINTER(_i), _vp], _i),
     "axipcg_profile_select": ([_vp, _i, _i], _i),
     "axipcg_profile_read": ([_vp, _dp, ctypes.POINTER(ctypes.c_longlong), _i], _i),
     "axipcg_strerror": ([_i], ctypes.c_char_p),
@@ -469,6 +471,38 @@ def series_run(op: Op, m0: int, g, src_i: int, src_k: int, S1, S2, b, u: list, g
                                    _stream(stream))
     u[:] = [by_ptr[ptrs[j]] for j in range(3)]
     _check(code, "series_run", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    return code, [st[j].as_dict() for j in range(done.value)]
+
+
+def series_run_alpha(op: Op, m0: int, alpha: int, g, src_i: int, src_k: int, coef, S1, S2, b, u: list, rec_idx, Q,
+                     guess: str, solver: str = "pcg", rtol=1e-10, maxit=1000, prec=PREC_FP32, stream=None,
+                     allow_notconv=True):
+    """The paper's pipeline over harmonics m0 .. m0 + len(g) - 1 in one call:
+    right-hand side with alpha, zero or previous guess, solve, receiver
+    samples into Q[m] (Q device [>= m0 + len(g)][n_rec], rec_idx int64 device
+    or None).  u is [u_{m0-1}, work], swapped in place after each harmonic.
+    Returns (code, per-harmonic stats dicts)."""
+    import torch
+    if guess not in ("zero", "prev"):
+        raise ValueError("guess must be 'zero' or 'prev'")
+    gv = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    count = int(gv.size)
+    n_rec = 0 if rec_idx is None else int(rec_idx.numel())
+    if n_rec:
+        if Q.dim() != 2 or Q.shape[1] != n_rec or Q.shape[0] < m0 + count:
+            raise ValueError("Q must be [>= m0 + count][n_rec]")
+    ptrs = (_vp * 2)(*[_dev(t, "u") for t in u])
+    by_ptr = {t.data_ptr(): t for t in u}
+    st = (Stats * max(count, 1))()
+    done = _i()
+    code = lib().axipcg_series_run_alpha(op.handle, m0, count, alpha, gv.ctypes.data_as(_dp), src_i, src_k,
+                                         _opt_dev(coef, "coef"), _dev(S1, "S1"), _dev(S2, "S2"), _dev(b, "b"), ptrs,
+                                         _dev_any(rec_idx, "rec_idx", torch.int64) if n_rec else None, n_rec,
+                                         _dev(Q, "Q") if n_rec else None, SERIES_GUESS[guess],
+                                         {"pcg": 0, "cheb": 1}[solver], rtol, maxit, prec, st, ctypes.byref(done),
+                                         _stream(stream))
+    u[:] = [by_ptr[ptrs[j]] for j in range(2)]
+    _check(code, "series_run_alpha", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
     return code, [st[j].as_dict() for j in range(done.value)]
 
 

@@ -105,3 +105,63 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
     });
     return code != AXIPCG_OK ? code : worst;
 }
+
+extern "C" int axipcg_series_run_alpha(axipcg_op_t hop, int m0, int count, int alpha, const double *g, int src_i,
+                                       int src_k, const double *coef, double *S1, double *S2, double *b,
+                                       double **u, const long long *rec_idx, int n_rec, double *Q, int guess,
+                                       int solver, double rtol, int maxit, int prec, axipcg_stats *st, int *done,
+                                       void *stream)
+{
+    if (done) *done = 0;
+    int code = guarded([&] {
+        const Operator *op = reinterpret_cast<const Operator *>(hop);
+        AXI_REQUIRE(op != nullptr, "NULL operator");
+        AXI_REQUIRE(m0 >= 0 && count >= 0, "m0 and count must be >= 0");
+        AXI_REQUIRE(count == 0 || g != nullptr, "g is NULL");
+        AXI_REQUIRE(u != nullptr && u[0] && u[1] && u[0] != u[1], "u must hold two distinct device arrays");
+        AXI_REQUIRE(u[0] != b && u[1] != b && u[0] != S1 && u[1] != S1 && u[0] != S2 && u[1] != S2,
+                    "u aliases b, S1 or S2");
+        AXI_REQUIRE(guess == AXIPCG_GUESS_ZERO || guess == AXIPCG_GUESS_PREV, "guess must be zero or prev");
+        AXI_REQUIRE(solver == 0 || solver == 1, "unknown solver");
+        AXI_REQUIRE(n_rec == 0 || (rec_idx && Q), "receivers need rec_idx and Q");
+        return AXIPCG_OK;
+    });
+    if (code != AXIPCG_OK) return code;
+    const Operator *op = reinterpret_cast<const Operator *>(hop);
+    const size_t bytes = (size_t)op->nr * op->nz * sizeof(double);
+    hipStream_t s = (hipStream_t)stream;
+    int worst = AXIPCG_OK;
+    for (int j = 0; j < count; ++j) {
+        const int m = m0 + j;
+        double *u1 = u[0], *x = u[1];
+        code = axipcg_laguerre_rhs_alpha(hop, m, alpha, g[j], src_i, src_k, coef, m > 0 ? u1 : nullptr, S1, S2, b,
+                                         stream);
+        if (code == AXIPCG_OK)
+            code = guarded([&] {
+                if (guess == AXIPCG_GUESS_ZERO) AXI_CHECK_HIP(hipMemsetAsync(x, 0, bytes, s));
+                else AXI_CHECK_HIP(hipMemcpyAsync(x, u1, bytes, hipMemcpyDeviceToDevice, s));
+                return AXIPCG_OK;
+            });
+        if (code == AXIPCG_OK || code == AXIPCG_ENOTCONV)
+            code = solver == 1
+                       ? cheb_solve_entry(hop, b, x, 0.0, 0.0, rtol, maxit, prec, st ? st + j : nullptr, stream, false)
+                       : pcg_solve_entry(hop, b, x, rtol, maxit, prec, 0u, st ? st + j : nullptr, stream, false);
+        if (code >= 0 && n_rec > 0) {
+            const int gc = axipcg_gather(hop, x, rec_idx, n_rec, Q + (size_t)m * n_rec, stream);
+            if (gc != AXIPCG_OK) code = gc;
+        }
+        if (code < 0) {              // the failed harmonic's buffers keep their roles
+            (void)hipStreamSynchronize(s);
+            return code;
+        }
+        if (code == AXIPCG_ENOTCONV) worst = AXIPCG_ENOTCONV;
+        u[0] = x;
+        u[1] = u1;
+        if (done) *done = j + 1;
+    }
+    code = guarded([&] {
+        AXI_CHECK_HIP(hipStreamSynchronize(s));
+        return AXIPCG_OK;
+    });
+    return code != AXIPCG_OK ? code : worst;
+}

@@ -190,6 +190,22 @@ class PaperSeries:
         self.u1, self.u = self.u, self.u1
         self.m += 1
 
+    def run_harmonics(self, n: int, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats,
+                      solver: str = "pcg"):
+        """The next n harmonics in one library call (series_run_alpha)."""
+        if n <= 0:
+            return
+        if self.m + n > len(self.g):
+            raise ValueError("not enough Laguerre coefficients")
+        u = [self.u1, self.u]
+        code, sts = ax.series_run_alpha(self.op, self.m, self.alpha, self.g[self.m:self.m + n], self.src_i,
+                                        self.src_k, self.coef, self.S1, self.S2, self.b, u, self.rec_idx, self.Q,
+                                        guess, solver=solver, rtol=rtol, maxit=maxit, prec=prec)
+        stats.iters.extend(st["iters"] for st in sts)
+        stats.status.extend(st["status"] for st in sts)
+        self.u1, self.u = u
+        self.m += len(sts)
+
     def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000,
             solver: str = "pcg") -> SeriesStats:
         torch = self.torch
@@ -197,8 +213,7 @@ class PaperSeries:
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(n):
-            self.step(guess, prec, rtol, maxit, stats, solver=solver)
+        self.run_harmonics(n, guess, prec, rtol, maxit, stats, solver=solver)
         e1.record()
         torch.cuda.synchronize()
         stats.gpu_ms = e0.elapsed_time(e1)

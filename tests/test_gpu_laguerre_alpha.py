@@ -64,6 +64,32 @@ def test_paper_chain_and_traces_match_oracle(ax, orc, prec):
         assert np.abs(tr - tro).max() <= 1e-8 * np.abs(tro).max()
 
 
+@pytest.mark.parametrize("guess,solver", [("zero", "pcg"), ("prev", "pcg"), ("prev", "cheb")])
+def test_paper_run_matches_steps(ax, guess, solver):
+    """series_run_alpha (harmonics in one call, runs of 5 and 7) against the
+    same harmonics step by step: the same kernels in the same order, so the
+    solutions and receiver samples agree bit for bit."""
+    from paper_1002_3094_amd.series import PaperSeries, SeriesStats
+    log(f"paper run guess={guess} solver={solver}")
+    nr, nz, n_harm = 96, 128, 12
+    inp = synth.paper_series_inputs(nr, nz, seed=3)
+    with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"]) as op:
+        g = ax.laguerre_coeffs_alpha(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+        args = (op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"], inp["rec_idx"])
+        s1, st1 = PaperSeries(*args), SeriesStats()
+        for _ in range(n_harm):
+            s1.step(guess, ax.PREC_FP32, 1e-10, 1000, st1, solver=solver)
+        s2, st2 = PaperSeries(*args), SeriesStats()
+        s2.run_harmonics(5, guess, ax.PREC_FP32, 1e-10, 1000, st2, solver=solver)
+        s2.run_harmonics(7, guess, ax.PREC_FP32, 1e-10, 1000, st2, solver=solver)
+        log(f"  iterations {st2.iters}")
+        assert st2.iters == st1.iters and all(c == ax.OK for c in st2.status) and s2.m == n_harm
+        np.testing.assert_array_equal(host(s2.u1), host(s1.u1))
+        np.testing.assert_array_equal(host(s2.Q), host(s1.Q))
+        with pytest.raises(ValueError):         # more harmonics than coefficients
+            s2.run_harmonics(1, guess, ax.PREC_FP32, 1e-10, 1000, st2)
+
+
 def test_synthesis_matches_oracle_on_the_same_input(ax, orc):
     import torch
     rng = np.random.default_rng(0)
