@@ -101,23 +101,25 @@ k_nn_norms(const double *__restrict__ u1, const double *__restrict__ b, size_t n
     }
 }
 
-__global__ void __launch_bounds__(256) k_nn_norms_fin(const double *red, int nb, size_t n, double *scal)
+// Every workgroup first sums the norm partials itself (the same fixed order in
+// each, so all agree), instead of a one-workgroup launch doing it in between;
+// workgroup 0 keeps the scales in scal[0..1] for the later kernels.
+__global__ void __launch_bounds__(256)
+k_nn_pack(const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ b,
+          const double *__restrict__ kap, bf16 *__restrict__ act0, size_t n, const double *red, int nb,
+          double *scal)
 {
     __shared__ double sm[8];
     const double t1 = block_total(red, nb, sm);
     const double t2 = block_total(red + MAX_PARTIALS, nb, sm);
-    if (threadIdx.x == 0) {
-        const double s = sqrt(t1 / (double)n), sb = sqrt(t2 / (double)n);
-        scal[0] = s > 0 ? s : 1.0;
-        scal[1] = sb > 0 ? sb : 1.0;
+    double s = sqrt(t1 / (double)n), sb = sqrt(t2 / (double)n);
+    s = s > 0 ? s : 1.0;
+    sb = sb > 0 ? sb : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[0] = s;
+        scal[1] = sb;
     }
-}
-
-__global__ void __launch_bounds__(256)
-k_nn_pack(const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ b,
-          const double *__restrict__ kap, bf16 *__restrict__ act0, size_t n, const double *scal)
-{
-    const double is = 1.0 / scal[0], ib = 1.0 / scal[1];
+    const double is = 1.0 / s, ib = 1.0 / sb;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         bf16x4 v;
         v[0] = (short)to_bf16((float)(u1[e] * is));
@@ -680,35 +682,32 @@ k_guess_res(const double *__restrict__ b, const double *__restrict__ u1, const d
     }
 }
 
-// res[0..2] = residual norms of (network, extrapolation, previous) (res[0]
-// NaN without a network); res[3] = choice (0 previous, 1 extrapolation,
-// 2 network): a candidate replaces a simpler one only when its residual is
-// strictly smaller (a NaN never does).
+// The pick: every workgroup sums the residual partials itself (the same
+// fixed order in each, so all agree) into the norms of (network,
+// extrapolation, previous) (the first NaN without a network) and the choice
+// (0 previous, 1 extrapolation, 2 network): a candidate replaces a simpler one
+// only when its residual is strictly smaller (a NaN never does).  Workgroup 0
+// records them in res[0..3]; then x = the chosen candidate.  x may alias u1
+// or u2 (element-wise read before write).
 template <bool NET>
-__global__ void __launch_bounds__(256) k_guess_fin(const double *red, int nb, double *res)
+__global__ void __launch_bounds__(256)
+k_guess_select(const double *u1, const double *u2, const float *__restrict__ out, double *x, size_t n,
+               const double *red, int nb, double *res, const double *scal)
 {
     __shared__ double sm[8];
     const double fn = NET ? sqrt(block_total(red, nb, sm)) : __builtin_nan("");
     const double fe = sqrt(block_total(red + MAX_PARTIALS, nb, sm));
     const double fp = sqrt(block_total(red + 2 * MAX_PARTIALS, nb, sm));
-    if (threadIdx.x == 0) {
-        int c = 0;
-        double best = fp;
-        if (fe < best) { c = 1; best = fe; }
-        if (NET && fn < best) c = 2;
+    int c = 0;
+    double best = fp;
+    if (fe < best) { c = 1; best = fe; }
+    if (NET && fn < best) c = 2;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         res[0] = fn;
         res[1] = fe;
         res[2] = fp;
         res[3] = (double)c;
     }
-}
-
-template <bool NET>
-__global__ void __launch_bounds__(256)
-k_guess_select(const double *u1, const double *u2, const float *__restrict__ out, double *x, size_t n,
-               const double *res, const double *scal)
-{
-    const int c = (int)res[3];
     const double s = NET ? scal[0] : 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const double p = u1[e], q = u2[e];
@@ -753,6 +752,14 @@ unsigned red_blocks(size_t n)
     return b < 1024 ? b : 1024;
 }
 
+// grid of an element-wise kernel that first sums up to 1024 partials in every
+// workgroup: few enough workgroups that the repeated sums stay cheap
+unsigned fin_blocks(size_t n)
+{
+    const unsigned b = pointwise_blocks(n);
+    return b < 512 ? b : 512;
+}
+
 // grid of the guard's residual kernel: whole rows per workgroup, at most 1024
 // partial sums
 unsigned guard_blocks(int nr) { return nr < 1024 ? (unsigned)nr : 1024u; }
@@ -790,8 +797,8 @@ void forward_impl(Net &n, const double *u1, const double *u2, const double *b, c
     const size_t np = (size_t)n.nr * n.nz;
     const unsigned rb = red_blocks(np);
     hipLaunchKernelGGL(k_nn_norms, dim3(rb), dim3(256), 0, s, u1, b, np, n.red);
-    hipLaunchKernelGGL(k_nn_norms_fin, dim3(1), dim3(256), 0, s, n.red, (int)rb, np, n.scal);
-    hipLaunchKernelGGL(k_nn_pack, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.scal);
+    hipLaunchKernelGGL(k_nn_pack, dim3(fin_blocks(np)), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.red,
+                       (int)rb, n.scal);
     const int rows = conv_rows(n.nr, n.nz);
     const dim3 cg(conv_blocks(n.nr, n.nz, rows)), cb(256);
     const int rows_in = conv_rows(n.nr, n.nz, 8192);
@@ -1006,9 +1013,8 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
         const unsigned pb = guard_blocks(op->nr);
         hipLaunchKernelGGL(k_guess_res<true>, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ,
                            op->nr, op->nz, n->scal, n->red);
-        hipLaunchKernelGGL(k_guess_fin<true>, dim3(1), dim3(256), 0, s, n->red, (int)pb, n->scal + 3);
-        hipLaunchKernelGGL(k_guess_select<true>, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, n->out, x, np,
-                           n->scal + 3, n->scal);
+        hipLaunchKernelGGL(k_guess_select<true>, dim3(fin_blocks(np)), dim3(256), 0, s, u1, u2, n->out, x, np,
+                           n->red, (int)pb, n->scal + 3, n->scal);
         AXI_CHECK_HIP(hipGetLastError());
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1036,9 +1042,8 @@ int axipcg_guess_extrap(axipcg_op_t hop, const double *b, const double *u1, cons
         double *res = op->dscal + 8;
         hipLaunchKernelGGL(k_guess_res<false>, dim3(pb), dim3(256), 0, s, b, u1, u2, nullptr, op->D, op->CR, op->CZ,
                            op->nr, op->nz, nullptr, op->partials);
-        hipLaunchKernelGGL(k_guess_fin<false>, dim3(1), dim3(256), 0, s, op->partials, (int)pb, res);
-        hipLaunchKernelGGL(k_guess_select<false>, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, nullptr, x, np, res,
-                           nullptr);
+        hipLaunchKernelGGL(k_guess_select<false>, dim3(fin_blocks(np)), dim3(256), 0, s, u1, u2, nullptr, x, np,
+                           op->partials, (int)pb, res, nullptr);
         AXI_CHECK_HIP(hipGetLastError());
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
