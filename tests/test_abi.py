@@ -117,3 +117,30 @@ def test_nn_entry_points_validate_before_device_work(ax):
     assert lib.axipcg_nn_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == ax.EINVAL
     assert lib.axipcg_nn_guess(None, None, None, None, None, None, None, None, None, None) == ax.EINVAL
     lib.axipcg_nn_destroy(None)  # NULL-safe
+
+
+def test_series_runs_validate_before_device_work(ax):
+    lib = ax.lib()
+    VP = ctypes.c_void_p
+    g = np.ones(3)
+    a, b, c = VP(1 << 20), VP(2 << 20), VP(3 << 20)       # never dereferenced: rejected first
+    same = (VP * 3)(a, a, c)
+    done = ctypes.c_int(-1)
+    code = lib.axipcg_series_run(None, None, 0, -1, g.ctypes.data_as(ax._dp), 0, 0, None, a, b, c, same, None, 1, 0,
+                                 1e-10, 10, 1, None, ctypes.byref(done), None)
+    assert code == ax.EINVAL and done.value == 0
+    code = lib.axipcg_series_run(None, None, 0, 2, g.ctypes.data_as(ax._dp), 0, 0, None, a, b, c, same, None, 1, 0,
+                                 1e-10, 10, 1, None, None, None)
+    assert code == ax.EINVAL                                 # the three u arrays must be distinct
+    two = (VP * 2)(a, b)
+    code = lib.axipcg_series_run_alpha(None, 0, 2, 5, g.ctypes.data_as(ax._dp), 0, 0, None, a, b, c, two, None, 0,
+                                       None, 0, 0, 1e-10, 10, 1, None, ctypes.byref(done), None)
+    assert code == ax.EINVAL and done.value == 0             # NULL operator
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
