@@ -61,7 +61,7 @@ def parse():
     ap.add_argument("--nr", type=int, default=1024)
     ap.add_argument("--nz", type=int, default=1024)
     ap.add_argument("--seed", type=int, default=101)
-    ap.add_argument("--modes", default="A,B,X,Z,Y,W,C", help="comma-separated modes to run")
+    ap.add_argument("--modes", default="A,B,L,X,Z,Y,W,C", help="comma-separated modes to run")
     ap.add_argument("--headline", default="C", help="mode whose throughput is the value")
     ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--train-harmonics", type=int, default=200)
@@ -330,11 +330,12 @@ def batch_measure(ax, torch, prec, reps=3):
 MODES = {   # (preconditioner, guess, solver)
     "A": ("fp64", "prev", "pcg"),
     "B": ("fp32", "prev", "pcg"),
-    "X": ("fp32", "extrap", "pcg"),
+    "L": ("fp32", "extrap", "pcg"),
+    "X": ("fp32", "poly", "pcg"),
     "Z": ("fp32", "zero", "pcg"),
-    "Y": ("fp32", "extrap", "cheb"),
-    "C": ("fp32", "nn", "pcg"),
-    "W": ("fp32", "nn", "cheb"),
+    "Y": ("fp32", "poly", "cheb"),
+    "C": ("fp32", "nn_poly", "pcg"),
+    "W": ("fp32", "nn_poly", "cheb"),
 }
 NN_FLOP_PER_POINT = 2 * 9 * (4 * 32 + 4 * 32 * 32 + 32 * 1)   # 76 608: six 3x3 convolutions
 BF16_PEAK_TFLOPS = 2500.0
@@ -399,7 +400,7 @@ def main():
     t_setup = time.perf_counter() - t_setup
 
     net, training = (None, None)
-    if any(MODES[m][1] == "nn" for m in modes):
+    if any(MODES[m][1] in ("nn", "nn_poly") for m in modes):
         net, training = train_network(ax, torch, synth, series, a)
 
     results = {}
@@ -445,7 +446,8 @@ def main():
         s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
         st = s.run(n_harm, MODES[a.headline][1], ax.PREC_FP32, rtol=rtol, net=net, want_info=True,
                    solver=MODES[a.headline][2])
-        results[a.headline]["guard_picks_prev_extrap_net"] = np.bincount(st.choice, minlength=3).tolist()
+        k = ax.history_len(MODES[a.headline][1]) + (1 if MODES[a.headline][1] in ("nn", "nn_poly") else 0)
+        results[a.headline]["guard_picks_by_candidate"] = np.bincount(st.choice, minlength=k).tolist()
 
     n_pts = a.nr * a.nz
     # preconditioner applies (3 launches: transform, r-solves, inverse), standalone
@@ -498,7 +500,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64+f32+bf16" if guess == "nn" else ("f64+f32" if prec_name == "fp32" else "f64"),
+        "dtype": "f64+f32+bf16" if guess in ("nn", "nn_poly") else ("f64+f32" if prec_name == "fp32" else "f64"),
         "data": "synthetic",
         "config": {"workload": workload, "nr": a.nr, "nz": a.nz, "medium": "layered", "seed": a.seed,
                    "eta": inp["eta"], "harmonics_timed": a.steps, "mode": a.headline, "preconditioner": prec_name,

@@ -190,6 +190,32 @@ def guard(b, u1, u2, guess, apply_A):
     return (res[2], res[1], res[0]), pick
 
 
+def extrapolate(hist, p):
+    """Order-p polynomial extrapolation to harmonic m through hist[i] =
+    u_{m-1-i}, i <= p: the value at m of the degree-p polynomial in the
+    harmonic index through the last p + 1 harmonics (Lagrange form on equally
+    spaced nodes: weights (-1)^i C(p+1, i+1))."""
+    from math import comb
+    return sum((-1) ** i * comb(p + 1, i + 1) * np.asarray(hist[i], dtype=np.float64) for i in range(p + 1))
+
+
+def guard_poly(b, hist, apply_A, net_guess=None):
+    """Residual norms |b - A x| of the extrapolations of order 0 .. K-1
+    (K = len(hist)) and, last, of net_guess; the pick takes them in that
+    order, a later one replacing the choice only when strictly smaller.
+    Returns (norms, pick, candidates)."""
+    b = np.asarray(b, dtype=np.float64)
+    cands = [extrapolate(hist, p) for p in range(len(hist))]
+    if net_guess is not None:
+        cands.append(np.asarray(net_guess, dtype=np.float64))
+    res = [float(np.sqrt(np.sum((b - apply_A(x)) ** 2))) for x in cands]
+    pick, best = 0, res[0]
+    for j in range(1, len(res)):
+        if res[j] < best:
+            pick, best = j, res[j]
+    return res, pick, cands
+
+
 def adam(params, grads, m1, m2, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam step (bias-corrected moments); returns new (params, m1, m2)."""
     m1 = beta1 * m1 + (1 - beta1) * grads

@@ -62,6 +62,7 @@ SIGNATURES = {
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_guess_extrap": ([_vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
+    "axipcg_guess_poly": ([_vp, _vp, ctypes.POINTER(_vp), _i, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_laguerre_coeffs_alpha": ([_i, _i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs_alpha": ([_vp, _i, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_gather": ([_vp, _vp, _vp, _i, _vp, _vp], _i),
@@ -75,6 +76,7 @@ SIGNATURES = {
     "axipcg_nn_backward": ([_vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_nn_adam": ([_vp, _d, _d, _d, _d, _vp], _i),
     "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
+    "axipcg_nn_guess_poly": ([_vp, _vp, _vp, ctypes.POINTER(_vp), _i, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_series_step": ([_vp, _vp, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _i,
                             ctypes.POINTER(Stats), _vp], _i),
     "axipcg_series_run": ([_vp, _vp, _i, _i, _dp, _i, _i, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp), _vp, _i, _i,
@@ -338,6 +340,20 @@ def guess_extrap(op: Op, b, u1, u2, x, stream=None, want_info=False):
     return (res, choice.value) if want_info else None
 
 
+def guess_poly(op: Op, b, hist: list, x, stream=None, want_info=False):
+    """Polynomial extrapolation of order 0 .. len(hist) - 1 through hist =
+    [u_{m-1}, u_{m-2}, ...] (1 to 5 arrays) with the smallest residual into
+    x; returns (residual norms by order, chosen order) when want_info (which
+    synchronises)."""
+    k = len(hist)
+    res = np.zeros(max(k, 1))
+    choice = _i()
+    ptrs = (_vp * max(k, 1))(*[_dev(t, "hist") for t in hist])
+    _check(lib().axipcg_guess_poly(op.handle, _dev(b, "b"), ptrs, k, _dev(x, "x"), _hp(res) if want_info else None,
+                                   ctypes.byref(choice) if want_info else None, _stream(stream)), "guess_poly")
+    return (res, choice.value) if want_info else None
+
+
 def _fp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
 
@@ -430,8 +446,31 @@ def nn_guess(op: Op, net: Net, b, u1, u2, kappa, x, stream=None, want_info=True)
     return (phi, choice.value) if want_info else None
 
 
-# initial-guess modes of series_step
-SERIES_GUESS = {"zero": 0, "prev": 1, "extrap": 2, "nn": 3}
+def nn_guess_poly(op: Op, net: Net, b, hist: list, kappa, x, stream=None, want_info=True):
+    """The learned guess among the polynomial extrapolations through hist
+    (2 to 5 arrays); returns (residual norms [orders..., network], choice:
+    the order, or len(hist) for the network) when want_info (which
+    synchronises), else None."""
+    k = len(hist)
+    phi = np.zeros(k + 1)
+    choice = _i()
+    ptrs = (_vp * max(k, 1))(*[_dev(t, "hist") for t in hist])
+    _check(lib().axipcg_nn_guess_poly(op.handle, net.handle, _dev(b, "b"), ptrs, k, _dev(kappa, "kappa"),
+                                      _dev(x, "x"), _hp(phi) if want_info else None,
+                                      ctypes.byref(choice) if want_info else None, _stream(stream)),
+           "nn_guess_poly")
+    return (phi, choice.value) if want_info else None
+
+
+# initial-guess modes of series_step / series_run; the polynomial ones read
+# POLY_HISTORY earlier harmonics and exist in series_run only
+SERIES_GUESS = {"zero": 0, "prev": 1, "extrap": 2, "nn": 3, "poly": 4, "nn_poly": 5}
+POLY_HISTORY = 5
+
+
+def history_len(guess: str) -> int:
+    """Earlier harmonics a guess mode reads."""
+    return POLY_HISTORY if guess in ("poly", "nn_poly") else 2
 
 
 def series_step(op: Op, m: int, g_m: float, src_i: int, src_k: int, S1, S2, b, u1, u2, x, guess: str,
@@ -455,12 +494,16 @@ def series_run(op: Op, m0: int, g, src_i: int, src_k: int, S1, S2, b, u: list, g
                solver: str = "pcg", net=None, kappa=None, coef=None, rtol=1e-10, maxit=1000, prec=PREC_FP32,
                stream=None, allow_notconv=True):
     """Harmonics m0 .. m0 + len(g) - 1 in one call (see series_step).  u is a
-    list of three device arrays [u_{m0-1}, u_{m0-2}, work]; it is rotated in
-    place so that afterwards u[0] holds the last solution and u[1] the one
-    before.  Returns (code, per-harmonic stats dicts)."""
+    list of device arrays [u_{m0-1}, u_{m0-2}, ..., work]: three, or six for
+    the polynomial guesses; it is rotated in place so that afterwards u[0]
+    holds the last solution, u[1] the one before, and so on.  Returns (code,
+    per-harmonic stats dicts)."""
     gv = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
     count = int(gv.size)
-    ptrs = (_vp * 3)(*[_dev(t, "u") for t in u])
+    nu = history_len(guess) + 1
+    if len(u) != nu:
+        raise ValueError(f"guess {guess!r} needs {nu} arrays in u")
+    ptrs = (_vp * nu)(*[_dev(t, "u") for t in u])
     by_ptr = {t.data_ptr(): t for t in u}
     st = (Stats * max(count, 1))()
     done = _i()
@@ -469,7 +512,7 @@ def series_run(op: Op, m0: int, g, src_i: int, src_k: int, S1, S2, b, u: list, g
                                    _dev(S2, "S2"), _dev(b, "b"), ptrs, _opt_dev(kappa, "kappa"), SERIES_GUESS[guess],
                                    {"pcg": 0, "cheb": 1}[solver], rtol, maxit, prec, st, ctypes.byref(done),
                                    _stream(stream))
-    u[:] = [by_ptr[ptrs[j]] for j in range(3)]
+    u[:] = [by_ptr[ptrs[j]] for j in range(nu)]
     _check(code, "series_run", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
     return code, [st[j].as_dict() for j in range(done.value)]
 

@@ -76,7 +76,7 @@ struct Net {
     bf16 *dpre[2] = {};          // gradient w.r.t. a layer's pre-activation (<= 32 ch)
     float *wpart = nullptr;      // weight-gradient partials [WG_BLOCKS][9*32*32 + 32]
     double *scal = nullptr;      // [0] s, [1] s_b, [2] loss, [3] residual of guess, [4] residual of u1
-    double *red = nullptr;       // [3][MAX_PARTIALS] partial sums
+    double *red = nullptr;       // [GMAX + 1][MAX_PARTIALS] partial sums
     double *res_host = nullptr;  // pinned
 };
 
@@ -599,120 +599,156 @@ k_nn_unpack(const double *u1, const double *u2, const float *__restrict__ out, d
 }
 
 // ---- guard -------------------------------------------------------------------------
-// Partial sums of |b - A x|^2 for the candidates x_p = u1, x_e = 2 u1 - u2 and
-// (NET) x_n = x_e + s out (PCG's stop test measures this norm, and with a
-// spectrally equivalent preconditioner the iterations a start needs follow
-// it).  red[0..2][MAX_PARTIALS]: network, extrapolation, previous.
-template <bool NET>
-__global__ void __launch_bounds__(256)
-k_guess_res(const double *__restrict__ b, const double *__restrict__ u1, const double *__restrict__ u2,
-            const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
-            const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
+// ---- the guard: candidate initial guesses ranked by residual ----------------
+// History u_{m-1}, ..., u_{m-K} (K <= GMAX).  Candidate p < K is the
+// polynomial extrapolation of order p through the last p + 1 harmonics,
+//     x_p = sum_{i <= p} (-1)^i C(p+1, i+1) u_{m-1-i}
+// (u_{m-1}; 2 u_{m-1} - u_{m-2}; 3 u_{m-1} - 3 u_{m-2} + u_{m-3}; ...), and
+// with a network candidate K the learned guess x_1 + s out (its correction
+// sits on the linear extrapolation).  PCG's stop test measures |b - A x|, and
+// with a spectrally equivalent preconditioner the iterations a start needs
+// follow it, so the guard ranks the candidates by that norm.
+constexpr int GMAX = 5;
+struct Hist {
+    const double *u[GMAX];
+};
+__device__ constexpr double kExtrap[GMAX][GMAX] = {
+    {1, 0, 0, 0, 0}, {2, -1, 0, 0, 0}, {3, -3, 1, 0, 0}, {4, -6, 4, -1, 0}, {5, -10, 10, -5, 1}};
+
+__device__ inline double2 ld_pair(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+__device__ inline double2 ld_pair(const float *p)
 {
-    // workgroups take whole rows, the rows of one XCD contiguous (their
-    // neighbour rows then come from that XCD's L2); each thread the element
-    // pairs (k, k + 1), k even, read as 16-byte (8-byte for out) vectors; the
-    // coefficients are read once for the three candidates
+    const float2 v = *reinterpret_cast<const float2 *>(p);
+    return double2{(double)v.x, (double)v.y};
+}
+
+// f + |r|^2 without contraction into fused multiply-adds, so that equal
+// residuals give bit-equal sums whichever candidate they belong to (ties then
+// keep the lower-order candidate)
+__device__ inline double add_sq(double f, double2 r)
+{
+    return __dadd_rn(f, __dadd_rn(__dmul_rn(r.x, r.x), __dmul_rn(r.y, r.y)));
+}
+
+// (A v) at the element pair (k, k + 1) of row i, k even (d, cz: the pair's
+// diagonal and z-couplings, already loaded)
+template <typename V>
+__device__ inline double2 apply_pair(const V *__restrict__ v, double2 d, double2 cz, const double *__restrict__ CR,
+                                     const double *__restrict__ CZ, size_t e, int i, int k, int nr, int nz)
+{
+    const double2 c = ld_pair(v + e);
+    double2 a{d.x * c.x, d.y * c.y};
+    if (i + 1 < nr) {
+        const double2 cr = ld_pair(CR + e), vn = ld_pair(v + e + nz);
+        a.x -= cr.x * vn.x;
+        a.y -= cr.y * vn.y;
+    }
+    if (i > 0) {
+        const double2 cr = ld_pair(CR + e - nz), vn = ld_pair(v + e - nz);
+        a.x -= cr.x * vn.x;
+        a.y -= cr.y * vn.y;
+    }
+    a.x -= cz.x * c.y;   // (k, k+1) inside the pair, k-1 and k+2 outside
+    a.y -= cz.x * c.x;
+    if (k + 2 < nz) a.y -= cz.y * (double)v[e + 2];
+    if (k > 0) a.x -= CZ[e - 1] * (double)v[e - 1];
+    return a;
+}
+
+// Partial sums of |b - A x_p|^2 for every candidate: red[p][MAX_PARTIALS],
+// p < K the extrapolations, p = K the network.  Workgroups take whole rows,
+// the rows of one XCD contiguous (their neighbour rows then come from that
+// XCD's L2); each thread the element pairs (k, k + 1), k even.  A x_p is
+// formed from the A u_j, so each history array is read once.
+template <int K, bool NET>
+__global__ void __launch_bounds__(256)
+k_guess_hist(const double *__restrict__ b, Hist h, const float *__restrict__ out, const double *__restrict__ D,
+             const double *__restrict__ CR, const double *__restrict__ CZ, int nr, int nz, const double *scal,
+             double *red)
+{
+    static_assert(K >= 1 && K <= GMAX && (!NET || K >= 2), "history length");
     __shared__ double sm[8];
     const double s = NET ? scal[0] : 0.0;
-    double fp = 0.0, fe = 0.0, fn = 0.0;
-    auto ld = [](const double *p) { return *reinterpret_cast<const double2 *>(p); };
-    auto ldo = [](const float *p) {
-        const float2 v = *reinterpret_cast<const float2 *>(p);
-        return double2{(double)v.x, (double)v.y};
-    };
+    double f[K + 1];
+#pragma unroll
+    for (int p = 0; p <= K; ++p) f[p] = 0.0;
     for (int blk = blockIdx.x; blk < nr; blk += gridDim.x) {
         const int i = xcd_swizzle(blk, nr);
         for (int k = 2 * threadIdx.x; k < nz; k += 512) {
             const size_t e = (size_t)i * nz + k;
-            const double2 d = ld(D + e), cz = ld(CZ + e), bv = ld(b + e);
-            const double2 c1 = ld(u1 + e), c2 = ld(u2 + e);
-            const double2 co = NET ? ldo(out + e) : double2{0.0, 0.0};
-            double2 a1{d.x * c1.x, d.y * c1.y}, a2{d.x * c2.x, d.y * c2.y}, ao{d.x * co.x, d.y * co.y};
-            if (i + 1 < nr) {
-                const double2 c = ld(CR + e), v1 = ld(u1 + e + nz), v2 = ld(u2 + e + nz);
-                a1.x -= c.x * v1.x; a1.y -= c.y * v1.y;
-                a2.x -= c.x * v2.x; a2.y -= c.y * v2.y;
-                if (NET) {
-                    const double2 vo = ldo(out + e + nz);
-                    ao.x -= c.x * vo.x; ao.y -= c.y * vo.y;
+            const double2 d = ld_pair(D + e), cz = ld_pair(CZ + e), bv = ld_pair(b + e);
+            double2 au[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) au[j] = apply_pair(h.u[j], d, cz, CR, CZ, e, i, k, nr, nz);
+            double2 r1{0.0, 0.0};
+#pragma unroll
+            for (int p = 0; p < K; ++p) {
+                double2 a{0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q <= p; ++q) {
+                    a.x += kExtrap[p][q] * au[q].x;
+                    a.y += kExtrap[p][q] * au[q].y;
                 }
+                const double2 r{bv.x - a.x, bv.y - a.y};
+                if (p == 1) r1 = r;
+                f[p] = add_sq(f[p], r);
             }
-            if (i > 0) {
-                const double2 c = ld(CR + e - nz), v1 = ld(u1 + e - nz), v2 = ld(u2 + e - nz);
-                a1.x -= c.x * v1.x; a1.y -= c.y * v1.y;
-                a2.x -= c.x * v2.x; a2.y -= c.y * v2.y;
-                if (NET) {
-                    const double2 vo = ldo(out + e - nz);
-                    ao.x -= c.x * vo.x; ao.y -= c.y * vo.y;
-                }
-            }
-            // z-couplings: (k, k+1) inside the pair, k-1 and k+2 outside
-            a1.x -= cz.x * c1.y; a1.y -= cz.x * c1.x;
-            a2.x -= cz.x * c2.y; a2.y -= cz.x * c2.x;
-            ao.x -= cz.x * co.y; ao.y -= cz.x * co.x;
-            if (k + 2 < nz) {
-                a1.y -= cz.y * u1[e + 2];
-                a2.y -= cz.y * u2[e + 2];
-                if (NET) ao.y -= cz.y * (double)out[e + 2];
-            }
-            if (k > 0) {
-                const double c = CZ[e - 1];
-                a1.x -= c * u1[e - 1];
-                a2.x -= c * u2[e - 1];
-                if (NET) ao.x -= c * (double)out[e - 1];
-            }
-            const double rpx = bv.x - a1.x, rpy = bv.y - a1.y;
-            const double rex = bv.x - (2.0 * a1.x - a2.x), rey = bv.y - (2.0 * a1.y - a2.y);
-            fp += rpx * rpx + rpy * rpy;
-            fe += rex * rex + rey * rey;
             if (NET) {
-                const double rnx = rex - s * ao.x, rny = rey - s * ao.y;
-                fn += rnx * rnx + rny * rny;
+                // the network's candidate is x_1 + s out: its residual is r_1 - s A out
+                const double2 ao = apply_pair(out, d, cz, CR, CZ, e, i, k, nr, nz);
+                f[K] = add_sq(f[K], double2{r1.x - s * ao.x, r1.y - s * ao.y});
             }
         }
     }
-    const double tp = block_sum(fp, sm);
-    const double te = block_sum(fe, sm);
-    const double tn = NET ? block_sum(fn, sm) : 0.0;
-    if (threadIdx.x == 0) {
-        if (NET) red[blockIdx.x] = tn;
-        red[MAX_PARTIALS + blockIdx.x] = te;
-        red[2 * MAX_PARTIALS + blockIdx.x] = tp;
+#pragma unroll
+    for (int p = 0; p <= K; ++p) {
+        if (p == K && !NET) break;
+        const double t = block_sum(f[p], sm);
+        if (threadIdx.x == 0) red[(size_t)p * MAX_PARTIALS + blockIdx.x] = t;
     }
 }
 
-// The pick: every workgroup sums the residual partials itself (the same
-// fixed order in each, so all agree) into the norms of (network,
-// extrapolation, previous) (the first NaN without a network) and the choice
-// (0 previous, 1 extrapolation, 2 network): a candidate replaces a simpler one
+// The pick: every workgroup sums the partials itself (the same fixed order in
+// each, so all agree) into the residual norms, and takes the candidates in
+// the order x_0, x_1, ..., network: a later one replaces the current choice
 // only when its residual is strictly smaller (a NaN never does).  Workgroup 0
-// records them in res[0..3]; then x = the chosen candidate.  x may alias u1
-// or u2 (element-wise read before write).
-template <bool NET>
+// records res[p] (p <= K; res[K] NaN without a network) and res[K + 1] = the
+// choice; then x = the chosen candidate.  x may alias a history array
+// (element-wise read before write).
+template <int K, bool NET>
 __global__ void __launch_bounds__(256)
-k_guess_select(const double *u1, const double *u2, const float *__restrict__ out, double *x, size_t n,
-               const double *red, int nb, double *res, const double *scal)
+k_guess_pick(Hist h, const float *__restrict__ out, double *x, size_t n, const double *red, int nb, double *res,
+             const double *scal)
 {
     __shared__ double sm[8];
-    const double fn = NET ? sqrt(block_total(red, nb, sm)) : __builtin_nan("");
-    const double fe = sqrt(block_total(red + MAX_PARTIALS, nb, sm));
-    const double fp = sqrt(block_total(red + 2 * MAX_PARTIALS, nb, sm));
+    double f[K + 1];
+#pragma unroll
+    for (int p = 0; p < K; ++p) f[p] = sqrt(block_total(red + (size_t)p * MAX_PARTIALS, nb, sm));
+    f[K] = NET ? sqrt(block_total(red + (size_t)K * MAX_PARTIALS, nb, sm)) : __builtin_nan("");
     int c = 0;
-    double best = fp;
-    if (fe < best) { c = 1; best = fe; }
-    if (NET && fn < best) c = 2;
+    double best = f[0];
+#pragma unroll
+    for (int p = 1; p <= K; ++p)
+        if ((p < K || NET) && f[p] < best) {
+            c = p;
+            best = f[p];
+        }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        res[0] = fn;
-        res[1] = fe;
-        res[2] = fp;
-        res[3] = (double)c;
+#pragma unroll
+        for (int p = 0; p <= K; ++p) res[p] = f[p];
+        res[K + 1] = (double)c;
     }
     const double s = NET ? scal[0] : 0.0;
+    const int order = c < K ? c : 1;   // the network's base is the linear extrapolation
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
-        const double p = u1[e], q = u2[e];
-        double v = c == 0 ? p : 2.0 * p - q;
-        if (NET && c == 2) v += s * (double)out[e];
+        double u[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) u[q] = q <= order ? h.u[q][e] : 0.0;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q)
+            if (q <= order) v += kExtrap[order][q] * u[q];
+        if (NET && c == K) v += s * (double)out[e];
         x[e] = v;
     }
 }
@@ -763,6 +799,60 @@ unsigned fin_blocks(size_t n)
 // grid of the guard's residual kernel: whole rows per workgroup, at most 1024
 // partial sums
 unsigned guard_blocks(int nr) { return nr < 1024 ? (unsigned)nr : 1024u; }
+
+template <int K, bool NET>
+void guard_k(const Operator &op, const double *b, const Hist &h, const float *out, const double *scal, double *red,
+             double *x, double *res, hipStream_t s)
+{
+    const size_t np = (size_t)op.nr * op.nz;
+    const unsigned pb = guard_blocks(op.nr);
+    hipLaunchKernelGGL((k_guess_hist<K, NET>), dim3(pb), dim3(256), 0, s, b, h, out, op.D, op.CR, op.CZ, op.nr,
+                       op.nz, scal, red);
+    hipLaunchKernelGGL((k_guess_pick<K, NET>), dim3(fin_blocks(np)), dim3(256), 0, s, h, out, x, np, red, (int)pb,
+                       res, scal);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+// Guard over the history h (K arrays) and, with out, the network candidate:
+// partial sums in red (K + 1 rows), norms and choice in res (K + 2 values).
+void run_guard(const Operator &op, const double *b, const Hist &h, int K, const float *out, const double *scal,
+               double *red, double *x, double *res, hipStream_t s)
+{
+    if (out) {
+        switch (K) {
+        case 2: return guard_k<2, true>(op, b, h, out, scal, red, x, res, s);
+        case 3: return guard_k<3, true>(op, b, h, out, scal, red, x, res, s);
+        case 4: return guard_k<4, true>(op, b, h, out, scal, red, x, res, s);
+        case 5: return guard_k<5, true>(op, b, h, out, scal, red, x, res, s);
+        default: break;
+        }
+    } else {
+        switch (K) {
+        case 1: return guard_k<1, false>(op, b, h, out, scal, red, x, res, s);
+        case 2: return guard_k<2, false>(op, b, h, out, scal, red, x, res, s);
+        case 3: return guard_k<3, false>(op, b, h, out, scal, red, x, res, s);
+        case 4: return guard_k<4, false>(op, b, h, out, scal, red, x, res, s);
+        case 5: return guard_k<5, false>(op, b, h, out, scal, red, x, res, s);
+        default: break;
+        }
+    }
+    throw Error{AXIPCG_EINVAL, "history length out of range"};
+}
+
+// The history arrays of a guard call (host array of K device pointers).
+Hist make_hist(const double *const *hist, int K, const double *x, const double *b, const double *kappa)
+{
+    AXI_REQUIRE(hist != nullptr, "hist is NULL");
+    AXI_REQUIRE(K >= 1 && K <= GMAX, "history length must be in [1, 5]");
+    Hist h{};
+    for (int j = 0; j < K; ++j) {
+        AXI_REQUIRE(hist[j] != nullptr, "NULL history array");
+        AXI_REQUIRE(hist[j] != b && hist[j] != kappa, "a history array aliases b or kappa");
+        h.u[j] = hist[j];
+    }
+    AXI_REQUIRE(x != b && x != kappa, "x aliases b or kappa");
+    return h;
+}
 
 void pack_all(Net &n, hipStream_t s)
 {
@@ -875,8 +965,8 @@ Net *create_impl_nn(int nr, int nz, const float *params)
         nalloc(&n->dpre[0], np * 32);
         nalloc(&n->dpre[1], np * 32);
         nalloc(&n->wpart, (size_t)WG_BLOCKS * (9 * 32 * 32 + 32));
-        nalloc(&n->scal, 8);
-        nalloc(&n->red, 3 * (size_t)MAX_PARTIALS);
+        nalloc(&n->scal, 16);
+        nalloc(&n->red, (GMAX + 1) * (size_t)MAX_PARTIALS);
         AXI_CHECK_HIP(hipHostMalloc((void **)&n->res_host, 8 * sizeof(double), hipHostMallocDefault));
         AXI_CHECK_HIP(hipMemcpy(n->params, params, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
         AXI_CHECK_HIP(hipMemset(n->grads, 0, sizeof(float) * NPARAM));
@@ -1009,19 +1099,44 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
         AXI_REQUIRE(x != b && x != kappa, "x aliases b or kappa");
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
-        const size_t np = (size_t)n->nr * n->nz;
-        const unsigned pb = guard_blocks(op->nr);
-        hipLaunchKernelGGL(k_guess_res<true>, dim3(pb), dim3(256), 0, s, b, u1, u2, n->out, op->D, op->CR, op->CZ,
-                           op->nr, op->nz, n->scal, n->red);
-        hipLaunchKernelGGL(k_guess_select<true>, dim3(fin_blocks(np)), dim3(256), 0, s, u1, u2, n->out, x, np,
-                           n->red, (int)pb, n->scal + 3, n->scal);
-        AXI_CHECK_HIP(hipGetLastError());
+        const double *hist[2] = {u1, u2};
+        // res: u1, extrapolation, network, choice (0 u1, 1 extrapolation, 2 network)
+        double *res = n->scal + 3;
+        run_guard(*op, b, make_hist(hist, 2, x, b, kappa), 2, n->out, n->scal, n->red, x, res, s);
         if (resid_host || choice_host) {
-            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 3, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            if (resid_host) {
+                resid_host[0] = n->res_host[2];
+                resid_host[1] = n->res_host[1];
+                resid_host[2] = n->res_host[0];
+            }
+            if (choice_host) *choice_host = (int)n->res_host[3];
+        }
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_guess_poly(axipcg_op_t hop, axipcg_nn_t h, const double *b, const double *const *hist, int K,
+                         const double *kappa, double *x, double *resid_host, int *choice_host, void *stream)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(hop);
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(op && n && b && kappa && x, "NULL argument");
+        AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
+        AXI_REQUIRE(K >= 2, "the learned guess needs at least two history arrays");
+        const Hist hh = make_hist(hist, K, x, b, kappa);
+        hipStream_t s = (hipStream_t)stream;
+        forward_impl(*n, hist[0], hist[1], b, kappa, s);
+        double *res = n->scal + 3;
+        run_guard(*op, b, hh, K, n->out, n->scal, n->red, x, res, s);
+        if (resid_host || choice_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, res, (K + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
             if (resid_host)
-                for (int j = 0; j < 3; ++j) resid_host[j] = n->res_host[j];
-            if (choice_host) *choice_host = (int)n->res_host[3];
+                for (int p = 0; p <= K; ++p) resid_host[p] = n->res_host[p];
+            if (choice_host) *choice_host = (int)n->res_host[K + 1];
         }
         return AXIPCG_OK;
     });
@@ -1033,26 +1148,43 @@ int axipcg_guess_extrap(axipcg_op_t hop, const double *b, const double *u1, cons
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(hop);
         AXI_REQUIRE(op && b && u1 && u2 && x, "NULL argument");
-        AXI_REQUIRE(x != b, "x aliases b");
         hipStream_t s = (hipStream_t)stream;
-        const size_t np = (size_t)op->nr * op->nz;
-        const unsigned pb = guard_blocks(op->nr);
-        // the reductions use the handle's partial-sum rows 0..2 and scalars 8..11,
-        // which a solve only reads after writing them itself
+        const double *hist[2] = {u1, u2};
+        // the reductions use the handle's partial-sum rows 0..1 and scalars 8..11,
+        // which a solve only reads after writing them itself; res: u1,
+        // extrapolation, (no network), choice
         double *res = op->dscal + 8;
-        hipLaunchKernelGGL(k_guess_res<false>, dim3(pb), dim3(256), 0, s, b, u1, u2, nullptr, op->D, op->CR, op->CZ,
-                           op->nr, op->nz, nullptr, op->partials);
-        hipLaunchKernelGGL(k_guess_select<false>, dim3(fin_blocks(np)), dim3(256), 0, s, u1, u2, nullptr, x, np,
-                           op->partials, (int)pb, res, nullptr);
-        AXI_CHECK_HIP(hipGetLastError());
+        run_guard(*op, b, make_hist(hist, 2, x, b, nullptr), 2, nullptr, nullptr, op->partials, x, res, s);
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
             if (resid_host) {
                 resid_host[0] = op->scratch_host[1];
-                resid_host[1] = op->scratch_host[2];
+                resid_host[1] = op->scratch_host[0];
             }
             if (choice_host) *choice_host = (int)op->scratch_host[3];
+        }
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_guess_poly(axipcg_op_t hop, const double *b, const double *const *hist, int K, double *x,
+                      double *resid_host, int *choice_host, void *stream)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(hop);
+        AXI_REQUIRE(op && b && x, "NULL argument");
+        const Hist hh = make_hist(hist, K, x, b, nullptr);
+        hipStream_t s = (hipStream_t)stream;
+        // partial-sum rows 0..K-1 and scalars 8..8+K+1 of the handle (see guess_extrap)
+        double *res = op->dscal + 8;
+        run_guard(*op, b, hh, K, nullptr, nullptr, op->partials, x, res, s);
+        if (resid_host || choice_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, (K + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            if (resid_host)
+                for (int p = 0; p < K; ++p) resid_host[p] = op->scratch_host[p];
+            if (choice_host) *choice_host = (int)op->scratch_host[K + 1];
         }
         return AXIPCG_OK;
     });

@@ -13,18 +13,30 @@ namespace {
 
 // sync_end = false: return once the host has seen the solve's outcome, with
 // the tail of its last chunk possibly still queued (see pcg_solve_entry).
+// Number of earlier harmonics a guess mode reads.
+int history_of(int guess)
+{
+    return (guess == AXIPCG_GUESS_POLY || guess == AXIPCG_GUESS_NN_POLY) ? AXIPCG_POLY_HISTORY : 2;
+}
+
+// hist[j] = u_{m-1-j}, nh = history_of(guess) arrays.
 int series_step_impl(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k, const double *coef,
-                     double *S1, double *S2, double *b, const double *u1, const double *u2, const double *kappa,
+                     double *S1, double *S2, double *b, const double *const *hist, int nh, const double *kappa,
                      double *x, int guess, int solver, double rtol, int maxit, int prec, axipcg_stats *st,
                      void *stream, bool sync_end)
 {
+    const double *u1 = hist[0], *u2 = hist[1];
     int code = guarded([&] {
-        AXI_REQUIRE(hop && S1 && S2 && b && u1 && u2 && x, "NULL argument");
+        AXI_REQUIRE(hop && S1 && S2 && b && x, "NULL argument");
+        for (int j = 0; j < nh; ++j) AXI_REQUIRE(hist[j] != nullptr, "NULL argument");
         AXI_REQUIRE(m >= 0, "m must be >= 0");
-        AXI_REQUIRE(guess >= AXIPCG_GUESS_ZERO && guess <= AXIPCG_GUESS_NN, "unknown guess mode");
+        AXI_REQUIRE(guess >= AXIPCG_GUESS_ZERO && guess <= AXIPCG_GUESS_NN_POLY, "unknown guess mode");
+        AXI_REQUIRE(nh == history_of(guess), "polynomial guesses need axipcg_series_run");
         AXI_REQUIRE(solver == 0 || solver == 1, "unknown solver");
-        AXI_REQUIRE(guess != AXIPCG_GUESS_NN || (nn && kappa), "the learned guess needs nn and kappa");
-        AXI_REQUIRE(x != b && x != S1 && x != S2 && x != u1 && x != u2, "x aliases another array");
+        AXI_REQUIRE((guess != AXIPCG_GUESS_NN && guess != AXIPCG_GUESS_NN_POLY) || (nn && kappa),
+                    "the learned guess needs nn and kappa");
+        AXI_REQUIRE(x != b && x != S1 && x != S2, "x aliases another array");
+        for (int j = 0; j < nh; ++j) AXI_REQUIRE(x != hist[j], "x aliases another array");
         return AXIPCG_OK;
     });
     if (code != AXIPCG_OK) return code;
@@ -48,8 +60,14 @@ int series_step_impl(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src
     case AXIPCG_GUESS_EXTRAP:
         code = axipcg_guess_extrap(hop, b, u1, u2, x, nullptr, nullptr, stream);
         break;
-    default:
+    case AXIPCG_GUESS_NN:
         code = axipcg_nn_guess(hop, nn, b, u1, u2, kappa, x, nullptr, nullptr, stream);
+        break;
+    case AXIPCG_GUESS_POLY:
+        code = axipcg_guess_poly(hop, b, hist, nh, x, nullptr, nullptr, stream);
+        break;
+    default:
+        code = axipcg_nn_guess_poly(hop, nn, b, hist, nh, kappa, x, nullptr, nullptr, stream);
         break;
     }
     if (code != AXIPCG_OK) return code;
@@ -64,7 +82,8 @@ extern "C" int axipcg_series_step(axipcg_op_t hop, axipcg_nn_t nn, int m, double
                                   const double *u2, const double *kappa, double *x, int guess, int solver,
                                   double rtol, int maxit, int prec, axipcg_stats *st, void *stream)
 {
-    return series_step_impl(hop, nn, m, g_m, src_i, src_k, coef, S1, S2, b, u1, u2, kappa, x, guess, solver, rtol,
+    const double *hist[2] = {u1, u2};
+    return series_step_impl(hop, nn, m, g_m, src_i, src_k, coef, S1, S2, b, hist, 2, kappa, x, guess, solver, rtol,
                             maxit, prec, st, stream, true);
 }
 
@@ -74,11 +93,15 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
                                  axipcg_stats *st, int *done, void *stream)
 {
     if (done) *done = 0;
+    const int nh = history_of(guess);
     int code = guarded([&] {
         AXI_REQUIRE(m0 >= 0 && count >= 0, "m0 and count must be >= 0");
         AXI_REQUIRE(count == 0 || g != nullptr, "g is NULL");
-        AXI_REQUIRE(u != nullptr && u[0] && u[1] && u[2], "u must hold three device arrays");
-        AXI_REQUIRE(u[0] != u[1] && u[1] != u[2] && u[0] != u[2], "the three u arrays must be distinct");
+        AXI_REQUIRE(u != nullptr, "u is NULL");
+        for (int j = 0; j <= nh; ++j) {
+            AXI_REQUIRE(u[j] != nullptr, "u must hold the history arrays and a work array");
+            for (int i = 0; i < j; ++i) AXI_REQUIRE(u[i] != u[j], "the u arrays must be distinct");
+        }
         return AXIPCG_OK;
     });
     if (code != AXIPCG_OK) return code;
@@ -86,17 +109,17 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
     // next right-hand side is queued behind the tail of the previous solve
     int worst = AXIPCG_OK;
     for (int j = 0; j < count; ++j) {
-        code = series_step_impl(hop, nn, m0 + j, g[j], src_i, src_k, coef, S1, S2, b, u[0], u[1], kappa, u[2], guess,
+        code = series_step_impl(hop, nn, m0 + j, g[j], src_i, src_k, coef, S1, S2, b, u, nh, kappa, u[nh], guess,
                                 solver, rtol, maxit, prec, st ? st + j : nullptr, stream, false);
         if (code < 0) {              // the failed harmonic's buffers keep their roles
             (void)hipStreamSynchronize((hipStream_t)stream);
             return code;
         }
         if (code == AXIPCG_ENOTCONV) worst = AXIPCG_ENOTCONV;
-        double *w = u[1];            // u_{m-2} becomes the next work array
-        u[1] = u[0];
-        u[0] = u[2];
-        u[2] = w;
+        double *w = u[nh - 1];       // the oldest harmonic becomes the next work array
+        for (int i = nh - 1; i > 0; --i) u[i] = u[i - 1];
+        u[0] = u[nh];
+        u[nh] = w;
         if (done) *done = j + 1;
     }
     code = guarded([&] {

@@ -250,7 +250,7 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         AXI_CHECK_HIP(hipMemsetAsync(op->pf_bar, 0, (1 + 256) * sizeof(unsigned), s));
         AXI_CHECK_HIP(hipMemsetAsync(op->pf_err, 0, sizeof(int), s));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->state_host, sizeof(PcgState), hipHostMallocDefault));
-        AXI_CHECK_HIP(hipHostMalloc((void **)&op->scratch_host, 4 * sizeof(double), hipHostMallocDefault));
+        AXI_CHECK_HIP(hipHostMalloc((void **)&op->scratch_host, 16 * sizeof(double), hipHostMallocDefault));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->mirror_host, sizeof(HostMirror),
                                     hipHostMallocCoherent | hipHostMallocMapped));
         *op->mirror_host = HostMirror{};

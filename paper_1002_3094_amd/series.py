@@ -35,9 +35,10 @@ class SeriesStats:
 
 
 class LaguerreSeries:
-    """Device state of one series: running sums, right-hand side, the last two
-    solutions and the current one.  ``kappa`` (host [nr][nz]) feeds the
-    learned guess."""
+    """Device state of one series: running sums, right-hand side, the last
+    five solutions (``hist[0]`` = u_{m-1}, the guesses read two or all five)
+    and the current one.  ``kappa`` (host [nr][nz]) feeds the learned guess.
+    One series keeps to one guess mode."""
 
     def __init__(self, op: "ax.Op", g, src_i: int, src_k: int, kappa=None, coef=None):
         import torch
@@ -47,13 +48,26 @@ class LaguerreSeries:
         shape = (op.nr, op.nz)
         z = lambda: torch.zeros(shape, dtype=torch.float64, device="cuda")  # noqa: E731
         self.S1, self.S2, self.b = z(), z(), z()
-        self.u1, self.u2, self.u = z(), z(), z()
+        self.hist = [z() for _ in range(ax.POLY_HISTORY)]
+        self.u = z()
         self.coef = coef
         self.kappa = None if kappa is None else torch.as_tensor(kappa, dtype=torch.float64).cuda().contiguous()
         self.m = 0
 
+    @property
+    def u1(self):
+        return self.hist[0]
+
+    @property
+    def u2(self):
+        return self.hist[1]
+
+    def _rotate(self):
+        """The solved harmonic becomes u_{m-1}; the oldest array is the next work array."""
+        self.hist, self.u = [self.u] + self.hist[:-1], self.hist[-1]
+
     def reset(self):
-        for t in (self.S1, self.S2, self.b, self.u1, self.u2, self.u):
+        for t in (self.S1, self.S2, self.b, self.u, *self.hist):
             t.zero_()
         self.m = 0
 
@@ -62,18 +76,19 @@ class LaguerreSeries:
         """Solve harmonic self.m (PCG, or the Chebyshev iteration of eq. (8)
         with the operator's own bounds); afterwards self.u1 holds u_m."""
         m = self.m
-        if not want_info and lr is None:
+        nn_mode = guess in ("nn", "nn_poly")
+        if nn_mode and (net is None or self.kappa is None):
+            raise ValueError("nn guess needs a network and kappa")
+        if not want_info and lr is None and guess not in ("poly", "nn_poly"):
             # the whole harmonic in one library call (no host round trips
             # between the right-hand side, the guess and the solve)
-            if guess == "nn" and (net is None or self.kappa is None):
-                raise ValueError("nn guess needs a network and kappa")
             st = ax.series_step(self.op, m, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
                                 self.u1, self.u2, self.u, guess, solver=solver, net=net,
-                                kappa=self.kappa if guess == "nn" else None, coef=self.coef, rtol=rtol,
+                                kappa=self.kappa if nn_mode else None, coef=self.coef, rtol=rtol,
                                 maxit=maxit, prec=prec)
             stats.iters.append(st["iters"])
             stats.status.append(st["code"])
-            self.u2, self.u1, self.u = self.u1, self.u, self.u2
+            self._rotate()
             self.m += 1
             return
         ax.laguerre_rhs(self.op, self.g[m], self.src_i, self.src_k, self.S1, self.S2, self.b,
@@ -88,9 +103,17 @@ class LaguerreSeries:
                 stats.resid.append(r[0])
                 stats.choice.append(r[1])
         elif guess == "nn":
-            if net is None or self.kappa is None:
-                raise ValueError("nn guess needs a network and kappa")
             r = ax.nn_guess(self.op, net, self.b, self.u1, self.u2, self.kappa, self.u, want_info=want_info)
+            if r is not None:
+                stats.resid.append(r[0])
+                stats.choice.append(r[1])
+        elif guess == "poly":
+            r = ax.guess_poly(self.op, self.b, self.hist, self.u, want_info=want_info)
+            if r is not None:
+                stats.resid.append(r[0])
+                stats.choice.append(r[1])
+        elif guess == "nn_poly":
+            r = ax.nn_guess_poly(self.op, net, self.b, self.hist, self.kappa, self.u, want_info=want_info)
             if r is not None:
                 stats.resid.append(r[0])
                 stats.choice.append(r[1])
@@ -102,11 +125,10 @@ class LaguerreSeries:
             st = ax.pcg_solve(self.op, self.b, self.u, rtol=rtol, maxit=maxit, prec=prec)
         stats.iters.append(st["iters"])
         stats.status.append(st["code"])
-        if guess == "nn" and lr is not None:
+        if nn_mode and lr is not None:
             stats.loss.append(ax.nn_backward(self.op, net, self.u1, self.u2, self.u, want_loss=want_info))
             ax.nn_adam(net, lr=lr)
-        # rotate: u2 <- u1 <- u
-        self.u2, self.u1, self.u = self.u1, self.u, self.u2
+        self._rotate()
         self.m += 1
 
     def run_harmonics(self, n: int, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats,
@@ -118,16 +140,18 @@ class LaguerreSeries:
             return
         if self.m + n > len(self.g):
             raise ValueError("not enough Laguerre coefficients")
-        if guess == "nn" and (net is None or self.kappa is None):
+        nn_mode = guess in ("nn", "nn_poly")
+        if nn_mode and (net is None or self.kappa is None):
             raise ValueError("nn guess needs a network and kappa")
-        u = [self.u1, self.u2, self.u]
+        nh = ax.history_len(guess)
+        u = self.hist[:nh] + [self.u]
         code, sts = ax.series_run(self.op, self.m, self.g[self.m:self.m + n], self.src_i, self.src_k, self.S1,
                                   self.S2, self.b, u, guess, solver=solver, net=net,
-                                  kappa=self.kappa if guess == "nn" else None, coef=self.coef, rtol=rtol,
+                                  kappa=self.kappa if nn_mode else None, coef=self.coef, rtol=rtol,
                                   maxit=maxit, prec=prec)
         stats.iters.extend(st["iters"] for st in sts)
         stats.status.extend(st["status"] for st in sts)
-        self.u1, self.u2, self.u = u
+        self.hist[:nh], self.u = u[:nh], u[nh]
         self.m += len(sts)
 
     def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000, net=None,

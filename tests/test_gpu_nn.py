@@ -227,3 +227,81 @@ def test_extrapolation_guard(ax, onn, orc, nr, nz):
     ax.guess_extrap(op, bd, u1d, dev(2 * u1 - ustar), u1d)
     np.testing.assert_allclose(host(u1d), ustar, rtol=0, atol=1e-12 * np.abs(ustar).max())
     op.close()
+
+
+@pytest.mark.parametrize("nr,nz", GUARD_SHAPES)
+def test_poly_guard_matches_oracle(ax, onn, orc, nr, nz):
+    """Extrapolations of every order against the oracle's: residual norms,
+    the pick, and x = the chosen candidate."""
+    kappa, q = synth.medium_layered(nr, nz, 6)
+    op, oop = _ops(ax, orc, kappa, q)
+    f = synth.gaussian_source(nr, nz, 1.0, 1.0, 0.25, 0.5, 0.05)
+    b = orc.rhs(oop, f)
+    ustar, status, _, _ = orc.pcg(oop, b, np.zeros_like(b), rtol=1e-14, maxit=2000)
+    assert status == 0
+    A = lambda x: orc.apply(oop, x)  # noqa: E731
+    rng = np.random.default_rng(12)
+    scale = np.abs(ustar).max()
+    w = [rng.standard_normal(b.shape) * 0.1 * scale for _ in range(3)]
+    hist = [ustar + sum(wd * float(i + 1) ** (d + 1) for d, wd in enumerate(w))
+            + 1e-5 * scale * rng.standard_normal(b.shape) for i in range(5)]
+    bd = dev(b)
+    hd = [dev(h) for h in hist]
+    for k in range(1, 6):
+        x = dev(np.zeros_like(b))
+        res, pick = ax.guess_poly(op, bd, hd[:k], x, want_info=True)
+        res_ref, pick_ref, cands = onn.guard_poly(b, hist[:k], A)
+        log(f"poly guard {nr}x{nz} K={k}: pick {pick} (oracle {pick_ref}) resid {res}")
+        # orders >= 3 reproduce the cubic and differ only in the noise they amplify
+        assert pick == pick_ref and (k < 4 or pick == 3)
+        np.testing.assert_allclose(res, res_ref, rtol=1e-9)
+        np.testing.assert_allclose(host(x), cands[pick], rtol=1e-13, atol=1e-14 * scale)
+    # x may alias the newest history array
+    x = hd[0].clone()
+    h2 = [x] + hd[1:]
+    ax.guess_poly(op, bd, h2, x)
+    _, pick_ref, cands = onn.guard_poly(b, hist, A)
+    np.testing.assert_allclose(host(x), cands[pick_ref], rtol=1e-13, atol=1e-14 * scale)
+    with pytest.raises(ax.AxipcgError):
+        ax.guess_poly(op, bd, hd + [hd[0]], dev(np.zeros_like(b)))   # six arrays
+    with pytest.raises(ax.AxipcgError):
+        ax.guess_poly(op, bd, [bd], dev(np.zeros_like(b)))           # history aliasing b
+    op.close()
+
+
+def test_nn_poly_guard_matches_oracle(ax, onn, orc):
+    nr, nz = 32, 64
+    kappa, q = synth.medium_layered(nr, nz, 3)
+    op, oop = _ops(ax, orc, kappa, q)
+    f = synth.gaussian_source(nr, nz, 1.0, 1.0, 0.2, 0.5, 0.05)
+    b = orc.rhs(oop, f)
+    ustar, status, _, _ = orc.pcg(oop, b, np.zeros_like(b), rtol=1e-14, maxit=2000)
+    assert status == 0
+    A = lambda x: orc.apply(oop, x)  # noqa: E731
+    shift = 0.1 * np.abs(ustar).max()
+    u1 = ustar - shift
+    s = np.sqrt(np.mean(u1 * u1))
+    c32 = float(np.float32(shift / s))
+    kd, bd = dev(kappa), dev(b)
+    # a constant history: every extrapolation is u1; a bias-only network
+    # whose correction is the shift makes the learned guess (nearly) u*
+    hist = [u1] * 4
+    net = ax.nn_create(nr, nz, _bias_only(onn, shift / s))
+    x = dev(np.zeros_like(b))
+    phi, pick = ax.nn_guess_poly(op, net, bd, [dev(h) for h in hist], kd, x)
+    res_ref, pick_ref, _ = onn.guard_poly(b, hist, A, net_guess=u1 + s * c32)
+    log(f"nn poly guard: resid {phi} (oracle {res_ref}), pick {pick}")
+    assert pick == pick_ref == 4
+    np.testing.assert_allclose(phi[:4], res_ref[:4], rtol=1e-9)
+    assert phi[4] == pytest.approx(res_ref[4], rel=1e-5)
+    np.testing.assert_allclose(host(x), u1 + s * c32, rtol=1e-12, atol=1e-14 * np.abs(ustar).max())
+    # a zero network equals the linear extrapolation, which comes first: it never wins
+    ax.nn_set_params(net, _bias_only(onn, 0.0))
+    phi, pick = ax.nn_guess_poly(op, net, bd, [dev(h) for h in hist], kd, x)
+    assert pick < 4
+    np.testing.assert_allclose(host(x), u1, rtol=1e-14, atol=1e-15 * np.abs(ustar).max())
+    with pytest.raises(ax.AxipcgError):       # the network needs two history arrays
+        ax.nn_guess_poly(op, net, bd, [dev(u1)], kd, x)
+    net.close()
+    op.close()
+

@@ -50,14 +50,15 @@ def test_series_step_matches_separate_calls(ax, guess, solver):
         net.close()
 
 
-@pytest.mark.parametrize("guess,solver", [("prev", "pcg"), ("nn", "pcg"), ("extrap", "cheb"), ("nn", "cheb")])
+@pytest.mark.parametrize("guess,solver", [("prev", "pcg"), ("nn", "pcg"), ("extrap", "cheb"), ("nn", "cheb"),
+                                          ("poly", "pcg"), ("nn_poly", "pcg"), ("poly", "cheb")])
 def test_series_run_matches_steps(ax, guess, solver):
     """Harmonics 0..6 as one run of 2 and one of 5 against seven single steps."""
     from paper_1002_3094_amd.series import LaguerreSeries, SeriesStats, nn_init_params
     log(f"series_run guess={guess} solver={solver}")
     n_harm = 7
     inp = synth.laguerre_series_inputs(N, N, seed=4)
-    net = ax.nn_create(N, N, nn_init_params(6, last_zero=False)) if guess == "nn" else None
+    net = ax.nn_create(N, N, nn_init_params(6, last_zero=False)) if guess in ("nn", "nn_poly") else None
     with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
         g = ax.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
         s1 = LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
@@ -94,6 +95,10 @@ def test_series_run_edge_cases(ax):
             ax.series_run(op, 0, [1.0], inp["src_i"], inp["src_k"], S1, S2, b, [u[0], u[0], u[2]], "prev")
         with pytest.raises(ax.AxipcgError):   # the learned guess without a network
             ax.series_run(op, 0, [1.0, 0.5], inp["src_i"], inp["src_k"], S1, S2, b, u, "nn")
+        with pytest.raises(ValueError):       # polynomial guesses need six arrays
+            ax.series_run(op, 0, [1.0], inp["src_i"], inp["src_k"], S1, S2, b, u, "poly")
+        with pytest.raises(ax.AxipcgError):   # and series_step cannot hold their history
+            ax.series_step(op, 0, 1.0, inp["src_i"], inp["src_k"], S1, S2, b, u[0], u[1], u[2], "poly")
         assert [t.data_ptr() for t in u] == before
         # a harmonic that stops at maxit is kept and the run goes on
         code, sts = ax.series_run(op, 0, [1.0, 0.5, 0.25], inp["src_i"], inp["src_k"], S1, S2, b, u, "zero",

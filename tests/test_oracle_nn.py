@@ -10,6 +10,8 @@
   network stays within bfloat16's error of the FP64 one; every stored
   activation is a bfloat16 value.
 """
+import math
+
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -149,6 +151,49 @@ def test_guard_picks_smallest_residual():
         np.testing.assert_allclose((res[2], res[1], res[0]), ref, rtol=1e-8)
     # ties keep the simpler candidate
     res, pick = onn.guard(ex["b"], ustar, ustar, ustar, apply_A)
+    assert pick == 0
+
+
+def test_extrapolation_is_exact_for_polynomial_sequences():
+    """Order p reproduces the next value of any sequence that is a polynomial
+    of degree <= p in the harmonic index, and misses one of degree p + 1 by
+    the (p+1)-th difference (the first dropped term of Newton's form)."""
+    rng = np.random.default_rng(9)
+    shape = (5, 7)
+    for deg in range(5):
+        coef = [rng.standard_normal(shape) for _ in range(deg + 1)]
+        seq = lambda t: sum(c * float(t) ** d for d, c in enumerate(coef))  # noqa: E731
+        m = 11
+        hist = [seq(m - 1 - i) for i in range(5)]
+        for p in range(5):
+            x = onn.extrapolate(hist, p)
+            if p >= deg:
+                np.testing.assert_allclose(x, seq(m), rtol=1e-9, atol=1e-9 * np.abs(seq(m)).max())
+            elif p == deg - 1:
+                # error = leading coefficient * deg! (the deg-th difference of t^deg)
+                err = seq(m) - x
+                np.testing.assert_allclose(err, coef[deg] * math.factorial(deg), rtol=1e-8, atol=1e-8)
+    assert np.array_equal(onn.extrapolate([np.ones(3), 5 * np.ones(3)], 1), -3 * np.ones(3))
+
+
+def test_guard_poly_ranks_by_residual():
+    ex = nn_example(12, 16, seed=19)
+    A, apply_A = _matrix(ex)
+    ustar = spla.spsolve(A.tocsc(), ex["b"].ravel()).reshape(ex["b"].shape)
+    rng = np.random.default_rng(5)
+    # u_{m-1-i} = u* + a cubic in (i + 1) + small noise: orders 0..2 miss the
+    # cubic, order 3 only sees the noise, order 4 amplifies it more
+    w = [rng.standard_normal(ustar.shape) * 0.1 for _ in range(3)]
+    hist = [ustar + sum(wd * float(i + 1) ** (d + 1) for d, wd in enumerate(w))
+            + 1e-5 * rng.standard_normal(ustar.shape) for i in range(5)]
+    res, pick, cands = onn.guard_poly(ex["b"], hist, apply_A)
+    ref = [np.linalg.norm(A @ (x - ustar).ravel()) for x in cands]
+    np.testing.assert_allclose(res, ref, rtol=1e-8)
+    assert pick == 3 == int(np.argmin(ref))
+    # a network candidate is ranked last and wins only when strictly smaller
+    res, pick, _ = onn.guard_poly(ex["b"], hist, apply_A, net_guess=ustar)
+    assert pick == 5 and res[5] < 1e-8 * res[0]
+    res, pick, _ = onn.guard_poly(ex["b"], [ustar] * 3, apply_A, net_guess=ustar)
     assert pick == 0
 
 
