@@ -101,25 +101,25 @@ k_nn_norms(const double *__restrict__ u1, const double *__restrict__ b, size_t n
     }
 }
 
-// Every workgroup first sums the norm partials itself (the same fixed order in
-// each, so all agree), instead of a one-workgroup launch doing it in between;
-// workgroup 0 keeps the scales in scal[0..1] for the later kernels.
-__global__ void __launch_bounds__(256)
-k_nn_pack(const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ b,
-          const double *__restrict__ kap, bf16 *__restrict__ act0, size_t n, const double *red, int nb,
-          double *scal)
+// (a one-workgroup launch: folding these sums into every workgroup of the
+// packing kernel made it slower than the two launches together)
+__global__ void __launch_bounds__(256) k_nn_norms_fin(const double *red, int nb, size_t n, double *scal)
 {
     __shared__ double sm[8];
     const double t1 = block_total(red, nb, sm);
     const double t2 = block_total(red + MAX_PARTIALS, nb, sm);
-    double s = sqrt(t1 / (double)n), sb = sqrt(t2 / (double)n);
-    s = s > 0 ? s : 1.0;
-    sb = sb > 0 ? sb : 1.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        scal[0] = s;
-        scal[1] = sb;
+    if (threadIdx.x == 0) {
+        const double s = sqrt(t1 / (double)n), sb = sqrt(t2 / (double)n);
+        scal[0] = s > 0 ? s : 1.0;
+        scal[1] = sb > 0 ? sb : 1.0;
     }
-    const double is = 1.0 / s, ib = 1.0 / sb;
+}
+
+__global__ void __launch_bounds__(256)
+k_nn_pack(const double *__restrict__ u1, const double *__restrict__ u2, const double *__restrict__ b,
+          const double *__restrict__ kap, bf16 *__restrict__ act0, size_t n, const double *scal)
+{
+    const double is = 1.0 / scal[0], ib = 1.0 / scal[1];
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         bf16x4 v;
         v[0] = (short)to_bf16((float)(u1[e] * is));
@@ -708,17 +708,12 @@ k_guess_hist(const double *__restrict__ b, Hist h, const float *__restrict__ out
     }
 }
 
-// The pick: every workgroup sums the partials itself (the same fixed order in
-// each, so all agree) into the residual norms, and takes the candidates in
-// the order x_0, x_1, ..., network: a later one replaces the current choice
-// only when its residual is strictly smaller (a NaN never does).  Workgroup 0
-// records res[p] (p <= K; res[K] NaN without a network) and res[K + 1] = the
-// choice; then x = the chosen candidate.  x may alias a history array
-// (element-wise read before write).
+// The residual norms res[p] (p <= K; res[K] NaN without a network) and the
+// choice res[K + 1]: the candidates in the order x_0, x_1, ..., network, a
+// later one replacing the choice only when its residual is strictly smaller
+// (a NaN never does).  One workgroup.
 template <int K, bool NET>
-__global__ void __launch_bounds__(256)
-k_guess_pick(Hist h, const float *__restrict__ out, double *x, size_t n, const double *red, int nb, double *res,
-             const double *scal)
+__global__ void __launch_bounds__(256) k_guess_fin(const double *red, int nb, double *res)
 {
     __shared__ double sm[8];
     double f[K + 1];
@@ -733,11 +728,20 @@ k_guess_pick(Hist h, const float *__restrict__ out, double *x, size_t n, const d
             c = p;
             best = f[p];
         }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
 #pragma unroll
         for (int p = 0; p <= K; ++p) res[p] = f[p];
         res[K + 1] = (double)c;
     }
+}
+
+// x = the chosen candidate; x may alias a history array (element-wise read
+// before write).
+template <int K, bool NET>
+__global__ void __launch_bounds__(256)
+k_guess_pick(Hist h, const float *__restrict__ out, double *x, size_t n, const double *res, const double *scal)
+{
+    const int c = (int)res[K + 1];
     const double s = NET ? scal[0] : 0.0;
     const int order = c < K ? c : 1;   // the network's base is the linear extrapolation
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
@@ -788,14 +792,6 @@ unsigned red_blocks(size_t n)
     return b < 1024 ? b : 1024;
 }
 
-// grid of an element-wise kernel that first sums up to 1024 partials in every
-// workgroup: few enough workgroups that the repeated sums stay cheap
-unsigned fin_blocks(size_t n)
-{
-    const unsigned b = pointwise_blocks(n);
-    return b < 512 ? b : 512;
-}
-
 // grid of the guard's residual kernel: whole rows per workgroup, at most 1024
 // partial sums
 unsigned guard_blocks(int nr) { return nr < 1024 ? (unsigned)nr : 1024u; }
@@ -808,8 +804,8 @@ void guard_k(const Operator &op, const double *b, const Hist &h, const float *ou
     const unsigned pb = guard_blocks(op.nr);
     hipLaunchKernelGGL((k_guess_hist<K, NET>), dim3(pb), dim3(256), 0, s, b, h, out, op.D, op.CR, op.CZ, op.nr,
                        op.nz, scal, red);
-    hipLaunchKernelGGL((k_guess_pick<K, NET>), dim3(fin_blocks(np)), dim3(256), 0, s, h, out, x, np, red, (int)pb,
-                       res, scal);
+    hipLaunchKernelGGL((k_guess_fin<K, NET>), dim3(1), dim3(256), 0, s, red, (int)pb, res);
+    hipLaunchKernelGGL((k_guess_pick<K, NET>), dim3(pw_blocks(np)), dim3(256), 0, s, h, out, x, np, res, scal);
     AXI_CHECK_HIP(hipGetLastError());
 }
 
@@ -887,8 +883,8 @@ void forward_impl(Net &n, const double *u1, const double *u2, const double *b, c
     const size_t np = (size_t)n.nr * n.nz;
     const unsigned rb = red_blocks(np);
     hipLaunchKernelGGL(k_nn_norms, dim3(rb), dim3(256), 0, s, u1, b, np, n.red);
-    hipLaunchKernelGGL(k_nn_pack, dim3(fin_blocks(np)), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.red,
-                       (int)rb, n.scal);
+    hipLaunchKernelGGL(k_nn_norms_fin, dim3(1), dim3(256), 0, s, n.red, (int)rb, np, n.scal);
+    hipLaunchKernelGGL(k_nn_pack, dim3(pw_blocks(np)), dim3(256), 0, s, u1, u2, b, kap, n.act[0], np, n.scal);
     const int rows = conv_rows(n.nr, n.nz);
     const dim3 cg(conv_blocks(n.nr, n.nz, rows)), cb(256);
     const int rows_in = conv_rows(n.nr, n.nz, 8192);
