@@ -244,7 +244,7 @@ int axipcg_laguerre_synth(int n, int alpha, double eta, int nrec, const double *
  * the same handle. */
 int axipcg_guess_extrap(axipcg_op_t op, const double *b, const double *u1, const double *u2, double *x,
                         double *resid_host, int *choice_host, void *stream);
-/* The same guard over K = 1..5 earlier harmonics hist[j] = u_{m-1-j} (host
+/* The same guard over K = 1..7 earlier harmonics hist[j] = u_{m-1-j} (host
  * array of device [nr][nz] arrays): candidate p < K is the polynomial
  * extrapolation of order p through u_{m-1}, ..., u_{m-1-p},
  *     x_p = sum_{i <= p} (-1)^i C(p+1, i+1) u_{m-1-i}
@@ -306,7 +306,7 @@ int axipcg_nn_adam(axipcg_nn_t nn, double lr, double beta1, double beta2, double
 int axipcg_nn_guess(axipcg_op_t op, axipcg_nn_t nn, const double *b, const double *u1, const double *u2,
                     const double *kappa, double *x, double *resid_host, int *choice_host, void *stream);
 /* The learned guess among the polynomial extrapolations of guess_poly:
- * the network reads hist[0] = u_{m-1} and hist[1] = u_{m-2} (K = 2..5) and
+ * the network reads hist[0] = u_{m-1} and hist[1] = u_{m-2} (K = 2..7) and
  * its candidate (the linear extrapolation plus its correction) comes after
  * the K extrapolations.  resid_host (host double[K + 1]: orders 0..K-1, then
  * the network) and choice_host (the order, or K for the network) may be
@@ -333,7 +333,7 @@ enum {
     AXIPCG_GUESS_NN = 3,
     AXIPCG_GUESS_POLY = 4,     /* guess_poly over AXIPCG_POLY_HISTORY harmonics (series_run only) */
     AXIPCG_GUESS_NN_POLY = 5,  /* nn_guess_poly over as many (series_run only) */
-    AXIPCG_POLY_HISTORY = 5
+    AXIPCG_POLY_HISTORY = 7
 };
 int axipcg_series_step(axipcg_op_t op, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k,
                        const double *coef, double *S1, double *S2, double *b, const double *u1,
@@ -348,8 +348,8 @@ int axipcg_series_step(axipcg_op_t op, axipcg_nn_t nn, int m, double g_m, int sr
  * holds u_{m0+count-1}, u[1] u_{m0+count-2} and u[2] is free.  st (host,
  * count entries, may be NULL) receives each solve's statistics; done (host,
  * may be NULL) the number of harmonics completed.  With the polynomial
- * guesses (AXIPCG_GUESS_POLY, _NN_POLY) u holds AXIPCG_POLY_HISTORY + 1 = six
- * arrays, {u_{m0-1}, ..., u_{m0-5}, work}, rotated the same way (u[0] the
+ * guesses (AXIPCG_GUESS_POLY, _NN_POLY) u holds AXIPCG_POLY_HISTORY + 1 = eight
+ * arrays, {u_{m0-1}, ..., u_{m0-7}, work}, rotated the same way (u[0] the
  * last solution, u[1] the one before, ...).  A harmonic that does not
  * converge is kept and the run goes on (the return value is then
  * AXIPCG_ENOTCONV); a breakdown or any other error stops the run at that

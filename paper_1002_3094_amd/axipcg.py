@@ -342,7 +342,7 @@ def guess_extrap(op: Op, b, u1, u2, x, stream=None, want_info=False):
 
 def guess_poly(op: Op, b, hist: list, x, stream=None, want_info=False):
     """Polynomial extrapolation of order 0 .. len(hist) - 1 through hist =
-    [u_{m-1}, u_{m-2}, ...] (1 to 5 arrays) with the smallest residual into
+    [u_{m-1}, u_{m-2}, ...] (1 to 7 arrays) with the smallest residual into
     x; returns (residual norms by order, chosen order) when want_info (which
     synchronises)."""
     k = len(hist)
@@ -448,7 +448,7 @@ def nn_guess(op: Op, net: Net, b, u1, u2, kappa, x, stream=None, want_info=True)
 
 def nn_guess_poly(op: Op, net: Net, b, hist: list, kappa, x, stream=None, want_info=True):
     """The learned guess among the polynomial extrapolations through hist
-    (2 to 5 arrays); returns (residual norms [orders..., network], choice:
+    (2 to 7 arrays); returns (residual norms [orders..., network], choice:
     the order, or len(hist) for the network) when want_info (which
     synchronises), else None."""
     k = len(hist)
@@ -465,7 +465,7 @@ def nn_guess_poly(op: Op, net: Net, b, hist: list, kappa, x, stream=None, want_i
 # initial-guess modes of series_step / series_run; the polynomial ones read
 # POLY_HISTORY earlier harmonics and exist in series_run only
 SERIES_GUESS = {"zero": 0, "prev": 1, "extrap": 2, "nn": 3, "poly": 4, "nn_poly": 5}
-POLY_HISTORY = 5
+POLY_HISTORY = 7
 
 
 def history_len(guess: str) -> int:
@@ -494,7 +494,7 @@ def series_run(op: Op, m0: int, g, src_i: int, src_k: int, S1, S2, b, u: list, g
                solver: str = "pcg", net=None, kappa=None, coef=None, rtol=1e-10, maxit=1000, prec=PREC_FP32,
                stream=None, allow_notconv=True):
     """Harmonics m0 .. m0 + len(g) - 1 in one call (see series_step).  u is a
-    list of device arrays [u_{m0-1}, u_{m0-2}, ..., work]: three, or six for
+    list of device arrays [u_{m0-1}, u_{m0-2}, ..., work]: three, or eight for
     the polynomial guesses; it is rotated in place so that afterwards u[0]
     holds the last solution, u[1] the one before, and so on.  Returns (code,
     per-harmonic stats dicts)."""

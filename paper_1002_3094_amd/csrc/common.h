@@ -82,6 +82,10 @@ enum Slot { SLOT_PQ = 0, SLOT_RR = 1, SLOT_RZ = 2, SLOT_MISC = 3, SLOT_RZOLD = 4
 enum { ST_RUN = 0, ST_CONV = 1, ST_BREAK = 2, ST_MAXIT = 3, ST_BZERO = 4 };
 
 constexpr int MAX_PARTIALS = 16384;
+// Rows of an operator's partial-sum array: the PCG slots, and up to seven
+// rows for the initial-guess guard (one per extrapolation order).
+constexpr int PARTIAL_ROWS = 7;
+static_assert(PARTIAL_ROWS >= NUM_SLOTS, "partial rows");
 
 // Launch plan of the single-pass preconditioner for one precision.
 struct PfPlan {
@@ -121,7 +125,7 @@ struct Operator {
     // PCG workspace (device)
     double *r = nullptr, *z = nullptr, *p0 = nullptr, *p1 = nullptr, *q = nullptr;
     void *spec = nullptr;          // spectral buffer, nr*nz doubles (used as float or double)
-    double *partials = nullptr;    // [NUM_SLOTS][MAX_PARTIALS] per-workgroup partial sums
+    double *partials = nullptr;    // [PARTIAL_ROWS][MAX_PARTIALS] per-workgroup partial sums
     PcgState *state = nullptr;
     double *dscal = nullptr;         // 16 device scalars (residual norms)
     PcgState *state_host = nullptr;  // pinned copy of the state (read after the stream drains)

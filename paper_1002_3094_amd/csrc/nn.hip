@@ -608,12 +608,15 @@ k_nn_unpack(const double *u1, const double *u2, const float *__restrict__ out, d
 // sits on the linear extrapolation).  PCG's stop test measures |b - A x|, and
 // with a spectrally equivalent preconditioner the iterations a start needs
 // follow it, so the guard ranks the candidates by that norm.
-constexpr int GMAX = 5;
+constexpr int GMAX = 7;
+static_assert(GMAX <= PARTIAL_ROWS, "the guard's partial rows");
 struct Hist {
     const double *u[GMAX];
 };
 __device__ constexpr double kExtrap[GMAX][GMAX] = {
-    {1, 0, 0, 0, 0}, {2, -1, 0, 0, 0}, {3, -3, 1, 0, 0}, {4, -6, 4, -1, 0}, {5, -10, 10, -5, 1}};
+    {1, 0, 0, 0, 0, 0, 0},           {2, -1, 0, 0, 0, 0, 0},         {3, -3, 1, 0, 0, 0, 0},
+    {4, -6, 4, -1, 0, 0, 0},         {5, -10, 10, -5, 1, 0, 0},      {6, -15, 20, -15, 6, -1, 0},
+    {7, -21, 35, -35, 21, -7, 1}};
 
 __device__ inline double2 ld_pair(const double *p) { return *reinterpret_cast<const double2 *>(p); }
 __device__ inline double2 ld_pair(const float *p)
@@ -820,6 +823,8 @@ void run_guard(const Operator &op, const double *b, const Hist &h, int K, const 
         case 3: return guard_k<3, true>(op, b, h, out, scal, red, x, res, s);
         case 4: return guard_k<4, true>(op, b, h, out, scal, red, x, res, s);
         case 5: return guard_k<5, true>(op, b, h, out, scal, red, x, res, s);
+        case 6: return guard_k<6, true>(op, b, h, out, scal, red, x, res, s);
+        case 7: return guard_k<7, true>(op, b, h, out, scal, red, x, res, s);
         default: break;
         }
     } else {
@@ -829,6 +834,8 @@ void run_guard(const Operator &op, const double *b, const Hist &h, int K, const 
         case 3: return guard_k<3, false>(op, b, h, out, scal, red, x, res, s);
         case 4: return guard_k<4, false>(op, b, h, out, scal, red, x, res, s);
         case 5: return guard_k<5, false>(op, b, h, out, scal, red, x, res, s);
+        case 6: return guard_k<6, false>(op, b, h, out, scal, red, x, res, s);
+        case 7: return guard_k<7, false>(op, b, h, out, scal, red, x, res, s);
         default: break;
         }
     }
@@ -839,7 +846,7 @@ void run_guard(const Operator &op, const double *b, const Hist &h, int K, const 
 Hist make_hist(const double *const *hist, int K, const double *x, const double *b, const double *kappa)
 {
     AXI_REQUIRE(hist != nullptr, "hist is NULL");
-    AXI_REQUIRE(K >= 1 && K <= GMAX, "history length must be in [1, 5]");
+    AXI_REQUIRE(K >= 1 && K <= GMAX, "history length must be in [1, 7]");
     Hist h{};
     for (int j = 0; j < K; ++j) {
         AXI_REQUIRE(hist[j] != nullptr, "NULL history array");
@@ -963,7 +970,7 @@ Net *create_impl_nn(int nr, int nz, const float *params)
         nalloc(&n->wpart, (size_t)WG_BLOCKS * (9 * 32 * 32 + 32));
         nalloc(&n->scal, 16);
         nalloc(&n->red, (GMAX + 1) * (size_t)MAX_PARTIALS);
-        AXI_CHECK_HIP(hipHostMalloc((void **)&n->res_host, 8 * sizeof(double), hipHostMallocDefault));
+        AXI_CHECK_HIP(hipHostMalloc((void **)&n->res_host, 16 * sizeof(double), hipHostMallocDefault));
         AXI_CHECK_HIP(hipMemcpy(n->params, params, sizeof(float) * NPARAM, hipMemcpyHostToDevice));
         AXI_CHECK_HIP(hipMemset(n->grads, 0, sizeof(float) * NPARAM));
         AXI_CHECK_HIP(hipMemset(n->m1, 0, sizeof(float) * NPARAM));

@@ -242,9 +242,9 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         dmalloc(&op->tw64, nz); dmalloc(&op->pt64, nz); dmalloc(&op->tw32, nz); dmalloc(&op->pt32, nz);
         dmalloc(&op->r, n); dmalloc(&op->z, n); dmalloc(&op->p0, n); dmalloc(&op->p1, n); dmalloc(&op->q, n);
         dmalloc((double **)&op->spec, n);
-        dmalloc(&op->partials, (size_t)NUM_SLOTS * MAX_PARTIALS);
+        dmalloc(&op->partials, (size_t)PARTIAL_ROWS * MAX_PARTIALS);
         dmalloc(&op->state, 1);
-        dmalloc(&op->dscal, 16);
+        dmalloc(&op->dscal, 24);
         AXI_CHECK_HIP(hipMalloc((void **)&op->pf_bar, (1 + 256) * sizeof(unsigned)));
         AXI_CHECK_HIP(hipMalloc((void **)&op->pf_err, sizeof(int)));
         AXI_CHECK_HIP(hipMemsetAsync(op->pf_bar, 0, (1 + 256) * sizeof(unsigned), s));
@@ -255,7 +255,7 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
                                     hipHostMallocCoherent | hipHostMallocMapped));
         *op->mirror_host = HostMirror{};
         AXI_CHECK_HIP(hipHostGetDevicePointer((void **)&op->mirror_dev, op->mirror_host, 0));
-        AXI_CHECK_HIP(hipMemsetAsync(op->partials, 0, sizeof(double) * NUM_SLOTS * MAX_PARTIALS, s));
+        AXI_CHECK_HIP(hipMemsetAsync(op->partials, 0, sizeof(double) * PARTIAL_ROWS * MAX_PARTIALS, s));
         AXI_CHECK_HIP(hipMemsetAsync(op->p0, 0, sizeof(double) * n, s));
         AXI_CHECK_HIP(hipMemsetAsync(op->p1, 0, sizeof(double) * n, s));
         AXI_CHECK_HIP(hipMemsetAsync(op->state, 0, sizeof(PcgState), s));

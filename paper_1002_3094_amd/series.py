@@ -36,7 +36,7 @@ class SeriesStats:
 
 class LaguerreSeries:
     """Device state of one series: running sums, right-hand side, the last
-    five solutions (``hist[0]`` = u_{m-1}, the guesses read two or all five)
+    seven solutions (``hist[0]`` = u_{m-1}, the guesses read two or all seven)
     and the current one.  ``kappa`` (host [nr][nz]) feeds the learned guess.
     One series keeps to one guess mode."""
 

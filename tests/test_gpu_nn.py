@@ -244,10 +244,10 @@ def test_poly_guard_matches_oracle(ax, onn, orc, nr, nz):
     scale = np.abs(ustar).max()
     w = [rng.standard_normal(b.shape) * 0.1 * scale for _ in range(3)]
     hist = [ustar + sum(wd * float(i + 1) ** (d + 1) for d, wd in enumerate(w))
-            + 1e-5 * scale * rng.standard_normal(b.shape) for i in range(5)]
+            + 1e-5 * scale * rng.standard_normal(b.shape) for i in range(7)]
     bd = dev(b)
     hd = [dev(h) for h in hist]
-    for k in range(1, 6):
+    for k in range(1, 8):
         x = dev(np.zeros_like(b))
         res, pick = ax.guess_poly(op, bd, hd[:k], x, want_info=True)
         res_ref, pick_ref, cands = onn.guard_poly(b, hist[:k], A)
@@ -263,7 +263,7 @@ def test_poly_guard_matches_oracle(ax, onn, orc, nr, nz):
     _, pick_ref, cands = onn.guard_poly(b, hist, A)
     np.testing.assert_allclose(host(x), cands[pick_ref], rtol=1e-13, atol=1e-14 * scale)
     with pytest.raises(ax.AxipcgError):
-        ax.guess_poly(op, bd, hd + [hd[0]], dev(np.zeros_like(b)))   # six arrays
+        ax.guess_poly(op, bd, hd + [hd[0]], dev(np.zeros_like(b)))   # eight arrays
     with pytest.raises(ax.AxipcgError):
         ax.guess_poly(op, bd, [bd], dev(np.zeros_like(b)))           # history aliasing b
     op.close()

@@ -95,7 +95,7 @@ def test_series_run_edge_cases(ax):
             ax.series_run(op, 0, [1.0], inp["src_i"], inp["src_k"], S1, S2, b, [u[0], u[0], u[2]], "prev")
         with pytest.raises(ax.AxipcgError):   # the learned guess without a network
             ax.series_run(op, 0, [1.0, 0.5], inp["src_i"], inp["src_k"], S1, S2, b, u, "nn")
-        with pytest.raises(ValueError):       # polynomial guesses need six arrays
+        with pytest.raises(ValueError):       # polynomial guesses need eight arrays
             ax.series_run(op, 0, [1.0], inp["src_i"], inp["src_k"], S1, S2, b, u, "poly")
         with pytest.raises(ax.AxipcgError):   # and series_step cannot hold their history
             ax.series_step(op, 0, 1.0, inp["src_i"], inp["src_k"], S1, S2, b, u[0], u[1], u[2], "poly")
