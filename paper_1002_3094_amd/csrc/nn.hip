@@ -711,6 +711,33 @@ k_guess_hist(const double *__restrict__ b, Hist h, const float *__restrict__ out
     }
 }
 
+// Block sums of R rows of partials (row stride MAX_PARTIALS), every row's
+// loads in flight together (one row after another waits R round trips);
+// each row in the same fixed order, so equal rows give equal sums.  The
+// result is valid in thread 0.
+template <int R>
+__device__ inline void block_totals(const double *__restrict__ parts, int n, double (&out)[R], double *sm)
+{
+    const int nt = blockDim.x;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int base = 0; base < n; base += 4 * nt) {
+        double v[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = base + (int)threadIdx.x + j * nt;
+                v[r][j] = (i < n) ? parts[(size_t)r * MAX_PARTIALS + i] : 0.0;
+            }
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] += (v[r][0] + v[r][1]) + (v[r][2] + v[r][3]);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = block_sum(acc[r], sm);
+}
+
 // The residual norms res[p] (p <= K; res[K] NaN without a network) and the
 // choice res[K + 1]: the candidates in the order x_0, x_1, ..., network, a
 // later one replacing the choice only when its residual is strictly smaller
@@ -719,10 +746,13 @@ template <int K, bool NET>
 __global__ void __launch_bounds__(256) k_guess_fin(const double *red, int nb, double *res)
 {
     __shared__ double sm[8];
+    constexpr int R = NET ? K + 1 : K;
+    double t[R];
+    block_totals<R>(red, nb, t, sm);
     double f[K + 1];
 #pragma unroll
-    for (int p = 0; p < K; ++p) f[p] = sqrt(block_total(red + (size_t)p * MAX_PARTIALS, nb, sm));
-    f[K] = NET ? sqrt(block_total(red + (size_t)K * MAX_PARTIALS, nb, sm)) : __builtin_nan("");
+    for (int p = 0; p < K; ++p) f[p] = sqrt(t[p]);
+    f[K] = NET ? sqrt(t[R - 1]) : __builtin_nan("");
     int c = 0;
     double best = f[0];
 #pragma unroll
