@@ -230,6 +230,18 @@ def large_measure(ax, torch, n, n_harm, seed):
             rec["spmv"] = {"mean_us": round(k_s * 1e6, 2), "gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                            "launches": k_n}
     rec["speedup_fp32_vs_fp64"] = round(rec["fp32"]["harmonics_per_s"] / rec["fp64"]["harmonics_per_s"], 3)
+    # the same series from the order 0-6 extrapolation guard instead of u_{m-1}
+    s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"])
+    s.run(3, "poly", ax.PREC_FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.run(n_harm, "poly", ax.PREC_FP32)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    assert all(c == ax.OK for c in st.status), st.status
+    rec["fp32_poly_guard"] = {"harmonics_per_s": round(n_harm / el, 2),
+                              "iters_per_harmonic": round(float(np.mean(st.iters)), 3),
+                              "us_per_iteration": round(el * 1e6 / max(1, sum(st.iters)), 2)}
     r = torch.randn((n, n), dtype=torch.float64, device="cuda")
     z = torch.empty_like(r)
     e0 = torch.cuda.Event(enable_timing=True)

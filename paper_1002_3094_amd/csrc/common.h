@@ -127,7 +127,7 @@ struct Operator {
     void *spec = nullptr;          // spectral buffer, nr*nz doubles (used as float or double)
     double *partials = nullptr;    // [PARTIAL_ROWS][MAX_PARTIALS] per-workgroup partial sums
     PcgState *state = nullptr;
-    double *dscal = nullptr;         // 16 device scalars (residual norms)
+    double *dscal = nullptr;         // 24 device scalars: residual norms [0..1], the guard [8..16]
     PcgState *state_host = nullptr;  // pinned copy of the state (read after the stream drains)
     HostMirror *mirror_host = nullptr;   // coherent pinned progress record (host address)
     HostMirror *mirror_dev = nullptr;    // the same, device address
