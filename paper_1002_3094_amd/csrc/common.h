@@ -132,6 +132,7 @@ struct Operator {
     HostMirror *mirror_host = nullptr;   // coherent pinned progress record (host address)
     HostMirror *mirror_dev = nullptr;    // the same, device address
     unsigned mirror_seq = 0;             // number of the current solve
+    double *au_cache = nullptr;          // series_run's cache of A u for the guard (POLY_HISTORY arrays)
     double *scratch_host = nullptr;  // pinned host scalars (16)
 
     // single-pass preconditioner (pfused.hip): plan per precision [FP64, FP32]

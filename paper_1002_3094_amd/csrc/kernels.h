@@ -99,6 +99,15 @@ inline unsigned pointwise_blocks(size_t n, int threads = 256)
     return (unsigned)b;
 }
 
+// The guard of axipcg_guess_poly (nn NULL) or axipcg_nn_guess_poly with a
+// cache of A u: ah[j] holds A hist[j] for 1 <= j < K on entry, and A hist[0]
+// is written to ah[0] (each array nr * nz).  Same choice and x as the
+// uncached calls.
+void guess_poly_cached(Operator &op, axipcg_nn_t nn, const double *b, const double *const *hist, int K,
+                       double *const *ah, const double *kappa, double *x, hipStream_t s);
+// y = A v with the guard's arithmetic (to fill that cache).
+void apply_a_pairs(const Operator &op, const double *v, double *y, hipStream_t s);
+
 // The solve entry points behind axipcg_pcg_solve / axipcg_cheb_solve (which
 // pass sync_end = true).  With sync_end = false the call returns as soon as
 // the host has seen the stop test's outcome: launches of the last chunk may

@@ -639,6 +639,9 @@ template <typename V>
 __device__ inline double2 apply_pair(const V *__restrict__ v, double2 d, double2 cz, const double *__restrict__ CR,
                                      const double *__restrict__ CZ, size_t e, int i, int k, int nr, int nz)
 {
+    // no fused multiply-adds: A u computed here, cached, or in another kernel
+    // is the same to the last bit
+#pragma clang fp contract(off)
     const double2 c = ld_pair(v + e);
     double2 a{d.x * c.x, d.y * c.y};
     if (i + 1 < nr) {
@@ -662,13 +665,16 @@ __device__ inline double2 apply_pair(const V *__restrict__ v, double2 d, double2
 // p < K the extrapolations, p = K the network.  Workgroups take whole rows,
 // the rows of one XCD contiguous (their neighbour rows then come from that
 // XCD's L2); each thread the element pairs (k, k + 1), k even.  A x_p is
-// formed from the A u_j, so each history array is read once.
-template <int K, bool NET>
+// formed from the A u_j, so each history array is read once.  CACHED: A u_j
+// for j >= 1 is read from ah.u[j] (computed for an earlier harmonic), and
+// A u_0 is computed and also stored in ah0 for the next one.
+template <int K, bool NET, bool CACHED>
 __global__ void __launch_bounds__(256)
-k_guess_hist(const double *__restrict__ b, Hist h, const float *__restrict__ out, const double *__restrict__ D,
-             const double *__restrict__ CR, const double *__restrict__ CZ, int nr, int nz, const double *scal,
-             double *red)
+k_guess_hist(const double *__restrict__ b, Hist h, Hist ah, double *__restrict__ ah0,
+             const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
+             const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
 {
+#pragma clang fp contract(off)
     static_assert(K >= 1 && K <= GMAX && (!NET || K >= 2), "history length");
     __shared__ double sm[8];
     const double s = NET ? scal[0] : 0.0;
@@ -681,8 +687,11 @@ k_guess_hist(const double *__restrict__ b, Hist h, const float *__restrict__ out
             const size_t e = (size_t)i * nz + k;
             const double2 d = ld_pair(D + e), cz = ld_pair(CZ + e), bv = ld_pair(b + e);
             double2 au[K];
+            au[0] = apply_pair(h.u[0], d, cz, CR, CZ, e, i, k, nr, nz);
+            if (CACHED) *reinterpret_cast<double2 *>(ah0 + e) = au[0];
 #pragma unroll
-            for (int j = 0; j < K; ++j) au[j] = apply_pair(h.u[j], d, cz, CR, CZ, e, i, k, nr, nz);
+            for (int j = 1; j < K; ++j)
+                au[j] = CACHED ? ld_pair(ah.u[j] + e) : apply_pair(h.u[j], d, cz, CR, CZ, e, i, k, nr, nz);
             double2 r1{0.0, 0.0};
 #pragma unroll
             for (int p = 0; p < K; ++p) {
@@ -829,14 +838,33 @@ unsigned red_blocks(size_t n)
 // partial sums
 unsigned guard_blocks(int nr) { return nr < 1024 ? (unsigned)nr : 1024u; }
 
+// y = A v with the guard's own stencil arithmetic (fills the cache of A u).
+__global__ void __launch_bounds__(256)
+k_apply_pairs(const double *__restrict__ v, double *__restrict__ y, const double *__restrict__ D,
+              const double *__restrict__ CR, const double *__restrict__ CZ, int nr, int nz)
+{
+    for (int blk = blockIdx.x; blk < nr; blk += gridDim.x) {
+        const int i = xcd_swizzle(blk, nr);
+        for (int k = 2 * threadIdx.x; k < nz; k += 512) {
+            const size_t e = (size_t)i * nz + k;
+            *reinterpret_cast<double2 *>(y + e) =
+                apply_pair(v, ld_pair(D + e), ld_pair(CZ + e), CR, CZ, e, i, k, nr, nz);
+        }
+    }
+}
+
 template <int K, bool NET>
 void guard_k(const Operator &op, const double *b, const Hist &h, const float *out, const double *scal, double *red,
-             double *x, double *res, hipStream_t s)
+             double *x, double *res, hipStream_t s, const Hist *ah, double *ah0)
 {
     const size_t np = (size_t)op.nr * op.nz;
     const unsigned pb = guard_blocks(op.nr);
-    hipLaunchKernelGGL((k_guess_hist<K, NET>), dim3(pb), dim3(256), 0, s, b, h, out, op.D, op.CR, op.CZ, op.nr,
-                       op.nz, scal, red);
+    if (ah)
+        hipLaunchKernelGGL((k_guess_hist<K, NET, true>), dim3(pb), dim3(256), 0, s, b, h, *ah, ah0, out, op.D, op.CR,
+                           op.CZ, op.nr, op.nz, scal, red);
+    else
+        hipLaunchKernelGGL((k_guess_hist<K, NET, false>), dim3(pb), dim3(256), 0, s, b, h, h, nullptr, out, op.D,
+                           op.CR, op.CZ, op.nr, op.nz, scal, red);
     hipLaunchKernelGGL((k_guess_fin<K, NET>), dim3(1), dim3(256), 0, s, red, (int)pb, res);
     hipLaunchKernelGGL((k_guess_pick<K, NET>), dim3(pw_blocks(np)), dim3(256), 0, s, h, out, x, np, res, scal);
     AXI_CHECK_HIP(hipGetLastError());
@@ -844,31 +872,34 @@ void guard_k(const Operator &op, const double *b, const Hist &h, const float *ou
 
 // Guard over the history h (K arrays) and, with out, the network candidate:
 // partial sums in red (K + 1 rows), norms and choice in res (K + 2 values).
+// With ah: A h.u[j] for j >= 1 cached there, A h.u[0] stored into ah0.
 void run_guard(const Operator &op, const double *b, const Hist &h, int K, const float *out, const double *scal,
-               double *red, double *x, double *res, hipStream_t s)
+               double *red, double *x, double *res, hipStream_t s, const Hist *ah = nullptr, double *ah0 = nullptr)
 {
+#define AXI_G(KK, NN) return guard_k<KK, NN>(op, b, h, out, scal, red, x, res, s, ah, ah0)
     if (out) {
         switch (K) {
-        case 2: return guard_k<2, true>(op, b, h, out, scal, red, x, res, s);
-        case 3: return guard_k<3, true>(op, b, h, out, scal, red, x, res, s);
-        case 4: return guard_k<4, true>(op, b, h, out, scal, red, x, res, s);
-        case 5: return guard_k<5, true>(op, b, h, out, scal, red, x, res, s);
-        case 6: return guard_k<6, true>(op, b, h, out, scal, red, x, res, s);
-        case 7: return guard_k<7, true>(op, b, h, out, scal, red, x, res, s);
+        case 2: AXI_G(2, true);
+        case 3: AXI_G(3, true);
+        case 4: AXI_G(4, true);
+        case 5: AXI_G(5, true);
+        case 6: AXI_G(6, true);
+        case 7: AXI_G(7, true);
         default: break;
         }
     } else {
         switch (K) {
-        case 1: return guard_k<1, false>(op, b, h, out, scal, red, x, res, s);
-        case 2: return guard_k<2, false>(op, b, h, out, scal, red, x, res, s);
-        case 3: return guard_k<3, false>(op, b, h, out, scal, red, x, res, s);
-        case 4: return guard_k<4, false>(op, b, h, out, scal, red, x, res, s);
-        case 5: return guard_k<5, false>(op, b, h, out, scal, red, x, res, s);
-        case 6: return guard_k<6, false>(op, b, h, out, scal, red, x, res, s);
-        case 7: return guard_k<7, false>(op, b, h, out, scal, red, x, res, s);
+        case 1: AXI_G(1, false);
+        case 2: AXI_G(2, false);
+        case 3: AXI_G(3, false);
+        case 4: AXI_G(4, false);
+        case 5: AXI_G(5, false);
+        case 6: AXI_G(6, false);
+        case 7: AXI_G(7, false);
         default: break;
         }
     }
+#undef AXI_G
     throw Error{AXIPCG_EINVAL, "history length out of range"};
 }
 
@@ -1015,6 +1046,34 @@ Net *create_impl_nn(int nr, int nz, const float *params)
 }
 
 }  // namespace
+
+void apply_a_pairs(const Operator &op, const double *v, double *y, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_apply_pairs, dim3(guard_blocks(op.nr)), dim3(256), 0, s, v, y, op.D, op.CR, op.CZ, op.nr,
+                       op.nz);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void guess_poly_cached(Operator &op, axipcg_nn_t nn, const double *b, const double *const *hist, int K,
+                       double *const *ah, const double *kappa, double *x, hipStream_t s)
+{
+    const Hist hh = make_hist(hist, K, x, b, kappa);
+    Hist ahh{};
+    for (int j = 0; j < K; ++j) {
+        AXI_REQUIRE(ah && ah[j], "NULL cache array");
+        ahh.u[j] = ah[j];
+    }
+    if (nn) {
+        Net *n = reinterpret_cast<Net *>(nn);
+        AXI_REQUIRE(K >= 2 && kappa, "the learned guess needs two history arrays and kappa");
+        AXI_REQUIRE(op.nr == n->nr && op.nz == n->nz, "operator and network sizes differ");
+        forward_impl(*n, hist[0], hist[1], b, kappa, s);
+        run_guard(op, b, hh, K, n->out, n->scal, n->red, x, n->scal + 3, s, &ahh, ah[0]);
+    } else {
+        run_guard(op, b, hh, K, nullptr, nullptr, op.partials, x, op.dscal + 8, s, &ahh, ah[0]);
+    }
+}
+
 }  // namespace axipcg
 
 using namespace axipcg;

@@ -20,10 +20,12 @@ int history_of(int guess)
 }
 
 // hist[j] = u_{m-1-j}, nh = history_of(guess) arrays.
+// ah (may be NULL): the cache of A hist[j] for the polynomial guesses (see
+// guess_poly_cached).
 int series_step_impl(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src_i, int src_k, const double *coef,
                      double *S1, double *S2, double *b, const double *const *hist, int nh, const double *kappa,
                      double *x, int guess, int solver, double rtol, int maxit, int prec, axipcg_stats *st,
-                     void *stream, bool sync_end)
+                     void *stream, bool sync_end, double *const *ah = nullptr)
 {
     const double *u1 = hist[0], *u2 = hist[1];
     int code = guarded([&] {
@@ -64,10 +66,24 @@ int series_step_impl(axipcg_op_t hop, axipcg_nn_t nn, int m, double g_m, int src
         code = axipcg_nn_guess(hop, nn, b, u1, u2, kappa, x, nullptr, nullptr, stream);
         break;
     case AXIPCG_GUESS_POLY:
-        code = axipcg_guess_poly(hop, b, hist, nh, x, nullptr, nullptr, stream);
+        if (ah)
+            code = guarded([&] {
+                guess_poly_cached(*reinterpret_cast<Operator *>(hop), nullptr, b, hist, nh, ah, nullptr, x,
+                                  (hipStream_t)stream);
+                return AXIPCG_OK;
+            });
+        else
+            code = axipcg_guess_poly(hop, b, hist, nh, x, nullptr, nullptr, stream);
         break;
     default:
-        code = axipcg_nn_guess_poly(hop, nn, b, hist, nh, kappa, x, nullptr, nullptr, stream);
+        if (ah)
+            code = guarded([&] {
+                guess_poly_cached(*reinterpret_cast<Operator *>(hop), nn, b, hist, nh, ah, kappa, x,
+                                  (hipStream_t)stream);
+                return AXIPCG_OK;
+            });
+        else
+            code = axipcg_nn_guess_poly(hop, nn, b, hist, nh, kappa, x, nullptr, nullptr, stream);
         break;
     }
     if (code != AXIPCG_OK) return code;
@@ -105,12 +121,30 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
         return AXIPCG_OK;
     });
     if (code != AXIPCG_OK) return code;
+    // the polynomial guesses keep A u of the history arrays (one application
+    // of A per harmonic instead of nh): filled here for u[1..nh-1], rotated
+    // with u, u[0]'s written by each harmonic's guard
+    double *ah[AXIPCG_POLY_HISTORY + 1] = {};
+    const bool poly = (guess == AXIPCG_GUESS_POLY || guess == AXIPCG_GUESS_NN_POLY) && count > 0;
+    if (poly) {
+        code = guarded([&] {
+            Operator *op = reinterpret_cast<Operator *>(hop);
+            AXI_REQUIRE(op != nullptr, "NULL argument");
+            const size_t n = (size_t)op->nr * op->nz;
+            if (!op->au_cache)
+                AXI_CHECK_HIP(hipMalloc((void **)&op->au_cache, sizeof(double) * n * AXIPCG_POLY_HISTORY));
+            for (int i = 0; i < nh; ++i) ah[i] = op->au_cache + (size_t)i * n;
+            for (int i = 1; i < nh; ++i) apply_a_pairs(*op, u[i], ah[i], (hipStream_t)stream);
+            return AXIPCG_OK;
+        });
+        if (code != AXIPCG_OK) return code;
+    }
     // between harmonics the host does not wait for the stream to drain: the
     // next right-hand side is queued behind the tail of the previous solve
     int worst = AXIPCG_OK;
     for (int j = 0; j < count; ++j) {
         code = series_step_impl(hop, nn, m0 + j, g[j], src_i, src_k, coef, S1, S2, b, u, nh, kappa, u[nh], guess,
-                                solver, rtol, maxit, prec, st ? st + j : nullptr, stream, false);
+                                solver, rtol, maxit, prec, st ? st + j : nullptr, stream, false, poly ? ah : nullptr);
         if (code < 0) {              // the failed harmonic's buffers keep their roles
             (void)hipStreamSynchronize((hipStream_t)stream);
             return code;
@@ -120,6 +154,11 @@ extern "C" int axipcg_series_run(axipcg_op_t hop, axipcg_nn_t nn, int m0, int co
         for (int i = nh - 1; i > 0; --i) u[i] = u[i - 1];
         u[0] = u[nh];
         u[nh] = w;
+        if (poly) {                  // A u moves with u; the new u[0]'s is computed next
+            double *wa = ah[nh - 1];
+            for (int i = nh - 1; i > 0; --i) ah[i] = ah[i - 1];
+            ah[0] = wa;
+        }
         if (done) *done = j + 1;
     }
     code = guarded([&] {

@@ -192,6 +192,7 @@ void free_op(Operator *op)
     if (op->state_host) (void)hipHostFree(op->state_host);
     if (op->scratch_host) (void)hipHostFree(op->scratch_host);
     if (op->mirror_host) (void)hipHostFree(op->mirror_host);
+    if (op->au_cache) (void)hipFree(op->au_cache);
     delete op;
 }
 
