@@ -267,8 +267,8 @@ def large_measure(ax, torch, n, n_harm, seed):
 def paper_measure(ax, torch, n_harm):
     """The paper's experiment (§4.3) at 1024^2: the fault stand-in, Neumann in
     z, alpha = 5, h = 300, the pulse of eq. (40), FP32 preconditioner; a zero
-    initial guess (the paper's) and the previous harmonic; receiver traces
-    synthesised from the harmonics."""
+    initial guess (the paper's), the previous harmonic, and the polynomial
+    extrapolation guard; receiver traces synthesised from the harmonics."""
     import synth
     from paper_1002_3094_amd import series
     inp = synth.paper_series_inputs(1024, 1024, seed=101)
@@ -276,7 +276,7 @@ def paper_measure(ax, torch, n_harm):
     g = ax.laguerre_coeffs_alpha(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
     rec = {"workload": "laguerre_paper_1024x1024_alpha5_h300", "harmonics": n_harm, "alpha": inp["alpha"],
            "eta": inp["eta"], "bc_z": "neumann", "receivers": int(len(inp["rec_idx"]))}
-    for guess in ("zero", "prev"):
+    for guess in ("zero", "prev", "poly"):
         s = series.PaperSeries(op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"],
                                inp["rec_idx"])
         torch.cuda.synchronize()

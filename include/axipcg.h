@@ -361,12 +361,15 @@ int axipcg_series_run(axipcg_op_t op, axipcg_nn_t nn, int m0, int count, const d
 /* The paper's experiment (§4.3) over harmonics m0 .. m0 + count - 1 in one
  * call: for each, the right-hand side of eq. (35) with alpha
  * (laguerre_rhs_alpha, u_prev = u[0] when m > 0), a zero
- * (AXIPCG_GUESS_ZERO) or previous-harmonic (AXIPCG_GUESS_PREV) initial
- * guess in u[1], the solve (solver 0 PCG, 1 Chebyshev with the operator's
+ * (AXIPCG_GUESS_ZERO), previous-harmonic (AXIPCG_GUESS_PREV) or polynomial
+ * extrapolation (AXIPCG_GUESS_POLY, as guess_poly over the last
+ * AXIPCG_POLY_HISTORY harmonics) initial guess in the work array, the solve
+ * (solver 0 PCG, 1 Chebyshev with the operator's
  * bounds), and the receiver samples Q[m][r] = u_m[rec_idx[r]] (axipcg_gather;
  * Q device [m0 + count][n_rec] at least, rec_idx device; n_rec = 0 skips
- * them).  g (host): g_{m0} ... .  u (host array of two distinct device
- * arrays): {u_{m0-1}, work} on entry, swapped after each harmonic, so that on
+ * them).  g (host): g_{m0} ... .  u (host array of distinct device
+ * arrays): {u_{m0-1}, work} on entry, or {u_{m0-1}, ..., u_{m0-7}, work} for
+ * AXIPCG_GUESS_POLY, rotated after each harmonic as in series_run, so that on
  * return u[0] holds the last solution.  st, done and the error behaviour as
  * for axipcg_series_run. */
 int axipcg_series_run_alpha(axipcg_op_t op, int m0, int count, int alpha, const double *g, int src_i, int src_k,

@@ -523,18 +523,22 @@ def series_run_alpha(op: Op, m0: int, alpha: int, g, src_i: int, src_k: int, coe
     """The paper's pipeline over harmonics m0 .. m0 + len(g) - 1 in one call:
     right-hand side with alpha, zero or previous guess, solve, receiver
     samples into Q[m] (Q device [>= m0 + len(g)][n_rec], rec_idx int64 device
-    or None).  u is [u_{m0-1}, work], swapped in place after each harmonic.
-    Returns (code, per-harmonic stats dicts)."""
+    or None).  u is [u_{m0-1}, work], or [u_{m0-1}, ..., u_{m0-7}, work] for
+    guess 'poly', rotated in place after each harmonic.  Returns (code,
+    per-harmonic stats dicts)."""
     import torch
-    if guess not in ("zero", "prev"):
-        raise ValueError("guess must be 'zero' or 'prev'")
+    if guess not in ("zero", "prev", "poly"):
+        raise ValueError("guess must be 'zero', 'prev' or 'poly'")
+    nu = (POLY_HISTORY if guess == "poly" else 1) + 1
+    if len(u) != nu:
+        raise ValueError(f"guess {guess!r} needs {nu} arrays in u")
     gv = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
     count = int(gv.size)
     n_rec = 0 if rec_idx is None else int(rec_idx.numel())
     if n_rec:
         if Q.dim() != 2 or Q.shape[1] != n_rec or Q.shape[0] < m0 + count:
             raise ValueError("Q must be [>= m0 + count][n_rec]")
-    ptrs = (_vp * 2)(*[_dev(t, "u") for t in u])
+    ptrs = (_vp * nu)(*[_dev(t, "u") for t in u])
     by_ptr = {t.data_ptr(): t for t in u}
     st = (Stats * max(count, 1))()
     done = _i()
@@ -544,7 +548,7 @@ def series_run_alpha(op: Op, m0: int, alpha: int, g, src_i: int, src_k: int, coe
                                          _dev(Q, "Q") if n_rec else None, SERIES_GUESS[guess],
                                          {"pcg": 0, "cheb": 1}[solver], rtol, maxit, prec, st, ctypes.byref(done),
                                          _stream(stream))
-    u[:] = [by_ptr[ptrs[j]] for j in range(2)]
+    u[:] = [by_ptr[ptrs[j]] for j in range(nu)]
     _check(code, "series_run_alpha", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
     return code, [st[j].as_dict() for j in range(done.value)]
 

@@ -175,33 +175,54 @@ extern "C" int axipcg_series_run_alpha(axipcg_op_t hop, int m0, int count, int a
                                        void *stream)
 {
     if (done) *done = 0;
+    const bool poly = guess == AXIPCG_GUESS_POLY;
+    const int nh = poly ? AXIPCG_POLY_HISTORY : 1;   // earlier harmonics kept; u[nh] is the work array
     int code = guarded([&] {
         const Operator *op = reinterpret_cast<const Operator *>(hop);
         AXI_REQUIRE(op != nullptr, "NULL operator");
         AXI_REQUIRE(m0 >= 0 && count >= 0, "m0 and count must be >= 0");
         AXI_REQUIRE(count == 0 || g != nullptr, "g is NULL");
-        AXI_REQUIRE(u != nullptr && u[0] && u[1] && u[0] != u[1], "u must hold two distinct device arrays");
-        AXI_REQUIRE(u[0] != b && u[1] != b && u[0] != S1 && u[1] != S1 && u[0] != S2 && u[1] != S2,
-                    "u aliases b, S1 or S2");
-        AXI_REQUIRE(guess == AXIPCG_GUESS_ZERO || guess == AXIPCG_GUESS_PREV, "guess must be zero or prev");
+        AXI_REQUIRE(guess == AXIPCG_GUESS_ZERO || guess == AXIPCG_GUESS_PREV || poly,
+                    "guess must be zero, prev or poly");
+        AXI_REQUIRE(u != nullptr, "u is NULL");
+        for (int a = 0; a <= nh; ++a) {
+            AXI_REQUIRE(u[a] != nullptr, "u must hold the history arrays and a work array");
+            AXI_REQUIRE(u[a] != b && u[a] != S1 && u[a] != S2, "u aliases b, S1 or S2");
+            for (int c = 0; c < a; ++c) AXI_REQUIRE(u[c] != u[a], "the u arrays must be distinct");
+        }
         AXI_REQUIRE(solver == 0 || solver == 1, "unknown solver");
         AXI_REQUIRE(n_rec == 0 || (rec_idx && Q), "receivers need rec_idx and Q");
         return AXIPCG_OK;
     });
     if (code != AXIPCG_OK) return code;
-    const Operator *op = reinterpret_cast<const Operator *>(hop);
+    Operator *op = reinterpret_cast<Operator *>(hop);
     const size_t bytes = (size_t)op->nr * op->nz * sizeof(double);
     hipStream_t s = (hipStream_t)stream;
+    double *ah[AXIPCG_POLY_HISTORY + 1] = {};
+    if (poly && count > 0) {         // the cache of A u, as in series_run
+        code = guarded([&] {
+            const size_t n = (size_t)op->nr * op->nz;
+            if (!op->au_cache)
+                AXI_CHECK_HIP(hipMalloc((void **)&op->au_cache, sizeof(double) * n * AXIPCG_POLY_HISTORY));
+            for (int i = 0; i < nh; ++i) ah[i] = op->au_cache + (size_t)i * n;
+            for (int i = 1; i < nh; ++i) apply_a_pairs(*op, u[i], ah[i], s);
+            return AXIPCG_OK;
+        });
+        if (code != AXIPCG_OK) return code;
+    }
     int worst = AXIPCG_OK;
     for (int j = 0; j < count; ++j) {
         const int m = m0 + j;
-        double *u1 = u[0], *x = u[1];
+        double *u1 = u[0], *x = u[nh];
         code = axipcg_laguerre_rhs_alpha(hop, m, alpha, g[j], src_i, src_k, coef, m > 0 ? u1 : nullptr, S1, S2, b,
                                          stream);
         if (code == AXIPCG_OK)
             code = guarded([&] {
                 if (guess == AXIPCG_GUESS_ZERO) AXI_CHECK_HIP(hipMemsetAsync(x, 0, bytes, s));
-                else AXI_CHECK_HIP(hipMemcpyAsync(x, u1, bytes, hipMemcpyDeviceToDevice, s));
+                else if (guess == AXIPCG_GUESS_PREV)
+                    AXI_CHECK_HIP(hipMemcpyAsync(x, u1, bytes, hipMemcpyDeviceToDevice, s));
+                else
+                    guess_poly_cached(*op, nullptr, b, u, nh, ah, nullptr, x, s);
                 return AXIPCG_OK;
             });
         if (code == AXIPCG_OK || code == AXIPCG_ENOTCONV)
@@ -217,8 +238,15 @@ extern "C" int axipcg_series_run_alpha(axipcg_op_t hop, int m0, int count, int a
             return code;
         }
         if (code == AXIPCG_ENOTCONV) worst = AXIPCG_ENOTCONV;
-        u[0] = x;
-        u[1] = u1;
+        double *w = u[nh - 1];       // rotate as in series_run
+        for (int i = nh - 1; i > 0; --i) u[i] = u[i - 1];
+        u[0] = u[nh];
+        u[nh] = w;
+        if (poly) {
+            double *wa = ah[nh - 1];
+            for (int i = nh - 1; i > 0; --i) ah[i] = ah[i - 1];
+            ah[0] = wa;
+        }
         if (done) *done = j + 1;
     }
     code = guarded([&] {

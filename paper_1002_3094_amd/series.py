@@ -179,7 +179,8 @@ class PaperSeries:
     alpha (alpha = 5, eta = h = 300 there), a zero or previous-harmonic
     initial guess, the receiver samples of every harmonic, and the time
     traces synthesised from them (eq. (34)).  ``coef`` (device or host
-    [nr][nz]) is eta^2/rho^2; ``rec_idx`` flat receiver indices."""
+    [nr][nz]) is eta^2/rho^2; ``rec_idx`` flat receiver indices.  The guess
+    'poly' (the extrapolation guard) reads the last seven harmonics."""
 
     def __init__(self, op: "ax.Op", g, alpha: int, eta: float, src_i: int, src_k: int, coef, rec_idx):
         import torch
@@ -188,11 +189,16 @@ class PaperSeries:
         self.src_i, self.src_k = int(src_i), int(src_k)
         shape = (op.nr, op.nz)
         z = lambda: torch.zeros(shape, dtype=torch.float64, device="cuda")  # noqa: E731
-        self.S1, self.S2, self.b, self.u1, self.u = z(), z(), z(), z(), z()
+        self.S1, self.S2, self.b, self.u = z(), z(), z(), z()
+        self.hist = [z() for _ in range(ax.POLY_HISTORY)]
         self.coef = torch.as_tensor(coef, dtype=torch.float64).cuda().contiguous()
         self.rec_idx = torch.as_tensor(rec_idx, dtype=torch.int64).cuda().contiguous()
         self.Q = torch.zeros((len(self.g), self.rec_idx.numel()), dtype=torch.float64, device="cuda")
         self.m = 0
+
+    @property
+    def u1(self):
+        return self.hist[0]
 
     def step(self, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats, solver: str = "pcg"):
         m = self.m
@@ -202,6 +208,8 @@ class PaperSeries:
             self.u.zero_()
         elif guess == "prev":
             self.u.copy_(self.u1)
+        elif guess == "poly":
+            ax.guess_poly(self.op, self.b, self.hist, self.u)
         else:
             raise ValueError(f"unknown guess {guess!r}")
         if solver == "cheb":
@@ -211,7 +219,7 @@ class PaperSeries:
         stats.iters.append(st["iters"])
         stats.status.append(st["code"])
         ax.gather(self.op, self.u, self.rec_idx, self.Q[m])
-        self.u1, self.u = self.u, self.u1
+        self.hist, self.u = [self.u] + self.hist[:-1], self.hist[-1]
         self.m += 1
 
     def run_harmonics(self, n: int, guess: str, prec: int, rtol: float, maxit: int, stats: SeriesStats,
@@ -221,13 +229,14 @@ class PaperSeries:
             return
         if self.m + n > len(self.g):
             raise ValueError("not enough Laguerre coefficients")
-        u = [self.u1, self.u]
+        nh = ax.POLY_HISTORY if guess == "poly" else 1
+        u = self.hist[:nh] + [self.u]
         code, sts = ax.series_run_alpha(self.op, self.m, self.alpha, self.g[self.m:self.m + n], self.src_i,
                                         self.src_k, self.coef, self.S1, self.S2, self.b, u, self.rec_idx, self.Q,
                                         guess, solver=solver, rtol=rtol, maxit=maxit, prec=prec)
         stats.iters.extend(st["iters"] for st in sts)
         stats.status.extend(st["status"] for st in sts)
-        self.u1, self.u = u
+        self.hist[:nh], self.u = u[:nh], u[nh]
         self.m += len(sts)
 
     def run(self, n: int, guess: str, prec: int, rtol: float = 1e-10, maxit: int = 1000,

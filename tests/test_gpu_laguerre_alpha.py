@@ -64,7 +64,7 @@ def test_paper_chain_and_traces_match_oracle(ax, orc, prec):
         assert np.abs(tr - tro).max() <= 1e-8 * np.abs(tro).max()
 
 
-@pytest.mark.parametrize("guess,solver", [("zero", "pcg"), ("prev", "pcg"), ("prev", "cheb")])
+@pytest.mark.parametrize("guess,solver", [("zero", "pcg"), ("prev", "pcg"), ("prev", "cheb"), ("poly", "pcg")])
 def test_paper_run_matches_steps(ax, guess, solver):
     """series_run_alpha (harmonics in one call, runs of 5 and 7) against the
     same harmonics step by step: the same kernels in the same order, so the
