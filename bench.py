@@ -379,8 +379,8 @@ def main():
         ingest_traffic(a, *a.ingest_traffic)
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU r-strip "
-              "decomposition is a design in DESIGN.md, not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); splitting the grid into "
+              "r-strips across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch

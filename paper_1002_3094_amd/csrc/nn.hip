@@ -1,5 +1,5 @@
 // Learned initial guess for the Laguerre series (an extension beyond the
-// paper; PCG of §2.2 stays the judge of the answer).
+// paper; PCG of §2.2 still decides the answer).
 //
 // A 6-layer 3x3 convolutional network, 32 channels wide, maps four input
 // channels of harmonic m -- u_{m-1}/s, u_{m-2}/s, b_m/s_b and (kappa-2.5)/1.5,
