@@ -7,7 +7,10 @@
 * the Laguerre series itself: the GPU chain (running-sum right-hand sides,
   previous-harmonic guess, FP32 preconditioner, rtol 1e-10) against the
   oracle's chain (direct history sum, FP64, rtol 1e-13) from the same seeded
-  inputs, every harmonic within 1e-8 relative L2.
+  inputs, every harmonic within 1e-8 relative L2;
+* the benchmark's launch configuration (one series_run call over the
+  harmonics with the polynomial-extrapolation guard, with and without the
+  learned candidate) against the same oracle chain, 1e-8 relative L2.
 """
 import numpy as np
 import pytest
@@ -83,4 +86,42 @@ def test_laguerre_chain_matches_oracle(ax, orc, nr, nz, n_harm):
                                  rtol=1e-13 if nr < 2048 else 1e-12)
     errs = [rel(a, b) for a, b in zip(ug, uo)]
     log(f"  iters={its} errs={[f'{e:.1e}' for e in errs]}")
+    assert max(errs) <= 1e-8
+
+
+# The benchmark's own launch configuration: the whole run of harmonics in one
+# series_run call (right-hand side, guard over the seven-harmonic polynomial
+# extrapolations -- and the learned candidate --, FP64 PCG with the FP32
+# preconditioner, rtol 1e-10) on the 1024^2 layered medium.  The call keeps
+# the last seven solutions; each must match the oracle's harmonic, since the
+# answer does not depend on the guess.
+N_HEAD = 9
+
+
+@pytest.fixture(scope="module")
+def head_oracle(orc):
+    inp = synth.laguerre_series_inputs(1024, 1024, seed=0)
+    oop = orc.operator_from_cells(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
+    go = orc.laguerre_coeffs(N_HEAD, inp["eta"], inp["ft"], inp["t"][-1])
+    uo, _ = orc.laguerre_chain(oop, inp["kappa"], go, inp["eta"], inp["src_i"], inp["src_k"], N_HEAD,
+                               rtol=1e-13)
+    return inp, uo
+
+
+@pytest.mark.parametrize("guess", ["nn_poly", "poly"])
+def test_series_run_1024_matches_oracle(ax, head_oracle, guess):
+    from paper_1002_3094_amd.series import LaguerreSeries, nn_init_params
+    log(f"series_run 1024^2 guess={guess} harmonics={N_HEAD}")
+    inp, uo = head_oracle
+    net = ax.nn_create(1024, 1024, nn_init_params(0, last_zero=False)) if guess == "nn_poly" else None
+    with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
+        g = ax.laguerre_coeffs(N_HEAD, inp["eta"], inp["ft"], inp["t"][-1])
+        s = LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+        st = s.run(N_HEAD, guess, ax.PREC_FP32, rtol=1e-10, net=net)
+        assert st.status == [ax.OK] * N_HEAD
+        kept = [host(h).copy() for h in s.hist]   # u_8, u_7, ..., u_2
+    if net is not None:
+        net.close()
+    errs = [rel(kept[j], uo[N_HEAD - 1 - j]) for j in range(len(kept))]
+    log(f"  iters={st.iters} errs={[f'{e:.1e}' for e in errs]}")
     assert max(errs) <= 1e-8
