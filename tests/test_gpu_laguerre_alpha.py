@@ -1,6 +1,7 @@
 """The paper's Laguerre experiment (§4.3; eqs. (34)-(35) with alpha = 5,
 h = 300, Neumann in z, the pulse of eq. (40)) on the GPU against the oracle:
-coefficients, harmonics from zero guesses, receiver samples and traces."""
+coefficients, harmonics from zero guesses, receiver samples and traces, and
+the benchmark's one-call run of harmonics at 1024^2."""
 import numpy as np
 import pytest
 
@@ -117,3 +118,41 @@ def test_gather_and_rhs_edge_cases(ax):
             ax.laguerre_rhs_alpha(op, 1, 5, 1.0, 0, 0, S1, S2, b)
         with pytest.raises(ax.AxipcgError):
             ax.laguerre_rhs_alpha(op, 0, -1, 1.0, 0, 0, S1, S2, b)
+
+
+# The benchmark's launch configuration of the paper's experiment: 1024^2
+# fault stand-in, the whole run of harmonics in one series_run_alpha call
+# (FP32 preconditioner, rtol 1e-10), zero guess as in the paper and the
+# polynomial-extrapolation guard.  Every harmonic is checked at the receivers
+# (the call's own samples) and the solutions the call keeps over the whole
+# field.
+N_PAPER = 9
+
+
+@pytest.fixture(scope="module")
+def paper_oracle(orc):
+    inp = synth.paper_series_inputs(1024, 1024, seed=101)
+    oop = orc.operator_from_cells(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"])
+    go = orc.laguerre_coeffs_a(N_PAPER, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+    uo, _ = orc.laguerre_chain_a(oop, inp["coef"], go, inp["alpha"], inp["src_i"], inp["src_k"], N_PAPER)
+    return inp, uo
+
+
+@pytest.mark.parametrize("guess", ["zero", "poly"])
+def test_paper_run_1024_matches_oracle(ax, paper_oracle, guess):
+    from paper_1002_3094_amd.series import PaperSeries
+    log(f"series_run_alpha 1024^2 guess={guess} harmonics={N_PAPER}")
+    inp, uo = paper_oracle
+    with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"]) as op:
+        g = ax.laguerre_coeffs_alpha(N_PAPER, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+        s = PaperSeries(op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"], inp["rec_idx"])
+        st = s.run(N_PAPER, guess, ax.PREC_FP32, rtol=1e-10)
+        assert st.status == [ax.OK] * N_PAPER
+        nh = ax.POLY_HISTORY if guess == "poly" else 1
+        kept = [host(h).copy() for h in s.hist[:nh]]   # u_8, u_7, ...
+        Qg = host(s.Q)
+    errs = [rel(kept[j], uo[N_PAPER - 1 - j]) for j in range(nh)]
+    Qo = np.array([u.ravel()[inp["rec_idx"]] for u in uo])
+    qerr = np.abs(Qg - Qo).max() / np.abs(Qo).max()
+    log(f"  iters={st.iters} field errs={[f'{e:.1e}' for e in errs]} receiver err={qerr:.1e}")
+    assert max(errs) <= 1e-8 and qerr <= 1e-8
