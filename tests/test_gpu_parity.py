@@ -122,7 +122,23 @@ def test_precond_fp32(ax, orc, nr, nz, bc):
 
 SOLVE_CASES = [("smooth", 64, 64, 0), ("layered", 256, 256, 0), ("layered", 128, 64, 1),
                ("layered", 96, 256, 0), ("layered", 100, 128, 1), ("layered", 8, 4, 0),
-               ("layered", 66, 1024, 0), ("layered", 30, 2048, 1), ("layered", 45, 512, 1)]
+               ("layered", 66, 1024, 0), ("layered", 30, 2048, 1), ("layered", 45, 512, 1),
+               # the most rows op_create accepts (64 per r-solve lane), and a
+               # ragged row count in the same r-solve variant
+               ("layered", 4096, 32, 0), ("layered", 3000, 64, 1)]
+
+
+# The most rows op_create accepts, and a ragged count in the same r-solve
+# variant (segments of 46 and 47 rows).  Only the backward error is bounded:
+# the forward error of a correct solve grows with the condition number of the
+# r-systems (about nr^2), so a fixed forward bound would not hold at any size.
+@pytest.mark.parametrize("nr,nz,bc", [(4096, 32, 0), (3000, 64, 1)])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_precond_max_rows(ax, orc, nr, nz, bc, prec):
+    log(f"precond max rows {nr}x{nz} bc={bc} prec={prec}")
+    back, fwd = _precond_case(ax, orc, nr, nz, bc, prec)
+    log(f"  backward={back:.2e} forward={fwd:.2e}")
+    assert back <= (1e-14 if prec == ax.PREC_FP64 else 32 * EPS32 * max(1.0, math.log2(nz)))
 
 
 @pytest.mark.parametrize("kind,nr,nz,bc", SOLVE_CASES)
