@@ -1,5 +1,6 @@
 """Batched PCG over independent problems of different sizes, against the
-oracle (each problem solved on its own) and against single-problem solves."""
+oracle (each problem solved on its own) and against single-problem solves,
+up to the largest member count a batch accepts."""
 import numpy as np
 import pytest
 
@@ -119,5 +120,36 @@ def test_uneven_batch_of_64(ax, orc):
         # sums may be added in another order than in the single solve
         assert abs(s1["iters"] - st[p]["iters"]) <= 1
         assert rel(host(xs[p]), host(xs1)) <= 1e-9, p
+    for op in ops:
+        op.close()
+
+
+def test_batch_of_the_most_members(ax, orc):
+    """A batch of 4096 members (the most batch_solve accepts) of tiny mixed
+    shapes and both z boundaries: every member converges by its true
+    residual, and every 64th matches the oracle."""
+    shapes = [(2, 4), (3, 8), (4, 4), (8, 4), (7, 16), (16, 32)]   # members need nz >= 4
+    n = 4096
+    log(f"batch of {n} members")
+    ops, bs, xs, members = [], [], [], []
+    for p in range(n):
+        kappa, q, f, bc = _member(shapes[p % len(shapes)], (p // len(shapes)) % 2, 7000 + p)
+        op = ax.op_create(kappa, q, bc_z=bc)
+        b = dev(np.zeros(kappa.shape))
+        ax.rhs_from_f(op, dev(f), b)
+        ops.append(op)
+        bs.append(b)
+        xs.append(dev(np.zeros(kappa.shape)))
+        members.append((kappa, q, f, bc))
+    code, st = ax.batch_solve(ops, bs, xs, 1e-10, 500, ax.PREC_FP32, ax.FLAG_TRUE_RESIDUAL)
+    assert code == ax.OK
+    assert all(s["status"] == ax.OK and s["relres_true"] <= 1e-9 for s in st)
+    errs = []
+    for p in range(0, n, 64):
+        kappa, q, f, bc = members[p]
+        oop = orc.operator_from_cells(kappa, q, bc_z=bc)
+        errs.append(rel(host(xs[p]), orc.solve_reference(oop, orc.rhs(oop, f))))
+    log(f"  iters max {max(s['iters'] for s in st)}, sampled max rel err {max(errs):.1e}")
+    assert max(errs) <= 1e-8
     for op in ops:
         op.close()
