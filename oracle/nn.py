@@ -114,14 +114,20 @@ def conv3(x, W, bias=None):
     return y
 
 
-def inputs(u1, u2, b, kappa, bf16=True):
-    """Normalised input channels and the scale s."""
-    rnd = bf16_round if bf16 else _ident
-    u1, u2, b, kappa = (np.asarray(a, dtype=np.float64) for a in (u1, u2, b, kappa))
+def scales(u1, b):
+    """s = RMS(u_{m-1}) and s_b = RMS(b_m) over the whole grid (1 when zero)."""
+    u1, b = np.asarray(u1, dtype=np.float64), np.asarray(b, dtype=np.float64)
     s = float(np.sqrt(np.mean(u1 * u1)))
     sb = float(np.sqrt(np.mean(b * b)))
-    s = s if s > 0 else 1.0
-    sb = sb if sb > 0 else 1.0
+    return (s if s > 0 else 1.0), (sb if sb > 0 else 1.0)
+
+
+def inputs(u1, u2, b, kappa, bf16=True, sc=None):
+    """Normalised input channels and the scale s (``sc`` = (s, s_b) when the
+    arrays are a window of a larger grid)."""
+    rnd = bf16_round if bf16 else _ident
+    u1, u2, b, kappa = (np.asarray(a, dtype=np.float64) for a in (u1, u2, b, kappa))
+    s, sb = scales(u1, b) if sc is None else sc
     x = np.stack([u1 / s, u2 / s, b / sb, (kappa - 2.5) / 1.5], axis=-1)
     return rnd(x), s
 
@@ -141,6 +147,31 @@ def forward(params, u1, u2, b, kappa, bf16=True):
     u1, u2 = np.asarray(u1, dtype=np.float64), np.asarray(u2, dtype=np.float64)
     guess = 2.0 * u1 - u2 + s * out
     return guess, {"acts": acts, "out": out, "s": s, "bf16": bf16, "guess": guess}
+
+
+def forward_at(params, u1, u2, b, kappa, points, bf16=True):
+    """The network output ``out`` at the cells ``points`` ((i, k) pairs) of a
+    grid too large to evaluate whole.  The output of a cell depends only on
+    the inputs within six cells in each direction (six 3x3 layers), so each
+    point is evaluated on that window: its normalisation uses the scales of
+    the whole grid, and zero padding falls at the grid's edges where the
+    window meets them.  Values at the window's inner border are wrong after a
+    layer, but they never reach the centre in the layers that remain."""
+    rnd = bf16_round if bf16 else _ident
+    layers = unpack(params)
+    sc = scales(u1, b)
+    nr, nz = np.shape(u1)
+    out = np.empty(len(points))
+    for j, (i, k) in enumerate(points):
+        i0, i1 = max(0, i - N_LAYERS), min(nr, i + N_LAYERS + 1)
+        k0, k1 = max(0, k - N_LAYERS), min(nz, k + N_LAYERS + 1)
+        win = tuple(np.asarray(a)[i0:i1, k0:k1] for a in (u1, u2, b, kappa))
+        x, _ = inputs(*win, bf16=bf16, sc=sc)
+        for l, (W, bias) in enumerate(layers):
+            y = conv3(x, rnd(W), bias)
+            x = rnd(np.maximum(y, 0.0)) if l < N_LAYERS - 1 else y
+        out[j] = x[i - i0, k - k0, 0]
+    return out
 
 
 def backward(params, cache, apply_A, u_target):

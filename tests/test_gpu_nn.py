@@ -305,3 +305,29 @@ def test_nn_poly_guard_matches_oracle(ax, onn, orc):
     net.close()
     op.close()
 
+
+
+def test_forward_1024_sampled(ax, onn):
+    """Forward pass at the benchmark's 1024^2 grid against the oracle on
+    sampled cells (corners, edges and seeded interior cells), each evaluated
+    by the oracle on its receptive field; the bound is the one of the small
+    shapes above."""
+    n = 1024
+    log("nn forward 1024^2 sampled")
+    ex = synth.nn_example(n, n, seed=77)
+    params = onn.init_params(5, last_zero=False)
+    params[onn.OFFSETS[5] + 9 * 32] = 0.25
+    net = ax.nn_create(n, n, params)
+    guess = _gpu_out(ax, net, ex)
+    net.close()
+    s, _ = onn.scales(ex["u1"], ex["b"])
+    out_gpu = (guess - (2 * ex["u1"] - ex["u2"])) / s
+    rng = np.random.default_rng(77)
+    edge = [0, 1, 5, 6, n // 2, n - 7, n - 2, n - 1]
+    pts = [(i, k) for i in edge for k in edge] + [tuple(p) for p in rng.integers(0, n, size=(200, 2))]
+    ref = onn.forward_at(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], pts, bf16=True)
+    got = np.array([out_gpu[i, k] for i, k in pts])
+    e = rel(got, ref)
+    log(f"  {len(pts)} cells: out rel err {e:.2e}")
+    assert e < 5e-3
+    assert np.abs(got - ref).max() < 0.05 * np.abs(ref).max()

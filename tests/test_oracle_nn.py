@@ -240,3 +240,23 @@ def test_adam_matches_torch():
         opt.step()
         p, m1, m2 = onn.adam(p, g, m1, m2, step, 1e-2)
         np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_forward_at_equals_whole_grid_forward(bf16):
+    """The windowed evaluation (six-cell receptive field, whole-grid scales,
+    zero padding at the grid's edges only) gives the whole-grid output at
+    every cell, corners and edges included."""
+    ex = nn_example(19, 23, seed=31)
+    params = onn.init_params(4, last_zero=False)
+    params[onn.OFFSETS[5] + 9 * 32] = 0.25
+    _, cache = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=bf16)
+    pts = [(i, k) for i in range(19) for k in range(23)]
+    got = onn.forward_at(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], pts, bf16=bf16)
+    want = cache["out"].ravel()
+    if bf16:
+        # FP64 sums of another length may round a hidden activation to the
+        # neighbouring bfloat16 now and then
+        assert np.linalg.norm(got - want) <= 1e-3 * np.linalg.norm(want)
+    else:
+        np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
