@@ -45,6 +45,32 @@ def test_binding_never_imports_the_oracle():
     assert "oracle" not in src.replace("no CPU fallback", "")
 
 
+def test_product_and_oracle_share_no_code():
+    """No product source imports or includes the oracle, and the oracle
+    neither imports the package nor includes the library's headers; the
+    seeded input generators (synth) are the only code both sides use."""
+    import glob
+    import re
+    pkg = os.path.join(ROOT, "paper_1002_3094_amd")
+    product = glob.glob(os.path.join(pkg, "*.py")) + glob.glob(os.path.join(pkg, "csrc", "*")) + \
+        glob.glob(os.path.join(ROOT, "include", "*.h"))
+    py_import = re.compile(r"^\s*(import|from)\s+(\S+)", re.M)
+    c_include = re.compile(r'^\s*#\s*include\s*[<"]([^>"]+)[>"]', re.M)
+    for path in product:
+        if path.endswith((".so", ".o")) or os.path.isdir(path):
+            continue
+        src = open(path, errors="replace").read()
+        assert not any(m.group(2).split(".")[0] == "oracle" for m in py_import.finditer(src)), path
+        assert not any("oracle" in m.group(1) for m in c_include.finditer(src)), path
+    for path in glob.glob(os.path.join(ROOT, "oracle", "*")):
+        if not path.endswith((".py", ".c", ".h")):
+            continue
+        src = open(path).read()
+        assert not any(m.group(2).split(".")[0] == "paper_1002_3094_amd" for m in py_import.finditer(src)), path
+        for m in c_include.finditer(src):
+            assert "axipcg" not in m.group(1) and "csrc" not in m.group(1), path
+
+
 def test_strerror(ax):
     assert ax.strerror(ax.EINVAL) == "invalid argument"
     assert ax.strerror(ax.ENOTCONV) == "not converged within maxit"
