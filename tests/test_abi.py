@@ -71,6 +71,20 @@ def test_product_and_oracle_share_no_code():
             assert "axipcg" not in m.group(1) and "csrc" not in m.group(1), path
 
 
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every entry point raises: there is no CPU
+    fallback to land on."""
+    import paper_1002_3094_amd.axipcg as b
+    monkeypatch.setattr(b, "_lib", None)
+    monkeypatch.setattr(b, "LIB_PATH", os.path.join(ROOT, "_no_such_dir", "libaxipcg.so"))
+    with pytest.raises(ImportError):
+        b.lib()
+    with pytest.raises(ImportError):
+        b.strerror(0)
+    with pytest.raises(ImportError):
+        b.laguerre_coeffs(4, 10.0, np.ones(5), 1.0)
+
+
 def test_strerror(ax):
     assert ax.strerror(ax.EINVAL) == "invalid argument"
     assert ax.strerror(ax.ENOTCONV) == "not converged within maxit"
