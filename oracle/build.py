@@ -1,4 +1,9 @@
-"""Build the CPU oracle library (plain C, FP64, OpenMP over rows)."""
+"""Build the CPU oracle library (plain C, FP64, OpenMP over rows).
+
+TEST INFRASTRUCTURE ONLY: the library this builds is loaded by ``tests/``,
+``__graft_entry__.smoke()`` and the CPU leg of ``bench.py``, never by the
+product path; ``__graft_entry__.build()`` compiles it so that the checker is
+ready, which is not a use of it."""
 import os
 import subprocess
 
