@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--large-harmonics", type=int, default=100, help="timed harmonics of the 2048^2 record")
     ap.add_argument("--paper-harmonics", type=int, default=200,
                     help="harmonics timed in the paper-experiment record (the paper used 2000)")
+    ap.add_argument("--precond-only", type=int, default=0, metavar="N",
+                    help="only time standalone preconditioner applies on an N x N layered medium (FP32 "
+                         "then FP64, --steps applies each) and print their rates; the run to profile "
+                         "the preconditioner's kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy a 64 MiB tensor five times (the known-size kernel that scales the "
                          "FETCH_SIZE / WRITE_SIZE counters of a --pmc run)")
@@ -264,6 +268,40 @@ def large_measure(ax, torch, n, n_harm, seed):
     return rec
 
 
+def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
+    """Standalone preconditioner applies z = B^{-1} r on the n x n layered
+    medium, timed with HIP events on the current stream over `reps` applies
+    after three untimed ones."""
+    import synth
+    inp = synth.laguerre_series_inputs(n, n, seed=seed)
+    op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
+    r = torch.randn((n, n), dtype=torch.float64, device="cuda", generator=torch.Generator("cuda").manual_seed(seed))
+    z = torch.empty_like(r)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    rec = {"workload": f"precond_{n}x{n}"}
+    for name in precs:
+        prec = ax.PREC_FP32 if name == "fp32" else ax.PREC_FP64
+        for _ in range(3):
+            ax.precond_apply(op, r, z, prec)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            ax.precond_apply(op, r, z, prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pc_s = e0.elapsed_time(e1) / 1e3 / reps
+        bpp = PRECOND_BYTES_PER_POINT if prec == ax.PREC_FP32 else PRECOND_BYTES_PER_POINT_FP64
+        gbs = bpp * n * n / pc_s / 1e9
+        rec[name] = {"applies_per_s": round(1.0 / pc_s, 1), "mean_us": round(pc_s * 1e6, 2), "bytes_per_point": bpp,
+                     "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                     "min_bytes_per_point": 16, "gbs_at_min_bytes": round(16 * n * n / pc_s / 1e9, 1)}
+        print(f"[precond] {n}x{n} {name}: {pc_s * 1e6:.2f} us per apply ({reps} applies)", flush=True)
+    op.close()
+    return rec
+
+
 def paper_measure(ax, torch, n_harm):
     """The paper's experiment (§4.3) at 1024^2: the fault stand-in, Neumann in
     z, alpha = 5, h = 300, the pulse of eq. (40), FP32 preconditioner; a zero
@@ -339,6 +377,37 @@ def batch_measure(ax, torch, prec, reps=3):
             "iters_min_max": [min(iters), max(iters)]}
 
 
+def per_step_parity(ax, series, op, g, inp, a, net, last_b, last_u):
+    """Per-step parity of the headline chain: at harmonics spread over the
+    timed range, and at the last timed one, the oracle solves A u = b_m from
+    the GPU's own right-hand side b_m to a relative residual of 1e-13 and
+    u_m must match it to 1e-8.  The last timed harmonic is checked on the b_m
+    and u_m the timed run itself left behind; the others come from an untimed
+    replay of the same series in chunks, which reproduces the timed run
+    bit for bit (checked on the last harmonic)."""
+    import oracle
+    prec_name, guess, solver = MODES[a.headline]
+    prec = ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64
+    oop = oracle.operator_from_cells(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
+    n_harm = a.warmup + a.steps
+    marks = sorted({a.warmup + (a.steps * q) // 4 for q in (1, 2, 3)} | {n_harm - 1})
+    s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+    st = series.SeriesStats()
+    cases = []
+    for m in marks:
+        if m + 1 > s.m:
+            s.run_harmonics(m + 1 - s.m, guess, prec, 1e-10, 1000, st, net=net, solver=solver)
+        cases.append((m, s.b.cpu().numpy(), s.u1.cpu().numpy()))
+    replay_equal = bool(np.array_equal(cases[-1][1], last_b) and np.array_equal(cases[-1][2], last_u))
+    cases[-1] = (n_harm - 1, last_b, last_u)
+    errs = []
+    for m, b, u in cases:
+        ref = oracle.solve_reference(oop, b, rtol=1e-13, maxit=1000)
+        errs.append(float(np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300)))
+    return {"harmonics": [m for m, _, _ in cases], "rel_err": errs, "max_rel_err": max(errs),
+            "oracle_rtol": 1e-13, "last_timed_harmonic": n_harm - 1, "replay_bitwise_equal_to_timed": replay_equal}
+
+
 MODES = {   # (preconditioner, guess, solver)
     "A": ("fp64", "prev", "pcg"),
     "B": ("fp32", "prev", "pcg"),
@@ -391,6 +460,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if a.precond_only:
+        print(json.dumps(precond_measure(ax, torch, a.precond_only, a.steps)), flush=True)
+        return
     if a.copy_calibration:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
@@ -435,6 +507,9 @@ def main():
         wall = time.perf_counter() - t0
         assert all(c == ax.OK for c in st.status), st.status
         elapsed = max(wall, st.gpu_ms / 1e3)
+        if head:
+            # the last timed harmonic as the timed run left it (copied after the clock stopped)
+            last_b, last_u = s.b.cpu().numpy(), s.u1.cpu().numpy()
         results[mode] = {"precond": prec_name, "guess": guess, "solver": solver,
                          "harmonics_per_s": round(a.steps / elapsed, 2),
                          "ms_per_harmonic": round(elapsed * 1e3 / a.steps, 4),
@@ -545,8 +620,11 @@ def main():
                    solver=solver)
             ug = s.u1.cpu().numpy()
             errs.append(float(np.linalg.norm(ug - uo) / max(np.linalg.norm(uo), 1e-300)))
-        out["accuracy"] = {"harmonics_checked": len(errs), "max_rel_err_vs_oracle": max(errs) if errs else None,
+        out["accuracy"] = {"chain_prefix": {"harmonics_checked": len(errs),
+                                            "max_rel_err_vs_oracle_chain": max(errs) if errs else None},
+                           "per_step": per_step_parity(ax, series, op, g, inp, a, net, last_b, last_u),
                            "tolerance": 1e-8}
+        assert out["accuracy"]["per_step"]["max_rel_err"] <= 1e-8, out["accuracy"]
     if net is not None:
         net.close()
     op.close()

@@ -85,7 +85,7 @@ typedef struct {
  * face takes its cell's value).  kbar <= 0 selects the mean of kappa, qbar < 0
  * the mean of q (the paper's footnote to eq. (37) uses the mid-range; PCG is
  * invariant to scaling B, so this only changes iteration counts).
- * Limits: 2 <= nr <= 4096; nz a power of two with 2 <= nz <= 4096; lr, lz > 0;
+ * Limits: 2 <= nr <= 4096; nz a power of two with 2 <= nz <= 2048; lr, lz > 0;
  * kappa > 0 and q >= 0, all finite.  Allocates ~ (10 * 8) bytes per cell of
  * device memory.  *out receives the handle. */
 int axipcg_op_create(int nr, int nz, double lr, double lz, int bc_z,
@@ -155,7 +155,7 @@ int axipcg_pcg_solve(axipcg_op_t op, const double *b, double *x, double rtol, in
  * The two-step scheme of eq. (8) with tau = 2 / (gamma1 + gamma2) and
  * alpha_1 = 1, alpha_2 = 2 / (2 - rho0^2), alpha_{k+1} = 4 / (4 - rho0^2
  * alpha_k), rho0 = (1 - xi) / (1 + xi), xi = gamma1 / gamma2, where
- * gamma1 <= (Au,u)/(Bu,u) <= gamma2 (eq. (7)).  Run in increment form
+ * gamma1 <= (Au,u)/(Bu,u) <= gamma2 (eq. (10)).  Run in increment form
  * (d_k = (alpha_{k+1} - 1) d_{k-1} + alpha_{k+1} tau B^{-1} r_k,
  * x += d_k, r -= A d_k): no dot products except ||r||^2 for the stop test
  * ||r_k|| / ||b|| <= rtol.  gamma1 = gamma2 = 0 takes the operator's own
@@ -165,7 +165,7 @@ int axipcg_pcg_solve(axipcg_op_t op, const double *b, double *x, double rtol, in
  * workspace. */
 int axipcg_cheb_solve(axipcg_op_t op, const double *b, double *x, double gamma1, double gamma2,
                       double rtol, int maxit, int prec, axipcg_stats *st, void *stream);
-/* The operator's energy-equivalence bounds of eq. (7) for its B: the extreme
+/* The operator's energy-equivalence bounds of eq. (10) for its B: the extreme
  * ratios kappa_face / kbar over faces with non-zero conductance and q / qbar
  * over cells (when qbar > 0).  gamma1 is 0 when some q is 0 and qbar > 0. */
 int axipcg_op_bounds(axipcg_op_t op, double *gamma1, double *gamma2);

@@ -344,7 +344,7 @@ def laguerre_chain(op: Operator, kappa, g, eta: float, src_i: int, src_k: int,
 
 
 def energy_bounds(op: Operator):
-    """Energy-equivalence constants of eq. (7) for B = the same scheme with
+    """Energy-equivalence constants of eq. (10) for B = the same scheme with
     kbar, qbar in place of kappa, q (§4.2 eqs. (36)-(37)): both quadratic forms
     are sums over faces of conductance * (difference)^2 plus sums over cells of
     w * u^2, so gamma1 / gamma2 are the smallest / largest ratio of matching
@@ -374,7 +374,7 @@ def cheb_alpha(m: int, rho2: float) -> float:
 def cheb(op: Operator, b, x0=None, gamma1=None, gamma2=None, rtol=1e-13, maxit=500, iters=None):
     """The two-step iteration of §2.2 eq. (8),
         B (ybar - y_k) / tau + A y_k = f,   y_{k+1} = alpha_{k+1} ybar + (1 - alpha_{k+1}) y_{k-1},
-    with the Chebyshev parameters for the bounds gamma1, gamma2 of eq. (7):
+    with the Chebyshev parameters for the bounds gamma1, gamma2 of eq. (10):
     tau = 2 / (gamma1 + gamma2), rho0 = (1 - xi) / (1 + xi), xi = gamma1 / gamma2
     (alpha_1 = 1, so y_{-1} does not enter).  Stops when ||f - A y_k|| / ||f||
     <= rtol, or after exactly `iters` steps when given.  Returns

@@ -8,8 +8,11 @@ when the library has not been built: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -23,6 +26,20 @@ FLAG_TRUE_RESIDUAL, FLAG_POLAK_RIBIERE = 1, 2
 KERNEL_NONE, KERNEL_SPMV, KERNEL_ZFWD, KERNEL_TRIDIAG, KERNEL_ZINV = -1, 0, 1, 2, 3
 
 _lib = None
+# Handles still open: released by an exit hook, before the interpreter and
+# the HIP runtime shut down, never from a finaliser during shutdown.
+_live = weakref.WeakSet()
+
+
+def _release_all():
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
+
+
+atexit.register(_release_all)
 
 
 class AxipcgError(RuntimeError):
@@ -147,6 +164,7 @@ class Op:
 
     def __init__(self, handle: int):
         self.handle = _vp(handle)
+        _live.add(self)
         n_r, n_z, kb, qb = _i(), _i(), _d(), _d()
         _check(lib().axipcg_op_info(self.handle, ctypes.byref(n_r), ctypes.byref(n_z),
                                     ctypes.byref(kb), ctypes.byref(qb)), "op_info")
@@ -156,8 +174,13 @@ class Op:
         if self.handle is not None and self.handle.value:
             lib().axipcg_op_destroy(self.handle)
         self.handle = None
+        _live.discard(self)
 
     def __del__(self):
+        # at interpreter shutdown the exit hook has already released it (or
+        # the runtime is going away): touch nothing
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -367,14 +390,20 @@ class Net:
 
     def __init__(self, handle: int, nr: int, nz: int):
         self.handle = _vp(handle)
+        _live.add(self)
         self.nr, self.nz = nr, nz
 
     def close(self):
         if self.handle is not None and self.handle.value:
             lib().axipcg_nn_destroy(self.handle)
         self.handle = None
+        _live.discard(self)
 
     def __del__(self):
+        # at interpreter shutdown the exit hook has already released it (or
+        # the runtime is going away): touch nothing
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

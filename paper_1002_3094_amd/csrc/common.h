@@ -99,7 +99,7 @@ struct Operator {
     int nr = 0, nz = 0, bc_z = 0;
     double lr = 0, lz = 0, hr = 0, hz = 0;
     double kbar = 0, qbar = 0;
-    double gamma1 = 0, gamma2 = 0;   // energy-equivalence bounds of B^{-1} A (eq. (7))
+    double gamma1 = 0, gamma2 = 0;   // energy-equivalence bounds of B^{-1} A (eq. (10))
     int device = 0;
     int last_iters = 0;              // iterations of the previous solve (chunk sizing)
     hipStream_t create_stream = nullptr;
@@ -152,6 +152,7 @@ struct Operator {
     size_t prof_used = 0;
     double prof_ms = 0.0;
     long long prof_count = 0;
+    bool prof_error = false;              // a stop event failed to record (reported by profile_read)
 };
 
 // One problem of a batched solve, as the batched kernels see it.  Workgroup g

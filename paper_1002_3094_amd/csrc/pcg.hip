@@ -18,6 +18,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <climits>
+
 #include "kernels.h"
 
 namespace axipcg {
@@ -300,9 +302,14 @@ struct ProfScope {
     }
     hipEvent_t start() const { return on ? op.prof_events[2 * slot] : nullptr; }
     hipEvent_t stop() const { return on ? op.prof_events[2 * slot + 1] : nullptr; }
-    ~ProfScope() noexcept(false)
+    // Never throws (it may run during unwinding): a failed stop record drops
+    // the sample and marks the profile, which axipcg_profile_read reports.
+    ~ProfScope() noexcept
     {
-        if (on && !ext) AXI_CHECK_HIP(hipEventRecord(op.prof_events[2 * slot + 1], s));
+        if (on && !ext && hipEventRecord(op.prof_events[2 * slot + 1], s) != hipSuccess) {
+            op.prof_error = true;
+            op.prof_iter[slot] = INT_MAX;   // dropped by collect_profile
+        }
     }
 };
 
@@ -632,6 +639,10 @@ extern "C" int axipcg_profile_read(axipcg_op_t h, double *total_ms, long long *l
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(h);
         AXI_REQUIRE(op != nullptr, "op is NULL");
+        if (op->prof_error) {
+            op->prof_error = false;
+            throw Error{AXIPCG_EDEVICE, "a profiling event could not be recorded; samples were dropped"};
+        }
         if (total_ms) *total_ms = op->prof_ms;
         if (launches) *launches = op->prof_count;
         if (reset) {

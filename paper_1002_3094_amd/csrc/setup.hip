@@ -293,7 +293,7 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         const double qb = qbar >= 0 ? qbar : op->scratch_host[1] / (double)n;
         op->kbar = kb;
         op->qbar = qb;
-        // energy-equivalence bounds of eq. (7) for B (kbar, qbar): both
+        // energy-equivalence bounds of eq. (10) for B (kbar, qbar): both
         // quadratic forms are sums of face terms (conductance x squared
         // difference) and cell terms (r q u^2), so gamma1 / gamma2 are the
         // extreme ratios of matching terms where B's is non-zero

@@ -21,7 +21,6 @@ from tests.gpu_util import dev, host, log, rel, spectral_norm_estimate
 
 pytestmark = pytest.mark.gpu
 
-EPS32 = float(np.finfo(np.float32).eps)
 
 
 @pytest.fixture(scope="module")
@@ -116,7 +115,7 @@ def test_precond_fp32(ax, orc, nr, nz, bc):
     log(f"precond fp32 {nr}x{nz} bc={bc}")
     back, fwd = _precond_case(ax, orc, nr, nz, bc, ax.PREC_FP32)
     log(f"  backward={back:.2e} forward={fwd:.2e}")
-    assert back <= 32 * EPS32 * max(1.0, math.log2(nz))
+    assert back <= 2e-6   # FP32 transforms: normwise backward error (about eps32 log2 N)
     assert fwd <= 2e-3
 
 
@@ -138,7 +137,7 @@ def test_precond_max_rows(ax, orc, nr, nz, bc, prec):
     log(f"precond max rows {nr}x{nz} bc={bc} prec={prec}")
     back, fwd = _precond_case(ax, orc, nr, nz, bc, prec)
     log(f"  backward={back:.2e} forward={fwd:.2e}")
-    assert back <= (1e-14 if prec == ax.PREC_FP64 else 32 * EPS32 * max(1.0, math.log2(nz)))
+    assert back <= (1e-14 if prec == ax.PREC_FP64 else 2e-6)
 
 
 @pytest.mark.parametrize("kind,nr,nz,bc", SOLVE_CASES)

@@ -1,6 +1,6 @@
 """Pins of the Chebyshev form of eq. (8) in the oracle.
 
-* the energy bounds of eq. (7) contain every eigenvalue of B^{-1}A (dense
+* the energy bounds of eq. (10) contain every eigenvalue of B^{-1}A (dense
   generalized eigenproblem of the independently assembled matrices);
 * after n steps the error is exactly P_n(B^{-1}A) e_0 with the scaled
   Chebyshev polynomial P_n(x) = T_n((g2 + g1 - 2x)/(g2 - g1)) / T_n((g2 + g1)/(g2 - g1))

@@ -260,3 +260,82 @@ def test_forward_at_equals_whole_grid_forward(bf16):
         assert np.linalg.norm(got - want) <= 1e-3 * np.linalg.norm(want)
     else:
         np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+
+
+# ---- the input normalisation (scales / inputs) -----------------------------------
+# A hand-checked 2x2 case: u_{m-1} = 2 everywhere (RMS 2), u_{m-2} one 1 (RMS 1/2),
+# b one 4 (RMS 2), kappa in {1, 2.5, 4}.  The channels are then u_{m-1}/2,
+# u_{m-2}/2, b/2 and (kappa - 2.5)/1.5, all exact in bfloat16.
+_U1 = np.full((2, 2), 2.0)
+_U2 = np.array([[1.0, 0.0], [0.0, 0.0]])
+_B = np.array([[0.0, 4.0], [0.0, 0.0]])
+_K = np.array([[1.0, 2.5], [4.0, 1.0]])
+_CH = np.array([[[1.0, 0.5, 0.0, -1.0], [1.0, 0.0, 2.0, 0.0]],
+                [[1.0, 0.0, 0.0, 1.0], [1.0, 0.0, 0.0, -1.0]]])
+
+
+def _normalisation_failures(inputs_fn, forward_fn):
+    """Checks of the input normalisation that do not use its own formula:
+    the hand-checked 2x2 channels, the zero-field fallbacks, and two exact
+    invariances of the guess (scaling the earlier harmonics by 2^k scales
+    the guess by 2^k; scaling b alone by 2^k leaves it unchanged).  Returns
+    the names of the checks that fail."""
+    bad = []
+    for bf in (False, True):
+        x, s = inputs_fn(_U1, _U2, _B, _K, bf16=bf)
+        if s != 2.0 or not np.array_equal(x, _CH):
+            bad.append(f"hand_2x2_bf16={bf}")
+    x, s = inputs_fn(np.zeros((2, 2)), _U2, np.zeros((2, 2)), _K, bf16=False)
+    if s != 1.0 or not np.array_equal(x[..., 1], _U2) or np.any(x[..., 2] != 0.0):
+        bad.append("zero_fields")
+    ex = nn_example(10, 14, seed=23)
+    params = onn.init_params(6, last_zero=False)
+    g0, _ = forward_fn(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=True)
+    for c in (0.25, 8.0):
+        gu, _ = forward_fn(params, c * ex["u1"], c * ex["u2"], ex["b"], ex["kappa"], bf16=True)
+        if not np.array_equal(gu, c * g0):
+            bad.append(f"scale_u_{c}")
+        gb, _ = forward_fn(params, ex["u1"], ex["u2"], c * ex["b"], ex["kappa"], bf16=True)
+        if not np.array_equal(gb, g0):
+            bad.append(f"scale_b_{c}")
+    return bad
+
+
+def test_input_normalisation_pinned():
+    assert _normalisation_failures(onn.inputs, onn.forward) == []
+
+
+def _mutant_forward(mutant_inputs):
+    """onn.forward with its input normalisation replaced (the rest unchanged)."""
+    def fwd(params, u1, u2, b, kappa, bf16=True):
+        saved = onn.inputs
+        onn.inputs = mutant_inputs
+        try:
+            return onn.forward(params, u1, u2, b, kappa, bf16=bf16)
+        finally:
+            onn.inputs = saved
+    return fwd
+
+
+def _mutant(kind):
+    def inputs(u1, u2, b, kappa, bf16=True, sc=None):
+        rnd = onn.bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+        u1, u2, b, kappa = (np.asarray(a, dtype=np.float64) for a in (u1, u2, b, kappa))
+        s, sb = onn.scales(u1, b)
+        if kind == "b_over_s":
+            sb = s
+        elif kind == "s_from_u2":
+            s = float(np.sqrt(np.mean(u2 * u2))) or 1.0
+        elif kind == "kappa_shift":
+            kappa = kappa + 1.5
+        x = np.stack([u1 / s, u2 / s, b / sb, (kappa - 2.5) / 1.5], axis=-1)
+        return rnd(x), s
+    return inputs
+
+
+@pytest.mark.parametrize("kind", ["b_over_s", "s_from_u2", "kappa_shift"])
+def test_planted_normalisation_mistakes_are_caught(kind):
+    """Each plausible misreading of the normalisation, planted in a copy of
+    the oracle's input step, fails the pins above."""
+    m = _mutant(kind)
+    assert _normalisation_failures(m, _mutant_forward(m)) != []
