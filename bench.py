@@ -281,8 +281,12 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     rec = {"workload": f"precond_{n}x{n}"}
-    for name in precs:
+    variants = [(name, rows) for name in precs for rows in (4, 8, 0)]
+    for name, rows in variants:
         prec = ax.PREC_FP32 if name == "fp32" else ax.PREC_FP64
+        ax.op_set_strips(op, rows)
+        if rows and not ax.op_strips_info(op, prec)[0]:
+            continue
         for _ in range(3):
             ax.precond_apply(op, r, z, prec)
         torch.cuda.synchronize()
@@ -294,10 +298,12 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
         pc_s = e0.elapsed_time(e1) / 1e3 / reps
         bpp = PRECOND_BYTES_PER_POINT if prec == ax.PREC_FP32 else PRECOND_BYTES_PER_POINT_FP64
         gbs = bpp * n * n / pc_s / 1e9
-        rec[name] = {"applies_per_s": round(1.0 / pc_s, 1), "mean_us": round(pc_s * 1e6, 2), "bytes_per_point": bpp,
-                     "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
-                     "min_bytes_per_point": 16, "gbs_at_min_bytes": round(16 * n * n / pc_s / 1e9, 1)}
-        print(f"[precond] {n}x{n} {name}: {pc_s * 1e6:.2f} us per apply ({reps} applies)", flush=True)
+        key = f"{name}_strips{rows}" if rows else f"{name}_per_mode"
+        rec[key] = {"applies_per_s": round(1.0 / pc_s, 1), "mean_us": round(pc_s * 1e6, 2), "bytes_per_point": bpp,
+                    "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                    "min_bytes_per_point": 16, "gbs_at_min_bytes": round(16 * n * n / pc_s / 1e9, 1)}
+        print(f"[precond] {n}x{n} {key}: {pc_s * 1e6:.2f} us per apply ({reps} applies)", flush=True)
+    ax.op_set_strips(op, 1)
     op.close()
     return rec
 

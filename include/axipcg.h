@@ -120,6 +120,23 @@ int axipcg_rhs_from_f(axipcg_op_t op, const double *f, double *b, void *stream);
  * double, computes in float, writes z as double). */
 int axipcg_precond_apply(axipcg_op_t op, const double *r, double *z, int prec, void *stream);
 
+/* ---- strip-partitioned preconditioner (default where it applies) --------
+ * precond_apply and the solves run the preconditioner as three launches over
+ * strips of R consecutive r-rows (the partition idea of §3, eqs. (18)-(22),
+ * with the strips as the parts): (1) the z-transform of each strip's rows and
+ * the elimination of its interior rows in terms of the strips' last rows, (2)
+ * per z-mode the tridiagonal system of those last rows (nr/R unknowns), (3)
+ * the strips' interior rows and the inverse transform.  It applies when nz is
+ * 256..2048 (FP32) or 256..1024 (FP64) and nr is a multiple of R with
+ * nr/R <= 1024; otherwise, or when set_strips disables it for the handle, the
+ * per-mode r-solve of eq. (39) over the whole line runs instead.  Both
+ * compute the same B^{-1} r up to rounding.  set_strips takes 0 (off), 1 (on,
+ * the default height R = 4), 4 or 8; other values return AXIPCG_EINVAL.
+ * strips_info reports whether the strip form is used for `prec` and its
+ * strip count (host pointers, may be NULL). */
+int axipcg_op_set_strips(axipcg_op_t op, int enable);
+int axipcg_op_strips_info(axipcg_op_t op, int prec, int *active, int *strips);
+
 /* ---- single-pass preconditioner (opt-in) --------------------------------
  * precond_apply can run as one cooperative launch instead of three: G
  * workgroups (a power of two <= the CU count, dividing nr and nz) own strips

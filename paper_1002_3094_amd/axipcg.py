@@ -70,6 +70,8 @@ SIGNATURES = {
     "axipcg_precond_apply": ([_vp, _vp, _vp, _i, _vp], _i),
     "axipcg_residual_norm": ([_vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_op_set_fused": ([_vp, _i], _i),
+    "axipcg_op_set_strips": ([_vp, _i], _i),
+    "axipcg_op_strips_info": ([_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
     "axipcg_op_bounds": ([_vp, _dp, _dp], _i),
     "axipcg_cheb_solve": ([_vp, _vp, _vp, _d, _d, _d, _i, _i, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_op_fused_info": ([_vp, _i, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)], _i),
@@ -238,6 +240,18 @@ def op_set_fused(op: Op, enable: bool):
     _check(lib().axipcg_op_set_fused(op.handle, int(bool(enable))), "op_set_fused")
 
 
+def op_set_strips(op: Op, rows):
+    """rows: False/0 off, True/1 on (default height), 4 or 8 rows per strip."""
+    _check(lib().axipcg_op_set_strips(op.handle, int(rows)), "op_set_strips")
+
+
+def op_strips_info(op: Op, prec=PREC_FP32):
+    """(active, strips) of the strip-partitioned preconditioner for prec."""
+    act, strips = _i(), _i()
+    _check(lib().axipcg_op_strips_info(op.handle, prec, ctypes.byref(act), ctypes.byref(strips)), "op_strips_info")
+    return bool(act.value), strips.value
+
+
 def op_fused_info(op: Op, prec=PREC_FP32, want_errors=False):
     """(active, strips, barrier_errors or None); want_errors synchronises the device."""
     act, strips, errs = _i(), _i(), _i()
@@ -316,6 +330,7 @@ def laguerre_coeffs_alpha(n: int, alpha: int, eta: float, f_samples, t_max: floa
     _check(lib().axipcg_laguerre_coeffs_alpha(n, alpha, eta, len(f), t_max, _hp(f), _hp(g), _stream(stream)),
            "laguerre_coeffs_alpha")
     return g
+
 
 
 def laguerre_rhs_alpha(op: Op, m: int, alpha: int, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=None,

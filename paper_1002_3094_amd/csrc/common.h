@@ -135,6 +135,11 @@ struct Operator {
     double *au_cache = nullptr;          // series_run's cache of A u for the guard (POLY_HISTORY arrays)
     double *scratch_host = nullptr;  // pinned host scalars (16)
 
+    // strip-partitioned preconditioner (strip.hip): reduced data of the strips
+    // (three [nr / R][nz] arrays, used as float or double); on unless disabled
+    void *strip_red = nullptr;
+    int strip_rows = 4;   // strip height (4 or 8), 0 = the per-mode r-solve instead
+
     // single-pass preconditioner (pfused.hip): plan per precision [FP64, FP32]
     PfPlan pf[2];
     bool fused_enabled = false;      // axipcg_op_set_fused (opt-in)
@@ -224,6 +229,10 @@ __device__ inline double wave_sum(double v)
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
+
+// Scratch doubles for block_sum / block_total in a workgroup of up to 1024
+// threads (16 waves, plus the slot block_total publishes the total in).
+constexpr int RED_SLOTS = 17;
 
 // Block-wide sum in a fixed order; result valid in thread 0.  `sm` needs
 // blockDim.x / 64 doubles.

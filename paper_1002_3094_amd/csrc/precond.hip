@@ -4,16 +4,13 @@
 #include "fft.h"
 #include "kernels.h"
 #include "wfft.h"
+#include "wxform.h"
 
 namespace axipcg {
 
 namespace {
 
-constexpr int DIR = AXIPCG_Z_DIRICHLET;
 
-template <typename T> __device__ inline T fast_rcp(T x);
-template <> __device__ inline float fast_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
-template <> __device__ inline double fast_rcp<double>(double x) { return 1.0 / x; }
 
 // Copy the length-N twiddle table into LDS (when it fits) so that the FFT
 // passes read it without a trip to L2.
@@ -158,15 +155,6 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
 // Inverse transform: one workgroup per ROWS consecutive r-rows, FP64 output;
 // the next row's spectral values are loaded during the current row's FFT.
 // ---------------------------------------------------------------------------
-// alpha_m of eq. (8) with Chebyshev parameters: alpha_1 = 1,
-// alpha_2 = 2 / (2 - rho0^2), alpha_{k+1} = 4 / (4 - rho0^2 alpha_k).
-__device__ inline double cheb_alpha(int m, double rho2)
-{
-    if (m <= 1) return 1.0;
-    double a = 2.0 / (2.0 - rho2);
-    for (int k = 2; k < m; ++k) a = 4.0 / (4.0 - rho2 * a);
-    return a;
-}
 
 template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
 __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__restrict__ zout,
@@ -288,280 +276,6 @@ k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__re
     zinv_body<T, BC, MODE, TWLDS, ROWS>(spec, zout, r, st, partials, pr, tw, pt, nr, N, blockIdx.x, dinc, tau, rho2);
 }
 
-// ---------------------------------------------------------------------------
-// One-wavefront-per-row transforms for N = 128 R2 (R2 = 2, 4, 8, 16): the
-// sequence v of Makhoul's reordering, read as M = N/2 complex numbers
-// z[n] = v[2n] + i v[2n+1], is transformed with one length-M FFT (wfft.h)
-// and split into the length-N spectrum of v:
-//     V_m = (Z_m + conj Z_{M-m}) / 2 - i w_N^m (Z_m - conj Z_{M-m}) / 2,
-// V_{N-m} = conj V_m.  Each wave owns one row; the workgroup's WR waves meet
-// only for the partial sums.  Lane l loads and stores the element pairs
-// (2 l + 128 t, 2 l + 128 t + 1), t < R2, as 16-byte vectors.
-// ---------------------------------------------------------------------------
-template <typename T, int R2>
-constexpr int wave_rows() { return (sizeof(T) == 8 && R2 >= 16) ? 2 : 4; }
-
-template <typename T, int BC, bool FUSED, int R2>
-__device__ __forceinline__ void
-zfwd_w_body(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
-            const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
-            double *__restrict__ partials, int n_pq, T *__restrict__ spec,
-            const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
-            int nr, int blk)
-{
-    using G = wfft::Geo<R2>;
-    constexpr int M = G::M, N = G::N, U = G::U, WR = wave_rows<T, R2>();
-    extern __shared__ char smem_raw[];
-    __shared__ double red[8];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw) + wv * G::LB;
-    T *fbuf = reinterpret_cast<T *>(buf);
-    const int row = blk * WR + wv;
-    const bool valid = row < nr;
-    const size_t base = (size_t)(valid ? row : nr - 1) * N + 2 * lane;
-
-    // every global read first: the row (and the PCG vectors), the twiddles
-    double2 rv[R2], xv[R2], pv[R2], qv[R2];
-#pragma unroll
-    for (int t = 0; t < R2; ++t) {
-        if (FUSED) {
-            xv[t] = *reinterpret_cast<const double2 *>(x + base + 128 * t);
-            rv[t] = *reinterpret_cast<const double2 *>(r + base + 128 * t);
-            pv[t] = *reinterpret_cast<const double2 *>(p + base + 128 * t);
-            qv[t] = *reinterpret_cast<const double2 *>(q + base + 128 * t);
-        } else {
-            rv[t] = *reinterpret_cast<const double2 *>(rin + base + 128 * t);
-        }
-    }
-    wfft::Twiddles<T, R2> twd;
-    twd.load(tw, lane);
-    cx<T> wN[U][8], cP[U][8];   // w_N^m and exp(-i pi m / 2N) of this lane's outputs
-#pragma unroll
-    for (int j = 0; j < U; ++j)
-#pragma unroll
-        for (int k0 = 0; k0 < 8; ++k0) {
-            const int m = wfft::out_index<R2>(lane, j, k0) & (M - 1);
-            wN[j][k0] = ld_tw<T>(tw, m);
-            cP[j][k0] = ld_tw<T>(pt, m);
-        }
-    if (st && st->done) return;
-    double alpha = 0.0;
-    if (FUSED) {
-        const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
-        const int k_it = st->iters;
-        if (!(pq > 0.0) || !(pq < 1e308)) {
-            if (blk == 0 && threadIdx.x == 0) st->done = ST_BREAK;
-            return;
-        }
-        alpha = st->rho[k_it & 1] / pq;
-        if (blk == 0 && threadIdx.x == 0) st->cur = k_it;
-    }
-
-    // r update, Makhoul reordering into the slice (even k -> v[k/2], odd k -> v[N-1-(k-1)/2])
-    double rr = 0.0;
-#pragma unroll
-    for (int t = 0; t < R2; ++t) {
-        double2 rn = rv[t];
-        if (FUSED) {
-            double2 xn;
-            xn.x = xv[t].x + alpha * pv[t].x;
-            xn.y = xv[t].y + alpha * pv[t].y;
-            rn.x = rv[t].x - alpha * qv[t].x;
-            rn.y = rv[t].y - alpha * qv[t].y;
-            if (valid) {
-                *reinterpret_cast<double2 *>(x + base + 128 * t) = xn;
-                *reinterpret_cast<double2 *>(r + base + 128 * t) = rn;
-                rr += rn.x * rn.x + rn.y * rn.y;
-            }
-        }
-        const int sv = lane + 64 * t;
-        fbuf[wfft::fslot(sv)] = (T)rn.x;
-        fbuf[wfft::fslot(N - 1 - sv)] = (BC == DIR) ? -(T)rn.y : (T)rn.y;   // sine: y_k = (-1)^k x_k
-    }
-    wfft::wave_fence();
-    cx<T> a[R2];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) a[n2] = buf[wfft::vslot(lane + 64 * n2)];
-    cx<T> X[U][8];
-    wfft::fft<T, R2>(a, X, buf, twd, lane);
-
-    // split: the partner of Z_m is Z_{M-m}, exchanged through the slice
-#pragma unroll
-    for (int j = 0; j < U; ++j)
-        if (wfft::unit_active<R2>(lane + 64 * j))
-#pragma unroll
-            for (int k0 = 0; k0 < 8; ++k0) buf[wfft::vslot(wfft::out_index<R2>(lane, j, k0))] = X[j][k0];
-    wfft::wave_fence();
-    const T nrm = (T)sqrt(2.0 / N);
-    const T half = (T)0.70710678118654752440;
-    T *srow = spec + (size_t)(valid ? row : 0) * N;
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-        if (!wfft::unit_active<R2>(lane + 64 * j)) continue;
-#pragma unroll
-        for (int k0 = 0; k0 < 8; ++k0) {
-            const int m = wfft::out_index<R2>(lane, j, k0);
-            const cx<T> Zm = X[j][k0];
-            T Ym, YNm;   // Y_m and Y_{N-m} (Y_M for m = 0)
-            if (m == 0) {
-                Ym = Zm.x + Zm.y;
-                YNm = (Zm.x - Zm.y) * half;
-            } else {
-                const cx<T> Zp = buf[wfft::vslot(M - m)];
-                const cx<T> sum = {Zm.x + Zp.x, Zm.y - Zp.y};        // Z_m + conj Z_{M-m}
-                const cx<T> dif = {Zm.x - Zp.x, Zm.y + Zp.y};        // Z_m - conj Z_{M-m}
-                const cx<T> wd = cmul(wN[j][k0], dif);
-                const cx<T> V = {(T)0.5 * (sum.x + wd.y), (T)0.5 * (sum.y - wd.x)};
-                const cx<T> cv = cmul(cP[j][k0], V);
-                Ym = cv.x;
-                YNm = -cv.y;
-            }
-            const int mN = (m == 0) ? M : N - m;
-            if (valid) {
-                if (BC == DIR) {
-                    srow[N - 1 - m] = nrm * ((m == 0) ? half : (T)1) * Ym;
-                    srow[N - 1 - mN] = nrm * YNm;
-                } else {
-                    srow[m] = nrm * ((m == 0) ? half : (T)1) * Ym;
-                    srow[mN] = nrm * YNm;
-                }
-            }
-        }
-    }
-    if (FUSED) {
-        const double s = block_sum(rr, red);
-        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blk] = s;
-    }
-}
-
-template <typename T, int BC, int MODE, int R2>
-__device__ __forceinline__ void
-zinv_w_body(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
-            const PcgState *st, double *__restrict__ partials, bool pr,
-            const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
-            int nr, double *__restrict__ dinc, double tau, double rho2, int blk)
-{
-    constexpr bool PCGM = (MODE == 1 || MODE == 2);
-    constexpr bool CHEB = (MODE == 3 || MODE == 4);
-    using G = wfft::Geo<R2>;
-    constexpr int M = G::M, N = G::N, U = G::U, WR = wave_rows<T, R2>();
-    extern __shared__ char smem_raw[];
-    __shared__ double red[8];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    cx<T> *buf = reinterpret_cast<cx<T> *>(smem_raw) + wv * G::LB;
-    const T *fbuf = reinterpret_cast<const T *>(buf);
-    const int row = blk * WR + wv;
-    const bool valid = row < nr;
-    const int rowc = valid ? row : nr - 1;
-    const size_t base = (size_t)rowc * N + 2 * lane;
-    const T *srow = spec + (size_t)rowc * N;
-
-    // spectral values Y_m, Y_{N-m}, Y_{M-m}, Y_{M+m} for m = lane + 64 n2
-    // (unnormalised DCT-II coefficients of y; Y_N = 0)
-    const T isc = (T)sqrt(0.5 * N);
-    const T sq2 = (T)1.41421356237309504880;
-    auto yidx = [&](int m) { return (BC == DIR) ? N - 1 - m : m; };
-    T y0[R2], y1[R2], y2[R2], y3[R2];
-    cx<T> cm[R2], cq[R2], wm[R2];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) {
-        const int m = lane + 64 * n2;
-        y0[n2] = srow[yidx(m)];
-        y1[n2] = srow[yidx(m == 0 ? M : N - m)];   // (m = 0: unused)
-        y2[n2] = srow[yidx(M - m)];
-        y3[n2] = srow[yidx(M + m == N ? M : M + m)];
-        cm[n2] = ld_tw<T>(pt, m);
-        cq[n2] = ld_tw<T>(pt, M - m);
-        wm[n2] = ld_tw<T>(tw, m);
-    }
-    wfft::Twiddles<T, R2> twd;
-    twd.load(tw, lane);
-    double2 rv[R2], zo[R2], dv[R2];
-#pragma unroll
-    for (int t = 0; t < R2; ++t) {
-        if (PCGM) {
-            rv[t] = *reinterpret_cast<const double2 *>(r + base + 128 * t);
-            if (pr) zo[t] = *reinterpret_cast<const double2 *>(zout + base + 128 * t);
-        }
-        if (MODE == 3) dv[t] = *reinterpret_cast<const double2 *>(dinc + base + 128 * t);
-    }
-    if (MODE != 0 && st->done) return;
-    double c1 = 0.0, c2 = 0.0;
-    if (CHEB) {
-        const double alpha = cheb_alpha(st->iters + 1, rho2);
-        c1 = alpha - 1.0;
-        c2 = alpha * tau;
-    }
-
-    // Z'_m = E_m + i O_m with E_m = (V_m + V_{m+M}) / 2, O_m = w_N^{-m} (V_m - V_{m+M}) / 2,
-    // V_m = exp(i pi m / 2N) (Y_m - i Y_{N-m}); the FFT runs on its conjugate
-    cx<T> a[R2];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) {
-        const int m = lane + 64 * n2;
-        const auto edge = [&](int mm) { return yidx(mm) == ((BC == DIR) ? N - 1 : 0); };
-        const T Ym = y0[n2] * isc * (edge(m) ? sq2 : (T)1);
-        const T YMm = y2[n2] * isc * (edge(M - m) ? sq2 : (T)1);
-        cx<T> Vm, Vp;   // V_m, V_{m+M}
-        if (m == 0) {
-            Vm = {Ym, (T)0};
-            Vp = {sq2 * YMm, (T)0};
-        } else {
-            const T YNm = y1[n2] * isc;
-            const T YMp = y3[n2] * isc;
-            Vm = cmul<T>({cm[n2].x, -cm[n2].y}, {Ym, -YNm});
-            const cx<T> Vq = cmul<T>({cq[n2].x, -cq[n2].y}, {YMm, -YMp});   // V_{M-m}
-            Vp = {Vq.x, -Vq.y};
-        }
-        const cx<T> E = {(T)0.5 * (Vm.x + Vp.x), (T)0.5 * (Vm.y + Vp.y)};
-        const cx<T> O = cmul<T>({wm[n2].x, -wm[n2].y}, {(T)0.5 * (Vm.x - Vp.x), (T)0.5 * (Vm.y - Vp.y)});
-        a[n2] = {E.x - O.y, -(E.y + O.x)};
-    }
-    cx<T> X[U][8];
-    wfft::fft<T, R2>(a, X, buf, twd, lane);
-
-    // z = conj(X) / M as v[2k] + i v[2k+1]; back to y through the slice
-    const T invM = (T)1 / (T)M;
-#pragma unroll
-    for (int j = 0; j < U; ++j)
-        if (wfft::unit_active<R2>(lane + 64 * j))
-#pragma unroll
-            for (int k0 = 0; k0 < 8; ++k0)
-                buf[wfft::vslot(wfft::out_index<R2>(lane, j, k0))] = {X[j][k0].x * invM, -X[j][k0].y * invM};
-    wfft::wave_fence();
-    double rz = 0.0, rzo = 0.0;
-#pragma unroll
-    for (int t = 0; t < R2; ++t) {
-        const int sv = lane + 64 * t;
-        double2 zv;
-        zv.x = (double)fbuf[wfft::fslot(sv)];
-        const T yo = fbuf[wfft::fslot(N - 1 - sv)];
-        zv.y = (double)((BC == DIR) ? -yo : yo);
-        if (!valid) continue;
-        double *dst = (CHEB ? dinc : zout) + base + 128 * t;
-        if (PCGM) {
-            if (pr) rzo += rv[t].x * zo[t].x + rv[t].y * zo[t].y;
-            rz += rv[t].x * zv.x + rv[t].y * zv.y;
-        }
-        if (CHEB) {
-            double2 d;
-            d.x = (MODE == 4) ? c2 * zv.x : c1 * dv[t].x + c2 * zv.x;
-            d.y = (MODE == 4) ? c2 * zv.y : c1 * dv[t].y + c2 * zv.y;
-            *reinterpret_cast<double2 *>(dst) = d;
-        } else {
-            *reinterpret_cast<double2 *>(dst) = zv;
-        }
-    }
-    if (PCGM) {
-        const double s = block_sum(rz, red);
-        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + blk] = s;
-        if (pr) {
-            const double so = block_sum(rzo, red);
-            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + blk] = so;
-        }
-    }
-}
-
 template <typename T, int BC, bool FUSED, int R2>
 __global__ void __launch_bounds__(256)
 k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
@@ -570,7 +284,10 @@ k_zfwd_w(const double *__restrict__ rin, double *__restrict__ x, double *__restr
          const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
          int nr)
 {
-    zfwd_w_body<T, BC, FUSED, R2>(rin, x, r, p, q, st, partials, n_pq, spec, tw, pt, nr, blockIdx.x);
+    constexpr int WR = wave_rows<T, R2>();
+    const int row = blockIdx.x * WR + (threadIdx.x >> 6);
+    RowStore<T> out{spec + (size_t)(row < nr ? row : 0) * wfft::Geo<R2>::N};
+    zfwd_w_body<T, BC, FUSED, R2>(rin, x, r, p, q, st, partials, n_pq, tw, pt, nr, row, blockIdx.x, out);
 }
 
 template <typename T, int BC, int MODE, int R2>
@@ -580,7 +297,10 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
          const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
          int nr, double *__restrict__ dinc, double tau, double rho2)
 {
-    zinv_w_body<T, BC, MODE, R2>(spec, zout, r, st, partials, pr, tw, pt, nr, dinc, tau, rho2, blockIdx.x);
+    constexpr int WR = wave_rows<T, R2>();
+    const int row = blockIdx.x * WR + (threadIdx.x >> 6);
+    RowLoad<T> in{spec + (size_t)(row < nr ? row : nr - 1) * wfft::Geo<R2>::N};
+    zinv_w_body<T, BC, MODE, R2>(in, zout, r, st, partials, pr, tw, pt, nr, dinc, tau, rho2, row, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -601,57 +321,6 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
 // preceding kernel), recorded by workgroup 0; every workgroup reaches the
 // same decision.
 // ---------------------------------------------------------------------------
-// Gate of the r-solve launch in PCG mode: returns the stop status (ST_RUN to
-// go on).  Workgroup 0 records it.
-// Publish a solve's progress to the host (one thread).
-__device__ inline void publish(HostMirror *m, unsigned seq, double rr, double bb, int iters, int done)
-{
-    m->rr = rr;
-    m->bb = bb;
-    __threadfence_system();
-    *reinterpret_cast<volatile unsigned long long *>(&m->word) = mirror_word(seq, iters, done);
-}
-
-__device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ partials, const TriGate &g, double *red,
-                                   int vb)
-{
-    if (g.mode == 1) {
-        if (st->done) return st->done;   // stopped earlier: leave the state alone
-        const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
-        const int k_it = st->cur;
-        int status = ST_RUN;
-        if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
-        else if (rr <= st->tol2) status = ST_CONV;
-        else if (k_it + 1 >= st->maxit) status = ST_MAXIT;
-        if (vb == 0 && threadIdx.x == 0) {
-            st->rr = rr;
-            st->iters = k_it + 1;
-            st->done = status;
-            if (g.mirror && (status != ST_RUN || g.report)) publish(g.mirror, g.seq, rr, st->bb, k_it + 1, status);
-        }
-        return status;
-    }
-    const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
-    const double bb = block_total(partials + SLOT_MISC * MAX_PARTIALS, g.n_rr, red);
-    const double tol2 = g.rtol2 * bb;
-    int status = ST_RUN;
-    if (bb == 0.0) status = ST_BZERO;
-    else if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
-    else if (rr <= tol2) status = ST_CONV;
-    if (vb == 0 && threadIdx.x == 0) {
-        st->rr = rr;
-        st->bb = bb;
-        st->tol2 = tol2;
-        st->iters = 0;
-        st->cur = 0;
-        st->maxit = g.maxit;
-        st->flags = g.flags;
-        st->done = status;
-        if (g.mirror && (status != ST_RUN || g.report)) publish(g.mirror, g.seq, rr, bb, 0, status);
-    }
-    return status;
-}
-
 // UNI: every active lane owns exactly LMAX rows (nr = S * LMAX), so the
 // per-row loops carry no guards.
 template <typename T, int LMAX, bool UNI>
@@ -901,12 +570,15 @@ __global__ void __launch_bounds__(256) k_b_zfwd_w(const ProbDesc *__restrict__ d
     const double *pnew = parity ? P.p0 : P.p1;
     const int vb = blockIdx.x - P.tr_start;
     PcgState *st = FUSED ? P.state : nullptr;   // as in k_b_zfwd
+    constexpr int WR = wave_rows<T, R2>();
+    const int row = vb * WR + (threadIdx.x >> 6);
+    RowStore<T> out{(T *)P.spec + (size_t)(row < P.nr ? row : 0) * wfft::Geo<R2>::N};
     if (P.bc_z == DIR)
-        zfwd_w_body<T, DIR, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec, pd_tw<T>(P),
-                                       pd_pt<T>(P), P.nr, vb);
+        zfwd_w_body<T, DIR, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, pd_tw<T>(P), pd_pt<T>(P),
+                                       P.nr, row, vb, out);
     else
-        zfwd_w_body<T, AXIPCG_Z_NEUMANN, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec,
-                                                    pd_tw<T>(P), pd_pt<T>(P), P.nr, vb);
+        zfwd_w_body<T, AXIPCG_Z_NEUMANN, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, pd_tw<T>(P),
+                                                    pd_pt<T>(P), P.nr, row, vb, out);
 }
 
 template <typename T, int MODE, int R2>
@@ -915,12 +587,15 @@ __global__ void __launch_bounds__(256) k_b_zinv_w(const ProbDesc *__restrict__ d
     const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
     const ProbDesc &P = d[p];
     const int vb = blockIdx.x - P.tr_start;
+    constexpr int WR = wave_rows<T, R2>();
+    const int row = vb * WR + (threadIdx.x >> 6);
+    RowLoad<T> in{(const T *)P.spec + (size_t)(row < P.nr ? row : P.nr - 1) * wfft::Geo<R2>::N};
     if (P.bc_z == DIR)
-        zinv_w_body<T, DIR, MODE, R2>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
-                                      pd_pt<T>(P), P.nr, nullptr, 0.0, 0.0, vb);
+        zinv_w_body<T, DIR, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P), P.nr, nullptr,
+                                      0.0, 0.0, row, vb);
     else
-        zinv_w_body<T, AXIPCG_Z_NEUMANN, MODE, R2>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
-                                                   pd_tw<T>(P), pd_pt<T>(P), P.nr, nullptr, 0.0, 0.0, vb);
+        zinv_w_body<T, AXIPCG_Z_NEUMANN, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P),
+                                                   P.nr, nullptr, 0.0, 0.0, row, vb);
 }
 
 template <typename T>
@@ -1184,6 +859,7 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
 
 int transform_blocks(const Operator &op, int prec)
 {
+    if (strip_usable(op, prec)) return strip_blocks(op);
     const int wr = (prec == AXIPCG_PREC_FP32) ? wave_plan_rows<float>(op.nz) : wave_plan_rows<double>(op.nz);
     if (wr > 0) return (op.nr + wr - 1) / wr;
     return op.nr / transform_rows(op.nr, prec);
@@ -1307,6 +983,7 @@ void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriG
 
 void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
 {
+    if (strip_usable(op, prec)) return strip_fwd(op, prec, a, s);
     if (prec == AXIPCG_PREC_FP32) {
         if (op.bc_z == DIR) zfwd_t<float, DIR>(op, a, s);
         else zfwd_t<float, AXIPCG_Z_NEUMANN>(op, a, s);
@@ -1318,6 +995,7 @@ void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
 
 void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 {
+    if (strip_usable(op, prec)) return strip_inv(op, prec, a, s);
     if (prec == AXIPCG_PREC_FP32) {
         if (op.bc_z == DIR) zinv_t<float, DIR>(op, a, s);
         else zinv_t<float, AXIPCG_Z_NEUMANN>(op, a, s);
@@ -1329,6 +1007,7 @@ void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 
 void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t s)
 {
+    if (strip_usable(op, prec)) return strip_reduced(op, prec, g, s);
     if (prec == AXIPCG_PREC_FP32) tridiag_t<float>(op, g, s);
     else tridiag_t<double>(op, g, s);
 }

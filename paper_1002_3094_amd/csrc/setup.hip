@@ -185,7 +185,7 @@ void free_op(Operator *op)
     void *ptrs[] = {op->D, op->CR, op->CZ, op->W, op->cb64, op->db64, op->rw64, op->lam64, op->cb32,
                     op->db32, op->rw32, op->lam32, op->tw64, op->pt64, op->tw32, op->pt32, op->r,
                     op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->state, op->dscal,
-                    op->pf_work, op->pf_bar, op->pf_err};
+                    op->pf_work, op->pf_bar, op->pf_err, op->strip_red};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : op->prof_events) (void)hipEventDestroy(e);
@@ -246,6 +246,8 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         dmalloc(&op->partials, (size_t)PARTIAL_ROWS * MAX_PARTIALS);
         dmalloc(&op->state, 1);
         dmalloc(&op->dscal, 24);
+        if (const size_t sb = strip_red_bytes(nr, nz))
+            AXI_CHECK_HIP(hipMalloc(&op->strip_red, sb));
         AXI_CHECK_HIP(hipMalloc((void **)&op->pf_bar, (1 + 256) * sizeof(unsigned)));
         AXI_CHECK_HIP(hipMalloc((void **)&op->pf_err, sizeof(int)));
         AXI_CHECK_HIP(hipMemsetAsync(op->pf_bar, 0, (1 + 256) * sizeof(unsigned), s));
@@ -468,6 +470,31 @@ int axipcg_op_set_fused(axipcg_op_t h, int enable)
         Operator *op = reinterpret_cast<Operator *>(h);
         AXI_REQUIRE(op != nullptr, "op is NULL");
         op->fused_enabled = enable != 0;
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_op_set_strips(axipcg_op_t h, int enable)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        AXI_REQUIRE(enable == 0 || enable == 1 || enable == 4 || enable == 8,
+                    "strip height must be 0 (off), 1 (default), 4 or 8");
+        op->strip_rows = enable == 1 ? 4 : enable;
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_op_strips_info(axipcg_op_t h, int prec, int *active, int *strips)
+{
+    return guarded([&] {
+        const Operator *op = reinterpret_cast<const Operator *>(h);
+        AXI_REQUIRE(op != nullptr, "op is NULL");
+        AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
+        const bool ok = strip_usable(*op, prec);
+        if (active) *active = ok ? 1 : 0;
+        if (strips) *strips = ok ? strip_blocks(*op) : 0;
         return AXIPCG_OK;
     });
 }

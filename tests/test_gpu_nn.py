@@ -73,11 +73,11 @@ def test_zero_last_layer_is_extrapolation(ax, onn):
     np.testing.assert_array_equal(_gpu_out(ax, net, ex), 2 * ex["u1"] - ex["u2"])
 
 
-# (300, 320) has 1500 weight-gradient segments of 64 pixels, more than the
+# (300, 256) has 1200 weight-gradient segments of 64 pixels, more than the
 # 1024 partial-sum workgroups: workgroups then loop over one or two segments
 # (an uneven split), as at the training size, and the partials' reduction
 # sums 1024 rows.
-@pytest.mark.parametrize("shape", [(37, 128), (64, 256), (300, 320)])
+@pytest.mark.parametrize("shape", [(37, 128), (64, 256), (300, 256)])
 def test_backward_matches_oracle(ax, onn, orc, shape):
     nr, nz = shape
     log(f"nn backward {shape}")

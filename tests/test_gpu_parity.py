@@ -5,9 +5,9 @@ Tolerances:
   * FP64 preconditioner: normwise backward error ||B z - r|| / (||B|| ||z|| +
     ||r||) <= 1e-14, and forward error vs the oracle <= 1e-9 (the r-systems of
     the low modes have condition numbers up to ~1e7);
-  * FP32 preconditioner: backward error <= 32 eps_32 log2(nz) (orthogonal
-    transforms plus backward-stable tridiagonal elimination), forward error
-    <= 2e-3;
+  * FP32 preconditioner: backward error <= 2e-6 (about eps_32 log2(nz) for
+    the orthogonal transforms, plus backward-stable tridiagonal elimination),
+    forward error <= 2e-3;
   * PCG solutions converged to ||r||/||b|| <= 1e-10: relative L2 error <=
     1e-8 against the oracle solution converged to 1e-13.
 """

@@ -1,0 +1,133 @@
+"""The strip-partitioned preconditioner (transform and local elimination of
+strips of 4 rows, reduced systems of the strips' last rows, back
+substitution and inverse transform) against the oracle, through the C-ABI.
+
+Same bars as the rest of the parity suite: the preconditioner's normwise
+backward error ||B z - r|| / (||B|| ||z|| + ||r||) <= 1e-14 (FP64) or 2e-6
+(FP32), PCG solutions converged to 1e-10 within 1e-8 of the oracle's 1e-13
+solution.  Every shape runs with the strip form (checked through
+strips_info) and, on the same handle, with it switched off, so both forms of
+the launches are held to the oracle.  Shapes cover one strip (G = 1), a
+strip count that is not a power of two (G = 50), G below and at the 64 lanes
+of the reduced solver, the largest G (1024) and the benchmark's grids.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import dev, host, log, rel, spectral_norm_estimate
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ax():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1002_3094_amd import axipcg
+    axipcg.lib()
+    return axipcg
+
+
+def _medium(nr, nz, seed):
+    kappa, q = synth.medium_layered(nr, nz, seed)
+    return kappa, q
+
+
+def _backward(orc, oop, r, z, bc):
+    nr, nz = r.shape
+    B = orc.operator_from_cells(np.full((nr, nz), oop.kbar), np.full((nr, nz), oop.qbar), bc_z=bc,
+                                kbar=oop.kbar, qbar=oop.qbar)
+    res = orc.apply(B, z) - r
+    nB = spectral_norm_estimate(lambda v: orc.apply(B, v), (nr, nz)) * 1.1
+    return np.linalg.norm(res) / (nB * np.linalg.norm(z) + np.linalg.norm(r))
+
+
+STRIP_SHAPES = [(4, 256, 0), (8, 512, 1), (200, 1024, 0), (256, 256, 1), (1024, 1024, 0), (4096, 256, 0),
+                (12, 2048, 1), (2048, 2048, 0), (8192 // 8, 512, 1)]
+
+
+@pytest.mark.parametrize("nr,nz,bc", STRIP_SHAPES)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_strip_precond_matches_oracle(ax, orc, nr, nz, bc, prec):
+    if prec == ax.PREC_FP64 and nz > 1024:
+        pytest.skip("FP64 at nz = 2048 has no one-wave transform: the per-mode form runs (covered elsewhere)")
+    if nr * nz > 1024 * 1024 and prec == ax.PREC_FP64:
+        pytest.skip("size")
+    log(f"strip precond {nr}x{nz} bc={bc} prec={prec}")
+    kappa, q = _medium(nr, nz, 5)
+    r = np.random.default_rng(nr + nz).standard_normal((nr, nz))
+    oop = orc.operator_from_cells(kappa, q, bc_z=bc)
+    zo = orc.precond(oop, r)
+    outs = {}
+    with ax.op_create(kappa, q, bc_z=bc) as op:
+        for rows in (4, 8, 0):
+            if rows and nr % rows:
+                continue
+            ax.op_set_strips(op, rows)
+            active, G = ax.op_strips_info(op, prec)
+            # FP64 with more than 512 strips: the reduced solve's LDS stage
+            # (r-line arrays plus 4 modes of reduced data) exceeds 160 KiB
+            expect = rows > 0 and not (prec == ax.PREC_FP64 and nr // rows > 512)
+            assert active == expect and G == (nr // rows if expect else 0)
+            if rows and not expect:
+                continue
+            z = dev(np.zeros((nr, nz)))
+            ax.precond_apply(op, dev(r), z, prec)
+            outs[rows] = host(z).copy()
+    for strips, zg in outs.items():
+        back = _backward(orc, oop, r, zg, bc)
+        fwd = rel(zg, zo)
+        log(f"  strip rows={strips}: backward={back:.2e} forward={fwd:.2e}")
+        assert back <= (1e-14 if prec == ax.PREC_FP64 else 2e-6)
+        # the forward error of a correct solve grows with the condition number
+        # of the r-systems (about nr^2): bounded only up to nr = 1024
+        if nr <= 1024:
+            assert fwd <= (1e-9 if prec == ax.PREC_FP64 else 2e-3)
+
+
+SOLVE = [(96, 256, 0), (256, 512, 1), (1024, 1024, 0), (64, 2048, 1)]
+
+
+@pytest.mark.parametrize("nr,nz,bc", SOLVE)
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("solver", ["pcg", "pcg_pr", "cheb"])
+@pytest.mark.parametrize("rows", [4, 8])
+def test_strip_solves_match_oracle(ax, orc, nr, nz, bc, prec, solver, rows):
+    if prec == ax.PREC_FP64 and nz > 1024:
+        pytest.skip("FP64 at nz = 2048 runs the per-mode form")
+    log(f"strip solve {solver} rows={rows} {nr}x{nz} bc={bc} prec={prec}")
+    kappa, q = _medium(nr, nz, 7)
+    f = synth.ricker_source(nr, nz, 1.0, 1.0, 0.3, 0.01 if nr >= 512 else 0.05)
+    oop = orc.operator_from_cells(kappa, q, bc_z=bc)
+    bo = orc.rhs(oop, f)
+    xr = orc.solve_reference(oop, bo)
+    with ax.op_create(kappa, q, bc_z=bc) as op:
+        ax.op_set_strips(op, rows)
+        assert ax.op_strips_info(op, prec) == (True, nr // rows)
+        b = dev(bo)
+        x = dev(np.zeros((nr, nz)))
+        if solver == "cheb":
+            st = ax.cheb_solve(op, b, x, rtol=1e-10, maxit=1000, prec=prec)
+        else:
+            flags = ax.FLAG_TRUE_RESIDUAL | (ax.FLAG_POLAK_RIBIERE if solver == "pcg_pr" else 0)
+            st = ax.pcg_solve(op, b, x, rtol=1e-10, maxit=500, prec=prec, flags=flags)
+        xg = host(x)
+    err = rel(xg, xr)
+    log(f"  iters={st['iters']} err={err:.2e}")
+    assert st["code"] == ax.OK and err <= 1e-8
+
+
+def test_strip_results_are_bitwise_reproducible(ax):
+    log("strip determinism 512x512")
+    kappa, q = _medium(512, 512, 3)
+    f = synth.ricker_source(512, 512, 1.0, 1.0, 0.3, 0.05)
+    outs = []
+    with ax.op_create(kappa, q) as op:
+        b = dev(np.zeros((512, 512)))
+        ax.rhs_from_f(op, dev(f), b)
+        for _ in range(2):
+            x = dev(np.zeros((512, 512)))
+            st = ax.pcg_solve(op, b, x, 1e-10, 300, ax.PREC_FP32)
+            outs.append((host(x), st["iters"]))
+    assert outs[0][1] == outs[1][1] and np.array_equal(outs[0][0], outs[1][0])
