@@ -231,6 +231,17 @@ int axipcg_laguerre_rhs(axipcg_op_t op, double g_m, int src_i, int src_k,
  * (trapezoid rule), into g_host (host double[n]); 0 <= alpha <= 64. */
 int axipcg_laguerre_coeffs_alpha(int n, int alpha, double eta, int nt, double t_max,
                                  const double *f_host, double *g_host, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same as
+ * axipcg_laguerre_coeffs_alpha and the same kernel, with the staged samples
+ * and coefficients in a fixed device array of the library (1 MiB per device,
+ * held until the process ends) instead of per-call hipMalloc'd buffers.  It
+ * calls no hipMalloc, hipFree or other allocating routine.  Limit:
+ * nt + n <= 131072, else AXIPCG_EINVAL.  Synchronises `stream` before
+ * returning.  Every call on one device shares that array: calls that overlap
+ * on one device (two host threads, or two streams) race. */
+int axipcg_laguerre_coeffs_alpha_noalloc(int n, int alpha, double eta, int nt, double t_max,
+                                         const double *f_host, double *g_host, void *stream);
 /* Right-hand side of harmonic m of eq. (35) with alpha:
  *     b = r * (f_m delta_h - c * c_m * sum_{k<m} (m-k) d_k u_k),
  *     c_m = sqrt(m!/(m+alpha)!),  d_k = sqrt((k+alpha)!/k!),

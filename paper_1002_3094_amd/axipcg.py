@@ -83,6 +83,7 @@ SIGNATURES = {
     "axipcg_guess_extrap": ([_vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_guess_poly": ([_vp, _vp, ctypes.POINTER(_vp), _i, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_laguerre_coeffs_alpha": ([_i, _i, _d, _i, _d, _dp, _dp, _vp], _i),
+    "axipcg_laguerre_coeffs_alpha_noalloc": ([_i, _i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs_alpha": ([_vp, _i, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_gather": ([_vp, _vp, _vp, _i, _vp, _vp], _i),
     "axipcg_laguerre_synth": ([_i, _i, _d, _i, _vp, _i, _d, _vp, _vp], _i),
@@ -331,6 +332,14 @@ def laguerre_coeffs_alpha(n: int, alpha: int, eta: float, f_samples, t_max: floa
            "laguerre_coeffs_alpha")
     return g
 
+
+def laguerre_coeffs_alpha_noalloc(n: int, alpha: int, eta: float, f_samples, t_max: float,
+                                  stream=None) -> np.ndarray:
+    f = _host(f_samples)
+    g = np.zeros(n)
+    _check(lib().axipcg_laguerre_coeffs_alpha_noalloc(n, alpha, eta, len(f), t_max, _hp(f), _hp(g),
+                                                      _stream(stream)), "laguerre_coeffs_alpha_noalloc")
+    return g
 
 
 def laguerre_rhs_alpha(op: Op, m: int, alpha: int, g_m: float, src_i: int, src_k: int, S1, S2, b, u_prev=None,

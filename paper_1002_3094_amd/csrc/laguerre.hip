@@ -2,6 +2,7 @@
 // pulse, right-hand sides of the harmonics (alpha = 0 and general integer
 // alpha), receiver samples and the synthesis of time traces.
 #include <cmath>
+#include <mutex>
 
 #include "kernels.h"
 
@@ -216,6 +217,64 @@ extern "C" int axipcg_laguerre_coeffs_alpha(int n, int alpha, double eta, int nt
         } tmp{&d_f, &d_g};
         AXI_CHECK_HIP(hipMalloc((void **)&d_f, sizeof(double) * nt));
         AXI_CHECK_HIP(hipMalloc((void **)&d_g, sizeof(double) * n));
+        AXI_CHECK_HIP(hipMemcpyAsync(d_f, f_host, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_laguerre_coeffs_a, dim3(n), dim3(256), 0, s, d_f, nt, t_max / (nt - 1), eta, alpha, d_g);
+        AXI_CHECK_HIP(hipGetLastError());
+        AXI_CHECK_HIP(hipMemcpyAsync(g_host, d_g, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        AXI_CHECK_HIP(hipStreamSynchronize(s));
+        return AXIPCG_OK;
+    });
+}
+
+// ---- allocation-free variant of axipcg_laguerre_coeffs_alpha ---------------
+// The staged pulse samples and the coefficients live in one file-scope device
+// array instead of two hipMalloc'd buffers.  Each device holds its own copy;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that device (the array's name in host code is a stand-in, not a device
+// address).
+namespace {
+
+constexpr size_t NOALLOC_DOUBLES = size_t(1) << 17;   // 1 MiB per device: nt + n <= 131072
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// Address of `scratch` on the current device, looked up once per device.
+double *scratch_on_current_device()
+{
+    int dev = -1;
+    AXI_CHECK_HIP(hipGetDevice(&dev));
+    AXI_REQUIRE(dev >= 0 && dev < NOALLOC_MAX_DEVICES, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        AXI_CHECK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        AXI_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned NULL for the scratch array");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" int axipcg_laguerre_coeffs_alpha_noalloc(int n, int alpha, double eta, int nt, double t_max,
+                                                    const double *f_host, double *g_host, void *stream)
+{
+    return guarded([&] {
+        AXI_REQUIRE(n >= 1 && n <= 100000, "n must be in [1, 100000]");
+        AXI_REQUIRE(alpha >= 0 && alpha <= 64, "alpha must be in [0, 64]");
+        AXI_REQUIRE(nt >= 3, "nt must be >= 3");
+        AXI_REQUIRE((size_t)nt + (size_t)n <= NOALLOC_DOUBLES,
+                    "nt + n exceeds the 131072 doubles of the allocation-free scratch");
+        AXI_REQUIRE(std::isfinite(eta) && eta > 0 && std::isfinite(t_max) && t_max > 0, "eta, t_max must be > 0");
+        AXI_REQUIRE(f_host && g_host, "NULL argument");
+        for (int j = 0; j < nt; ++j) AXI_REQUIRE(std::isfinite(f_host[j]), "f has non-finite values");
+        hipStream_t s = (hipStream_t)stream;
+        double *d_f = scratch_on_current_device();
+        double *d_g = d_f + nt;
         AXI_CHECK_HIP(hipMemcpyAsync(d_f, f_host, sizeof(double) * nt, hipMemcpyHostToDevice, s));
         hipLaunchKernelGGL(k_laguerre_coeffs_a, dim3(n), dim3(256), 0, s, d_f, nt, t_max / (nt - 1), eta, alpha, d_g);
         AXI_CHECK_HIP(hipGetLastError());
