@@ -73,8 +73,13 @@ def parse():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-experiment pipeline record")
     ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 series record")
     ap.add_argument("--large-harmonics", type=int, default=100, help="timed harmonics of the 2048^2 record")
-    ap.add_argument("--paper-harmonics", type=int, default=200,
-                    help="harmonics timed in the paper-experiment record (the paper used 2000)")
+    ap.add_argument("--paper-harmonics", type=int, default=2000,
+                    help="harmonics of the paper-experiment records (the paper's n = 2000)")
+    ap.add_argument("--no-refinement", action="store_true",
+                    help="skip the paper experiment's grid-refinement record (256^2 .. 2048^2)")
+    ap.add_argument("--strips", type=int, default=1, choices=[0, 1, 4, 8],
+                    help="preconditioner form of the solves: strips of 4 or 8 rows, 1 = the library's "
+                         "default, 0 = the per-mode r-solve over whole lines")
     ap.add_argument("--precond-only", type=int, default=0, metavar="N",
                     help="only time standalone preconditioner applies on an N x N layered medium (FP32 "
                          "then FP64, --steps applies each) and print their rates; the run to profile "
@@ -309,17 +314,19 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
 
 
 def paper_measure(ax, torch, n_harm):
-    """The paper's experiment (§4.3) at 1024^2: the fault stand-in, Neumann in
-    z, alpha = 5, h = 300, the pulse of eq. (40), FP32 preconditioner; a zero
-    initial guess (the paper's), the previous harmonic, and the polynomial
-    extrapolation guard; receiver traces synthesised from the harmonics."""
+    """The paper's experiment (§4.3) at 1024^2 on its node grid in r: the
+    fault stand-in, Neumann in z, alpha = 5, h = 300, the pulse of eq. (40),
+    FP32 preconditioner; a zero initial guess (the paper's), the previous
+    harmonic, and the polynomial extrapolation guard; receiver traces
+    synthesised from the harmonics."""
     import synth
     from paper_1002_3094_amd import series
-    inp = synth.paper_series_inputs(1024, 1024, seed=101)
+    inp = synth.paper_series_inputs(1024, 1024, seed=101, grid="nodes")
     op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"])
     g = ax.laguerre_coeffs_alpha(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
-    rec = {"workload": "laguerre_paper_1024x1024_alpha5_h300", "harmonics": n_harm, "alpha": inp["alpha"],
-           "eta": inp["eta"], "bc_z": "neumann", "receivers": int(len(inp["rec_idx"]))}
+    rec = {"workload": "laguerre_paper_1024x1024_alpha5_h300", "grid": "paper nodes in r (h_r = l/(N - 1/2))",
+           "harmonics": n_harm, "alpha": inp["alpha"], "eta": inp["eta"], "bc_z": "neumann",
+           "receivers": int(len(inp["rec_idx"]))}
     for guess in ("zero", "prev", "poly"):
         s = series.PaperSeries(op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"],
                                inp["rec_idx"])
@@ -330,6 +337,7 @@ def paper_measure(ax, torch, n_harm):
         el = time.perf_counter() - t0
         assert all(c == ax.OK for c in st.status), st.status
         rec[guess] = {"harmonics_per_s": round(n_harm / el, 2), "iters_per_harmonic": round(float(np.mean(st.iters)), 2),
+                      "preconditioner_inversions": int(sum(st.iters)),
                       "us_per_iteration": round(el * 1e6 / max(1, sum(st.iters)), 2)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -339,6 +347,47 @@ def paper_measure(ax, torch, n_harm):
     rec["trace_peak"] = float(tr.abs().max().item())
     op.close()
     return rec
+
+
+def paper_refinement(ax, torch, n_harm, grids=(256, 512, 1024, 2048), length=1.0, r_star=0.25, t_star=0.4):
+    """Table 2 of §4.3 on the stand-in: the paper's experiment (node grid in
+    r, zero guesses, FP32 preconditioner, n_harm harmonics) on N^2 grids of
+    the same medium over a length x length km domain (1 km: 17 to 136 nodes
+    per 67 m wavelength of the 30 Hz pulse in the 2 km/s layer, the paper's
+    range being 35 to 280); the wave field u(t*, r*, z) along the vertical slice
+    r = r* (linear interpolation between the two bracketing r-nodes, then in
+    z onto the coarsest grid's z points), each grid's relative L2 error
+    against the finest, their ratio per halving, and the preconditioner
+    inversions (PCG iterations) per harmonic of each grid."""
+    import synth
+    from paper_1002_3094_amd import series
+    slices, iters = {}, {}
+    z_ref = None
+    for n in grids:
+        inp = synth.paper_series_inputs(n, n, seed=101, grid="nodes", lr=length, lz=length)
+        hr = inp["lr"] / (n + 0.5)
+        i0 = int(r_star / hr - 0.5)
+        w1 = (r_star - (i0 + 0.5) * hr) / hr
+        idx = np.concatenate([i0 * n + np.arange(n), (i0 + 1) * n + np.arange(n)]).astype(np.int64)
+        op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"], bc_z=inp["bc_z"])
+        g = ax.laguerre_coeffs_alpha(n_harm, inp["alpha"], inp["eta"], inp["ft"], inp["t"][-1])
+        s = series.PaperSeries(op, g, inp["alpha"], inp["eta"], inp["src_i"], inp["src_k"], inp["coef"], idx)
+        st = s.run(n_harm, "zero", ax.PREC_FP32)
+        assert all(c == ax.OK for c in st.status), st.status
+        u = s.traces(2, t_star)[:, 1].cpu().numpy()          # u(t*) at the receivers
+        col = (1.0 - w1) * u[:n] + w1 * u[n:]
+        z = synth.cell_centres(n, inp["lz"])
+        if z_ref is None:
+            z_ref = z
+        slices[n] = np.interp(z_ref, z, col)
+        iters[n] = float(np.mean(st.iters))
+        op.close()
+    fine = slices[grids[-1]]
+    errs = [float(np.linalg.norm(slices[n] - fine) / np.linalg.norm(fine)) for n in grids[:-1]]
+    return {"workload": "laguerre_paper_refinement", "grids": list(grids), "harmonics": n_harm,
+            "domain_km": [length, length], "slice": {"r_km": r_star, "t_s": t_star}, "iters_per_harmonic": [round(iters[n], 3) for n in grids],
+            "rel_err_vs_finest": [round(e, 6) for e in errs],
+            "error_ratio_per_halving": [round(e0 / e1, 3) for e0, e1 in zip(errs, errs[1:])]}
 
 
 def batch_measure(ax, torch, prec, reps=3):
@@ -485,6 +534,8 @@ def main():
 
     t_setup = time.perf_counter()
     op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
+    if a.strips != 1:
+        ax.op_set_strips(op, a.strips)
     g = ax.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup
@@ -612,6 +663,8 @@ def main():
         out["batch"] = batch_measure(ax, torch, ax.PREC_FP32)
     if not a.no_paper:
         out["paper_pipeline"] = paper_measure(ax, torch, a.paper_harmonics)
+        if not a.no_refinement:
+            out["paper_refinement"] = paper_refinement(ax, torch, a.paper_harmonics)
     if not a.no_large:
         out["series_2048"] = large_measure(ax, torch, 2048, a.large_harmonics, a.seed)
     if not a.no_cpu_baseline:

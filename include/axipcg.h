@@ -62,6 +62,20 @@ enum {
 
 enum { AXIPCG_Z_DIRICHLET = 0, AXIPCG_Z_NEUMANN = 1 };
 
+/* Grid flag, OR-ed into bc_z of op_create / op_create_faces.  Without it the
+ * grid is cell-centred: h_r = lr/nr, h_z = lz/nz, r_i = (i+1/2) h_r, and the
+ * boundaries lie on cell faces (the Dirichlet face at r = lr half a step from
+ * the last unknown, its conductance doubled).  With it the r-grid is the
+ * paper's (§2.1): nodes at (i - 1/2) h_r, i = 1..N_1, h_r = lr/(N_1 - 1/2),
+ * so the last node lies on r = lr and carries u = 0; the nr = N_1 - 1 unknown
+ * rows give h_r = lr/(nr + 1/2), and the coupling to the boundary node keeps
+ * its plain conductance.  z stays cell-centred (h_z = lz/nz): the paper's
+ * cosine basis of eq. (38) with its one-sided boundary flux is exact for a
+ * Neumann wall at N_2 h_z, which h_z = lz/(N_2 - 1/2) would put half a step
+ * beyond z = lz (first order).  The flag requires AXIPCG_Z_NEUMANN, the
+ * paper's z condition. */
+enum { AXIPCG_GRID_NODES = 0x100 };
+
 /* Arithmetic of the preconditioner.  The outer PCG vectors, dot products,
  * residual recurrence and stop test are FP64 in both cases. */
 enum { AXIPCG_PREC_FP64 = 0, AXIPCG_PREC_FP32 = 1 };
@@ -132,6 +146,9 @@ int axipcg_precond_apply(axipcg_op_t op, const double *r, double *z, int prec, v
  * per-mode r-solve of eq. (39) over the whole line runs instead.  Both
  * compute the same B^{-1} r up to rounding.  set_strips takes 0 (off), 1 (on,
  * the default height R = 4), 4 or 8; other values return AXIPCG_EINVAL.
+ * With the default height, standalone FP32 applies of rows of length 2048
+ * use strips of 8 rows (faster there; the solves keep 4, whose in-loop
+ * kernels need the registers of 4-wave workgroups).
  * strips_info reports whether the strip form is used for `prec` and its
  * strip count (host pointers, may be NULL). */
 int axipcg_op_set_strips(axipcg_op_t op, int enable);

@@ -28,6 +28,12 @@ _lib = None
 
 Z_DIRICHLET = 0
 Z_NEUMANN = 1
+GRID_CELLS = 0   # cell-centred grid (h = l / N), boundaries on faces
+# the paper's r-grid of §2.1 (h_r = l_r / (N_1 - 1/2), the last r-node on r = l_r
+# carrying u = 0); z stays cell-centred, the grid on which the cosine basis of
+# eq. (38) is exact (with h_z = l_z / (N_2 - 1/2) the Neumann wall would sit half
+# a step beyond l_z)
+GRID_NODES = 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _ip = ctypes.POINTER(ctypes.c_int)
@@ -45,17 +51,17 @@ def _load():
     sig = {
         "orc_num_threads": ([], i),
         "orc_face_kappa": ([i, i, _dp, _dp, _dp], None),
-        "orc_coeffs": ([i, i, d, d, i, _dp, _dp, _dp, _dp, _dp, _dp], None),
+        "orc_coeffs": ([i, i, d, d, i, i, _dp, _dp, _dp, _dp, _dp, _dp], None),
         "orc_apply": ([i, i, _dp, _dp, _dp, _dp, _dp], None),
-        "orc_rhs": ([i, i, d, _dp, _dp], None),
+        "orc_rhs": ([i, i, d, d, i, _dp, _dp], None),
         "orc_dot": ([i, i, _dp, _dp], d),
         "orc_fft": ([i, _dp, _dp], None),
         "orc_ztrans_fwd": ([i, i, _dp, _dp], None),
         "orc_ztrans_inv": ([i, i, _dp, _dp], None),
-        "orc_mode_eig": ([i, d, i, _dp], None),
+        "orc_mode_eig": ([i, d, i, i, _dp], None),
         "orc_thomas": ([i, _dp, _dp, _dp, _dp, _dp], None),
-        "orc_precond": ([i, i, d, d, i, d, d, _dp, _dp], None),
-        "orc_pcg": ([i, i, d, d, i, _dp, _dp, _dp, d, d, _dp, _dp, d, i, _ip, _dp], i),
+        "orc_precond": ([i, i, d, d, i, i, d, d, _dp, _dp], None),
+        "orc_pcg": ([i, i, d, d, i, i, _dp, _dp, _dp, d, d, _dp, _dp, d, i, _ip, _dp], i),
         "orc_laguerre_coeffs": ([i, d, i, d, _dp, _dp], None),
         "orc_laguerre_functions": ([i, d, i, _dp, _dp], None),
         "orc_laguerre_psi": ([i, i, d, i, _dp, _dp], None),
@@ -97,14 +103,15 @@ class Operator:
     w: np.ndarray       # [nr][nz]   r q
     kbar: float         # preconditioner constants, §4.2 eq. (37)
     qbar: float
+    grid: int = 0       # GRID_CELLS or GRID_NODES (the paper's grid of §2.1)
 
     @property
     def hr(self):
-        return self.lr / self.nr
+        return self.lr / (self.nr + 0.5) if self.grid == GRID_NODES else self.lr / self.nr
 
     @property
     def hz(self):
-        return self.lz / self.nz
+        return self.lz / self.nz   # both grids: see GRID_NODES
 
     @property
     def r(self):
@@ -120,24 +127,34 @@ def face_kappa(kappa: np.ndarray):
     return kr, kz
 
 
-def operator_from_faces(kr, kz, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, qbar=None) -> Operator:
+def operator_from_faces(kr, kz, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, qbar=None,
+                        grid=GRID_CELLS) -> Operator:
+    """The scheme from kappa at the faces.  ``grid`` = GRID_NODES is the
+    paper's r-grid of §2.1 (nodes at (i - 1/2) h_r with h_r = l_r/(N_1 - 1/2),
+    the last r-node on the boundary r = l_r carrying u = 0, so nr = N_1 - 1
+    unknown rows) with z cell-centred, paired, as in the paper, with Neumann
+    z."""
     kr, kz, q = _c(kr), _c(kz), _c(q)
     nr, nz = q.shape
     assert kr.shape == (nr, nz) and kz.shape == (nr, nz + 1)
+    assert grid == GRID_CELLS or bc_z == Z_NEUMANN, "the node grid is defined with Neumann z"
     cr = np.empty((nr, nz))
     cz = np.empty((nr, nz + 1))
     w = np.empty((nr, nz))
-    _load().orc_coeffs(nr, nz, float(lr), float(lz), int(bc_z), _p(kr), _p(kz), _p(q), _p(cr), _p(cz), _p(w))
+    _load().orc_coeffs(nr, nz, float(lr), float(lz), int(bc_z), int(grid), _p(kr), _p(kz), _p(q), _p(cr), _p(cz),
+                       _p(w))
     if kbar is None:
         kbar = float(kr.mean())
     if qbar is None:
         qbar = float(q.mean())
-    return Operator(nr, nz, float(lr), float(lz), int(bc_z), cr, cz, w, float(kbar), float(qbar))
+    return Operator(nr, nz, float(lr), float(lz), int(bc_z), cr, cz, w, float(kbar), float(qbar), int(grid))
 
 
-def operator_from_cells(kappa, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, qbar=None) -> Operator:
-    """Operator from cell-centre kappa and q.  Preconditioner constants default
-    to the arithmetic means of the cell values (the paper's footnote to
+def operator_from_cells(kappa, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, qbar=None,
+                        grid=GRID_CELLS) -> Operator:
+    """Operator from kappa and q at the unknowns (cell centres, or the
+    paper's nodes with ``grid`` = GRID_NODES).  Preconditioner constants
+    default to the arithmetic means of the values (the paper's footnote to
     eq. (37) uses the mid-range (min+max)/2; CG is invariant to scaling B, so
     this choice only changes iteration counts)."""
     kappa = _c(kappa)
@@ -146,7 +163,7 @@ def operator_from_cells(kappa, q, lr=1.0, lz=1.0, bc_z=Z_DIRICHLET, kbar=None, q
         kbar = float(kappa.mean())
     if qbar is None:
         qbar = float(np.asarray(q).mean())
-    return operator_from_faces(kr, kz, q, lr, lz, bc_z, kbar, qbar)
+    return operator_from_faces(kr, kz, q, lr, lz, bc_z, kbar, qbar, grid)
 
 
 def apply(op: Operator, x) -> np.ndarray:
@@ -160,7 +177,7 @@ def rhs(op: Operator, f) -> np.ndarray:
     """phi = r f, eq. (6)."""
     f = _c(f)
     b = np.empty_like(f)
-    _load().orc_rhs(op.nr, op.nz, op.lr, _p(f), _p(b))
+    _load().orc_rhs(op.nr, op.nz, op.lr, op.lz, op.grid, _p(f), _p(b))
     return b
 
 
@@ -203,9 +220,9 @@ def ztrans_inv(X, bc_z=Z_DIRICHLET) -> np.ndarray:
     return out.reshape(X.shape)
 
 
-def mode_eig(nz, lz=1.0, bc_z=Z_DIRICHLET) -> np.ndarray:
+def mode_eig(nz, lz=1.0, bc_z=Z_DIRICHLET, grid=GRID_CELLS) -> np.ndarray:
     mu = np.empty(nz)
-    _load().orc_mode_eig(nz, float(lz), int(bc_z), _p(mu))
+    _load().orc_mode_eig(nz, float(lz), int(bc_z), int(grid), _p(mu))
     return mu
 
 
@@ -220,7 +237,7 @@ def precond(op: Operator, r) -> np.ndarray:
     """B^{-1} r, §4.2 eqs. (36)-(39)."""
     r = _c(r)
     z = np.empty_like(r)
-    _load().orc_precond(op.nr, op.nz, op.lr, op.lz, op.bc_z, op.kbar, op.qbar, _p(r), _p(z))
+    _load().orc_precond(op.nr, op.nz, op.lr, op.lz, op.bc_z, op.grid, op.kbar, op.qbar, _p(r), _p(z))
     return z
 
 
@@ -230,7 +247,7 @@ def pcg(op: Operator, b, x0=None, rtol=1e-13, maxit=500):
     x = np.zeros_like(b) if x0 is None else _c(x0).copy()
     it = ctypes.c_int(0)
     rel = ctypes.c_double(0.0)
-    st = _load().orc_pcg(op.nr, op.nz, op.lr, op.lz, op.bc_z, _p(op.cr), _p(op.cz), _p(op.w),
+    st = _load().orc_pcg(op.nr, op.nz, op.lr, op.lz, op.bc_z, op.grid, _p(op.cr), _p(op.cz), _p(op.w),
                          op.kbar, op.qbar, _p(b), _p(x), float(rtol), int(maxit),
                          ctypes.byref(it), ctypes.byref(rel))
     return x, int(st), int(it.value), float(rel.value)
@@ -350,7 +367,7 @@ def energy_bounds(op: Operator):
     w * u^2, so gamma1 / gamma2 are the smallest / largest ratio of matching
     terms (faces and cells where B's term is non-zero)."""
     B = operator_from_cells(np.full((op.nr, op.nz), op.kbar), np.full((op.nr, op.nz), op.qbar),
-                            op.lr, op.lz, op.bc_z, op.kbar, op.qbar)
+                            op.lr, op.lz, op.bc_z, op.kbar, op.qbar, op.grid)
     ratios = []
     for a, b in ((op.cr, B.cr), (op.cz, B.cz), (op.w, B.w)):
         m = b > 0

@@ -31,6 +31,28 @@
 
 #define ORC_Z_DIRICHLET 0
 #define ORC_Z_NEUMANN 1
+#define ORC_GRID_CELLS 0
+#define ORC_GRID_NODES 1
+
+/* Grid steps (§2.1).  Cells (the default reading): h_r = l_r / N_r,
+ * h_z = l_z / N_z, unknowns at cell centres (i + 1/2) h, boundaries on faces.
+ * Nodes (the paper's r-grid): nodes at (i - 1/2) h_r, i = 1..N_1, with
+ * h_r = l_r / (N_1 - 1/2), so the last node lies on r = l_r and carries the
+ * Dirichlet value; the nr = N_1 - 1 unknown rows give h_r = l_r/(nr + 1/2).
+ * In z the node grid keeps h_z = l_z / N_z: the paper's cosine basis
+ * (eq. (38)) and its one-sided boundary flux are exact for a Neumann wall at
+ * N_2 h_z, and with h_z = l_z/(N_2 - 1/2) that wall would sit half a step
+ * beyond z = l_z (first order; a test shows it). */
+static void orc_steps(int nr, int nz, double lr, double lz, int grid, double *hr, double *hz)
+{
+    if (grid == ORC_GRID_NODES) {
+        *hr = lr / (nr + 0.5);
+        *hz = lz / nz;
+    } else {
+        *hr = lr / nr;
+        *hz = lz / nz;
+    }
+}
 
 int orc_num_threads(void)
 {
@@ -71,7 +93,7 @@ void orc_face_kappa(int nr, int nz, const double *kc, double *kr, double *kz)
 }
 
 /* Face conductances of the r-weighted scheme (eq. (6): a1 = rbar kappa,
- * a2 = r kappa, w = r q), divided by the squared step so that
+ * a2 = r kappa, w = r q), divided by the squared step (orc_steps) so that
  *   (A y)_c = sum over the faces f of cell c of C_f (y_c - y_nb(f)) + w_c y_c.
  *   cr[i][k]  conductance of r-face i+1/2 : rho_{i+1/2} kappa / h_r^2;
  *             the outer face r = lr (Dirichlet, eq. (2)) is doubled, its
@@ -81,15 +103,19 @@ void orc_face_kappa(int nr, int nz, const double *kc, double *kr, double *kz)
  *             boundary faces are doubled for Dirichlet z and zero for
  *             Neumann z (the paper's d u/dz = 0, eq. (2)).
  *   w[i][k]   = r_i q.                                                       */
-void orc_coeffs(int nr, int nz, double lr, double lz, int bcz,
+void orc_coeffs(int nr, int nz, double lr, double lz, int bcz, int grid,
                 const double *kr, const double *kz, const double *q,
                 double *cr, double *cz, double *w)
 {
-    const double hr = lr / nr, hz = lz / nz;
+    double hr, hz;
+    orc_steps(nr, nz, lr, lz, grid, &hr, &hz);
     for (int i = 0; i < nr; ++i) {
         const double ri = (i + 0.5) * hr;
         const double rho = (i + 1) * hr;
-        const double bnd_r = (i == nr - 1) ? 2.0 : 1.0;
+        /* cells: the outer face lies half a step from the last unknown (ghost
+         * -y, doubled); nodes: the boundary node carrying u = 0 is a full step
+         * away, so the face keeps its plain conductance */
+        const double bnd_r = (i == nr - 1 && grid == ORC_GRID_CELLS) ? 2.0 : 1.0;
         for (int k = 0; k < nz; ++k) {
             cr[(size_t)i * nz + k] = bnd_r * rho * kr[(size_t)i * nz + k] / (hr * hr);
             w[(size_t)i * nz + k] = ri * q[(size_t)i * nz + k];
@@ -130,9 +156,10 @@ void orc_apply(int nr, int nz, const double *cr, const double *cz, const double 
 }
 
 /* Right-hand side of the scheme: phi = r f (eq. (6)). */
-void orc_rhs(int nr, int nz, double lr, const double *f, double *b)
+void orc_rhs(int nr, int nz, double lr, double lz, int grid, const double *f, double *b)
 {
-    const double hr = lr / nr;
+    double hr, hz;
+    orc_steps(nr, nz, lr, lz, grid, &hr, &hz);
     for (int i = 0; i < nr; ++i)
         for (int k = 0; k < nz; ++k)
             b[(size_t)i * nz + k] = (i + 0.5) * hr * f[(size_t)i * nz + k];
@@ -250,9 +277,10 @@ void orc_ztrans_inv(int n, int bcz, const double *X, double *x)
  * sign convention (the paper's "+4 a2/h^2 sin^2" term inside Lambda_r + ... - d
  * has the opposite sign of the eigenvalue of Lambda_z; this oracle takes the
  * eigenvalue of the operator itself). */
-void orc_mode_eig(int nz, double lz, int bcz, double *mu)
+void orc_mode_eig(int nz, double lz, int bcz, int grid, double *mu)
 {
-    const double hz = lz / nz;
+    const double hz = lz / nz;   /* both grids (orc_steps) */
+    (void)grid;
     for (int j = 0; j < nz; ++j) {
         const int l = (bcz == ORC_Z_DIRICHLET) ? j + 1 : j;
         const double s = sin(M_PI * l / (2.0 * nz));
@@ -284,13 +312,14 @@ void orc_thomas(int n, const double *a, const double *b, const double *c,
 /* transform each r-row along z (eq. (38)), solve one tridiagonal system in r */
 /* per z-mode (eq. (39)), transform back.                                     */
 /* ------------------------------------------------------------------------ */
-void orc_precond(int nr, int nz, double lr, double lz, int bcz, double kbar, double qbar,
+void orc_precond(int nr, int nz, double lr, double lz, int bcz, int grid, double kbar, double qbar,
                  const double *r, double *z)
 {
-    const double hr = lr / nr;
+    double hr, hz;
+    orc_steps(nr, nz, lr, lz, grid, &hr, &hz);
     double *spec = (double *)malloc(sizeof(double) * (size_t)nr * nz);
     double *mu = (double *)malloc(sizeof(double) * nz);
-    orc_mode_eig(nz, lz, bcz, mu);
+    orc_mode_eig(nz, lz, bcz, grid, mu);
 
     /* step 1: forward transform of each row */
 #pragma omp parallel for schedule(static)
@@ -309,7 +338,8 @@ void orc_precond(int nr, int nz, double lr, double lz, int bcz, double kbar, dou
         for (int j = 0; j < nz; ++j) {
             for (int i = 0; i < nr; ++i) {
                 const double ri = (i + 0.5) * hr;
-                const double cup = (i + 1) * hr * kbar / (hr * hr) * ((i == nr - 1) ? 2.0 : 1.0);
+                const double cup = (i + 1) * hr * kbar / (hr * hr) *
+                                   ((i == nr - 1 && grid == ORC_GRID_CELLS) ? 2.0 : 1.0);
                 const double cdn = (i > 0) ? i * hr * kbar / (hr * hr) : 0.0;
                 a[i] = -cdn;
                 c[i] = (i < nr - 1) ? -cup : 0.0;
@@ -337,7 +367,7 @@ void orc_precond(int nr, int nz, double lr, double lz, int bcz, double kbar, dou
 /* recursively updated residual.  x holds the initial guess on entry.         */
 /* Returns 0 on convergence, 1 if maxit was reached, -1 on breakdown.         */
 /* ------------------------------------------------------------------------ */
-int orc_pcg(int nr, int nz, double lr, double lz, int bcz,
+int orc_pcg(int nr, int nz, double lr, double lz, int bcz, int grid,
             const double *cr, const double *cz, const double *w,
             double kbar, double qbar, const double *b, double *x,
             double rtol, int maxit, int *iters, double *relres)
@@ -359,7 +389,7 @@ int orc_pcg(int nr, int nz, double lr, double lz, int bcz,
         free(r); free(zv); free(p); free(q);
         return 0;
     }
-    orc_precond(nr, nz, lr, lz, bcz, kbar, qbar, r, zv);
+    orc_precond(nr, nz, lr, lz, bcz, grid, kbar, qbar, r, zv);
     memcpy(p, zv, sizeof(double) * n);
     double rho = orc_dot(nr, nz, r, zv);
     while (rn / bn > rtol && it < maxit) {
@@ -371,7 +401,7 @@ int orc_pcg(int nr, int nz, double lr, double lz, int bcz,
         rn = sqrt(orc_dot(nr, nz, r, r));
         ++it;
         if (rn / bn <= rtol) break;
-        orc_precond(nr, nz, lr, lz, bcz, kbar, qbar, r, zv);
+        orc_precond(nr, nz, lr, lz, bcz, grid, kbar, qbar, r, zv);
         const double rho1 = orc_dot(nr, nz, r, zv);
         const double beta = rho1 / rho;
         rho = rho1;

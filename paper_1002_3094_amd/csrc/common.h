@@ -97,6 +97,7 @@ struct PfPlan {
 
 struct Operator {
     int nr = 0, nz = 0, bc_z = 0;
+    bool nodes = false;              // the paper's node grid (AXIPCG_GRID_NODES)
     double lr = 0, lz = 0, hr = 0, hz = 0;
     double kbar = 0, qbar = 0;
     double gamma1 = 0, gamma2 = 0;   // energy-equivalence bounds of B^{-1} A (eq. (10))

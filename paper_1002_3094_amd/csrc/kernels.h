@@ -63,15 +63,15 @@ struct ZinvArgs {
 void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s);
 
 // Strip-partitioned form of the same three launches (strip.hip): forward
-// transform + local elimination of strips of rows, the reduced systems of the
-// strips' boundary rows, back substitution + inverse transform.  The
-// launch_* functions above route to it when strip_usable holds.
-bool strip_usable(const Operator &op, int prec);
-int strip_blocks(const Operator &op);
+// transform + local elimination of strips of `rows` rows, the reduced
+// systems of the strips' boundary rows, back substitution + inverse
+// transform.  The launch_* functions above route to it with the handle's
+// strip height when strip_usable holds for it.
+bool strip_usable(const Operator &op, int prec, int rows);
 size_t strip_red_bytes(int nr, int nz);
-void strip_fwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s);
-void strip_reduced(const Operator &op, int prec, const TriGate &g, hipStream_t s);
-void strip_inv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s);
+void strip_fwd(const Operator &op, int prec, int rows, const ZfwdArgs &a, hipStream_t s);
+void strip_reduced(const Operator &op, int prec, int rows, const TriGate &g, hipStream_t s);
+void strip_inv(const Operator &op, int prec, int rows, const ZinvArgs &a, hipStream_t s);
 
 // z = B^{-1} r with three launches (forward, r-solves, inverse).
 void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s);

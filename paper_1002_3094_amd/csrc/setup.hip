@@ -32,14 +32,14 @@ __global__ void k_face_kappa(const double *__restrict__ kc, double *__restrict__
 __global__ void k_coeffs(const double *__restrict__ kr, const double *__restrict__ kz,
                          const double *__restrict__ q, double *__restrict__ D, double *__restrict__ CR,
                          double *__restrict__ CZ, double *__restrict__ W, int nr, int nz, double hr,
-                         double hz, double zb)
+                         double hz, double zb, double rb)
 {
     const size_t n = (size_t)nr * nz;
     const double ihr2 = 1.0 / (hr * hr), ihz2 = 1.0 / (hz * hz);
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
         const double ri = (i + 0.5) * hr;
-        const double up = (i + 1) * hr * kr[e] * ihr2 * (i == nr - 1 ? 2.0 : 1.0);
+        const double up = (i + 1) * hr * kr[e] * ihr2 * (i == nr - 1 ? rb : 1.0);
         const double dn = (i > 0) ? i * hr * kr[e - nz] * ihr2 : 0.0;
         const double *kzr = kz + (size_t)i * (nz + 1);
         const double zd = ri * kzr[k] * ihz2 * (k == 0 ? zb : 1.0);
@@ -71,7 +71,7 @@ __global__ void k_sum2(const double *__restrict__ a, const double *__restrict__ 
 }
 
 // r-line arrays and mode eigenvalues of the preconditioner, FFT tables.
-__global__ void k_tables(Operator op, double kbar, double qbar)
+__global__ void k_tables(Operator op, double kbar, double qbar, double rb)
 {
     const int nr = op.nr, N = op.nz;
     const double hr = op.hr, hz = op.hz;
@@ -79,7 +79,7 @@ __global__ void k_tables(Operator op, double kbar, double qbar)
     const int nthr = gridDim.x * blockDim.x;
     for (int i = tid; i < nr; i += nthr) {
         const double cbi = (i < nr - 1) ? (i + 1) * hr * kbar / (hr * hr) : 0.0;
-        const double up = (i < nr - 1) ? cbi : 2.0 * nr * hr * kbar / (hr * hr);
+        const double up = (i < nr - 1) ? cbi : rb * nr * hr * kbar / (hr * hr);
         const double dn = (i > 0) ? i * hr * kbar / (hr * hr) : 0.0;
         const double ri = (i + 0.5) * hr;
         op.cb64[i] = cbi;
@@ -209,7 +209,11 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
     AXI_REQUIRE(nr >= 2 && nr <= 4096, "nr must be in [2, 4096]");
     AXI_REQUIRE(is_pow2(nz) && nz >= 2 && nz <= 2048, "nz must be a power of two in [2, 2048]");
     AXI_REQUIRE(std::isfinite(lr) && lr > 0 && std::isfinite(lz) && lz > 0, "lr and lz must be positive");
-    AXI_REQUIRE(bc_z == AXIPCG_Z_DIRICHLET || bc_z == AXIPCG_Z_NEUMANN, "bc_z must be 0 or 1");
+    const bool nodes = (bc_z & AXIPCG_GRID_NODES) != 0;
+    bc_z &= ~AXIPCG_GRID_NODES;
+    AXI_REQUIRE(bc_z == AXIPCG_Z_DIRICHLET || bc_z == AXIPCG_Z_NEUMANN,
+                "bc_z must be 0 or 1 (optionally with AXIPCG_GRID_NODES)");
+    AXI_REQUIRE(!nodes || bc_z == AXIPCG_Z_NEUMANN, "the node grid is defined with Neumann z");
     AXI_REQUIRE(q != nullptr, "q is NULL");
     const size_t n = (size_t)nr * nz;
     AXI_REQUIRE(all_finite(q, n), "q has non-finite values");
@@ -234,7 +238,9 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
     if (!op) throw Error{AXIPCG_ENOMEM, "host allocation failed"};
     try {
         op->nr = nr; op->nz = nz; op->bc_z = bc_z; op->lr = lr; op->lz = lz;
-        op->hr = lr / nr; op->hz = lz / nz;
+        op->nodes = nodes;
+        op->hr = nodes ? lr / (nr + 0.5) : lr / nr;
+        op->hz = lz / nz;   // z is cell-centred on both grids
         op->create_stream = s;
         AXI_CHECK_HIP(hipGetDevice(&op->device));
         dmalloc(&op->D, n); dmalloc(&op->CR, n); dmalloc(&op->CZ, n); dmalloc(&op->W, n);
@@ -286,7 +292,7 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
             AXI_CHECK_HIP(hipMemsetAsync(d_kq, 0, 2 * sizeof(double), s));
         }
         hipLaunchKernelGGL(k_coeffs, dim3(blocks), dim3(256), 0, s, d_kr, d_kz, d_q, op->D, op->CR, op->CZ, op->W,
-                           nr, nz, op->hr, op->hz, bc_z == AXIPCG_Z_DIRICHLET ? 2.0 : 0.0);
+                           nr, nz, op->hr, op->hz, bc_z == AXIPCG_Z_DIRICHLET ? 2.0 : 0.0, nodes ? 1.0 : 2.0);
         AXI_CHECK_HIP(hipGetLastError());
         // means of kappa and q (cells) unless given
         AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, d_kq, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -327,7 +333,7 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
             op->gamma2 = g2;
         }
         const int tb = (nr > nz ? nr : nz);
-        hipLaunchKernelGGL(k_tables, dim3((tb + 255) / 256), dim3(256), 0, s, *op, kb, qb);
+        hipLaunchKernelGGL(k_tables, dim3((tb + 255) / 256), dim3(256), 0, s, *op, kb, qb, nodes ? 1.0 : 2.0);
         AXI_CHECK_HIP(hipGetLastError());
         AXI_CHECK_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -492,9 +498,9 @@ int axipcg_op_strips_info(axipcg_op_t h, int prec, int *active, int *strips)
         const Operator *op = reinterpret_cast<const Operator *>(h);
         AXI_REQUIRE(op != nullptr, "op is NULL");
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
-        const bool ok = strip_usable(*op, prec);
+        const bool ok = op->strip_rows > 0 && strip_usable(*op, prec, op->strip_rows);
         if (active) *active = ok ? 1 : 0;
-        if (strips) *strips = ok ? strip_blocks(*op) : 0;
+        if (strips) *strips = ok ? op->nr / op->strip_rows : 0;
         return AXIPCG_OK;
     });
 }

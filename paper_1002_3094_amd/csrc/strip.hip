@@ -349,8 +349,17 @@ k_strip_inv(const T *__restrict__ fprime, const T *__restrict__ red_x, double *_
     if (MODE != 0 && st->done) return;
     extern __shared__ char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
-    const int wv = threadIdx.x >> 6;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int s = blockIdx.x, i0 = s * R;
+    // PCG modes: this wave's r row is loaded first, so that its latency
+    // overlaps the back substitution (where it fits in registers)
+    constexpr bool PRE = (MODE == 1 || MODE == 2) && R2 <= 8;
+    double2 rpre[PRE ? R2 : 1];
+    if constexpr (PRE) {
+#pragma unroll
+        for (int t = 0; t < R2; ++t)
+            rpre[t] = *reinterpret_cast<const double2 *>(r + (size_t)(i0 + wv) * N + 2 * lane + 128 * t);
+    }
     // f' of the interior rows into the tile, 16 bytes per access
     constexpr int VW = 16 / (int)sizeof(T);
     typedef T V __attribute__((ext_vector_type(VW)));
@@ -394,7 +403,7 @@ k_strip_inv(const T *__restrict__ fprime, const T *__restrict__ red_x, double *_
     }
     __syncthreads();
     zinv_w_body<T, BC, MODE, R2>(RowLoad<T>{tile + wv * PITCH}, zout, r, st, partials, pr, tw, pt, nr, dinc, tau,
-                                 rho2, i0 + wv, s);
+                                 rho2, i0 + wv, s, PRE ? rpre : nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -425,10 +434,10 @@ struct RedBufs {
     T *e, *g, *x;
 };
 template <typename T>
-RedBufs<T> red_bufs(const Operator &op)
+RedBufs<T> red_bufs(const Operator &op, int R)
 {
     T *b = static_cast<T *>(op.strip_red);
-    const size_t gn = (size_t)(op.nr / op.strip_rows) * op.nz;
+    const size_t gn = (size_t)(op.nr / R) * op.nz;
     return {b, b + gn, b + 2 * gn};
 }
 
@@ -448,7 +457,7 @@ void allow_lds(const void *fn, size_t bytes, bool &done)
 template <typename T, int BC, int R2, int R>
 void fwd_r(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
-    const RedBufs<T> rb = red_bufs<T>(op);
+    const RedBufs<T> rb = red_bufs<T>(op, R);
     const dim3 grid(op.nr / R), block(64 * R);
     const size_t shm = (size_t)R * wfft::Geo<R2>::LB * sizeof(cx<T>);
     if (a.fused)
@@ -465,7 +474,7 @@ void fwd_r(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 template <typename T, int BC, int R2, int R>
 void inv_r(const Operator &op, const ZinvArgs &a, hipStream_t s)
 {
-    const RedBufs<T> rb = red_bufs<T>(op);
+    const RedBufs<T> rb = red_bufs<T>(op, R);
     const dim3 grid(op.nr / R), block(64 * R);
     const size_t shm = (size_t)R * wfft::Geo<R2>::LB * sizeof(cx<T>);
     const T *fp = (const T *)op.spec;
@@ -490,7 +499,7 @@ template <typename T, int R, int LM>
 void red_launch(const Operator &op, const TriGate &g, hipStream_t s)
 {
     constexpr int MT = red_mt<T>();
-    const RedBufs<T> rb = red_bufs<T>(op);
+    const RedBufs<T> rb = red_bufs<T>(op, R);
     const int G = op.nr / R;
     const size_t shm = strip_red_lds<T, MT>(op.nr, G);
     static bool lds_set = false;
@@ -550,10 +559,10 @@ void inv_rb(const Operator &op, const ZinvArgs &a, hipStream_t s)
 }
 
 template <typename T>
-void fwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
+void fwd_t(const Operator &op, int rows, const ZfwdArgs &a, hipStream_t s)
 {
     const bool dir = op.bc_z == DIR;
-    if (op.strip_rows == 8) {
+    if (rows == 8) {
         if (dir) fwd_rb<T, DIR, 8>(op, a, s);
         else fwd_rb<T, AXIPCG_Z_NEUMANN, 8>(op, a, s);
     } else {
@@ -563,10 +572,10 @@ void fwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 }
 
 template <typename T>
-void inv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
+void inv_t(const Operator &op, int rows, const ZinvArgs &a, hipStream_t s)
 {
     const bool dir = op.bc_z == DIR;
-    if (op.strip_rows == 8) {
+    if (rows == 8) {
         if (dir) inv_rb<T, DIR, 8>(op, a, s);
         else inv_rb<T, AXIPCG_Z_NEUMANN, 8>(op, a, s);
     } else {
@@ -576,9 +585,8 @@ void inv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
 }
 
 template <typename T>
-bool usable_t(const Operator &op)
+bool usable_t(const Operator &op, int R)
 {
-    const int R = op.strip_rows;
     if (R != 4 && R != 8) return false;
     if (strip_r2<T>(op.nz) == 0 || op.nr % R != 0) return false;
     const int G = op.nr / R;
@@ -587,17 +595,15 @@ bool usable_t(const Operator &op)
 
 }  // namespace
 
-// The strip path serves an operator and precision when the one-wave
-// transforms cover nz, the rows split into strips of the handle's height
-// (4 or 8) and the reduced system fits one wavefront's registers (at most
+// The strip path serves an operator and precision with strips of `rows`
+// rows (4 or 8) when the one-wave transforms cover nz, the rows split into
+// such strips and the reduced system fits one wavefront's registers (at most
 // 1024 strips) and its workgroup's LDS.
-bool strip_usable(const Operator &op, int prec)
+bool strip_usable(const Operator &op, int prec, int rows)
 {
     if (!op.strip_red) return false;
-    return prec == AXIPCG_PREC_FP32 ? usable_t<float>(op) : usable_t<double>(op);
+    return prec == AXIPCG_PREC_FP32 ? usable_t<float>(op, rows) : usable_t<double>(op, rows);
 }
-
-int strip_blocks(const Operator &op) { return op.nr / op.strip_rows; }
 
 // Reduced data for strips of 4 rows (the larger of the two heights' needs).
 size_t strip_red_bytes(int nr, int nz)
@@ -605,27 +611,27 @@ size_t strip_red_bytes(int nr, int nz)
     return (nr % 4 == 0) ? 3 * (size_t)(nr / 4) * nz * sizeof(double) : 0;
 }
 
-void strip_fwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
+void strip_fwd(const Operator &op, int prec, int rows, const ZfwdArgs &a, hipStream_t s)
 {
-    if (prec == AXIPCG_PREC_FP32) fwd_t<float>(op, a, s);
-    else fwd_t<double>(op, a, s);
+    if (prec == AXIPCG_PREC_FP32) fwd_t<float>(op, rows, a, s);
+    else fwd_t<double>(op, rows, a, s);
 }
 
-void strip_reduced(const Operator &op, int prec, const TriGate &g, hipStream_t s)
+void strip_reduced(const Operator &op, int prec, int rows, const TriGate &g, hipStream_t s)
 {
     if (prec == AXIPCG_PREC_FP32) {
-        if (op.strip_rows == 8) red_r<float, 8>(op, g, s);
+        if (rows == 8) red_r<float, 8>(op, g, s);
         else red_r<float, 4>(op, g, s);
     } else {
-        if (op.strip_rows == 8) red_r<double, 8>(op, g, s);
+        if (rows == 8) red_r<double, 8>(op, g, s);
         else red_r<double, 4>(op, g, s);
     }
 }
 
-void strip_inv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
+void strip_inv(const Operator &op, int prec, int rows, const ZinvArgs &a, hipStream_t s)
 {
-    if (prec == AXIPCG_PREC_FP32) inv_t<float>(op, a, s);
-    else inv_t<double>(op, a, s);
+    if (prec == AXIPCG_PREC_FP32) inv_t<float>(op, rows, a, s);
+    else inv_t<double>(op, rows, a, s);
 }
 
 }  // namespace axipcg

@@ -199,12 +199,15 @@ zfwd_w_body(const double *__restrict__ rin, double *__restrict__ x, double *__re
 // its LDS slice, so ld may read from that slice); z (or, in the Chebyshev
 // modes, the increment d) is written to global memory.  Every wave of the
 // workgroup calls it (block-wide reductions).
+// `rpre`, when given, holds this lane's r values of the row (the element
+// pairs the body would load, t < R2), already loaded by the caller.
 template <typename T, int BC, int MODE, int R2, typename Load>
 __device__ __forceinline__ void
 zinv_w_body(const Load &ld, double *__restrict__ zout, const double *__restrict__ r,
             const PcgState *st, double *__restrict__ partials, bool pr,
             const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
-            int nr, double *__restrict__ dinc, double tau, double rho2, int row, int blk)
+            int nr, double *__restrict__ dinc, double tau, double rho2, int row, int blk,
+            const double2 *rpre = nullptr)
 {
     constexpr bool PCGM = (MODE == 1 || MODE == 2);
     constexpr bool CHEB = (MODE == 3 || MODE == 4);
@@ -243,7 +246,7 @@ zinv_w_body(const Load &ld, double *__restrict__ zout, const double *__restrict_
 #pragma unroll
     for (int t = 0; t < R2; ++t) {
         if (PCGM) {
-            rv[t] = *reinterpret_cast<const double2 *>(r + base + 128 * t);
+            rv[t] = rpre ? rpre[t] : *reinterpret_cast<const double2 *>(r + base + 128 * t);
             if (pr) zo[t] = *reinterpret_cast<const double2 *>(zout + base + 128 * t);
         }
         if (MODE == 3) dv[t] = *reinterpret_cast<const double2 *>(dinc + base + 128 * t);

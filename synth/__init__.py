@@ -38,6 +38,8 @@ __all__ = [
     "laguerre_series_inputs",
     "gauss_sine_pulse_samples",
     "medium_fault",
+    "medium_fault_smooth",
+    "node_coords",
     "paper_series_inputs",
 ]
 
@@ -65,6 +67,16 @@ class Problem:
     bc_z: int = 0  # 0: Dirichlet at z = 0, lz; 1: Neumann
     seed: int = 0
     name: str = ""
+
+
+def node_coords(n: int, length: float, boundary_unknown: bool) -> np.ndarray:
+    """Unknown positions of the paper's node grid (§2.1): nodes at
+    (i - 1/2) h, i = 1..N, with h = length / (N - 1/2), the last node on the
+    boundary.  ``boundary_unknown`` False (r, Dirichlet at the boundary
+    node): the n unknowns are the first N - 1 = n nodes, h = length/(n + 1/2);
+    True (z, Neumann): all n = N nodes, h = length/(n - 1/2)."""
+    h = length / (n + 0.5) if not boundary_unknown else length / (n - 0.5)
+    return (np.arange(n, dtype=np.float64) + 0.5) * h
 
 
 def _unit_std(g: np.ndarray) -> np.ndarray:
@@ -242,18 +254,47 @@ def medium_fault(nr: int, nz: int, lr: float = 2.0, lz: float = 2.0, seed: int =
     return np.ascontiguousarray(v * np.exp(0.05 * g))
 
 
+def medium_fault_smooth(r, z, seed: int = 0):
+    """The fault stand-in as a function of position (so that grids of every
+    size sample the same medium, for refinement studies): 2.0 km/s above and
+    3.5 km/s below an interface at depth 0.6 km for r < 0.8 km and 0.9 km
+    beyond, both steps tanh-smoothed over 20 m, times exp(0.05 g) with g a sum
+    of six seeded plane waves (wavelengths 0.3-2 km) scaled to unit variance.
+    r, z broadcastable arrays (km); returns V."""
+    rng = np.random.default_rng(seed)
+    step = lambda x: 0.5 * (1.0 + np.tanh(x / 0.02))  # noqa: E731
+    depth = 0.6 + 0.3 * step(r - 0.8)
+    v = 2.0 + 1.5 * step(z - depth)
+    kr = rng.uniform(0.5, 3.0, 6)
+    kz = rng.uniform(0.5, 3.0, 6)
+    ph = rng.uniform(0.0, 2.0 * math.pi, 6)
+    g = sum(np.sin(2.0 * math.pi * (kr[j] * r + kz[j] * z) + ph[j]) for j in range(6)) / math.sqrt(3.0)
+    return v * np.exp(0.05 * g)
+
+
 def paper_series_inputs(nr: int, nz: int, seed: int = 0, eta: float = 300.0, alpha: int = 5, n_rec: int = 16,
-                        lr: float = 2.0, lz: float = 2.0):
+                        lr: float = 2.0, lz: float = 2.0, grid: str = "cells"):
     """Inputs of the paper's Laguerre experiment (§4.3): the fault stand-in
     (kappa = V), density rho = 1 so that q = eta^2/4 and the history
     coefficient is eta^2 (eq. (35)), Neumann in z (free surface, eq. (32)), the
     point source at the origin (cell (0, 0)), the pulse of eq. (40), alpha = 5,
     eta (the paper's h) = 300, and n_rec receivers on the surface row k = 0 at
-    r = (j + 1/2) lr / (2 n_rec) (flat indices i * nz)."""
-    kappa = medium_fault(nr, nz, lr, lz, seed)
+    r = (j + 1/2) lr / (2 n_rec) (flat indices i * nz).
+
+    ``grid`` "nodes": the paper's r-grid (§2.1; bc_z carries the node-grid
+    flag 0x100; z cell-centred) with the medium sampled from
+    ``medium_fault_smooth`` at the unknowns, so that every grid size sees the
+    same medium; "cells" (default):
+    the cell-centred grid with the grid-sampled ``medium_fault``."""
+    if grid == "nodes":
+        r = node_coords(nr, lr, False)[:, None]
+        z = cell_centres(nz, lz)[None, :]
+        kappa = np.ascontiguousarray(medium_fault_smooth(r, z, seed) * np.ones((nr, nz)))
+    else:
+        kappa = medium_fault(nr, nz, lr, lz, seed)
     q = np.full((nr, nz), eta * eta / 4.0)
     coef = np.full((nr, nz), eta * eta)
     t, ft = gauss_sine_pulse_samples()
     ri = np.minimum(((np.arange(n_rec) + 0.5) * nr / (2 * n_rec)).astype(np.int64), nr - 1)
-    return dict(nr=nr, nz=nz, lr=lr, lz=lz, kappa=kappa, q=q, coef=coef, bc_z=1, src_i=0, src_k=0,
-                eta=eta, alpha=alpha, t=t, ft=ft, rec_idx=ri * nz, seed=seed)
+    return dict(nr=nr, nz=nz, lr=lr, lz=lz, kappa=kappa, q=q, coef=coef, bc_z=1 | (0x100 if grid == "nodes" else 0),
+                src_i=0, src_k=0, eta=eta, alpha=alpha, t=t, ft=ft, rec_idx=ri * nz, seed=seed, grid=grid)

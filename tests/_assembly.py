@@ -15,9 +15,19 @@ import numpy as np
 import scipy.sparse as sp
 
 
-def conductances(kr, kz, q, lr, lz, bc_z):
+def steps(nr, nz, lr, lz, grid=0, z_nodes=False):
+    """Grid steps: cells h = l / N; the paper's r-nodes (grid 1)
+    h_r = l_r / (N_1 - 1/2) with N_1 = nr + 1 (the boundary node on r = lr is
+    not an unknown), z cell-centred -- or, with z_nodes, the literal
+    h_z = l_z / (N_2 - 1/2) of the paper's z-grid."""
+    hr = lr / (nr + 0.5) if grid == 1 else lr / nr
+    hz = lz / (nz - 0.5) if z_nodes else lz / nz
+    return hr, hz
+
+
+def conductances(kr, kz, q, lr, lz, bc_z, grid=0):
     nr, nz = q.shape
-    hr, hz = lr / nr, lz / nz
+    hr, hz = steps(nr, nz, lr, lz, grid)
     r = (np.arange(nr) + 0.5) * hr
     rho = (np.arange(nr) + 1.0) * hr
     cr = rho[:, None] * kr / hr**2          # face i+1/2 ; i = nr-1 is r = lr
@@ -26,10 +36,12 @@ def conductances(kr, kz, q, lr, lz, bc_z):
     return cr, cz, w
 
 
-def assemble(kr, kz, q, lr=1.0, lz=1.0, bc_z=0):
-    """Sparse CSR matrix of the r-weighted operator, unknowns ordered i*nz + k."""
+def assemble(kr, kz, q, lr=1.0, lz=1.0, bc_z=0, grid=0):
+    """Sparse CSR matrix of the r-weighted operator, unknowns ordered i*nz + k.
+    On the node grid (grid 1) the outer r-face term couples the last unknown
+    to the boundary node's value 0 one full step away: C y^2, not 2 C y^2."""
     nr, nz = q.shape
-    cr, cz, w = conductances(kr, kz, q, lr, lz, bc_z)
+    cr, cz, w = conductances(kr, kz, q, lr, lz, bc_z, grid)
     idx = lambda i, k: i * nz + k
     rows, cols, vals = [], [], []
     faces_a, faces_b, faces_c = [], [], []
@@ -48,7 +60,8 @@ def assemble(kr, kz, q, lr=1.0, lz=1.0, bc_z=0):
     A = G.T @ sp.diags(np.asarray(faces_c)) @ G
     diag = w.ravel().copy()
     # Dirichlet outer r-face: half-cell flux to the boundary value 0 -> 2 C
-    diag[[idx(nr - 1, k) for k in range(nz)]] += 2.0 * cr[nr - 1, :]
+    # (cells), full-step flux to the boundary node -> C (nodes)
+    diag[[idx(nr - 1, k) for k in range(nz)]] += (1.0 if grid == 1 else 2.0) * cr[nr - 1, :]
     if bc_z == 0:
         diag[[idx(i, 0) for i in range(nr)]] += 2.0 * cz[:, 0]
         diag[[idx(i, nz - 1) for i in range(nr)]] += 2.0 * cz[:, nz]
