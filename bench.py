@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--strips", type=int, default=1, choices=[0, 1, 4, 8],
                     help="preconditioner form of the solves: strips of 4 or 8 rows, 1 = the library's "
                          "default, 0 = the per-mode r-solve over whole lines")
+    ap.add_argument("--fused", type=int, default=0, choices=[0, 1],
+                    help="1: the single-launch preconditioner for FP32 applies and PCG iterations")
     ap.add_argument("--precond-only", type=int, default=0, metavar="N",
                     help="only time standalone preconditioner applies on an N x N layered medium (FP32 "
                          "then FP64, --steps applies each) and print their rates; the run to profile "
@@ -286,11 +288,14 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     rec = {"workload": f"precond_{n}x{n}"}
-    variants = [(name, rows) for name in precs for rows in (4, 8, 0)]
-    for name, rows in variants:
+    variants = [(name, rows, False) for name in precs for rows in (4, 8, 0)] + [("fp32", 4, True)]
+    for name, rows, one in variants:
         prec = ax.PREC_FP32 if name == "fp32" else ax.PREC_FP64
         ax.op_set_strips(op, rows)
+        ax.op_set_fused(op, one)
         if rows and not ax.op_strips_info(op, prec)[0]:
+            continue
+        if one and not ax.op_fused_info(op, ax.FUSED_APPLY)[0]:
             continue
         for _ in range(3):
             ax.precond_apply(op, r, z, prec)
@@ -303,12 +308,13 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
         pc_s = e0.elapsed_time(e1) / 1e3 / reps
         bpp = PRECOND_BYTES_PER_POINT if prec == ax.PREC_FP32 else PRECOND_BYTES_PER_POINT_FP64
         gbs = bpp * n * n / pc_s / 1e9
-        key = f"{name}_strips{rows}" if rows else f"{name}_per_mode"
+        key = f"{name}_single_launch" if one else (f"{name}_strips{rows}" if rows else f"{name}_per_mode")
         rec[key] = {"applies_per_s": round(1.0 / pc_s, 1), "mean_us": round(pc_s * 1e6, 2), "bytes_per_point": bpp,
                     "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
                     "min_bytes_per_point": 16, "gbs_at_min_bytes": round(16 * n * n / pc_s / 1e9, 1)}
         print(f"[precond] {n}x{n} {key}: {pc_s * 1e6:.2f} us per apply ({reps} applies)", flush=True)
     ax.op_set_strips(op, 1)
+    ax.op_set_fused(op, False)
     op.close()
     return rec
 
@@ -536,6 +542,8 @@ def main():
     op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
     if a.strips != 1:
         ax.op_set_strips(op, a.strips)
+    if a.fused:
+        ax.op_set_fused(op, True)
     g = ax.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t_setup

@@ -146,27 +146,34 @@ int axipcg_precond_apply(axipcg_op_t op, const double *r, double *z, int prec, v
  * per-mode r-solve of eq. (39) over the whole line runs instead.  Both
  * compute the same B^{-1} r up to rounding.  set_strips takes 0 (off), 1 (on,
  * the default height R = 4), 4 or 8; other values return AXIPCG_EINVAL.
- * With the default height, standalone FP32 applies of rows of length 2048
- * use strips of 8 rows (faster there; the solves keep 4, whose in-loop
- * kernels need the registers of 4-wave workgroups).
+ * Standalone FP32 applies of rows of length 2048 use strips of 8 rows
+ * (faster there), and the solves' FP32 launches at that length use strips of
+ * 4 whatever the height (their in-loop kernels need the registers of 4-wave
+ * workgroups); strips_info reports the solves' strips.
  * strips_info reports whether the strip form is used for `prec` and its
  * strip count (host pointers, may be NULL). */
 int axipcg_op_set_strips(axipcg_op_t op, int enable);
 int axipcg_op_strips_info(axipcg_op_t op, int prec, int *active, int *strips);
 
-/* ---- single-pass preconditioner (opt-in) --------------------------------
- * precond_apply can run as one cooperative launch instead of three: G
- * workgroups (a power of two <= the CU count, dividing nr and nz) own strips
- * of R = nr / G in {2, 4, 8, 16} rows, transform and eliminate them in LDS,
- * and exchange only two reduced equations per strip and mode (the partition
- * idea of §3 across workgroups), with two grid barriers.  Both forms compute
- * the same B^{-1} r up to rounding.  On MI355X at 1024^2 the single pass is
- * slower (one workgroup per CU hides less latency than four), so it is off
- * unless set_fused enables it for the handle; fused_info reports whether it
- * is used for `prec`, its strip count and (synchronising the device) whether
- * a grid barrier ever gave up (host pointers, may be NULL). */
+/* ---- single-launch preconditioner (opt-in) -------------------------------
+ * The strip form in one cooperative launch: the three phases separated by
+ * two grid barriers, the strips' forward-eliminated spectra kept in LDS
+ * between the phases (only three values per strip and mode cross
+ * workgroups), for FP32.  set_fused(op, 1) enables it for the handle's
+ * standalone FP32 applies (strips of 8 rows for nz = 2048, else 4) and for
+ * the iterations of its FP32 PCG solves (strips of 4; the x, r update, the
+ * stop test and the r.z partials in the same launch, after the SpMV), where
+ * every strip's workgroup fits the chip at once and nz is 256..2048; the
+ * three launches run otherwise.  Barriers are numbered from a per-handle
+ * launch counter, and every wait is bounded: a barrier that gives up fills
+ * the strip's output with NaN, marks a PCG solve broken down and sets the
+ * handle's error word.  fused_info(op, kind, ...) reports for kind
+ * AXIPCG_FUSED_APPLY (0) or AXIPCG_FUSED_PCG (1) whether the single launch
+ * is used and its strip count, and (synchronising the device) whether a
+ * barrier ever gave up (host pointers, may be NULL). */
+enum { AXIPCG_FUSED_APPLY = 0, AXIPCG_FUSED_PCG = 1 };
 int axipcg_op_set_fused(axipcg_op_t op, int enable);
-int axipcg_op_fused_info(axipcg_op_t op, int prec, int *active, int *strips, int *barrier_errors);
+int axipcg_op_fused_info(axipcg_op_t op, int kind, int *active, int *strips, int *barrier_errors);
 
 /* out_host[0] = ||b - A x||_2, out_host[1] = ||b||_2 (host double[2]).
  * b, x device.  Synchronises the stream. */

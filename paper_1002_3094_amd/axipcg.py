@@ -254,10 +254,15 @@ def op_strips_info(op: Op, prec=PREC_FP32):
     return bool(act.value), strips.value
 
 
-def op_fused_info(op: Op, prec=PREC_FP32, want_errors=False):
-    """(active, strips, barrier_errors or None); want_errors synchronises the device."""
+FUSED_APPLY, FUSED_PCG = 0, 1
+
+
+def op_fused_info(op: Op, kind=FUSED_APPLY, want_errors=False):
+    """(active, strips, barrier_errors or None) of the single-launch form for
+    standalone FP32 applies (kind 0) or FP32 PCG iterations (kind 1);
+    want_errors synchronises the device."""
     act, strips, errs = _i(), _i(), _i()
-    _check(lib().axipcg_op_fused_info(op.handle, prec, ctypes.byref(act), ctypes.byref(strips),
+    _check(lib().axipcg_op_fused_info(op.handle, kind, ctypes.byref(act), ctypes.byref(strips),
                                       ctypes.byref(errs) if want_errors else None), "op_fused_info")
     return bool(act.value), strips.value, (errs.value if want_errors else None)
 

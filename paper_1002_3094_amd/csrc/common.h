@@ -87,10 +87,11 @@ constexpr int MAX_PARTIALS = 16384;
 constexpr int PARTIAL_ROWS = 7;
 static_assert(PARTIAL_ROWS >= NUM_SLOTS, "partial rows");
 
-// Launch plan of the single-pass preconditioner for one precision.
+// Launch plan of the single-launch preconditioner (pfused.hip) for one kind
+// of launch: 0 standalone apply, 1 PCG iteration.
 struct PfPlan {
     int state = 0;   // 0 not planned, 1 usable, -1 not usable (three launches)
-    int G = 0, R = 0, L2 = 0, RP = 1;
+    int G = 0, R = 0, L2 = 0;   // strips, rows per strip, modes per workgroup of the reduced phase
     size_t shm = 0;
     void *fn = nullptr;
 };
@@ -141,13 +142,12 @@ struct Operator {
     void *strip_red = nullptr;
     int strip_rows = 4;   // strip height (4 or 8), 0 = the per-mode r-solve instead
 
-    // single-pass preconditioner (pfused.hip): plan per precision [FP64, FP32]
+    // single-launch preconditioner (pfused.hip): plans [standalone, PCG]
     PfPlan pf[2];
-    bool fused_enabled = false;      // axipcg_op_set_fused (opt-in)
-    void *pf_work = nullptr;         // reduced equations and unknowns
-    size_t pf_work_bytes = 0;
-    unsigned *pf_bar = nullptr;      // grid barrier words: generation, then one flag per workgroup
+    bool fused_enabled = false;      // axipcg_op_set_fused
+    unsigned *pf_bar = nullptr;      // grid barrier numbers: completed, then one per strip
     int *pf_err = nullptr;           // set when a grid barrier gave up
+    unsigned pf_epoch = 0;           // launches so far (barrier numbers 2 epoch + 1, + 2)
 
     // per-kernel timing (axipcg_profile_*)
     int prof_kernel = -1;

@@ -68,6 +68,8 @@ void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 // transform.  The launch_* functions above route to it with the handle's
 // strip height when strip_usable holds for it.
 bool strip_usable(const Operator &op, int prec, int rows);
+// The strip height of the solves' launches for this precision (0: per-mode).
+int strip_solve_rows(const Operator &op, int prec);
 size_t strip_red_bytes(int nr, int nz);
 void strip_fwd(const Operator &op, int prec, int rows, const ZfwdArgs &a, hipStream_t s);
 void strip_reduced(const Operator &op, int prec, int rows, const TriGate &g, hipStream_t s);
@@ -76,10 +78,13 @@ void strip_inv(const Operator &op, int prec, int rows, const ZinvArgs &a, hipStr
 // z = B^{-1} r with three launches (forward, r-solves, inverse).
 void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s);
 
-// The same in one cooperative launch (pfused.hip), when pfused_plan accepts
-// the operator's geometry for this precision.
-bool pfused_plan(Operator &op, int prec);
-void pfused_apply(const Operator &op, const double *r, double *z, int prec, hipStream_t s);
+// The strip form in one cooperative launch (pfused.hip), FP32, when
+// pfused_plan accepts the operator for the kind of launch (0 standalone
+// apply, 1 PCG iteration: the forward kernel's x, r update, the r-solve
+// launch's stop test and the inverse's r.z partials in the same launch).
+bool pfused_plan(Operator &op, int kind);
+void pfused_apply(Operator &op, const double *r, double *z, hipStream_t s);
+void pfused_pcg_step(Operator &op, const ZfwdArgs &fa, const TriGate &g, const ZinvArgs &ia, hipStream_t s);
 
 // ---- batched solve: one launch per PCG phase covers every problem ----------
 void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm);

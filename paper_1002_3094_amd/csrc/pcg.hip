@@ -274,6 +274,7 @@ struct SolveCtx {
     int n_tr;   // workgroups (partials) of the transform kernels
     unsigned seq = 0;     // solve number published through the host mirror
     int report_it = -1;   // iteration whose stop test publishes even without a stop
+    bool one = false;     // iterations through the single-launch preconditioner
 };
 
 // Event pair around one launch of the profiled kernel class.  With `ext`
@@ -337,27 +338,34 @@ void launch_iteration(const SolveCtx &c, int parity, int iter)
     fa.q = op.q;
     fa.state = op.state;
     fa.n_pq = (int)gs;
-    {
-        ProfScope ps(op, c.s, AXIPCG_KERNEL_ZFWD, iter);
-        launch_zfwd(op, c.prec, fa, c.s);
-    }
-    {
-        ProfScope ps(op, c.s, AXIPCG_KERNEL_TRIDIAG, iter);
-        TriGate g;
-        g.mode = 1;
-        g.state = op.state;
-        g.n_rr = c.n_tr;
-        g.mirror = op.mirror_dev;
-        g.seq = c.seq;
-        g.report = iter == c.report_it;
-        launch_tridiag(op, c.prec, g, c.s);
-    }
+    TriGate g;
+    g.mode = 1;
+    g.state = op.state;
+    g.n_rr = c.n_tr;
+    g.mirror = op.mirror_dev;
+    g.seq = c.seq;
+    g.report = iter == c.report_it;
     ZinvArgs ia;
     ia.zout = op.z;
     ia.r = op.r;
     ia.state = op.state;
     ia.mode = 1;
     ia.pr = c.pr;
+    if (c.one) {
+        // the preconditioner phases in one cooperative launch (timed as the
+        // forward-transform class)
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_ZFWD, iter);
+        pfused_pcg_step(op, fa, g, ia, c.s);
+        return;
+    }
+    {
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_ZFWD, iter);
+        launch_zfwd(op, c.prec, fa, c.s);
+    }
+    {
+        ProfScope ps(op, c.s, AXIPCG_KERNEL_TRIDIAG, iter);
+        launch_tridiag(op, c.prec, g, c.s);
+    }
     {
         ProfScope ps(op, c.s, AXIPCG_KERNEL_ZINV, iter);
         launch_zinv(op, c.prec, ia, c.s);
@@ -425,6 +433,10 @@ int solve_impl(Operator &op, const double *b, double *x, double rtol, int maxit,
     const size_t n = (size_t)op.nr * op.nz;
     SolveCtx c{&op, x, prec, (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0, s, transform_blocks(op, prec)};
     c.seq = ++op.mirror_seq;
+    // the single launch keeps the three-launch strips' partial counts (4-row
+    // strips), and has no Polak-Ribiere form
+    c.one = op.fused_enabled && prec == AXIPCG_PREC_FP32 && !c.pr && pfused_plan(op, AXIPCG_FUSED_PCG) &&
+            op.pf[AXIPCG_FUSED_PCG].G == c.n_tr;
     op.prof_used = 0;
     // start: r = b - A x; z = B^{-1} r (the r-solve launch runs the start test)
     const unsigned gi = row_blocks(op.nr);

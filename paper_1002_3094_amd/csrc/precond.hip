@@ -857,9 +857,17 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
 
 }  // namespace
 
+// Strip height of the solves' launches: the handle's, except that 8-row
+// strips at FP32 rows of 2048 (whose PCG-form kernels would spill registers
+// in 8-wave workgroups) run as 4-row strips.
+int strip_solve_rows(const Operator &op, int prec)
+{
+    return (op.strip_rows == 8 && prec == AXIPCG_PREC_FP32 && op.nz == 2048) ? 4 : op.strip_rows;
+}
+
 int transform_blocks(const Operator &op, int prec)
 {
-    if (strip_usable(op, prec, op.strip_rows)) return op.nr / op.strip_rows;
+    if (strip_usable(op, prec, strip_solve_rows(op, prec))) return op.nr / strip_solve_rows(op, prec);
     const int wr = (prec == AXIPCG_PREC_FP32) ? wave_plan_rows<float>(op.nz) : wave_plan_rows<double>(op.nz);
     if (wr > 0) return (op.nr + wr - 1) / wr;
     return op.nr / transform_rows(op.nr, prec);
@@ -983,7 +991,7 @@ void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriG
 
 void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
 {
-    if (strip_usable(op, prec, op.strip_rows)) return strip_fwd(op, prec, op.strip_rows, a, s);
+    if (strip_usable(op, prec, strip_solve_rows(op, prec))) return strip_fwd(op, prec, strip_solve_rows(op, prec), a, s);
     if (prec == AXIPCG_PREC_FP32) {
         if (op.bc_z == DIR) zfwd_t<float, DIR>(op, a, s);
         else zfwd_t<float, AXIPCG_Z_NEUMANN>(op, a, s);
@@ -995,7 +1003,7 @@ void launch_zfwd(const Operator &op, int prec, const ZfwdArgs &a, hipStream_t s)
 
 void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 {
-    if (strip_usable(op, prec, op.strip_rows)) return strip_inv(op, prec, op.strip_rows, a, s);
+    if (strip_usable(op, prec, strip_solve_rows(op, prec))) return strip_inv(op, prec, strip_solve_rows(op, prec), a, s);
     if (prec == AXIPCG_PREC_FP32) {
         if (op.bc_z == DIR) zinv_t<float, DIR>(op, a, s);
         else zinv_t<float, AXIPCG_Z_NEUMANN>(op, a, s);
@@ -1007,25 +1015,28 @@ void launch_zinv(const Operator &op, int prec, const ZinvArgs &a, hipStream_t s)
 
 void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t s)
 {
-    if (strip_usable(op, prec, op.strip_rows)) return strip_reduced(op, prec, op.strip_rows, g, s);
+    if (strip_usable(op, prec, strip_solve_rows(op, prec)))
+        return strip_reduced(op, prec, strip_solve_rows(op, prec), g, s);
     if (prec == AXIPCG_PREC_FP32) tridiag_t<float>(op, g, s);
     else tridiag_t<double>(op, g, s);
 }
 
 // Standalone applies of FP32 rows of length 2048 use strips of 8 rows when
-// the handle runs strips of 4 (their transform kernels fit the registers of
-// 8-wave workgroups without the PCG vectors, and the reduced system halves);
-// the solves keep the handle's height.
+// strips are on (their transform kernels fit the registers of 8-wave
+// workgroups without the PCG vectors, and the reduced system halves); the
+// solves keep strip_solve_rows.
 void precond_apply_impl(const Operator &op, const double *r, double *z, int prec, hipStream_t s)
 {
-    if (op.strip_rows == 4 && prec == AXIPCG_PREC_FP32 && op.nz == 2048 && strip_usable(op, prec, 8)) {
+    int rows = strip_solve_rows(op, prec);
+    if (rows == 4 && prec == AXIPCG_PREC_FP32 && op.nz == 2048 && strip_usable(op, prec, 8)) rows = 8;
+    if (rows > 0 && strip_usable(op, prec, rows)) {
         ZfwdArgs fa;
         fa.rin = r;
-        strip_fwd(op, prec, 8, fa, s);
-        strip_reduced(op, prec, 8, TriGate{}, s);
+        strip_fwd(op, prec, rows, fa, s);
+        strip_reduced(op, prec, rows, TriGate{}, s);
         ZinvArgs ia;
         ia.zout = z;
-        strip_inv(op, prec, 8, ia, s);
+        strip_inv(op, prec, rows, ia, s);
         return;
     }
     ZfwdArgs fa;

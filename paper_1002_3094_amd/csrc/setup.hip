@@ -185,7 +185,7 @@ void free_op(Operator *op)
     void *ptrs[] = {op->D, op->CR, op->CZ, op->W, op->cb64, op->db64, op->rw64, op->lam64, op->cb32,
                     op->db32, op->rw32, op->lam32, op->tw64, op->pt64, op->tw32, op->pt32, op->r,
                     op->z, op->p0, op->p1, op->q, op->spec, op->partials, op->state, op->dscal,
-                    op->pf_work, op->pf_bar, op->pf_err, op->strip_red};
+                    op->pf_bar, op->pf_err, op->strip_red};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (hipEvent_t e : op->prof_events) (void)hipEventDestroy(e);
@@ -254,9 +254,9 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
         dmalloc(&op->dscal, 24);
         if (const size_t sb = strip_red_bytes(nr, nz))
             AXI_CHECK_HIP(hipMalloc(&op->strip_red, sb));
-        AXI_CHECK_HIP(hipMalloc((void **)&op->pf_bar, (1 + 256) * sizeof(unsigned)));
+        AXI_CHECK_HIP(hipMalloc((void **)&op->pf_bar, (1 + 1024) * sizeof(unsigned)));
         AXI_CHECK_HIP(hipMalloc((void **)&op->pf_err, sizeof(int)));
-        AXI_CHECK_HIP(hipMemsetAsync(op->pf_bar, 0, (1 + 256) * sizeof(unsigned), s));
+        AXI_CHECK_HIP(hipMemsetAsync(op->pf_bar, 0, (1 + 1024) * sizeof(unsigned), s));
         AXI_CHECK_HIP(hipMemsetAsync(op->pf_err, 0, sizeof(int), s));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->state_host, sizeof(PcgState), hipHostMallocDefault));
         AXI_CHECK_HIP(hipHostMalloc((void **)&op->scratch_host, 16 * sizeof(double), hipHostMallocDefault));
@@ -453,7 +453,8 @@ int axipcg_precond_apply(axipcg_op_t h, const double *r, double *z, int prec, vo
         AXI_REQUIRE(op && r && z, "NULL argument");
         AXI_REQUIRE(r != z, "r and z must not alias");
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
-        if (op->fused_enabled && pfused_plan(*op, prec)) pfused_apply(*op, r, z, prec, (hipStream_t)stream);
+        if (op->fused_enabled && prec == AXIPCG_PREC_FP32 && pfused_plan(*op, 0))
+            pfused_apply(*op, r, z, (hipStream_t)stream);
         else precond_apply_impl(*op, r, z, prec, (hipStream_t)stream);
         return AXIPCG_OK;
     });
@@ -498,22 +499,23 @@ int axipcg_op_strips_info(axipcg_op_t h, int prec, int *active, int *strips)
         const Operator *op = reinterpret_cast<const Operator *>(h);
         AXI_REQUIRE(op != nullptr, "op is NULL");
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
-        const bool ok = op->strip_rows > 0 && strip_usable(*op, prec, op->strip_rows);
+        const int rows = strip_solve_rows(*op, prec);
+        const bool ok = rows > 0 && strip_usable(*op, prec, rows);
         if (active) *active = ok ? 1 : 0;
-        if (strips) *strips = ok ? op->nr / op->strip_rows : 0;
+        if (strips) *strips = ok ? op->nr / rows : 0;
         return AXIPCG_OK;
     });
 }
 
-int axipcg_op_fused_info(axipcg_op_t h, int prec, int *active, int *strips, int *barrier_errors)
+int axipcg_op_fused_info(axipcg_op_t h, int kind, int *active, int *strips, int *barrier_errors)
 {
     return guarded([&] {
         Operator *op = reinterpret_cast<Operator *>(h);
         AXI_REQUIRE(op != nullptr, "op is NULL");
-        AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
-        const bool ok = op->fused_enabled && pfused_plan(*op, prec);
+        AXI_REQUIRE(kind == AXIPCG_FUSED_APPLY || kind == AXIPCG_FUSED_PCG, "kind must be 0 or 1");
+        const bool ok = op->fused_enabled && pfused_plan(*op, kind);
         if (active) *active = ok ? 1 : 0;
-        if (strips) *strips = ok ? op->pf[prec == AXIPCG_PREC_FP32 ? 1 : 0].G : 0;
+        if (strips) *strips = ok ? op->pf[kind].G : 0;
         if (barrier_errors) {
             int e = 0;
             AXI_CHECK_HIP(hipDeviceSynchronize());
