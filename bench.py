@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--headline", default="C", help="mode whose throughput is the value")
     ap.add_argument("--train-seeds", default="1,2,3,4,5,6,7,8")
     ap.add_argument("--train-harmonics", type=int, default=200)
+    ap.add_argument("--nn-base", type=int, default=6,
+                    help="order of the extrapolation the network corrects (1..6)")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--roofline-kernel", choices=list(KERNEL_IDS), default="spmv")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-baseline sample")
@@ -486,6 +488,8 @@ BF16_PEAK_TFLOPS = 2500.0
 def train_network(ax, torch, synth, series, a):
     """Online training on the series of each training medium (untimed)."""
     net = ax.nn_create(a.nr, a.nz, series.nn_init_params(0))
+    ax.nn_set_base(net, a.nn_base)
+    mode = "nn" if a.nn_base == 1 else "nn_poly"
     seeds = [int(v) for v in a.train_seeds.split(",") if v]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -495,11 +499,12 @@ def train_network(ax, torch, synth, series, a):
         with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
             g = ax.laguerre_coeffs(a.train_harmonics, inp["eta"], inp["ft"], inp["t"][-1])
             s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
-            st = s.run(a.train_harmonics, "nn", ax.PREC_FP32, net=net, lr=a.lr, want_info=True)
+            st = s.run(a.train_harmonics, mode, ax.PREC_FP32, net=net, lr=a.lr, want_info=True)
             iters.append(float(np.mean(st.iters)))
             losses.append(float(np.mean(st.loss[-20:])))
     torch.cuda.synchronize()
-    return net, {"seeds": seeds, "harmonics_per_seed": a.train_harmonics, "seconds": round(time.perf_counter() - t0, 2),
+    return net, {"seeds": seeds, "harmonics_per_seed": a.train_harmonics, "base_order": a.nn_base, "mode": mode,
+                 "seconds": round(time.perf_counter() - t0, 2),
                  "final_loss_per_seed": [round(v, 5) for v in losses]}
 
 
@@ -625,6 +630,7 @@ def main():
         s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
         s.run(3, "prev", ax.PREC_FP32, rtol=rtol)
         gx = torch.empty_like(s.u)
+        ax.nn_set_base(net, 1)      # the unguarded two-array forward; the same network pass
         for _ in range(3):
             ax.nn_forward(net, s.u1, s.u2, s.b, s.kappa, gx)
         n_nn = 20
@@ -635,6 +641,7 @@ def main():
         p1.record(stream)
         torch.cuda.synchronize()
         f_s = p0.elapsed_time(p1) / 1e3 / n_nn
+        ax.nn_set_base(net, a.nn_base)
         tfl = NN_FLOP_PER_POINT * n_pts / f_s / 1e12
         nn_rec = {"forward_ms": round(f_s * 1e3, 4), "tflops": round(tfl, 1), "peak_tflops": BF16_PEAK_TFLOPS,
                   "frac": round(tfl / BF16_PEAK_TFLOPS, 4), "flop_per_point": NN_FLOP_PER_POINT,

@@ -316,8 +316,9 @@ int axipcg_guess_poly(axipcg_op_t op, const double *b, const double *const *hist
  * (device [nr][nz] doubles): u1 = u_{m-1}, u2 = u_{m-2}, b = right-hand side
  * of harmonic m, kappa per cell.  With s = RMS(u1) and s_b = RMS(b) (1 where
  * zero) the channels are u1/s, u2/s, b/s_b, (kappa - 2.5)/1.5, and the guess
- * is 2 u1 - u2 + s * out (a network whose last layer is zero returns the
- * linear extrapolation).  Parameters (host float[axipcg_nn_num_params()]):
+ * is x_P + s * out, x_P the polynomial extrapolation of the handle's base
+ * order P (guess_poly's candidate P; P = 1, the default, is the linear
+ * 2 u1 - u2), so a network whose last layer is zero returns x_P.  Parameters (host float[axipcg_nn_num_params()]):
  * for each layer l = 0..5, W_l[t][ci][co] (t = 3 (di+1) + (dk+1) over the
  * 3x3 window in (r, z), ci < cin_l, co < cout_l; cin = 4,32,32,32,32,32,
  * cout = 32,...,32,1) then bias_l[co].  The handle owns device copies, the
@@ -333,8 +334,16 @@ void axipcg_nn_destroy(axipcg_nn_t nn);
 int axipcg_nn_get_params(axipcg_nn_t nn, float *params, float *grads);
 /* Replace the parameters (finite values only); Adam moments are kept. */
 int axipcg_nn_set_params(axipcg_nn_t nn, const float *params);
+/* The base order P in [1, 6] (default 1).  With P > 1 the base reads
+ * u_{m-1}, ..., u_{m-1-P}, so only the history-form calls take the network
+ * (nn_guess_poly and series_step / series_run with AXIPCG_GUESS_NN_POLY with
+ * K > P arrays, nn_backward_poly); nn_forward, nn_guess, nn_backward and
+ * AXIPCG_GUESS_NN then return AXIPCG_EINVAL.  nn_get_base returns P (or
+ * AXIPCG_EINVAL for a NULL handle). */
+int axipcg_nn_set_base(axipcg_nn_t nn, int order);
+int axipcg_nn_get_base(axipcg_nn_t nn);
 /* guess = 2 u1 - u2 + s * net(u1, u2, b, kappa), unguarded (device
- * [nr][nz]; guess may alias u1 or u2, not b or kappa). */
+ * [nr][nz]; guess may alias u1 or u2, not b or kappa); base order 1 only. */
 int axipcg_nn_forward(axipcg_nn_t nn, const double *u1, const double *u2, const double *b,
                       const double *kappa, double *guess, void *stream);
 /* Training loss of the last forward (or nn_guess) against the solved
@@ -346,6 +355,11 @@ int axipcg_nn_forward(axipcg_nn_t nn, const double *u1, const double *u2, const 
  * synchronises the stream. */
 int axipcg_nn_backward(axipcg_op_t op, axipcg_nn_t nn, const double *u1, const double *u2,
                        const double *u_target, double *loss_host, void *stream);
+/* The same for any base order: e = x_P + s * out - u_target with x_P formed
+ * from hist[0..P] (host array of K > P device arrays, hist[0] = u_{m-1},
+ * hist[1] = u_{m-2} as read by the last nn_guess_poly, unchanged since). */
+int axipcg_nn_backward_poly(axipcg_op_t op, axipcg_nn_t nn, const double *const *hist, int K,
+                            const double *u_target, double *loss_host, void *stream);
 /* One Adam step with the last gradients (bias-corrected moments, step count
  * kept by the handle). */
 int axipcg_nn_adam(axipcg_nn_t nn, double lr, double beta1, double beta2, double eps, void *stream);
@@ -358,8 +372,8 @@ int axipcg_nn_adam(axipcg_nn_t nn, double lr, double beta1, double beta2, double
 int axipcg_nn_guess(axipcg_op_t op, axipcg_nn_t nn, const double *b, const double *u1, const double *u2,
                     const double *kappa, double *x, double *resid_host, int *choice_host, void *stream);
 /* The learned guess among the polynomial extrapolations of guess_poly:
- * the network reads hist[0] = u_{m-1} and hist[1] = u_{m-2} (K = 2..7) and
- * its candidate (the linear extrapolation plus its correction) comes after
+ * the network reads hist[0] = u_{m-1} and hist[1] = u_{m-2} (K = P+1..7 for
+ * base order P) and its candidate (x_P plus its correction) comes after
  * the K extrapolations.  resid_host (host double[K + 1]: orders 0..K-1, then
  * the network) and choice_host (the order, or K for the network) may be
  * NULL; when either is given the call synchronises the stream.  x may alias a

@@ -12,8 +12,9 @@ header rather than by the paper:
   u_{m-1}/s, u_{m-2}/s, b_m/s_b, (kappa - 2.5)/1.5;
 * six 3x3 convolutions with zero "same" padding, 4 -> 32 -> ... -> 32 -> 1
   channels, ReLU after every layer but the last;
-* guess = 2 u_{m-1} - u_{m-2} + s * out (the network corrects the linear
-  extrapolation in m);
+* guess = x_P + s * out: the network corrects the polynomial extrapolation
+  in m of order P (``extrapolate``; P = 1, the default, is the linear
+  2 u_{m-1} - u_{m-2}; a larger P reads u_{m-1}, ..., u_{m-1-P});
 * loss: the energy norm of the guess error, L = e^T A e / (s^2 P) with
   e = guess - u_target, A the scheme's matrix and P the number of cells;
   Adam on the parameters;
@@ -132,8 +133,20 @@ def inputs(u1, u2, b, kappa, bf16=True, sc=None):
     return rnd(x), s
 
 
-def forward(params, u1, u2, b, kappa, bf16=True):
-    """Return (guess, cache) where cache holds what backward needs."""
+def base(u1, u2, hist=None, order=1):
+    """The extrapolation x_P the network corrects: ``extrapolate`` of order
+    P = ``order`` through hist = (u_{m-1}, u_{m-2}, ...) (u1, u2 when hist is
+    None, which allows P = 1 only)."""
+    h = (u1, u2) if hist is None else hist
+    if not 1 <= order < len(h):
+        raise ValueError("the base order needs order + 1 history arrays")
+    return extrapolate(h, order)
+
+
+def forward(params, u1, u2, b, kappa, bf16=True, hist=None, order=1):
+    """Return (guess, cache) where cache holds what backward needs.  The
+    network reads u1 = u_{m-1} and u2 = u_{m-2} whatever the base order;
+    ``hist`` (hist[0] = u1, hist[1] = u2) is needed for order > 1."""
     rnd = bf16_round if bf16 else _ident
     layers = unpack(params)
     x, s = inputs(u1, u2, b, kappa, bf16)
@@ -144,8 +157,7 @@ def forward(params, u1, u2, b, kappa, bf16=True):
             acts.append(rnd(np.maximum(y, 0.0)))
         else:
             out = y[..., 0]
-    u1, u2 = np.asarray(u1, dtype=np.float64), np.asarray(u2, dtype=np.float64)
-    guess = 2.0 * u1 - u2 + s * out
+    guess = base(u1, u2, hist, order) + s * out
     return guess, {"acts": acts, "out": out, "s": s, "bf16": bf16, "guess": guess}
 
 

@@ -96,6 +96,9 @@ SIGNATURES = {
     "axipcg_nn_forward": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_nn_backward": ([_vp, _vp, _vp, _vp, _vp, _dp, _vp], _i),
     "axipcg_nn_adam": ([_vp, _d, _d, _d, _d, _vp], _i),
+    "axipcg_nn_set_base": ([_vp, _i], _i),
+    "axipcg_nn_get_base": ([_vp], _i),
+    "axipcg_nn_backward_poly": ([_vp, _vp, ctypes.POINTER(_vp), _i, _vp, _dp, _vp], _i),
     "axipcg_nn_guess": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_nn_guess_poly": ([_vp, _vp, _vp, ctypes.POINTER(_vp), _i, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_series_step": ([_vp, _vp, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _i, _i, _d, _i, _i,
@@ -180,10 +183,11 @@ class Op:
         self.handle = None
         _live.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the exit hook has already released it (or
-        # the runtime is going away): touch nothing
-        if sys.is_finalizing():
+        # the runtime is going away): touch nothing (the check is bound at
+        # definition, since module globals may already be cleared then)
+        if _finalizing():
             return
         try:
             self.close()
@@ -429,10 +433,11 @@ class Net:
         self.handle = None
         _live.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the exit hook has already released it (or
-        # the runtime is going away): touch nothing
-        if sys.is_finalizing():
+        # the runtime is going away): touch nothing (the check is bound at
+        # definition, since module globals may already be cleared then)
+        if _finalizing():
             return
         try:
             self.close()
@@ -485,6 +490,25 @@ def nn_backward(op: Op, net: Net, u1, u2, u_target, stream=None, want_loss=True)
                                     _dev(u_target, "u_target"), _hp(loss) if want_loss else None,
                                     _stream(stream)), "nn_backward")
     return float(loss[0]) if want_loss else None
+
+
+def nn_backward_poly(op: Op, net: Net, hist: list, u_target, stream=None, want_loss=True):
+    """nn_backward for any base order: hist as read by the last nn_guess_poly."""
+    loss = np.zeros(1)
+    k = len(hist)
+    ptrs = (_vp * max(k, 1))(*[_dev(t, "hist") for t in hist])
+    _check(lib().axipcg_nn_backward_poly(op.handle, net.handle, ptrs, k, _dev(u_target, "u_target"),
+                                         _hp(loss) if want_loss else None, _stream(stream)), "nn_backward_poly")
+    return float(loss[0]) if want_loss else None
+
+
+def nn_set_base(net: Net, order: int):
+    """Order of the polynomial extrapolation the network corrects (1..6)."""
+    _check(lib().axipcg_nn_set_base(net.handle, int(order)), "nn_set_base")
+
+
+def nn_get_base(net: Net) -> int:
+    return int(lib().axipcg_nn_get_base(net.handle))
 
 
 def nn_adam(net: Net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

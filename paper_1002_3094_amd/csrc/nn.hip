@@ -4,9 +4,10 @@
 // A 6-layer 3x3 convolutional network, 32 channels wide, maps four input
 // channels of harmonic m -- u_{m-1}/s, u_{m-2}/s, b_m/s_b and (kappa-2.5)/1.5,
 // s = RMS(u_{m-1}), s_b = RMS(b_m) -- to a correction c, and the guess is
-// 2 u_{m-1} - u_{m-2} + s c: the network corrects the linear extrapolation
-// in m, which is formed in FP64 outside it, so the network's own rounding
-// noise scales with the correction only.  ReLU after every layer but the
+// x_P + s c: the network corrects the polynomial extrapolation in m of the
+// handle's base order P (P = 1, the default: 2 u_{m-1} - u_{m-2}; P up to 6
+// through u_{m-1}, ..., u_{m-1-P}), which is formed in FP64 outside it, so
+// the network's own rounding noise scales with the correction only.  ReLU after every layer but the
 // last, zero "same" padding.  Weights and activations are BF16, products are
 // accumulated in FP32 by MFMA (v_mfma_f32_16x16x16_bf16); training keeps FP32
 // master weights with Adam.
@@ -78,6 +79,7 @@ struct Net {
     double *scal = nullptr;      // [0] s, [1] s_b, [2] loss, [3] residual of guess, [4] residual of u1
     double *red = nullptr;       // [GMAX + 1][MAX_PARTIALS] partial sums
     double *res_host = nullptr;  // pinned
+    int base = 1;                // order of the extrapolation the network corrects
 };
 
 constexpr int WG_BLOCKS = 1024;
@@ -347,20 +349,38 @@ k_conv3(const bf16 *__restrict__ in, void *__restrict__ outp, const typename Fra
     }
 }
 
+// ---- history of earlier harmonics and the extrapolation weights -------------
+// History u_{m-1}, ..., u_{m-K} (K <= GMAX); row p of kExtrap holds the
+// weights of the order-p polynomial extrapolation through the last p + 1
+// harmonics, (-1)^i C(p+1, i+1) for u_{m-1-i}.
+constexpr int GMAX = 7;
+static_assert(GMAX <= PARTIAL_ROWS, "the guard's partial rows");
+struct Hist {
+    const double *u[GMAX];
+};
+__device__ constexpr double kExtrap[GMAX][GMAX] = {
+    {1, 0, 0, 0, 0, 0, 0},           {2, -1, 0, 0, 0, 0, 0},         {3, -3, 1, 0, 0, 0, 0},
+    {4, -6, 4, -1, 0, 0, 0},         {5, -10, 10, -5, 1, 0, 0},      {6, -15, 20, -15, 6, -1, 0},
+    {7, -21, 35, -35, 21, -7, 1}};
+
 // ---- loss: energy norm of the guess error ----------------------------------------
-// e = 2 u1 - u2 + s out - u_target, y = A e (A symmetric), L = e.y / (s^2 P);
+// e = x_P + s out - u_target, y = A e (A symmetric), L = e.y / (s^2 P);
 // dL/dout = 2 y / (s P), written as the BF16 gradient seed (channel 0 of 16).
-__device__ inline double guess_err(const float *out, const double *u1, const double *u2, const double *ut,
-                                   double s, size_t q)
+// x_P, the base, from the history h: sum_{j <= P} kExtrap[P][j] h_j.
+__device__ inline double guess_err(const float *out, const Hist &h, int order, const double *ut, double s,
+                                   size_t q)
 {
-    return 2.0 * u1[q] - u2[q] + s * (double)out[q] - ut[q];
+    double x = 0.0;
+#pragma unroll
+    for (int j = 0; j < GMAX; ++j)
+        if (j <= order) x += kExtrap[order][j] * h.u[j][q];
+    return x + s * (double)out[q] - ut[q];
 }
 
 __global__ void __launch_bounds__(256)
-k_nn_energy_seed(const float *__restrict__ out, const double *__restrict__ u1, const double *__restrict__ u2,
-                 const double *__restrict__ ut, const double *__restrict__ D, const double *__restrict__ CR,
-                 const double *__restrict__ CZ, int nr, int nz, bf16 *__restrict__ dpre, const double *scal,
-                 double *red)
+k_nn_energy_seed(const float *__restrict__ out, Hist h, int order, const double *__restrict__ ut,
+                 const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
+                 int nz, bf16 *__restrict__ dpre, const double *scal, double *red)
 {
     __shared__ double sm[8];
     const size_t n = (size_t)nr * nz;
@@ -369,12 +389,12 @@ k_nn_energy_seed(const float *__restrict__ out, const double *__restrict__ u1, c
     double acc = 0.0;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / nz), k = (int)(e - (size_t)i * nz);
-        const double ee = guess_err(out, u1, u2, ut, s, e);
+        const double ee = guess_err(out, h, order, ut, s, e);
         double y = D[e] * ee;
-        if (i + 1 < nr) y -= CR[e] * guess_err(out, u1, u2, ut, s, e + nz);
-        if (i > 0) y -= CR[e - nz] * guess_err(out, u1, u2, ut, s, e - nz);
-        if (k + 1 < nz) y -= CZ[e] * guess_err(out, u1, u2, ut, s, e + 1);
-        if (k > 0) y -= CZ[e - 1] * guess_err(out, u1, u2, ut, s, e - 1);
+        if (i + 1 < nr) y -= CR[e] * guess_err(out, h, order, ut, s, e + nz);
+        if (i > 0) y -= CR[e - nz] * guess_err(out, h, order, ut, s, e - nz);
+        if (k + 1 < nz) y -= CZ[e] * guess_err(out, h, order, ut, s, e + 1);
+        if (k > 0) y -= CZ[e - 1] * guess_err(out, h, order, ut, s, e - 1);
         acc += ee * y;
         alignas(16) bf16 v[16] = {};
         v[0] = to_bf16((float)(g * y));
@@ -604,19 +624,10 @@ k_nn_unpack(const double *u1, const double *u2, const float *__restrict__ out, d
 // polynomial extrapolation of order p through the last p + 1 harmonics,
 //     x_p = sum_{i <= p} (-1)^i C(p+1, i+1) u_{m-1-i}
 // (u_{m-1}; 2 u_{m-1} - u_{m-2}; 3 u_{m-1} - 3 u_{m-2} + u_{m-3}; ...), and
-// with a network candidate K the learned guess x_1 + s out (its correction
-// sits on the linear extrapolation).  PCG's stop test measures |b - A x|, and
+// with a network candidate K the learned guess x_P + s out (its correction
+// sits on the extrapolation of the handle's base order P).  PCG's stop test measures |b - A x|, and
 // with a spectrally equivalent preconditioner the iterations a start needs
 // follow it, so the guard ranks the candidates by that norm.
-constexpr int GMAX = 7;
-static_assert(GMAX <= PARTIAL_ROWS, "the guard's partial rows");
-struct Hist {
-    const double *u[GMAX];
-};
-__device__ constexpr double kExtrap[GMAX][GMAX] = {
-    {1, 0, 0, 0, 0, 0, 0},           {2, -1, 0, 0, 0, 0, 0},         {3, -3, 1, 0, 0, 0, 0},
-    {4, -6, 4, -1, 0, 0, 0},         {5, -10, 10, -5, 1, 0, 0},      {6, -15, 20, -15, 6, -1, 0},
-    {7, -21, 35, -35, 21, -7, 1}};
 
 __device__ inline double2 ld_pair(const double *p) { return *reinterpret_cast<const double2 *>(p); }
 __device__ inline double2 ld_pair(const float *p)
@@ -671,7 +682,7 @@ __device__ inline double2 apply_pair(const V *__restrict__ v, double2 d, double2
 template <int K, bool NET, bool CACHED>
 __global__ void __launch_bounds__(256)
 k_guess_hist(const double *__restrict__ b, Hist h, Hist ah, double *__restrict__ ah0,
-             const float *__restrict__ out, const double *__restrict__ D, const double *__restrict__ CR,
+             const float *__restrict__ out, int nbase, const double *__restrict__ D, const double *__restrict__ CR,
              const double *__restrict__ CZ, int nr, int nz, const double *scal, double *red)
 {
 #pragma clang fp contract(off)
@@ -702,11 +713,12 @@ k_guess_hist(const double *__restrict__ b, Hist h, Hist ah, double *__restrict__
                     a.y += kExtrap[p][q] * au[q].y;
                 }
                 const double2 r{bv.x - a.x, bv.y - a.y};
-                if (p == 1) r1 = r;
+                if (p == nbase) r1 = r;
                 f[p] = add_sq(f[p], r);
             }
             if (NET) {
-                // the network's candidate is x_1 + s out: its residual is r_1 - s A out
+                // the network's candidate is x_P + s out (P = nbase): its
+                // residual is r_P - s A out
                 const double2 ao = apply_pair(out, d, cz, CR, CZ, e, i, k, nr, nz);
                 f[K] = add_sq(f[K], double2{r1.x - s * ao.x, r1.y - s * ao.y});
             }
@@ -781,11 +793,12 @@ __global__ void __launch_bounds__(256) k_guess_fin(const double *red, int nb, do
 // before write).
 template <int K, bool NET>
 __global__ void __launch_bounds__(256)
-k_guess_pick(Hist h, const float *__restrict__ out, double *x, size_t n, const double *res, const double *scal)
+k_guess_pick(Hist h, const float *__restrict__ out, int nbase, double *x, size_t n, const double *res,
+             const double *scal)
 {
     const int c = (int)res[K + 1];
     const double s = NET ? scal[0] : 0.0;
-    const int order = c < K ? c : 1;   // the network's base is the linear extrapolation
+    const int order = c < K ? c : nbase;   // the network's candidate sits on x_nbase
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         double u[K];
 #pragma unroll
@@ -854,29 +867,32 @@ k_apply_pairs(const double *__restrict__ v, double *__restrict__ y, const double
 }
 
 template <int K, bool NET>
-void guard_k(const Operator &op, const double *b, const Hist &h, const float *out, const double *scal, double *red,
-             double *x, double *res, hipStream_t s, const Hist *ah, double *ah0)
+void guard_k(const Operator &op, const double *b, const Hist &h, const float *out, int nbase, const double *scal,
+             double *red, double *x, double *res, hipStream_t s, const Hist *ah, double *ah0)
 {
     const size_t np = (size_t)op.nr * op.nz;
     const unsigned pb = guard_blocks(op.nr);
     if (ah)
-        hipLaunchKernelGGL((k_guess_hist<K, NET, true>), dim3(pb), dim3(256), 0, s, b, h, *ah, ah0, out, op.D, op.CR,
+        hipLaunchKernelGGL((k_guess_hist<K, NET, true>), dim3(pb), dim3(256), 0, s, b, h, *ah, ah0, out, nbase, op.D, op.CR,
                            op.CZ, op.nr, op.nz, scal, red);
     else
-        hipLaunchKernelGGL((k_guess_hist<K, NET, false>), dim3(pb), dim3(256), 0, s, b, h, h, nullptr, out, op.D,
+        hipLaunchKernelGGL((k_guess_hist<K, NET, false>), dim3(pb), dim3(256), 0, s, b, h, h, nullptr, out, nbase, op.D,
                            op.CR, op.CZ, op.nr, op.nz, scal, red);
     hipLaunchKernelGGL((k_guess_fin<K, NET>), dim3(1), dim3(256), 0, s, red, (int)pb, res);
-    hipLaunchKernelGGL((k_guess_pick<K, NET>), dim3(pw_blocks(np)), dim3(256), 0, s, h, out, x, np, res, scal);
+    hipLaunchKernelGGL((k_guess_pick<K, NET>), dim3(pw_blocks(np)), dim3(256), 0, s, h, out, nbase, x, np, res, scal);
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-// Guard over the history h (K arrays) and, with out, the network candidate:
-// partial sums in red (K + 1 rows), norms and choice in res (K + 2 values).
-// With ah: A h.u[j] for j >= 1 cached there, A h.u[0] stored into ah0.
-void run_guard(const Operator &op, const double *b, const Hist &h, int K, const float *out, const double *scal,
-               double *red, double *x, double *res, hipStream_t s, const Hist *ah = nullptr, double *ah0 = nullptr)
+// Guard over the history h (K arrays) and, with out, the network candidate
+// x_nbase + s out (nbase < K): partial sums in red (K + 1 rows), norms and
+// choice in res (K + 2 values).  With ah: A h.u[j] for j >= 1 cached there,
+// A h.u[0] stored into ah0.
+void run_guard(const Operator &op, const double *b, const Hist &h, int K, const float *out, int nbase,
+               const double *scal, double *red, double *x, double *res, hipStream_t s, const Hist *ah = nullptr,
+               double *ah0 = nullptr)
 {
-#define AXI_G(KK, NN) return guard_k<KK, NN>(op, b, h, out, scal, red, x, res, s, ah, ah0)
+    if (out) AXI_REQUIRE(nbase >= 1 && nbase < K, "the network's base order needs more history arrays");
+#define AXI_G(KK, NN) return guard_k<KK, NN>(op, b, h, out, nbase, scal, red, x, res, s, ah, ah0)
     if (out) {
         switch (K) {
         case 2: AXI_G(2, true);
@@ -966,11 +982,12 @@ void forward_impl(Net &n, const double *u1, const double *u2, const double *b, c
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-void backward_impl(Net &n, const Operator &op, const double *u1, const double *u2, const double *ut, hipStream_t s)
+// h: the forward's history (at least base + 1 arrays)
+void backward_impl(Net &n, const Operator &op, const Hist &h, const double *ut, hipStream_t s)
 {
     const size_t np = (size_t)n.nr * n.nz;
     const unsigned pb = red_blocks(np);
-    hipLaunchKernelGGL(k_nn_energy_seed, dim3(pb), dim3(256), 0, s, n.out, u1, u2, ut, op.D, op.CR, op.CZ, n.nr,
+    hipLaunchKernelGGL(k_nn_energy_seed, dim3(pb), dim3(256), 0, s, n.out, h, n.base, ut, op.D, op.CR, op.CZ, n.nr,
                        n.nz, n.dpre[0], n.scal, n.red);
     hipLaunchKernelGGL(k_nn_loss_fin, dim3(1), dim3(256), 0, s, n.red, (int)pb, np, n.scal);
     const int rows = conv_rows(n.nr, n.nz);
@@ -1065,12 +1082,12 @@ void guess_poly_cached(Operator &op, axipcg_nn_t nn, const double *b, const doub
     }
     if (nn) {
         Net *n = reinterpret_cast<Net *>(nn);
-        AXI_REQUIRE(K >= 2 && kappa, "the learned guess needs two history arrays and kappa");
+        AXI_REQUIRE(K > n->base && kappa, "the learned guess needs base order + 1 history arrays and kappa");
         AXI_REQUIRE(op.nr == n->nr && op.nz == n->nz, "operator and network sizes differ");
         forward_impl(*n, hist[0], hist[1], b, kappa, s);
-        run_guard(op, b, hh, K, n->out, n->scal, n->red, x, n->scal + 3, s, &ahh, ah[0]);
+        run_guard(op, b, hh, K, n->out, n->base, n->scal, n->red, x, n->scal + 3, s, &ahh, ah[0]);
     } else {
-        run_guard(op, b, hh, K, nullptr, nullptr, op.partials, x, op.dscal + 8, s, &ahh, ah[0]);
+        run_guard(op, b, hh, K, nullptr, 0, nullptr, op.partials, x, op.dscal + 8, s, &ahh, ah[0]);
     }
 }
 
@@ -1134,6 +1151,7 @@ int axipcg_nn_forward(axipcg_nn_t h, const double *u1, const double *u2, const d
     return guarded([&] {
         Net *n = reinterpret_cast<Net *>(h);
         AXI_REQUIRE(n && u1 && u2 && b && kappa && guess, "NULL argument");
+        AXI_REQUIRE(n->base == 1, "the network's base order needs the history form (nn_guess_poly)");
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
         const size_t np = (size_t)n->nr * n->nz;
@@ -1151,8 +1169,10 @@ int axipcg_nn_backward(axipcg_op_t hop, axipcg_nn_t h, const double *u1, const d
         Net *n = reinterpret_cast<Net *>(h);
         AXI_REQUIRE(op && n && u1 && u2 && u_target, "NULL argument");
         AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
+        AXI_REQUIRE(n->base == 1, "the network's base order needs the history form (nn_backward_poly)");
         hipStream_t s = (hipStream_t)stream;
-        backward_impl(*n, *op, u1, u2, u_target, s);
+        const double *hist[2] = {u1, u2};
+        backward_impl(*n, *op, make_hist(hist, 2, u_target, nullptr, nullptr), u_target, s);
         if (loss_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
@@ -1180,6 +1200,44 @@ int axipcg_nn_adam(axipcg_nn_t h, double lr, double beta1, double beta2, double 
     });
 }
 
+int axipcg_nn_set_base(axipcg_nn_t h, int order)
+{
+    return guarded([&] {
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(n != nullptr, "NULL network");
+        AXI_REQUIRE(order >= 1 && order <= GMAX - 1, "base order must be in [1, 6]");
+        n->base = order;
+        return AXIPCG_OK;
+    });
+}
+
+int axipcg_nn_get_base(axipcg_nn_t h)
+{
+    const Net *n = reinterpret_cast<const Net *>(h);
+    return n ? n->base : AXIPCG_EINVAL;
+}
+
+int axipcg_nn_backward_poly(axipcg_op_t hop, axipcg_nn_t h, const double *const *hist, int K,
+                            const double *u_target, double *loss_host, void *stream)
+{
+    return guarded([&] {
+        Operator *op = reinterpret_cast<Operator *>(hop);
+        Net *n = reinterpret_cast<Net *>(h);
+        AXI_REQUIRE(op && n && u_target, "NULL argument");
+        AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
+        AXI_REQUIRE(K > n->base, "the base order needs base + 1 history arrays");
+        const Hist hh = make_hist(hist, K, u_target, nullptr, nullptr);
+        hipStream_t s = (hipStream_t)stream;
+        backward_impl(*n, *op, hh, u_target, s);
+        if (loss_host) {
+            AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, n->scal + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            *loss_host = n->res_host[0];
+        }
+        return AXIPCG_OK;
+    });
+}
+
 int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const double *u1, const double *u2,
                     const double *kappa, double *x, double *resid_host, int *choice_host, void *stream)
 {
@@ -1189,12 +1247,13 @@ int axipcg_nn_guess(axipcg_op_t hop, axipcg_nn_t h, const double *b, const doubl
         AXI_REQUIRE(op && n && b && u1 && u2 && kappa && x, "NULL argument");
         AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
         AXI_REQUIRE(x != b && x != kappa, "x aliases b or kappa");
+        AXI_REQUIRE(n->base == 1, "the network's base order needs the history form (nn_guess_poly)");
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, u1, u2, b, kappa, s);
         const double *hist[2] = {u1, u2};
         // res: u1, extrapolation, network, choice (0 u1, 1 extrapolation, 2 network)
         double *res = n->scal + 3;
-        run_guard(*op, b, make_hist(hist, 2, x, b, kappa), 2, n->out, n->scal, n->red, x, res, s);
+        run_guard(*op, b, make_hist(hist, 2, x, b, kappa), 2, n->out, 1, n->scal, n->red, x, res, s);
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
@@ -1217,12 +1276,12 @@ int axipcg_nn_guess_poly(axipcg_op_t hop, axipcg_nn_t h, const double *b, const 
         Net *n = reinterpret_cast<Net *>(h);
         AXI_REQUIRE(op && n && b && kappa && x, "NULL argument");
         AXI_REQUIRE(op->nr == n->nr && op->nz == n->nz, "operator and network sizes differ");
-        AXI_REQUIRE(K >= 2, "the learned guess needs at least two history arrays");
+        AXI_REQUIRE(K > n->base, "the learned guess needs base order + 1 history arrays");
         const Hist hh = make_hist(hist, K, x, b, kappa);
         hipStream_t s = (hipStream_t)stream;
         forward_impl(*n, hist[0], hist[1], b, kappa, s);
         double *res = n->scal + 3;
-        run_guard(*op, b, hh, K, n->out, n->scal, n->red, x, res, s);
+        run_guard(*op, b, hh, K, n->out, n->base, n->scal, n->red, x, res, s);
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(n->res_host, res, (K + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
@@ -1246,7 +1305,7 @@ int axipcg_guess_extrap(axipcg_op_t hop, const double *b, const double *u1, cons
         // which a solve only reads after writing them itself; res: u1,
         // extrapolation, (no network), choice
         double *res = op->dscal + 8;
-        run_guard(*op, b, make_hist(hist, 2, x, b, nullptr), 2, nullptr, nullptr, op->partials, x, res, s);
+        run_guard(*op, b, make_hist(hist, 2, x, b, nullptr), 2, nullptr, 0, nullptr, op->partials, x, res, s);
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));
@@ -1270,7 +1329,7 @@ int axipcg_guess_poly(axipcg_op_t hop, const double *b, const double *const *his
         hipStream_t s = (hipStream_t)stream;
         // partial-sum rows 0..K-1 and scalars 8..8+K+1 of the handle (see guess_extrap)
         double *res = op->dscal + 8;
-        run_guard(*op, b, hh, K, nullptr, nullptr, op->partials, x, res, s);
+        run_guard(*op, b, hh, K, nullptr, 0, nullptr, op->partials, x, res, s);
         if (resid_host || choice_host) {
             AXI_CHECK_HIP(hipMemcpyAsync(op->scratch_host, res, (K + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
             AXI_CHECK_HIP(hipStreamSynchronize(s));

@@ -126,7 +126,10 @@ class LaguerreSeries:
         stats.iters.append(st["iters"])
         stats.status.append(st["code"])
         if nn_mode and lr is not None:
-            stats.loss.append(ax.nn_backward(self.op, net, self.u1, self.u2, self.u, want_loss=want_info))
+            if guess == "nn_poly":
+                stats.loss.append(ax.nn_backward_poly(self.op, net, self.hist, self.u, want_loss=want_info))
+            else:
+                stats.loss.append(ax.nn_backward(self.op, net, self.u1, self.u2, self.u, want_loss=want_info))
             ax.nn_adam(net, lr=lr)
         self._rotate()
         self.m += 1
@@ -260,8 +263,9 @@ class PaperSeries:
 
 
 def train_online(net, problems, n_harm: int, prec: int, lr: float = 1e-3, rtol: float = 1e-10,
-                 maxit: int = 1000):
-    """Train the learned guess on the series of each problem in turn.
+                 maxit: int = 1000, guess: str = "nn"):
+    """Train the learned guess on the series of each problem in turn, in the
+    guess mode it will serve ("nn", or "nn_poly" for a base order above 1).
 
     ``problems`` yields (op, g, src_i, src_k, kappa).  Returns (seconds,
     per-problem mean iterations, last losses)."""
@@ -269,7 +273,7 @@ def train_online(net, problems, n_harm: int, prec: int, lr: float = 1e-3, rtol: 
     iters, losses = [], []
     for op, g, si, sk, kappa in problems:
         s = LaguerreSeries(op, g, si, sk, kappa=kappa)
-        st = s.run(n_harm, "nn", prec, rtol=rtol, maxit=maxit, net=net, lr=lr, want_info=True)
+        st = s.run(n_harm, guess, prec, rtol=rtol, maxit=maxit, net=net, lr=lr, want_info=True)
         iters.append(sum(st.iters) / len(st.iters))
         losses.append(st.loss[-1] if st.loss else None)
     return time.perf_counter() - t0, iters, losses

@@ -155,6 +155,9 @@ def test_nn_entry_points_validate_before_device_work(ax):
     assert lib.axipcg_nn_forward(None, None, None, None, None, None, None) == ax.EINVAL
     assert lib.axipcg_nn_backward(None, None, None, None, None, None, None) == ax.EINVAL
     assert lib.axipcg_nn_adam(None, 1e-3, 0.9, 0.999, 1e-8, None) == ax.EINVAL
+    assert lib.axipcg_nn_set_base(None, 2) == ax.EINVAL
+    assert lib.axipcg_nn_get_base(None) == ax.EINVAL
+    assert lib.axipcg_nn_backward_poly(None, None, None, 3, None, None, None) == ax.EINVAL
     assert lib.axipcg_nn_guess(None, None, None, None, None, None, None, None, None, None) == ax.EINVAL
     lib.axipcg_nn_destroy(None)  # NULL-safe
 

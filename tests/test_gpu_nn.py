@@ -311,6 +311,87 @@ def test_nn_poly_guard_matches_oracle(ax, onn, orc):
 
 
 
+def test_nn_base_order_guard_matches_oracle(ax, onn, orc):
+    """Base order 4: the network's candidate is x_4 + s out.  A history that
+    is u* - shift plus a cubic in the harmonic index makes x_3 .. x_6 equal
+    u* - shift (orders 0..2 miss the cubic); a bias-only network whose
+    correction is the shift makes its candidate (nearly) u*."""
+    nr, nz = 32, 64
+    kappa, q = synth.medium_layered(nr, nz, 4)
+    op, oop = _ops(ax, orc, kappa, q)
+    b = orc.rhs(oop, synth.gaussian_source(nr, nz, 1.0, 1.0, 0.2, 0.5, 0.05))
+    ustar, status, _, _ = orc.pcg(oop, b, np.zeros_like(b), rtol=1e-14, maxit=2000)
+    assert status == 0
+    A = lambda x: orc.apply(oop, x)  # noqa: E731
+    rng = np.random.default_rng(3)
+    w = 0.05 * np.abs(ustar).max() * rng.standard_normal((3, nr, nz))
+    shift = 0.1 * np.abs(ustar).max()
+    hist = [ustar - shift + sum(w[d] * float(i + 1) ** (d + 1) for d in range(3)) for i in range(7)]
+    s = np.sqrt(np.mean(hist[0] * hist[0]))
+    c32 = float(np.float32(shift / s))
+    net = ax.nn_create(nr, nz, _bias_only(onn, shift / s))
+    assert ax.nn_get_base(net) == 1
+    ax.nn_set_base(net, 4)
+    assert ax.nn_get_base(net) == 4
+    kd, bd, hd = dev(kappa), dev(b), [dev(h) for h in hist]
+    x = dev(np.zeros_like(b))
+    phi, pick = ax.nn_guess_poly(op, net, bd, hd, kd, x)
+    base4 = onn.extrapolate(hist, 4)
+    res_ref, pick_ref, _ = onn.guard_poly(b, hist, A, net_guess=base4 + s * c32)
+    log(f"nn base-4 guard: resid {phi} (oracle {res_ref}), pick {pick}")
+    assert pick == pick_ref == 7
+    np.testing.assert_allclose(phi[:7], res_ref[:7], rtol=1e-8)
+    assert phi[7] == pytest.approx(res_ref[7], rel=1e-5)
+    np.testing.assert_allclose(host(x), base4 + s * c32, rtol=1e-12, atol=1e-13 * np.abs(ustar).max())
+    # too few history arrays for the base, and the two-array calls, are refused
+    with pytest.raises(ax.AxipcgError):
+        ax.nn_guess_poly(op, net, bd, hd[:4], kd, x)
+    with pytest.raises(ax.AxipcgError):
+        ax.nn_guess(op, net, bd, hd[0], hd[1], kd, x)
+    with pytest.raises(ax.AxipcgError):
+        ax.nn_forward(net, hd[0], hd[1], bd, kd, x)
+    with pytest.raises(ax.AxipcgError):
+        ax.nn_backward(op, net, hd[0], hd[1], x)
+    for bad in (0, 7):
+        with pytest.raises(ax.AxipcgError):
+            ax.nn_set_base(net, bad)
+    assert ax.nn_get_base(net) == 4
+    net.close()
+    op.close()
+
+
+@pytest.mark.parametrize("shape,order", [((37, 128), 2), ((64, 256), 6)])
+def test_backward_base_order_matches_oracle(ax, onn, orc, shape, order):
+    nr, nz = shape
+    log(f"nn backward base order {order} {shape}")
+    ex = synth.nn_example(nr, nz, seed=5 * nr + nz)
+    rng = np.random.default_rng(order)
+    hist = [ex["u1"], ex["u2"]] + [ex["u1"] + 0.3 * rng.standard_normal((nr, nz)) for _ in range(order - 1)]
+    op, oop = _ops(ax, orc, ex["kappa"], np.full((nr, nz), 0.5))
+    params = onn.init_params(5, last_zero=False)
+    params[onn.OFFSETS[5]:onn.OFFSETS[5] + 9 * 32] *= 0.001
+    net = ax.nn_create(nr, nz, params)
+    ax.nn_set_base(net, order)
+    hd = [dev(h) for h in hist]
+    x = dev(np.zeros_like(ex["u1"]))
+    ax.nn_guess_poly(op, net, dev(ex["b"]), hd, dev(ex["kappa"]), x)
+    loss = ax.nn_backward_poly(op, net, hd, dev(ex["ut"]))
+    _, grads = ax.nn_get_params(net)
+    _, cache = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=True, hist=hist, order=order)
+    lref, gref = onn.backward(params, cache, lambda e: orc.apply(oop, e), ex["ut"])
+    log(f"  loss {loss:.6e} vs {lref:.6e}")
+    assert loss == pytest.approx(lref, rel=1e-3)
+    for l in range(onn.N_LAYERS):
+        o = onn.OFFSETS[l]
+        nw = 9 * onn.CIN[l] * onn.COUT[l]
+        ew = rel(grads[o:o + nw], gref[o:o + nw])
+        eb = rel(grads[o + nw:o + nw + onn.COUT[l]], gref[o + nw:o + nw + onn.COUT[l]])
+        log(f"  layer {l}: dW rel {ew:.2e}, db rel {eb:.2e}")
+        assert ew < 2e-2 and eb < 2e-2
+    net.close()
+    op.close()
+
+
 def test_forward_1024_sampled(ax, onn):
     """Forward pass at the benchmark's 1024^2 grid against the oracle on
     sampled cells (corners, edges and seeded interior cells), each evaluated

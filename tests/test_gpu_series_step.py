@@ -50,15 +50,19 @@ def test_series_step_matches_separate_calls(ax, guess, solver):
         net.close()
 
 
-@pytest.mark.parametrize("guess,solver", [("prev", "pcg"), ("nn", "pcg"), ("extrap", "cheb"), ("nn", "cheb"),
-                                          ("poly", "pcg"), ("nn_poly", "pcg"), ("poly", "cheb")])
-def test_series_run_matches_steps(ax, guess, solver):
-    """Harmonics 0..6 as one run of 2 and one of 5 against seven single steps."""
+@pytest.mark.parametrize("guess,solver,base", [("prev", "pcg", 1), ("nn", "pcg", 1), ("extrap", "cheb", 1),
+                                               ("nn", "cheb", 1), ("poly", "pcg", 1), ("nn_poly", "pcg", 1),
+                                               ("nn_poly", "pcg", 6), ("poly", "cheb", 1)])
+def test_series_run_matches_steps(ax, guess, solver, base):
+    """Harmonics 0..6 as one run of 2 and one of 5 against seven single steps
+    (base: the order of the extrapolation the network corrects)."""
     from paper_1002_3094_amd.series import LaguerreSeries, SeriesStats, nn_init_params
-    log(f"series_run guess={guess} solver={solver}")
+    log(f"series_run guess={guess} solver={solver} base={base}")
     n_harm = 7
     inp = synth.laguerre_series_inputs(N, N, seed=4)
     net = ax.nn_create(N, N, nn_init_params(6, last_zero=False)) if guess in ("nn", "nn_poly") else None
+    if net is not None:
+        ax.nn_set_base(net, base)
     with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
         g = ax.laguerre_coeffs(n_harm, inp["eta"], inp["ft"], inp["t"][-1])
         s1 = LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])

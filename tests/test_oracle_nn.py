@@ -197,12 +197,75 @@ def test_guard_poly_ranks_by_residual():
     assert pick == 0
 
 
+def _history(ex, n, seed):
+    """u_{m-1} = ex's u1, u_{m-2} = u2 and n - 2 more smooth fields."""
+    rng = np.random.default_rng(seed)
+    more = [ex["u1"] + 0.3 * rng.standard_normal(ex["u1"].shape) for _ in range(n - 2)]
+    return [ex["u1"], ex["u2"]] + more
+
+
+def _fit_extrapolation(hist, p):
+    """The value at t = 0 of the degree-p least-squares polynomial through
+    (t, hist[i]) at t = -1 - i, i <= p (an interpolant: p + 1 points), by
+    numpy's polynomial fit; independent of the oracle's Lagrange weights."""
+    t = -1.0 - np.arange(p + 1)
+    ys = np.stack([np.asarray(hist[i]).ravel() for i in range(p + 1)])
+    c = np.polynomial.polynomial.polyfit(t, ys, p)
+    return c[0].reshape(np.shape(hist[0]))
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_forward_base_order_matches_torch(order):
+    """Order-P base: the guess is the network's (torch) output times s plus
+    the degree-P polynomial through the last P + 1 harmonics at harmonic m."""
+    ex = nn_example(12, 20, seed=21)
+    hist = _history(ex, 7, order)
+    params = onn.init_params(7, last_zero=False)
+    guess, cache = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False, hist=hist,
+                               order=order)
+    x, s = onn.inputs(ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
+    out = _torch_forward(_torch_net(params), x).detach().numpy()
+    ref = _fit_extrapolation(hist, order) + s * out
+    np.testing.assert_allclose(guess, ref, rtol=1e-8, atol=1e-8 * np.abs(ref).max())
+
+
+def test_backward_base_order_matches_torch_autograd():
+    ex = nn_example(10, 16, seed=22)
+    A, apply_A = _matrix(ex)
+    hist = _history(ex, 5, 3)
+    params = onn.init_params(8, last_zero=False)
+    _, cache = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False, hist=hist, order=4)
+    loss, grads = onn.backward(params, cache, apply_A, ex["ut"])
+    x, s = onn.inputs(ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=False)
+    ws = _torch_net(params)
+    guess = torch.tensor(_fit_extrapolation(hist, 4)) + s * _torch_forward(ws, x)
+    e = (guess - torch.tensor(ex["ut"])).reshape(-1)
+    tl = (e @ (torch.tensor(A.toarray()) @ e)) / (s * s * e.numel())
+    tl.backward()
+    assert loss == pytest.approx(tl.item(), rel=1e-9)
+    ref = _flat_grads(ws)
+    np.testing.assert_allclose(grads, ref, rtol=1e-7, atol=1e-10 * np.abs(ref).max())
+
+
+def test_base_order_needs_history():
+    ex = nn_example(4, 8, seed=23)
+    params = onn.init_params(1)
+    with pytest.raises(ValueError):
+        onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], order=2)
+    with pytest.raises(ValueError):
+        onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], hist=_history(ex, 3, 0), order=3)
+
+
 def test_zero_last_layer_returns_extrapolation():
     ex = nn_example(9, 14, seed=11)
     params = onn.init_params(12, last_zero=True)
     for bf in (False, True):
         guess, _ = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=bf)
         np.testing.assert_array_equal(guess, 2 * ex["u1"] - ex["u2"])
+        hist = _history(ex, 7, 4)
+        for p in range(1, 7):
+            guess, _ = onn.forward(params, ex["u1"], ex["u2"], ex["b"], ex["kappa"], bf16=bf, hist=hist, order=p)
+            np.testing.assert_array_equal(guess, onn.extrapolate(hist, p))
 
 
 def test_rounded_network_close_to_fp64_and_on_bf16_grid():
