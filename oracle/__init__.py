@@ -23,7 +23,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# AXIPCG_ORACLE_LIB selects another build of oracle.c (the sanitized one of
+# build.build_sanitized)
+_LIB_PATH = os.environ.get("AXIPCG_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 Z_DIRICHLET = 0

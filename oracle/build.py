@@ -23,5 +23,19 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+def build_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """The same library with AddressSanitizer and UndefinedBehaviorSanitizer
+    (gcc's runtimes: preload the path of ``gcc -print-file-name=libasan.so``)."""
+    os.makedirs(out_dir, exist_ok=True)
+    out = os.path.join(out_dir, "liboracle_san.so")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared", "-fopenmp",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-Wall", "-Wextra", "-o", out, os.path.join(HERE, "oracle.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -17,7 +17,9 @@ import weakref
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libaxipcg.so")
+# AXIPCG_LIB selects another build of the same library (the host-sanitized
+# one of build.build_host_sanitized, for CPU-only checks)
+LIB_PATH = os.environ.get("AXIPCG_LIB") or os.path.join(_HERE, "libaxipcg.so")
 
 OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 Z_DIRICHLET, Z_NEUMANN = 0, 1

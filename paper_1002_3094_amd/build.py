@@ -59,5 +59,46 @@ def build(verbose: bool = False, extra=None) -> str:
     return LIB
 
 
+# Host-side sanitizer build (AddressSanitizer + UndefinedBehaviorSanitizer on
+# the host code only; the device code is compiled unoptimised, to keep the
+# build short, and is not meant to run): for CPU-only runs of the boundary's
+# argument validation and handle logic.  Load it with the compiler's ASan runtime preloaded
+# (san_runtime()) and AXIPCG_LIB pointing at it.
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+
+
+def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(out_dir, exist_ok=True)
+    inc = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    base = ["--offload-arch=gfx950", "-O1", "-Xarch_device", "-O0", "-std=c++17", "-fPIC"]
+
+    def compile_one(src):
+        obj = os.path.join(out_dir, os.path.basename(src)[:-4] + ".o")
+        cmd = [hipcc, *base, *SAN_FLAGS, *inc, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        objs = list(ex.map(compile_one, sources()))
+    lib = os.path.join(out_dir, "libaxipcg_san.so")
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *SAN_FLAGS, "-o", lib, *objs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return lib
+
+
+def san_runtime() -> str:
+    """The ASan runtime of the compiler behind hipcc (to preload)."""
+    hits = sorted(glob.glob("/opt/rocm/lib/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise FileNotFoundError("clang's ASan runtime is not installed")
+    return hits[-1]
+
+
 if __name__ == "__main__":
     print(build(verbose=True, extra=sys.argv[1:]))
