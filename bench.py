@@ -109,12 +109,11 @@ def _block(text, start):
 
 def source_sha():
     """Hash of the source text the roofline kernel (the PCG SpMV) is built
-    from: its body, kernel and stencil helpers and launch size in pcg.hip, and
+    from: its kernel, stencil helpers and launch size in pcg.hip, and
     the state, slot layout and reduction helpers it uses from common.h."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1002_3094_amd", "csrc")
     pcg = open(os.path.join(csrc, "pcg.hip")).read()
-    h.update(_block(pcg, "inline unsigned row_blocks").encode())
     h.update(pcg[pcg.index("struct Pair {"):pcg.index("// Chebyshev step of eq. (8)")].encode())
     com = open(os.path.join(csrc, "common.h")).read()
     for start in ("struct PcgState {", "enum Slot {", "constexpr int MAX_PARTIALS",
