@@ -68,10 +68,11 @@ k_strip_reduced(const T *__restrict__ red_e, const T *__restrict__ red_g, T *__r
     extern __shared__ char smem_raw[];
     T *base = reinterpret_cast<T *>(smem_raw);
     const int l0 = xcd_swizzle(blockIdx.x, N / MT) * MT;
-    strip_stage2<T, true>(red_e, red_g, ln, nr, N, G, l0, MT, base);
+    constexpr bool VEC = MT % (16 / (int)sizeof(T)) == 0;   // 16-byte staging loads
+    strip_stage2<T, VEC>(red_e, red_g, ln, nr, N, G, l0, MT, base);
     if (g.mode != 0 && tridiag_gate(st, partials, g, red, blockIdx.x) != ST_RUN) return;
     __syncthreads();
-    strip_solve2<T, R, LMAX, true>(red_x, ln, nr, N, G, l0, MT, base);
+    strip_solve2<T, R, LMAX, VEC>(red_x, ln, nr, N, G, l0, MT, base);
 }
 
 template <typename T, int BC, int MODE, int R2, int R>
@@ -122,6 +123,13 @@ RedBufs<T> red_bufs(const Operator &op, int R)
 // modes per reduced-system workgroup: 32 bytes of each strip's row
 template <typename T>
 constexpr int red_mt() { return 32 / (int)sizeof(T); }
+template <typename T>
+int red_mt_for(int nz)
+{
+    int mt = red_mt<T>();
+    while (mt > 2 && nz / mt < 256) mt /= 2;
+    return mt;
+}
 
 // Dynamic LDS above the default 64 KiB needs the kernel's attribute, set
 // once per kernel.
@@ -173,10 +181,9 @@ void inv_r(const Operator &op, const ZinvArgs &a, hipStream_t s)
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-template <typename T, int R, int LM>
-void red_launch(const Operator &op, const TriGate &g, hipStream_t s)
+template <typename T, int R, int LM, int MT>
+void red_launch_mt(const Operator &op, const TriGate &g, hipStream_t s)
 {
-    constexpr int MT = red_mt<T>();
     const RedBufs<T> rb = red_bufs<T>(op, R);
     const int G = op.nr / R;
     const size_t shm = strip_red_lds<T>(op.nr, G, MT);
@@ -185,6 +192,17 @@ void red_launch(const Operator &op, const TriGate &g, hipStream_t s)
     hipLaunchKernelGGL((k_strip_reduced<T, R, LM, MT>), dim3(op.nz / MT), dim3(64 * MT), shm, s, rb.e, rb.g, rb.x,
                        lines_of<T>(op), g.state, op.partials, g, op.nr, op.nz, G);
     AXI_CHECK_HIP(hipGetLastError());
+}
+
+// Modes per workgroup: up to red_mt (one 32-byte piece of a strip's row), but
+// no more than leaves 256 workgroups, one per CU (at least 2 modes)
+template <typename T, int R, int LM>
+void red_launch(const Operator &op, const TriGate &g, hipStream_t s)
+{
+    const int mt = red_mt_for<T>(op.nz);
+    if (mt >= 8) red_launch_mt<T, R, LM, (red_mt<T>() >= 8 ? 8 : 2)>(op, g, s);
+    else if (mt >= 4) red_launch_mt<T, R, LM, 4>(op, g, s);
+    else red_launch_mt<T, R, LM, 2>(op, g, s);
 }
 
 template <typename T, int R>
@@ -268,7 +286,7 @@ bool usable_t(const Operator &op, int R)
     if (R != 4 && R != 8) return false;
     if (strip_r2<T>(op.nz) == 0 || op.nr % R != 0) return false;
     const int G = op.nr / R;
-    return G >= 1 && G <= 1024 && strip_red_lds<T>(op.nr, G, red_mt<T>()) <= 160 * 1024;
+    return G >= 1 && G <= 1024 && strip_red_lds<T>(op.nr, G, red_mt_for<T>(op.nz)) <= 160 * 1024;
 }
 
 }  // namespace
