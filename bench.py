@@ -40,17 +40,17 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic bytes per grid point of each PCG kernel class with the FP32
 # preconditioner (FP64 = 8 B, FP32 = 4 B per value).
-BYTES_PER_POINT = {
+BYTES_PER_POINT = {   # one PCG iteration, FP32 preconditioner in 4-row strips
     "spmv": 56,      # read z, p_old, D, CR, CZ; write p, q
-    "zfwd": 52,      # read x, r, p, q; write x, r, spectral (f32)
-    "tridiag": 8,    # read + write spectral (f32)
-    "zinv": 20,      # read spectral (f32), r; write z
+    "zfwd": 53,      # read x, r, p, q; write x, r, 3/4 of f' (f32), E1 and G0 (2 f32 per strip and mode)
+    "tridiag": 3,    # read E1, G0; write X (f32 per strip and mode)
+    "zinv": 21,      # read 3/4 of f', X of the strip and the one before, r; write z
 }
 PRECOND_BYTES_PER_POINT = 32  # r (8) -> spectral (4+4) -> spectral (4+4) -> z (8)
 PRECOND_BYTES_PER_POINT_FP64 = 48  # r (8) -> spectral (8+8) -> spectral (8+8) -> z (8)
 KERNEL_IDS = {"spmv": 0, "zfwd": 1, "tridiag": 2, "zinv": 3}
 PROFILE_EVERY = 8   # time one launch in 8 of the roofline kernel inside the timed loop
-KERNEL_SYMBOLS = {"spmv": "k_pcg_spmv", "zfwd": "k_zfwd", "tridiag": "k_tridiag", "zinv": "k_zinv"}
+KERNEL_SYMBOLS = {"spmv": "k_pcg_spmv", "zfwd": "k_strip_fwd", "tridiag": "k_strip_reduced", "zinv": "k_strip_inv"}
 
 
 def parse():
@@ -84,6 +84,8 @@ def parse():
                          "default, 0 = the per-mode r-solve over whole lines")
     ap.add_argument("--fused", type=int, default=0, choices=[0, 1],
                     help="1: the single-launch preconditioner for FP32 applies and PCG iterations")
+    ap.add_argument("--precond-variants", default="",
+                    help="with --precond-only: comma list of variant keys (e.g. fp32_strips8); default all")
     ap.add_argument("--precond-only", type=int, default=0, metavar="N",
                     help="only time standalone preconditioner applies on an N x N layered medium (FP32 "
                          "then FP64, --steps applies each) and print their rates; the run to profile "
@@ -276,10 +278,10 @@ def large_measure(ax, torch, n, n_harm, seed):
     return rec
 
 
-def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
+def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64"), only=None):
     """Standalone preconditioner applies z = B^{-1} r on the n x n layered
     medium, timed with HIP events on the current stream over `reps` applies
-    after three untimed ones."""
+    after three untimed ones (`only`: the variant keys to run, else all)."""
     import synth
     inp = synth.laguerre_series_inputs(n, n, seed=seed)
     op = ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"])
@@ -292,6 +294,9 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
     variants = [(name, rows, False) for name in precs for rows in (4, 8, 0)] + [("fp32", 4, True)]
     for name, rows, one in variants:
         prec = ax.PREC_FP32 if name == "fp32" else ax.PREC_FP64
+        key = f"{name}_single_launch" if one else (f"{name}_strips{rows}" if rows else f"{name}_per_mode")
+        if only and key not in only:
+            continue
         ax.op_set_strips(op, rows)
         ax.op_set_fused(op, one)
         if rows and not ax.op_strips_info(op, prec)[0]:
@@ -309,7 +314,6 @@ def precond_measure(ax, torch, n, reps, seed=101, precs=("fp32", "fp64")):
         pc_s = e0.elapsed_time(e1) / 1e3 / reps
         bpp = PRECOND_BYTES_PER_POINT if prec == ax.PREC_FP32 else PRECOND_BYTES_PER_POINT_FP64
         gbs = bpp * n * n / pc_s / 1e9
-        key = f"{name}_single_launch" if one else (f"{name}_strips{rows}" if rows else f"{name}_per_mode")
         rec[key] = {"applies_per_s": round(1.0 / pc_s, 1), "mean_us": round(pc_s * 1e6, 2), "bytes_per_point": bpp,
                     "gbs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4),
                     "min_bytes_per_point": 16, "gbs_at_min_bytes": round(16 * n * n / pc_s / 1e9, 1)}
@@ -525,15 +529,16 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    if a.precond_only:
-        print(json.dumps(precond_measure(ax, torch, a.precond_only, a.steps)), flush=True)
-        return
     if a.copy_calibration:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
+    if a.precond_only:
+        only = [v for v in a.precond_variants.split(",") if v] if a.precond_variants else None
+        print(json.dumps(precond_measure(ax, torch, a.precond_only, a.steps, only=only)), flush=True)
+        return
     modes = [m for m in a.modes.split(",") if m]
     if a.headline not in modes:
         modes.append(a.headline)
