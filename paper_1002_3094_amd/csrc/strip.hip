@@ -123,11 +123,14 @@ RedBufs<T> red_bufs(const Operator &op, int R)
 // modes per reduced-system workgroup: 32 bytes of each strip's row
 template <typename T>
 constexpr int red_mt() { return 32 / (int)sizeof(T); }
+// Modes per workgroup for nr rows in G strips: red_mt, halved (down to 2)
+// only while the LDS stage would not fit (FP64 with 1024 strips).  Fewer
+// modes per workgroup than red_mt made PCG iterations slower at 1024^2.
 template <typename T>
-int red_mt_for(int nz)
+int red_mt_for(int nr, int G)
 {
     int mt = red_mt<T>();
-    while (mt > 2 && nz / mt < 256) mt /= 2;
+    while (mt > 2 && strip_red_lds<T>(nr, G, mt) > 160 * 1024) mt /= 2;
     return mt;
 }
 
@@ -194,12 +197,10 @@ void red_launch_mt(const Operator &op, const TriGate &g, hipStream_t s)
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-// Modes per workgroup: up to red_mt (one 32-byte piece of a strip's row), but
-// no more than leaves 256 workgroups, one per CU (at least 2 modes)
 template <typename T, int R, int LM>
 void red_launch(const Operator &op, const TriGate &g, hipStream_t s)
 {
-    const int mt = red_mt_for<T>(op.nz);
+    const int mt = red_mt_for<T>(op.nr, op.nr / R);
     if (mt >= 8) red_launch_mt<T, R, LM, (red_mt<T>() >= 8 ? 8 : 2)>(op, g, s);
     else if (mt >= 4) red_launch_mt<T, R, LM, 4>(op, g, s);
     else red_launch_mt<T, R, LM, 2>(op, g, s);
@@ -286,7 +287,7 @@ bool usable_t(const Operator &op, int R)
     if (R != 4 && R != 8) return false;
     if (strip_r2<T>(op.nz) == 0 || op.nr % R != 0) return false;
     const int G = op.nr / R;
-    return G >= 1 && G <= 1024 && strip_red_lds<T>(op.nr, G, red_mt_for<T>(op.nz)) <= 160 * 1024;
+    return G >= 1 && G <= 1024 && strip_red_lds<T>(op.nr, G, red_mt_for<T>(op.nr, G)) <= 160 * 1024;
 }
 
 }  // namespace

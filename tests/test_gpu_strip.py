@@ -45,10 +45,11 @@ def _backward(orc, oop, r, z, bc):
 
 def _red_lds(nr, nz, G, prec):
     elem = 4 if prec == 0 else 8
+    lds = lambda mt: (3 * (nr + nr // 32 + 1) + 2 * mt * G) * elem  # noqa: E731
     mt = 32 // elem
-    while mt > 2 and nz // mt < 256:
+    while mt > 2 and lds(mt) > 160 * 1024:
         mt //= 2
-    return (3 * (nr + nr // 32 + 1) + 2 * mt * G) * elem
+    return lds(mt)
 
 
 STRIP_SHAPES = [(4, 256, 0), (8, 512, 1), (200, 1024, 0), (256, 256, 1), (1024, 1024, 0), (4096, 256, 0),
@@ -75,8 +76,8 @@ def test_strip_precond_matches_oracle(ax, orc, nr, nz, bc, prec):
             ax.op_set_strips(op, rows)
             active, G = ax.op_strips_info(op, prec)
             # the reduced solve stages the r-line arrays and mt modes of
-            # reduced data in LDS (mt halved down to 2 while the grid has
-            # fewer than 256 workgroups): usable while that fits 160 KiB
+            # reduced data in LDS (mt halved down to 2 while that exceeds
+            # 160 KiB): usable while it fits
             expect = rows > 0 and _red_lds(nr, nz, nr // rows, prec) <= 160 * 1024
             used = 4 if (rows and prec == ax.PREC_FP32 and nz == 2048) else rows   # the solves' height
             assert active == expect and G == (nr // used if expect else 0)
