@@ -222,13 +222,18 @@ k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double
             const Pair az = row(zw[1], zw[2], zw[0], zl, zr);
             const Pair ap = row(pw[1], pw[2], pw[0], pl, pr);
             if (!have_beta) {   // scalars once per workgroup, after the first row's loads
-                if (st->done) return;
+                // every state field read at once (the r.z slot needed depends
+                // on iters), their latency overlapping the reduction; the
+                // stop flag is acted on after it (every workgroup alike)
+                const int done = st->done;
                 k_it = st->iters;
+                const double rho_slot[2] = {st->rho[0], st->rho[1]};
                 const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
+                if (done) return;
                 if (k_it > 0) {
                     double num = rho;
                     if (PR) num -= block_total(partials + SLOT_RZOLD * MAX_PARTIALS, n_rz, red);
-                    beta = num / st->rho[(k_it - 1) & 1];
+                    beta = num / rho_slot[(k_it - 1) & 1];
                 }
                 if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k_it & 1] = rho;
                 have_beta = true;

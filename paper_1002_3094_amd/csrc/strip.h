@@ -373,6 +373,9 @@ strip_phase3(const T *__restrict__ fprime, const T *__restrict__ red_x, double *
         rwv[t] = ln.rw[i0 + t];
     }
     const T cbm = s > 0 ? ln.cb[i0 - 1] : (T)0;
+    // a stopped solve (every workgroup alike) returns here, its loads already
+    // issued rather than waiting on the flag before them
+    if (MODE != 0 && st->done) return;
     __syncthreads();
     for (int l = threadIdx.x; l < N; l += NT) {
         const T lam = ln.lam[l];

@@ -82,7 +82,6 @@ k_strip_inv(const T *__restrict__ fprime, const T *__restrict__ red_x, double *_
             const typename vec2_of<T>::type *__restrict__ tw, const typename vec2_of<T>::type *__restrict__ pt,
             Lines<T> ln, int nr, double *__restrict__ dinc, double tau, double rho2)
 {
-    if (MODE != 0 && st->done) return;
     extern __shared__ char smem_raw[];
     strip_phase3<T, BC, MODE, R2, R>(fprime, red_x, zout, r, st, partials, pr, tw, pt, ln, nr, dinc, tau, rho2,
                                      blockIdx.x, reinterpret_cast<T *>(smem_raw));

@@ -97,16 +97,20 @@ zfwd_w_body(const double *__restrict__ rin, double *__restrict__ x, double *__re
             wN[j][k0] = ld_tw<T>(tw, m);
             cP[j][k0] = ld_tw<T>(pt, m);
         }
+    // (the stop flag before the reduction: deferring it past the reduction,
+    // as the other PCG kernels do, made the 2048-point forward kernel slower)
     if (st && st->done) return false;
     double alpha = 0.0;
     if (FUSED) {
-        const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
         const int k_it = st->iters;
+        // both r.z slots read now: the loads overlap the reduction
+        const double rho_slot[2] = {st->rho[0], st->rho[1]};
+        const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
         if (!(pq > 0.0) || !(pq < 1e308)) {
             if (blk == 0 && threadIdx.x == 0) st->done = ST_BREAK;
             return false;
         }
-        alpha = st->rho[k_it & 1] / pq;
+        alpha = rho_slot[k_it & 1] / pq;
         if (blk == 0 && threadIdx.x == 0) st->cur = k_it;
     }
 
@@ -343,13 +347,16 @@ __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ part
                                    int vb)
 {
     if (g.mode == 1) {
-        if (st->done) return st->done;   // stopped earlier: leave the state alone
+        // every state field read at once, their latency overlapping the
+        // reduction
+        const int done = st->done, k_it = st->cur, maxit = st->maxit;
+        const double tol2 = st->tol2;
         const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
-        const int k_it = st->cur;
+        if (done) return done;   // stopped earlier: leave the state alone
         int status = ST_RUN;
         if (!(rr == rr) || rr > 1e300) status = ST_BREAK;
-        else if (rr <= st->tol2) status = ST_CONV;
-        else if (k_it + 1 >= st->maxit) status = ST_MAXIT;
+        else if (rr <= tol2) status = ST_CONV;
+        else if (k_it + 1 >= maxit) status = ST_MAXIT;
         if (vb == 0 && threadIdx.x == 0) {
             st->rr = rr;
             st->iters = k_it + 1;
