@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-experiment pipeline record")
     ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 series record")
     ap.add_argument("--large-harmonics", type=int, default=100, help="timed harmonics of the 2048^2 record")
+    ap.add_argument("--no-xl", action="store_true", help="skip the 4096^2 series record")
+    ap.add_argument("--xl-harmonics", type=int, default=20, help="timed harmonics of the 4096^2 record")
     ap.add_argument("--paper-harmonics", type=int, default=2000,
                     help="harmonics of the paper-experiment records (the paper's n = 2000)")
     ap.add_argument("--no-refinement", action="store_true",
@@ -686,6 +688,10 @@ def main():
             out["paper_refinement"] = paper_refinement(ax, torch, a.paper_harmonics)
     if not a.no_large:
         out["series_2048"] = large_measure(ax, torch, 2048, a.large_harmonics, a.seed)
+    if not a.no_xl:
+        # rows of 4096: the block-wide transforms and the per-mode r-solve;
+        # a working set of about 3 GB, far beyond the 256 MB Infinity Cache
+        out["series_4096"] = large_measure(ax, torch, 4096, a.xl_harmonics, a.seed)
     if not a.no_cpu_baseline:
         rec, us = cpu_baseline(inp, rtol, a.cpu_seconds)
         out["cpu_baseline"] = rec

@@ -99,7 +99,8 @@ typedef struct {
  * face takes its cell's value).  kbar <= 0 selects the mean of kappa, qbar < 0
  * the mean of q (the paper's footnote to eq. (37) uses the mid-range; PCG is
  * invariant to scaling B, so this only changes iteration counts).
- * Limits: 2 <= nr <= 4096; nz a power of two with 2 <= nz <= 2048; lr, lz > 0;
+ * Limits: 2 <= nr <= 4096; nz a power of two with 2 <= nz <= 4096 (rows of
+ * 4096 take the block-wide transforms and the per-mode r-solve); lr, lz > 0;
  * kappa > 0 and q >= 0, all finite.  Allocates ~ (10 * 8) bytes per cell of
  * device memory.  *out receives the handle. */
 int axipcg_op_create(int nr, int nz, double lr, double lz, int bc_z,
@@ -218,7 +219,7 @@ int axipcg_op_bounds(axipcg_op_t op, double *gamma1, double *gamma2);
  * over the whole batch, so the launch count per iteration does not grow with
  * n; each problem stops on its own test.  st (host, may be NULL) receives n
  * statistics.  Returns the worst status (AXIPCG_EBREAKDOWN, then
- * AXIPCG_ENOTCONV, else AXIPCG_OK).  Members need nr <= 1024 and nz >= 4; all
+ * AXIPCG_ENOTCONV, else AXIPCG_OK).  Members need nr <= 1024 and 4 <= nz <= 2048; all
  * handles must live on the current device.  Synchronises the stream. */
 int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *const *b, double *const *x,
                        double rtol, int maxit, int prec, unsigned flags, axipcg_stats *st, void *stream);

@@ -184,7 +184,7 @@ extern "C" int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *c
             AXI_REQUIRE(v[p] && b[p] && x[p], "NULL operator or vector in the batch");
             AXI_REQUIRE(b[p] != x[p], "b and x must not alias");
             AXI_REQUIRE(v[p]->nr <= 1024, "batch members need nr <= 1024");
-            AXI_REQUIRE(v[p]->nz % 4 == 0, "batch members need nz >= 4");
+            AXI_REQUIRE(v[p]->nz % 4 == 0 && v[p]->nz <= 2048, "batch members need nz in [4, 2048]");
             for (int q = 0; q < p; ++q) AXI_REQUIRE(v[q] != v[p], "an operator appears twice in the batch");
             rows += v[p]->nr;
         }

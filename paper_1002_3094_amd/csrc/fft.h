@@ -103,8 +103,11 @@ __device__ cx<T> *fft_stockham_part(cx<T> *a, cx<T> *b, int N, const typename ve
 }
 
 // Threads per row for a transform of length N.
+// Threads of a block-wide transform: N / 4 in [64, 256], and N / 8 above
+// N = 2048 (each thread handles eight elements).
 inline int fft_threads(int N)
 {
+    if (N > 2048) return N / 8;
     int t = N / 4;
     if (t < 64) t = 64;
     if (t > 256) t = 256;

@@ -290,23 +290,19 @@ k_cheb_update(const double *__restrict__ d, double *__restrict__ x, double *__re
     double acc = 0.0;
     for (int b = blockIdx.x; b < nr; b += gridDim.x) {
         const int i = xcd_swizzle(b, nr);
-#pragma unroll
-        for (int j = 0; j < SPMV_PAIRS; ++j) {
-            const int k = 2 * (threadIdx.x + j * 256);
-            if (k < nz) {
-                const size_t e = (size_t)i * nz + k;
-                const Pair dc = ld2(d + e);
-                const Pair ad = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc);
-                const Pair xc = ld2(x + e), rc = ld2(r + e);
-                double2 xn, rn;
-                xn.x = xc.a + dc.a;
-                xn.y = xc.b + dc.b;
-                rn.x = rc.a - ad.a;
-                rn.y = rc.b - ad.b;
-                *reinterpret_cast<double2 *>(x + e) = xn;
-                *reinterpret_cast<double2 *>(r + e) = rn;
-                acc += rn.x * rn.x + rn.y * rn.y;
-            }
+        for (int k = 2 * (int)threadIdx.x; k < nz; k += 2 * (int)blockDim.x) {
+            const size_t e = (size_t)i * nz + k;
+            const Pair dc = ld2(d + e);
+            const Pair ad = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc);
+            const Pair xc = ld2(x + e), rc = ld2(r + e);
+            double2 xn, rn;
+            xn.x = xc.a + dc.a;
+            xn.y = xc.b + dc.b;
+            rn.x = rc.a - ad.a;
+            rn.y = rc.b - ad.b;
+            *reinterpret_cast<double2 *>(x + e) = xn;
+            *reinterpret_cast<double2 *>(r + e) = rn;
+            acc += rn.x * rn.x + rn.y * rn.y;
         }
     }
     const double s = block_sum(acc, red);

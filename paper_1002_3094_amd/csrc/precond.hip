@@ -54,11 +54,11 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *b = a + N;
     V2 *twl = reinterpret_cast<V2 *>(b + N);
-    __shared__ double red[8];
+    __shared__ double red[RED_SLOTS];
 
     if (st && st->done) return;
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
-    constexpr int KPT = 8;   // elements per thread (N <= 2048, >= 256 threads for N >= 1024)
+    constexpr int KPT = 8;   // elements per thread (fft_threads gives N <= 8 blockDim.x)
     double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
     auto load = [&](int i) {
         const size_t row = (size_t)i * N;
@@ -140,8 +140,9 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     }
 }
 
+// (512 threads for N = 4096, 256 or fewer below)
 template <typename T, int BC, bool FUSED, bool TWLDS, int ROWS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
        const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
        double *__restrict__ partials, int n_pq,
@@ -172,13 +173,13 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
     cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
     cx<T> *b = a + N;
     V2 *twl = reinterpret_cast<V2 *>(b + N);
-    __shared__ double red[8];
+    __shared__ double red[RED_SLOTS];
     const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
 
     const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
     const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
     const T sq2 = (T)1.41421356237309504880;
-    constexpr int KPT = 8;   // N <= 2048, >= 256 threads for N >= 1024
+    constexpr int KPT = 8;   // fft_threads gives N <= 8 blockDim.x
     T ymv[KPT], ynv[KPT];
     auto Yval = [&](size_t row, int m) -> T {
         // unnormalised DCT-II coefficient Y_m of y
@@ -266,7 +267,7 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
 }
 
 template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_zinv(const T *__restrict__ spec, double *__restrict__ zout, const double *__restrict__ r,
        const PcgState *st, double *__restrict__ partials, bool pr,
        const typename vec2_of<T>::type *__restrict__ tw,
@@ -652,6 +653,15 @@ inline int transform_rows(int nr, int prec)
     return (prec == AXIPCG_PREC_FP64 && nr % 2 == 0 && nr >= 512) ? 2 : 1;
 }
 
+// Dynamic LDS above the default 64 KiB (FP64 rows of 4096) needs the
+// kernel's attribute, set once per kernel.
+inline void allow_transform_lds(const void *fn, size_t bytes, bool &done)
+{
+    if (done || bytes <= 65536) return;
+    AXI_CHECK_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    done = true;
+}
+
 template <typename T, int BC, bool TWL, int ROWS>
 void zfwd_ttr(const Operator &op, const ZfwdArgs &a, hipStream_t s)
 {
@@ -660,6 +670,9 @@ void zfwd_ttr(const Operator &op, const ZfwdArgs &a, hipStream_t s)
     const size_t shm = transform_lds<T>(N);
     const int thr = fft_threads(N);
     const dim3 grid(op.nr / ROWS);
+    static bool lds_set[2] = {false, false};
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zfwd<T, BC, true, TWL, ROWS>), shm, lds_set[0]);
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zfwd<T, BC, false, TWL, ROWS>), shm, lds_set[1]);
     if (a.fused)
         hipLaunchKernelGGL((k_zfwd<T, BC, true, TWL, ROWS>), grid, dim3(thr), shm, s, nullptr, a.x, a.r, a.p, a.q,
                            a.state, op.partials, a.n_pq, (T *)op.spec, tb.tw, tb.pt, op.nr, N);
@@ -729,6 +742,12 @@ void zinv_ttr(const Operator &op, const ZinvArgs &a, hipStream_t s)
     const size_t shm = transform_lds<T>(N);
     const int thr = fft_threads(N);
     const dim3 grid(op.nr / ROWS);
+    static bool lds_set[5] = {false, false, false, false, false};
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zinv<T, BC, 0, TWL, ROWS>), shm, lds_set[0]);
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zinv<T, BC, 1, TWL, ROWS>), shm, lds_set[1]);
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zinv<T, BC, 2, TWL, ROWS>), shm, lds_set[2]);
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zinv<T, BC, 3, TWL, ROWS>), shm, lds_set[3]);
+    allow_transform_lds(reinterpret_cast<const void *>(&k_zinv<T, BC, 4, TWL, ROWS>), shm, lds_set[4]);
     switch (a.mode) {
     case 0:
         hipLaunchKernelGGL((k_zinv<T, BC, 0, TWL, ROWS>), grid, dim3(thr), shm, s, (const T *)op.spec, a.zout,

@@ -207,7 +207,7 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
                       double qbar, hipStream_t s)
 {
     AXI_REQUIRE(nr >= 2 && nr <= 4096, "nr must be in [2, 4096]");
-    AXI_REQUIRE(is_pow2(nz) && nz >= 2 && nz <= 2048, "nz must be a power of two in [2, 2048]");
+    AXI_REQUIRE(is_pow2(nz) && nz >= 2 && nz <= 4096, "nz must be a power of two in [2, 4096]");
     AXI_REQUIRE(std::isfinite(lr) && lr > 0 && std::isfinite(lz) && lz > 0, "lr and lz must be positive");
     const bool nodes = (bc_z & AXIPCG_GRID_NODES) != 0;
     bc_z &= ~AXIPCG_GRID_NODES;

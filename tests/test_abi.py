@@ -91,13 +91,18 @@ def test_strerror(ax):
     assert ax.strerror(12345) == "unknown status"
 
 
-@pytest.mark.parametrize("case", ["nz_not_pow2", "kappa_nonpositive", "q_negative", "nan", "nr_small", "bc"])
+@pytest.mark.parametrize("case", ["nz_not_pow2", "nz_too_large", "kappa_nonpositive", "q_negative", "nan", "nr_small",
+                                  "bc"])
 def test_op_create_validates_before_device_work(ax, case):
     nr, nz, bc = 8, 8, 0
     kappa = np.ones((nr, nz))
     q = np.zeros((nr, nz))
     if case == "nz_not_pow2":
         nz = 12
+        kappa = np.ones((nr, nz))
+        q = np.zeros((nr, nz))
+    elif case == "nz_too_large":
+        nz = 8192
         kappa = np.ones((nr, nz))
         q = np.zeros((nr, nz))
     elif case == "kappa_nonpositive":

@@ -25,7 +25,7 @@ def ax():
     return axipcg
 
 
-CASES = [(64, 64, 0), (128, 256, 1), (96, 64, 0), (256, 256, 0), (42, 1024, 1)]
+CASES = [(64, 64, 0), (128, 256, 1), (96, 64, 0), (256, 256, 0), (42, 1024, 1), (20, 4096, 1)]
 
 
 @pytest.mark.parametrize("nr,nz,bc", CASES)
@@ -64,7 +64,11 @@ def test_iterates_match_oracle(ax, orc, nr, nz, bc):
         assert st["code"] == ax.ENOTCONV and st["iters"] == k
         e = rel(host(x), yo)
     log(f"  after {k} steps: rel diff {e:.2e}")
-    assert e <= 1e-11
+    # two FP64 evaluations of the same 25-step polynomial differ by rounding
+    # only; the per-step difference grows with the row length (the
+    # transforms' log2 N rounding and the z-modes' spread, h_z^-2), so the
+    # bound scales with nz beyond 1024
+    assert e <= 1e-11 * max(1, nz // 1024)
 
 
 @pytest.mark.parametrize("nr,nz,bc", CASES)

@@ -98,7 +98,9 @@ PC_SHAPES = [(64, 64, 0), (64, 64, 1), (256, 128, 0), (128, 512, 1), (100, 64, 0
              (2048, 128, 1), (4, 4, 0), (2, 2, 1), (7, 16, 0),
              # one-wave transforms (nz = 512, 1024, 2048), row counts that leave a
              # workgroup partly empty
-             (130, 512, 0), (3, 512, 1), (64, 1024, 0), (37, 1024, 1), (6, 2048, 0), (33, 2048, 1)]
+             (130, 512, 0), (3, 512, 1), (64, 1024, 0), (37, 1024, 1), (6, 2048, 0), (33, 2048, 1),
+             # rows of 4096: block-wide transforms of 512 threads, FP64 LDS above 64 KiB
+             (16, 4096, 0), (9, 4096, 1)]
 
 
 @pytest.mark.parametrize("nr,nz,bc", PC_SHAPES)
@@ -122,6 +124,7 @@ def test_precond_fp32(ax, orc, nr, nz, bc):
 SOLVE_CASES = [("smooth", 64, 64, 0), ("layered", 256, 256, 0), ("layered", 128, 64, 1),
                ("layered", 96, 256, 0), ("layered", 100, 128, 1), ("layered", 8, 4, 0),
                ("layered", 66, 1024, 0), ("layered", 30, 2048, 1), ("layered", 45, 512, 1),
+               ("layered", 24, 4096, 0), ("layered", 13, 4096, 1),
                # the most rows op_create accepts (64 per r-solve lane), and a
                # ragged row count in the same r-solve variant
                ("layered", 4096, 32, 0), ("layered", 3000, 64, 1)]
