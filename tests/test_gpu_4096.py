@@ -11,7 +11,9 @@ the C-ABI.
   own apply of A gives a true residual within 1e-9 of ||b|| for each, and the
   two solutions of the same system agree to 1e-8 (the solve's parity
   property at any size; the oracle's full solve at 16.8 M points would take
-  minutes).
+  minutes);
+* solves whose row count leaves the SpMV's 16-row tiles ragged (2063 x 2048,
+  1031 x 4096), checked the same way.
 """
 import numpy as np
 import pytest
@@ -79,3 +81,21 @@ def test_pcg_4096(ax, orc, medium):
     d = rel(sols[ax.PREC_FP32], sols[ax.PREC_FP64])
     log(f"  FP32 vs FP64 preconditioner solutions: {d:.2e}")
     assert d <= 1e-8
+
+
+# 2063 = 128 * 16 + 15 rows of 2048 (and 1031 = 64 * 16 + 7 of 4096): the
+# SpMV takes tiles of 16 rows there, the last one partly empty
+@pytest.mark.parametrize("nr,nz", [(2063, 2048), (1031, 4096)])
+def test_pcg_ragged_spmv_tiles(ax, orc, nr, nz):
+    kappa, q = synth.medium_layered(nr, nz, 5)
+    f = synth.ricker_source(nr, nz, 1.0, 1.0, 0.3, 0.01)
+    oop = orc.operator_from_cells(kappa, q, bc_z=1)
+    bo = orc.rhs(oop, f)
+    with ax.op_create(kappa, q, bc_z=1) as op:
+        x = dev(np.zeros((nr, nz)))
+        st = ax.pcg_solve(op, dev(bo), x, rtol=1e-10, maxit=500, prec=ax.PREC_FP32, flags=ax.FLAG_TRUE_RESIDUAL)
+        xg = host(x)
+    true = np.linalg.norm(bo - orc.apply(oop, xg)) / np.linalg.norm(bo)
+    log(f"pcg {nr}x{nz}: iters={st['iters']} relres={st['relres_rec']:.2e} oracle true residual={true:.2e}")
+    assert st["code"] == ax.OK and st["relres_rec"] <= 1e-10
+    assert true <= 1e-9
