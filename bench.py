@@ -19,7 +19,11 @@ Modes (each a fresh series of warmup + steps harmonics on the same medium):
   C  FP32 preconditioner, learned guess with its guard (headline), the network
      trained beforehand (untimed) on harmonics of eight other media
 The first harmonics of the headline mode are checked against the FP64 oracle
-chain that the CPU-baseline leg computes on the same inputs.
+chain that the CPU-baseline leg computes on the same inputs, and harmonics
+across the timed range (the last one included) against the oracle's solve of
+the same right-hand side, with the iterations PCG needs to first reach an
+error of 1e-8 there (untimed).  A fixed 400-harmonic comparison of B, X and C
+on the two held-out media (seeds 101, 102) follows.
 
 Prints one JSON line (see the design doc for the fields).
 """
@@ -75,6 +79,10 @@ def parse():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper-experiment pipeline record")
     ap.add_argument("--no-large", action="store_true", help="skip the 2048^2 series record")
     ap.add_argument("--large-harmonics", type=int, default=100, help="timed harmonics of the 2048^2 record")
+    ap.add_argument("--no-held-out", action="store_true",
+                    help="skip the fixed-length comparison on the two held-out media")
+    ap.add_argument("--held-out-harmonics", type=int, default=400,
+                    help="timed harmonics per mode and medium of the held-out comparison")
     ap.add_argument("--no-xl", action="store_true", help="skip the 4096^2 series record")
     ap.add_argument("--xl-harmonics", type=int, default=20, help="timed harmonics of the 4096^2 record")
     ap.add_argument("--paper-harmonics", type=int, default=2000,
@@ -403,6 +411,49 @@ def paper_refinement(ax, torch, n_harm, grids=(256, 512, 1024, 2048), length=1.0
             "error_ratio_per_halving": [round(e0 / e1, 3) for e0, e1 in zip(errs, errs[1:])]}
 
 
+def held_out_measure(ax, torch, a, net, seeds=(101, 102), modes=("B", "X", "C")):
+    """The learned guess evaluated as trained: a fixed number of harmonics
+    (400 by default, whatever --steps is) on each held-out medium, for the
+    plain previous-harmonic guess (B), the extrapolation guard without the
+    network (X) and the network with its guard (C), each timed after 5 warmup
+    harmonics; the guard's picks from an untimed replay of the C series."""
+    import synth
+    from paper_1002_3094_amd import series
+    n = a.held_out_harmonics
+    rec = {"workload": f"laguerre_{a.nr}x{a.nz}_held_out", "harmonics": n, "warmup": 5, "rtol": 1e-10,
+           "seeds": {}}
+    for seed in seeds:
+        inp = synth.laguerre_series_inputs(a.nr, a.nz, seed=seed)
+        r = {}
+        with ax.op_create(inp["kappa"], inp["q"], lr=inp["lr"], lz=inp["lz"]) as op:
+            g = ax.laguerre_coeffs(n + 5, inp["eta"], inp["ft"], inp["t"][-1])
+            for mode in modes:
+                prec_name, guess, solver = MODES[mode]
+                if guess in ("nn", "nn_poly") and net is None:
+                    continue
+                prec = ax.PREC_FP32 if prec_name == "fp32" else ax.PREC_FP64
+                s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+                s.run(5, guess, prec, net=net, solver=solver)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = s.run(n, guess, prec, net=net, solver=solver)
+                torch.cuda.synchronize()
+                el = max(time.perf_counter() - t0, st.gpu_ms / 1e3)
+                assert all(c == ax.OK for c in st.status), st.status
+                r[mode] = {"guess": guess, "harmonics_per_s": round(n / el, 2),
+                           "iters_per_harmonic": round(float(np.mean(st.iters)), 3)}
+                if guess == "nn_poly":
+                    s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
+                    st = s.run(n + 5, guess, prec, net=net, want_info=True, solver=solver)
+                    k = ax.history_len(guess) + 1
+                    r[mode]["guard_picks_by_candidate"] = np.bincount(st.choice, minlength=k).tolist()
+        if "B" in r:
+            for mode in r:
+                r[mode]["iters_vs_B"] = round(r[mode]["iters_per_harmonic"] / r["B"]["iters_per_harmonic"], 3)
+        rec["seeds"][str(seed)] = r
+    return rec
+
+
 def batch_measure(ax, torch, prec, reps=3):
     """64 independent uneven problems (N_r, N_z ~ U{256,512,1024}, seeds
     1000+p): one batched solve versus the same problems solved one by one."""
@@ -461,19 +512,63 @@ def per_step_parity(ax, series, op, g, inp, a, net, last_b, last_u):
     marks = sorted({a.warmup + (a.steps * q) // 4 for q in (1, 2, 3)} | {n_harm - 1})
     s = series.LaguerreSeries(op, g, inp["src_i"], inp["src_k"], kappa=inp["kappa"])
     st = series.SeriesStats()
-    cases = []
+    cases, reach = [], []
     for m in marks:
         if m + 1 > s.m:
             s.run_harmonics(m + 1 - s.m, guess, prec, 1e-10, 1000, st, net=net, solver=solver)
-        cases.append((m, s.b.cpu().numpy(), s.u1.cpu().numpy()))
+        ref = oracle.solve_reference(oop, s.b.cpu().numpy(), rtol=1e-13, maxit=1000)
+        reach.append(first_reach(ax, op, s, ref, prec, guess, net, st.iters[-1]))
+        cases.append((m, s.b.cpu().numpy(), s.u1.cpu().numpy(), ref))
     replay_equal = bool(np.array_equal(cases[-1][1], last_b) and np.array_equal(cases[-1][2], last_u))
-    cases[-1] = (n_harm - 1, last_b, last_u)
-    errs = []
-    for m, b, u in cases:
-        ref = oracle.solve_reference(oop, b, rtol=1e-13, maxit=1000)
-        errs.append(float(np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300)))
-    return {"harmonics": [m for m, _, _ in cases], "rel_err": errs, "max_rel_err": max(errs),
-            "oracle_rtol": 1e-13, "last_timed_harmonic": n_harm - 1, "replay_bitwise_equal_to_timed": replay_equal}
+    cases[-1] = (n_harm - 1, last_b, last_u, cases[-1][3])
+    errs = [float(np.linalg.norm(u - ref) / max(np.linalg.norm(ref), 1e-300)) for _, _, u, ref in cases]
+    return {"harmonics": [c[0] for c in cases], "rel_err": errs, "max_rel_err": max(errs),
+            "oracle_rtol": 1e-13, "last_timed_harmonic": n_harm - 1, "replay_bitwise_equal_to_timed": replay_equal,
+            "iterations_to_1e-8_error": reach}
+
+
+def first_reach(ax, op, s, ref, prec, guess, net, iters_stop, kmax=80):
+    """Untimed diagnostic at the harmonic m the series `s` has just solved:
+    PCG restarted from the harmonic's initial guess, stopped after k = 1, 2,
+    ... iterations, until its iterate's error against the oracle's solution
+    `ref` of the same A u = b_m falls to 1e-8 relative.  Done for the
+    previous-harmonic guess u_{m-1} and for the guess of the mode itself
+    (recomputed from the history the step started from); reported next to
+    the iterations the 1e-10 residual test took."""
+    torch = s.torch
+    b = s.b
+    nh = ax.history_len(guess)
+    hist = s.hist[1:nh] + [s.u]   # u_{m-1}, u_{m-2}, ... as the step saw them
+    nref = max(np.linalg.norm(ref), 1e-300)
+    out = {"harmonic": s.m - 1, "iters_at_1e-10_residual": int(iters_stop)}
+    for name in dict.fromkeys(("prev", guess)):
+        x0 = torch.empty_like(b)
+        if name == "prev":
+            x0.copy_(hist[0])
+        elif name == "zero":
+            x0.zero_()
+        elif name == "extrap":
+            ax.guess_extrap(op, b, hist[0], hist[1], x0)
+        elif name == "poly":
+            ax.guess_poly(op, b, hist, x0)
+        elif name == "nn_poly":
+            ax.nn_guess_poly(op, net, b, hist, s.kappa, x0)
+        elif name == "nn":
+            ax.nn_guess(op, net, b, hist[0], hist[1], s.kappa, x0)
+        else:
+            raise ValueError(name)
+        x = torch.empty_like(b)
+        err0 = float(np.linalg.norm(x0.cpu().numpy() - ref) / nref)
+        reached = 0 if err0 <= 1e-8 else None
+        for k in range(1, kmax + 1):
+            if reached is not None:
+                break
+            x.copy_(x0)
+            ax.pcg_solve(op, b, x, rtol=1e-30, maxit=k, prec=prec)
+            if np.linalg.norm(x.cpu().numpy() - ref) / nref <= 1e-8:
+                reached = k
+        out[name] = {"guess_rel_err": err0, "iters": reached}
+    return out
 
 
 MODES = {   # (preconditioner, guess, solver)
@@ -680,6 +775,8 @@ def main():
     }
     if "A" in results:
         out["speedup_vs_plain_fp64"] = round(results[a.headline]["harmonics_per_s"] / results["A"]["harmonics_per_s"], 3)
+    if not a.no_held_out:
+        out["held_out"] = held_out_measure(ax, torch, a, net)
     if not a.no_batch:
         out["batch"] = batch_measure(ax, torch, ax.PREC_FP32)
     if not a.no_paper:
