@@ -121,12 +121,15 @@ def _block(text, start):
 
 def source_sha():
     """Hash of the source text the roofline kernel (the PCG SpMV) is built
-    from: its kernel, stencil helpers and launch size in pcg.hip, and
-    the state, slot layout and reduction helpers it uses from common.h."""
+    from: its stencil helpers (spmv.h, through the row-per-workgroup body),
+    its kernel and launch size in pcg.hip, and the state, slot layout and
+    reduction helpers it uses from common.h."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1002_3094_amd", "csrc")
+    hdr = open(os.path.join(csrc, "spmv.h")).read()
+    h.update(hdr[hdr.index("struct Pair {"):hdr.index("// r = b - A x;")].encode())
     pcg = open(os.path.join(csrc, "pcg.hip")).read()
-    h.update(pcg[pcg.index("struct Pair {"):pcg.index("// Chebyshev step of eq. (8)")].encode())
+    h.update(pcg[pcg.index("// The same step for one problem"):pcg.index("// Chebyshev step of eq. (8)")].encode())
     com = open(os.path.join(csrc, "common.h")).read()
     for start in ("struct PcgState {", "enum Slot {", "constexpr int MAX_PARTIALS",
                   "__device__ inline double block_sum(", "__device__ inline double block_total(",
@@ -456,7 +459,8 @@ def held_out_measure(ax, torch, a, net, seeds=(101, 102), modes=("B", "X", "C"))
 
 def batch_measure(ax, torch, prec, reps=3):
     """64 independent uneven problems (N_r, N_z ~ U{256,512,1024}, seeds
-    1000+p): one batched solve versus the same problems solved one by one."""
+    1000+p): one batched solve with a launch per phase, the same solve in one
+    cooperative launch, and the problems solved one by one."""
     import synth
     probs = [synth.problem_batch_member(p) for p in range(64)]
     ops, bs, xs = [], [], []
@@ -467,18 +471,24 @@ def batch_measure(ax, torch, prec, reps=3):
         ops.append(op)
         bs.append(b)
         xs.append(torch.zeros_like(b))
-    ax.batch_solve(ops, bs, xs, 1e-10, 1000, prec)      # warm-up
-    times, iters = [], []
-    for _ in range(reps):
-        for x in xs:
-            x.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        code, st = ax.batch_solve(ops, bs, xs, 1e-10, 1000, prec)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-        iters = [s["iters"] for s in st]
-        assert code == ax.OK
+
+    def timed(flags):
+        ax.batch_solve(ops, bs, xs, 1e-10, 1000, prec, flags)      # warm-up
+        times, iters = [], []
+        for _ in range(reps):
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, st = ax.batch_solve(ops, bs, xs, 1e-10, 1000, prec, flags)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            iters = [s["iters"] for s in st]
+            assert code == ax.OK
+        return min(times), iters
+
+    t_b, iters = timed(0)
+    t_s, iters_s = timed(ax.FLAG_SINGLE_LAUNCH)
     for x in xs:
         x.zero_()
     torch.cuda.synchronize()
@@ -490,10 +500,11 @@ def batch_measure(ax, torch, prec, reps=3):
     pts = sum(p.nr * p.nz for p in probs)
     for op in ops:
         op.close()
-    t_b = min(times)
     return {"workload": "batch_64_uneven_256-1024", "points": pts, "solves_per_s": round(64 / t_b, 1),
             "ms_per_batch": round(t_b * 1e3, 3), "sequential_solves_per_s": round(64 / t_seq, 1),
-            "iters_min_max": [min(iters), max(iters)]}
+            "iters_min_max": [min(iters), max(iters)],
+            "single_launch": {"solves_per_s": round(64 / t_s, 1), "ms_per_batch": round(t_s * 1e3, 3),
+                              "iters_min_max": [min(iters_s), max(iters_s)]}}
 
 
 def per_step_parity(ax, series, op, g, inp, a, net, last_b, last_u):

@@ -80,10 +80,11 @@ enum { AXIPCG_GRID_NODES = 0x100 };
  * residual recurrence and stop test are FP64 in both cases. */
 enum { AXIPCG_PREC_FP64 = 0, AXIPCG_PREC_FP32 = 1 };
 
-/* pcg_solve flags */
+/* pcg_solve flags (and batch_solve's) */
 enum {
     AXIPCG_FLAG_TRUE_RESIDUAL = 1u,  /* also compute ||b - A x|| / ||b|| at exit */
-    AXIPCG_FLAG_POLAK_RIBIERE = 2u   /* beta = r.(z - z_old) / rho_old (flexible CG) */
+    AXIPCG_FLAG_POLAK_RIBIERE = 2u,  /* beta = r.(z - z_old) / rho_old (flexible CG) */
+    AXIPCG_FLAG_SINGLE_LAUNCH = 4u   /* batch_solve only: the whole solve in one launch */
 };
 
 typedef struct {
@@ -220,7 +221,16 @@ int axipcg_op_bounds(axipcg_op_t op, double *gamma1, double *gamma2);
  * n; each problem stops on its own test.  st (host, may be NULL) receives n
  * statistics.  Returns the worst status (AXIPCG_EBREAKDOWN, then
  * AXIPCG_ENOTCONV, else AXIPCG_OK).  Members need nr <= 1024 and 4 <= nz <= 2048; all
- * handles must live on the current device.  Synchronises the stream. */
+ * handles must live on the current device.  Synchronises the stream.
+ *
+ * flags as for pcg_solve, plus AXIPCG_FLAG_SINGLE_LAUNCH: the whole solve,
+ * start to stop, in one cooperative launch whose resident workgroups take the
+ * same phases in turn with grid barriers between them (the host reads the
+ * states once, at the end).  The same operations in the same order as the
+ * launch-per-phase form (results equal up to the compiler's fused
+ * multiply-adds).  Members need nz <= 1024 and the device cooperative launches
+ * (else AXIPCG_EINVAL); AXIPCG_EDEVICE if a grid barrier gives up (every
+ * wait is bounded). */
 int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *const *b, double *const *x,
                        double rtol, int maxit, int prec, unsigned flags, axipcg_stats *st, void *stream);
 

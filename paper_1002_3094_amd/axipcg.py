@@ -25,7 +25,7 @@ OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 Z_DIRICHLET, Z_NEUMANN = 0, 1
 GRID_NODES = 0x100   # OR into bc_z: the paper's node grid (h = l / (N - 1/2)); Neumann z only
 PREC_FP64, PREC_FP32 = 0, 1
-FLAG_TRUE_RESIDUAL, FLAG_POLAK_RIBIERE = 1, 2
+FLAG_TRUE_RESIDUAL, FLAG_POLAK_RIBIERE, FLAG_SINGLE_LAUNCH = 1, 2, 4
 KERNEL_NONE, KERNEL_SPMV, KERNEL_ZFWD, KERNEL_TRIDIAG, KERNEL_ZINV = -1, 0, 1, 2, 3
 
 _lib = None

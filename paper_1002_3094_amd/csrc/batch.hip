@@ -8,6 +8,11 @@
 // number of launches per iteration does not grow with the number of problems
 // (four, plus one transform launch per extra transform plan present), and the
 // host reads all states back once per chunk of iterations.
+//
+// With AXIPCG_FLAG_SINGLE_LAUNCH the same phases run in one cooperative
+// launch for the whole solve (bsingle.hip), the host reading the states back
+// once at the end; the operations and their order are those of the launches
+// above.
 #include <cmath>
 #include <vector>
 
@@ -24,7 +29,10 @@ struct DevBuf {
 int batch_impl(int n, Operator *const *ops, const double *const *b, double *const *x, double rtol, int maxit,
                int prec, unsigned flags, axipcg_stats *st, hipStream_t s)
 {
-    const int M = (prec == AXIPCG_PREC_FP32) ? 4 : 2;   // modes per r-solve workgroup
+    const bool single = (flags & AXIPCG_FLAG_SINGLE_LAUNCH) != 0;
+    // modes per r-solve workgroup, one per wave: 256 threads, as every
+    // workgroup of the single launch has
+    const int M = 4;
     std::vector<ProbDesc> h(n);
     std::vector<int> plan(n);
     int rows = 0, tri = 0;
@@ -95,38 +103,77 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
     AXI_CHECK_HIP(hipMemcpyAsync((void *)dp, hp.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice, s));
 
     const bool pr = (flags & AXIPCG_FLAG_POLAK_RIBIERE) != 0;
-    // start: r = b - A x, z = B^{-1} r (the r-solve launch initialises each state)
-    launch_b_init(d, n, rows, s);
-    for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, false, 0, s);
     TriGate g;
     g.mode = 2;
     g.rtol2 = rtol * rtol;
     g.maxit = maxit;
     g.flags = (int)flags;
-    launch_b_tridiag(d, n, tri, prec, g, M, tri_shm, s);
-    launch_b_zero(d, n, rows, s);
-    for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 2, false, s);
+    if (!single) {
+        // start: r = b - A x, z = B^{-1} r (the r-solve launch initialises each state)
+        launch_b_init(d, n, rows, s);
+        for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, false, 0, s);
+        launch_b_tridiag(d, n, tri, prec, g, M, tri_shm, s);
+        launch_b_zero(d, n, rows, s);
+        for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 2, false, s);
+    }
 
     TriGate gi;
     gi.mode = 1;
-    int launched = 0, parity = 0, chunk = 16;
-    for (;;) {
-        if (chunk > maxit - launched) chunk = maxit - launched;
-        for (int it = 0; it < chunk; ++it) {
-            launch_b_spmv(d, n, rows, pr, parity, s);
-            for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, true, parity, s);
-            launch_b_tridiag(d, n, tri, prec, gi, M, tri_shm, s);
-            for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 1, pr, s);
-            parity ^= 1;
+    if (single) {
+        BatchSingle bs;
+        bs.d = d;
+        bs.dp = dp;
+        bs.n = n;
+        bs.rows = rows;
+        bs.tri = tri;
+        bs.nplan = (int)plans.size();
+        size_t shm = tri_shm;
+        for (int i = 0; i < bs.nplan; ++i) {
+            bs.plans[i] = plans[i];
+            const size_t b = batch_plan_lds(plans[i], prec, &bs.twl[i]);
+            if (b > shm) shm = b;
         }
-        launched += chunk;
-        launch_b_gather(d, n, dstates, s);
+        bs.g_start = g;
+        bs.g_step = gi;
+        bs.M = M;
+        bs.maxit = maxit;
+        int rmax = 2;
+        for (const BatchPlan &pl : plans) rmax = pl.r2 > rmax ? pl.r2 : rmax;
+        const int grid = batch_single_grid(prec, rmax, pr, shm);
+        // barrier words (1 + grid) and the error word, zero before the launch
+        DevBuf db;
+        AXI_CHECK_HIP(hipMalloc(&db.p, sizeof(unsigned) * (grid + 2)));
+        const std::vector<unsigned> zero(grid + 2, 0u);
+        AXI_CHECK_HIP(hipMemcpyAsync(db.p, zero.data(), sizeof(unsigned) * (grid + 2), hipMemcpyHostToDevice, s));
+        bs.bar = static_cast<unsigned *>(db.p);
+        bs.err = reinterpret_cast<int *>(bs.bar + grid + 1);
+        bs.out = dstates;
+        launch_b_single(bs, prec, rmax, pr, grid, shm, s);
         AXI_CHECK_HIP(hipMemcpyAsync(hs, dstates, sizeof(PcgState) * n, hipMemcpyDeviceToHost, s));
+        int err = 0;
+        AXI_CHECK_HIP(hipMemcpyAsync(&err, bs.err, sizeof(int), hipMemcpyDeviceToHost, s));
         AXI_CHECK_HIP(hipStreamSynchronize(s));
-        bool all = true;
-        for (int p = 0; p < n; ++p) all = all && hs[p].done != ST_RUN;
-        if (all || launched >= maxit) break;
-        chunk = 4;
+        if (err) throw Error{AXIPCG_EDEVICE, "a grid barrier of the single-launch batch gave up"};
+    } else {
+        int launched = 0, parity = 0, chunk = 16;
+        for (;;) {
+            if (chunk > maxit - launched) chunk = maxit - launched;
+            for (int it = 0; it < chunk; ++it) {
+                launch_b_spmv(d, n, rows, pr, parity, s);
+                for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, true, parity, s);
+                launch_b_tridiag(d, n, tri, prec, gi, M, tri_shm, s);
+                for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 1, pr, s);
+                parity ^= 1;
+            }
+            launched += chunk;
+            launch_b_gather(d, n, dstates, s);
+            AXI_CHECK_HIP(hipMemcpyAsync(hs, dstates, sizeof(PcgState) * n, hipMemcpyDeviceToHost, s));
+            AXI_CHECK_HIP(hipStreamSynchronize(s));
+            bool all = true;
+            for (int p = 0; p < n; ++p) all = all && hs[p].done != ST_RUN;
+            if (all || launched >= maxit) break;
+            chunk = 4;
+        }
     }
 
     int worst = AXIPCG_OK;
@@ -176,7 +223,7 @@ extern "C" int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *c
         AXI_REQUIRE(std::isfinite(rtol) && rtol > 0, "rtol must be > 0");
         AXI_REQUIRE(maxit >= 1 && maxit <= 100000, "maxit must be in [1, 100000]");
         AXI_REQUIRE(prec == AXIPCG_PREC_FP32 || prec == AXIPCG_PREC_FP64, "prec must be 0 or 1");
-        AXI_REQUIRE((flags & ~3u) == 0, "unknown flags");
+        AXI_REQUIRE((flags & ~7u) == 0, "unknown flags");
         std::vector<Operator *> v(n);
         long rows = 0;
         for (int p = 0; p < n; ++p) {
@@ -185,6 +232,8 @@ extern "C" int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *c
             AXI_REQUIRE(b[p] != x[p], "b and x must not alias");
             AXI_REQUIRE(v[p]->nr <= 1024, "batch members need nr <= 1024");
             AXI_REQUIRE(v[p]->nz % 4 == 0 && v[p]->nz <= 2048, "batch members need nz in [4, 2048]");
+            AXI_REQUIRE(!(flags & AXIPCG_FLAG_SINGLE_LAUNCH) || v[p]->nz <= 1024,
+                        "the single-launch batch takes members with nz <= 1024");
             for (int q = 0; q < p; ++q) AXI_REQUIRE(v[q] != v[p], "an operator appears twice in the batch");
             rows += v[p]->nr;
         }

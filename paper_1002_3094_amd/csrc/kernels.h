@@ -105,6 +105,28 @@ void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriG
                       hipStream_t s);
 void launch_b_zinv(const ProbDesc *d, const BatchPlan &pl, int prec, int mode, bool pr, hipStream_t s);
 void launch_b_gather(const ProbDesc *d, int n, PcgState *out, hipStream_t s);
+// Dynamic LDS of a transform plan's workgroup; *twl: twiddles staged in LDS
+// (block-wide plans).
+size_t batch_plan_lds(const BatchPlan &pl, int prec, bool *twl);
+
+// The whole batched solve in one cooperative launch (bsingle.hip): the
+// phases above dealt to resident workgroups, grid barriers between them.
+struct BatchSingle {
+    const ProbDesc *d = nullptr;    // by problem
+    const ProbDesc *dp = nullptr;   // by transform plan
+    int n = 0, rows = 0, tri = 0, nplan = 0;
+    BatchPlan plans[5];
+    bool twl[5] = {};
+    TriGate g_start, g_step;
+    int M = 4, maxit = 0;
+    unsigned *bar = nullptr;   // 1 + grid words, zero before the launch
+    int *err = nullptr;        // set when a barrier gives up
+    PcgState *out = nullptr;   // the n states at the end
+};
+// Workgroups of the single launch (all resident) for `shm` bytes of LDS;
+// rmax: the batch's largest one-wave transform plan (BatchPlan::r2).
+int batch_single_grid(int prec, int rmax, bool pr, size_t shm);
+void launch_b_single(const BatchSingle &b, int prec, int rmax, bool pr, int grid, size_t shm, hipStream_t s);
 void resid_impl(const Operator &op, const double *b, const double *x, double *out_dev, hipStream_t s);
 
 // Flattened grid geometry for pointwise kernels.

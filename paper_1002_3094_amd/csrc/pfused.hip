@@ -19,64 +19,16 @@
 // iteration (the x, r update fused into phase 1, ||r||^2 and r.z partials as
 // in the three launches), when the strips fit the chip at once.
 //
-// Grid barriers.  bar[0] is the last completed barrier number and bar[1 + s]
-// the last barrier number strip s has reached.  Barrier numbers come from a
-// per-handle launch counter (2 epoch + 1 and 2 epoch + 2), so they only grow:
-// a flag left behind by an earlier launch (even one whose barrier gave up)
-// is always below the number a later launch waits for and can never let it
-// through early.  Each workgroup releases its stores at agent scope (the XCDs'
-// L2s are not coherent with each other otherwise) and posts its flag;
-// workgroup 0 waits for every flag, acquires, and publishes the number; the
-// others wait for it and acquire.  Every wait is bounded: a barrier that
-// does not complete within the spin limit sets the error word, fills the
-// strip's output with NaN and (in PCG mode) marks the solve broken down, and
-// the kernel returns.
+// Grid barriers (gridbar.h).  Barrier numbers come from a per-handle launch
+// counter (2 epoch + 1 and 2 epoch + 2).  A barrier that does not complete
+// within the spin limit sets the error word, fills the strip's output with
+// NaN and (in PCG mode) marks the solve broken down, and the kernel returns.
+#include "gridbar.h"
 #include "strip.h"
 
 namespace axipcg {
 namespace {
 
-constexpr unsigned long long ONE_SPIN_LIMIT = 1ull << 20;
-
-__device__ inline bool one_wait(const unsigned *w, unsigned target)
-{
-    unsigned long long n = 0;
-    while ((int)(__hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - target) < 0) {
-        if (++n > ONE_SPIN_LIMIT) return false;
-        __builtin_amdgcn_s_sleep(1);
-    }
-    return true;
-}
-
-// One release and one acquire per workgroup (thread 0), the workgroup's own
-// ordering through its barriers: an agent-scope fence writes back / drops
-// the XCD's L2, so one per wave would repeat that work many times over.
-__device__ inline bool grid_sync(unsigned *bar, int nblk, unsigned target, int *flag_lds)
-{
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        *flag_lds = 1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&bar[1 + blockIdx.x], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (blockIdx.x == 0) {
-        __syncthreads();
-        bool ok = true;
-        for (int t = threadIdx.x; t < nblk; t += blockDim.x)
-            if (!one_wait(&bar[1 + t], target)) ok = false;
-        if (!ok) *flag_lds = 0;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            __hip_atomic_store(&bar[0], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    } else if (threadIdx.x == 0) {
-        if (!one_wait(&bar[0], target)) *flag_lds = 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    __syncthreads();
-    return *flag_lds != 0;
-}
 
 template <typename T>
 struct OneArgs {

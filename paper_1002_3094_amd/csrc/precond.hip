@@ -1,144 +1,13 @@
-// Preconditioner B^{-1} of §4.2 (eqs. (36)-(39)) on gfx950: batched z-transforms
-// in LDS and a partitioned r-tridiagonal solver with an in-wavefront reduced
-// system.
-#include "fft.h"
-#include "kernels.h"
-#include "wfft.h"
-#include "wxform.h"
+// Preconditioner B^{-1} of §4.2 (eqs. (36)-(39)) on gfx950: the launches of
+// the z-transforms (one wave per row, or block-wide) and of the partitioned
+// r-tridiagonal solver, for one operator and for a batch, with their plans
+// (rows per workgroup, LDS, twiddle placement).  The device bodies are in
+// xform.h and wxform.h.
+#include "xform.h"
 
 namespace axipcg {
 
 namespace {
-
-
-
-// Copy the length-N twiddle table into LDS (when it fits) so that the FFT
-// passes read it without a trip to L2.
-template <typename T>
-__device__ inline const typename vec2_of<T>::type *stage_twiddles(const typename vec2_of<T>::type *tw,
-                                                                  typename vec2_of<T>::type *lds, int N)
-{
-    // eight loads in flight per round (N <= 2048, >= 64 threads: at most four rounds)
-    for (int base = 0; base < N; base += 8 * (int)blockDim.x) {
-        typename vec2_of<T>::type v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = base + (int)threadIdx.x + j * (int)blockDim.x;
-            if (k < N) v[j] = tw[k];
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int k = base + (int)threadIdx.x + j * (int)blockDim.x;
-            if (k < N) lds[k] = v[j];
-        }
-    }
-    return lds;
-}
-
-// ---------------------------------------------------------------------------
-// Forward transform: one workgroup per ROWS consecutive r-rows.  With two
-// rows the second row's loads are issued before the first row's FFT, so the
-// memory traffic of one row overlaps the LDS work of the other.
-// ---------------------------------------------------------------------------
-template <typename T, int BC, bool FUSED, bool TWLDS, int ROWS>
-__device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double *__restrict__ x,
-                                          double *__restrict__ r, const double *__restrict__ p,
-                                          const double *__restrict__ q, PcgState *st,
-                                          double *__restrict__ partials, int n_pq, T *__restrict__ spec,
-                                          const typename vec2_of<T>::type *__restrict__ tw,
-                                          const typename vec2_of<T>::type *__restrict__ pt, int nr, int N,
-                                          int vb)
-{
-    using V2 = typename vec2_of<T>::type;
-    extern __shared__ char smem_raw[];
-    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *b = a + N;
-    V2 *twl = reinterpret_cast<V2 *>(b + N);
-    __shared__ double red[RED_SLOTS];
-
-    if (st && st->done) return;
-    const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
-    constexpr int KPT = 8;   // elements per thread (fft_threads gives N <= 8 blockDim.x)
-    double xv[KPT], rv0[KPT], pv[KPT], qv[KPT];
-    auto load = [&](int i) {
-        const size_t row = (size_t)i * N;
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const int k = threadIdx.x + j * blockDim.x;
-            if (k < N) {
-                if (FUSED) {
-                    xv[j] = x[row + k];
-                    rv0[j] = r[row + k];
-                    pv[j] = p[row + k];
-                    qv[j] = q[row + k];
-                } else {
-                    rv0[j] = rin[row + k];
-                }
-            }
-        }
-    };
-    // issue the first row's loads before the p.q reduction so the latencies overlap
-    load(i0);
-    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
-    double alpha = 0.0;
-    if (FUSED) {
-        const double pq = block_total(partials + SLOT_PQ * MAX_PARTIALS, n_pq, red);
-        const int k_it = st->iters;
-        if (!(pq > 0.0) || !(pq < 1e308)) {
-            if (vb == 0 && threadIdx.x == 0) st->done = ST_BREAK;
-            return;
-        }
-        alpha = st->rho[k_it & 1] / pq;
-        if (vb == 0 && threadIdx.x == 0) st->cur = k_it;
-    }
-
-    double rr = 0.0;
-    const T nrm = (T)sqrt(2.0 / N);
-    const T half = (T)0.70710678118654752440;
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-        const size_t row = (size_t)(i0 + s) * N;
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const int k = threadIdx.x + j * blockDim.x;
-            if (k >= N) continue;
-            double rv;
-            if (FUSED) {
-                const size_t c = row + k;
-                x[c] = xv[j] + alpha * pv[j];
-                rv = rv0[j] - alpha * qv[j];
-                r[c] = rv;
-                rr += rv * rv;
-            } else {
-                rv = rv0[j];
-            }
-            T v = (T)rv;
-            int n;
-            if ((k & 1) == 0) {
-                n = k >> 1;
-            } else {
-                n = N - 1 - (k >> 1);
-                if (BC == DIR) v = -v;
-            }
-            a[n] = {v, (T)0};
-        }
-        if (s + 1 < ROWS) load(i0 + s + 1);
-        __syncthreads();
-        const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
-        for (int j = threadIdx.x; j < N; j += blockDim.x) {
-            const int m = (BC == DIR) ? N - 1 - j : j;
-            const cx<T> w = ld_tw<T>(pt, m);
-            const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
-            const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
-            spec[row + j] = nrm * (edge ? half : (T)1) * Y;
-        }
-        if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
-    }
-    if (FUSED) {
-        const double s = block_sum(rr, red);
-        if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + vb] = s;
-    }
-}
 
 // (512 threads for N = 4096, 256 or fewer below)
 template <typename T, int BC, bool FUSED, bool TWLDS, int ROWS>
@@ -150,120 +19,6 @@ k_zfwd(const double *__restrict__ rin, double *__restrict__ x, double *__restric
        const typename vec2_of<T>::type *__restrict__ pt, int nr, int N)
 {
     zfwd_body<T, BC, FUSED, TWLDS, ROWS>(rin, x, r, p, q, st, partials, n_pq, spec, tw, pt, nr, N, blockIdx.x);
-}
-
-// ---------------------------------------------------------------------------
-// Inverse transform: one workgroup per ROWS consecutive r-rows, FP64 output;
-// the next row's spectral values are loaded during the current row's FFT.
-// ---------------------------------------------------------------------------
-
-template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
-__device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__restrict__ zout,
-                                          const double *__restrict__ r, const PcgState *st,
-                                          double *__restrict__ partials, bool pr,
-                                          const typename vec2_of<T>::type *__restrict__ tw,
-                                          const typename vec2_of<T>::type *__restrict__ pt, int nr, int N, int vb,
-                                          double *__restrict__ dinc = nullptr, double tau = 0.0, double rho2 = 0.0)
-{
-    constexpr bool PCGM = (MODE == 1 || MODE == 2);
-    constexpr bool CHEB = (MODE == 3 || MODE == 4);
-    using V2 = typename vec2_of<T>::type;
-    if (MODE != 0 && st->done) return;
-    extern __shared__ char smem_raw[];
-    cx<T> *a = reinterpret_cast<cx<T> *>(smem_raw);
-    cx<T> *b = a + N;
-    V2 *twl = reinterpret_cast<V2 *>(b + N);
-    __shared__ double red[RED_SLOTS];
-    const V2 *twp = TWLDS ? stage_twiddles<T>(tw, twl, N) : tw;
-
-    const int i0 = xcd_swizzle(vb, nr / ROWS) * ROWS;
-    const T isc = (T)sqrt(0.5 * N);      // 1 / sqrt(2/N)
-    const T sq2 = (T)1.41421356237309504880;
-    constexpr int KPT = 8;   // fft_threads gives N <= 8 blockDim.x
-    T ymv[KPT], ynv[KPT];
-    auto Yval = [&](size_t row, int m) -> T {
-        // unnormalised DCT-II coefficient Y_m of y
-        const int j = (BC == DIR) ? N - 1 - m : m;
-        const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
-        return spec[row + j] * isc * (edge ? sq2 : (T)1);
-    };
-    auto load = [&](int i) {
-        const size_t row = (size_t)i * N;
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const int m = threadIdx.x + j * blockDim.x;
-            if (m < N) {
-                ymv[j] = Yval(row, m);
-                ynv[j] = (m == 0) ? (T)0 : Yval(row, N - m);
-            }
-        }
-    };
-    load(i0);
-    const T invN = (T)1 / (T)N;
-    double rz = 0.0, rzo = 0.0;
-    double c1 = 0.0, c2 = 0.0;
-    if (CHEB) {
-        const double alpha = cheb_alpha(st->iters + 1, rho2);
-        c1 = alpha - 1.0;
-        c2 = alpha * tau;
-    }
-#pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-        const size_t row = (size_t)(i0 + s) * N;
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const int m = threadIdx.x + j * blockDim.x;
-            if (m < N) {
-                const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
-                // V = conj(w) (ym - i yn); store conj(V) = w (ym + i yn)
-                a[m] = {w.x * ymv[j] - w.y * ynv[j], w.x * ynv[j] + w.y * ymv[j]};
-            }
-        }
-        // r (and the old z) of this row, and the next row's spectral values,
-        // are in flight during the FFT
-        double rv[KPT], zo[KPT];
-        if (PCGM) {
-#pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                const int k = threadIdx.x + j * blockDim.x;
-                if (k < N) {
-                    rv[j] = r[row + k];
-                    if (pr) zo[j] = zout[row + k];
-                }
-            }
-        }
-        if (s + 1 < ROWS) load(i0 + s + 1);
-        __syncthreads();
-        const cx<T> *res = fft_stockham<T>(a, b, N, twp);
-#pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const int k = threadIdx.x + j * blockDim.x;
-            if (k >= N) continue;
-            const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
-            T v = res[n].x * invN;
-            if (BC == DIR && (k & 1)) v = -v;
-            const double zv = (double)v;
-            if (PCGM) {
-                if (pr) rzo += rv[j] * zo[j];
-                rz += rv[j] * zv;
-            }
-            if (CHEB) {
-                if (MODE == 4) dinc[row + k] = c2 * zv;
-                else dinc[row + k] = c1 * dinc[row + k] + c2 * zv;
-            } else {
-                zout[row + k] = zv;
-            }
-        }
-        if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
-    }
-    if (PCGM) {
-        const double s = block_sum(rz, red);
-        if (threadIdx.x == 0) partials[SLOT_RZ * MAX_PARTIALS + vb] = s;
-        if (pr) {
-            const double so = block_sum(rzo, red);
-            if (threadIdx.x == 0) partials[SLOT_RZOLD * MAX_PARTIALS + vb] = so;
-        }
-    }
 }
 
 template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
@@ -304,202 +59,6 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
     zinv_w_body<T, BC, MODE, R2>(in, zout, r, st, partials, pr, tw, pt, nr, dinc, tau, rho2, row, blockIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Partitioned r-tridiagonal solve (one system per z-mode l):
-//     -cb[i-1] y[i-1] + (db[i] + r_i lam_l) y[i] - cb[i] y[i+1] = f[i].
-// A workgroup loads the [nr][M] tile of M consecutive modes into LDS; wave w
-// solves mode l0 + w.  Lane s owns rows [lo_s, hi_s): its interior rows
-// lo_s..hi_s-2 are eliminated locally against three right-hand sides (data and
-// the two couplings to the neighbouring interface rows), which reduces the
-// line to a tridiagonal system in the interface rows hi_s - 1, one per lane;
-// that system is solved across the wavefront by parallel cyclic reduction
-// with cross-lane shuffles, after which each lane back-substitutes.  This is
-// the divide-and-conquer idea of §3 (split a tridiagonal system into
-// independent subsystems by first computing values at the partition
-// boundaries) mapped onto the lanes of one wavefront.
-//
-// In PCG mode the kernel first runs the stop test on ||r||^2 (partials of the
-// preceding kernel), recorded by workgroup 0; every workgroup reaches the
-// same decision.
-// ---------------------------------------------------------------------------
-// UNI: every active lane owns exactly LMAX rows (nr = S * LMAX), so the
-// per-row loops carry no guards.
-template <typename T, int LMAX, bool UNI>
-__device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__restrict__ cb_g,
-                                             const T *__restrict__ db_g, const T *__restrict__ rw_g,
-                                             const T *__restrict__ lam, PcgState *st,
-                                             const double *__restrict__ partials, const TriGate &g, int nr,
-                                             int nz, int M, int S, int pitch, int Lp, int vb)
-{
-    __shared__ double red[8];
-    extern __shared__ char smem_raw[];
-    T *tile = reinterpret_cast<T *>(smem_raw);
-    // r-line coefficients: each lane reads its own contiguous rows from global
-    // memory (L2-resident, a few KB); staged in LDS they would be read at a
-    // stride of a segment, one bank for the whole wave
-    const T *__restrict__ cb = cb_g;
-    const T *__restrict__ db = db_g;
-    const T *__restrict__ rw = rw_g;
-    const int ngroups = nz / M;
-    const int l0 = xcd_swizzle(vb, ngroups) * M;
-    // padded LDS row index (one gap per Lp rows); for UNI, Lp = LMAX, a power of
-    // two, so the division is a shift
-    auto prow = [&](int row) { return UNI ? row + row / LMAX : row + row / Lp; };
-
-    if (M * sizeof(T) == 16) {
-        // one 16-byte load per row
-        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
-            const T *tv = reinterpret_cast<const T *>(&v);
-            for (int m = 0; m < M; ++m) tile[m * pitch + prow(row)] = tv[m];
-        }
-    } else {
-        for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
-            const int row = e / M, m = e - row * M;
-            tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
-        }
-    }
-    if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb) != ST_RUN) return;
-    __syncthreads();
-
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (w < M) {
-        T *col = tile + w * pitch;
-        const T lm = lam[l0 + w];
-        const bool active = lane < S;
-        const int lo = active ? (UNI ? lane * LMAX : (int)(((long)lane * nr) / S)) : 0;
-        const int hi = active ? (UNI ? lo + LMAX : (int)(((long)(lane + 1) * nr) / S)) : 0;
-        const int n = active ? hi - lo - 1 : 0;   // interior rows (>= 1 when active)
-        auto in_seg = [&](int t) { return UNI ? (active && t < LMAX - 1) : (t < n); };
-
-        // prefetch the lane's data (LDS), diagonal and couplings (global)
-        T fv[LMAX], dv[LMAX], cv[LMAX];
-        constexpr int VW = 16 / (int)sizeof(T);
-        if constexpr (UNI && LMAX % VW == 0) {
-            // all LMAX rows, the interface row included, as 16-byte vectors
-            typedef T V __attribute__((ext_vector_type(VW)));
-            if (active) {
-#pragma unroll
-                for (int j = 0; j < LMAX / VW; ++j) {
-                    const V c4 = *reinterpret_cast<const V *>(cb + lo + j * VW);
-                    const V d4 = *reinterpret_cast<const V *>(db + lo + j * VW);
-                    const V r4 = *reinterpret_cast<const V *>(rw + lo + j * VW);
-#pragma unroll
-                    for (int e = 0; e < VW; ++e) {
-                        cv[j * VW + e] = c4[e];
-                        dv[j * VW + e] = d4[e] + r4[e] * lm;
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < LMAX; ++t)
-                if (in_seg(t)) fv[t] = col[prow(lo + t)];
-        } else {
-#pragma unroll
-            for (int t = 0; t < LMAX; ++t) {
-                if (in_seg(t)) {
-                    const int i = lo + t;
-                    fv[t] = col[prow(i)];
-                    dv[t] = db[i] + rw[i] * lm;
-                    cv[t] = cb[i];
-                }
-            }
-        }
-        const T cbm = (active && lo > 0) ? cb[lo - 1] : (T)0;
-        T cp[LMAX], gp[LMAX], vp[LMAX];
-        T cprev = 0, gprev = 0, vprev = 0, inv = 1;
-#pragma unroll
-        for (int t = 0; t < LMAX; ++t) {
-            if (in_seg(t)) {
-                const T sub = (t > 0) ? -cv[t - 1] : (T)0;
-                inv = fast_rcp<T>(dv[t] - sub * cprev);
-                cprev = -cv[t] * inv;
-                gprev = (fv[t] - sub * gprev) * inv;
-                const T vr = (t == 0) ? cbm : (T)0;
-                vprev = (vr - sub * vprev) * inv;
-                cp[t] = cprev;
-                gp[t] = gprev;
-                vp[t] = vprev;
-            }
-        }
-        const int R = hi - 1;                        // interface row of this lane
-        const T cbR1 = active ? cb[R - 1] : (T)0;    // coupling interface <- last interior
-        const T wl = cbR1 * inv;                     // w' of the last interior row
-        T gl = active ? gprev : (T)0, vl = active ? vprev : (T)0;
-        // back-substitute to obtain the first interior values of g, v, w
-        T gq = gl, v = vl, ww = wl;
-#pragma unroll
-        for (int t = LMAX - 2; t >= 0; --t) {
-            if (UNI ? (t < LMAX - 2 + 0 && active) : (t < n - 1)) {
-                gq = gp[t] - cp[t] * gq;
-                v = vp[t] - cp[t] * v;
-                ww = -cp[t] * ww;
-            }
-        }
-        if (!active) { gq = 0; v = 0; ww = 0; }
-        // neighbour (lane + 1) first values
-        const T gfn = __shfl_down(gq, 1, 64);
-        const T vfn = __shfl_down(v, 1, 64);
-        const T wfn = __shfl_down(ww, 1, 64);
-        const bool has_right = active && (lane + 1 < S);
-        const T cbR = has_right ? cb[R] : (T)0;
-        T ra = 0, rb = 1, rc = 0, re = 0;
-        if (active) {
-            ra = -cbR1 * vl;
-            rb = db[R] + rw[R] * lm - cbR1 * wl - (has_right ? cbR * vfn : (T)0);
-            rc = has_right ? -cbR * wfn : (T)0;
-            re = col[prow(R)] + cbR1 * gl + (has_right ? cbR * gfn : (T)0);
-        }
-        // parallel cyclic reduction over the S interface unknowns
-        for (int k = 1; k < S; k <<= 1) {
-            const T am = __shfl_up(ra, k, 64), bm = __shfl_up(rb, k, 64);
-            const T cm = __shfl_up(rc, k, 64), em = __shfl_up(re, k, 64);
-            const T ap = __shfl_down(ra, k, 64), bp = __shfl_down(rb, k, 64);
-            const T cq = __shfl_down(rc, k, 64), ep = __shfl_down(re, k, 64);
-            const bool hm = lane >= k, hp = lane + k < S;
-            const T al = hm ? -ra * fast_rcp<T>(bm) : (T)0;
-            const T ga = hp ? -rc * fast_rcp<T>(bp) : (T)0;
-            const T na = hm ? al * am : (T)0;
-            const T nc = hp ? ga * cq : (T)0;
-            const T nb = rb + (hm ? al * cm : (T)0) + (hp ? ga * ap : (T)0);
-            const T ne = re + (hm ? al * em : (T)0) + (hp ? ga * ep : (T)0);
-            if (active) { ra = na; rb = nb; rc = nc; re = ne; }
-        }
-        const T xs = active ? re / rb : (T)0;
-        T xm = __shfl_up(xs, 1, 64);
-        if (lane == 0) xm = 0;
-        // interior values: forward-eliminated rhs y' = g' + v' x_{s-1} (+ w' x_s
-        // on the last interior row), then the backward sweep
-        if (active) {
-            T y = 0;
-#pragma unroll
-            for (int t = LMAX - 1; t >= 0; --t) {
-                if (in_seg(t)) {
-                    const T yp = gp[t] + vp[t] * xm;
-                    if (t == n - 1) y = yp + wl * xs;
-                    else y = yp - cp[t] * y;
-                    col[prow(lo + t)] = y;
-                }
-            }
-            col[prow(R)] = xs;
-        }
-    }
-    __syncthreads();
-    if (M * sizeof(T) == 16) {
-        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
-            uint4 v;
-            T *tv = reinterpret_cast<T *>(&v);
-            for (int m = 0; m < M; ++m) tv[m] = tile[m * pitch + prow(row)];
-            *reinterpret_cast<uint4 *>(spec + (size_t)row * nz + l0) = v;
-        }
-    } else {
-        for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
-            const int row = e / M, m = e - row * M;
-            spec[(size_t)row * nz + l0 + m] = tile[m * pitch + prow(row)];
-        }
-    }
-}
-
 template <typename T, int LMAX, bool UNI>
 __global__ void __launch_bounds__(256)
 k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
@@ -510,115 +69,38 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict_
 }
 
 // ---- batched launches ----------------------------------------------------
-template <typename T> __device__ inline const T *pd_cb(const ProbDesc &P);
-template <> __device__ inline const float *pd_cb<float>(const ProbDesc &P) { return P.cb32; }
-template <> __device__ inline const double *pd_cb<double>(const ProbDesc &P) { return P.cb64; }
-template <typename T> __device__ inline const T *pd_db(const ProbDesc &P);
-template <> __device__ inline const float *pd_db<float>(const ProbDesc &P) { return P.db32; }
-template <> __device__ inline const double *pd_db<double>(const ProbDesc &P) { return P.db64; }
-template <typename T> __device__ inline const T *pd_rw(const ProbDesc &P);
-template <> __device__ inline const float *pd_rw<float>(const ProbDesc &P) { return P.rw32; }
-template <> __device__ inline const double *pd_rw<double>(const ProbDesc &P) { return P.rw64; }
-template <typename T> __device__ inline const T *pd_lam(const ProbDesc &P);
-template <> __device__ inline const float *pd_lam<float>(const ProbDesc &P) { return P.lam32; }
-template <> __device__ inline const double *pd_lam<double>(const ProbDesc &P) { return P.lam64; }
-template <typename T> __device__ inline const typename vec2_of<T>::type *pd_tw(const ProbDesc &P);
-template <> __device__ inline const float2 *pd_tw<float>(const ProbDesc &P) { return P.tw32; }
-template <> __device__ inline const double2 *pd_tw<double>(const ProbDesc &P) { return P.tw64; }
-template <typename T> __device__ inline const typename vec2_of<T>::type *pd_pt(const ProbDesc &P);
-template <> __device__ inline const float2 *pd_pt<float>(const ProbDesc &P) { return P.pt32; }
-template <> __device__ inline const double2 *pd_pt<double>(const ProbDesc &P) { return P.pt64; }
 
 // The batched transforms run one launch per transform plan; `d` holds the
-// problems of that plan, with tr_start counted within the launch.
+// problems of that plan, with tr_start counted within the launch.  One work
+// item (xform.h) per workgroup.
 template <typename T, bool FUSED, bool TWLDS>
 __global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, int n, int parity)
 {
-    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
-    const ProbDesc &P = d[p];
-    const double *pnew = parity ? P.p0 : P.p1;   // written by this iteration's SpMV
-    const int vb = blockIdx.x - P.tr_start;
-    // the start-up transform runs before the r-solve launch resets the state,
-    // so only the in-loop (fused) transform may read the stop flag
-    PcgState *st = FUSED ? P.state : nullptr;
-    if (P.bc_z == DIR)
-        zfwd_body<T, DIR, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec,
-                                        pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
-    else
-        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS, 1>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr,
-                                                     (T *)P.spec, pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
+    b_zfwd_item<T, FUSED, TWLDS, false>(d, n, blockIdx.x, parity);
 }
 
 template <typename T, int MODE, bool TWLDS>
 __global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, int n, bool pr)
 {
-    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
-    const ProbDesc &P = d[p];
-    const int vb = blockIdx.x - P.tr_start;
-    if (P.bc_z == DIR)
-        zinv_body<T, DIR, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
-                                       pd_pt<T>(P), P.nr, P.nz, vb);
-    else
-        zinv_body<T, AXIPCG_Z_NEUMANN, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
-                                                    pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
+    b_zinv_item<T, MODE, TWLDS>(d, n, blockIdx.x, pr);
 }
 
 template <typename T, bool FUSED, int R2>
 __global__ void __launch_bounds__(256) k_b_zfwd_w(const ProbDesc *__restrict__ d, int n, int parity)
 {
-    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
-    const ProbDesc &P = d[p];
-    const double *pnew = parity ? P.p0 : P.p1;
-    const int vb = blockIdx.x - P.tr_start;
-    PcgState *st = FUSED ? P.state : nullptr;   // as in k_b_zfwd
-    constexpr int WR = wave_rows<T, R2>();
-    const int row = vb * WR + (threadIdx.x >> 6);
-    RowStore<T> out{(T *)P.spec + (size_t)(row < P.nr ? row : 0) * wfft::Geo<R2>::N};
-    if (P.bc_z == DIR)
-        zfwd_w_body<T, DIR, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, pd_tw<T>(P), pd_pt<T>(P),
-                                       P.nr, row, vb, out);
-    else
-        zfwd_w_body<T, AXIPCG_Z_NEUMANN, FUSED, R2>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, pd_tw<T>(P),
-                                                    pd_pt<T>(P), P.nr, row, vb, out);
+    b_zfwd_w_item<T, FUSED, R2, false>(d, n, blockIdx.x, parity);
 }
 
 template <typename T, int MODE, int R2>
 __global__ void __launch_bounds__(256) k_b_zinv_w(const ProbDesc *__restrict__ d, int n, bool pr)
 {
-    const int p = find_problem(d, n, blockIdx.x, RANGE_TR);
-    const ProbDesc &P = d[p];
-    const int vb = blockIdx.x - P.tr_start;
-    constexpr int WR = wave_rows<T, R2>();
-    const int row = vb * WR + (threadIdx.x >> 6);
-    RowLoad<T> in{(const T *)P.spec + (size_t)(row < P.nr ? row : P.nr - 1) * wfft::Geo<R2>::N};
-    if (P.bc_z == DIR)
-        zinv_w_body<T, DIR, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P), P.nr, nullptr,
-                                      0.0, 0.0, row, vb);
-    else
-        zinv_w_body<T, AXIPCG_Z_NEUMANN, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P),
-                                                   P.nr, nullptr, 0.0, 0.0, row, vb);
+    b_zinv_w_item<T, MODE, R2>(d, n, blockIdx.x, pr);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_b_tridiag(const ProbDesc *__restrict__ d, int n, TriGate g, int M)
 {
-    const int p = find_problem(d, n, blockIdx.x, RANGE_TRI);
-    const ProbDesc &P = d[p];
-    const int vb = blockIdx.x - P.tri_start;
-    g.state = P.state;
-    g.n_rr = g.mode == 2 ? P.nr : P.n_tr;   // start: the init partials, one per row
-    const bool uni = (P.nr % P.tri_S) == 0;
-#define AXI_BTRI(LM, U)                                                                                       \
-    tridiag_body<T, LM, U>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,           \
-                           P.partials, g, P.nr, P.nz, M, P.tri_S, P.tri_pitch, P.tri_Lp, vb)
-    if (uni && P.tri_L == 2) AXI_BTRI(2, true);
-    else if (uni && P.tri_L == 4) AXI_BTRI(4, true);
-    else if (uni && P.tri_L == 8) AXI_BTRI(8, true);
-    else if (uni && P.tri_L == 16) AXI_BTRI(16, true);
-    else if (P.tri_L <= 4) AXI_BTRI(4, false);
-    else if (P.tri_L <= 8) AXI_BTRI(8, false);
-    else AXI_BTRI(16, false);
-#undef AXI_BTRI
+    b_tridiag_item<T>(d, n, g, M, blockIdx.x);
 }
 
 template <typename T>
@@ -901,6 +383,26 @@ void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch
     *pitch = nr + nr / *Lp + 1;
     const size_t el = (prec == AXIPCG_PREC_FP32) ? sizeof(float) : sizeof(double);
     *shm = (size_t)M * *pitch * el;
+}
+
+template <typename T>
+size_t plan_lds_t(const BatchPlan &pl, bool *twl)
+{
+    *twl = false;
+    switch (pl.r2) {
+    case 2: return (size_t)wave_rows<T, 2>() * wfft::Geo<2>::LB * sizeof(cx<T>);
+    case 4: return (size_t)wave_rows<T, 4>() * wfft::Geo<4>::LB * sizeof(cx<T>);
+    case 8: return (size_t)wave_rows<T, 8>() * wfft::Geo<8>::LB * sizeof(cx<T>);
+    case 16: return (size_t)wave_rows<T, 16>() * wfft::Geo<16>::LB * sizeof(cx<T>);
+    default:
+        *twl = twiddles_in_lds<T>(pl.nz_max);
+        return transform_lds<T>(pl.nz_max);
+    }
+}
+
+size_t batch_plan_lds(const BatchPlan &pl, int prec, bool *twl)
+{
+    return prec == AXIPCG_PREC_FP32 ? plan_lds_t<float>(pl, twl) : plan_lds_t<double>(pl, twl);
 }
 
 int batch_transform_plan(int nz, int prec, int *rows_per_wg)

@@ -49,13 +49,26 @@ __device__ inline double cheb_alpha(int m, double rho2)
 template <typename T, int R2>
 constexpr int wave_rows() { return (sizeof(T) == 8 && R2 >= 16) ? 2 : 4; }
 
+// A flag as one value for the whole workgroup (thread 0 reads it), for bodies
+// whose workgroup goes on to other work after they return: waves that read
+// different values would next meet at different barriers.
+__device__ inline int wg_flag(const int *p)
+{
+    __shared__ int f;
+    if (threadIdx.x == 0) f = *(const volatile int *)p;
+    __syncthreads();
+    const int v = f;
+    __syncthreads();
+    return v;
+}
+
 // Forward transform of row `row` by the calling wave (rows >= nr: the wave
 // runs for the partial sums only).  Every wave of the workgroup calls it
 // (block-wide reductions).  The spectrum leaves through store(j, value) for
 // each index j of the row, after the wave's last read of its LDS slice, so
 // the store may write into that slice.  Returns false when the solve has
 // stopped (or the step broke down): the whole workgroup then returns.
-template <typename T, int BC, bool FUSED, int R2, typename Store>
+template <typename T, int BC, bool FUSED, int R2, bool WG_STOP = false, typename Store>
 __device__ __forceinline__ bool
 zfwd_w_body(const double *__restrict__ rin, double *__restrict__ x, double *__restrict__ r,
             const double *__restrict__ p, const double *__restrict__ q, PcgState *st,
@@ -99,7 +112,11 @@ zfwd_w_body(const double *__restrict__ rin, double *__restrict__ x, double *__re
         }
     // (the stop flag before the reduction: deferring it past the reduction,
     // as the other PCG kernels do, made the 2048-point forward kernel slower)
-    if (st && st->done) return false;
+    if constexpr (WG_STOP) {
+        if (st && wg_flag(&st->done)) return false;
+    } else {
+        if (st && st->done) return false;
+    }
     double alpha = 0.0;
     if (FUSED) {
         const int k_it = st->iters;
