@@ -121,15 +121,15 @@ def _block(text, start):
 
 def source_sha():
     """Hash of the source text the roofline kernel (the PCG SpMV) is built
-    from: its stencil helpers (spmv.h, through the row-per-workgroup body),
-    its kernel and launch size in pcg.hip, and the state, slot layout and
-    reduction helpers it uses from common.h."""
+    from: its tile body and stencil helpers (spmv.h), its kernel wrapper and
+    launch size in pcg.hip, and the state, slot layout and reduction helpers
+    it uses from common.h."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1002_3094_amd", "csrc")
     hdr = open(os.path.join(csrc, "spmv.h")).read()
     h.update(hdr[hdr.index("struct Pair {"):hdr.index("// r = b - A x;")].encode())
     pcg = open(os.path.join(csrc, "pcg.hip")).read()
-    h.update(pcg[pcg.index("// The same step for one problem"):pcg.index("// Chebyshev step of eq. (8)")].encode())
+    h.update(pcg[pcg.index("template <bool PR, int RW>\n__global__"):pcg.index("// Chebyshev step of eq. (8)")].encode())
     com = open(os.path.join(csrc, "common.h")).read()
     for start in ("struct PcgState {", "enum Slot {", "constexpr int MAX_PARTIALS",
                   "__device__ inline double block_sum(", "__device__ inline double block_total(",

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "spmv.h"
 
 namespace axipcg {
 namespace {
@@ -35,7 +36,7 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
     const int M = 4;
     std::vector<ProbDesc> h(n);
     std::vector<int> plan(n);
-    int rows = 0, tri = 0;
+    int rows = 0, tri = 0, spt = 0;
     size_t tri_shm = 0;
     for (int p = 0; p < n; ++p) {
         const Operator &op = *ops[p];
@@ -45,6 +46,9 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         d.bc_z = op.bc_z;
         d.row_start = rows;
         d.tri_start = tri;
+        d.sp_start = spt;
+        d.n_sp = batch_spmv_tiles(op.nr, op.nz);
+        spt += d.n_sp;
         size_t shm = 0;
         batch_tri_geom(op.nr, prec, M, &d.tri_S, &d.tri_L, &d.tri_Lp, &d.tri_pitch, &shm);
         rows += op.nr;
@@ -126,6 +130,7 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         bs.n = n;
         bs.rows = rows;
         bs.tri = tri;
+        bs.spt = spt;
         bs.nplan = (int)plans.size();
         size_t shm = tri_shm;
         for (int i = 0; i < bs.nplan; ++i) {
@@ -159,7 +164,7 @@ int batch_impl(int n, Operator *const *ops, const double *const *b, double *cons
         for (;;) {
             if (chunk > maxit - launched) chunk = maxit - launched;
             for (int it = 0; it < chunk; ++it) {
-                launch_b_spmv(d, n, rows, pr, parity, s);
+                launch_b_spmv(d, n, spt, pr, parity, s);
                 for (const BatchPlan &pl : plans) launch_b_zfwd(dp, pl, prec, true, parity, s);
                 launch_b_tridiag(d, n, tri, prec, gi, M, tri_shm, s);
                 for (const BatchPlan &pl : plans) launch_b_zinv(dp, pl, prec, 1, pr, s);

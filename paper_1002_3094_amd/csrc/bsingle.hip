@@ -8,7 +8,7 @@
 //              forward z-transform of r              items: transform blocks
 //              start test; r-solves                  items: mode groups
 //              x = 0 where b = 0; inverse, r.z       items: rows; transform blocks
-//   iteration  SpMV: beta, p update, q = A p, p.q   items: rows
+//   iteration  SpMV: beta, p update, q = A p, p.q   items: SpMV tiles
 //              alpha; x, r update; forward           items: transform blocks
 //              stop test; r-solves                   items: mode groups
 //              inverse transform, r.z                items: transform blocks
@@ -33,7 +33,7 @@ constexpr int MAX_PLANS = 5;
 struct SingleArgs {
     const ProbDesc *d;    // by problem (row_start, tri_start)
     const ProbDesc *dp;   // by transform plan (tr_start counted within the plan)
-    int n, rows, tri, nplan;
+    int n, rows, tri, spt, nplan;
     int r2[MAX_PLANS], off[MAX_PLANS], np[MAX_PLANS], twl[MAX_PLANS];
     int base[MAX_PLANS + 1];   // first transform item of each plan
     TriGate g_start, g_step;
@@ -132,7 +132,7 @@ __device__ __forceinline__ bool single_run(const SingleArgs &A, int *flag)
 
     int parity = 0;
     for (int it = 0; it < A.maxit && any_running(A); ++it) {
-        for (int g = blockIdx.x; g < A.rows; g += G) {
+        for (int g = blockIdx.x; g < A.spt; g += G) {
             b_spmv_item<PR>(A.d, A.n, g, parity);
             __syncthreads();
         }
@@ -202,6 +202,7 @@ void launch_b_single(const BatchSingle &b, int prec, int rmax, bool pr, int grid
     a.n = b.n;
     a.rows = b.rows;
     a.tri = b.tri;
+    a.spt = b.spt;
     a.nplan = b.nplan;
     a.base[0] = 0;
     for (int i = 0; i < b.nplan; ++i) {

@@ -164,11 +164,14 @@ struct Operator {
 // One problem of a batched solve, as the batched kernels see it.  Workgroup g
 // of a row-indexed launch belongs to the problem whose [row_start, row_start +
 // nr) range holds g; of the r-solve launch, [tri_start, tri_start + nz / M);
-// of its transform launch, [tr_start, tr_start + n_tr).
+// of its transform launch, [tr_start, tr_start + n_tr); of the SpMV launch
+// (one tile of BATCH_SPMV_RW rows by SPMV_CHUNK columns per workgroup),
+// [sp_start, sp_start + n_sp).
 struct ProbDesc {
     int nr, nz, bc_z;
     int row_start, tri_start;
     int tr_start, n_tr;
+    int sp_start, n_sp;
     int tri_S, tri_L, tri_Lp, tri_pitch;
     const double *b;
     double *x;
@@ -184,15 +187,18 @@ struct ProbDesc {
 };
 
 // Index of the problem owning global workgroup g (binary search on the
-// starts of the launch's ranges: rows, r-solve mode groups or transform
-// workgroups).
-enum : int { RANGE_ROWS = 0, RANGE_TRI = 1, RANGE_TR = 2 };
+// starts of the launch's ranges: rows, r-solve mode groups, transform
+// workgroups or SpMV tiles).
+enum : int { RANGE_ROWS = 0, RANGE_TRI = 1, RANGE_TR = 2, RANGE_SP = 3 };
 __device__ inline int find_problem(const ProbDesc *d, int n, int g, int range)
 {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        const int st = range == RANGE_TRI ? d[mid].tri_start : range == RANGE_TR ? d[mid].tr_start : d[mid].row_start;
+        const int st = range == RANGE_TRI ? d[mid].tri_start
+                       : range == RANGE_TR ? d[mid].tr_start
+                       : range == RANGE_SP ? d[mid].sp_start
+                                           : d[mid].row_start;
         if (st <= g) lo = mid;
         else hi = mid - 1;
     }

@@ -90,7 +90,7 @@ void pfused_pcg_step(Operator &op, const ZfwdArgs &fa, const TriGate &g, const Z
 void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch, size_t *shm);
 void launch_b_init(const ProbDesc *d, int n, int rows, hipStream_t s);
 void launch_b_zero(const ProbDesc *d, int n, int rows, hipStream_t s);
-void launch_b_spmv(const ProbDesc *d, int n, int rows, bool pr, int parity, hipStream_t s);
+void launch_b_spmv(const ProbDesc *d, int n, int tiles, bool pr, int parity, hipStream_t s);
 // One batched transform launch covers the problems d[off, off + n) of an
 // array sorted by transform plan: r2 = N / 128 for the one-wave plans, 0 for
 // the block-wide kernels (one row per workgroup); `blocks` workgroups in all.
@@ -114,7 +114,7 @@ size_t batch_plan_lds(const BatchPlan &pl, int prec, bool *twl);
 struct BatchSingle {
     const ProbDesc *d = nullptr;    // by problem
     const ProbDesc *dp = nullptr;   // by transform plan
-    int n = 0, rows = 0, tri = 0, nplan = 0;
+    int n = 0, rows = 0, tri = 0, spt = 0, nplan = 0;   // items: rows, mode groups, SpMV tiles
     BatchPlan plans[5];
     bool twl[5] = {};
     TriGate g_start, g_step;

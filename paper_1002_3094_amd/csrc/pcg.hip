@@ -31,123 +31,13 @@ namespace {
 
 inline unsigned row_blocks(int nr) { return (unsigned)(nr < MAX_PARTIALS ? nr : MAX_PARTIALS); }
 
-// The same step for one problem, on tiles of RW consecutive rows by
-// SPMV_CHUNK columns: a thread owns one column pair and sweeps the tile's
-// rows with a three-row window of z and p_old in registers (each row is
-// loaded once per tile, plus one halo row above and below), and the
-// z-neighbours k - 1, k + 2 (and the coupling CZ[k - 1]) come from the
-// adjacent lanes, with loads only at the wave's edges.  The stencil's
-// arithmetic is that of stencil2, term for term.  Tiles are dealt to the
-// XCDs in contiguous runs (xcd_swizzle), so a tile's halo rows are the
-// neighbouring tiles' rows in the same L2.
-constexpr int SPMV_CHUNK = 512;   // columns per tile: 256 threads x one pair
-
 template <bool PR, int RW>
 __global__ void __launch_bounds__(256)
 k_pcg_spmv(const double *__restrict__ z, const double *__restrict__ pold, double *__restrict__ pnew,
            double *__restrict__ q, const double *__restrict__ D, const double *__restrict__ CR,
            const double *__restrict__ CZ, int nr, int nz, PcgState *st, double *__restrict__ partials, int n_rz)
 {
-    __shared__ double red[8];
-    double acc = 0.0, beta = 0.0;
-    bool have_beta = false;
-    int k_it = 0;
-    const int nb = (nr + RW - 1) / RW, nc = (nz + SPMV_CHUNK - 1) / SPMV_CHUNK;
-    const int lane = threadIdx.x & 63;
-    for (int t = blockIdx.x; t < nb * nc; t += gridDim.x) {
-        const int item = xcd_swizzle(t, nb * nc);
-        const int i0 = RW * (item / nc);
-        const int k = (item % nc) * SPMV_CHUNK + 2 * (int)threadIdx.x;
-        const bool in = k < nz;
-        // window: [0] row i - 1, [1] row i, [2] row i + 1; crm = CR of row i - 1
-        Pair zw[3], pw[3], crm;
-        {
-            const size_t e = (size_t)i0 * nz + k;
-            const bool dn = in && i0 > 0;
-            zw[0] = dn ? ld2(z + e - nz) : Pair{0.0, 0.0};
-            pw[0] = dn ? ld2(pold + e - nz) : Pair{0.0, 0.0};
-            crm = dn ? ld2(CR + e - nz) : Pair{0.0, 0.0};
-            zw[1] = in ? ld2(z + e) : Pair{0.0, 0.0};
-            pw[1] = in ? ld2(pold + e) : Pair{0.0, 0.0};
-        }
-#pragma unroll
-        for (int rr = 0; rr < RW; ++rr) {
-            const int i = i0 + rr;
-            if (i >= nr) break;
-            const bool up = i + 1 < nr;
-            const size_t e = (size_t)i * nz + k;
-            zw[2] = (in && up) ? ld2(z + e + nz) : Pair{0.0, 0.0};
-            pw[2] = (in && up) ? ld2(pold + e + nz) : Pair{0.0, 0.0};
-            const Pair cr = (in && up) ? ld2(CR + e) : Pair{0.0, 0.0};
-            const Pair d = in ? ld2(D + e) : Pair{0.0, 0.0};
-            const Pair cz = in ? ld2(CZ + e) : Pair{0.0, 0.0};
-            // every lane takes part in the shuffles (lanes past nz hold zeros)
-            double zl = __shfl_up(zw[1].b, 1), pl = __shfl_up(pw[1].b, 1), czl = __shfl_up(cz.b, 1);
-            double zr = __shfl_down(zw[1].a, 1), pr = __shfl_down(pw[1].a, 1);
-            if (lane == 0 && in && k > 0) {
-                zl = z[e - 1];
-                pl = pold[e - 1];
-                czl = CZ[e - 1];
-            }
-            if (lane == 63 && in && k + 2 < nz) {
-                zr = z[e + 2];
-                pr = pold[e + 2];
-            }
-            auto row = [&](const Pair &c, const Pair &vu, const Pair &vd, double vl, double vr) {
-                Pair y{d.a * c.a, d.b * c.b};
-                if (up) {
-                    y.a -= cr.a * vu.a;
-                    y.b -= cr.b * vu.b;
-                }
-                if (i > 0) {
-                    y.a -= crm.a * vd.a;
-                    y.b -= crm.b * vd.b;
-                }
-                y.a -= cz.a * c.b;
-                y.b -= cz.a * c.a;
-                if (k + 2 < nz) y.b -= cz.b * vr;
-                if (k > 0) y.a -= czl * vl;
-                return y;
-            };
-            const Pair az = row(zw[1], zw[2], zw[0], zl, zr);
-            const Pair ap = row(pw[1], pw[2], pw[0], pl, pr);
-            if (!have_beta) {   // scalars once per workgroup, after the first row's loads
-                // every state field read at once (the r.z slot needed depends
-                // on iters), their latency overlapping the reduction; the
-                // stop flag is acted on after it (every workgroup alike)
-                const int done = st->done;
-                k_it = st->iters;
-                const double rho_slot[2] = {st->rho[0], st->rho[1]};
-                const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
-                if (done) return;
-                if (k_it > 0) {
-                    double num = rho;
-                    if (PR) num -= block_total(partials + SLOT_RZOLD * MAX_PARTIALS, n_rz, red);
-                    beta = num / rho_slot[(k_it - 1) & 1];
-                }
-                if (blockIdx.x == 0 && threadIdx.x == 0) st->rho[k_it & 1] = rho;
-                have_beta = true;
-            }
-            if (in) {
-                double2 pn, qn;
-                pn.x = (k_it > 0) ? zw[1].a + beta * pw[1].a : zw[1].a;
-                pn.y = (k_it > 0) ? zw[1].b + beta * pw[1].b : zw[1].b;
-                qn.x = (k_it > 0) ? az.a + beta * ap.a : az.a;
-                qn.y = (k_it > 0) ? az.b + beta * ap.b : az.b;
-                *reinterpret_cast<double2 *>(pnew + e) = pn;
-                *reinterpret_cast<double2 *>(q + e) = qn;
-                acc += pn.x * qn.x;
-                acc += pn.y * qn.y;
-            }
-            zw[0] = zw[1];
-            zw[1] = zw[2];
-            pw[0] = pw[1];
-            pw[1] = pw[2];
-            crm = cr;
-        }
-    }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[SLOT_PQ * MAX_PARTIALS + blockIdx.x] = s;
+    spmv_tiles<PR, RW>(z, pold, pnew, q, D, CR, CZ, nr, nz, st, partials, n_rz, blockIdx.x, gridDim.x);
 }
 
 // Rows per SpMV tile: 16 when that still leaves 512 tiles or more (long
@@ -582,10 +472,10 @@ int cheb_solve_impl(Operator &op, const double *b, double *x, double gamma1, dou
 
 }  // namespace
 
-void launch_b_spmv(const ProbDesc *d, int n, int rows, bool pr, int parity, hipStream_t s)
+void launch_b_spmv(const ProbDesc *d, int n, int tiles, bool pr, int parity, hipStream_t s)
 {
-    if (pr) hipLaunchKernelGGL(k_b_spmv<true>, dim3(rows), dim3(256), 0, s, d, n, parity);
-    else hipLaunchKernelGGL(k_b_spmv<false>, dim3(rows), dim3(256), 0, s, d, n, parity);
+    if (pr) hipLaunchKernelGGL(k_b_spmv<true>, dim3(tiles), dim3(256), 0, s, d, n, parity);
+    else hipLaunchKernelGGL(k_b_spmv<false>, dim3(tiles), dim3(256), 0, s, d, n, parity);
     AXI_CHECK_HIP(hipGetLastError());
 }
 

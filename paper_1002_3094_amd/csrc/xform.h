@@ -495,10 +495,10 @@ __device__ __forceinline__ void b_zfwd_item(const ProbDesc *__restrict__ d, int 
     // so only the in-loop (fused) transform may read the stop flag
     PcgState *st = FUSED ? P.state : nullptr;
     if (P.bc_z == DIR)
-        zfwd_body<T, DIR, FUSED, TWLDS, 1, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, (T *)P.spec,
+        zfwd_body<T, DIR, FUSED, TWLDS, 1, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.n_sp, (T *)P.spec,
                                         pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
     else
-        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS, 1, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr,
+        zfwd_body<T, AXIPCG_Z_NEUMANN, FUSED, TWLDS, 1, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.n_sp,
                                                      (T *)P.spec, pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
 }
 
@@ -528,10 +528,10 @@ __device__ __forceinline__ void b_zfwd_w_item(const ProbDesc *__restrict__ d, in
     const int row = vb * WR + (threadIdx.x >> 6);
     RowStore<T> out{(T *)P.spec + (size_t)(row < P.nr ? row : 0) * wfft::Geo<R2>::N};
     if (P.bc_z == DIR)
-        zfwd_w_body<T, DIR, FUSED, R2, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, pd_tw<T>(P), pd_pt<T>(P),
+        zfwd_w_body<T, DIR, FUSED, R2, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.n_sp, pd_tw<T>(P), pd_pt<T>(P),
                                        P.nr, row, vb, out);
     else
-        zfwd_w_body<T, AXIPCG_Z_NEUMANN, FUSED, R2, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.nr, pd_tw<T>(P),
+        zfwd_w_body<T, AXIPCG_Z_NEUMANN, FUSED, R2, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.n_sp, pd_tw<T>(P),
                                                     pd_pt<T>(P), P.nr, row, vb, out);
 }
 
