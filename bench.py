@@ -127,7 +127,7 @@ def source_sha():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1002_3094_amd", "csrc")
     hdr = open(os.path.join(csrc, "spmv.h")).read()
-    h.update(hdr[hdr.index("struct Pair {"):hdr.index("// r = b - A x;")].encode())
+    h.update(hdr[hdr.index("struct Pair {"):hdr.index("// Chebyshev step of eq. (8) in increment form")].encode())
     pcg = open(os.path.join(csrc, "pcg.hip")).read()
     h.update(pcg[pcg.index("template <bool PR, int RW>\n__global__"):pcg.index("// Chebyshev step of eq. (8)")].encode())
     com = open(os.path.join(csrc, "common.h")).read()
@@ -460,7 +460,8 @@ def held_out_measure(ax, torch, a, net, seeds=(101, 102), modes=("B", "X", "C"))
 def batch_measure(ax, torch, prec, reps=3):
     """64 independent uneven problems (N_r, N_z ~ U{256,512,1024}, seeds
     1000+p): one batched solve with a launch per phase, the same solve in one
-    cooperative launch, and the problems solved one by one."""
+    cooperative launch, the batched Chebyshev form, and the problems solved
+    one by one."""
     import synth
     probs = [synth.problem_batch_member(p) for p in range(64)]
     ops, bs, xs = [], [], []
@@ -489,6 +490,31 @@ def batch_measure(ax, torch, prec, reps=3):
 
     t_b, iters = timed(0)
     t_s, iters_s = timed(ax.FLAG_SINGLE_LAUNCH)
+    # the Chebyshev form of eq. (8), each member with its own bounds; these
+    # media have cells with q = 0, where eq. (10) bounds B^-1 A from below
+    # only for a B without the q term, so both forms run on such operators
+    ops0 = [ax.op_create(pr.kappa, pr.q, qbar=0.0) for pr in probs]
+
+    def timed_on(fn):
+        fn()      # warm-up
+        best, its = None, []
+        for _ in range(reps):
+            for x in xs:
+                x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            code, st = fn()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+            its = [s["iters"] for s in st]
+            assert code == ax.OK
+        return best, its
+
+    t_c, iters_c = timed_on(lambda: ax.batch_cheb_solve(ops0, bs, xs, rtol=1e-10, maxit=1000, prec=prec))
+    t_c0, iters_c0 = timed_on(lambda: ax.batch_solve(ops0, bs, xs, 1e-10, 1000, prec))
+    for op in ops0:
+        op.close()
     for x in xs:
         x.zero_()
     torch.cuda.synchronize()
@@ -504,7 +530,12 @@ def batch_measure(ax, torch, prec, reps=3):
             "ms_per_batch": round(t_b * 1e3, 3), "sequential_solves_per_s": round(64 / t_seq, 1),
             "iters_min_max": [min(iters), max(iters)],
             "single_launch": {"solves_per_s": round(64 / t_s, 1), "ms_per_batch": round(t_s * 1e3, 3),
-                              "iters_min_max": [min(iters_s), max(iters_s)]}}
+                              "iters_min_max": [min(iters_s), max(iters_s)]},
+            "chebyshev": {"preconditioner": "kbar only (qbar = 0)",
+                          "solves_per_s": round(64 / t_c, 1), "ms_per_batch": round(t_c * 1e3, 3),
+                          "iters_min_max": [min(iters_c), max(iters_c)],
+                          "pcg_same_operators": {"solves_per_s": round(64 / t_c0, 1),
+                                                 "iters_min_max": [min(iters_c0), max(iters_c0)]}}}
 
 
 def per_step_parity(ax, series, op, g, inp, a, net, last_b, last_u):

@@ -234,6 +234,19 @@ int axipcg_op_bounds(axipcg_op_t op, double *gamma1, double *gamma2);
 int axipcg_batch_solve(int n, const axipcg_op_t *ops, const double *const *b, double *const *x,
                        double rtol, int maxit, int prec, unsigned flags, axipcg_stats *st, void *stream);
 
+/* The Chebyshev form of eq. (8) (as axipcg_cheb_solve) for every problem of
+ * a batch, one launch per phase over the whole batch, with no inner products
+ * but ||r||^2 for the stop test.  gamma1, gamma2: host arrays of n bounds
+ * 0 < gamma1[p] <= gamma2[p] of the spectrum of B^{-1} A_p; NULL, or both
+ * entries <= 0, takes member p's own energy-equivalence bounds (eq. (10),
+ * which need gamma1 > 0: every q > 0 or qbar = 0).  ops, b, x, st, the member
+ * limits and the return value as for axipcg_batch_solve; flags: 0 or
+ * AXIPCG_FLAG_TRUE_RESIDUAL.  Each member's p0 work buffer holds its
+ * increment.  Synchronises the stream. */
+int axipcg_batch_cheb_solve(int n, const axipcg_op_t *ops, const double *const *b, double *const *x,
+                            const double *gamma1, const double *gamma2, double rtol, int maxit, int prec,
+                            unsigned flags, axipcg_stats *st, void *stream);
+
 /* ---- Laguerre series (§4.1 eqs. (34)-(35), alpha = 0) ----------------------
  * g_m = int_0^{t_max} f(t) l_m(t) dt, l_m(t) = sqrt(eta) e^{-eta t/2} L_m(eta t),
  * for m < n, from nt >= 3 uniform samples f_host[j] = f(j t_max/(nt-1)) (host).

@@ -81,6 +81,9 @@ SIGNATURES = {
     "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_batch_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _d, _i, _i, _u,
                             ctypes.POINTER(Stats), _vp], _i),
+    "axipcg_batch_cheb_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_d), ctypes.POINTER(_d), _d, _i, _i, _u, ctypes.POINTER(Stats), _vp],
+                                _i),
     "axipcg_laguerre_coeffs": ([_i, _d, _i, _d, _dp, _dp, _vp], _i),
     "axipcg_laguerre_rhs": ([_vp, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp], _i),
     "axipcg_guess_extrap": ([_vp, _vp, _vp, _vp, _vp, _dp, ctypes.POINTER(_i), _vp], _i),
@@ -319,6 +322,24 @@ def batch_solve(ops, bs, xs, rtol=1e-10, maxit=1000, prec=PREC_FP32, flags=0, st
     st = (Stats * n)()
     code = lib().axipcg_batch_solve(n, h, bp, xp, rtol, maxit, prec, flags, st, _stream(stream))
     _check(code, "batch_solve", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
+    return code, [s.as_dict() for s in st]
+
+
+def batch_cheb_solve(ops, bs, xs, gamma1=None, gamma2=None, rtol=1e-10, maxit=1000, prec=PREC_FP32, flags=0,
+                     stream=None, allow_notconv=True):
+    """The Chebyshev form for every member of a batch; gamma1, gamma2: a
+    bound per member (None: each member's own energy bounds)."""
+    n = len(ops)
+    if not (len(bs) == len(xs) == n):
+        raise ValueError("ops, bs and xs must have the same length")
+    h = (_vp * n)(*[o.handle.value for o in ops])
+    bp = (_vp * n)(*[_dev(t, "b").value for t in bs])
+    xp = (_vp * n)(*[_dev(t, "x").value for t in xs])
+    g1 = None if gamma1 is None else (_d * n)(*[float(v) for v in gamma1])
+    g2 = None if gamma2 is None else (_d * n)(*[float(v) for v in gamma2])
+    st = (Stats * n)()
+    code = lib().axipcg_batch_cheb_solve(n, h, bp, xp, g1, g2, rtol, maxit, prec, flags, st, _stream(stream))
+    _check(code, "batch_cheb_solve", allow=(OK, ENOTCONV) if allow_notconv else (OK,))
     return code, [s.as_dict() for s in st]
 
 

@@ -173,6 +173,7 @@ struct ProbDesc {
     int tr_start, n_tr;
     int sp_start, n_sp;
     int tri_S, tri_L, tri_Lp, tri_pitch;
+    double tau, rho2;   // Chebyshev form: 2 / (gamma1 + gamma2), ((1 - xi) / (1 + xi))^2, xi = gamma1 / gamma2
     const double *b;
     double *x;
     const double *D, *CR, *CZ;

@@ -40,6 +40,7 @@ struct TriGate {
     HostMirror *mirror = nullptr;
     unsigned seq = 0;
     int report = 0;
+    int rr_rows = 0;       // batched mode 1: one ||r||^2 partial per row (the Chebyshev update's)
 };
 void launch_tridiag(const Operator &op, int prec, const TriGate &g, hipStream_t s);
 
@@ -91,6 +92,9 @@ void batch_tri_geom(int nr, int prec, int M, int *S, int *L, int *Lp, int *pitch
 void launch_b_init(const ProbDesc *d, int n, int rows, hipStream_t s);
 void launch_b_zero(const ProbDesc *d, int n, int rows, hipStream_t s);
 void launch_b_spmv(const ProbDesc *d, int n, int tiles, bool pr, int parity, hipStream_t s);
+// Chebyshev step of every member (one workgroup per row): x += d, r -= A d,
+// ||r||^2 partials; d is the member's p0 buffer.
+void launch_b_cheb(const ProbDesc *d, int n, int rows, hipStream_t s);
 // One batched transform launch covers the problems d[off, off + n) of an
 // array sorted by transform plan: r2 = N / 128 for the one-wave plans, 0 for
 // the block-wide kernels (one row per workgroup); `blocks` workgroups in all.
@@ -100,9 +104,13 @@ struct BatchPlan {
 // Plan of a batch member with nz points per row: returns r2 and sets the rows
 // per transform workgroup.
 int batch_transform_plan(int nz, int prec, int *rows_per_wg);
-void launch_b_zfwd(const ProbDesc *d, const BatchPlan &pl, int prec, bool fused, int parity, hipStream_t s);
+// kind 0: start (plain transform of r); 1: PCG step (alpha, x and r update,
+// transform); 2: Chebyshev step (plain transform of r, skipped once stopped).
+enum { BZ_START = 0, BZ_PCG = 1, BZ_CHEB = 2 };
+void launch_b_zfwd(const ProbDesc *d, const BatchPlan &pl, int prec, int kind, int parity, hipStream_t s);
 void launch_b_tridiag(const ProbDesc *d, int n, int blocks, int prec, const TriGate &g, int M, size_t shm,
                       hipStream_t s);
+// mode as for launch_zinv (1, 2: PCG; 3, 4: Chebyshev, d in each member's p0)
 void launch_b_zinv(const ProbDesc *d, const BatchPlan &pl, int prec, int mode, bool pr, hipStream_t s);
 void launch_b_gather(const ProbDesc *d, int n, PcgState *out, hipStream_t s);
 // Dynamic LDS of a transform plan's workgroup; *twl: twiddles staged in LDS

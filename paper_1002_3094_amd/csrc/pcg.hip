@@ -56,37 +56,13 @@ unsigned spmv_blocks(int nr, int nz)
     return (unsigned)(tiles < MAX_PARTIALS ? tiles : MAX_PARTIALS);
 }
 
-// Chebyshev step of eq. (8) in increment form: x += d, r -= A d, ||r||^2
-// partials (one per workgroup, for the stop test of the r-solve launch);
-// workgroup 0 records the iteration being processed.
+// Chebyshev step of eq. (8) (spmv.h), the workgroups looping over the rows.
 __global__ void __launch_bounds__(256)
 k_cheb_update(const double *__restrict__ d, double *__restrict__ x, double *__restrict__ r,
               const double *__restrict__ D, const double *__restrict__ CR, const double *__restrict__ CZ, int nr,
               int nz, PcgState *st, double *__restrict__ partials)
 {
-    __shared__ double red[8];
-    if (st->done) return;
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->cur = st->iters;
-    double acc = 0.0;
-    for (int b = blockIdx.x; b < nr; b += gridDim.x) {
-        const int i = xcd_swizzle(b, nr);
-        for (int k = 2 * (int)threadIdx.x; k < nz; k += 2 * (int)blockDim.x) {
-            const size_t e = (size_t)i * nz + k;
-            const Pair dc = ld2(d + e);
-            const Pair ad = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc);
-            const Pair xc = ld2(x + e), rc = ld2(r + e);
-            double2 xn, rn;
-            xn.x = xc.a + dc.a;
-            xn.y = xc.b + dc.b;
-            rn.x = rc.a - ad.a;
-            rn.y = rc.b - ad.b;
-            *reinterpret_cast<double2 *>(x + e) = xn;
-            *reinterpret_cast<double2 *>(r + e) = rn;
-            acc += rn.x * rn.x + rn.y * rn.y;
-        }
-    }
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + blockIdx.x] = s;
+    cheb_update_body(d, x, r, D, CR, CZ, nr, nz, st, partials, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(256)
@@ -103,6 +79,11 @@ template <bool PR>
 __global__ void __launch_bounds__(256) k_b_spmv(const ProbDesc *__restrict__ d, int n, int parity)
 {
     b_spmv_item<PR>(d, n, blockIdx.x, parity);
+}
+
+__global__ void __launch_bounds__(256) k_b_cheb(const ProbDesc *__restrict__ d, int n)
+{
+    b_cheb_item(d, n, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(256) k_b_init(const ProbDesc *__restrict__ d, int n)
@@ -476,6 +457,12 @@ void launch_b_spmv(const ProbDesc *d, int n, int tiles, bool pr, int parity, hip
 {
     if (pr) hipLaunchKernelGGL(k_b_spmv<true>, dim3(tiles), dim3(256), 0, s, d, n, parity);
     else hipLaunchKernelGGL(k_b_spmv<false>, dim3(tiles), dim3(256), 0, s, d, n, parity);
+    AXI_CHECK_HIP(hipGetLastError());
+}
+
+void launch_b_cheb(const ProbDesc *d, int n, int rows, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_b_cheb, dim3(rows), dim3(256), 0, s, d, n);
     AXI_CHECK_HIP(hipGetLastError());
 }
 

@@ -73,10 +73,10 @@ k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict_
 // The batched transforms run one launch per transform plan; `d` holds the
 // problems of that plan, with tr_start counted within the launch.  One work
 // item (xform.h) per workgroup.
-template <typename T, bool FUSED, bool TWLDS>
+template <typename T, int KIND, bool TWLDS>
 __global__ void __launch_bounds__(256) k_b_zfwd(const ProbDesc *__restrict__ d, int n, int parity)
 {
-    b_zfwd_item<T, FUSED, TWLDS, false>(d, n, blockIdx.x, parity);
+    b_zfwd_item<T, KIND == BZ_PCG, TWLDS, false, KIND == BZ_CHEB>(d, n, blockIdx.x, parity);
 }
 
 template <typename T, int MODE, bool TWLDS>
@@ -85,10 +85,10 @@ __global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, 
     b_zinv_item<T, MODE, TWLDS>(d, n, blockIdx.x, pr);
 }
 
-template <typename T, bool FUSED, int R2>
+template <typename T, int KIND, int R2>
 __global__ void __launch_bounds__(256) k_b_zfwd_w(const ProbDesc *__restrict__ d, int n, int parity)
 {
-    b_zfwd_w_item<T, FUSED, R2, false>(d, n, blockIdx.x, parity);
+    b_zfwd_w_item<T, KIND == BZ_PCG, R2, false, KIND == BZ_CHEB>(d, n, blockIdx.x, parity);
 }
 
 template <typename T, int MODE, int R2>
@@ -413,16 +413,15 @@ int batch_transform_plan(int nz, int prec, int *rows_per_wg)
 }
 
 template <typename T, int R2>
-void b_zfwd_wave(const ProbDesc *d, const BatchPlan &pl, bool fused, int parity, hipStream_t s)
+void b_zfwd_wave(const ProbDesc *d, const BatchPlan &pl, int kind, int parity, hipStream_t s)
 {
     constexpr int WR = wave_rows<T, R2>();
     const size_t shm = (size_t)WR * wfft::Geo<R2>::LB * sizeof(cx<T>);
-    if (fused)
-        hipLaunchKernelGGL((k_b_zfwd_w<T, true, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n,
-                           parity);
-    else
-        hipLaunchKernelGGL((k_b_zfwd_w<T, false, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n,
-                           parity);
+#define AXI_BZW(K) hipLaunchKernelGGL((k_b_zfwd_w<T, K, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n, parity)
+    if (kind == BZ_PCG) AXI_BZW(BZ_PCG);
+    else if (kind == BZ_CHEB) AXI_BZW(BZ_CHEB);
+    else AXI_BZW(BZ_START);
+#undef AXI_BZW
 }
 
 template <typename T, int R2>
@@ -430,34 +429,42 @@ void b_zinv_wave(const ProbDesc *d, const BatchPlan &pl, int mode, bool pr, hipS
 {
     constexpr int WR = wave_rows<T, R2>();
     const size_t shm = (size_t)WR * wfft::Geo<R2>::LB * sizeof(cx<T>);
-    if (mode == 1)
-        hipLaunchKernelGGL((k_b_zinv_w<T, 1, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n, pr);
-    else
-        hipLaunchKernelGGL((k_b_zinv_w<T, 2, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n, pr);
+#define AXI_BIW(MD) hipLaunchKernelGGL((k_b_zinv_w<T, MD, R2>), dim3(pl.blocks), dim3(64 * WR), shm, s, d + pl.off, pl.n, pr)
+    switch (mode) {
+    case 1: AXI_BIW(1); break;
+    case 2: AXI_BIW(2); break;
+    case 3: AXI_BIW(3); break;
+    default: AXI_BIW(4);
+    }
+#undef AXI_BIW
 }
 
 template <typename T>
-void b_zfwd_t(const ProbDesc *d, const BatchPlan &pl, bool fused, int parity, hipStream_t s)
+void b_zfwd_t(const ProbDesc *d, const BatchPlan &pl, int kind, int parity, hipStream_t s)
 {
     switch (pl.r2) {
-    case 2: b_zfwd_wave<T, 2>(d, pl, fused, parity, s); break;
-    case 4: b_zfwd_wave<T, 4>(d, pl, fused, parity, s); break;
-    case 8: b_zfwd_wave<T, 8>(d, pl, fused, parity, s); break;
+    case 2: b_zfwd_wave<T, 2>(d, pl, kind, parity, s); break;
+    case 4: b_zfwd_wave<T, 4>(d, pl, kind, parity, s); break;
+    case 8: b_zfwd_wave<T, 8>(d, pl, kind, parity, s); break;
     case 16:
-        if constexpr (sizeof(T) == 4) b_zfwd_wave<T, 16>(d, pl, fused, parity, s);
+        if constexpr (sizeof(T) == 4) b_zfwd_wave<T, 16>(d, pl, kind, parity, s);
         else AXI_REQUIRE(false, "no one-wave FP64 plan for N = 2048");
         break;
     default: {
         const size_t shm = transform_lds<T>(pl.nz_max);
         const dim3 grid(pl.blocks), block(256);
         const ProbDesc *dp = d + pl.off;
+#define AXI_BZF(K, TW) hipLaunchKernelGGL((k_b_zfwd<T, K, TW>), grid, block, shm, s, dp, pl.n, parity)
         if (twiddles_in_lds<T>(pl.nz_max)) {
-            if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, true>), grid, block, shm, s, dp, pl.n, parity);
-            else hipLaunchKernelGGL((k_b_zfwd<T, false, true>), grid, block, shm, s, dp, pl.n, parity);
+            if (kind == BZ_PCG) AXI_BZF(BZ_PCG, true);
+            else if (kind == BZ_CHEB) AXI_BZF(BZ_CHEB, true);
+            else AXI_BZF(BZ_START, true);
         } else {
-            if (fused) hipLaunchKernelGGL((k_b_zfwd<T, true, false>), grid, block, shm, s, dp, pl.n, parity);
-            else hipLaunchKernelGGL((k_b_zfwd<T, false, false>), grid, block, shm, s, dp, pl.n, parity);
+            if (kind == BZ_PCG) AXI_BZF(BZ_PCG, false);
+            else if (kind == BZ_CHEB) AXI_BZF(BZ_CHEB, false);
+            else AXI_BZF(BZ_START, false);
         }
+#undef AXI_BZF
     }
     }
     AXI_CHECK_HIP(hipGetLastError());
@@ -480,22 +487,29 @@ void b_zinv_t(const ProbDesc *d, const BatchPlan &pl, int mode, bool pr, hipStre
         const dim3 grid(pl.blocks), block(256);
         const ProbDesc *dp = d + pl.off;
 #define AXI_BZI(MD, TW) hipLaunchKernelGGL((k_b_zinv<T, MD, TW>), grid, block, shm, s, dp, pl.n, pr)
-        if (mode == 1) { if (twl) AXI_BZI(1, true); else AXI_BZI(1, false); }
-        else { if (twl) AXI_BZI(2, true); else AXI_BZI(2, false); }
+#define AXI_BZI2(MD) do { if (twl) AXI_BZI(MD, true); else AXI_BZI(MD, false); } while (0)
+        switch (mode) {
+        case 1: AXI_BZI2(1); break;
+        case 2: AXI_BZI2(2); break;
+        case 3: AXI_BZI2(3); break;
+        default: AXI_BZI2(4);
+        }
+#undef AXI_BZI2
 #undef AXI_BZI
     }
     }
     AXI_CHECK_HIP(hipGetLastError());
 }
 
-void launch_b_zfwd(const ProbDesc *d, const BatchPlan &pl, int prec, bool fused, int parity, hipStream_t s)
+void launch_b_zfwd(const ProbDesc *d, const BatchPlan &pl, int prec, int kind, int parity, hipStream_t s)
 {
-    if (prec == AXIPCG_PREC_FP32) b_zfwd_t<float>(d, pl, fused, parity, s);
-    else b_zfwd_t<double>(d, pl, fused, parity, s);
+    if (prec == AXIPCG_PREC_FP32) b_zfwd_t<float>(d, pl, kind, parity, s);
+    else b_zfwd_t<double>(d, pl, kind, parity, s);
 }
 
 void launch_b_zinv(const ProbDesc *d, const BatchPlan &pl, int prec, int mode, bool pr, hipStream_t s)
 {
+    AXI_REQUIRE(mode >= 1 && mode <= 4, "batched inverse transform mode must be 1..4");
     if (prec == AXIPCG_PREC_FP32) b_zinv_t<float>(d, pl, mode, pr, s);
     else b_zinv_t<double>(d, pl, mode, pr, s);
 }

@@ -180,6 +180,40 @@ __device__ __forceinline__ void spmv_tiles(const double *__restrict__ z, const d
     if (threadIdx.x == 0) partials[SLOT_PQ * MAX_PARTIALS + vb] = s;
 }
 
+// Chebyshev step of eq. (8) in increment form: x += d, r -= A d, ||r||^2
+// partials (rows vb, vb + vnb, ...; one partial, in slot vb, for the stop
+// test of the r-solve launch); item 0 records the iteration being processed.
+__device__ __forceinline__ void cheb_update_body(const double *__restrict__ d, double *__restrict__ x,
+                                                 double *__restrict__ r, const double *__restrict__ D,
+                                                 const double *__restrict__ CR, const double *__restrict__ CZ,
+                                                 int nr, int nz, PcgState *st, double *__restrict__ partials, int vb,
+                                                 int vnb)
+{
+    __shared__ double red[8];
+    if (st->done) return;
+    if (vb == 0 && threadIdx.x == 0) st->cur = st->iters;
+    double acc = 0.0;
+    for (int b = vb; b < nr; b += vnb) {
+        const int i = xcd_swizzle(b, nr);
+        for (int k = 2 * (int)threadIdx.x; k < nz; k += 2 * (int)blockDim.x) {
+            const size_t e = (size_t)i * nz + k;
+            const Pair dc = ld2(d + e);
+            const Pair ad = stencil2(d, D, CR, CZ, e, i, k, nr, nz, dc);
+            const Pair xc = ld2(x + e), rc = ld2(r + e);
+            double2 xn, rn;
+            xn.x = xc.a + dc.a;
+            xn.y = xc.b + dc.b;
+            rn.x = rc.a - ad.a;
+            rn.y = rc.b - ad.b;
+            *reinterpret_cast<double2 *>(x + e) = xn;
+            *reinterpret_cast<double2 *>(r + e) = rn;
+            acc += rn.x * rn.x + rn.y * rn.y;
+        }
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[SLOT_RR * MAX_PARTIALS + vb] = s;
+}
+
 // r = b - A x; ||r||^2 and ||b||^2 partials.
 __device__ __forceinline__ void init_body(const double *__restrict__ b, const double *__restrict__ x,
                                           double *__restrict__ r, const double *__restrict__ D,
@@ -236,6 +270,14 @@ __device__ __forceinline__ void b_init_item(const ProbDesc *__restrict__ d, int 
     const int p = find_problem(d, n, g, RANGE_ROWS);
     const ProbDesc &P = d[p];
     init_body(P.b, P.x, P.r, P.D, P.CR, P.CZ, P.nr, P.nz, P.partials, g - P.row_start, P.nr);
+}
+
+// Chebyshev step on one row of a member (d in its p0 buffer).
+__device__ __forceinline__ void b_cheb_item(const ProbDesc *__restrict__ d, int n, int g)
+{
+    const int p = find_problem(d, n, g, RANGE_ROWS);
+    const ProbDesc &P = d[p];
+    cheb_update_body(P.p0, P.x, P.r, P.D, P.CR, P.CZ, P.nr, P.nz, P.state, P.partials, g - P.row_start, P.nr);
 }
 
 // x = 0 on the row when the problem's b = 0 (after the start test).

@@ -483,8 +483,10 @@ template <> __device__ inline const double2 *pd_pt<double>(const ProbDesc &P) { 
 // problems of one transform plan, with tr_start counted within the plan.
 // WG_STOP: the fused forward reads the stop flag once per workgroup, for
 // workgroups that go on to other items (no wave may leave an item that the
-// others go on with).
-template <typename T, bool FUSED, bool TWLDS, bool WG_STOP>
+// others go on with).  GATE: the plain transform of the Chebyshev step, which
+// returns once the member has stopped.  The inverse transforms' modes 3 and 4
+// form the Chebyshev increment in the member's p0 buffer with its tau, rho2.
+template <typename T, bool FUSED, bool TWLDS, bool WG_STOP, bool GATE = false>
 __device__ __forceinline__ void b_zfwd_item(const ProbDesc *__restrict__ d, int n, int g, int parity)
 {
     const int p = find_problem(d, n, g, RANGE_TR);
@@ -492,8 +494,8 @@ __device__ __forceinline__ void b_zfwd_item(const ProbDesc *__restrict__ d, int 
     const double *pnew = parity ? P.p0 : P.p1;   // written by this iteration's SpMV
     const int vb = g - P.tr_start;
     // the start-up transform runs before the r-solve launch resets the state,
-    // so only the in-loop (fused) transform may read the stop flag
-    PcgState *st = FUSED ? P.state : nullptr;
+    // so only the in-loop transforms may read the stop flag
+    PcgState *st = (FUSED || GATE) ? P.state : nullptr;
     if (P.bc_z == DIR)
         zfwd_body<T, DIR, FUSED, TWLDS, 1, WG_STOP>(P.r, P.x, P.r, pnew, P.q, st, P.partials, P.n_sp, (T *)P.spec,
                                         pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
@@ -510,20 +512,20 @@ __device__ __forceinline__ void b_zinv_item(const ProbDesc *__restrict__ d, int 
     const int vb = g - P.tr_start;
     if (P.bc_z == DIR)
         zinv_body<T, DIR, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P),
-                                       pd_pt<T>(P), P.nr, P.nz, vb);
+                                       pd_pt<T>(P), P.nr, P.nz, vb, P.p0, P.tau, P.rho2);
     else
         zinv_body<T, AXIPCG_Z_NEUMANN, MODE, TWLDS, 1>((const T *)P.spec, P.z, P.r, P.state, P.partials, pr,
-                                                    pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb);
+                                                    pd_tw<T>(P), pd_pt<T>(P), P.nr, P.nz, vb, P.p0, P.tau, P.rho2);
 }
 
-template <typename T, bool FUSED, int R2, bool WG_STOP>
+template <typename T, bool FUSED, int R2, bool WG_STOP, bool GATE = false>
 __device__ __forceinline__ void b_zfwd_w_item(const ProbDesc *__restrict__ d, int n, int g, int parity)
 {
     const int p = find_problem(d, n, g, RANGE_TR);
     const ProbDesc &P = d[p];
     const double *pnew = parity ? P.p0 : P.p1;
     const int vb = g - P.tr_start;
-    PcgState *st = FUSED ? P.state : nullptr;   // as in k_b_zfwd
+    PcgState *st = (FUSED || GATE) ? P.state : nullptr;   // as in b_zfwd_item
     constexpr int WR = wave_rows<T, R2>();
     const int row = vb * WR + (threadIdx.x >> 6);
     RowStore<T> out{(T *)P.spec + (size_t)(row < P.nr ? row : 0) * wfft::Geo<R2>::N};
@@ -545,11 +547,11 @@ __device__ __forceinline__ void b_zinv_w_item(const ProbDesc *__restrict__ d, in
     const int row = vb * WR + (threadIdx.x >> 6);
     RowLoad<T> in{(const T *)P.spec + (size_t)(row < P.nr ? row : P.nr - 1) * wfft::Geo<R2>::N};
     if (P.bc_z == DIR)
-        zinv_w_body<T, DIR, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P), P.nr, nullptr,
-                                      0.0, 0.0, row, vb);
+        zinv_w_body<T, DIR, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P), P.nr, P.p0,
+                                      P.tau, P.rho2, row, vb);
     else
         zinv_w_body<T, AXIPCG_Z_NEUMANN, MODE, R2>(in, P.z, P.r, P.state, P.partials, pr, pd_tw<T>(P), pd_pt<T>(P),
-                                                   P.nr, nullptr, 0.0, 0.0, row, vb);
+                                                   P.nr, P.p0, P.tau, P.rho2, row, vb);
 }
 
 template <typename T>
@@ -559,7 +561,7 @@ __device__ __forceinline__ void b_tridiag_item(const ProbDesc *__restrict__ d, i
     const ProbDesc &P = d[p];
     const int vb = item - P.tri_start;
     g.state = P.state;
-    g.n_rr = g.mode == 2 ? P.nr : P.n_tr;   // start: the init partials, one per row
+    g.n_rr = (g.mode == 2 || g.rr_rows) ? P.nr : P.n_tr;   // one partial per row: the start's, Chebyshev's
     const bool uni = (P.nr % P.tri_S) == 0;
 #define AXI_BTRI(LM, U)                                                                                       \
     tridiag_body<T, LM, U>((T *)P.spec, pd_cb<T>(P), pd_db<T>(P), pd_rw<T>(P), pd_lam<T>(P), P.state,           \

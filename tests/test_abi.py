@@ -132,6 +132,16 @@ def test_null_handles_rejected(ax):
     assert lib.axipcg_pcg_solve(None, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
     assert lib.axipcg_precond_apply(None, None, None, 1, None) == ax.EINVAL
     lib.axipcg_op_destroy(None)  # NULL-safe
+    # batched solves: NULL arrays, a NULL member, bad counts, flags and bounds
+    n1 = (ax._vp * 1)(None)
+    assert lib.axipcg_batch_solve(1, None, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_solve(1, n1, n1, n1, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_solve(0, n1, n1, n1, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_solve(1, n1, n1, n1, 1e-10, 10, 1, 8, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_cheb_solve(1, None, None, None, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_cheb_solve(1, n1, n1, n1, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_cheb_solve(1, n1, n1, n1, None, None, 1e-10, 10, 1, 2, None, None) == ax.EINVAL
+    assert lib.axipcg_batch_cheb_solve(1, n1, n1, n1, None, None, 2.0, 10, 1, 0, None, None) == ax.EINVAL
 
 
 def test_laguerre_coeffs_validates(ax):
