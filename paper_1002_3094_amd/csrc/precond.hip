@@ -85,8 +85,14 @@ __global__ void __launch_bounds__(256) k_b_zinv(const ProbDesc *__restrict__ d, 
     b_zinv_item<T, MODE, TWLDS>(d, n, blockIdx.x, pr);
 }
 
+// Two waves per SIMD for the FP32 plans up to rows of 1024 points: the fused
+// 1024-point forward needs 259 registers when left unbounded (one wave per
+// SIMD) and fits 256 without spilling; the larger plans would spill.
+template <typename T, int R2>
+constexpr int bzw_waves() { return (sizeof(T) == 4 && R2 <= 8) ? 2 : 1; }
+
 template <typename T, int KIND, int R2>
-__global__ void __launch_bounds__(256) k_b_zfwd_w(const ProbDesc *__restrict__ d, int n, int parity)
+__global__ void __launch_bounds__(256, (bzw_waves<T, R2>())) k_b_zfwd_w(const ProbDesc *__restrict__ d, int n, int parity)
 {
     b_zfwd_w_item<T, KIND == BZ_PCG, R2, false, KIND == BZ_CHEB>(d, n, blockIdx.x, parity);
 }
