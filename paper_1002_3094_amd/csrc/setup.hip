@@ -52,15 +52,32 @@ __global__ void k_coeffs(const double *__restrict__ kr, const double *__restrict
     }
 }
 
-// Deterministic sums of two fields (one block, fixed order).
-__global__ void k_sum2(const double *__restrict__ a, const double *__restrict__ b, size_t n,
-                       double *__restrict__ out)
+// Deterministic sums of two fields: one partial pair per workgroup (fixed
+// grid-stride order), then one workgroup adds the partials in index order.
+__global__ void __launch_bounds__(256)
+k_sum2_part(const double *__restrict__ a, const double *__restrict__ b, size_t n, double *__restrict__ part)
 {
     __shared__ double red[16];
     double sa = 0.0, sb = 0.0;
-    for (size_t e = threadIdx.x; e < n; e += blockDim.x) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
         sa += a[e];
         sb += b[e];
+    }
+    const double ta = block_sum(sa, red);
+    const double tb = block_sum(sb, red);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = ta;
+        part[2 * blockIdx.x + 1] = tb;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_sum2_fin(const double *__restrict__ part, int nb, double *__restrict__ out)
+{
+    __shared__ double red[16];
+    double sa = 0.0, sb = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        sa += part[2 * i];
+        sb += part[2 * i + 1];
     }
     const double ta = block_sum(sa, red);
     const double tb = block_sum(sb, red);
@@ -275,15 +292,18 @@ Operator *create_impl(int nr, int nz, double lr, double lz, int bc_z, const doub
             double **p[5];
             ~Tmp() { for (auto pp : p) if (*pp) (void)hipFree(*pp); }
         } tmp{{&d_kr, &d_kz, &d_q, &d_kc, &d_kq}};
-        dmalloc(&d_kr, n); dmalloc(&d_kz, (size_t)nr * (nz + 1)); dmalloc(&d_q, n); dmalloc(&d_kq, 2);
-        AXI_CHECK_HIP(hipMemcpyAsync(d_q, q, n * sizeof(double), hipMemcpyHostToDevice, s));
         const unsigned blocks = pointwise_blocks(n);
+        dmalloc(&d_kr, n); dmalloc(&d_kz, (size_t)nr * (nz + 1)); dmalloc(&d_q, n);
+        dmalloc(&d_kq, 2 + 2 * (size_t)blocks);   // the two sums, then the partials
+        AXI_CHECK_HIP(hipMemcpyAsync(d_q, q, n * sizeof(double), hipMemcpyHostToDevice, s));
         if (kappa_cells) {
             dmalloc(&d_kc, n);
             AXI_CHECK_HIP(hipMemcpyAsync(d_kc, kappa_cells, n * sizeof(double), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_face_kappa, dim3(blocks), dim3(256), 0, s, d_kc, d_kr, d_kz, nr, nz);
             AXI_CHECK_HIP(hipGetLastError());
-            hipLaunchKernelGGL(k_sum2, dim3(1), dim3(1024), 0, s, d_kc, d_q, n, d_kq);
+            hipLaunchKernelGGL(k_sum2_part, dim3(blocks), dim3(256), 0, s, d_kc, d_q, n, d_kq + 2);
+            AXI_CHECK_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_sum2_fin, dim3(1), dim3(1024), 0, s, d_kq + 2, (int)blocks, d_kq);
             AXI_CHECK_HIP(hipGetLastError());
         } else {
             AXI_CHECK_HIP(hipMemcpyAsync(d_kr, kappa_r, n * sizeof(double), hipMemcpyHostToDevice, s));
