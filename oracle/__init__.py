@@ -379,6 +379,48 @@ def energy_bounds(op: Operator):
     return float(allr.min()), float(allr.max())
 
 
+def lanczos_tridiagonal(op: Operator, b, steps: int):
+    """The Lanczos matrix T_k of B^{-1} A (symmetric in the B inner product)
+    taken out of k steps of PCG from x = 0 on A x = b (§2.2 eq. (8) with the
+    conjugate-gradient parameters alpha_j = r_j.z_j / p_j.A p_j and
+    beta_j = r_{j+1}.z_{j+1} / r_j.z_j): the Lanczos vectors are the
+    normalised residuals, and
+        T[j][j]   = 1 / alpha_j + beta_{j-1} / alpha_{j-1}   (no second term for j = 0),
+        T[j][j+1] = sqrt(beta_j) / alpha_j.
+    Stops early when r.z vanishes.  Returns (diagonal, off-diagonal)."""
+    r = _c(b).copy()
+    z = precond(op, r)
+    p = z.copy()
+    rho = dot(r, z)
+    alphas, betas = [], []
+    for _ in range(steps):
+        if not rho > 0.0:
+            break
+        q = apply(op, p)
+        alpha = rho / dot(p, q)
+        r -= alpha * q
+        z = precond(op, r)
+        rho_new = dot(r, z)
+        alphas.append(alpha)
+        betas.append(rho_new / rho)
+        p = z + betas[-1] * p
+        rho = rho_new
+    m = len(alphas)
+    d = np.array([1.0 / alphas[j] + (betas[j - 1] / alphas[j - 1] if j > 0 else 0.0) for j in range(m)])
+    e = np.array([math.sqrt(max(betas[j], 0.0)) / alphas[j] for j in range(m - 1)])
+    return d, e
+
+
+def lanczos_bounds(op: Operator, b, steps: int):
+    """The smallest and largest eigenvalues of the Lanczos matrix of
+    lanczos_tridiagonal (Ritz values of B^{-1} A: inside its spectrum, the
+    extreme ones approaching its ends as the steps grow)."""
+    d, e = lanczos_tridiagonal(op, b, steps)
+    T = np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1])
+
+
 def cheb_alpha(m: int, rho2: float) -> float:
     """alpha_m of the Chebyshev parameters of eq. (8): alpha_1 = 1,
     alpha_2 = 2 / (2 - rho0^2), alpha_{k+1} = 4 / (4 - rho0^2 alpha_k)."""
