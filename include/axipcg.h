@@ -213,6 +213,20 @@ int axipcg_cheb_solve(axipcg_op_t op, const double *b, double *x, double gamma1,
  * over cells (when qbar > 0).  gamma1 is 0 when some q is 0 and qbar > 0. */
 int axipcg_op_bounds(axipcg_op_t op, double *gamma1, double *gamma2);
 
+/* Lanczos estimates of the spectrum of B^{-1} A taken out of `steps` PCG
+ * steps (§2.2 eq. (8) with conjugate-gradient parameters) from x = 0 on
+ * A x = b: the extreme eigenvalues of the Lanczos matrix (diagonal
+ * 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j).
+ * They lie inside the spectrum and approach its ends as the steps grow, so
+ * gamma1 suits the Chebyshev form as its lower parameter where eq. (10) gives
+ * none (components below it are still damped), with eq. (10)'s gamma2 as the
+ * upper one.  b: device [nr][nz], non-zero; steps in [1, 1000]; prec as for
+ * pcg_solve; gamma1, gamma2, steps_done (the steps completed; fewer when the
+ * residual vanishes): host pointers, each may be NULL.  Uses the handle's
+ * work vectors (not b).  Synchronises the stream after every step. */
+int axipcg_op_bounds_lanczos(axipcg_op_t op, const double *b, int steps, int prec, double *gamma1,
+                             double *gamma2, int *steps_done, void *stream);
+
 /* ---- batched PCG over independent problems (§2.2 eq. (8) for each) ---------
  * Solve A_p x_p = b_p for p < n at once; ops[p] are distinct handles (each
  * problem uses its handle's workspace), b[p] and x[p] device pointers of that

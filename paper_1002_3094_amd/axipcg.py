@@ -81,6 +81,7 @@ SIGNATURES = {
     "axipcg_pcg_solve": ([_vp, _vp, _vp, _d, _i, _i, _u, ctypes.POINTER(Stats), _vp], _i),
     "axipcg_batch_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp), _d, _i, _i, _u,
                             ctypes.POINTER(Stats), _vp], _i),
+    "axipcg_op_bounds_lanczos": ([_vp, _vp, _i, _i, _dp, _dp, ctypes.POINTER(_i), _vp], _i),
     "axipcg_batch_cheb_solve": ([_i, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(_d), ctypes.POINTER(_d), _d, _i, _i, _u, ctypes.POINTER(Stats), _vp],
                                 _i),
@@ -298,6 +299,16 @@ def op_bounds(op: Op):
     g1, g2 = _d(), _d()
     _check(lib().axipcg_op_bounds(op.handle, ctypes.byref(g1), ctypes.byref(g2)), "op_bounds")
     return g1.value, g2.value
+
+
+def op_bounds_lanczos(op: Op, b, steps=20, prec=PREC_FP64, stream=None):
+    """Extreme Ritz values of B^{-1} A from `steps` PCG steps on A x = b:
+    (gamma1, gamma2, steps done)."""
+    g1, g2, k = _d(), _d(), _i()
+    _check(lib().axipcg_op_bounds_lanczos(op.handle, _dev(b, "b"), int(steps), prec, ctypes.byref(g1),
+                                          ctypes.byref(g2), ctypes.byref(k), _stream(stream)),
+           "op_bounds_lanczos")
+    return g1.value, g2.value, k.value
 
 
 def cheb_solve(op: Op, b, x, gamma1=0.0, gamma2=0.0, rtol=1e-10, maxit=1000, prec=PREC_FP32, stream=None,

@@ -132,6 +132,7 @@ def test_null_handles_rejected(ax):
     assert lib.axipcg_pcg_solve(None, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
     assert lib.axipcg_precond_apply(None, None, None, 1, None) == ax.EINVAL
     lib.axipcg_op_destroy(None)  # NULL-safe
+    assert lib.axipcg_op_bounds_lanczos(None, None, 10, 1, None, None, None, None) == ax.EINVAL
     # batched solves: NULL arrays, a NULL member, bad counts, flags and bounds
     n1 = (ax._vp * 1)(None)
     assert lib.axipcg_batch_solve(1, None, None, None, 1e-10, 10, 1, 0, None, None) == ax.EINVAL
