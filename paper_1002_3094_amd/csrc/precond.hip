@@ -131,14 +131,15 @@ bool twiddles_in_lds(int N) { return 3 * (size_t)N * sizeof(cx<T>) <= 65536; }
 template <typename T>
 size_t transform_lds(int N) { return (twiddles_in_lds<T>(N) ? 3 : 2) * (size_t)N * sizeof(cx<T>); }
 
-// Rows per transform workgroup: two (pipelined) for the FP64 transforms when
-// that still leaves at least 256 workgroups, else one.  (Measured at 1024^2:
-// two rows take the FP64 forward transform from 28 to 25 us but slow the FP32
-// ones, whose FFT is too short to hide a second row's loads behind while the
-// grid loses half its workgroups.)
-inline int transform_rows(int nr, int prec)
+// Rows per transform workgroup: two (pipelined) for the FP64 transforms, and
+// for the FP32 ones of rows of 4096 points, when that still leaves at least
+// 256 workgroups, else one.  (Measured at 1024^2: two rows take the FP64
+// forward transform from 28 to 25 us but slow the FP32 ones, whose FFT is too
+// short to hide a second row's loads behind while the grid loses half its
+// workgroups; at 4096^2 the FP32 apply goes from 528 to 503 us with two.)
+inline int transform_rows(int nr, int nz, int prec)
 {
-    return (prec == AXIPCG_PREC_FP64 && nr % 2 == 0 && nr >= 512) ? 2 : 1;
+    return ((prec == AXIPCG_PREC_FP64 || nz >= 4096) && nr % 2 == 0 && nr >= 512) ? 2 : 1;
 }
 
 // Dynamic LDS above the default 64 KiB (FP64 rows of 4096) needs the
@@ -213,7 +214,7 @@ void zfwd_t(const Operator &op, const ZfwdArgs &a, hipStream_t s)
     default: break;
     }
     const bool twl = twiddles_in_lds<T>(op.nz);
-    if (transform_rows(op.nr, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
+    if (transform_rows(op.nr, op.nz, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
         if (twl) zfwd_ttr<T, BC, true, 2>(op, a, s);
         else zfwd_ttr<T, BC, false, 2>(op, a, s);
     } else {
@@ -307,7 +308,7 @@ void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
     default: break;
     }
     const bool twl = twiddles_in_lds<T>(op.nz);
-    if (transform_rows(op.nr, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
+    if (transform_rows(op.nr, op.nz, sizeof(T) == 8 ? AXIPCG_PREC_FP64 : AXIPCG_PREC_FP32) == 2) {
         if (twl) zinv_ttr<T, BC, true, 2>(op, a, s);
         else zinv_ttr<T, BC, false, 2>(op, a, s);
     } else {
@@ -377,7 +378,7 @@ int transform_blocks(const Operator &op, int prec)
     if (strip_usable(op, prec, strip_solve_rows(op, prec))) return op.nr / strip_solve_rows(op, prec);
     const int wr = (prec == AXIPCG_PREC_FP32) ? wave_plan_rows<float>(op.nz) : wave_plan_rows<double>(op.nz);
     if (wr > 0) return (op.nr + wr - 1) / wr;
-    return op.nr / transform_rows(op.nr, prec);
+    return op.nr / transform_rows(op.nr, op.nz, prec);
 }
 
 // ---- batched launchers -------------------------------------------------------
