@@ -317,6 +317,11 @@ void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
     }
 }
 
+// LDS of an r-solve workgroup (its [M][N_r] tile, padded): up to 96 KiB, so
+// that rows of 4096 keep four FP32 modes (16-byte row loads) or two FP64 ones
+// per workgroup (the kernels' attribute raised on first use).
+constexpr size_t TRI_LDS_MAX = 96 * 1024;
+
 struct TriGeom {
     int M, S, L, Lp, pitch;
     size_t shm;
@@ -332,7 +337,7 @@ TriGeom tri_geom(int nr, int nz)
     g.pitch = nr + nr / g.Lp + 1;
     g.M = 16 / (int)sizeof(T);   // one 16-byte vector of modes per row
     auto lds = [&](int M) { return (size_t)M * g.pitch * sizeof(T); };
-    while (g.M > 1 && (lds(g.M) > 65536 || nz % g.M != 0)) g.M >>= 1;
+    while (g.M > 1 && (lds(g.M) > TRI_LDS_MAX || nz % g.M != 0)) g.M >>= 1;
     g.shm = lds(g.M);
     return g;
 }
@@ -345,14 +350,23 @@ void tridiag_t(const Operator &op, const TriGate &gate, hipStream_t s)
     const dim3 grid(op.nz / g.M), block(64 * g.M);
     T *spec = (T *)op.spec;
 #define AXI_TRI(LM, U)                                                                                   \
-    hipLaunchKernelGGL((k_tridiag<T, LM, U>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam,  \
-                       gate.state, op.partials, gate, op.nr, op.nz, g.M, g.S, g.pitch, g.Lp)
+    do {                                                                                                 \
+        static bool lds_set = false;                                                                     \
+        if (g.shm > 65536 && !lds_set) {                                                                 \
+            AXI_CHECK_HIP(hipFuncSetAttribute((const void *)k_tridiag<T, LM, U>,                          \
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)TRI_LDS_MAX)); \
+            lds_set = true;                                                                              \
+        }                                                                                                \
+        hipLaunchKernelGGL((k_tridiag<T, LM, U>), grid, block, g.shm, s, spec, tb.cb, tb.db, tb.rw, tb.lam, \
+                           gate.state, op.partials, gate, op.nr, op.nz, g.M, g.S, g.pitch, g.Lp);          \
+    } while (0)
     const bool uni = (op.nr % g.S) == 0;
     if (uni && g.L == 2) AXI_TRI(2, true);
     else if (uni && g.L == 4) AXI_TRI(4, true);
     else if (uni && g.L == 8) AXI_TRI(8, true);
     else if (uni && g.L == 16) AXI_TRI(16, true);
     else if (uni && g.L == 32) AXI_TRI(32, true);
+    else if (uni && g.L == 64) AXI_TRI(64, true);
     else if (g.L <= 4) AXI_TRI(4, false);
     else if (g.L <= 8) AXI_TRI(8, false);
     else if (g.L <= 16) AXI_TRI(16, false);
