@@ -14,7 +14,7 @@ u = 0), z cell-centred with Neumann walls as in §4.1 eq. (32):
   steps) fails the closed-form pin;
 * the literal z-grid of §2.1 (h_z = l_2/(N_2 - 1/2)) with the one-sided
   boundary flux the paper prints (and its cosine basis, eq. (38), assumes)
-  is first order: the reason this build keeps z cell-centred.
+  is first order: the reason the solver keeps z cell-centred.
 """
 import numpy as np
 import pytest
