@@ -132,7 +132,8 @@ def source_sha():
     h.update(pcg[pcg.index("template <bool PR, int RW>\n__global__"):pcg.index("// Chebyshev step of eq. (8)")].encode())
     com = open(os.path.join(csrc, "common.h")).read()
     for start in ("struct PcgState {", "enum Slot {", "constexpr int MAX_PARTIALS",
-                  "__device__ inline double block_sum(", "__device__ inline double block_total(",
+                  "__device__ inline double block_sum(", "struct TotalLoads {", "__device__ inline void total_issue(",
+                  "__device__ inline double total_finish(", "__device__ inline double block_total(",
                   "__device__ inline int xcd_swizzle("):
         h.update(_block(com, start).encode())
     return h.hexdigest()[:16]

@@ -263,11 +263,27 @@ __device__ inline double block_sum(double v, double *sm)
 // tree), returned in every thread.  `sm` needs blockDim.x / 64 + 1 doubles.
 // Each thread issues its (up to eight) loads before the first add, so the
 // reads of one round are in flight together rather than one latency apiece.
-__device__ inline double block_total(const double *__restrict__ parts, int n, double *sm)
+// The first round can be issued early (total_issue) and the sum finished
+// later (total_finish), with the same additions in the same order.
+struct TotalLoads {
+    double v[8];
+};
+
+__device__ inline void total_issue(const double *__restrict__ parts, int n, TotalLoads &t)
 {
-    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int i = (int)threadIdx.x + j * (int)blockDim.x;
+        t.v[j] = (i < n) ? parts[i] : 0.0;
+    }
+}
+
+__device__ inline double total_finish(const double *__restrict__ parts, int n, const TotalLoads &t, double *sm)
+{
     const int nt = blockDim.x;
-    for (int base = 0; base < n; base += 8 * nt) {
+    double s = 0.0;
+    s += ((t.v[0] + t.v[1]) + (t.v[2] + t.v[3])) + ((t.v[4] + t.v[5]) + (t.v[6] + t.v[7]));
+    for (int base = 8 * nt; base < n; base += 8 * nt) {
         double v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -283,6 +299,13 @@ __device__ inline double block_total(const double *__restrict__ parts, int n, do
     s = sm[nw];
     __syncthreads();
     return s;
+}
+
+__device__ inline double block_total(const double *__restrict__ parts, int n, double *sm)
+{
+    TotalLoads t;
+    total_issue(parts, n, t);
+    return total_finish(parts, n, t, sm);
 }
 
 // Map a block index to a logical tile so that each XCD (blocks are dealt to

@@ -69,8 +69,11 @@ k_strip_reduced(const T *__restrict__ red_e, const T *__restrict__ red_g, T *__r
     T *base = reinterpret_cast<T *>(smem_raw);
     const int l0 = xcd_swizzle(blockIdx.x, N / MT) * MT;
     constexpr bool VEC = MT % (16 / (int)sizeof(T)) == 0;   // 16-byte staging loads
+    GatePre pre;
+    if (g.mode == 1) gate_issue(st, partials, g, pre);
     strip_stage2<T, VEC>(red_e, red_g, ln, nr, N, G, l0, MT, base);
-    if (g.mode != 0 && tridiag_gate(st, partials, g, red, blockIdx.x) != ST_RUN) return;
+    if (g.mode != 0 && tridiag_gate(st, partials, g, red, blockIdx.x, g.mode == 1 ? &pre : nullptr) != ST_RUN)
+        return;
     __syncthreads();
     strip_solve2<T, R, LMAX, VEC>(red_x, ln, nr, N, G, l0, MT, base);
 }

@@ -360,15 +360,39 @@ __device__ inline void publish(HostMirror *m, unsigned seq, double rr, double bb
     *reinterpret_cast<volatile unsigned long long *>(&m->word) = mirror_word(seq, iters, done);
 }
 
+// The loads of a PCG step's gate (mode 1): the state fields and the first
+// round of the ||r||^2 partials, issued before the launch stages its own
+// data so that the two latencies overlap.
+struct GatePre {
+    TotalLoads rr;
+    int done, cur, maxit;
+    double tol2;
+};
+
+__device__ inline void gate_issue(const PcgState *st, const double *__restrict__ partials, const TriGate &g,
+                                  GatePre &p)
+{
+    p.done = st->done;
+    p.cur = st->cur;
+    p.maxit = st->maxit;
+    p.tol2 = st->tol2;
+    total_issue(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, p.rr);
+}
+
 __device__ inline int tridiag_gate(PcgState *st, const double *__restrict__ partials, const TriGate &g, double *red,
-                                   int vb)
+                                   int vb, const GatePre *pre = nullptr)
 {
     if (g.mode == 1) {
         // every state field read at once, their latency overlapping the
         // reduction
-        const int done = st->done, k_it = st->cur, maxit = st->maxit;
-        const double tol2 = st->tol2;
-        const double rr = block_total(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, red);
+        GatePre loc;
+        if (!pre) {
+            gate_issue(st, partials, g, loc);
+            pre = &loc;
+        }
+        const int done = pre->done, k_it = pre->cur, maxit = pre->maxit;
+        const double tol2 = pre->tol2;
+        const double rr = total_finish(partials + SLOT_RR * MAX_PARTIALS, g.n_rr, pre->rr, red);
         if (done) return done;   // stopped earlier: leave the state alone
         int status = ST_RUN;
         if (!(rr == rr) || rr > 1e300) status = ST_BREAK;

@@ -302,6 +302,8 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
     // two, so the division is a shift
     auto prow = [&](int row) { return UNI ? row + row / LMAX : row + row / Lp; };
 
+    GatePre pre;
+    if (g.mode == 1) gate_issue(st, partials, g, pre);
     if (M * sizeof(T) == 16) {
         // one 16-byte load per row
         for (int row = threadIdx.x; row < nr; row += blockDim.x) {
@@ -315,7 +317,7 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
             tile[m * pitch + prow(row)] = spec[(size_t)row * nz + l0 + m];
         }
     }
-    if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb) != ST_RUN) return;
+    if (g.mode != 0 && tridiag_gate(st, partials, g, red, vb, g.mode == 1 ? &pre : nullptr) != ST_RUN) return;
     __syncthreads();
 
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
