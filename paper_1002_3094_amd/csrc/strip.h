@@ -33,9 +33,8 @@ strip_phase1(const double *__restrict__ rin, double *__restrict__ x, double *__r
     constexpr int N = Gm::N, PITCH = 2 * Gm::LB, n = R - 1, NT = 64 * R;
     const int wv = threadIdx.x >> 6;
     const int i0 = s * R;
-    if (!zfwd_w_body<T, BC, FUSED, R2>(rin, x, r, p, q, st, partials, n_pq, tw, pt, nr, i0 + wv, s,
-                                        RowStore<T>{tile + wv * PITCH}))
-        return false;
+    // the r-line coefficients of the strip and this thread's modes'
+    // eigenvalues, issued before the transform rather than after it
     T cbv[R], dbv[R], rwv[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) {
@@ -43,9 +42,22 @@ strip_phase1(const double *__restrict__ rin, double *__restrict__ x, double *__r
         dbv[t] = ln.db[i0 + t];
         rwv[t] = ln.rw[i0 + t];
     }
+    constexpr int NL = (N + NT - 1) / NT;
+    T lamv[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int l = threadIdx.x + u * NT;
+        lamv[u] = l < N ? ln.lam[l] : (T)0;
+    }
+    if (!zfwd_w_body<T, BC, FUSED, R2>(rin, x, r, p, q, st, partials, n_pq, tw, pt, nr, i0 + wv, s,
+                                        RowStore<T>{tile + wv * PITCH}))
+        return false;
     __syncthreads();
-    for (int l = threadIdx.x; l < N; l += NT) {
-        const T lam = ln.lam[l];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int l = threadIdx.x + u * NT;
+        if (l >= N) break;
+        const T lam = lamv[u];
         T f[R];
 #pragma unroll
         for (int t = 0; t < R; ++t) f[t] = tile[t * PITCH + l];
@@ -354,6 +366,18 @@ strip_phase3(const T *__restrict__ fprime, const T *__restrict__ red_x, double *
         for (int t = 0; t < R2; ++t)
             rpre[t] = *reinterpret_cast<const double2 *>(r + (size_t)(i0 + wv) * N + 2 * lane + 128 * t);
     }
+    // this thread's modes' eigenvalues and reduced solutions X_s, X_{s-1}
+    // (the previous launch's output), issued with the row loads instead of
+    // after the workgroup barrier below
+    constexpr int NL = (N + NT - 1) / NT;
+    T lamv[NL], xsv[NL], xpv[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int l = threadIdx.x + u * NT;
+        lamv[u] = l < N ? ln.lam[l] : (T)0;
+        xsv[u] = l < N ? red_x[(size_t)s * N + l] : (T)0;
+        xpv[u] = (l < N && s > 0) ? red_x[(size_t)(s - 1) * N + l] : (T)0;
+    }
     if (fprime) {
         // f' of the interior rows into the tile, 16 bytes per access
         constexpr int VW = 16 / (int)sizeof(T);
@@ -377,10 +401,11 @@ strip_phase3(const T *__restrict__ fprime, const T *__restrict__ red_x, double *
     // issued rather than waiting on the flag before them
     if (MODE != 0 && st->done) return;
     __syncthreads();
-    for (int l = threadIdx.x; l < N; l += NT) {
-        const T lam = ln.lam[l];
-        const T Xs = red_x[(size_t)s * N + l];
-        const T Xp = s > 0 ? red_x[(size_t)(s - 1) * N + l] : (T)0;
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int l = threadIdx.x + u * NT;
+        if (l >= N) break;
+        const T lam = lamv[u], Xs = xsv[u], Xp = xpv[u];
         T cp[R], vp[R];
         T cprev = 0, vprev = 0;
 #pragma unroll
