@@ -263,8 +263,8 @@ __device__ inline double block_sum(double v, double *sm)
 // tree), returned in every thread.  `sm` needs blockDim.x / 64 + 1 doubles.
 // Each thread issues its (up to eight) loads before the first add, so the
 // reads of one round are in flight together rather than one latency apiece.
-// The first round can be issued early (total_issue) and the sum finished
-// later (total_finish), with the same additions in the same order.
+// total_issue and total_finish split the same sum in two: the first
+// round's loads issued early, the additions (in the same order) later.
 struct TotalLoads {
     double v[8];
 };
@@ -303,9 +303,24 @@ __device__ inline double total_finish(const double *__restrict__ parts, int n, c
 
 __device__ inline double block_total(const double *__restrict__ parts, int n, double *sm)
 {
-    TotalLoads t;
-    total_issue(parts, n, t);
-    return total_finish(parts, n, t, sm);
+    double s = 0.0;
+    const int nt = blockDim.x;
+    for (int base = 0; base < n; base += 8 * nt) {
+        double v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int i = base + (int)threadIdx.x + j * nt;
+            v[j] = (i < n) ? parts[i] : 0.0;
+        }
+        s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+    s = block_sum(s, sm);
+    const int nw = (blockDim.x + 63) >> 6;
+    if (threadIdx.x == 0) sm[nw] = s;
+    __syncthreads();
+    s = sm[nw];
+    __syncthreads();
+    return s;
 }
 
 // Map a block index to a logical tile so that each XCD (blocks are dealt to

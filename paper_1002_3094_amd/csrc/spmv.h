@@ -84,6 +84,11 @@ __device__ __forceinline__ void spmv_tiles(const double *__restrict__ z, const d
     int k_it = 0;
     const int nb = (nr + RW - 1) / RW, nc = (nz + SPMV_CHUNK - 1) / SPMV_CHUNK;
     const int lane = threadIdx.x & 63;
+    // the first round of the r.z partials, issued ahead of the first tile's
+    // rows so that the two reads are in flight together (not in the
+    // Polak-Ribiere form, whose second sum would cost it a wave per SIMD)
+    TotalLoads rz_pre;
+    if constexpr (!PR) total_issue(partials + SLOT_RZ * MAX_PARTIALS, n_rz, rz_pre);
     for (int t = vb; t < nb * nc; t += vnb) {
         const int item = xcd_swizzle(t, nb * nc);
         const int i0 = RW * (item / nc);
@@ -148,7 +153,8 @@ __device__ __forceinline__ void spmv_tiles(const double *__restrict__ z, const d
                 const int done = st->done;
                 k_it = st->iters;
                 const double rho_slot[2] = {st->rho[0], st->rho[1]};
-                const double rho = block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red);
+                const double rho = PR ? block_total(partials + SLOT_RZ * MAX_PARTIALS, n_rz, red)
+                                      : total_finish(partials + SLOT_RZ * MAX_PARTIALS, n_rz, rz_pre, red);
                 if (done) return;
                 if (k_it > 0) {
                     double num = rho;
