@@ -34,24 +34,30 @@ strip_phase1(const double *__restrict__ rin, double *__restrict__ x, double *__r
     const int wv = threadIdx.x >> 6;
     const int i0 = s * R;
     // the r-line coefficients of the strip and this thread's modes'
-    // eigenvalues, issued before the transform rather than after it
+    // eigenvalues: issued before the transform in the plain form, after it
+    // in the PCG form (there the early reads made the launch 1.3 us slower
+    // at 1024^2, 13.8 -> 15.1 us)
     T cbv[R], dbv[R], rwv[R];
-#pragma unroll
-    for (int t = 0; t < R; ++t) {
-        cbv[t] = ln.cb[i0 + t];
-        dbv[t] = ln.db[i0 + t];
-        rwv[t] = ln.rw[i0 + t];
-    }
     constexpr int NL = (N + NT - 1) / NT;
     T lamv[NL];
+    auto load_lines = [&]() {
 #pragma unroll
-    for (int u = 0; u < NL; ++u) {
-        const int l = threadIdx.x + u * NT;
-        lamv[u] = l < N ? ln.lam[l] : (T)0;
-    }
+        for (int t = 0; t < R; ++t) {
+            cbv[t] = ln.cb[i0 + t];
+            dbv[t] = ln.db[i0 + t];
+            rwv[t] = ln.rw[i0 + t];
+        }
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int l = threadIdx.x + u * NT;
+            lamv[u] = l < N ? ln.lam[l] : (T)0;
+        }
+    };
+    if constexpr (!FUSED) load_lines();
     if (!zfwd_w_body<T, BC, FUSED, R2>(rin, x, r, p, q, st, partials, n_pq, tw, pt, nr, i0 + wv, s,
                                         RowStore<T>{tile + wv * PITCH}))
         return false;
+    if constexpr (FUSED) load_lines();
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < NL; ++u) {
