@@ -39,8 +39,10 @@ __device__ inline const typename vec2_of<T>::type *stage_twiddles(const typename
 
 // ---------------------------------------------------------------------------
 // Forward transform: one workgroup per ROWS consecutive r-rows.  With two
-// rows the second row's loads are issued before the first row's FFT, so the
-// memory traffic of one row overlaps the LDS work of the other.
+// rows, both real, one complex FFT transforms them together (the first as
+// real, the second as imaginary part), and the two spectra are separated
+// by the conjugate symmetry of a real row's FFT; the second row's loads are
+// issued while the first row is reordered into LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int BC, bool FUSED, bool TWLDS, int ROWS, bool WG_STOP = false>
 __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double *__restrict__ x,
@@ -101,6 +103,9 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
     double rr = 0.0;
     const T nrm = (T)sqrt(2.0 / N);
     const T half = (T)0.70710678118654752440;
+    // two rows: one complex FFT of (row 0) + i (row 1), both rows real
+    constexpr bool PAIR = (ROWS == 2);
+    static_assert(ROWS == 1 || ROWS == 2, "one or two rows per workgroup");
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
         const size_t row = (size_t)(i0 + s) * N;
@@ -126,17 +131,40 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
                 n = N - 1 - (k >> 1);
                 if (BC == DIR) v = -v;
             }
-            a[n] = {v, (T)0};
+            if constexpr (PAIR) {
+                if (s == 0) a[n].x = v;
+                else a[n].y = v;
+            } else {
+                a[n] = {v, (T)0};
+            }
         }
         if (s + 1 < ROWS) load(i0 + s + 1);
+        if (PAIR && s == 0) continue;   // the second row fills the imaginary parts
         __syncthreads();
         const cx<T> *Vr = fft_stockham<T>(a, b, N, twp);
-        for (int j = threadIdx.x; j < N; j += blockDim.x) {
-            const int m = (BC == DIR) ? N - 1 - j : j;
-            const cx<T> w = ld_tw<T>(pt, m);
-            const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
-            const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
-            spec[row + j] = nrm * (edge ? half : (T)1) * Y;
+        if constexpr (PAIR) {
+            // Z = V0 + i V1 with V0, V1 the spectra of the two real rows:
+            // V0_m = (Z_m + conj Z_{N-m}) / 2, V1_m = (Z_m - conj Z_{N-m}) / 2i
+            const size_t row0 = (size_t)i0 * N;
+            for (int j = threadIdx.x; j < N; j += blockDim.x) {
+                const int m = (BC == DIR) ? N - 1 - j : j;
+                const cx<T> zm = Vr[m], zc = Vr[(N - m) & (N - 1)];
+                const cx<T> w = ld_tw<T>(pt, m);
+                const T v0x = (T)0.5 * (zm.x + zc.x), v0y = (T)0.5 * (zm.y - zc.y);
+                const T v1x = (T)0.5 * (zm.y + zc.y), v1y = (T)0.5 * (zc.x - zm.x);
+                const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
+                const T sc = nrm * (edge ? half : (T)1);
+                spec[row0 + j] = sc * (v0x * w.x - v0y * w.y);
+                spec[row0 + N + j] = sc * (v1x * w.x - v1y * w.y);
+            }
+        } else {
+            for (int j = threadIdx.x; j < N; j += blockDim.x) {
+                const int m = (BC == DIR) ? N - 1 - j : j;
+                const cx<T> w = ld_tw<T>(pt, m);
+                const T Y = Vr[m].x * w.x - Vr[m].y * w.y;
+                const bool edge = (BC == DIR) ? (j == N - 1) : (j == 0);
+                spec[row + j] = nrm * (edge ? half : (T)1) * Y;
+            }
         }
         if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
     }
@@ -148,7 +176,7 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
 
 // ---------------------------------------------------------------------------
 // Inverse transform: one workgroup per ROWS consecutive r-rows, FP64 output;
-// the next row's spectral values are loaded during the current row's FFT.
+// two rows go through one complex FFT as in the forward transform.
 // ---------------------------------------------------------------------------
 
 template <typename T, int BC, int MODE, bool TWLDS, int ROWS>
@@ -201,6 +229,14 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
         c1 = alpha - 1.0;
         c2 = alpha * tau;
     }
+    // two rows: one FFT of conj(V0) + i conj(V1), whose real and imaginary
+    // parts are N times the two real rows
+    constexpr bool PAIR = (ROWS == 2);
+    static_assert(ROWS == 1 || ROWS == 2, "one or two rows per workgroup");
+    cx<T> c0[PAIR ? KPT : 1];
+    // r (and the old z) of the rows, and the next row's spectral values, are
+    // in flight during the FFT
+    double rv[ROWS][KPT], zo[ROWS][KPT];
 #pragma unroll
     for (int s = 0; s < ROWS; ++s) {
         const size_t row = (size_t)(i0 + s) * N;
@@ -209,43 +245,52 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
             const int m = threadIdx.x + j * blockDim.x;
             if (m < N) {
                 const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
-                // V = conj(w) (ym - i yn); store conj(V) = w (ym + i yn)
-                a[m] = {w.x * ymv[j] - w.y * ynv[j], w.x * ynv[j] + w.y * ymv[j]};
+                // V = conj(w) (ym - i yn); conj(V) = w (ym + i yn)
+                const cx<T> cv = {w.x * ymv[j] - w.y * ynv[j], w.x * ynv[j] + w.y * ymv[j]};
+                if constexpr (PAIR) {
+                    if (s == 0) c0[j] = cv;
+                    else a[m] = {c0[j].x - cv.y, c0[j].y + cv.x};
+                } else {
+                    a[m] = cv;
+                }
             }
         }
-        // r (and the old z) of this row, and the next row's spectral values,
-        // are in flight during the FFT
-        double rv[KPT], zo[KPT];
         if (PCGM) {
 #pragma unroll
             for (int j = 0; j < KPT; ++j) {
                 const int k = threadIdx.x + j * blockDim.x;
                 if (k < N) {
-                    rv[j] = r[row + k];
-                    if (pr) zo[j] = zout[row + k];
+                    rv[s][j] = r[row + k];
+                    if (pr) zo[s][j] = zout[row + k];
                 }
             }
         }
         if (s + 1 < ROWS) load(i0 + s + 1);
+        if (PAIR && s == 0) continue;   // the second row completes a
         __syncthreads();
         const cx<T> *res = fft_stockham<T>(a, b, N, twp);
 #pragma unroll
-        for (int j = 0; j < KPT; ++j) {
-            const int k = threadIdx.x + j * blockDim.x;
-            if (k >= N) continue;
-            const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
-            T v = res[n].x * invN;
-            if (BC == DIR && (k & 1)) v = -v;
-            const double zv = (double)v;
-            if (PCGM) {
-                if (pr) rzo += rv[j] * zo[j];
-                rz += rv[j] * zv;
-            }
-            if (CHEB) {
-                if (MODE == 4) dinc[row + k] = c2 * zv;
-                else dinc[row + k] = c1 * dinc[row + k] + c2 * zv;
-            } else {
-                zout[row + k] = zv;
+        for (int t = 0; t < (PAIR ? 2 : 1); ++t) {
+            const int ri = PAIR ? t : s;   // the row's index in the workgroup
+            const size_t rowt = (size_t)(i0 + ri) * N;
+#pragma unroll
+            for (int j = 0; j < KPT; ++j) {
+                const int k = threadIdx.x + j * blockDim.x;
+                if (k >= N) continue;
+                const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
+                T v = (t == 0 ? res[n].x : res[n].y) * invN;
+                if (BC == DIR && (k & 1)) v = -v;
+                const double zv = (double)v;
+                if (PCGM) {
+                    if (pr) rzo += rv[ri][j] * zo[ri][j];
+                    rz += rv[ri][j] * zv;
+                }
+                if (CHEB) {
+                    if (MODE == 4) dinc[rowt + k] = c2 * zv;
+                    else dinc[rowt + k] = c1 * dinc[rowt + k] + c2 * zv;
+                } else {
+                    zout[rowt + k] = zv;
+                }
             }
         }
         if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b

@@ -25,7 +25,10 @@ def ax():
     return axipcg
 
 
-CASES = [(64, 64, 0), (128, 256, 1), (96, 64, 0), (256, 256, 0), (42, 1024, 1), (20, 4096, 1)]
+# (512, 32) and (600, 64): FP64 transforms two rows per workgroup (one complex
+# FFT for both), in the Chebyshev step and start modes too
+CASES = [(64, 64, 0), (128, 256, 1), (96, 64, 0), (256, 256, 0), (42, 1024, 1), (20, 4096, 1), (512, 32, 1),
+         (600, 64, 0)]
 
 
 @pytest.mark.parametrize("nr,nz,bc", CASES)
