@@ -220,7 +220,11 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
             }
         }
     };
-    load(i0);
+    // two rows: one FFT of conj(V0) + i conj(V1), whose real and imaginary
+    // parts are N times the two real rows
+    constexpr bool PAIR = (ROWS == 2);
+    static_assert(ROWS == 1 || ROWS == 2, "one or two rows per workgroup");
+    if (!PAIR) load(i0);
     const T invN = (T)1 / (T)N;
     double rz = 0.0, rzo = 0.0;
     double c1 = 0.0, c2 = 0.0;
@@ -229,71 +233,88 @@ __device__ __forceinline__ void zinv_body(const T *__restrict__ spec, double *__
         c1 = alpha - 1.0;
         c2 = alpha * tau;
     }
-    // two rows: one FFT of conj(V0) + i conj(V1), whose real and imaginary
-    // parts are N times the two real rows
-    constexpr bool PAIR = (ROWS == 2);
-    static_assert(ROWS == 1 || ROWS == 2, "one or two rows per workgroup");
-    cx<T> c0[PAIR ? KPT : 1];
-    // r (and the old z) of the rows, and the next row's spectral values, are
-    // in flight during the FFT
+    // r (and the old z) of the rows are in flight during the FFT
     double rv[ROWS][KPT], zo[ROWS][KPT];
+    auto load_r = [&](int si) {
+        const size_t row = (size_t)(i0 + si) * N;
 #pragma unroll
-    for (int s = 0; s < ROWS; ++s) {
-        const size_t row = (size_t)(i0 + s) * N;
+        for (int j = 0; j < KPT; ++j) {
+            const int k = threadIdx.x + j * blockDim.x;
+            if (k < N) {
+                rv[si][j] = r[row + k];
+                if (pr) zo[si][j] = zout[row + k];
+            }
+        }
+    };
+    // z of row si from the FFT's output: real (t = 0) or imaginary (t = 1) parts
+    auto store = [&](const cx<T> *res, int si, int t) {
+        const size_t rowt = (size_t)(i0 + si) * N;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int k = threadIdx.x + j * blockDim.x;
+            if (k >= N) continue;
+            const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
+            T v = (t == 0 ? res[n].x : res[n].y) * invN;
+            if (BC == DIR && (k & 1)) v = -v;
+            const double zv = (double)v;
+            if (PCGM) {
+                if (pr) rzo += rv[si][j] * zo[si][j];
+                rz += rv[si][j] * zv;
+            }
+            if (CHEB) {
+                if (MODE == 4) dinc[rowt + k] = c2 * zv;
+                else dinc[rowt + k] = c1 * dinc[rowt + k] + c2 * zv;
+            } else {
+                zout[rowt + k] = zv;
+            }
+        }
+    };
+    if constexpr (PAIR) {
+        // both rows' Y_m staged in b (the FFT's scratch until it starts), so
+        // that each spectral value is read from memory once; Y_{N-m} then
+        // comes from LDS
+        const size_t row0 = (size_t)i0 * N;
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int m = threadIdx.x + j * blockDim.x;
+            if (m < N) b[m] = {Yval(row0, m), Yval(row0 + N, m)};
+        }
+        if (PCGM) {
+            load_r(0);
+            load_r(1);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < KPT; ++j) {
+            const int m = threadIdx.x + j * blockDim.x;
+            if (m < N) {
+                const cx<T> y = b[m];
+                const cx<T> yn = (m == 0) ? cx<T>{(T)0, (T)0} : b[N - m];
+                const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
+                // conj(V) = w (ym + i yn) for each row
+                const cx<T> q0 = {w.x * y.x - w.y * yn.x, w.x * yn.x + w.y * y.x};
+                const cx<T> q1 = {w.x * y.y - w.y * yn.y, w.x * yn.y + w.y * y.y};
+                a[m] = {q0.x - q1.y, q0.y + q1.x};
+            }
+        }
+        __syncthreads();
+        const cx<T> *res = fft_stockham<T>(a, b, N, twp);
+        store(res, 0, 0);
+        store(res, 1, 1);
+    } else {
 #pragma unroll
         for (int j = 0; j < KPT; ++j) {
             const int m = threadIdx.x + j * blockDim.x;
             if (m < N) {
                 const cx<T> w = ld_tw<T>(pt, m);      // exp(-i pi m / 2N)
-                // V = conj(w) (ym - i yn); conj(V) = w (ym + i yn)
-                const cx<T> cv = {w.x * ymv[j] - w.y * ynv[j], w.x * ynv[j] + w.y * ymv[j]};
-                if constexpr (PAIR) {
-                    if (s == 0) c0[j] = cv;
-                    else a[m] = {c0[j].x - cv.y, c0[j].y + cv.x};
-                } else {
-                    a[m] = cv;
-                }
+                // V = conj(w) (ym - i yn); store conj(V) = w (ym + i yn)
+                a[m] = {w.x * ymv[j] - w.y * ynv[j], w.x * ynv[j] + w.y * ymv[j]};
             }
         }
-        if (PCGM) {
-#pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                const int k = threadIdx.x + j * blockDim.x;
-                if (k < N) {
-                    rv[s][j] = r[row + k];
-                    if (pr) zo[s][j] = zout[row + k];
-                }
-            }
-        }
-        if (s + 1 < ROWS) load(i0 + s + 1);
-        if (PAIR && s == 0) continue;   // the second row completes a
+        if (PCGM) load_r(0);
         __syncthreads();
         const cx<T> *res = fft_stockham<T>(a, b, N, twp);
-#pragma unroll
-        for (int t = 0; t < (PAIR ? 2 : 1); ++t) {
-            const int ri = PAIR ? t : s;   // the row's index in the workgroup
-            const size_t rowt = (size_t)(i0 + ri) * N;
-#pragma unroll
-            for (int j = 0; j < KPT; ++j) {
-                const int k = threadIdx.x + j * blockDim.x;
-                if (k >= N) continue;
-                const int n = (k & 1) ? N - 1 - (k >> 1) : (k >> 1);
-                T v = (t == 0 ? res[n].x : res[n].y) * invN;
-                if (BC == DIR && (k & 1)) v = -v;
-                const double zv = (double)v;
-                if (PCGM) {
-                    if (pr) rzo += rv[ri][j] * zo[ri][j];
-                    rz += rv[ri][j] * zv;
-                }
-                if (CHEB) {
-                    if (MODE == 4) dinc[rowt + k] = c2 * zv;
-                    else dinc[rowt + k] = c1 * dinc[rowt + k] + c2 * zv;
-                } else {
-                    zout[rowt + k] = zv;
-                }
-            }
-        }
-        if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
+        store(res, 0, 0);
     }
     if (PCGM) {
         const double s = block_sum(rz, red);
