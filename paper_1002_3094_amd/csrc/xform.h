@@ -166,7 +166,6 @@ __device__ __forceinline__ void zfwd_body(const double *__restrict__ rin, double
                 spec[row + j] = nrm * (edge ? half : (T)1) * Y;
             }
         }
-        if (s + 1 < ROWS) __syncthreads();   // the next row refills a and b
     }
     if (FUSED) {
         const double s = block_sum(rr, red);
