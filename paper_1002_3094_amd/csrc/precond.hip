@@ -59,8 +59,13 @@ k_zinv_w(const T *__restrict__ spec, double *__restrict__ zout, const double *__
     zinv_w_body<T, BC, MODE, R2>(in, zout, r, st, partials, pr, tw, pt, nr, dinc, tau, rho2, row, blockIdx.x);
 }
 
+// Threads of an r-solve workgroup (one wave per mode): up to eight FP32 modes
+// on lines of 2048 rows and more (32-byte row pieces), else up to four.
+template <typename T, int LMAX>
+constexpr int tri_threads() { return (sizeof(T) == 4 && LMAX >= 32) ? 512 : 256; }
+
 template <typename T, int LMAX, bool UNI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__((tri_threads<T, LMAX>()))
 k_tridiag(T *__restrict__ spec, const T *__restrict__ cb_g, const T *__restrict__ db_g,
           const T *__restrict__ rw_g, const T *__restrict__ lam, PcgState *st,
           const double *__restrict__ partials, TriGate g, int nr, int nz, int M, int S, int pitch, int Lp)
@@ -317,10 +322,10 @@ void zinv_t(const Operator &op, const ZinvArgs &a, hipStream_t s)
     }
 }
 
-// LDS of an r-solve workgroup (its [M][N_r] tile, padded): up to 96 KiB, so
-// that rows of 4096 keep four FP32 modes (16-byte row loads) or two FP64 ones
-// per workgroup (the kernels' attribute raised on first use).
-constexpr size_t TRI_LDS_MAX = 96 * 1024;
+// LDS of an r-solve workgroup (its [M][N_r] tile, padded): up to 136 KiB, so
+// that lines of 4096 rows keep eight FP32 or four FP64 modes per workgroup,
+// 32 bytes of each row (the kernels' attribute raised on first use).
+constexpr size_t TRI_LDS_MAX = 136 * 1024;
 
 struct TriGeom {
     int M, S, L, Lp, pitch;
@@ -335,7 +340,10 @@ TriGeom tri_geom(int nr, int nz)
     g.L = (nr + g.S - 1) / g.S;
     g.Lp = nr / g.S;
     g.pitch = nr + nr / g.Lp + 1;
-    g.M = 16 / (int)sizeof(T);   // one 16-byte vector of modes per row
+    // one 16-byte vector of modes per row; two on lines of 2048 rows and more,
+    // whose tiles written back 16 bytes per row left partly written lines
+    // (1.35x the FP32 tile's bytes at 4096 rows, 1.7x in FP64)
+    g.M = (g.L >= 32 ? 32 : 16) / (int)sizeof(T);
     auto lds = [&](int M) { return (size_t)M * g.pitch * sizeof(T); };
     while (g.M > 1 && (lds(g.M) > TRI_LDS_MAX || nz % g.M != 0)) g.M >>= 1;
     g.shm = lds(g.M);

@@ -352,7 +352,7 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
                                              const double *__restrict__ partials, const TriGate &g, int nr,
                                              int nz, int M, int S, int pitch, int Lp, int vb)
 {
-    __shared__ double red[8];
+    __shared__ double red[RED_SLOTS];
     extern __shared__ char smem_raw[];
     T *tile = reinterpret_cast<T *>(smem_raw);
     // r-line coefficients: each lane reads its own contiguous rows from global
@@ -369,12 +369,15 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
 
     GatePre pre;
     if (g.mode == 1) gate_issue(st, partials, g, pre);
-    if (M * sizeof(T) == 16) {
-        // one 16-byte load per row
-        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0);
+    constexpr int VW = 16 / (int)sizeof(T);   // modes per 16-byte piece
+    if (M % VW == 0) {
+        // the row's M modes as 16-byte pieces (one or two per row)
+        const int nv = M / VW;
+        for (int e = threadIdx.x; e < nr * nv; e += blockDim.x) {
+            const int row = e / nv, h = e - row * nv;
+            const uint4 v = *reinterpret_cast<const uint4 *>(spec + (size_t)row * nz + l0 + h * VW);
             const T *tv = reinterpret_cast<const T *>(&v);
-            for (int m = 0; m < M; ++m) tile[m * pitch + prow(row)] = tv[m];
+            for (int m = 0; m < VW; ++m) tile[(h * VW + m) * pitch + prow(row)] = tv[m];
         }
     } else {
         for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
@@ -508,12 +511,14 @@ __device__ __forceinline__ void tridiag_body(T *__restrict__ spec, const T *__re
         }
     }
     __syncthreads();
-    if (M * sizeof(T) == 16) {
-        for (int row = threadIdx.x; row < nr; row += blockDim.x) {
+    if (M % VW == 0) {
+        const int nv = M / VW;
+        for (int e = threadIdx.x; e < nr * nv; e += blockDim.x) {
+            const int row = e / nv, h = e - row * nv;
             uint4 v;
             T *tv = reinterpret_cast<T *>(&v);
-            for (int m = 0; m < M; ++m) tv[m] = tile[m * pitch + prow(row)];
-            *reinterpret_cast<uint4 *>(spec + (size_t)row * nz + l0) = v;
+            for (int m = 0; m < VW; ++m) tv[m] = tile[(h * VW + m) * pitch + prow(row)];
+            *reinterpret_cast<uint4 *>(spec + (size_t)row * nz + l0 + h * VW) = v;
         }
     } else {
         for (int e = threadIdx.x; e < nr * M; e += blockDim.x) {
